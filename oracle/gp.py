@@ -1,0 +1,285 @@
+"""FP64 oracle: kernel entries, K_y products, exact GP solve, mean, MLL, gradients.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Everything here is the
+plain definition, formed densely in float64 with numpy/scipy.
+
+Kernel parametrisation.  LightGP Sec. 3 ("Kernels") names the families RBF and
+Matern-1/2, 3/2, 5/2 and a ``Scale`` wrapper but prints no formulas.  The
+reading taken here is the standard one (Rasmussen & Williams, ch. 4), with the
+1/2 inside the RBF exponent, a lengthscale per input dimension (ARD) or one
+shared lengthscale, an outputscale s^2 (the ``Scale`` variance) and a noise
+variance sigma^2 (Sec. 2, the sigma_n^2 of K_y = K_ff + sigma_n^2 I):
+
+    r^2 = sum_k ((x_k - x'_k) / l_k)^2,   rho = sqrt(r^2)
+    RBF        k = s^2 exp(-r^2 / 2)
+    Matern-1/2 k = s^2 exp(-rho)
+    Matern-3/2 k = s^2 (1 + sqrt3 rho) exp(-sqrt3 rho)
+    Matern-5/2 k = s^2 (1 + sqrt5 rho + 5 rho^2 / 3) exp(-sqrt5 rho)
+
+Distances are formed by direct differences, never by the ||x||^2 + ||x'||^2 -
+2 x.x' expansion.
+
+Gradient order everywhere: [l_1 .. l_d] (ARD) or [l] (shared), then s^2, then
+sigma^2, as derivatives with respect to these positive parameters.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.linalg import cho_factor, cho_solve
+
+FAMILIES = ("rbf", "matern12", "matern32", "matern52")
+
+
+@dataclass
+class Kern:
+    """Kernel hyperparameters: family, lengthscale(s), outputscale s^2, noise sigma^2."""
+
+    family: str
+    lengthscale: object  # float (shared) or sequence of length d (ARD)
+    outputscale: float = 1.0
+    noise: float = 0.01
+    ard: bool = field(init=False)
+
+    def __post_init__(self):
+        if self.family not in FAMILIES:
+            raise ValueError(f"unknown family {self.family}")
+        ls = np.asarray(self.lengthscale, dtype=np.float64)
+        self.ard = ls.ndim == 1
+        self.lengthscale = ls
+
+    def ls_vec(self, d: int) -> np.ndarray:
+        ls = np.asarray(self.lengthscale, dtype=np.float64)
+        return np.full(d, float(ls)) if ls.ndim == 0 else ls.astype(np.float64)
+
+    def n_params(self, d: int) -> int:
+        return (d if self.ard else 1) + 2
+
+    def with_params(self, theta) -> "Kern":
+        """New kernel from a parameter vector in gradient order."""
+        theta = np.asarray(theta, dtype=np.float64)
+        nl = len(theta) - 2
+        ls = theta[:nl] if self.ard else float(theta[0])
+        return Kern(self.family, ls, float(theta[nl]), float(theta[nl + 1]))
+
+    def params(self, d: int) -> np.ndarray:
+        ls = self.ls_vec(d) if self.ard else np.array([float(self.lengthscale)])
+        return np.concatenate([ls, [self.outputscale, self.noise]])
+
+
+# --------------------------------------------------------------------------
+# Kernel entries (Sec. 3 "Kernels"; Sec. 2 defines K_ff, K_*f and K_y)
+# --------------------------------------------------------------------------
+
+def scaled_sqdist(X1: np.ndarray, X2: np.ndarray, ls: np.ndarray) -> np.ndarray:
+    """r^2_ij = sum_k ((X1_ik - X2_jk) / l_k)^2 by direct differences, FP64."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    r2 = np.zeros((X1.shape[0], X2.shape[0]))
+    for k in range(X1.shape[1]):
+        dk = (X1[:, k, None] - X2[None, :, k]) / ls[k]
+        r2 += dk * dk
+    return r2
+
+
+def shape_from_r2(family: str, r2: np.ndarray) -> np.ndarray:
+    """Kernel profile f(r^2) with k = s^2 f (unit outputscale)."""
+    if family == "rbf":
+        return np.exp(-0.5 * r2)
+    rho = np.sqrt(r2)
+    if family == "matern12":
+        return np.exp(-rho)
+    if family == "matern32":
+        a = math.sqrt(3.0) * rho
+        return (1.0 + a) * np.exp(-a)
+    if family == "matern52":
+        a = math.sqrt(5.0) * rho
+        return (1.0 + a + a * a / 3.0) * np.exp(-a)
+    raise ValueError(family)
+
+
+def dshape_factor(family: str, r2: np.ndarray) -> np.ndarray:
+    """g(r^2) such that d f / d l_k = g * Delta_k^2 / l_k^3 (unit outputscale).
+
+    From d r^2 / d l_k = -2 Delta_k^2 / l_k^3 and the chain rule:
+      RBF        g = exp(-r^2/2)
+      Matern-1/2 g = exp(-rho) / rho            (limit 0 at rho = 0, see below)
+      Matern-3/2 g = 3 exp(-sqrt3 rho)
+      Matern-5/2 g = (5/3) (1 + sqrt5 rho) exp(-sqrt5 rho)
+    For Matern-1/2 at rho = 0 every Delta_k is 0, so the product g Delta_k^2
+    is 0; the factor is set to 0 there.
+    """
+    if family == "rbf":
+        return np.exp(-0.5 * r2)
+    rho = np.sqrt(r2)
+    if family == "matern12":
+        out = np.zeros_like(rho)
+        nz = rho > 0
+        out[nz] = np.exp(-rho[nz]) / rho[nz]
+        return out
+    if family == "matern32":
+        return 3.0 * np.exp(-math.sqrt(3.0) * rho)
+    if family == "matern52":
+        a = math.sqrt(5.0) * rho
+        return (5.0 / 3.0) * (1.0 + a) * np.exp(-a)
+    raise ValueError(family)
+
+
+def kernel_matrix(kern: Kern, X1: np.ndarray, X2: np.ndarray) -> np.ndarray:
+    """K(X1, X2) with outputscale, no noise (Sec. 2: K_ff or K_*f)."""
+    d = np.asarray(X1).shape[1]
+    r2 = scaled_sqdist(X1, X2, kern.ls_vec(d))
+    return kern.outputscale * shape_from_r2(kern.family, r2)
+
+
+def ky_matrix(kern: Kern, X: np.ndarray) -> np.ndarray:
+    """K_y = K_ff + sigma^2 I (Sec. 2)."""
+    K = kernel_matrix(kern, X, X)
+    K[np.diag_indices_from(K)] += kern.noise
+    return K
+
+
+def ky_matvec(kern: Kern, X: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """K_y V in FP64, the product CG needs (Sec. 2 "CG-based inference")."""
+    V = np.asarray(V, dtype=np.float64)
+    return ky_matrix(kern, X) @ V
+
+
+def ky_matvec_rows(kern: Kern, X: np.ndarray, V: np.ndarray, rows, block: int = 256) -> np.ndarray:
+    """Selected rows of K_y V without forming K (sampled check at large N).
+
+    out[r] = s^2 sum_j k(x_r, x_j) V_j + sigma^2 V_r, accumulated in FP64 over
+    row blocks so memory stays O(block * N).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    V2 = V.reshape(V.shape[0], -1)
+    out = np.empty((len(rows), V2.shape[1]))
+    for b in range(0, len(rows), block):
+        rb = rows[b:b + block]
+        K = kernel_matrix(kern, X[rb], X)
+        out[b:b + block] = K @ V2 + kern.noise * V2[rb]
+    return out.reshape((len(rows),) + V.shape[1:])
+
+
+def cross_matvec_blocked(kern: Kern, Xs: np.ndarray, X: np.ndarray, a: np.ndarray,
+                         block: int = 512) -> np.ndarray:
+    """K(Xs, X) a accumulated over row blocks of Xs (O(block * N) memory)."""
+    a = np.asarray(a, dtype=np.float64)
+    out = np.empty((Xs.shape[0],) + a.shape[1:])
+    for b in range(0, Xs.shape[0], block):
+        out[b:b + block] = kernel_matrix(kern, Xs[b:b + block], X) @ a
+    return out
+
+
+# --------------------------------------------------------------------------
+# Exact inference (Sec. 2: mean, MLL; "Exact inference via Cholesky")
+# --------------------------------------------------------------------------
+
+def cholesky(kern: Kern, X: np.ndarray):
+    return cho_factor(ky_matrix(kern, X), lower=True)
+
+
+def solve(kern: Kern, X: np.ndarray, B: np.ndarray, chol=None) -> np.ndarray:
+    """K_y^{-1} B by Cholesky (LAPACK dpotrf / dpotrs through scipy)."""
+    c = chol if chol is not None else cholesky(kern, X)
+    return cho_solve(c, np.asarray(B, dtype=np.float64))
+
+
+def predict_mean(kern: Kern, X: np.ndarray, Xs: np.ndarray, alpha: np.ndarray) -> np.ndarray:
+    """mu_* = K_*f alpha with alpha = K_y^{-1} y (Sec. 2)."""
+    return kernel_matrix(kern, Xs, X) @ np.asarray(alpha, dtype=np.float64)
+
+
+def logdet(kern: Kern, X: np.ndarray, chol=None) -> float:
+    c = chol if chol is not None else cholesky(kern, X)
+    return 2.0 * float(np.sum(np.log(np.diag(c[0]))))
+
+
+def mll(kern: Kern, X: np.ndarray, y: np.ndarray) -> float:
+    """log p(y|X) = -1/2 [y^T K_y^{-1} y + log|K_y| + N log 2 pi] (Sec. 2)."""
+    y = np.asarray(y, dtype=np.float64)
+    c = cholesky(kern, X)
+    alpha = cho_solve(c, y)
+    n = y.shape[0]
+    return -0.5 * (float(y @ alpha) + logdet(kern, X, c) + n * math.log(2.0 * math.pi))
+
+
+def dky_matrices(kern: Kern, X: np.ndarray):
+    """dK_y/dtheta for theta in gradient order, as dense FP64 matrices.
+
+    d/dl_k : s^2 g(r^2) Delta_k^2 / l_k^3   (summed over k for a shared l)
+    d/ds^2 : K / s^2 = f(r^2)
+    d/dsigma^2 : I
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    ls = kern.ls_vec(d)
+    r2 = scaled_sqdist(X, X, ls)
+    g = kern.outputscale * dshape_factor(kern.family, r2)
+    per_dim = []
+    for k in range(d):
+        dk = X[:, k, None] - X[None, :, k]
+        per_dim.append(g * dk * dk / ls[k] ** 3)
+    mats = per_dim if kern.ard else [sum(per_dim)]
+    mats.append(shape_from_r2(kern.family, r2))
+    mats.append(np.eye(n))
+    return mats
+
+
+def mll_grad(kern: Kern, X: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Exact gradient of the MLL: 1/2 a^T dK a - 1/2 tr(K_y^{-1} dK), a = K_y^{-1} y.
+
+    The trace is taken as sum_ij (K_y^{-1})_ij (dK)_ij (both symmetric).
+    """
+    y = np.asarray(y, dtype=np.float64)
+    c = cholesky(kern, X)
+    a = cho_solve(c, y)
+    Kinv = cho_solve(c, np.eye(len(y)))
+    out = []
+    for dK in dky_matrices(kern, X):
+        out.append(0.5 * float(a @ dK @ a) - 0.5 * float(np.sum(Kinv * dK)))
+    return np.array(out)
+
+
+def same_probe_grad(kern: Kern, X: np.ndarray, y: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """The stochastic-trace gradient estimator evaluated exactly for given probes.
+
+    g_theta = 1/2 a^T dK a - 1/2 (1/p) sum_c u_c^T dK z_c,  u_c = K_y^{-1} z_c,
+    i.e. tr(K_y^{-1} dK) replaced by its Hutchinson estimate with the probes Z
+    (Rademacher, Sec. 4.3), with every solve exact (Cholesky).
+    """
+    y = np.asarray(y, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    p = Z.shape[1]
+    c = cholesky(kern, X)
+    a = cho_solve(c, y)
+    U = cho_solve(c, Z)
+    out = []
+    for dK in dky_matrices(kern, X):
+        out.append(0.5 * float(a @ dK @ a) - 0.5 / p * float(np.sum(U * (dK @ Z))))
+    return np.array(out)
+
+
+def adjoint_bilinear(kern: Kern, X: np.ndarray, A: np.ndarray, B: np.ndarray,
+                     colw) -> np.ndarray:
+    """sum_c colw_c A_c^T (dK_y/dtheta) B_c for every theta (vector-Jacobian product)."""
+    A = np.asarray(A, dtype=np.float64).reshape(len(X), -1)
+    B = np.asarray(B, dtype=np.float64).reshape(len(X), -1)
+    colw = np.asarray(colw, dtype=np.float64)
+    return np.array([float(np.sum((A * colw) * (dK @ B))) for dK in dky_matrices(kern, X)])
+
+
+def solve_residual(kern: Kern, X: np.ndarray, B: np.ndarray, Xsol: np.ndarray, rows=None) -> np.ndarray:
+    """Per-column ||B - K_y Xsol||_2 / ||B||_2 in FP64 (optionally over sampled rows)."""
+    B = np.asarray(B, dtype=np.float64).reshape(len(X), -1)
+    S = np.asarray(Xsol, dtype=np.float64).reshape(len(X), -1)
+    if rows is None:
+        R = B - ky_matvec(kern, X, S)
+        return np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
+    R = B[rows] - ky_matvec_rows(kern, X, S, rows)
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(B[rows], axis=0)

@@ -1,0 +1,327 @@
+"""Pins for the FP64 oracle: closed forms, brute force, library routines, invariants.
+
+Each check ties the oracle to something other than itself, so that a dropped
+term, a wrong sign or index or a transposed operand in it fails here.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+import torch
+
+from oracle import bf16, brute, gp, krylov, probes
+from paper_2605_17898_amd import inputs
+
+FAMS = gp.FAMILIES
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _pts(seed, n, d, scale=1.0):
+    return np.random.default_rng(seed).uniform(0, scale, size=(n, d))
+
+
+# ---------------------------------------------------------------- entries
+
+@pytest.mark.parametrize("s2", [1.0, 2.5])
+def test_entry_closed_forms(s2):
+    e = math.exp(-1.0)
+    x0 = np.zeros((1, 1))
+    # k(x, x) = s^2 for every family
+    for f in FAMS:
+        assert gp.kernel_matrix(gp.Kern(f, 0.7, s2), x0, x0)[0, 0] == pytest.approx(s2, rel=1e-15)
+    # RBF at r^2 = 2 (distance sqrt2 * l): s^2 e^-1
+    l = 0.4
+    k = gp.kernel_matrix(gp.Kern("rbf", l, s2), x0, np.array([[math.sqrt(2.0) * l]]))[0, 0]
+    assert k == pytest.approx(s2 * e, rel=1e-14)
+    # Matern-1/2 at rho = 1: s^2 e^-1
+    k = gp.kernel_matrix(gp.Kern("matern12", l, s2), x0, np.array([[l]]))[0, 0]
+    assert k == pytest.approx(s2 * e, rel=1e-14)
+    # Matern-3/2 at sqrt3 rho = 1: s^2 (1 + 1) e^-1
+    k = gp.kernel_matrix(gp.Kern("matern32", l, s2), x0, np.array([[l / math.sqrt(3.0)]]))[0, 0]
+    assert k == pytest.approx(2.0 * s2 * e, rel=1e-14)
+    # Matern-5/2 at sqrt5 rho = 1: s^2 (1 + 1 + 1/3) e^-1 = (7/3) s^2 e^-1
+    k = gp.kernel_matrix(gp.Kern("matern52", l, s2), x0, np.array([[l / math.sqrt(5.0)]]))[0, 0]
+    assert k == pytest.approx(7.0 / 3.0 * s2 * e, rel=1e-14)
+
+
+def test_ard_scales_each_dimension():
+    # ARD: an offset of l_k along axis k alone gives r^2 = 1 whatever k is.
+    ls = np.array([0.2, 0.5, 1.3])
+    for k in range(3):
+        x1 = np.zeros((1, 3))
+        x1[0, k] = ls[k]
+        val = gp.kernel_matrix(gp.Kern("rbf", ls, 1.0), np.zeros((1, 3)), x1)[0, 0]
+        assert val == pytest.approx(math.exp(-0.5), rel=1e-14)
+
+
+@pytest.mark.parametrize("family", FAMS)
+@pytest.mark.parametrize("ard", [False, True])
+def test_matvec_vs_brute_force(family, ard):
+    rng = np.random.default_rng(7)
+    n, d, t = 37, 3, 2
+    X = rng.uniform(0, 1, size=(n, d))
+    V = rng.standard_normal((n, t))
+    ls = rng.uniform(0.2, 0.7, size=d) if ard else 0.45
+    kern = gp.Kern(family, ls, 1.7, 0.03)
+    ref = np.array(brute.ky_matvec(family, X.tolist(), V.tolist(), list(kern.ls_vec(d)), 1.7, 0.03))
+    np.testing.assert_allclose(gp.ky_matvec(kern, X, V), ref, rtol=1e-13, atol=1e-13)
+    rows = np.array([0, 5, 36])
+    np.testing.assert_allclose(gp.ky_matvec_rows(kern, X, V, rows, block=2), ref[rows], rtol=1e-13)
+
+
+@pytest.mark.parametrize("family", FAMS)
+def test_operator_invariants(family):
+    rng = np.random.default_rng(3)
+    n, d = 120, 2
+    X = rng.uniform(0, 1, size=(n, d))
+    kern = gp.Kern(family, 0.3, 1.2, 0.02)
+    Ky = gp.ky_matrix(kern, X)
+    assert np.array_equal(Ky, Ky.T)
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    assert u @ gp.ky_matvec(kern, X, v) == pytest.approx(v @ gp.ky_matvec(kern, X, u), rel=1e-12)
+    # v^T K_y v >= sigma^2 ||v||^2 (K is PSD)
+    assert v @ gp.ky_matvec(kern, X, v) >= 0.02 * (v @ v) * (1 - 1e-12)
+    assert np.linalg.eigvalsh(Ky).min() >= 0.02 * (1 - 1e-9)
+    # permutation equivariance
+    perm = rng.permutation(n)
+    np.testing.assert_allclose(gp.ky_matvec(kern, X[perm], v[perm]), gp.ky_matvec(kern, X, v)[perm],
+                               rtol=1e-12, atol=1e-12)
+    # linearity
+    np.testing.assert_allclose(gp.ky_matvec(kern, X, 2 * u - 3 * v),
+                               2 * gp.ky_matvec(kern, X, u) - 3 * gp.ky_matvec(kern, X, v),
+                               rtol=1e-11, atol=1e-11)
+
+
+# ---------------------------------------------------------------- special cases
+
+@pytest.mark.parametrize("family", FAMS)
+def test_far_apart_points(family):
+    # points spaced far beyond the lengthscale: every off-diagonal entry is 0
+    n = 12
+    X = np.arange(n, dtype=float)[:, None] * 1e3
+    kern = gp.Kern(family, 0.5, 1.5, 0.1)
+    y = np.random.default_rng(1).standard_normal(n)
+    np.testing.assert_array_equal(gp.ky_matrix(kern, X), 1.6 * np.eye(n))
+    np.testing.assert_allclose(gp.solve(kern, X, y), y / 1.6, rtol=1e-14)
+    assert gp.logdet(kern, X) == pytest.approx(n * math.log(1.6), rel=1e-14)
+    # CG reaches the solution after one step; SLQ is exact at m = 1
+    x, al, be, it = krylov.cg(lambda V: gp.ky_matvec(kern, X, V), y, tol=1e-14)
+    assert it[0] == 1
+    np.testing.assert_allclose(x, y / 1.6, rtol=1e-14)
+    z = np.sign(np.random.default_rng(2).standard_normal(n))
+    _, q, _ = krylov.slq_logdet(lambda V: gp.ky_matvec(kern, X, V), z[:, None], tol=1e-14)
+    assert q[0] == pytest.approx(n * math.log(1.6), rel=1e-13)
+
+
+@pytest.mark.parametrize("family", FAMS)
+def test_identical_points(family):
+    # K_y = sigma^2 I + s^2 1 1^T: Sherman-Morrison solve and closed-form log-det / gradient
+    n, s2, sg = 9, 0.8, 0.05
+    X = np.full((n, 2), 0.37)
+    kern = gp.Kern(family, 0.4, s2, sg)
+    y = np.random.default_rng(4).standard_normal(n)
+    np.testing.assert_allclose(gp.ky_matrix(kern, X), sg * np.eye(n) + s2 * np.ones((n, n)), rtol=1e-15)
+    a_ref = (y - s2 * y.sum() / (sg + n * s2)) / sg
+    np.testing.assert_allclose(gp.solve(kern, X, y), a_ref, rtol=1e-11)
+    ld = (n - 1) * math.log(sg) + math.log(sg + n * s2)
+    assert gp.logdet(kern, X) == pytest.approx(ld, rel=1e-12)
+    g = gp.mll_grad(kern, X, y)
+    assert g[0] == pytest.approx(0.0, abs=1e-12)                         # d/dl
+    assert g[1] == pytest.approx(0.5 * a_ref.sum() ** 2 - 0.5 * n / (sg + n * s2), rel=1e-10)
+    assert g[2] == pytest.approx(0.5 * a_ref @ a_ref - 0.5 * ((n - 1) / sg + 1 / (sg + n * s2)), rel=1e-10)
+
+
+# ---------------------------------------------------------------- MLL / gradients
+
+@pytest.mark.parametrize("family", FAMS)
+def test_mll_vs_library_logpdf_and_brute(family):
+    rng = np.random.default_rng(11)
+    n, d = 30, 2
+    X = rng.uniform(0, 1, size=(n, d))
+    y = rng.standard_normal(n)
+    kern = gp.Kern(family, np.array([0.3, 0.6]), 1.4, 0.05)
+    ref = scipy.stats.multivariate_normal(mean=np.zeros(n), cov=gp.ky_matrix(kern, X)).logpdf(y)
+    assert gp.mll(kern, X, y) == pytest.approx(ref, rel=1e-11)
+    b = brute.mll(family, X.tolist(), y.tolist(), [0.3, 0.6], 1.4, 0.05)
+    assert gp.mll(kern, X, y) == pytest.approx(b, rel=1e-10)
+
+
+@pytest.mark.parametrize("family", FAMS)
+@pytest.mark.parametrize("ard", [False, True])
+def test_gradient_vs_central_fd(family, ard):
+    rng = np.random.default_rng(5)
+    n, d = 50, 3
+    X = rng.uniform(0, 1, size=(n, d))
+    y = np.sin(4 * X).sum(1) + 0.1 * rng.standard_normal(n)
+    ls = rng.uniform(0.2, 0.6, size=d) if ard else 0.4
+    kern = gp.Kern(family, ls, 1.3, 0.04)
+    th = kern.params(d)
+    g = gp.mll_grad(kern, X, y)
+    fd = np.zeros_like(th)
+    for p in range(len(th)):
+        h = 1e-5 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd[p] = (gp.mll(kern.with_params(tp), X, y) - gp.mll(kern.with_params(tm), X, y)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+def test_same_probe_estimator_exact_mode():
+    # probes sqrt(N) e_c (same norm as Rademacher): the Hutchinson trace is exact
+    rng = np.random.default_rng(8)
+    n, d = 40, 2
+    X = rng.uniform(0, 1, size=(n, d))
+    y = rng.standard_normal(n)
+    for fam in FAMS:
+        kern = gp.Kern(fam, np.array([0.3, 0.5]), 1.1, 0.03)
+        Z = math.sqrt(n) * np.eye(n)
+        np.testing.assert_allclose(gp.same_probe_grad(kern, X, y, Z), gp.mll_grad(kern, X, y), rtol=1e-10)
+
+
+def test_same_probe_estimator_is_unbiased():
+    rng = np.random.default_rng(9)
+    n = 60
+    X = rng.uniform(0, 1, size=(n, 2))
+    y = rng.standard_normal(n)
+    kern = gp.Kern("rbf", 0.3, 1.0, 0.05)
+    exact = gp.mll_grad(kern, X, y)
+    draws = np.array([gp.same_probe_grad(kern, X, y, probes.rademacher(1000 + s, n, 8)) for s in range(300)])
+    mean, se = draws.mean(0), draws.std(0, ddof=1) / math.sqrt(len(draws))
+    assert np.all(np.abs(mean - exact) < 4 * se + 1e-12)
+
+
+def test_adjoint_bilinear_matches_definition():
+    rng = np.random.default_rng(12)
+    n, d = 25, 2
+    X = rng.uniform(0, 1, size=(n, d))
+    A, B = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    w = np.array([0.5, -0.2, 1.5])
+    kern = gp.Kern("matern32", np.array([0.3, 0.5]), 1.2, 0.1)
+    th = kern.params(d)
+    # FD of sum_c w_c A_c^T K_y(theta) B_c
+    f = lambda k: float(np.sum((A * w) * (gp.ky_matrix(k, X) @ B)))
+    fd = []
+    for p in range(len(th)):
+        h = 1e-6 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd.append((f(kern.with_params(tp)) - f(kern.with_params(tm))) / (2 * h))
+    np.testing.assert_allclose(gp.adjoint_bilinear(kern, X, A, B, w), fd, rtol=1e-6)
+
+
+# ---------------------------------------------------------------- Krylov
+
+@pytest.mark.parametrize("family", ["rbf", "matern52"])
+def test_cg_equals_cholesky(family):
+    w = inputs.exact1k(n=300)
+    kern = gp.Kern(family, 0.2, 1.0, 0.01)
+    B = np.stack([w.y, np.random.default_rng(0).standard_normal(300)], 1)
+    x, al, be, it = krylov.cg(lambda V: gp.ky_matvec(kern, w.X, V), B, tol=1e-12)
+    np.testing.assert_allclose(x, gp.solve(kern, w.X, B), rtol=1e-9, atol=1e-9 * np.abs(x).max())
+    assert np.all(gp.solve_residual(kern, w.X, B, x) <= 1e-11)
+    # zero right-hand side: zero iterations, zero solution
+    x0, _, _, it0 = krylov.cg(lambda V: gp.ky_matvec(kern, w.X, V), np.zeros(300), tol=1e-6)
+    assert it0[0] == 0 and not x0.any()
+
+
+def test_cg_tridiagonal_equals_lanczos():
+    rng = np.random.default_rng(21)
+    n = 200
+    X = rng.uniform(0, 1, size=(n, 2))
+    kern = gp.Kern("rbf", 0.25, 1.0, 0.05)
+    A = gp.ky_matrix(kern, X)
+    z = np.sign(rng.standard_normal(n))
+    # short run: plain CG keeps its residuals orthogonal to working accuracy here
+    m = 8
+    _, al, be, _ = krylov.cg(lambda V: A @ V, z, tol=0.0, max_iter=m)
+    dc, oc = krylov.cg_to_tridiag(al[0], be[0])
+    dl, ol = krylov.lanczos(lambda v: A @ v, z, m)
+    np.testing.assert_allclose(dc, dl, rtol=1e-8)
+    np.testing.assert_allclose(np.abs(oc), np.abs(ol), rtol=1e-8)
+
+
+def test_slq_converged_equals_exact_quadratic_form():
+    rng = np.random.default_rng(22)
+    n = 150
+    X = rng.uniform(0, 1, size=(n, 2))
+    kern = gp.Kern("matern52", 0.3, 1.0, 0.05)
+    A = gp.ky_matrix(kern, X)
+    Z = probes.rademacher(77, n, 4)
+    # exact z^T log(A) z by a second library route (matrix logarithm)
+    L = scipy.linalg.logm(A).real
+    exact = np.einsum("ic,ij,jc->c", Z, L, Z)
+    np.testing.assert_allclose(krylov.quadform_log(A, Z), exact, rtol=1e-9)
+    _, q, it = krylov.slq_logdet(lambda V: A @ V, Z, tol=1e-12)
+    np.testing.assert_allclose(q, exact, rtol=1e-8)
+    # Lanczos run to m = n reproduces it as well
+    dl, ol = krylov.lanczos(lambda v: A @ v, Z[:, 0], n)
+    assert krylov.quadrature(dl, ol, float(Z[:, 0] @ Z[:, 0])) == pytest.approx(exact[0], rel=1e-8)
+
+
+def test_slq_unbiased_for_logdet():
+    rng = np.random.default_rng(23)
+    n = 120
+    X = rng.uniform(0, 1, size=(n, 2))
+    kern = gp.Kern("rbf", 0.2, 1.0, 0.05)
+    A = gp.ky_matrix(kern, X)
+    Z = probes.rademacher(5, n, 400)
+    q = krylov.quadform_log(A, Z)
+    exact = float(np.linalg.slogdet(A)[1])
+    assert abs(q.mean() - exact) < 4 * q.std(ddof=1) / math.sqrt(len(q))
+    assert gp.logdet(kern, X) == pytest.approx(exact, rel=1e-12)
+
+
+# ---------------------------------------------------------------- probes, bf16
+
+def _golden_splitmix():
+    out, seed = {}, None
+    with open(os.path.join(HERE, "golden", "splitmix64.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("seed"):
+                seed = int(line.split()[1])
+                out[seed] = []
+            else:
+                out[seed].append(int(line))
+    return out
+
+
+def test_splitmix64_published_vectors():
+    for seed, vals in _golden_splitmix().items():
+        assert probes.stream(seed, len(vals)) == vals
+
+
+def test_rademacher_counter_layout():
+    seed, n, p = 300, 7, 3
+    Z = probes.rademacher(seed, n, p)
+    s = probes.stream(seed, n * p)
+    for c in range(p):
+        for j in range(n):
+            assert Z[j, c] == (1.0 if s[c * n + j] >> 63 == 0 else -1.0)
+    big = probes.rademacher(1, 4000, 8)
+    assert set(np.unique(big)) == {-1.0, 1.0}
+    assert abs(big.mean()) < 0.03
+
+
+def test_bf16_rounding():
+    one = np.float32(1.0)
+    tie_even = np.float32(1.0 + 2.0 ** -8)            # halfway between 1 and 1+2^-7 -> 1
+    tie_odd = np.float32(1.0 + 3 * 2.0 ** -8)         # halfway between 1+2^-7 and 1+2^-6 -> 1+2^-6
+    above = np.float32(1.0 + 2.0 ** -8 + 2.0 ** -20)  # just above the tie -> 1+2^-7
+    got = bf16.round_bf16(np.array([one, tie_even, tie_odd, above, -tie_odd]))
+    np.testing.assert_array_equal(got, np.array([1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -(1 + 2.0 ** -6)],
+                                                np.float32))
+    # agree with the library conversion on random data
+    a = np.random.default_rng(0).standard_normal(100000).astype(np.float32) * 10
+    lib = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(bf16.round_bf16(a), lib)
+    hi, lo = bf16.split_bf16(a)
+    assert np.all(np.abs(a - hi - lo) <= np.abs(a) * 2.0 ** -15)
