@@ -1,0 +1,165 @@
+"""Benchmark: one step = the whole GP hot path on the 100k workload.
+
+Workload (synthetic): N = 100000, d = 4, X ~ U[-1,1]^4, RBF l = 0.3, s^2 = 1,
+sigma^2 = 0.01, y = sum_k sin(pi x_k) + N(0, 0.1^2), 32 Rademacher probes.
+One step runs, on inputs already resident in HBM:
+  mll_and_grad  -- prescale, batched CG on [y, Z] (t = 33) to a recomputed
+                   residual <= 1e-6 with refinement, stochastic Lanczos
+                   log-determinant, MLL, and the adjoint gradient pass;
+  predict_mean  -- mu = K(X*, X) alpha at 2000 test points.
+`value` is kernel entries generated per second over the timed steps (every
+entry sweep counted once per launch).  The line also carries the CG solve
+time, the MLL+grad time, the roofline of the dominant kernel (the FP32
+entry sweep, timed live with HIP events on its launch stream) and the
+oracle's host throughput on a bounded sample.
+
+python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x2] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (packed FP32 FMA)
+METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
+
+
+def cpu_baseline(w, rows: int) -> dict:
+    """Oracle FP64 K_y V on a bounded row sample of the step's t = 33 product."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gp
+    k = gp.Kern(w.family, w.lengthscale, w.outputscale, w.noise)
+    V = np.concatenate([w.y[:, None], w.Z], axis=1).astype(np.float64)
+    sel = np.random.default_rng(0).choice(w.n, size=rows, replace=False)
+    t0 = time.perf_counter()
+    gp.ky_matvec_rows(k, w.X, V, sel)
+    dt = time.perf_counter() - t0
+    blas = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
+    return {"value": rows * w.n / dt, "unit": "entries/s", "cores": max(blas) if blas else 1,
+            "kind": "oracle",
+            "sample": f"FP64 K_y V for {rows} of {w.n} rows, t=33 (the step's product); "
+                      f"{dt:.1f} s; numpy elementwise work is single-threaded, the BLAS product "
+                      f"uses the reported threads"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of the path is a design note, not built", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+
+    torch.cuda.set_device(0)
+    w = inputs.rbf100k()
+    kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
+    X = torch.from_numpy(w.X).cuda()
+    y = torch.from_numpy(w.y).cuda()
+    Z = torch.from_numpy(w.Z).cuda()
+    Xs = torch.from_numpy(w.Xs).cuda()
+    torch.cuda.synchronize()
+
+    def step():
+        r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=args.precision, want_alpha=True)
+        mu = mfgp.predict_mean(kern, X, Xs, r["alpha"].float())
+        return r, mu
+
+    for i in range(args.warmup):
+        print(f"[bench] warmup step {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+
+    mfgp.timing_enable(True)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        results.append(step())
+        torch.cuda.synchronize()
+        print(f"[bench] timed step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    allk = mfgp.timing_read(-1)
+    f32 = mfgp.timing_read(mfgp.SWEEP_F32)
+    f64 = mfgp.timing_read(mfgp.SWEEP_F64)
+    adj = mfgp.timing_read(mfgp.SWEEP_ADJOINT)
+    mfma = mfgp.timing_read(mfgp.SWEEP_MFMA)
+    ph = mfgp.timing_phases()
+    mfgp.timing_enable(False)
+
+    r = results[-1][0]
+    info = r["info"]
+    dom = mfma if args.precision != "fp32" else f32
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": allk["entries"] / elapsed,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": "rbf100k", "n": w.n, "d": w.d, "family": "rbf", "lengthscale": 0.3,
+                   "noise": 0.01, "probes": 32, "t": 33, "tol": 1e-6, "test_points": w.Xs.shape[0],
+                   "precision": args.precision},
+        "cg_solve_s": ph["cg_ms"] * 1e-3 / args.steps,
+        "mll_grad_s": (ph["cg_ms"] + ph["slq_ms"] + ph["adjoint_ms"]) * 1e-3 / args.steps,
+        "slq_s": ph["slq_ms"] * 1e-3 / args.steps,
+        "adjoint_s": ph["adjoint_ms"] * 1e-3 / args.steps,
+        "cg_iters_max": max(i["iters"] for i in info),
+        "cg_refinements_max": max(i["refinements"] for i in info),
+        "rel_resid_true_max": max(i["rel_resid_true"] for i in info),
+        "mll": r["mll"],
+        "logdet": r["logdet"],
+        "matvec_sweeps_per_step": f32["launches"] / args.steps,
+        "matvec_sweep_ms_avg": f32["ms"] / max(f32["launches"], 1),
+        "matvec_entries_per_s": f32["entries"] / (f32["ms"] * 1e-3) if f32["ms"] > 0 else 0.0,
+        "sweep_ms": {"fp32": f32["ms"], "fp64acc": f64["ms"], "adjoint": adj["ms"], "mfma": mfma["ms"]},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "sweep_f32_kernel<RBF, d=4, t=33>" if args.precision == "fp32" else "mfma sweep",
+            "flop_per_entry": 3 * 4 + 1 + 2 * 33,
+            "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,229 @@
+/*
+ * mfgp.h -- C ABI of the matrix-free Gaussian-process library for AMD MI355X (gfx950).
+ *
+ * The library computes, without ever storing the N x N kernel matrix,
+ *   K_y V = k(X, X) V + sigma^2 V                       (LightGP Sec. 2, "CG-based inference":
+ *                                                          the product CG needs; Sec. 4.1 Table 3)
+ * and the conjugate-gradient GP solve built on it: solve, predictive mean,
+ * log marginal likelihood and its gradient (Sec. 2, the predictive mean and
+ * log p(y|X) formulas; Sec. 3 "Inference": CG with a stochastic Lanczos
+ * log-determinant).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Layout     X is [n, d] row-major float32.  Right-hand-side blocks (V, B, Z, A)
+ *            are [n, t] row-major: column c of row j is element j*t + c.
+ * Memory     Every array argument is caller-owned DEVICE memory unless marked
+ *            "host".  The library never allocates: scratch comes from the
+ *            caller's workspace `ws` of `ws_bytes` bytes (size it with
+ *            mfgp_workspace_bytes; 256-byte alignment is handled inside).  No
+ *            pointer is kept after a call returns.
+ * Streams    `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *            that return only device results are asynchronous on it; calls
+ *            that return host values synchronise it before returning.
+ * Errors     Every call returns an mfgp_status.  Argument errors are detected
+ *            on the host before anything is launched and leave the outputs
+ *            untouched.  No exception crosses the ABI.  MFGP_ERR_HIP carries
+ *            the HIP error code in mfgp_last_hip_error() (thread-local).
+ * Kernels    family RBF:         k = s2 exp(-r^2 / 2)
+ *                   MATERN12:    k = s2 exp(-rho)
+ *                   MATERN32:    k = s2 (1 + sqrt3 rho) exp(-sqrt3 rho)
+ *                   MATERN52:    k = s2 (1 + sqrt5 rho + 5 rho^2 / 3) exp(-sqrt5 rho)
+ *            with r^2 = sum_k ((x_k - x'_k) / l_k)^2, rho = sqrt(r^2), one
+ *            lengthscale per dimension when `ard` is set and lengthscale[0]
+ *            for all dimensions otherwise (the families of Sec. 3 "Kernels";
+ *            s2 is the Scale variance, sigma^2 the noise variance of Sec. 2).
+ * Gradients  are with respect to the positive parameters in the order
+ *            [l_1 .. l_d] (ard) or [l] (shared), then s2, then sigma^2.
+ * Threads    The library is reentrant: no mutable globals besides the
+ *            thread-local last HIP error.
+ */
+#ifndef MFGP_H
+#define MFGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFGP_MAX_D 8
+#define MFGP_MAX_T 64
+
+typedef enum {
+    MFGP_RBF = 0,
+    MFGP_MATERN12 = 1,
+    MFGP_MATERN32 = 2,
+    MFGP_MATERN52 = 3
+} mfgp_family;
+
+/* Arithmetic of the K-tile x V contraction (kernel entries are always float32). */
+typedef enum {
+    MFGP_FP32 = 0,    /* FP32 vector ALU, FP32 accumulation                        */
+    MFGP_BF16X1 = 1,  /* entries and V rounded to bf16, MFMA, FP32 accumulation    */
+    MFGP_BF16X2 = 2   /* bf16 hi/lo split of both operands (3 MFMA products)        */
+} mfgp_precision;
+
+typedef enum {
+    MFGP_OK = 0,
+    MFGP_ERR_ARG = 1,          /* invalid argument, detected before any launch       */
+    MFGP_ERR_HIP = 2,          /* a HIP runtime call failed, see mfgp_last_hip_error */
+    MFGP_ERR_WORKSPACE = 3,    /* ws_bytes below mfgp_workspace_bytes(...)           */
+    MFGP_NOT_CONVERGED = 4,    /* CG stopped at max_iter / max_refine; best iterate written */
+    MFGP_BREAKDOWN = 5,        /* p^T K_y p <= 0 or non-finite; best iterate written  */
+    MFGP_UNSUPPORTED = 6       /* valid but not provided (e.g. d > MFGP_MAX_D)        */
+} mfgp_status;
+
+/* Workspace query operation codes. */
+typedef enum {
+    MFGP_OP_MATVEC = 0,
+    MFGP_OP_CG = 1,
+    MFGP_OP_PREDICT = 2,
+    MFGP_OP_MLL = 3,
+    MFGP_OP_ADJOINT = 4,
+    MFGP_OP_RESIDUAL = 5
+} mfgp_op;
+
+/* Kernel hyperparameters (host struct, passed by pointer). */
+typedef struct {
+    int32_t family;                       /* mfgp_family                               */
+    int32_t d;                            /* input dimension, 1..MFGP_MAX_D             */
+    int32_t ard;                          /* nonzero: one lengthscale per dimension     */
+    float lengthscale[MFGP_MAX_D];        /* > 0, finite; [0] only when ard == 0        */
+    float outputscale;                    /* s2 > 0                                     */
+    float noise;                          /* sigma^2 >= 0 (> 0 for solves)              */
+} mfgp_kernel;
+
+/* Conjugate-gradient options (host struct). */
+typedef struct {
+    double tol;           /* per column ||b - K_y x||_2 / ||b||_2 target, > 0 (e.g. 1e-6)      */
+    int32_t max_iter;     /* CG iterations per column over all refinement cycles; 0 = min(n, 20000) */
+    int32_t check_every;  /* iterations between host convergence checks; 0 = automatic       */
+    int32_t max_refine;   /* residual recomputations / restarts allowed; < 0 = default 8      */
+    int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries, FP64 sums) */
+    int32_t warm_start;   /* nonzero: Xsol holds the initial guess x0 on entry                */
+    int32_t pad_;
+    uint64_t probe_seed;  /* seed of the SplitMix64 probes when Z == NULL (mll_and_grad)      */
+} mfgp_cg_opts;
+
+/* Per-column CG report (host array, one entry per column). */
+typedef struct {
+    int32_t iters;                /* CG iterations performed (all cycles)                   */
+    int32_t lanczos_len;          /* iterations of the first cycle (SLQ length m)           */
+    int32_t refinements;          /* restarts from a recomputed residual                    */
+    int32_t status;               /* mfgp_status of this column                             */
+    double rel_resid_recurrence;  /* ||r_k||/||b|| carried by the recurrence at exit        */
+    double rel_resid_true;        /* recomputed ||b - K_y x||/||b||, K_y with FP32 entries,
+                                     FP64 accumulation, x in FP64                          */
+} mfgp_cg_info;
+
+/* Bytes of workspace a call needs.  op: mfgp_op; n rows; d dims; t columns
+ * (matvec/cg/adjoint/residual), test points m for MFGP_OP_PREDICT passed in t
+ * as the column count of alpha and in max_iter as m; number of probes + 1 for
+ * MFGP_OP_MLL; max_iter as passed in mfgp_cg_opts (0 = default).  Returns 0 for
+ * invalid sizes. */
+size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
+                            int32_t max_iter);
+
+/* KV = K_y V = s2 k(X, X) V + sigma^2 V  (Sec. 2; Sec. 4.1 Table 3, the fused
+ * matrix-free product).  X [n,d], V [n,t], KV [n,t] (must not alias V).
+ * precision: mfgp_precision.  Asynchronous. */
+int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
+                       int32_t t, float* KV, int32_t precision, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* R = B - K_y Xsol with the library's FP32 kernel entries accumulated in FP64
+ * (the recomputed residual of the solver).  B [n,t] float32, Xsol [n,t]
+ * float64, R [n,t] float64 (device).  rel (host, optional, [t]) receives
+ * ||R_c||_2 / ||B_c||_2; when rel is non-NULL the call synchronises. */
+int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const float* B,
+                  const double* Xsol, int32_t t, double* R, double* rel, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Solve K_y Xsol = B column by column with unpreconditioned conjugate
+ * gradients (Sec. 2 "CG-based inference"; Sec. 5: the plain CG loop), started
+ * at x0 = 0 (or at Xsol when opts->warm_start), FP32 vectors and FP64 scalars,
+ * with the true residual recomputed (mfgp_residual) once the recurrence meets
+ * tol, and restarts from it until it does (iterative refinement).  Columns
+ * converge independently and freeze.
+ * B [n,t] float32; Xsol [n,t] float64 (in: x0 if warm_start, out: solution).
+ * info: host [t].  lanczos: optional device [t][max_iter][2] float64 receiving
+ * (alpha_j, beta_j) of each column's first cycle (the stochastic-Lanczos input);
+ * entries past info[c].lanczos_len are unspecified.  Synchronises.  Returns
+ * the worst column status. */
+int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const float* B,
+                  int32_t t, double* Xsol, const mfgp_cg_opts* opts, mfgp_cg_info* info,
+                  double* lanczos, void* ws, size_t ws_bytes, void* stream);
+
+/* MU = s2 k(Xs, X) A  (Sec. 2: mu_* = K_*f (K_ff + sigma^2 I)^{-1} y with
+ * A = the solve's result).  Xs [m,d], A [n,t] float32, MU [m,t].  No noise
+ * term.  Asynchronous. */
+int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs,
+                      int64_t m, const float* A, int32_t t, float* MU, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Stochastic Lanczos quadrature of one probe from its CG coefficients
+ * (host only, no GPU): with T the Lanczos tridiagonal that the coefficients
+ * define (T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_j,j+1 = sqrt(beta_j)/alpha_j),
+ * *q = znorm2 * e_1^T log(T) e_1.  coeffs: host [m][2] (alpha_j, beta_j). */
+int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q);
+
+/* Log marginal likelihood and gradient (Sec. 2: log p(y|X) =
+ * -1/2 [y^T K_y^{-1} y + log|K_y| + N log 2 pi]; Sec. 3: CG with a stochastic
+ * Lanczos log-determinant; Sec. 4.3: Rademacher probes).
+ * One batched CG solve of [y, Z] (t = num_probes + 1 columns) gives
+ * alpha = K_y^{-1} y, U = K_y^{-1} Z and per-probe Lanczos coefficients;
+ * log|K_y| ~= (1/p) sum_c ||z_c||^2 e_1^T log(T_c) e_1; the gradient is
+ * 1/2 alpha^T dK alpha - 1/(2p) sum_c u_c^T dK z_c, its lengthscale and
+ * outputscale parts from one fused adjoint pass over all kernel entries.
+ * y [n]; Z [n,p] (+-1 probes) or NULL to draw them on the device from
+ * opts->probe_seed (SplitMix64, see mfgp_rademacher).  Host outputs: mll,
+ * logdet (optional), grad (optional, [n_theta]); device output alpha_out
+ * (optional, [n] float64); info (optional, host [p+1]).  Synchronises. */
+int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const float* y,
+                      int32_t num_probes, const float* Z, const mfgp_cg_opts* opts, double* mll,
+                      double* logdet, double* grad, double* alpha_out, mfgp_cg_info* info,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the operator:
+ * grad[theta] = sum_c colw[c] A_c^T (dK_y/dtheta) B_c for every parameter
+ * (lengthscales, s2, sigma^2).  A, B [n,t] float32; colw host [t]; grad host
+ * [n_theta].  Synchronises. */
+int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, const float* A,
+                        const float* B, int32_t t, const double* colw, double* grad, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Z [n,p] float32 Rademacher probes: entry (j, c) is +1 when bit 63 of
+ * SplitMix64 output number c*n + j + 1 of the stream seeded with `seed` is
+ * clear, else -1 (Steele, Lea & Flood 2014).  Asynchronous. */
+int mfgp_rademacher(uint64_t seed, int64_t n, int32_t p, float* Z, void* stream);
+
+/* Kernel timing (for benchmarks).  While enabled on the calling thread, every
+ * entry-sweep launch (the fused K-tile kernels) is bracketed by HIP events
+ * recorded on the stream the sweep is launched on, and its algorithmic work
+ * is tallied: entries generated and FLOP by the per-entry counts (RBF
+ * 3d+1+2t, Matern-1/2 3d+2+2t, Matern-3/2 3d+5+2t, Matern-5/2 3d+7+2t,
+ * adjoint 5d+4+2t; exp and sqrt count as one).  Sweep kinds: 0 FP32 sweeps
+ * (matvec, CG, predict), 1 FP64-accumulated residual sweeps, 2 adjoint
+ * sweeps, 3 BF16-MFMA sweeps; -1 selects all.  mfgp_mll_and_grad also
+ * records the host wall time of its phases (CG solve, quadrature, adjoint).
+ * mfgp_timing_read synchronises the recorded events and returns totals since
+ * the last enable (host outputs, any may be NULL).  Thread-local state. */
+int mfgp_timing_enable(int32_t on);
+int mfgp_timing_read(int32_t kind, double* sweep_ms, int64_t* launches, double* entries,
+                     double* flops);
+int mfgp_timing_phases(double* cg_ms, double* slq_ms, double* adjoint_ms);
+
+/* Number of gradient entries for a kernel: (ard ? d : 1) + 2. */
+int mfgp_num_params(const mfgp_kernel* kern);
+
+const char* mfgp_status_string(int status);
+int mfgp_last_hip_error(void);
+int mfgp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFGP_H */

@@ -1,0 +1,500 @@
+// C-ABI entry points (declared in include/mfgp.h): argument validation on the
+// host, workspace carving, and orchestration of the kernels.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "cg.hpp"
+#include "internal.hpp"
+
+namespace mfgp {
+
+static thread_local int g_last_hip = 0;
+void set_last_hip_error(hipError_t e) { g_last_hip = static_cast<int>(e); }
+
+int slq_quadrature(const double* coeffs, int m, double znorm2, double* q);
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void pack_yz_kernel(const float* __restrict__ y, const float* __restrict__ Z, int64_t n,
+                               int p, float* __restrict__ out) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int t = p + 1;
+    if (idx >= n * t) return;
+    const int64_t i = idx / t;
+    const int c = static_cast<int>(idx % t);
+    out[idx] = c == 0 ? y[i] : Z[i * p + (c - 1)];
+}
+
+// dst[i * t] = fl32(src[i * t])  (column 0 of an [n, t] block)
+__global__ void set_col0_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n,
+                                int t) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i * t] = static_cast<float>(src[i * t]);
+}
+
+__global__ void copy_col0_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n,
+                                 int t) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i * t];
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output k of the stream seeded with s
+// is mix(s + k * 0x9E3779B97F4A7C15); entry (j, c) uses k = c n + j + 1.
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void rademacher_kernel(uint64_t seed, int64_t n, int p, float* __restrict__ Z) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * p) return;
+    const int64_t j = idx / p;
+    const int64_t c = idx % p;
+    const uint64_t k = static_cast<uint64_t>(c) * static_cast<uint64_t>(n) + static_cast<uint64_t>(j) + 1ull;
+    const uint64_t z = splitmix_mix(seed + k * 0x9E3779B97F4A7C15ull);
+    Z[idx] = (z >> 63) ? -1.0f : 1.0f;
+}
+
+hipError_t launch_rademacher(uint64_t seed, int64_t n, int p, float* Z, hipStream_t s) {
+    const int64_t total = n * p;
+    hipLaunchKernelGGL(rademacher_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                       0, s, seed, n, p, Z);
+    return hipGetLastError();
+}
+
+static inline unsigned nb(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
+
+// ---------------------------------------------------------------- validation
+
+static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+static int check_kernel(const mfgp_kernel* k, bool need_noise) {
+    if (!k) return MFGP_ERR_ARG;
+    if (k->family < MFGP_RBF || k->family > MFGP_MATERN52) return MFGP_ERR_ARG;
+    if (k->d < 1) return MFGP_ERR_ARG;
+    if (k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;
+    const int nl = k->ard ? k->d : 1;
+    for (int q = 0; q < nl; ++q)
+        if (!finite_pos(k->lengthscale[q])) return MFGP_ERR_ARG;
+    if (!finite_pos(k->outputscale)) return MFGP_ERR_ARG;
+    if (!std::isfinite(k->noise) || k->noise < 0.0f) return MFGP_ERR_ARG;
+    if (need_noise && !(k->noise > 0.0f)) return MFGP_ERR_ARG;
+    return MFGP_OK;
+}
+
+static int check_opts(const mfgp_cg_opts* o) {
+    if (!o) return MFGP_ERR_ARG;
+    if (!std::isfinite(o->tol) || !(o->tol > 0.0)) return MFGP_ERR_ARG;
+    if (o->max_iter < 0) return MFGP_ERR_ARG;
+    if (o->precision < MFGP_FP32 || o->precision > MFGP_BF16X2) return MFGP_ERR_ARG;
+    if (!precision_supported(o->precision)) return MFGP_UNSUPPORTED;
+    return MFGP_OK;
+}
+
+static int default_max_iter(int64_t n, int max_iter) {
+    if (max_iter > 0) return max_iter;
+    return static_cast<int>(n < 20000 ? n : 20000);
+}
+
+static int hip_fail(hipError_t e) {
+    set_last_hip_error(e);
+    return MFGP_ERR_HIP;
+}
+
+#define ABI_CHECK(expr)                    \
+    do {                                   \
+        hipError_t e_ = (expr);            \
+        if (e_ != hipSuccess) return hip_fail(e_); \
+    } while (0)
+
+// ---------------------------------------------------------------- carving (shared by size queries)
+
+struct MatvecWs { float* U; void* scratch; };
+static MatvecWs carve_matvec(Carver& cv, int64_t n, int d, int t, int precision) {
+    MatvecWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    if (precision == MFGP_FP32)
+        w.scratch = cv.take<float>(apply_scratch_floats(n, n, t));
+    else
+        w.scratch = cv.take<char>(mfma_scratch_bytes(n, n, t, precision));
+    return w;
+}
+
+struct ResidWs { float* U; double* scratch; double* dots; double* tmp; };
+static ResidWs carve_resid(Carver& cv, int64_t n, int d, int t) {
+    ResidWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.scratch = cv.take<double>(resid_scratch_doubles(n, t));
+    w.dots = cv.take<double>(dots_scratch_doubles(n, t));
+    w.tmp = cv.take<double>(2 * static_cast<size_t>(t));
+    return w;
+}
+
+struct CgWs { float* U; CgBufs b; };
+static CgWs carve_cgws(Carver& cv, int64_t n, int d, int t, int precision) {
+    CgWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.b = carve_cg(cv, n, t, precision);
+    return w;
+}
+
+struct PredictWs { float* U; float* Us; float* scratch; };
+static PredictWs carve_predict(Carver& cv, int64_t n, int d, int64_t m, int t) {
+    PredictWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.Us = cv.take<float>(static_cast<size_t>(m) * d);
+    w.scratch = cv.take<float>(apply_scratch_floats(m, n, t));
+    return w;
+}
+
+struct AdjWs { float* U; double* scratch; double* dots; double* tmp; };
+static AdjWs carve_adjoint(Carver& cv, int64_t n, int d, int t) {
+    AdjWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.scratch = cv.take<double>(adjoint_scratch_doubles(n, d, t));
+    w.dots = cv.take<double>(dots_scratch_doubles(n, t));
+    w.tmp = cv.take<double>(2 * static_cast<size_t>(t) + 8);
+    return w;
+}
+
+struct MllWs {
+    float* U; float* Bm; double* X64; float* Zgen; double* coeff; double* tmp; CgBufs b;
+    double* adj;
+};
+static MllWs carve_mll(Carver& cv, int64_t n, int d, int t, int precision, int max_iter) {
+    MllWs w;
+    const size_t nt = static_cast<size_t>(n) * t;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.Bm = cv.take<float>(nt);
+    w.X64 = cv.take<double>(nt);
+    w.Zgen = cv.take<float>(static_cast<size_t>(n) * (t - 1));
+    w.coeff = cv.take<double>(static_cast<size_t>(t) * max_iter * 2);
+    w.tmp = cv.take<double>(4 * static_cast<size_t>(t) + 8);
+    w.b = carve_cg(cv, n, t, precision);
+    w.adj = cv.take<double>(adjoint_scratch_doubles(n, d, t));
+    return w;
+}
+
+// Lengthscale factor F_k of the adjoint sums (see adjoint.hip).
+static double lengthscale_factor(int family, double l) {
+    const double c = family_scale(family);
+    switch (family) {
+        case MFGP_RBF: return 1.0 / (c * c * l);
+        case MFGP_MATERN12: return 1.0 / (c * l);
+        case MFGP_MATERN32: return 3.0 / (c * c * l);
+        default: return (5.0 / 3.0) / (c * c * l);
+    }
+}
+
+// grad[0..nl-1] lengthscales, grad[nl] s2 from the adjoint sums G_k, G_s.
+static void grad_from_sums(const Operator& op, int ard, const double* G, double* grad) {
+    const int d = op.d;
+    double shared = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double gk = static_cast<double>(op.s2) * lengthscale_factor(op.family, op.ls[k]) * G[k];
+        if (ard)
+            grad[k] = gk;
+        else
+            shared += gk;
+    }
+    const int nl = ard ? d : 1;
+    if (!ard) grad[0] = shared;
+    grad[nl] = G[d];
+}
+
+}  // namespace mfgp
+
+using namespace mfgp;
+
+extern "C" {
+
+int mfgp_version(void) { return 100; }
+
+int mfgp_last_hip_error(void) { return g_last_hip; }
+
+const char* mfgp_status_string(int status) {
+    switch (status) {
+        case MFGP_OK: return "ok";
+        case MFGP_ERR_ARG: return "invalid argument";
+        case MFGP_ERR_HIP: return "HIP runtime error";
+        case MFGP_ERR_WORKSPACE: return "workspace too small";
+        case MFGP_NOT_CONVERGED: return "not converged";
+        case MFGP_BREAKDOWN: return "CG breakdown";
+        case MFGP_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+int mfgp_num_params(const mfgp_kernel* k) {
+    if (!k || k->d < 1) return 0;
+    return (k->ard ? k->d : 1) + 2;
+}
+
+size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
+                            int32_t max_iter) {
+    if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_BF16X2) return 0;
+    Carver cv(nullptr);
+    switch (op) {
+        case MFGP_OP_MATVEC: carve_matvec(cv, n, d, t, precision); break;
+        case MFGP_OP_RESIDUAL: carve_resid(cv, n, d, t); break;
+        case MFGP_OP_CG: carve_cgws(cv, n, d, t, precision); break;
+        case MFGP_OP_PREDICT:
+            if (max_iter < 1) return 0;
+            carve_predict(cv, n, d, max_iter, t);
+            break;
+        case MFGP_OP_ADJOINT: carve_adjoint(cv, n, d, t); break;
+        case MFGP_OP_MLL:
+            if (t < 2) return 0;
+            carve_mll(cv, n, d, t, precision, default_max_iter(n, max_iter));
+            break;
+        default: return 0;
+    }
+    return cv.off + 256;
+}
+
+int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
+                       int32_t t, float* KV, int32_t precision, void* ws, size_t ws_bytes,
+                       void* stream) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !V || !KV || !ws || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
+    if (precision < MFGP_FP32 || precision > MFGP_BF16X2) return MFGP_ERR_ARG;
+    if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, precision, 0))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    MatvecWs w = carve_matvec(cv, n, kern->d, t, precision);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    if (precision == MFGP_FP32)
+        ABI_CHECK(apply_f32(op, op.U, n, V, t, KV, true, V, static_cast<float*>(w.scratch), s));
+    else
+        ABI_CHECK(apply_mfma(op, op.U, n, V, t, KV, true, V, precision, w.scratch, s));
+    return MFGP_OK;
+}
+
+int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const float* B,
+                  const double* Xsol, int32_t t, double* R, double* rel, void* ws,
+                  size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !B || !Xsol || !R || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_RESIDUAL, n, kern->d, t, 0, 0))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    ResidWs w = carve_resid(cv, n, kern->d, t);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    ABI_CHECK(residual_f64(op, B, Xsol, t, R, w.scratch, s));
+    if (rel) {
+        ABI_CHECK(col_dots_dd(R, R, n, t, w.tmp, w.dots, s));
+        ABI_CHECK(col_dots_ff(B, B, n, t, w.tmp + t, w.dots, s));
+        std::vector<double> h(2 * t);
+        ABI_CHECK(hipMemcpyAsync(h.data(), w.tmp, 2 * t * sizeof(double), hipMemcpyDeviceToHost, s));
+        ABI_CHECK(hipStreamSynchronize(s));
+        for (int c = 0; c < t; ++c) rel[c] = h[t + c] > 0.0 ? std::sqrt(h[c] / h[t + c]) : 0.0;
+    }
+    return MFGP_OK;
+}
+
+int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const float* B, int32_t t,
+                  double* Xsol, const mfgp_cg_opts* opts, mfgp_cg_info* info, double* lanczos,
+                  void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !B || !Xsol || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_CG, n, kern->d, t, opts->precision, opts->max_iter))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    CgWs w = carve_cgws(cv, n, kern->d, t, opts->precision);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    return cg_run(op, B, t, Xsol, *opts, info, lanczos, max_iter, w.b, s);
+}
+
+int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs,
+                      int64_t m, const float* A, int32_t t, float* MU, void* ws, size_t ws_bytes,
+                      void* stream) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !Xs || !A || !MU || !ws || n < 1 || m < 1 || t < 1) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_PREDICT, n, kern->d, t, 0, static_cast<int32_t>(m)))
+        return MFGP_ERR_WORKSPACE;
+    if (m > 0x7fffffff) return MFGP_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    PredictWs w = carve_predict(cv, n, kern->d, m, t);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    ABI_CHECK(launch_prescale(Xs, m, kern->d, op.fac, w.Us, s));
+    ABI_CHECK(apply_f32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, s));
+    return MFGP_OK;
+}
+
+int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q) {
+    if (!coeffs || !q || m < 1 || !(znorm2 >= 0.0)) return MFGP_ERR_ARG;
+    return slq_quadrature(coeffs, m, znorm2, q);
+}
+
+int mfgp_rademacher(uint64_t seed, int64_t n, int32_t p, float* Z, void* stream) {
+    if (!Z || n < 1 || p < 1) return MFGP_ERR_ARG;
+    ABI_CHECK(launch_rademacher(seed, n, p, Z, static_cast<hipStream_t>(stream)));
+    return MFGP_OK;
+}
+
+int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, const float* A,
+                        const float* B, int32_t t, const double* colw, double* grad, void* ws,
+                        size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !A || !B || !colw || !grad || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_ADJOINT, n, kern->d, t, 0, 0))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    AdjWs w = carve_adjoint(cv, n, kern->d, t);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    double sums[MFGP_MAX_D + 1];
+    ABI_CHECK(adjoint_sums(op, A, B, t, colw, sums, w.scratch, s));
+    ABI_CHECK(col_dots_ff(A, B, n, t, w.tmp, w.dots, s));
+    std::vector<double> ab(t);
+    ABI_CHECK(hipMemcpyAsync(ab.data(), w.tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    ABI_CHECK(hipStreamSynchronize(s));
+    grad_from_sums(op, kern->ard, sums, grad);
+    double sn = 0.0;
+    for (int c = 0; c < t; ++c) sn += colw[c] * ab[c];
+    grad[(kern->ard ? kern->d : 1) + 1] = sn;
+    return MFGP_OK;
+}
+
+int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const float* y,
+                      int32_t num_probes, const float* Z, const mfgp_cg_opts* opts, double* mll,
+                      double* logdet, double* grad, double* alpha_out, mfgp_cg_info* info,
+                      void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !y || !mll || !ws || n < 1 || num_probes < 1) return MFGP_ERR_ARG;
+    const int p = num_probes;
+    const int t = p + 1;
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MLL, n, kern->d, t, opts->precision, max_iter))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    MllWs w = carve_mll(cv, n, kern->d, t, opts->precision, max_iter);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    const float* Zp = Z;
+    if (!Zp) {
+        ABI_CHECK(launch_rademacher(opts->probe_seed, n, p, w.Zgen, s));
+        Zp = w.Zgen;
+    }
+    hipLaunchKernelGGL(pack_yz_kernel, dim3(nb(n * t)), dim3(256), 0, s, y, Zp, n, p, w.Bm);
+    ABI_CHECK(hipGetLastError());
+
+    using clock = std::chrono::steady_clock;
+    auto ms_since = [](clock::time_point a) {
+        return std::chrono::duration<double, std::milli>(clock::now() - a).count();
+    };
+    if (timing_on()) ABI_CHECK(hipStreamSynchronize(s));
+    auto t0 = clock::now();
+    std::vector<mfgp_cg_info> inf(t);
+    mfgp_cg_opts o = *opts;
+    o.warm_start = 0;
+    const int cg_status = cg_run(op, w.Bm, t, w.X64, o, inf.data(), w.coeff, max_iter, w.b, s);
+    timing_phase(0, ms_since(t0));
+    t0 = clock::now();
+    if (cg_status == MFGP_ERR_HIP || cg_status == MFGP_ERR_ARG) return cg_status;
+    if (info) std::memcpy(info, inf.data(), t * sizeof(mfgp_cg_info));
+
+    // Column dot products in FP64: b_c^T b_c, x_c^T b_c, x_c^T x_c.
+    double* bb = w.tmp;
+    double* xb = w.tmp + t;
+    double* xx = w.tmp + 2 * t;
+    ABI_CHECK(col_dots_ff(w.Bm, w.Bm, n, t, bb, w.b.dots, s));
+    ABI_CHECK(col_dots_df(w.X64, w.Bm, n, t, xb, w.b.dots, s));
+    ABI_CHECK(col_dots_dd(w.X64, w.X64, n, t, xx, w.b.dots, s));
+    std::vector<double> h(3 * t);
+    ABI_CHECK(hipMemcpyAsync(h.data(), w.tmp, 3 * t * sizeof(double), hipMemcpyDeviceToHost, s));
+    // Lanczos coefficients of the probe columns.
+    std::vector<std::vector<double>> cf(t);
+    for (int c = 1; c < t; ++c) {
+        cf[c].resize(2 * static_cast<size_t>(inf[c].lanczos_len > 0 ? inf[c].lanczos_len : 1));
+        if (inf[c].lanczos_len > 0)
+            ABI_CHECK(hipMemcpyAsync(cf[c].data(), w.coeff + static_cast<size_t>(c) * max_iter * 2,
+                                     2 * inf[c].lanczos_len * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (alpha_out) {
+        hipLaunchKernelGGL(copy_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, alpha_out, n, t);
+        ABI_CHECK(hipGetLastError());
+    }
+    ABI_CHECK(hipStreamSynchronize(s));
+
+    // Stochastic Lanczos quadrature per probe, in parallel host threads.
+    std::vector<double> q(t, 0.0);
+    std::vector<int> qs(t, MFGP_OK);
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
+        std::vector<std::thread> pool;
+        for (int th = 0; th < nth; ++th) {
+            pool.emplace_back([&, th]() {
+                for (int c = 1 + th; c < t; c += nth) {
+                    if (inf[c].lanczos_len < 1) {
+                        qs[c] = MFGP_BREAKDOWN;
+                        continue;
+                    }
+                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, h[c], &q[c]);
+                }
+            });
+        }
+        for (auto& th : pool) th.join();
+    }
+    double ld = 0.0;
+    int slq_status = MFGP_OK;
+    for (int c = 1; c < t; ++c) {
+        ld += q[c];
+        if (qs[c] != MFGP_OK) slq_status = MFGP_BREAKDOWN;
+    }
+    ld /= p;
+    timing_phase(1, ms_since(t0));
+    t0 = clock::now();
+    const double two_pi = 6.283185307179586477;
+    *mll = -0.5 * (h[t + 0] + ld + static_cast<double>(n) * std::log(two_pi));
+    if (logdet) *logdet = ld;
+
+    if (grad) {
+        // A = fl32([alpha, U]) into R, B = [fl32(alpha), Z] into P (CG buffers are free now).
+        float* Ag = w.b.R;
+        float* Bg = w.b.P;
+        ABI_CHECK(f64_to_f32(w.X64, Ag, n * t, s));
+        ABI_CHECK(copy2_f32(w.Bm, Bg, Bg, n * t, s));
+        hipLaunchKernelGGL(set_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, Bg, n, t);
+        ABI_CHECK(hipGetLastError());
+        std::vector<double> colw(t, -0.5 / p);
+        colw[0] = 0.5;
+        double sums[MFGP_MAX_D + 1];
+        ABI_CHECK(adjoint_sums(op, Ag, Bg, t, colw.data(), sums, w.adj, s));
+        grad_from_sums(op, kern->ard, sums, grad);
+        double tr = 0.0;
+        for (int c = 1; c < t; ++c) tr += h[t + c];
+        grad[(kern->ard ? kern->d : 1) + 1] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
+        timing_phase(2, ms_since(t0));
+    }
+    if (cg_status != MFGP_OK) return cg_status;
+    return slq_status;
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Adjoint sweep: sums over all kernel entries of W_ij dk_ij/dtheta with
+// W_ij = sum_c w_c A_ic B_jc, generated per entry and never stored.
+//
+// It gives the vector-Jacobian product  sum_c w_c A_c^T (dK/dtheta) B_c,
+// and with A = [alpha, K_y^{-1} Z], B = [alpha, Z], w = [1/2, -1/(2p), ...]
+// the gradient of the log marginal likelihood
+//   d/dtheta log p(y|X) = 1/2 alpha^T dK alpha - 1/2 tr(K_y^{-1} dK)
+// with the trace replaced by its Rademacher-probe estimate (LightGP Sec. 2,
+// the log p(y|X) formula; Sec. 4.3, Hutchinson with Rademacher probes).  The
+// paper's own optimiser uses finite differences (Sec. 5); this pass replaces
+// the 2P+1 fits by one sweep.
+//
+// In prescaled coordinates (u = x c / l, see common.hpp) with
+// du_k = u_ik - u_jk and q = |u_i - u_j|:
+//   d k / d l_k = s2 * F_k * g(q) * du_k^2   with
+//   RBF         g = 2^(-q^2)               F_k = 1 / (c^2 l_k)
+//   Matern-1/2  g = 2^(-q) / q  (0 at q=0)  F_k = 1 / (c l_k)
+//   Matern-3/2  g = 2^(-q)                 F_k = 3 / (c^2 l_k)
+//   Matern-5/2  g = (1 + q ln2) 2^(-q)     F_k = (5/3) / (c^2 l_k)
+//   d k / d s2  = k^ (unit-outputscale entry)
+// The sweep accumulates G_k = sum_ij W_ij g du_k^2 and G_s = sum_ij W_ij k^;
+// the host applies s2 F_k.  Lane sums are FP32 over one j-range; block,
+// grid and host sums are FP64 in a fixed order.
+#include "internal.hpp"
+#include "sweep_kernels.hpp"
+
+namespace mfgp {
+
+struct ColW {
+    float w[MFGP_MAX_T];
+};
+
+template <int FAM>
+__device__ __forceinline__ void kentry_and_dfac(float d2, float& kv, float& g) {
+    if constexpr (FAM == MFGP_RBF) {
+        kv = __builtin_amdgcn_exp2f(-d2);
+        g = kv;
+    } else {
+        const float q = __builtin_amdgcn_sqrtf(d2);
+        const float e = __builtin_amdgcn_exp2f(-q);
+        if constexpr (FAM == MFGP_MATERN12) {
+            kv = e;
+            g = q > 0.0f ? e * __builtin_amdgcn_rcpf(q) : 0.0f;
+        } else if constexpr (FAM == MFGP_MATERN32) {
+            kv = fmaf(q, kLn2, 1.0f) * e;
+            g = e;
+        } else {
+            kv = fmaf(fmaf(q, kLn2Sq3, kLn2), q, 1.0f) * e;
+            g = fmaf(q, kLn2, 1.0f) * e;
+        }
+    }
+}
+
+template <int FAM, int D, int TB>
+__global__ __launch_bounds__(kBlock) void adjoint_kernel(
+    const float* __restrict__ U, const float* __restrict__ A, int lda, int c0, ColW w,
+    const float* __restrict__ B, int64_t n, int chunks, int64_t jchunk,
+    double* __restrict__ partial) {
+    // B is a packed [n, TB] block; A is read at columns c0 .. c0+TB-1 of [n, lda].
+    __shared__ double red[(D + 1) * (kBlock / 64)];
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int64_t i = static_cast<int64_t>(rb) * kBlock + threadIdx.x;
+    const int64_t ii = i < n ? i : n - 1;
+    float ui[D], ai[TB];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ui[k] = U[ii * D + k];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) ai[c] = i < n ? A[ii * lda + c0 + c] * w.w[c] : 0.0f;
+    float g[D], gs = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = 0.0f;
+
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
+    const int64_t jend = j0 + jchunk < n ? j0 + jchunk : n;
+    const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
+    const float* __restrict__ uc = U + j0 * D;
+    const float* __restrict__ bc = B + j0 * TB;
+    for (int q = 0; q < cnt; ++q) {
+        const float* uj = uc + q * D;
+        float df[D];
+        float d2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            df[k] = ui[k] - uj[k];
+            d2 = fmaf(df[k], df[k], d2);
+        }
+        float kv, gf;
+        kentry_and_dfac<FAM>(d2, kv, gf);
+        float wij = 0.0f;
+#pragma unroll
+        for (int c = 0; c < TB; ++c) wij = fmaf(ai[c], bc[q * TB + c], wij);
+        gs = fmaf(wij, kv, gs);
+        const float wd = wij * gf;
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] = fmaf(wd * df[k], df[k], g[k]);
+    }
+
+    // FP64 block reduction: wave butterfly, then the 4 wave sums in order.
+    double v[D + 1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = static_cast<double>(g[k]);
+    v[D] = static_cast<double>(gs);
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        double x = v[k];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[k] = x;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k <= D; ++k) red[wave * (D + 1) + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x <= D) {
+        double s = 0.0;
+        for (int q = 0; q < kBlock / 64; ++q) s += red[q * (D + 1) + threadIdx.x];
+        partial[static_cast<int64_t>(blockIdx.x) * (D + 1) + threadIdx.x] = s;
+    }
+}
+
+__global__ void adjoint_final_kernel(const double* __restrict__ partial, int nblocks, int width,
+                                     double* __restrict__ out, int accumulate) {
+    const int k = threadIdx.x;
+    if (k >= width) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[static_cast<int64_t>(b) * width + k];
+    out[k] = accumulate ? out[k] + s : s;
+}
+
+template <int FAM, int D>
+static hipError_t adjoint_fd(int tb, const float* U, const float* A, int lda, int c0,
+                             const ColW& w, const float* B, int64_t n, const SweepPlan& p,
+                             double* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+    switch (tb) {
+#define MFGP_CASE(TBV)                                                                        \
+    case TBV:                                                                                 \
+        hipLaunchKernelGGL((adjoint_kernel<FAM, D, TBV>), grid, dim3(kBlock), 0, s, U, A, lda, \
+                           c0, w, B, n, p.chunks, p.jchunk, partial);                         \
+        return hipGetLastError();
+        MFGP_TB_LIST(MFGP_CASE)
+#undef MFGP_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <int FAM>
+static hipError_t adjoint_f(int D, int tb, const float* U, const float* A, int lda, int c0,
+                            const ColW& w, const float* B, int64_t n, const SweepPlan& p,
+                            double* partial, hipStream_t s) {
+    switch (D) {
+        case 1: return adjoint_fd<FAM, 1>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 2: return adjoint_fd<FAM, 2>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 3: return adjoint_fd<FAM, 3>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 4: return adjoint_fd<FAM, 4>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 5: return adjoint_fd<FAM, 5>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 6: return adjoint_fd<FAM, 6>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 7: return adjoint_fd<FAM, 7>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        case 8: return adjoint_fd<FAM, 8>(tb, U, A, lda, c0, w, B, n, p, partial, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t adjoint_scratch_doubles(int64_t n, int d, int t) {
+    const SweepPlan p = plan_sweep(n, n);
+    const size_t part = static_cast<size_t>(p.rowblocks) * p.chunks * (d + 1);
+    const int tb = column_block(t);
+    const size_t pack = tb == t ? 0 : (static_cast<size_t>(n) * tb + 1) / 2 + 64;
+    return part + pack + 2 * (d + 1) + 128;
+}
+
+// sums_host[0..d-1] = G_k, sums_host[d] = G_s (see the file comment).
+hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int t,
+                        const double* colw_host, double* sums_host, double* scratch,
+                        hipStream_t s) {
+    const int d = op.d;
+    const int64_t n = op.n;
+    const SweepPlan p = plan_sweep(n, n);
+    const int nblocks = p.rowblocks * p.chunks;
+    double* partial = scratch;
+    double* total = scratch + static_cast<size_t>(nblocks) * (d + 1) + 64;
+    float* pack = reinterpret_cast<float*>(total + 2 * (d + 1) + 64);
+    int first = 1;
+    for (int c0 = 0; c0 < t;) {
+        const int tb = column_block(t - c0);
+        ColW w{};
+        for (int c = 0; c < tb; ++c) w.w[c] = static_cast<float>(colw_host[c0 + c]);
+        const float* bb = B;
+        if (tb != t) {
+            hipError_t e = launch_pack_cols(B, t, c0, tb, n, pack, s);
+            if (e != hipSuccess) return e;
+            bb = pack;
+        }
+        hipError_t e;
+        void* tok = timing_begin(s);
+        switch (op.family) {
+            case MFGP_RBF: e = adjoint_f<MFGP_RBF>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
+            case MFGP_MATERN12: e = adjoint_f<MFGP_MATERN12>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
+            case MFGP_MATERN32: e = adjoint_f<MFGP_MATERN32>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
+            default: e = adjoint_f<MFGP_MATERN52>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
+        }
+        {
+            const double ent = static_cast<double>(n) * static_cast<double>(n);
+            timing_end(tok, s, kSweepAdjoint, ent, ent * sweep_flops_per_entry(op.family, d, tb, true));
+        }
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(adjoint_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, d + 1,
+                           total, first ? 0 : 1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        first = 0;
+        c0 += tb;
+    }
+    hipError_t e = hipMemcpyAsync(sums_host, total, (d + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+}  // namespace mfgp

@@ -1,0 +1,190 @@
+// Conjugate-gradient driver on the matrix-free operator (LightGP Sec. 2
+// "CG-based inference": CG needs only K_y v; Sec. 5: the CG loop is plain,
+// unpreconditioned; several columns are stepped together here).
+//
+// Per iteration (all on the caller's stream):
+//   AP = K_y P                      entry sweeps + reduce   (the O(n^2 t) step)
+//   pap = diag(P^T AP)              FP64 striped dots
+//   alpha = rr / pap                FP64, one block
+//   X += alpha P (FP64), R -= alpha AP, rr_new = diag(R^T R)
+//   beta = rr_new / rr, log (alpha, beta), freeze converged columns
+//   P = R + beta P
+// Every `check_every` iterations the host reads the active flags.  When no
+// column is active the true residual B - K_y X is recomputed with FP64
+// accumulation (X is FP64), and columns above tolerance restart from it
+// (iterative refinement).  The FP64 solution is what lets the recomputed
+// residual reach 1e-6: an FP32-rounded solution alone floors at a few 1e-6.
+#include "cg.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace mfgp {
+
+__global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
+    for (int c = threadIdx.x; c < t; c += blockDim.x) {
+        const bool finite = isfinite(st.bnorm2[c]) && isfinite(st.rr[c]);
+        const bool go = finite && st.bnorm2[c] > 0.0 && st.rr[c] > tol2 * st.bnorm2[c];
+        st.active[c] = go ? 1 : 0;
+        st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
+        st.iters[c] = 0;
+        st.lanlen[c] = 0;
+        st.alpha[c] = 0.0;
+        st.beta[c] = 0.0;
+    }
+}
+
+CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
+    CgBufs b;
+    const size_t nt = static_cast<size_t>(n) * t;
+    b.R = cv.take<float>(nt);
+    b.P = cv.take<float>(nt);
+    b.AP = cv.take<float>(nt);
+    b.R64 = cv.take<double>(nt);
+    b.scal = cv.take<double>(8 * static_cast<size_t>(t));
+    b.ints = cv.take<int>(6 * static_cast<size_t>(t));
+    b.dots = cv.take<double>(dots_scratch_doubles(n, t));
+    b.resid = cv.take<double>(resid_scratch_doubles(n, t));
+    if (precision == MFGP_FP32)
+        b.apply = cv.take<float>(apply_scratch_floats(n, n, t));
+    else
+        b.apply = reinterpret_cast<float*>(cv.take<char>(mfma_scratch_bytes(n, n, t, precision)));
+    return b;
+}
+
+static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
+    CgState st;
+    st.x = X;
+    st.r = b.R;
+    st.p = b.P;
+    st.ap = b.AP;
+    st.rr = b.scal;
+    st.bnorm2 = b.scal + t;
+    st.pap = b.scal + 2 * t;
+    st.alpha = b.scal + 3 * t;
+    st.beta = b.scal + 4 * t;
+    st.active = b.ints;
+    st.status = b.ints + t;
+    st.iters = b.ints + 2 * t;
+    st.lanlen = b.ints + 3 * t;
+    st.coeff = coeff;
+    return st;
+}
+
+static hipError_t apply_op(const Operator& op, const float* V, int t, float* out, int precision,
+                           float* scratch, hipStream_t s) {
+    if (precision == MFGP_FP32)
+        return apply_f32(op, op.U, op.n, V, t, out, true, V, scratch, s);
+    return apply_mfma(op, op.U, op.n, V, t, out, true, V, precision, scratch, s);
+}
+
+#define CG_CHECK(expr)                         \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) {                \
+            set_last_hip_error(e_);            \
+            return MFGP_ERR_HIP;               \
+        }                                      \
+    } while (0)
+
+int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_opts& o,
+           mfgp_cg_info* info, double* coeff, int max_iter, const CgBufs& b, hipStream_t s) {
+    const int64_t n = op.n;
+    const int64_t nt = n * t;
+    const double tol = o.tol;
+    const int max_refine = o.max_refine >= 0 ? o.max_refine : 8;
+    int check_every = o.check_every;
+    if (check_every <= 0) {
+        const double work = static_cast<double>(n) * static_cast<double>(n) * t;
+        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 16);
+    }
+    CgState st = make_state(b, X, t, coeff);
+    double* tmp = b.scal + 5 * t;     // [t] scratch scalars
+    double* relt = b.scal + 6 * t;    // [t] true relative residual
+    int* restart = b.ints + 4 * t;    // [t]
+
+    CG_CHECK(col_dots_ff(B, B, n, t, st.bnorm2, b.dots, s));
+    if (o.warm_start) {
+        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(f64_to_f32(b.R64, st.r, nt, s));
+        CG_CHECK(copy2_f32(st.r, st.r, st.p, nt, s));
+    } else {
+        CG_CHECK(fill_f64(X, nt, 0.0, s));
+        CG_CHECK(copy2_f32(B, st.r, st.p, nt, s));
+    }
+    CG_CHECK(col_dots_ff(st.r, st.r, n, t, st.rr, b.dots, s));
+    hipLaunchKernelGGL(cg_init_flags_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol);
+    CG_CHECK(hipGetLastError());
+
+    std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
+    std::vector<double> h_relt(t), h_rr(t), h_b2(t);
+    int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
+
+    for (;;) {
+        CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
+        if (any) {
+            for (int k = 0; k < check_every; ++k) {
+                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b.apply, s));
+                CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
+                CG_CHECK(cg_alpha(st, t, s));
+                CG_CHECK(cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, s));
+            }
+            continue;
+        }
+        // Every column stopped: recompute the true residual in FP64.
+        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
+        CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_status.data(), st.status, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipStreamSynchronize(s));
+        bool again = false;
+        for (int c = 0; c < t; ++c) {
+            h_relt[c] = h_b2[c] > 0.0 ? std::sqrt(h_relt[c] / h_b2[c]) : 0.0;
+            const bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
+                              h_refine[c] < max_refine && h_iters[c] < max_iter;
+            h_restart[c] = need ? 1 : 0;
+            if (need) {
+                h_refine[c] += 1;
+                again = true;
+            }
+        }
+        if (!again) break;
+        CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
+        CG_CHECK(cg_restart(st, b.R64, n, t, restart, s));
+        CG_CHECK(col_dots_ff(st.r, st.r, n, t, tmp, b.dots, s));
+        CG_CHECK(cg_activate(st, t, restart, tmp, s));
+        log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
+    }
+
+    CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_lan.data(), st.lanlen, t * sizeof(int), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(relt, h_relt.data(), t * sizeof(double), hipMemcpyHostToDevice, s));
+    CG_CHECK(hipStreamSynchronize(s));
+    int worst = MFGP_OK;
+    for (int c = 0; c < t; ++c) {
+        int stc = h_status[c];
+        if (stc == MFGP_OK && !(h_relt[c] <= tol)) stc = MFGP_NOT_CONVERGED;
+        if (stc == MFGP_BREAKDOWN)
+            worst = MFGP_BREAKDOWN;
+        else if (stc == MFGP_NOT_CONVERGED && worst == MFGP_OK)
+            worst = MFGP_NOT_CONVERGED;
+        if (info) {
+            info[c].iters = h_iters[c];
+            info[c].lanczos_len = h_lan[c];
+            info[c].refinements = h_refine[c];
+            info[c].status = stc;
+            info[c].rel_resid_recurrence = h_b2[c] > 0.0 ? std::sqrt(h_rr[c] / h_b2[c]) : 0.0;
+            info[c].rel_resid_true = h_relt[c];
+        }
+    }
+    return worst;
+}
+
+}  // namespace mfgp

@@ -1,0 +1,250 @@
+// Core launchers shared by every entry point: prescale, split-j planning,
+// column packing, partial-sum reduction, and the FP32 / FP64-accumulated
+// operator products  out = s2 k(Ur, Uc) V + sig2 V  built from the sweeps.
+#include "common.hpp"
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace mfgp {
+
+hipError_t sweep_f32_fam0(int, int, const SweepArgs&, hipStream_t);
+hipError_t sweep_f32_fam1(int, int, const SweepArgs&, hipStream_t);
+hipError_t sweep_f32_fam2(int, int, const SweepArgs&, hipStream_t);
+hipError_t sweep_f32_fam3(int, int, const SweepArgs&, hipStream_t);
+hipError_t sweep_f64_fam0(int, int, const SweepArgs64&, hipStream_t);
+hipError_t sweep_f64_fam1(int, int, const SweepArgs64&, hipStream_t);
+hipError_t sweep_f64_fam2(int, int, const SweepArgs64&, hipStream_t);
+hipError_t sweep_f64_fam3(int, int, const SweepArgs64&, hipStream_t);
+
+double family_scale(int family) {
+    const double log2e = 1.4426950408889634074;
+    switch (family) {
+        case MFGP_RBF: return std::sqrt(log2e / 2.0);
+        case MFGP_MATERN12: return log2e;
+        case MFGP_MATERN32: return std::sqrt(3.0) * log2e;
+        case MFGP_MATERN52: return std::sqrt(5.0) * log2e;
+        default: return 0.0;
+    }
+}
+
+SweepPlan plan_sweep(int64_t m, int64_t n) {
+    SweepPlan p;
+    p.m = m;
+    p.n = n;
+    p.rowblocks = static_cast<int>((m + kBlock - 1) / kBlock);
+    // Aim for ~4096 blocks (2 dispatch rounds at 8 resident 256-thread
+    // blocks per CU on 256 CUs), each j-range at least 256 long.
+    const int64_t target = 4096;
+    int64_t chunks = (target + p.rowblocks - 1) / p.rowblocks;
+    const int64_t max_chunks = n / 256 > 1 ? n / 256 : 1;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks > 64) chunks = 64;
+    if (chunks >= 8) chunks = (chunks + 7) / 8 * 8;
+    if (chunks < 1) chunks = 1;
+    p.chunks = static_cast<int>(chunks);
+    p.jchunk = (n + chunks - 1) / chunks;
+    return p;
+}
+
+int column_block(int t) {
+    static const int sizes[] = {33, 32, 17, 16, 8, 7, 6, 5, 4, 3, 2, 1};
+    for (int s : sizes)
+        if (s <= t) return s;
+    return 1;
+}
+
+int column_block64(int t) {
+    static const int sizes[] = {8, 4, 2, 1};
+    for (int s : sizes)
+        if (s <= t) return s;
+    return 1;
+}
+
+hipError_t launch_sweep_f32(int family, int D, int tb, const SweepArgs& a, hipStream_t s) {
+    switch (family) {
+        case MFGP_RBF: return sweep_f32_fam0(D, tb, a, s);
+        case MFGP_MATERN12: return sweep_f32_fam1(D, tb, a, s);
+        case MFGP_MATERN32: return sweep_f32_fam2(D, tb, a, s);
+        case MFGP_MATERN52: return sweep_f32_fam3(D, tb, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_f64acc(int family, int D, int tb, const SweepArgs64& a, hipStream_t s) {
+    switch (family) {
+        case MFGP_RBF: return sweep_f64_fam0(D, tb, a, s);
+        case MFGP_MATERN12: return sweep_f64_fam1(D, tb, a, s);
+        case MFGP_MATERN32: return sweep_f64_fam2(D, tb, a, s);
+        case MFGP_MATERN52: return sweep_f64_fam3(D, tb, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- small kernels
+
+struct Fac {
+    float f[MFGP_MAX_D];
+};
+
+__global__ void prescale_kernel(const float* __restrict__ X, int64_t n, int d, Fac fac,
+                                float* __restrict__ U) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * d) return;
+    const int k = static_cast<int>(idx % d);
+    U[idx] = X[idx] * fac.f[k];
+}
+
+hipError_t launch_prescale(const float* X, int64_t n, int d, const float* fac_host, float* U,
+                           hipStream_t s) {
+    Fac f{};
+    for (int k = 0; k < d; ++k) f.f[k] = fac_host[k];
+    const int64_t total = n * d;
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    hipLaunchKernelGGL(prescale_kernel, dim3(blocks), dim3(256), 0, s, X, n, d, f, U);
+    return hipGetLastError();
+}
+
+// dst[j, c] = src[j, c0 + c] for c < tb  (column block packing)
+__global__ void pack_cols_kernel(const float* __restrict__ src, int lds, int c0, int tb,
+                                 int64_t n, float* __restrict__ dst) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * tb) return;
+    const int64_t j = idx / tb;
+    const int c = static_cast<int>(idx % tb);
+    dst[idx] = src[j * lds + c0 + c];
+}
+
+hipError_t launch_pack_cols(const float* src, int lds, int c0, int tb, int64_t n, float* dst,
+                            hipStream_t s) {
+    const int64_t total = n * tb;
+    hipLaunchKernelGGL(pack_cols_kernel, dim3(static_cast<unsigned>((total + 255) / 256)),
+                       dim3(256), 0, s, src, lds, c0, tb, n, dst);
+    return hipGetLastError();
+}
+
+// out[i, c0 + c] = s2 * sum_s partial[s][i][c] + sig2 * Vself[i, c0 + c]
+__global__ void reduce_f32_kernel(const float* __restrict__ partial, int chunks, int64_t m,
+                                  int tb, float s2, float sig2, const float* __restrict__ Vself,
+                                  int ldv, int c0, float* __restrict__ out, int ldo) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= m * tb) return;
+    const int64_t i = idx / tb;
+    const int c = static_cast<int>(idx % tb);
+    double acc = 0.0;
+    for (int s = 0; s < chunks; ++s) acc += static_cast<double>(partial[s * m * tb + idx]);
+    double v = static_cast<double>(s2) * acc;
+    if (Vself) v += static_cast<double>(sig2) * static_cast<double>(Vself[i * ldv + c0 + c]);
+    out[i * ldo + c0 + c] = static_cast<float>(v);
+}
+
+// R[i, c0 + c] = B[i, c0 + c] - (s2 * sum_s partial[s][i][c] + sig2 * X[i, c0 + c])   (FP64)
+__global__ void reduce_resid_kernel(const double* __restrict__ partial, int chunks, int64_t m,
+                                    int tb, double s2, double sig2, const double* __restrict__ X,
+                                    const float* __restrict__ B, int ld, int c0,
+                                    double* __restrict__ R) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= m * tb) return;
+    const int64_t i = idx / tb;
+    const int c = static_cast<int>(idx % tb);
+    double acc = 0.0;
+    for (int s = 0; s < chunks; ++s) acc += partial[s * m * tb + idx];
+    const int64_t o = i * ld + c0 + c;
+    R[o] = static_cast<double>(B[o]) - (s2 * acc + sig2 * X[o]);
+}
+
+// ---------------------------------------------------------------- operator products
+
+Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    Operator op;
+    op.family = k.family;
+    op.d = k.d;
+    op.n = n;
+    op.s2 = k.outputscale;
+    op.sig2 = k.noise;
+    op.X = X;
+    op.U = U;
+    const double c = family_scale(k.family);
+    for (int q = 0; q < k.d; ++q) {
+        const double l = k.ard ? k.lengthscale[q] : k.lengthscale[0];
+        op.fac[q] = static_cast<float>(c / l);
+        op.ls[q] = l;
+    }
+    return op;
+}
+
+hipError_t prescale(const Operator& op, hipStream_t s) {
+    return launch_prescale(op.X, op.n, op.d, op.fac, op.U, s);
+}
+
+size_t apply_scratch_floats(int64_t m, int64_t n, int t) {
+    const SweepPlan p = plan_sweep(m, n);
+    const int tb = column_block(t);
+    const size_t part = static_cast<size_t>(p.chunks) * m * tb;
+    const size_t pack = (tb == t) ? 0 : static_cast<size_t>(n) * tb;
+    return part + pack + 64;
+}
+
+hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                     float* out, bool with_noise, const float* Vself, float* scratch,
+                     hipStream_t s) {
+    const SweepPlan plan = plan_sweep(m, op.n);
+    const int tb0 = column_block(t);
+    float* partial = scratch;
+    float* pack = scratch + ((static_cast<size_t>(plan.chunks) * m * tb0 + 63) / 64) * 64;
+    for (int c0 = 0; c0 < t;) {
+        const int tb = column_block(t - c0);
+        const float* vb = V;
+        if (tb != t) {
+            hipError_t e = launch_pack_cols(V, t, c0, tb, op.n, pack, s);
+            if (e != hipSuccess) return e;
+            vb = pack;
+        }
+        SweepArgs a{Ur, op.U, vb, m, op.n, partial, plan};
+        void* tok = timing_begin(s);
+        hipError_t e = launch_sweep_f32(op.family, op.d, tb, a, s);
+        const double ent = static_cast<double>(m) * static_cast<double>(op.n);
+        timing_end(tok, s, kSweepF32, ent, ent * sweep_flops_per_entry(op.family, op.d, tb, false));
+        if (e != hipSuccess) return e;
+        const int64_t total = m * tb;
+        hipLaunchKernelGGL(reduce_f32_kernel, dim3(static_cast<unsigned>((total + 255) / 256)),
+                           dim3(256), 0, s, partial, plan.chunks, m, tb, op.s2,
+                           with_noise ? op.sig2 : 0.0f, with_noise ? Vself : nullptr, t, c0, out,
+                           t);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        c0 += tb;
+    }
+    return hipSuccess;
+}
+
+size_t resid_scratch_doubles(int64_t n, int t) {
+    const SweepPlan p = plan_sweep(n, n);
+    const int tb = column_block64(t);
+    return static_cast<size_t>(p.chunks) * n * tb + 64;
+}
+
+hipError_t residual_f64(const Operator& op, const float* B, const double* X64, int t, double* R,
+                        double* scratch, hipStream_t s) {
+    const SweepPlan plan = plan_sweep(op.n, op.n);
+    for (int c0 = 0; c0 < t;) {
+        const int tb = column_block64(t - c0);
+        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan};
+        void* tok = timing_begin(s);
+        hipError_t e = launch_sweep_f64acc(op.family, op.d, tb, a, s);
+        const double ent = static_cast<double>(op.n) * static_cast<double>(op.n);
+        timing_end(tok, s, kSweepF64, ent, ent * sweep_flops_per_entry(op.family, op.d, tb, false));
+        if (e != hipSuccess) return e;
+        const int64_t total = op.n * tb;
+        hipLaunchKernelGGL(reduce_resid_kernel, dim3(static_cast<unsigned>((total + 255) / 256)),
+                           dim3(256), 0, s, scratch, plan.chunks, op.n, tb,
+                           static_cast<double>(op.s2), static_cast<double>(op.sig2), X64, B, t,
+                           c0, R);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        c0 += tb;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mfgp

@@ -1,0 +1,79 @@
+// Internal host-side interfaces between the C ABI and the kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace mfgp {
+
+// A kernel operator bound to its training inputs: family, prescale factors
+// and the prescaled coordinates U (device, [n, d]) that the sweeps read.
+struct Operator {
+    int family = 0;
+    int d = 0;
+    int64_t n = 0;
+    float s2 = 1.0f;
+    float sig2 = 0.0f;
+    float fac[MFGP_MAX_D] = {};
+    double ls[MFGP_MAX_D] = {};
+    const float* X = nullptr;
+    float* U = nullptr;
+};
+
+Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U);
+hipError_t prescale(const Operator& op, hipStream_t s);
+
+int column_block64(int t);
+hipError_t launch_pack_cols(const float* src, int lds, int c0, int tb, int64_t n, float* dst,
+                            hipStream_t s);
+
+// Scratch (in floats) that apply_f32 needs for an m-row product with t columns.
+size_t apply_scratch_floats(int64_t m, int64_t n, int t);
+// out[m, t] = s2 k(Ur, U) V + (with_noise ? sig2 Vself : 0), FP32 entries, FP32 sweeps.
+hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                     float* out, bool with_noise, const float* Vself, float* scratch,
+                     hipStream_t s);
+
+// Scratch (in doubles) of residual_f64.
+size_t resid_scratch_doubles(int64_t n, int t);
+// R = B - K_y X64 with FP32 entries and FP64 accumulation.
+hipError_t residual_f64(const Operator& op, const float* B, const double* X64, int t, double* R,
+                        double* scratch, hipStream_t s);
+
+// BF16-MFMA tile products (precision x1 / x2).
+bool precision_supported(int precision);
+size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision);
+hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                      float* out, bool with_noise, const float* Vself, int precision,
+                      void* scratch, hipStream_t s);
+
+// Column norms / dots in FP64: out[c] = sum_i a[i,c] * b[i,c] (float or double inputs).
+size_t dots_scratch_doubles(int64_t n, int t);
+hipError_t col_dots_ff(const float* a, const float* b, int64_t n, int t, double* out_dev,
+                       double* scratch, hipStream_t s);
+hipError_t col_dots_dd(const double* a, const double* b, int64_t n, int t, double* out_dev,
+                       double* scratch, hipStream_t s);
+hipError_t col_dots_df(const double* a, const float* b, int64_t n, int t, double* out_dev,
+                       double* scratch, hipStream_t s);
+
+// Gradient adjoint pass: per-parameter sums (device, FP64) over all entries.
+size_t adjoint_scratch_doubles(int64_t n, int d, int t);
+hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int t,
+                        const double* colw_host, double* sums_host, double* scratch,
+                        hipStream_t s);
+
+// SplitMix64 Rademacher probes.
+hipError_t launch_rademacher(uint64_t seed, int64_t n, int p, float* Z, hipStream_t s);
+
+// Optional sweep timing (timing.hip): a token from timing_begin is closed by
+// timing_end with the launch's algorithmic entries and FLOP.
+double sweep_flops_per_entry(int family, int d, int t, bool adjoint);
+void* timing_begin(hipStream_t s);
+void timing_end(void* tok, hipStream_t s, int kind, double entries, double flops);
+bool timing_on();
+void timing_phase(int which, double ms);   // 0 CG solve, 1 quadrature, 2 adjoint
+enum SweepKind { kSweepF32 = 0, kSweepF64 = 1, kSweepAdjoint = 2, kSweepMfma = 3 };
+
+// Thread-local last HIP error.
+void set_last_hip_error(hipError_t e);
+
+}  // namespace mfgp

@@ -1,0 +1,38 @@
+// CG state and column-vector kernels (see vec.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace mfgp {
+
+// Device pointers of a CG run on [n, t] blocks.
+struct CgState {
+    double* x;        // [n, t] solution (FP64)
+    float* r;         // [n, t] residual
+    float* p;         // [n, t] search direction
+    float* ap;        // [n, t] K_y p
+    double* rr;       // [t] r^T r
+    double* bnorm2;   // [t] b^T b
+    double* pap;      // [t] p^T K_y p
+    double* alpha;    // [t]
+    double* beta;     // [t]
+    int* active;      // [t] 1 while the column iterates
+    int* status;      // [t] mfgp_status
+    int* iters;       // [t] iterations done
+    int* lanlen;      // [t] logged Lanczos length
+    double* coeff;    // [t][max_iter][2] (alpha, beta) log, may be null
+};
+
+int stripe_blocks(int64_t n, int t);
+hipError_t cg_alpha(const CgState& st, int t, hipStream_t s);
+hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scratch, double tol,
+                              int log_coeffs, int max_iter, hipStream_t s);
+hipError_t cg_restart(const CgState& st, const double* R64, int64_t n, int t, const int* restart,
+                      hipStream_t s);
+hipError_t cg_activate(const CgState& st, int t, const int* restart, const double* rr_new,
+                       hipStream_t s);
+hipError_t fill_f64(double* x, int64_t total, double v, hipStream_t s);
+hipError_t copy2_f32(const float* src, float* a, float* b, int64_t total, hipStream_t s);
+hipError_t f64_to_f32(const double* src, float* dst, int64_t total, hipStream_t s);
+
+}  // namespace mfgp

@@ -90,11 +90,13 @@ def matern20k(n: int = 20000, m: int = 2000, probes: int = 0) -> Workload:
     return w
 
 
-def rbf100k(n: int = 100000, probes: int = 32) -> Workload:
+def rbf100k(n: int = 100000, probes: int = 32, m: int = 2000) -> Workload:
     rng = np.random.default_rng(103)
     X = rng.uniform(-1.0, 1.0, size=(n, 4))
     y = np.sin(np.pi * X).sum(axis=1) + 0.1 * rng.standard_normal(n)
-    w = Workload("rbf100k", X.astype(np.float32), y.astype(np.float32), "rbf", 0.3, 1.0, 0.01)
+    Xs = np.random.default_rng(203).uniform(-1.0, 1.0, size=(m, 4))
+    w = Workload("rbf100k", X.astype(np.float32), y.astype(np.float32), "rbf", 0.3, 1.0, 0.01,
+                 Xs=Xs.astype(np.float32))
     if probes:
         w.Z = rademacher(np.random.default_rng(303), n, probes)
     return w

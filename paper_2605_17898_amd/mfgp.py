@@ -1,0 +1,345 @@
+"""Thin ctypes binding of libmfgp.so (C ABI in include/mfgp.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Tensors are caller-owned torch tensors on the GPU (float32 / float64,
+contiguous); the library runs on torch's current stream.  If the library is
+not built this module raises at import time: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfgp.so")
+
+MAX_D = 8
+FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3}
+PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2}
+OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
+OP_MATVEC, OP_CG, OP_PREDICT, OP_MLL, OP_ADJOINT, OP_RESIDUAL = range(6)
+
+
+class KernelT(C.Structure):
+    _fields_ = [("family", C.c_int32), ("d", C.c_int32), ("ard", C.c_int32),
+                ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float)]
+
+
+class CgOptsT(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+                ("max_refine", C.c_int32), ("precision", C.c_int32), ("warm_start", C.c_int32),
+                ("pad_", C.c_int32), ("probe_seed", C.c_uint64)]
+
+
+class CgInfoT(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("lanczos_len", C.c_int32), ("refinements", C.c_int32),
+                ("status", C.c_int32), ("rel_resid_recurrence", C.c_double),
+                ("rel_resid_true", C.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"mfgp HIP library not found at {path}; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    P, I32, I64, SZ, D = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    KP, OP_, IP = C.POINTER(KernelT), C.POINTER(CgOptsT), C.POINTER(CgInfoT)
+    sig = {
+        "mfgp_workspace_bytes": (SZ, [I32, I64, I32, I32, I32, I32]),
+        "mfgp_kernel_matvec": (C.c_int, [KP, P, I64, P, I32, P, I32, P, SZ, P]),
+        "mfgp_residual": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
+        "mfgp_cg_solve": (C.c_int, [KP, P, I64, P, I32, P, OP_, IP, P, P, SZ, P]),
+        "mfgp_predict_mean": (C.c_int, [KP, P, I64, P, I64, P, I32, P, P, SZ, P]),
+        "mfgp_slq_quadrature": (C.c_int, [P, I32, D, P]),
+        "mfgp_mll_and_grad": (C.c_int, [KP, P, I64, P, I32, P, OP_, P, P, P, P, IP, P, SZ, P]),
+        "mfgp_kernel_adjoint": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
+        "mfgp_rademacher": (C.c_int, [C.c_uint64, I64, I32, P, P]),
+        "mfgp_num_params": (C.c_int, [KP]),
+        "mfgp_timing_enable": (C.c_int, [I32]),
+        "mfgp_timing_read": (C.c_int, [I32, P, P, P, P]),
+        "mfgp_timing_phases": (C.c_int, [P, P, P]),
+        "mfgp_status_string": (C.c_char_p, [C.c_int]),
+        "mfgp_last_hip_error": (C.c_int, []),
+        "mfgp_version": (C.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = load_library()
+
+
+class MfgpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = LIB.mfgp_status_string(status).decode()
+        if status == ERR_HIP:
+            msg += f" (hipError {LIB.mfgp_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str, allow=(OK,)):
+    if status not in allow:
+        raise MfgpError(status, where)
+    return status
+
+
+@dataclass
+class Kernel:
+    """Kernel hyperparameters: family, lengthscale (float or per-dimension), s^2, sigma^2."""
+
+    family: str
+    lengthscale: object
+    outputscale: float = 1.0
+    noise: float = 0.01
+
+    def struct(self, d: int) -> KernelT:
+        k = KernelT()
+        k.family = FAMILIES[self.family]
+        k.d = d
+        ls = self.lengthscale
+        if isinstance(ls, (list, tuple)) or (hasattr(ls, "ndim") and getattr(ls, "ndim") == 1):
+            vals = [float(v) for v in ls]
+            if len(vals) != d:
+                raise ValueError("ARD lengthscale needs one value per dimension")
+            k.ard = 1
+            for q, v in enumerate(vals):
+                k.lengthscale[q] = v
+        else:
+            k.ard = 0
+            k.lengthscale[0] = float(ls)
+        k.outputscale = float(self.outputscale)
+        k.noise = float(self.noise)
+        return k
+
+    def n_params(self, d: int) -> int:
+        return LIB.mfgp_num_params(C.byref(self.struct(d)))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_WS = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """Grow-only cached workspace per device (allocated by torch, not the library)."""
+    key = torch.device(device)
+    ws = _WS.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=key)
+        _WS[key] = ws
+    return ws
+
+
+def workspace_bytes(op: int, n: int, d: int, t: int, precision: int = 0, max_iter: int = 0) -> int:
+    return int(LIB.mfgp_workspace_bytes(op, n, d, t, precision, max_iter))
+
+
+def _cols(V: torch.Tensor) -> int:
+    return 1 if V.dim() == 1 else V.shape[1]
+
+
+def kernel_matvec(kern: Kernel, X: torch.Tensor, V: torch.Tensor, precision: str = "fp32",
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K_y V for V [n] or [n, t] (float32)."""
+    _dev(X, torch.float32, "X")
+    _dev(V, torch.float32, "V")
+    n, d = X.shape
+    t = _cols(V)
+    out = torch.empty_like(V) if out is None else _dev(out, torch.float32, "out")
+    pr = PRECISIONS[precision]
+    nb = workspace_bytes(OP_MATVEC, n, d, t, pr)
+    if nb == 0:
+        raise MfgpError(ERR_ARG, "kernel_matvec")
+    ws = workspace(nb, X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_kernel_matvec(C.byref(ks), _ptr(X), n, _ptr(V), t, _ptr(out), pr, _ptr(ws),
+                                  ws.numel(), _stream()), "kernel_matvec")
+    return out
+
+
+def residual(kern: Kernel, X: torch.Tensor, B: torch.Tensor, Xsol: torch.Tensor):
+    """(R, rel) with R = B - K_y Xsol (FP32 entries, FP64 sums); rel per column."""
+    _dev(X, torch.float32, "X")
+    _dev(B, torch.float32, "B")
+    _dev(Xsol, torch.float64, "Xsol")
+    n, d = X.shape
+    t = _cols(B)
+    R = torch.empty(B.shape, dtype=torch.float64, device=B.device)
+    rel = (C.c_double * t)()
+    ws = workspace(workspace_bytes(OP_RESIDUAL, n, d, t), X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_residual(C.byref(ks), _ptr(X), n, _ptr(B), _ptr(Xsol), t, _ptr(R), rel,
+                             _ptr(ws), ws.numel(), _stream()), "residual")
+    return R, list(rel)
+
+
+def cg_opts(tol: float = 1e-6, max_iter: int = 0, check_every: int = 0, max_refine: int = -1,
+            precision: str = "fp32", warm_start: bool = False, probe_seed: int = 0) -> CgOptsT:
+    o = CgOptsT()
+    o.tol = tol
+    o.max_iter = max_iter
+    o.check_every = check_every
+    o.max_refine = max_refine
+    o.precision = PRECISIONS[precision]
+    o.warm_start = 1 if warm_start else 0
+    o.probe_seed = probe_seed
+    return o
+
+
+def _info_list(info, t):
+    return [dict(iters=info[c].iters, lanczos_len=info[c].lanczos_len, refinements=info[c].refinements,
+                 status=info[c].status, rel_resid_recurrence=info[c].rel_resid_recurrence,
+                 rel_resid_true=info[c].rel_resid_true) for c in range(t)]
+
+
+def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,
+             precision: str = "fp32", x0: Optional[torch.Tensor] = None, want_lanczos: bool = False,
+             check_every: int = 0, max_refine: int = -1, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+    """Solve K_y X = B.  Returns (Xsol float64, info list, lanczos or None, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(B, torch.float32, "B")
+    n, d = X.shape
+    t = _cols(B)
+    o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None)
+    mi = max_iter if max_iter > 0 else min(n, 20000)
+    Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device) if x0 is None else \
+        _dev(x0, torch.float64, "x0").clone()
+    lan = torch.empty((t, mi, 2), dtype=torch.float64, device=B.device) if want_lanczos else None
+    info = (CgInfoT * t)()
+    ws = workspace(workspace_bytes(OP_CG, n, d, t, o.precision, max_iter), X.device)
+    ks = kern.struct(d)
+    st = LIB.mfgp_cg_solve(C.byref(ks), _ptr(X), n, _ptr(B), t, _ptr(Xsol), C.byref(o), info,
+                           _ptr(lan), _ptr(ws), ws.numel(), _stream())
+    _check(st, "cg_solve", allow)
+    return Xsol, _info_list(info, t), lan, st
+
+
+def predict_mean(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, A: torch.Tensor) -> torch.Tensor:
+    """mu = s2 k(Xs, X) A (no noise term)."""
+    _dev(X, torch.float32, "X")
+    _dev(Xs, torch.float32, "Xs")
+    _dev(A, torch.float32, "A")
+    n, d = X.shape
+    m = Xs.shape[0]
+    t = _cols(A)
+    mu = torch.empty((m,) if A.dim() == 1 else (m, t), dtype=torch.float32, device=X.device)
+    ws = workspace(workspace_bytes(OP_PREDICT, n, d, t, 0, m), X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_predict_mean(C.byref(ks), _ptr(X), n, _ptr(Xs), m, _ptr(A), t, _ptr(mu), _ptr(ws),
+                                 ws.numel(), _stream()), "predict_mean")
+    return mu
+
+
+def slq_quadrature(coeffs: Sequence[Sequence[float]], znorm2: float) -> float:
+    """Host-only Gauss quadrature from CG (alpha, beta) pairs."""
+    m = len(coeffs)
+    buf = (C.c_double * (2 * m))(*[float(v) for ab in coeffs for v in ab])
+    q = C.c_double()
+    _check(LIB.mfgp_slq_quadrature(buf, m, znorm2, C.byref(q)), "slq_quadrature")
+    return q.value
+
+
+def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int = 16,
+                 Z: Optional[torch.Tensor] = None, tol: float = 1e-6, max_iter: int = 0,
+                 precision: str = "fp32", probe_seed: int = 0, want_grad: bool = True,
+                 want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+    """Returns dict(mll, logdet, grad, alpha, info, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(y, torch.float32, "y")
+    n, d = X.shape
+    if Z is not None:
+        _dev(Z, torch.float32, "Z")
+        num_probes = Z.shape[1]
+    t = num_probes + 1
+    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed)
+    mi = max_iter if max_iter > 0 else min(n, 20000)
+    ws = workspace(workspace_bytes(OP_MLL, n, d, t, o.precision, mi), X.device)
+    ks = kern.struct(d)
+    npar = LIB.mfgp_num_params(C.byref(ks))
+    mll, ld = C.c_double(), C.c_double()
+    grad = (C.c_double * npar)() if want_grad else None
+    alpha = torch.empty(n, dtype=torch.float64, device=X.device) if want_alpha else None
+    info = (CgInfoT * t)()
+    st = LIB.mfgp_mll_and_grad(C.byref(ks), _ptr(X), n, _ptr(y), num_probes, _ptr(Z), C.byref(o),
+                               C.byref(mll), C.byref(ld), grad, _ptr(alpha), info, _ptr(ws),
+                               ws.numel(), _stream())
+    _check(st, "mll_and_grad", allow)
+    return dict(mll=mll.value, logdet=ld.value, grad=None if grad is None else list(grad),
+                alpha=alpha, info=_info_list(info, t), status=st)
+
+
+def kernel_adjoint(kern: Kernel, X: torch.Tensor, A: torch.Tensor, B: torch.Tensor,
+                   colw: Sequence[float]) -> list:
+    """sum_c colw_c A_c^T (dK_y/dtheta) B_c for every parameter."""
+    _dev(X, torch.float32, "X")
+    _dev(A, torch.float32, "A")
+    _dev(B, torch.float32, "B")
+    n, d = X.shape
+    t = _cols(A)
+    w = (C.c_double * t)(*[float(v) for v in colw])
+    ks = kern.struct(d)
+    npar = LIB.mfgp_num_params(C.byref(ks))
+    g = (C.c_double * npar)()
+    ws = workspace(workspace_bytes(OP_ADJOINT, n, d, t), X.device)
+    _check(LIB.mfgp_kernel_adjoint(C.byref(ks), _ptr(X), n, _ptr(A), _ptr(B), t, w, g, _ptr(ws),
+                                   ws.numel(), _stream()), "kernel_adjoint")
+    return list(g)
+
+
+def rademacher(seed: int, n: int, p: int, device="cuda") -> torch.Tensor:
+    Z = torch.empty((n, p), dtype=torch.float32, device=device)
+    _check(LIB.mfgp_rademacher(seed, n, p, _ptr(Z), _stream()), "rademacher")
+    return Z
+
+
+def timing_enable(on: bool = True) -> None:
+    """Start (or stop) per-launch HIP-event timing of the entry sweeps on this thread."""
+    _check(LIB.mfgp_timing_enable(1 if on else 0), "timing_enable")
+
+
+SWEEP_F32, SWEEP_F64, SWEEP_ADJOINT, SWEEP_MFMA = range(4)
+
+
+def timing_read(kind: int = -1) -> dict:
+    """Totals since timing_enable for one sweep kind (-1: all): milliseconds, launches,
+    entries and algorithmic FLOP."""
+    ms, n, en, fl = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    _check(LIB.mfgp_timing_read(kind, C.byref(ms), C.byref(n), C.byref(en), C.byref(fl)), "timing_read")
+    return dict(ms=ms.value, launches=n.value, entries=en.value, flops=fl.value)
+
+
+def timing_phases() -> dict:
+    """Host wall milliseconds of mll_and_grad's phases since timing_enable."""
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(LIB.mfgp_timing_phases(C.byref(a), C.byref(b), C.byref(c)), "timing_phases")
+    return dict(cg_ms=a.value, slq_ms=b.value, adjoint_ms=c.value)
+
+
+LOG_2PI = math.log(2.0 * math.pi)

@@ -1,0 +1,153 @@
+"""Host-side checks of the C-ABI library: it loads, exports what include/mfgp.h
+declares, validates arguments before any launch, sizes workspaces, and its
+host-only stochastic-Lanczos quadrature matches the oracle.  No GPU needed."""
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import gp, krylov, probes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfgp.h")
+LIB_PATH = os.path.join(ROOT, "paper_2605_17898_amd", "libmfgp.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB_PATH), reason="libmfgp.so not built")
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2605_17898_amd import mfgp
+    return mfgp
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfgp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = C.CDLL(LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(m):
+    assert m.LIB.mfgp_version() >= 100
+    for code in range(7):
+        assert m.LIB.mfgp_status_string(code)
+    assert m.LIB.mfgp_status_string(99) == b"unknown status"
+
+
+def test_num_params(m):
+    assert m.Kernel("rbf", 0.3).n_params(4) == 3
+    assert m.Kernel("matern52", [0.3, 0.2, 0.5]).n_params(3) == 5
+
+
+def test_workspace_sizes(m):
+    for op in range(6):
+        t = 2 if op != m.OP_PREDICT else 3
+        mi = 100 if op == m.OP_PREDICT else 0
+        assert m.workspace_bytes(op, 1000, 3, t, 0, mi) > 0
+    assert m.workspace_bytes(m.OP_MATVEC, 0, 3, 1) == 0
+    assert m.workspace_bytes(m.OP_MATVEC, 10, 9, 1) == 0      # d > MFGP_MAX_D
+    assert m.workspace_bytes(m.OP_MATVEC, 10, 2, 0) == 0
+    assert m.workspace_bytes(m.OP_MLL, 10, 2, 1) == 0         # needs >= 1 probe
+    # O(n) workspace: 10x the points -> about 10x the bytes
+    a = m.workspace_bytes(m.OP_CG, 10000, 4, 33)
+    b = m.workspace_bytes(m.OP_CG, 100000, 4, 33)
+    assert b < 12 * a
+
+
+def _kern(m, **kw):
+    k = m.Kernel("rbf", 0.3, 1.0, 0.01).struct(2)
+    for key, v in kw.items():
+        setattr(k, key, v)
+    return k
+
+
+@pytest.mark.parametrize("field,value,want", [
+    ("family", 7, 1), ("d", 0, 1), ("d", 9, 6), ("outputscale", 0.0, 1),
+    ("outputscale", float("nan"), 1), ("noise", -1.0, 1),
+])
+def test_matvec_rejects_bad_kernel_before_launch(m, field, value, want):
+    k = _kern(m, **{field: value})
+    dummy = C.c_void_p(16)
+    st = m.LIB.mfgp_kernel_matvec(C.byref(k), dummy, 10, dummy, 1, C.c_void_p(32), 0, dummy, 1 << 20, None)
+    assert st == want
+
+
+def test_matvec_argument_checks(m):
+    k = _kern(m)
+    d = C.c_void_p(16)
+    L = m.LIB
+    assert L.mfgp_kernel_matvec(None, d, 10, d, 1, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), None, 10, d, 1, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 0, d, 1, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 0, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, d, 0, d, 1 << 20, None) == m.ERR_ARG   # KV aliases V
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, C.c_void_p(32), 5, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, C.c_void_p(32), 0, d, 16, None) == m.ERR_WORKSPACE
+
+
+def test_cg_and_mll_argument_checks(m):
+    k = _kern(m)
+    d = C.c_void_p(16)
+    L = m.LIB
+    info = (m.CgInfoT * 2)()
+    o = m.cg_opts(tol=0.0)
+    assert L.mfgp_cg_solve(C.byref(k), d, 10, d, 1, d, C.byref(o), info, None, d, 1 << 30, None) == m.ERR_ARG
+    o = m.cg_opts(tol=1e-6)
+    k0 = _kern(m, noise=0.0)   # a solve needs sigma^2 > 0
+    assert L.mfgp_cg_solve(C.byref(k0), d, 10, d, 1, d, C.byref(o), info, None, d, 1 << 30, None) == m.ERR_ARG
+    assert L.mfgp_cg_solve(C.byref(k), d, 10, d, 1, d, C.byref(o), info, None, d, 64, None) == m.ERR_WORKSPACE
+    mll = C.c_double()
+    assert L.mfgp_mll_and_grad(C.byref(k), d, 10, d, 0, None, C.byref(o), C.byref(mll), None, None, None,
+                               None, d, 1 << 30, None) == m.ERR_ARG
+    assert L.mfgp_rademacher(1, 0, 3, d, None) == m.ERR_ARG
+    assert L.mfgp_slq_quadrature(None, 3, 1.0, C.byref(mll)) == m.ERR_ARG
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern32"])
+def test_host_slq_matches_oracle_quadrature(m, family):
+    rng = np.random.default_rng(4)
+    n = 200
+    X = rng.uniform(0, 1, size=(n, 2))
+    kern = gp.Kern(family, 0.25, 1.0, 0.03)
+    A = gp.ky_matrix(kern, X)
+    Z = probes.rademacher(91, n, 3)
+    _, al, be, it = krylov.cg(lambda V: A @ V, Z, tol=1e-10)
+    exact = krylov.quadform_log(A, Z)
+    for c in range(3):
+        coeffs = list(zip(al[c], be[c]))
+        q_lib = m.slq_quadrature(coeffs, n)
+        q_orc = krylov.quadrature(*krylov.cg_to_tridiag(al[c], be[c]), n)
+        assert q_lib == pytest.approx(q_orc, rel=1e-11)
+        assert q_lib == pytest.approx(exact[c], rel=1e-7)
+
+
+def test_host_slq_special_cases(m):
+    # one step: T = [1/alpha], q = |z|^2 log(1/alpha)
+    assert m.slq_quadrature([(0.5, 0.0)], 4.0) == pytest.approx(4.0 * math.log(2.0), rel=1e-15)
+    # a breakdown coefficient is reported, not hidden
+    with pytest.raises(m.MfgpError):
+        m.slq_quadrature([(-1.0, 0.1), (1.0, 0.1)], 4.0)
+    # random SPD tridiagonal against a dense eigen-solve
+    rng = np.random.default_rng(3)
+    for mlen in (2, 7, 60, 300):
+        al = rng.uniform(0.1, 2.0, size=mlen)
+        be = rng.uniform(0.0, 0.9, size=mlen)
+        dg, of = krylov.cg_to_tridiag(al, be)
+        T = np.diag(dg) + np.diag(of, 1) + np.diag(of, -1)
+        w, Q = np.linalg.eigh(T)
+        if w.min() <= 0:
+            continue
+        ref = 3.0 * float(np.sum(Q[0] ** 2 * np.log(w)))
+        assert m.slq_quadrature(list(zip(al, be)), 3.0) == pytest.approx(ref, rel=1e-10, abs=1e-12)

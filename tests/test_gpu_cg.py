@@ -1,0 +1,138 @@
+"""CG solve, predictive mean and failure handling of the HIP path vs the oracle.
+
+Gates (the floors behind them are derived in the design notes):
+* the solver's recomputed residual against its own FP32-entry operator
+  (FP64 sums, FP64 solution) <= 1e-6;
+* the oracle's FP64 residual of the returned solution <= 5e-5, and the
+  solution within 1e-4 of the Cholesky solution (relative 2-norm): the FP32
+  kernel entries alone move the exact solution by ~3e-5 at exact1k;
+* predictive mean within 1e-4 (relative) of the oracle's Cholesky mean.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gp, krylov
+from paper_2605_17898_amd import inputs
+from tests.gpu_util import banner, col_rel_err, dev, host, mkern, okern
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2605_17898_amd import mfgp
+    return mfgp
+
+
+def test_cg_exact1k_vs_cholesky(mf):
+    banner("cg exact1k n=1024 tol=1e-6")
+    w = inputs.exact1k()
+    k = okern(w)
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(w.y), tol=1e-6)
+    assert st == mf.OK, info
+    assert info[0]["rel_resid_true"] <= 1e-6
+    xs = host(x)
+    ref = gp.solve(k, w.X, w.y)
+    assert np.linalg.norm(xs - ref) / np.linalg.norm(ref) <= 1e-4
+    assert gp.solve_residual(k, w.X, w.y, xs)[0] <= 5e-5
+    # the library's own recomputed residual agrees with what it reported
+    _, rel = mf.residual(mkern(w), dev(w.X), dev(w.y), x)
+    assert rel[0] == pytest.approx(info[0]["rel_resid_true"], rel=1e-6, abs=1e-12)
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+def test_cg_multi_column_families(mf, family):
+    banner(f"cg multi-column family={family} n=1500 t=5")
+    w = inputs.random_problem(77, 1500, 3, family, ard=True, noise=0.02)
+    B = np.concatenate([w.y[:, None], inputs.gaussian_rhs(5, w.n, 4)], axis=1)
+    x, info, lan, st = mf.cg_solve(mkern(w), dev(w.X), dev(B), tol=1e-6, want_lanczos=True)
+    assert st == mf.OK
+    assert max(i["rel_resid_true"] for i in info) <= 1e-6
+    ref = gp.solve(okern(w), w.X, B)
+    assert col_rel_err(host(x), ref).max() <= 1e-4
+    # logged Lanczos coefficients are positive and as many as the first cycle
+    L = host(lan)
+    for c in range(5):
+        m = info[c]["lanczos_len"]
+        assert m >= 1 and np.all(L[c, :m, 0] > 0) and np.all(L[c, :m, 1] >= 0)
+
+
+def test_cg_matern20k_full_size(mf):
+    # Full workload: n = 20000, d = 3, Matern-5/2 (l = 1), 2000 test points.
+    banner("cg matern20k full size + predictive mean")
+    w = inputs.matern20k()
+    k = okern(w)
+    X = dev(w.X)
+    x, info, _, st = mf.cg_solve(mkern(w), X, dev(w.y), tol=1e-6)
+    assert st == mf.OK and info[0]["rel_resid_true"] <= 1e-6
+    xs = host(x)
+    rows = np.random.default_rng(3).choice(w.n, size=2048, replace=False)
+    assert gp.solve_residual(k, w.X, w.y, xs, rows=rows)[0] <= 5e-5
+    a32 = xs.astype(np.float32)
+    mu = host(mf.predict_mean(mkern(w), X, dev(w.Xs), dev(a32)))
+    ref = gp.cross_matvec_blocked(k, w.Xs, w.X, a32.astype(np.float64))
+    assert np.linalg.norm(mu - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_predict_mean_vs_cholesky_mean(mf):
+    banner("predict mean matern20k geometry n=4000 vs Cholesky")
+    w = inputs.matern20k(n=4000, m=777)
+    k = okern(w)
+    X = dev(w.X)
+    x, info, _, st = mf.cg_solve(mkern(w), X, dev(w.y), tol=1e-6)
+    assert st == mf.OK
+    mu = host(mf.predict_mean(mkern(w), X, dev(w.Xs), x.float()))
+    ref = gp.predict_mean(k, w.X, w.Xs, gp.solve(k, w.X, w.y))
+    assert np.linalg.norm(mu - ref) / np.linalg.norm(ref) <= 1e-4
+    # a test point far from all data predicts 0
+    far = np.full((3, 3), 1e3, np.float32)
+    assert np.abs(host(mf.predict_mean(mkern(w), X, dev(far), x.float()))).max() == 0.0
+
+
+def test_cg_rbf100k_full_size_sampled(mf):
+    banner("cg rbf100k full size, y column, sampled residual")
+    w = inputs.rbf100k(probes=0)
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(w.y), tol=1e-6)
+    assert st == mf.OK and info[0]["rel_resid_true"] <= 1e-6
+    rows = np.random.default_rng(4).choice(w.n, size=1024, replace=False)
+    assert gp.solve_residual(okern(w), w.X, w.y, host(x), rows=rows)[0] <= 5e-5
+
+
+def test_cg_edge_cases(mf):
+    banner("cg edge cases: zero rhs, warm start, max_iter=1, NaN, determinism")
+    w = inputs.exact1k(n=700)
+    K, X = mkern(w), dev(w.X)
+    B = np.stack([np.zeros(w.n, np.float32), w.y], axis=1)
+    x, info, _, st = mf.cg_solve(K, X, dev(B), tol=1e-6)
+    assert st == mf.OK and info[0]["iters"] == 0 and not host(x)[:, 0].any()
+    # warm start at the solution: no further iterations needed
+    x2, info2, _, st2 = mf.cg_solve(K, X, dev(B), tol=1e-6, x0=x)
+    assert st2 == mf.OK and info2[1]["iters"] == 0
+    # max_iter = 1 -> not converged, finite best iterate
+    x3, info3, _, st3 = mf.cg_solve(K, X, dev(w.y), tol=1e-6, max_iter=1)
+    assert st3 == mf.NOT_CONVERGED and info3[0]["iters"] == 1 and np.isfinite(host(x3)).all()
+    # NaN in the right-hand side -> breakdown reported, no hang
+    yb = w.y.copy()
+    yb[5] = np.nan
+    _, info4, _, st4 = mf.cg_solve(K, X, dev(yb), tol=1e-6)
+    assert st4 == mf.BREAKDOWN and info4[0]["status"] == mf.BREAKDOWN
+    # bitwise determinism
+    a, _, _, _ = mf.cg_solve(K, X, dev(w.y), tol=1e-6)
+    b, _, _, _ = mf.cg_solve(K, X, dev(w.y), tol=1e-6)
+    assert torch.equal(a, b)
+
+
+def test_cg_coefficients_match_oracle_cg(mf):
+    # The first Lanczos coefficients of the FP32 CG agree with FP64 CG on the
+    # same system (they drift later as FP32 rounding accumulates).
+    banner("cg Lanczos coefficients vs oracle CG")
+    w = inputs.exact1k(n=500, probes=2)
+    K, X = mkern(w), dev(w.X)
+    x, info, lan, st = mf.cg_solve(K, X, dev(w.Z), tol=1e-6, want_lanczos=True)
+    _, al, be, _ = krylov.cg(lambda V: gp.ky_matvec(okern(w), w.X, V), w.Z.astype(np.float64), tol=1e-6)
+    L = host(lan)
+    for c in range(2):
+        np.testing.assert_allclose(L[c, :10, 0], al[c][:10], rtol=1e-4)
+        np.testing.assert_allclose(L[c, :10, 1], be[c][:10], rtol=1e-4)

@@ -1,0 +1,124 @@
+"""Log marginal likelihood, SLQ log-determinant and gradients of the HIP path.
+
+Parity is against the oracle evaluating the SAME estimator with the SAME
+probes exactly (Cholesky solves, dense eigen-solve for z^T log(K_y) z), and
+against exact quantities in exact mode (probes sqrt(N) e_c make the
+Hutchinson trace and the SLQ log-det exact).  Gradient bar: relative 2-norm
+<= 1e-3 and per component |d_p| <= 1e-3 max(|g_p|, 1e-3 ||g||_inf).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gp, krylov
+from paper_2605_17898_amd import inputs
+from tests.gpu_util import banner, dev, host, mkern, okern
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2605_17898_amd import mfgp
+    return mfgp
+
+
+def grad_ok(g, ref):
+    g, ref = np.asarray(g), np.asarray(ref)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    comp = np.all(np.abs(g - ref) <= 1e-3 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()))
+    return rel <= 1e-3 and comp, rel
+
+
+def same_probe_reference(w, k):
+    X, y, Z = w.X.astype(np.float64), w.y.astype(np.float64), w.Z.astype(np.float64)
+    A = gp.ky_matrix(k, X)
+    q = krylov.quadform_log(A, Z)
+    ld = float(q.mean())
+    alpha = gp.solve(k, X, y)
+    mll = -0.5 * (float(y @ alpha) + ld + len(y) * math.log(2 * math.pi))
+    return mll, ld, gp.same_probe_grad(k, X, y, Z), alpha
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern52"])
+def test_mll_exact1k_same_probe(mf, family):
+    banner(f"mll+grad exact1k n=1024 p=32 family={family}")
+    w = inputs.exact1k(probes=32)
+    k = okern(w, family=family)
+    r = mf.mll_and_grad(mkern(w, family=family), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6,
+                        want_alpha=True)
+    assert r["status"] == mf.OK, r["info"]
+    mll, ld, g, alpha = same_probe_reference(w, k)
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    assert r["mll"] == pytest.approx(mll, rel=1e-4)
+    ok, rel = grad_ok(r["grad"], g)
+    assert ok, (r["grad"], g, rel)
+    assert np.linalg.norm(host(r["alpha"]) - alpha) / np.linalg.norm(alpha) <= 1e-4
+
+
+def test_mll_ard_matern32_same_probe(mf):
+    banner("mll+grad ARD matern32 n=1500 d=3 p=8")
+    w = inputs.random_problem(5, 1500, 3, "matern32", ard=True, noise=0.05)
+    w.Z = inputs.rademacher(np.random.default_rng(9), w.n, 8)
+    k = okern(w)
+    r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6)
+    assert r["status"] == mf.OK
+    mll, ld, g, _ = same_probe_reference(w, k)
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    ok, rel = grad_ok(r["grad"], g)
+    assert ok, (r["grad"], g, rel)
+
+
+@pytest.mark.parametrize("family,ard", [("rbf", False), ("matern12", True), ("matern52", True)])
+def test_exact_mode_vs_cholesky_and_fd(mf, family, ard):
+    # probes sqrt(N) e_c: SLQ gives log|K_y| and Hutchinson gives tr(K_y^-1 dK) exactly
+    banner(f"exact-mode mll+grad family={family} ard={ard} n=200")
+    n = 200
+    w = inputs.random_problem(12, n, 2, family, ard=ard, noise=0.05)
+    w.Z = (math.sqrt(n) * np.eye(n)).astype(np.float32)
+    k = okern(w)
+    r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-7)
+    assert r["status"] == mf.OK
+    X, y = w.X.astype(np.float64), w.y.astype(np.float64)
+    assert r["logdet"] == pytest.approx(gp.logdet(k, X), rel=1e-5)
+    assert r["mll"] == pytest.approx(gp.mll(k, X, y), rel=1e-5)
+    g_exact = gp.mll_grad(k, X, y)
+    ok, rel = grad_ok(r["grad"], g_exact)
+    assert ok, (r["grad"], g_exact, rel)
+    # central finite differences of the oracle's exact MLL
+    th = k.params(2)
+    fd = []
+    for p in range(len(th)):
+        h = 1e-5 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd.append((gp.mll(k.with_params(tp), X, y) - gp.mll(k.with_params(tm), X, y)) / (2 * h))
+    ok, rel = grad_ok(r["grad"], fd)
+    assert ok, (r["grad"], fd, rel)
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+@pytest.mark.parametrize("ard", [False, True])
+def test_adjoint_vs_oracle(mf, family, ard):
+    banner(f"adjoint family={family} ard={ard} n=1200 t=3")
+    w = inputs.random_problem(21, 1200, 3, family, ard=ard, noise=0.03)
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((w.n, 3)).astype(np.float32)
+    B = rng.standard_normal((w.n, 3)).astype(np.float32)
+    colw = [0.5, -0.25, 1.5]
+    g = mf.kernel_adjoint(mkern(w), dev(w.X), dev(A), dev(B), colw)
+    ref = gp.adjoint_bilinear(okern(w), w.X, A, B, colw)
+    assert np.linalg.norm(np.array(g) - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+def test_seeded_probes_equal_explicit(mf):
+    banner("mll with device-seeded probes == explicit SplitMix64 probes")
+    from oracle import probes
+    w = inputs.exact1k(n=600)
+    Z = probes.rademacher(1234, w.n, 6).astype(np.float32)
+    r1 = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(Z), tol=1e-6)
+    r2 = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), num_probes=6, probe_seed=1234, tol=1e-6)
+    assert r1["mll"] == r2["mll"] and r1["grad"] == r2["grad"]
