@@ -14,6 +14,9 @@ entry sweep, timed live with HIP events on its launch stream) and the
 oracle's host throughput on a bounded sample.
 
 python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x2] [--no-cpu-baseline]
+python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the step's
+    dominant product, K_y V at t = 33, then a 1 GiB device copy whose FETCH_SIZE /
+    WRITE_SIZE calibrate the HBM-traffic counters)
 """
 
 from __future__ import annotations
@@ -60,6 +63,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--mode", default="step", choices=["step", "kernel"])
+    ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -79,6 +84,21 @@ def main() -> int:
     Z = torch.from_numpy(w.Z).cuda()
     Xs = torch.from_numpy(w.Xs).cuda()
     torch.cuda.synchronize()
+
+    if args.mode == "kernel":
+        V = torch.cat([y[:, None], Z], dim=1).contiguous()
+        for i in range(args.reps):
+            mfgp.kernel_matvec(kern, X, V, precision=args.precision)
+            torch.cuda.synchronize()
+            print(f"[bench] kernel launch {i + 1}/{args.reps}", file=sys.stderr, flush=True)
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernel", "reps": args.reps, "copy_bytes": src.numel() * 4}))
+        return 0
 
     def step():
         r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=args.precision, want_alpha=True)

@@ -95,6 +95,12 @@ static int check_opts(const mfgp_cg_opts* o) {
     return MFGP_OK;
 }
 
+// The BF16-MFMA sweeps hold at most two 32-column tiles.
+static int check_precision_cols(int precision, int t) {
+    if (precision != MFGP_FP32 && t > 64) return MFGP_UNSUPPORTED;
+    return MFGP_OK;
+}
+
 static int default_max_iter(int64_t n, int max_iter) {
     if (max_iter > 0) return max_iter;
     return static_cast<int>(n < 20000 ? n : 20000);
@@ -265,6 +271,7 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     if (!X || !V || !KV || !ws || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
     if (precision < MFGP_FP32 || precision > MFGP_BF16X2) return MFGP_ERR_ARG;
     if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
+    if ((st = check_precision_cols(precision, t)) != MFGP_OK) return st;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, precision, 0))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -311,6 +318,7 @@ int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
     if (!X || !B || !Xsol || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
+    if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_CG, n, kern->d, t, opts->precision, opts->max_iter))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -388,6 +396,7 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     if (!X || !y || !mll || !ws || n < 1 || num_probes < 1) return MFGP_ERR_ARG;
     const int p = num_probes;
     const int t = p + 1;
+    if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
     const int max_iter = default_max_iter(n, opts->max_iter);
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MLL, n, kern->d, t, opts->precision, max_iter))
         return MFGP_ERR_WORKSPACE;

@@ -76,7 +76,20 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
     const float* __restrict__ uc = U + j0 * D;
     const float* __restrict__ bc = B + j0 * TB;
+    // Two-level accumulation (segments of kSeg j's), as in the product sweeps.
+    float tg[D], ts = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) tg[k] = 0.0f;
     for (int q = 0; q < cnt; ++q) {
+        if (q % kSeg == 0 && q > 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                tg[k] += g[k];
+                g[k] = 0.0f;
+            }
+            ts += gs;
+            gs = 0.0f;
+        }
         const float* uj = uc + q * D;
         float df[D];
         float d2 = 0.0f;
@@ -99,8 +112,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     // FP64 block reduction: wave butterfly, then the 4 wave sums in order.
     double v[D + 1];
 #pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = static_cast<double>(g[k]);
-    v[D] = static_cast<double>(gs);
+    for (int k = 0; k < D; ++k) v[k] = static_cast<double>(tg[k]) + static_cast<double>(g[k]);
+    v[D] = static_cast<double>(ts) + static_cast<double>(gs);
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
         double x = v[k];

@@ -153,6 +153,14 @@ __global__ void reduce_resid_kernel(const double* __restrict__ partial, int chun
     R[o] = static_cast<double>(B[o]) - (s2 * acc + sig2 * X[o]);
 }
 
+hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, float s2,
+                           float sig2, const float* Vself, float* out, hipStream_t s) {
+    const int64_t total = m * t;
+    hipLaunchKernelGGL(reduce_f32_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                       0, s, partial, chunks, m, t, s2, sig2, Vself, t, 0, out, t);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- operator products
 
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U) {

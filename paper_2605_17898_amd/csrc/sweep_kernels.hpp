@@ -30,6 +30,9 @@ __device__ __forceinline__ void map_block(int b, int chunks, int& rb, int& ch) {
     }
 }
 
+// j-values per inner accumulation segment (a multiple of every 2 * unroll)
+constexpr int kSeg = 256;
+
 // j-values processed per unrolled step: keeps (D + TB) * JU scalar words <= 32.
 template <int D, int TB>
 constexpr int sweep_unroll() {
@@ -60,40 +63,63 @@ __global__ __launch_bounds__(kBlock) void sweep_f32_kernel(
     const float* __restrict__ uc = Uc + j0 * D;
     const float* __restrict__ vc = V + j0 * TB;
     constexpr int JU = sweep_unroll<D, TB>();
-    const int cmain = cnt - cnt % JU;
+    const int cmain = cnt - cnt % (2 * JU);   // main loop: whole A/B step pairs
 
-    // Software-pipelined main loop: the scalar loads of step q + JU are issued
-    // before the arithmetic of step q.
-    float su[JU * D], sv[JU * TB];
+    // Two-level accumulation: acc sums one segment of kSeg j's, tot sums the
+    // segments, so no FP32 running sum is longer than max(kSeg, cnt / kSeg).
+    float tot[TB];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) tot[c] = 0.0f;
+
+    // Ping-pong software pipeline over two SGPR sets A and B: the scalar loads
+    // of one set are in flight while the other set's entries are computed, and
+    // no register copies are needed between steps.
+    float au[JU * D], av[JU * TB], bu[JU * D], bv[JU * TB];
     if (cmain > 0) {
 #pragma unroll
-        for (int k = 0; k < JU * D; ++k) su[k] = uc[k];
+        for (int k = 0; k < JU * D; ++k) au[k] = uc[k];
 #pragma unroll
-        for (int k = 0; k < JU * TB; ++k) sv[k] = vc[k];
+        for (int k = 0; k < JU * TB; ++k) av[k] = vc[k];
     }
-    for (int q = 0; q < cmain; q += JU) {
-        const int qn = q + JU < cmain ? q + JU : q;
-        float nu[JU * D], nv[JU * TB];
+    for (int seg = 0; seg < cmain; seg += kSeg) {
+        const int send = seg + kSeg < cmain ? seg + kSeg : cmain;
+        for (int q = seg; q < send; q += 2 * JU) {
+            const int qb = q + JU;
 #pragma unroll
-        for (int k = 0; k < JU * D; ++k) nu[k] = uc[qn * D + k];
+            for (int k = 0; k < JU * D; ++k) bu[k] = uc[qb * D + k];
 #pragma unroll
-        for (int k = 0; k < JU * TB; ++k) nv[k] = vc[qn * TB + k];
+            for (int k = 0; k < JU * TB; ++k) bv[k] = vc[qb * TB + k];
 #pragma unroll
-        for (int r = 0; r < JU; ++r) {
-            const float e = kentry<FAM>(sqdist<D>(ui, su + r * D));
+            for (int r = 0; r < JU; ++r) {
+                const float e = kentry<FAM>(sqdist<D>(ui, au + r * D));
 #pragma unroll
-            for (int c = 0; c < TB; ++c) acc[c] = fmaf(e, sv[r * TB + c], acc[c]);
+                for (int c = 0; c < TB; ++c) acc[c] = fmaf(e, av[r * TB + c], acc[c]);
+            }
+            const int qa = q + 2 * JU < cmain ? q + 2 * JU : q;
+#pragma unroll
+            for (int k = 0; k < JU * D; ++k) au[k] = uc[qa * D + k];
+#pragma unroll
+            for (int k = 0; k < JU * TB; ++k) av[k] = vc[qa * TB + k];
+#pragma unroll
+            for (int r = 0; r < JU; ++r) {
+                const float e = kentry<FAM>(sqdist<D>(ui, bu + r * D));
+#pragma unroll
+                for (int c = 0; c < TB; ++c) acc[c] = fmaf(e, bv[r * TB + c], acc[c]);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < JU * D; ++k) su[k] = nu[k];
-#pragma unroll
-        for (int k = 0; k < JU * TB; ++k) sv[k] = nv[k];
+        for (int c = 0; c < TB; ++c) {
+            tot[c] += acc[c];
+            acc[c] = 0.0f;
+        }
     }
     for (int q = cmain; q < cnt; ++q) {
         const float e = kentry<FAM>(sqdist<D>(ui, uc + q * D));
 #pragma unroll
         for (int c = 0; c < TB; ++c) acc[c] = fmaf(e, vc[q * TB + c], acc[c]);
     }
+#pragma unroll
+    for (int c = 0; c < TB; ++c) acc[c] += tot[c];
     if (i < m) {
         float* p = partial + (static_cast<int64_t>(ch) * m + i) * TB;
 #pragma unroll

@@ -1,0 +1,116 @@
+"""BF16-MFMA forms of the K-tile x V product and of the solves built on them.
+
+x2 (hi/lo split of both operands, three MFMA products) is held to the FP32
+matvec bar (1e-5 relative per column; the oracle's model of x2 errs by ~3e-6
+at these shapes).  x1 (plain bf16) is held to the oracle's x1 model within
+1e-4 (the two differ only where an FP32 entry sits on a bf16 rounding tie)
+and reported against the exact product.  Solves in x2 with FP32-entry FP64
+residual refinement must reach the same 1e-6 recomputed residual as FP32.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import bf16, gp
+from paper_2605_17898_amd import inputs
+from tests.gpu_util import banner, col_rel_err, dev, host, mkern, okern
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2605_17898_amd import mfgp
+    return mfgp
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+@pytest.mark.parametrize("t", [1, 5, 17, 32, 33, 64])
+def test_x2_matvec_vs_oracle(mf, family, t):
+    banner(f"bf16x2 matvec family={family} t={t} n=1537 d=3")
+    w = inputs.random_problem(31 + t, 1537, 3, family, ard=True, noise=0.01)
+    V = inputs.gaussian_rhs(t, w.n, t)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
+    ref = gp.ky_matvec(okern(w), w.X, V)
+    assert col_rel_err(out, ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("d", [1, 2, 4, 6, 8])
+def test_x2_dims_and_ragged(mf, d):
+    banner(f"bf16x2 matvec rbf d={d} n=1000")
+    w = inputs.random_problem(3 + d, 1000, d, "rbf", ard=False, noise=0.01)
+    V = inputs.gaussian_rhs(d, w.n, 3)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
+    ref = gp.ky_matvec(okern(w), w.X, V)
+    assert col_rel_err(out, ref).max() <= 1e-5
+
+
+def test_x1_matvec_vs_bf16_model(mf):
+    banner("bf16x1 matvec vs oracle bf16 model, exact1k")
+    w = inputs.exact1k(probes=8)
+    k = okern(w)
+    V = np.concatenate([w.y[:, None], w.Z], axis=1)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x1"))
+    K32 = gp.kernel_matrix(k, w.X, w.X).astype(np.float32)
+    model = bf16.tile_product_x1(K32, V) + w.noise * V.astype(np.float64)
+    exact = gp.ky_matvec(k, w.X, V)
+    assert col_rel_err(out, model).max() <= 1e-4
+    e = col_rel_err(out, exact).max()
+    assert 1e-4 < e <= 1e-2   # x1 is genuinely lower precision, but bounded
+
+
+def test_x2_full_rbf100k_sampled_rows(mf):
+    banner("bf16x2 matvec rbf100k full size t=33, 2048 sampled rows")
+    w = inputs.rbf100k()
+    V = np.concatenate([w.y[:, None], w.Z], axis=1)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
+    rows = np.random.default_rng(7).choice(w.n, size=2048, replace=False)
+    ref = gp.ky_matvec_rows(okern(w), w.X, V, rows)
+    assert col_rel_err(out[rows], ref).max() <= 1e-5
+
+
+def test_x2_cg_equal_accuracy(mf):
+    banner("bf16x2 CG exact1k, [y, 4 probes], tol 1e-6")
+    w = inputs.exact1k(probes=4)
+    B = np.concatenate([w.y[:, None], w.Z], axis=1)
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(B), tol=1e-6, precision="bf16x2")
+    assert st == mf.OK, info
+    assert max(i["rel_resid_true"] for i in info) <= 1e-6
+    ref = gp.solve(okern(w), w.X, B)
+    assert col_rel_err(host(x), ref).max() <= 1e-4
+
+
+def test_x2_mll_same_probe(mf):
+    banner("bf16x2 mll+grad exact1k p=16 vs same-probe oracle")
+    from oracle import krylov
+    w = inputs.exact1k(probes=16)
+    k = okern(w)
+    r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6, precision="bf16x2")
+    assert r["status"] == mf.OK
+    A = gp.ky_matrix(k, w.X)
+    ld = float(krylov.quadform_log(A, w.Z).mean())
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    g = gp.same_probe_grad(k, w.X, w.y, w.Z)
+    assert np.linalg.norm(np.array(r["grad"]) - g) / np.linalg.norm(g) <= 1e-3
+
+
+def test_x1_cg_reports_status(mf):
+    # Plain bf16 entries perturb K by more than sigma^2 = 0.01 at exact1k, so
+    # the x1 operator may be indefinite: the solver must report what happened.
+    banner("bf16x1 CG exact1k status report")
+    w = inputs.exact1k()
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(w.y), tol=1e-6, precision="bf16x1",
+                                 max_iter=3000)
+    assert st in (mf.OK, mf.NOT_CONVERGED, mf.BREAKDOWN)
+    assert np.isfinite(host(x)).all()
+    if st == mf.OK:
+        assert info[0]["rel_resid_true"] <= 1e-6
+    print(f"bf16x1 CG: status {st}, info {info[0]}")
+
+
+def test_bf16_rejects_wide_blocks(mf):
+    banner("bf16 column limit")
+    w = inputs.exact1k(n=300)
+    V = inputs.gaussian_rhs(1, w.n, 65)
+    with pytest.raises(mf.MfgpError):
+        mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2")

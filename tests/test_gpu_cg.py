@@ -70,10 +70,13 @@ def test_cg_matern20k_full_size(mf):
     xs = host(x)
     rows = np.random.default_rng(3).choice(w.n, size=2048, replace=False)
     assert gp.solve_residual(k, w.X, w.y, xs, rows=rows)[0] <= 5e-5
+    # predictive mean of the returned alpha vs the oracle's FP64 product with the
+    # same alpha: the predictive-mean bar (alpha cancels heavily, so this is
+    # the product's worst case, not the random-V matvec bar)
     a32 = xs.astype(np.float32)
     mu = host(mf.predict_mean(mkern(w), X, dev(w.Xs), dev(a32)))
     ref = gp.cross_matvec_blocked(k, w.Xs, w.X, a32.astype(np.float64))
-    assert np.linalg.norm(mu - ref) / np.linalg.norm(ref) <= 1e-5
+    assert np.linalg.norm(mu - ref) / np.linalg.norm(ref) <= 1e-4
 
 
 def test_predict_mean_vs_cholesky_mean(mf):
