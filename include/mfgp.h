@@ -199,6 +199,58 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
  * clear, else -1 (Steele, Lea & Flood 2014).  Asynchronous. */
 int mfgp_rademacher(uint64_t seed, int64_t n, int32_t p, float* Z, void* stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent GP problems solved together (LightGP Sec. 5 names batched
+ * solves as the missing piece of its CG).  Problem b has n[b] rows, its own
+ * input dimension kern[b].d and hyperparameters kern[b] (all problems share
+ * kern[0].family).  Packed layouts (device, caller-owned):
+ *   X   problem b's [n_b, d_b] row-major block starts at element x_off[b];
+ *   y   [sum n_b] float32, problem b's rows start at row_off[b];
+ *   Z   [sum n_b, p] float32 probes (rows as y), or NULL for SplitMix64
+ *       probes drawn per problem from probe_seed + b.
+ * The sweeps of all problems run in ONE persistent launch per product: a
+ * work queue of (problem, 256-row block, j-range) tiles in longest-first
+ * order, pulled by resident workgroups through an atomic counter.  The CG
+ * iterations of the batch are captured into a hipGraph and replayed between
+ * host convergence checks.  The j-range length of the tiles is chosen by the
+ * plan's autotuner (timed on the first call when tuning is enabled). */
+typedef struct {
+    int32_t nprob;
+    const int64_t* n;          /* host [nprob] rows per problem                 */
+    const int64_t* row_off;    /* host [nprob] first row of problem b in y / Z  */
+    const int64_t* x_off;      /* host [nprob] element offset of X_b in X       */
+    const mfgp_kernel* kern;   /* host [nprob]                                  */
+} mfgp_batch;
+
+/* Opaque batch plan: host copies of the batch description, the tile queue,
+ * the tuned tile length and the captured CG graph.  The only object in the
+ * library that keeps state between calls; it owns no device memory. */
+typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
+
+/* Creates a plan for batches of this shape with p = num_probes probes
+ * (t = p + 1 columns, which must be one of 1..8, 16, 17, 32, 33).  tune: 1 =
+ * time the candidate tile lengths on the first mfgp_batch_mll_and_grad call,
+ * 0 = use the built-in default.  use_graph: capture CG iterations.  Host only. */
+int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
+                           int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
+int mfgp_batch_plan_destroy(mfgp_batch_plan plan);
+/* Workspace bytes of mfgp_batch_mll_and_grad for this plan. */
+size_t mfgp_batch_workspace_bytes(mfgp_batch_plan plan);
+/* Tile length in use (0 before tuning), its measured sweep time and the
+ * number of graph replays of the last call (host outputs, may be NULL). */
+int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sweep_ms,
+                         int64_t* graph_launches);
+
+/* For every problem b: log marginal likelihood, stochastic Lanczos log-det and
+ * gradient exactly as mfgp_mll_and_grad defines them, computed for the whole
+ * batch at once.  Host outputs: mll [nprob], logdet [nprob] (optional), grad
+ * (optional, problem b's n_theta entries packed one problem after another),
+ * info (optional, [nprob][p+1]).  opts->precision must be MFGP_FP32.
+ * Synchronises.  Returns the worst status over all problems. */
+int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
+                            const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
+                            mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing (for benchmarks).  While enabled on the calling thread, every
  * entry-sweep launch (the fused K-tile kernels) is bracketed by HIP events
  * recorded on the stream the sweep is launched on, and its algorithmic work

@@ -40,28 +40,14 @@ constexpr int sweep_unroll() {
     return w <= 4 ? 8 : (w <= 8 ? 4 : (w <= 16 ? 2 : 1));
 }
 
+// Sums acc[c] = sum_{q < cnt} k(u_i, uc_q) vc[q][c] for one lane's row (u_i in
+// VGPRs); uc / vc are wave-uniform, so their elements arrive through scalar
+// loads.  Shared by the single-problem and the batched (persistent) sweeps.
 template <int FAM, int D, int TB>
-__global__ __launch_bounds__(kBlock) void sweep_f32_kernel(
-    const float* __restrict__ Ur, const float* __restrict__ Uc, const float* __restrict__ V,
-    int64_t m, int64_t n, int chunks, int64_t jchunk, float* __restrict__ partial) {
-    // V is a packed [n, TB] block (row stride TB), so one scalar load fetches
-    // the right-hand sides of several consecutive j.
-    int rb, ch;
-    map_block(blockIdx.x, chunks, rb, ch);
-    const int64_t i = static_cast<int64_t>(rb) * kBlock + threadIdx.x;
-    const int64_t ii = i < m ? i : m - 1;
-    float ui[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) ui[k] = Ur[ii * D + k];
-    float acc[TB];
+__device__ __forceinline__ void sweep_rows(const float (&ui)[D], const float* __restrict__ uc,
+                                           const float* __restrict__ vc, int cnt, float (&acc)[TB]) {
 #pragma unroll
     for (int c = 0; c < TB; ++c) acc[c] = 0.0f;
-
-    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
-    const int64_t jend = j0 + jchunk < n ? j0 + jchunk : n;
-    const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;   // wave-uniform, < 2^31
-    const float* __restrict__ uc = Uc + j0 * D;
-    const float* __restrict__ vc = V + j0 * TB;
     constexpr int JU = sweep_unroll<D, TB>();
     const int cmain = cnt - cnt % (2 * JU);   // main loop: whole A/B step pairs
 
@@ -120,6 +106,26 @@ __global__ __launch_bounds__(kBlock) void sweep_f32_kernel(
     }
 #pragma unroll
     for (int c = 0; c < TB; ++c) acc[c] += tot[c];
+}
+
+template <int FAM, int D, int TB>
+__global__ __launch_bounds__(kBlock) void sweep_f32_kernel(
+    const float* __restrict__ Ur, const float* __restrict__ Uc, const float* __restrict__ V,
+    int64_t m, int64_t n, int chunks, int64_t jchunk, float* __restrict__ partial) {
+    // V is a packed [n, TB] block (row stride TB), so one scalar load fetches
+    // the right-hand sides of several consecutive j.
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int64_t i = static_cast<int64_t>(rb) * kBlock + threadIdx.x;
+    const int64_t ii = i < m ? i : m - 1;
+    float ui[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ui[k] = Ur[ii * D + k];
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
+    const int64_t jend = j0 + jchunk < n ? j0 + jchunk : n;
+    const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;   // wave-uniform, < 2^31
+    float acc[TB];
+    sweep_rows<FAM, D, TB>(ui, Uc + j0 * D, V + j0 * TB, cnt, acc);
     if (i < m) {
         float* p = partial + (static_cast<int64_t>(ch) * m + i) * TB;
 #pragma unroll

@@ -1,10 +1,14 @@
 """BF16-MFMA forms of the K-tile x V product and of the solves built on them.
 
-x2 (hi/lo split of both operands, three MFMA products) is held to the FP32
-matvec bar (1e-5 relative per column; the oracle's model of x2 errs by ~3e-6
-at these shapes).  x1 (plain bf16) is held to the oracle's x1 model within
-1e-4 (the two differ only where an FP32 entry sits on a bf16 rounding tie)
-and reported against the exact product.  Solves in x2 with FP32-entry FP64
+x2 (hi/lo split of both operands, three MFMA products) keeps about 16
+significant bits of each operand, so each product carries a relative error up
+to ~2 * 2^-17 = 1.5e-5; the oracle's own model of the x2 arithmetic errs by
+0.5-1.3e-5 (per-column relative 2-norm) on these shapes.  x2 is therefore held
+(a) to the oracle's x2 model within 2e-6, which pins the implementation, and
+(b) to the exact FP64 product within 3e-5, the bound of the form.  x1 (plain
+bf16) is held to the oracle's x1 model within 1e-4 (the two differ only where
+an FP32 entry sits on a bf16 rounding tie) and reported against the exact
+product.  Solves in x2 with FP32-entry FP64
 residual refinement must reach the same 1e-6 recomputed residual as FP32.
 """
 
@@ -31,8 +35,22 @@ def test_x2_matvec_vs_oracle(mf, family, t):
     w = inputs.random_problem(31 + t, 1537, 3, family, ard=True, noise=0.01)
     V = inputs.gaussian_rhs(t, w.n, t)
     out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
-    ref = gp.ky_matvec(okern(w), w.X, V)
-    assert col_rel_err(out, ref).max() <= 1e-5
+    k = okern(w)
+    ref = gp.ky_matvec(k, w.X, V)
+    model = x2_model(k, w.X, V)
+    assert col_rel_err(out, model).max() <= 2e-6
+    assert col_rel_err(out, ref).max() <= 3e-5
+
+
+def x2_model(k, X, V, rows=None, block=512):
+    """Oracle model of the x2 product with the noise term, optionally on sampled rows."""
+    rows = np.arange(X.shape[0]) if rows is None else rows
+    out = np.empty((len(rows), V.shape[1]))
+    for b in range(0, len(rows), block):
+        rb = rows[b:b + block]
+        K32 = gp.kernel_matrix(k, X[rb], X).astype(np.float32)
+        out[b:b + block] = bf16.tile_product_x2(K32, V) + k.noise * V[rb].astype(np.float64)
+    return out
 
 
 @pytest.mark.parametrize("d", [1, 2, 4, 6, 8])
@@ -41,8 +59,9 @@ def test_x2_dims_and_ragged(mf, d):
     w = inputs.random_problem(3 + d, 1000, d, "rbf", ard=False, noise=0.01)
     V = inputs.gaussian_rhs(d, w.n, 3)
     out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
-    ref = gp.ky_matvec(okern(w), w.X, V)
-    assert col_rel_err(out, ref).max() <= 1e-5
+    k = okern(w)
+    assert col_rel_err(out, x2_model(k, w.X, V)).max() <= 2e-6
+    assert col_rel_err(out, gp.ky_matvec(k, w.X, V)).max() <= 3e-5
 
 
 def test_x1_matvec_vs_bf16_model(mf):
@@ -64,9 +83,10 @@ def test_x2_full_rbf100k_sampled_rows(mf):
     w = inputs.rbf100k()
     V = np.concatenate([w.y[:, None], w.Z], axis=1)
     out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2"))
-    rows = np.random.default_rng(7).choice(w.n, size=2048, replace=False)
-    ref = gp.ky_matvec_rows(okern(w), w.X, V, rows)
-    assert col_rel_err(out[rows], ref).max() <= 1e-5
+    rows = np.random.default_rng(7).choice(w.n, size=1024, replace=False)
+    k = okern(w)
+    assert col_rel_err(out[rows], x2_model(k, w.X, V, rows=rows, block=128)).max() <= 2e-6
+    assert col_rel_err(out[rows], gp.ky_matvec_rows(k, w.X, V, rows)).max() <= 3e-5
 
 
 def test_x2_cg_equal_accuracy(mf):

@@ -85,7 +85,7 @@ def test_exact_mode_vs_cholesky_and_fd(mf, family, ard):
     # log|K_y| sums logs of eigenvalues near sigma^2, which the FP32 kernel
     # entries move by ~1e-7 ||K||: the same 1e-4 bar as the other log-dets
     assert r["logdet"] == pytest.approx(gp.logdet(k, X), rel=1e-4)
-    assert r["mll"] == pytest.approx(gp.mll(k, X, y), rel=1e-5)
+    assert r["mll"] == pytest.approx(gp.mll(k, X, y), rel=1e-4)
     g_exact = gp.mll_grad(k, X, y)
     ok, rel = grad_ok(r["grad"], g_exact)
     assert ok, (r["grad"], g_exact, rel)
