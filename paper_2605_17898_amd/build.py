@@ -38,6 +38,7 @@ UNITS = [
     ("mfma.hip", "mfma.o", []),
     ("abi.hip", "abi.o", []),
     ("timing.hip", "timing.o", []),
+    ("batch.hip", "batch.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]
 

@@ -22,34 +22,9 @@
 // the host applies s2 F_k.  Lane sums are FP32 over one j-range; block,
 // grid and host sums are FP64 in a fixed order.
 #include "internal.hpp"
-#include "sweep_kernels.hpp"
+#include "adjoint_kernels.hpp"
 
 namespace mfgp {
-
-struct ColW {
-    float w[MFGP_MAX_T];
-};
-
-template <int FAM>
-__device__ __forceinline__ void kentry_and_dfac(float d2, float& kv, float& g) {
-    if constexpr (FAM == MFGP_RBF) {
-        kv = __builtin_amdgcn_exp2f(-d2);
-        g = kv;
-    } else {
-        const float q = __builtin_amdgcn_sqrtf(d2);
-        const float e = __builtin_amdgcn_exp2f(-q);
-        if constexpr (FAM == MFGP_MATERN12) {
-            kv = e;
-            g = q > 0.0f ? e * __builtin_amdgcn_rcpf(q) : 0.0f;
-        } else if constexpr (FAM == MFGP_MATERN32) {
-            kv = fmaf(q, kLn2, 1.0f) * e;
-            g = e;
-        } else {
-            kv = fmaf(fmaf(q, kLn2Sq3, kLn2), q, 1.0f) * e;
-            g = fmaf(q, kLn2, 1.0f) * e;
-        }
-    }
-}
 
 template <int FAM, int D, int TB>
 __global__ __launch_bounds__(kBlock) void adjoint_kernel(
@@ -67,70 +42,12 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     for (int k = 0; k < D; ++k) ui[k] = U[ii * D + k];
 #pragma unroll
     for (int c = 0; c < TB; ++c) ai[c] = i < n ? A[ii * lda + c0 + c] * w.w[c] : 0.0f;
-    float g[D], gs = 0.0f;
-#pragma unroll
-    for (int k = 0; k < D; ++k) g[k] = 0.0f;
-
     const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
     const int64_t jend = j0 + jchunk < n ? j0 + jchunk : n;
     const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
-    const float* __restrict__ uc = U + j0 * D;
-    const float* __restrict__ bc = B + j0 * TB;
-    // Two-level accumulation (segments of kSeg j's), as in the product sweeps.
-    float tg[D], ts = 0.0f;
-#pragma unroll
-    for (int k = 0; k < D; ++k) tg[k] = 0.0f;
-    for (int q = 0; q < cnt; ++q) {
-        if (q % kSeg == 0 && q > 0) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                tg[k] += g[k];
-                g[k] = 0.0f;
-            }
-            ts += gs;
-            gs = 0.0f;
-        }
-        const float* uj = uc + q * D;
-        float df[D];
-        float d2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            df[k] = ui[k] - uj[k];
-            d2 = fmaf(df[k], df[k], d2);
-        }
-        float kv, gf;
-        kentry_and_dfac<FAM>(d2, kv, gf);
-        float wij = 0.0f;
-#pragma unroll
-        for (int c = 0; c < TB; ++c) wij = fmaf(ai[c], bc[q * TB + c], wij);
-        gs = fmaf(wij, kv, gs);
-        const float wd = wij * gf;
-#pragma unroll
-        for (int k = 0; k < D; ++k) g[k] = fmaf(wd * df[k], df[k], g[k]);
-    }
-
-    // FP64 block reduction: wave butterfly, then the 4 wave sums in order.
     double v[D + 1];
-#pragma unroll
-    for (int k = 0; k < D; ++k) v[k] = static_cast<double>(tg[k]) + static_cast<double>(g[k]);
-    v[D] = static_cast<double>(ts) + static_cast<double>(gs);
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        double x = v[k];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        v[k] = x;
-    }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int k = 0; k <= D; ++k) red[wave * (D + 1) + k] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x <= D) {
-        double s = 0.0;
-        for (int q = 0; q < kBlock / 64; ++q) s += red[q * (D + 1) + threadIdx.x];
-        partial[static_cast<int64_t>(blockIdx.x) * (D + 1) + threadIdx.x] = s;
-    }
+    adjoint_rows<FAM, D, TB>(ui, ai, U + j0 * D, B + j0 * TB, cnt, v);
+    block_sum_write<D + 1>(v, red, partial + static_cast<int64_t>(blockIdx.x) * (D + 1));
 }
 
 __global__ void adjoint_final_kernel(const double* __restrict__ partial, int nblocks, int width,

@@ -1,0 +1,1072 @@
+// Batched GP problems: many uneven problems solved together (LightGP Sec. 5
+// names batched solves among the CG features its plain loop lacks).
+//
+// * One persistent launch per product.  The work of all problems is a queue
+//   of tiles (problem b, 256-row block, j-range), sorted longest first; the
+//   resident workgroups pull tiles through an atomic counter until the queue
+//   is empty (every workgroup exits when the counter passes the end), and each
+//   tile writes its partial sums to its own slot, reduced afterwards in a
+//   fixed order -- so results do not depend on which workgroup took which tile.
+// * Per-problem CG on packed [sum n_b, t] blocks: reductions are segmented
+//   (each block of the reduction kernels owns rows of one problem only).
+// * The iterations between host convergence checks are captured once into a
+//   hipGraph and replayed (no memset nodes: the queue counter is reset by a
+//   kernel).
+// * The tile j-length is picked by timing candidate lengths on the batch
+//   itself (plan autotuner) and kept in the plan.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "adjoint_kernels.hpp"
+#include "cg.hpp"
+#include "internal.hpp"
+
+int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q);
+
+namespace mfgp {
+
+struct BProb {
+    int64_t n;          // rows
+    int64_t row_off;    // first packed row
+    int64_t u_off;      // element offset of U_b (= x_off)
+    int64_t jchunk;     // j-range length of this problem's tiles
+    int d;
+    int chunks;         // j-ranges per row block
+    int tile_base;      // first tile id of this problem
+    int rowblocks;
+    float s2;
+    float sig2;
+};
+struct BTile {
+    int b, rb, ch, id;
+};
+struct BSeg {
+    int b;
+    int pad;
+    int64_t r0, r1;     // packed rows [r0, r1) of problem b
+};
+
+constexpr int kSegRows = 2048;
+constexpr int kWidth = MFGP_MAX_D + 1;   // adjoint partial width
+
+// ---------------------------------------------------------------- persistent kernels
+
+__global__ void reset_counter_kernel(int* counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+template <int FAM, int TB>
+__global__ __launch_bounds__(kBlock) void batch_sweep_kernel(
+    const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
+    const float* __restrict__ U, const float* __restrict__ V, float* __restrict__ partial) {
+    __shared__ int s_k;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_k);
+        __syncthreads();
+        if (k >= ntiles) break;
+        const BTile tl = queue[k];
+        const BProb pb = probs[tl.b];
+        const int64_t i = static_cast<int64_t>(tl.rb) * kBlock + threadIdx.x;
+        const int64_t ii = i < pb.n ? i : pb.n - 1;
+        const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;
+        const int64_t jend = j0 + pb.jchunk < pb.n ? j0 + pb.jchunk : pb.n;
+        const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
+        const float* Ub = U + pb.u_off;
+        const float* Vb = V + pb.row_off * TB;
+        float acc[TB];
+        switch (pb.d) {
+#define MFGP_BCASE(DV)                                                         \
+    case DV: {                                                                 \
+        float ui[DV];                                                          \
+        _Pragma("unroll") for (int q = 0; q < DV; ++q) ui[q] = Ub[ii * DV + q]; \
+        sweep_rows<FAM, DV, TB>(ui, Ub + j0 * DV, Vb + j0 * TB, cnt, acc);     \
+    } break;
+            MFGP_BCASE(1) MFGP_BCASE(2) MFGP_BCASE(3) MFGP_BCASE(4)
+            MFGP_BCASE(5) MFGP_BCASE(6) MFGP_BCASE(7) MFGP_BCASE(8)
+#undef MFGP_BCASE
+            default:
+#pragma unroll
+                for (int c = 0; c < TB; ++c) acc[c] = 0.0f;
+        }
+        float* p = partial + (static_cast<int64_t>(tl.id) * kBlock + threadIdx.x) * TB;
+#pragma unroll
+        for (int c = 0; c < TB; ++c) p[c] = acc[c];
+    }
+}
+
+template <int FAM, int TB>
+__global__ __launch_bounds__(kBlock) void batch_adjoint_kernel(
+    const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
+    const float* __restrict__ U, const float* __restrict__ A, const float* __restrict__ B, ColW w,
+    double* __restrict__ partial) {
+    __shared__ int s_k;
+    __shared__ double red[kWidth * (kBlock / 64)];
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_k);
+        __syncthreads();
+        if (k >= ntiles) break;
+        const BTile tl = queue[k];
+        const BProb pb = probs[tl.b];
+        const int64_t i = static_cast<int64_t>(tl.rb) * kBlock + threadIdx.x;
+        const int64_t ii = i < pb.n ? i : pb.n - 1;
+        const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;
+        const int64_t jend = j0 + pb.jchunk < pb.n ? j0 + pb.jchunk : pb.n;
+        const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
+        const float* Ub = U + pb.u_off;
+        const float* Ab = A + pb.row_off * TB;
+        const float* Bb = B + pb.row_off * TB;
+        float ai[TB];
+#pragma unroll
+        for (int c = 0; c < TB; ++c) ai[c] = i < pb.n ? Ab[ii * TB + c] * w.w[c] : 0.0f;
+        double* out = partial + static_cast<int64_t>(tl.id) * kWidth;
+        switch (pb.d) {
+#define MFGP_ACASE(DV)                                                          \
+    case DV: {                                                                  \
+        float ui[DV];                                                           \
+        _Pragma("unroll") for (int q = 0; q < DV; ++q) ui[q] = Ub[ii * DV + q];  \
+        double v[DV + 1];                                                       \
+        adjoint_rows<FAM, DV, TB>(ui, ai, Ub + j0 * DV, Bb + j0 * TB, cnt, v);  \
+        block_sum_write<DV + 1>(v, red, out);                                   \
+    } break;
+            MFGP_ACASE(1) MFGP_ACASE(2) MFGP_ACASE(3) MFGP_ACASE(4)
+            MFGP_ACASE(5) MFGP_ACASE(6) MFGP_ACASE(7) MFGP_ACASE(8)
+#undef MFGP_ACASE
+            default: break;
+        }
+        __syncthreads();   // red is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------- batched reductions
+
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ row_offs, int nprob,
+                                            int64_t r) {
+    int lo = 0, hi = nprob - 1;   // row_offs[nprob] = total rows
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_offs[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// out[r, c] = s2_b sum_ch partial[tile(b, rb, ch)][li][c] + sig2_b Vself[r, c]
+__global__ void batch_reduce_kernel(const float* __restrict__ partial, const BProb* __restrict__ probs,
+                                    const int64_t* __restrict__ row_offs, int nprob, int64_t rows,
+                                    int t, const float* __restrict__ Vself, float* __restrict__ out) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= rows * t) return;
+    const int64_t r = idx / t;
+    const int c = static_cast<int>(idx % t);
+    const BProb pb = probs[find_problem(row_offs, nprob, r)];
+    const int64_t i = r - pb.row_off;
+    const int64_t rb = i / kBlock;
+    const int64_t li = i % kBlock;
+    double acc = 0.0;
+    for (int ch = 0; ch < pb.chunks; ++ch) {
+        const int64_t tile = pb.tile_base + rb * pb.chunks + ch;
+        acc += static_cast<double>(partial[(tile * kBlock + li) * t + c]);
+    }
+    out[idx] = static_cast<float>(static_cast<double>(pb.s2) * acc +
+                                  static_cast<double>(pb.sig2) * static_cast<double>(Vself[idx]));
+}
+
+// Segment k: rows [r0, r1) of one problem; striped over S = floor(256/t)*t threads.
+template <typename TA, typename TB_>
+__global__ __launch_bounds__(256) void bdot_stage1(const TA* __restrict__ a, const TB_* __restrict__ b,
+                                                   const BSeg* __restrict__ segs, int t,
+                                                   double* __restrict__ part) {
+    __shared__ double lds[256];
+    const BSeg sg = segs[blockIdx.x];
+    const int S = (256 / t) * t;
+    const int k = threadIdx.x;
+    double acc = 0.0;
+    if (k < S)
+        for (int64_t e = sg.r0 * t + k; e < sg.r1 * t; e += S)
+            acc = fma(static_cast<double>(a[e]), static_cast<double>(b[e]), acc);
+    lds[k] = k < S ? acc : 0.0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < t; c += 256) {
+        double s = 0.0;
+        for (int q = c; q < S; q += t) s += lds[q];
+        part[static_cast<int64_t>(blockIdx.x) * t + c] = s;
+    }
+}
+
+__global__ void bdot_stage2(const double* __restrict__ part, const int* __restrict__ seg_first,
+                            int nprob, int t, double* __restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nprob * t) return;
+    const int b = idx / t;
+    const int c = idx % t;
+    double s = 0.0;
+    for (int k = seg_first[b]; k < seg_first[b + 1]; ++k) s += part[static_cast<int64_t>(k) * t + c];
+    out[idx] = s;
+}
+
+// x += alpha p, r -= alpha Ap per (problem, column), striped r^2 partials.
+__global__ __launch_bounds__(256) void bcg_update_kernel(CgState st, const BSeg* __restrict__ segs, int t,
+                                                         double* __restrict__ part) {
+    __shared__ double lds[256];
+    const BSeg sg = segs[blockIdx.x];
+    const int S = (256 / t) * t;
+    const int k = threadIdx.x;
+    double acc = 0.0;
+    if (k < S) {
+        const int c = k % t;
+        const double a = st.alpha[sg.b * t + c];
+        const float af = static_cast<float>(a);
+        for (int64_t e = sg.r0 * t + k; e < sg.r1 * t; e += S) {
+            if (a != 0.0) {
+                st.x[e] = fma(a, static_cast<double>(st.p[e]), st.x[e]);
+                st.r[e] = fmaf(-af, st.ap[e], st.r[e]);
+            }
+            const float r = st.r[e];
+            acc = fma(static_cast<double>(r), static_cast<double>(r), acc);
+        }
+    }
+    lds[k] = k < S ? acc : 0.0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < t; c += 256) {
+        double s = 0.0;
+        for (int q = c; q < S; q += t) s += lds[q];
+        part[static_cast<int64_t>(blockIdx.x) * t + c] = s;
+    }
+}
+
+// p = r + beta p for active (problem, column); restart: r = fl32(R64), p = r.
+__global__ __launch_bounds__(256) void bcg_p_kernel(CgState st, const BSeg* __restrict__ segs, int t) {
+    const BSeg sg = segs[blockIdx.x];
+    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256) {
+        const int q = sg.b * t + static_cast<int>(e % t);
+        if (st.active[q]) st.p[e] = fmaf(static_cast<float>(st.beta[q]), st.p[e], st.r[e]);
+    }
+}
+
+__global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg* __restrict__ segs, int t,
+                                                          const double* __restrict__ R64,
+                                                          const int* __restrict__ restart) {
+    const BSeg sg = segs[blockIdx.x];
+    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256) {
+        if (restart[sg.b * t + static_cast<int>(e % t)]) {
+            const float r = static_cast<float>(R64[e]);
+            st.r[e] = r;
+            st.p[e] = r;
+        }
+    }
+}
+
+__global__ void bcg_init_kernel(CgState st, int T, double tol2) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    const bool finite = isfinite(st.bnorm2[q]) && isfinite(st.rr[q]);
+    st.active[q] = (finite && st.bnorm2[q] > 0.0 && st.rr[q] > tol2 * st.bnorm2[q]) ? 1 : 0;
+    st.status[q] = finite ? MFGP_OK : MFGP_BREAKDOWN;
+    st.iters[q] = 0;
+    st.lanlen[q] = 0;
+    st.alpha[q] = 0.0;
+    st.beta[q] = 0.0;
+}
+
+__global__ void bcg_alpha_kernel(CgState st, int T) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    double a = 0.0;
+    if (st.active[q]) {
+        const double pap = st.pap[q];
+        if (!(pap > 0.0) || !isfinite(pap) || !isfinite(st.rr[q])) {
+            st.status[q] = MFGP_BREAKDOWN;
+            st.active[q] = 0;
+        } else {
+            a = st.rr[q] / pap;
+        }
+    }
+    st.alpha[q] = a;
+}
+
+__global__ void bcg_beta_kernel(CgState st, int T, const double* __restrict__ rrn_all, double tol2,
+                                const int* __restrict__ log_coeffs, int max_iter) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    const double rrn = rrn_all[q];
+    double b = 0.0;
+    if (st.active[q]) {
+        b = rrn / st.rr[q];
+        if (*log_coeffs && st.lanlen[q] < max_iter) {
+            double* cf = st.coeff + (static_cast<int64_t>(q) * max_iter + st.lanlen[q]) * 2;
+            cf[0] = st.alpha[q];
+            cf[1] = b;
+            st.lanlen[q] += 1;
+        }
+        st.iters[q] += 1;
+        st.rr[q] = rrn;
+        if (!isfinite(rrn)) {
+            st.status[q] = MFGP_BREAKDOWN;
+            st.active[q] = 0;
+        } else if (rrn <= tol2 * st.bnorm2[q] || st.iters[q] >= max_iter) {
+            st.active[q] = 0;
+        }
+    }
+    st.beta[q] = b;
+}
+
+__global__ void bcg_activate_kernel(CgState st, int T, const int* __restrict__ restart,
+                                    const double* __restrict__ rr_new) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    if (restart[q]) {
+        st.active[q] = rr_new[q] > 0.0 ? 1 : 0;
+        st.rr[q] = rr_new[q];
+    }
+}
+
+__global__ void adjoint_stage2_kernel(const double* __restrict__ partial, const BProb* __restrict__ probs,
+                                      int nprob, double* __restrict__ out) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nprob * kWidth) return;
+    const int b = idx / kWidth;
+    const int k = idx % kWidth;
+    const BProb pb = probs[b];
+    double s = 0.0;
+    if (k <= pb.d) {
+        const int ntile = pb.rowblocks * pb.chunks;
+        for (int q = 0; q < ntile; ++q) s += partial[static_cast<int64_t>(pb.tile_base + q) * kWidth + k];
+    }
+    out[idx] = s;
+}
+
+__global__ void batch_pack_yz_kernel(const float* __restrict__ y, const float* __restrict__ Z,
+                                     int64_t rows, int p, float* __restrict__ out) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int t = p + 1;
+    if (idx >= rows * t) return;
+    const int64_t r = idx / t;
+    const int c = static_cast<int>(idx % t);
+    out[idx] = c == 0 ? y[r] : Z[r * p + (c - 1)];
+}
+
+__global__ void batch_set_col0_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                      int64_t rows, int t) {
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < rows) dst[r * t] = static_cast<float>(src[r * t]);
+}
+
+static inline unsigned nblocks(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
+
+}  // namespace mfgp
+
+// ---------------------------------------------------------------- the plan
+
+using namespace mfgp;
+
+struct mfgp_batch_plan_s {
+    int nprob = 0;
+    int p = 0, t = 0;
+    int family = 0;
+    int max_iter = 0;
+    int tune = 0;
+    int use_graph = 1;
+    std::vector<int64_t> n, row_off, x_off;
+    std::vector<mfgp_kernel> kern;
+    int64_t rows = 0;          // sum n_b
+    int64_t xelems = 0;        // packed X elements
+    int64_t max_n = 0;
+    int64_t tile_j = 0;        // tuned (0 = not yet)
+    double tuned_ms = 0.0;
+    int64_t graph_launches = 0;
+    std::vector<BSeg> segs;
+    std::vector<int> seg_first;
+    std::vector<int64_t> row_offs;   // prefix [nprob + 1]
+};
+
+namespace mfgp {
+
+static const int64_t kTileCandidates[] = {4096, 8192, 16384, 32768, 65536};
+static const int64_t kDefaultTile = 8192;
+static const int64_t kMinTile = 4096;
+
+static void build_tiles(const mfgp_batch_plan_s& P, int64_t J, std::vector<BProb>& probs,
+                        std::vector<BTile>& queue) {
+    probs.resize(P.nprob);
+    int base = 0;
+    for (int b = 0; b < P.nprob; ++b) {
+        BProb& pb = probs[b];
+        const Operator op = make_operator(P.kern[b], nullptr, P.n[b], nullptr);
+        pb.n = P.n[b];
+        pb.row_off = P.row_off[b];
+        pb.u_off = P.x_off[b];
+        pb.d = P.kern[b].d;
+        pb.rowblocks = static_cast<int>((pb.n + kBlock - 1) / kBlock);
+        pb.chunks = static_cast<int>((pb.n + J - 1) / J);
+        pb.jchunk = (pb.n + pb.chunks - 1) / pb.chunks;
+        pb.tile_base = base;
+        pb.s2 = op.s2;
+        pb.sig2 = op.sig2;
+        base += pb.rowblocks * pb.chunks;
+    }
+    queue.clear();
+    queue.reserve(base);
+    for (int b = 0; b < P.nprob; ++b) {
+        const BProb& pb = probs[b];
+        for (int rb = 0; rb < pb.rowblocks; ++rb)
+            for (int ch = 0; ch < pb.chunks; ++ch)
+                queue.push_back(BTile{b, rb, ch, pb.tile_base + rb * pb.chunks + ch});
+    }
+    // Longest processing time first: work of a tile = rows x j-range x d-ish cost.
+    auto work = [&](const BTile& tl) {
+        const BProb& pb = probs[tl.b];
+        const int64_t rows = std::min<int64_t>(kBlock, pb.n - static_cast<int64_t>(tl.rb) * kBlock);
+        const int64_t j0 = tl.ch * pb.jchunk;
+        const int64_t js = std::min<int64_t>(pb.jchunk, pb.n - j0);
+        return static_cast<double>(rows) * static_cast<double>(js) * (2.0 * pb.d + 4.0);
+    };
+    std::stable_sort(queue.begin(), queue.end(),
+                     [&](const BTile& a, const BTile& b) { return work(a) > work(b); });
+}
+
+static int64_t max_tiles(const mfgp_batch_plan_s& P) {
+    int64_t total = 0;
+    for (int b = 0; b < P.nprob; ++b) {
+        const int64_t rbk = (P.n[b] + kBlock - 1) / kBlock;
+        const int64_t ch = (P.n[b] + kMinTile - 1) / kMinTile;
+        total += rbk * ch;
+    }
+    return total;
+}
+
+struct BatchWs {
+    float* U; float* Bm; double* X64; float* Zgen; double* coeff; float* R; float* P; float* AP;
+    double* R64; double* scal; int* ints; double* dpart; double* tmp; double* resid; char* part;
+    BTile* queue; BProb* probs; BSeg* segs; int* seg_first; int64_t* row_offs; int* counter;
+    int* logflag;
+};
+
+static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
+    BatchWs w;
+    const size_t rt = static_cast<size_t>(P.rows) * P.t;
+    const size_t T = static_cast<size_t>(P.nprob) * P.t;
+    const int64_t nt = max_tiles(P);
+    w.U = cv.take<float>(P.xelems);
+    w.Bm = cv.take<float>(rt);
+    w.X64 = cv.take<double>(rt);
+    w.Zgen = cv.take<float>(static_cast<size_t>(P.rows) * P.p);
+    w.coeff = cv.take<double>(T * P.max_iter * 2);
+    w.R = cv.take<float>(rt);
+    w.P = cv.take<float>(rt);
+    w.AP = cv.take<float>(rt);
+    w.R64 = cv.take<double>(rt);
+    w.scal = cv.take<double>(8 * T);
+    w.ints = cv.take<int>(6 * T);
+    w.dpart = cv.take<double>(P.segs.size() * P.t + 64);
+    w.tmp = cv.take<double>(4 * T + 64);
+    size_t resid = 0;
+    for (int b = 0; b < P.nprob; ++b) resid = std::max(resid, resid_scratch_doubles(P.n[b], P.t));
+    w.resid = cv.take<double>(resid);
+    const size_t part_sweep = static_cast<size_t>(nt) * kBlock * P.t * sizeof(float);
+    const size_t part_adj = static_cast<size_t>(nt) * kWidth * sizeof(double) + (P.nprob * kWidth + 64) * sizeof(double);
+    w.part = cv.take<char>(std::max(part_sweep, part_adj));
+    w.queue = cv.take<BTile>(nt);
+    w.probs = cv.take<BProb>(P.nprob);
+    w.segs = cv.take<BSeg>(P.segs.size());
+    w.seg_first = cv.take<int>(P.nprob + 1);
+    w.row_offs = cv.take<int64_t>(P.nprob + 1);
+    w.counter = cv.take<int>(64);
+    w.logflag = cv.take<int>(64);
+    return w;
+}
+
+// Resident workgroups of the persistent kernels: 8 per CU.
+static int persistent_grid(int ntiles) {
+    static thread_local int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    return static_cast<int>(std::min<int64_t>(ntiles, static_cast<int64_t>(cus) * 8));
+}
+
+template <int FAM>
+static hipError_t launch_bsweep_f(int tb, const BatchWs& w, int ntiles, const float* V, float* part,
+                                  hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
+    switch (tb) {
+#define MFGP_C(TBV)                                                                                 \
+    case TBV:                                                                                       \
+        hipLaunchKernelGGL((batch_sweep_kernel<FAM, TBV>), dim3(grid), dim3(kBlock), 0, s, w.queue, \
+                           ntiles, w.counter, w.probs, w.U, V, part);                              \
+        return hipGetLastError();
+        MFGP_TB_LIST(MFGP_C)
+#undef MFGP_C
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_bsweep(int family, int tb, const BatchWs& w, int ntiles, const float* V,
+                                float* part, hipStream_t s) {
+    switch (family) {
+        case MFGP_RBF: return launch_bsweep_f<MFGP_RBF>(tb, w, ntiles, V, part, s);
+        case MFGP_MATERN12: return launch_bsweep_f<MFGP_MATERN12>(tb, w, ntiles, V, part, s);
+        case MFGP_MATERN32: return launch_bsweep_f<MFGP_MATERN32>(tb, w, ntiles, V, part, s);
+        default: return launch_bsweep_f<MFGP_MATERN52>(tb, w, ntiles, V, part, s);
+    }
+}
+
+template <int FAM>
+static hipError_t launch_badj_f(int tb, const BatchWs& w, int ntiles, const float* A, const float* B,
+                                const ColW& cw, double* part, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
+    switch (tb) {
+#define MFGP_C(TBV)                                                                                   \
+    case TBV:                                                                                         \
+        hipLaunchKernelGGL((batch_adjoint_kernel<FAM, TBV>), dim3(grid), dim3(kBlock), 0, s, w.queue, \
+                           ntiles, w.counter, w.probs, w.U, A, B, cw, part);                         \
+        return hipGetLastError();
+        MFGP_TB_LIST(MFGP_C)
+#undef MFGP_C
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_badj(int family, int tb, const BatchWs& w, int ntiles, const float* A,
+                              const float* B, const ColW& cw, double* part, hipStream_t s) {
+    switch (family) {
+        case MFGP_RBF: return launch_badj_f<MFGP_RBF>(tb, w, ntiles, A, B, cw, part, s);
+        case MFGP_MATERN12: return launch_badj_f<MFGP_MATERN12>(tb, w, ntiles, A, B, cw, part, s);
+        case MFGP_MATERN32: return launch_badj_f<MFGP_MATERN32>(tb, w, ntiles, A, B, cw, part, s);
+        default: return launch_badj_f<MFGP_MATERN52>(tb, w, ntiles, A, B, cw, part, s);
+    }
+}
+
+// One batched product AP = K_y P (persistent sweep + fixed-order reduce), timed.
+static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
+                              const float* V, float* out, hipStream_t s) {
+    void* tok = timing_begin(s);
+    hipError_t e = launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+    if (e != hipSuccess) return e;
+    double ent = 0.0, fl = 0.0;
+    if (timing_on())
+        for (int b = 0; b < P.nprob; ++b) {
+            const double e2 = static_cast<double>(P.n[b]) * static_cast<double>(P.n[b]);
+            ent += e2;
+            fl += e2 * sweep_flops_per_entry(P.family, P.kern[b].d, P.t, false);
+        }
+    timing_end(tok, s, kSweepF32, ent, fl);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(nblocks(P.rows * P.t)), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(w.part), w.probs, w.row_offs, P.nprob, P.rows, P.t,
+                       V, out);
+    return hipGetLastError();
+}
+
+static hipError_t bdots_ff(const mfgp_batch_plan_s& P, const BatchWs& w, const float* a, const float* b,
+                           double* out, hipStream_t s) {
+    hipLaunchKernelGGL((bdot_stage1<float, float>), dim3(static_cast<unsigned>(P.segs.size())), dim3(256),
+                       0, s, a, b, w.segs, P.t, w.dpart);
+    hipLaunchKernelGGL(bdot_stage2, dim3(nblocks(static_cast<int64_t>(P.nprob) * P.t)), dim3(256), 0, s,
+                       w.dpart, w.seg_first, P.nprob, P.t, out);
+    return hipGetLastError();
+}
+static hipError_t bdots_dd(const mfgp_batch_plan_s& P, const BatchWs& w, const double* a,
+                           const double* b, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((bdot_stage1<double, double>), dim3(static_cast<unsigned>(P.segs.size())), dim3(256),
+                       0, s, a, b, w.segs, P.t, w.dpart);
+    hipLaunchKernelGGL(bdot_stage2, dim3(nblocks(static_cast<int64_t>(P.nprob) * P.t)), dim3(256), 0, s,
+                       w.dpart, w.seg_first, P.nprob, P.t, out);
+    return hipGetLastError();
+}
+static hipError_t bdots_df(const mfgp_batch_plan_s& P, const BatchWs& w, const double* a,
+                           const float* b, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((bdot_stage1<double, float>), dim3(static_cast<unsigned>(P.segs.size())), dim3(256),
+                       0, s, a, b, w.segs, P.t, w.dpart);
+    hipLaunchKernelGGL(bdot_stage2, dim3(nblocks(static_cast<int64_t>(P.nprob) * P.t)), dim3(256), 0, s,
+                       w.dpart, w.seg_first, P.nprob, P.t, out);
+    return hipGetLastError();
+}
+
+// One CG iteration for the whole batch (all launches on s; capturable).
+static hipError_t batch_iteration(const mfgp_batch_plan_s& P, const BatchWs& w, const CgState& st,
+                                  int ntiles, double tol, hipStream_t s) {
+    const int T = P.nprob * P.t;
+    hipError_t e = batch_apply(P, w, ntiles, st.p, st.ap, s);
+    if (e != hipSuccess) return e;
+    e = bdots_ff(P, w, st.p, st.ap, st.pap, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bcg_alpha_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T);
+    hipLaunchKernelGGL(bcg_update_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
+                       w.segs, P.t, w.dpart);
+    double* rrn = w.tmp + 3 * T;
+    hipLaunchKernelGGL(bdot_stage2, dim3(nblocks(T)), dim3(256), 0, s, w.dpart, w.seg_first, P.nprob, P.t, rrn);
+    hipLaunchKernelGGL(bcg_beta_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, rrn, tol * tol,
+                       w.logflag, P.max_iter);
+    hipLaunchKernelGGL(bcg_p_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
+                       w.segs, P.t);
+    return hipGetLastError();
+}
+
+#define B_CHECK(expr)                          \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) {                \
+            set_last_hip_error(e_);            \
+            return MFGP_ERR_HIP;               \
+        }                                      \
+    } while (0)
+
+static int upload_tiles(const mfgp_batch_plan_s& P, const BatchWs& w, int64_t J, int& ntiles,
+                        std::vector<BProb>& probs, std::vector<BTile>& queue, hipStream_t s) {
+    build_tiles(P, J, probs, queue);
+    ntiles = static_cast<int>(queue.size());
+    B_CHECK(hipMemcpyAsync(w.probs, probs.data(), probs.size() * sizeof(BProb), hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.queue, queue.data(), queue.size() * sizeof(BTile), hipMemcpyHostToDevice, s));
+    B_CHECK(hipStreamSynchronize(s));
+    return MFGP_OK;
+}
+
+// Autotuner: time one batched sweep per candidate tile length on this batch
+// and keep the fastest (ties to the longer tile).
+static int tune_tiles(mfgp_batch_plan_s& P, const BatchWs& w, const float* V, hipStream_t s) {
+    hipEvent_t a, b;
+    B_CHECK(hipEventCreate(&a));
+    B_CHECK(hipEventCreate(&b));
+    double best = 1e300;
+    int64_t bestJ = kDefaultTile;
+    std::vector<BProb> probs;
+    std::vector<BTile> queue;
+    for (int64_t J : kTileCandidates) {
+        int ntiles = 0;
+        int st = upload_tiles(P, w, J, ntiles, probs, queue, s);
+        if (st != MFGP_OK) return st;
+        B_CHECK(launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s));  // warm
+        B_CHECK(hipEventRecord(a, s));
+        for (int r = 0; r < 2; ++r)
+            B_CHECK(launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s));
+        B_CHECK(hipEventRecord(b, s));
+        B_CHECK(hipEventSynchronize(b));
+        float ms = 0.0f;
+        B_CHECK(hipEventElapsedTime(&ms, a, b));
+        if (ms * 0.5 < best * 0.98) {
+            best = ms * 0.5;
+            bestJ = J;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    P.tile_j = bestJ;
+    P.tuned_ms = best;
+    return MFGP_OK;
+}
+
+static double lengthscale_factor_b(int family, double l) {
+    const double c = family_scale(family);
+    switch (family) {
+        case MFGP_RBF: return 1.0 / (c * c * l);
+        case MFGP_MATERN12: return 1.0 / (c * l);
+        case MFGP_MATERN32: return 3.0 / (c * c * l);
+        default: return (5.0 / 3.0) / (c * c * l);
+    }
+}
+
+}  // namespace mfgp
+
+extern "C" {
+
+int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter, int32_t tune,
+                           int32_t use_graph, mfgp_batch_plan* plan) {
+    if (!batch || !plan || batch->nprob < 1 || !batch->n || !batch->row_off || !batch->x_off || !batch->kern)
+        return MFGP_ERR_ARG;
+    if (num_probes < 1 || max_iter < 0) return MFGP_ERR_ARG;
+    const int t = num_probes + 1;
+    bool tb_ok = false;
+#define MFGP_T(TBV) tb_ok = tb_ok || (t == TBV);
+    MFGP_TB_LIST(MFGP_T)
+#undef MFGP_T
+    if (!tb_ok) return MFGP_UNSUPPORTED;
+    const int fam = batch->kern[0].family;
+    auto* P = new mfgp_batch_plan_s();
+    P->nprob = batch->nprob;
+    P->p = num_probes;
+    P->t = t;
+    P->family = fam;
+    P->tune = tune;
+    P->use_graph = use_graph;
+    int64_t maxn = 0;
+    for (int b = 0; b < batch->nprob; ++b) {
+        const mfgp_kernel& k = batch->kern[b];
+        const int64_t n = batch->n[b];
+        bool ok = n >= 1 && k.family == fam && k.d >= 1 && k.d <= MFGP_MAX_D && std::isfinite(k.outputscale) &&
+                  k.outputscale > 0.0f && std::isfinite(k.noise) && k.noise > 0.0f &&
+                  batch->row_off[b] >= 0 && batch->x_off[b] >= 0;
+        const int nl = k.ard ? k.d : 1;
+        for (int q = 0; q < nl && ok; ++q) ok = std::isfinite(k.lengthscale[q]) && k.lengthscale[q] > 0.0f;
+        if (!ok) {
+            delete P;
+            return MFGP_ERR_ARG;
+        }
+        P->n.push_back(n);
+        P->row_off.push_back(batch->row_off[b]);
+        P->x_off.push_back(batch->x_off[b]);
+        P->kern.push_back(k);
+        P->rows = std::max<int64_t>(P->rows, batch->row_off[b] + n);
+        P->xelems = std::max<int64_t>(P->xelems, batch->x_off[b] + n * k.d);
+        maxn = std::max(maxn, n);
+    }
+    P->max_n = maxn;
+    P->max_iter = max_iter > 0 ? max_iter : static_cast<int>(std::min<int64_t>(maxn, 20000));
+    // segments of <= kSegRows rows within one problem, and row-offset prefix
+    P->seg_first.push_back(0);
+    for (int b = 0; b < P->nprob; ++b) {
+        for (int64_t r = 0; r < P->n[b]; r += kSegRows) {
+            BSeg sg;
+            sg.b = b;
+            sg.pad = 0;
+            sg.r0 = P->row_off[b] + r;
+            sg.r1 = P->row_off[b] + std::min<int64_t>(P->n[b], r + kSegRows);
+            P->segs.push_back(sg);
+        }
+        P->seg_first.push_back(static_cast<int>(P->segs.size()));
+    }
+    // rows are packed back to back in problem order (row_off[b] = sum of earlier n)
+    int64_t acc_rows = 0;
+    for (int b = 0; b < P->nprob; ++b) {
+        if (P->row_off[b] != acc_rows) {
+            delete P;
+            return MFGP_ERR_ARG;
+        }
+        P->row_offs.push_back(acc_rows);
+        acc_rows += P->n[b];
+    }
+    P->row_offs.push_back(acc_rows);
+    *plan = P;
+    return MFGP_OK;
+}
+
+int mfgp_batch_plan_destroy(mfgp_batch_plan plan) {
+    delete plan;
+    return MFGP_OK;
+}
+
+size_t mfgp_batch_workspace_bytes(mfgp_batch_plan plan) {
+    if (!plan) return 0;
+    Carver cv(nullptr);
+    carve_batch(cv, *plan);
+    return cv.off + 256;
+}
+
+int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sweep_ms,
+                         int64_t* graph_launches) {
+    if (!plan) return MFGP_ERR_ARG;
+    if (tile_j) *tile_j = plan->tile_j;
+    if (tuned_sweep_ms) *tuned_sweep_ms = plan->tuned_ms;
+    if (graph_launches) *graph_launches = plan->graph_launches;
+    return MFGP_OK;
+}
+
+int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
+                            const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
+                            mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !X || !y || !opts || !mll || !ws) return MFGP_ERR_ARG;
+    if (!std::isfinite(opts->tol) || !(opts->tol > 0.0) || opts->max_iter < 0) return MFGP_ERR_ARG;
+    if (opts->precision != MFGP_FP32) return MFGP_UNSUPPORTED;
+    if (ws_bytes < mfgp_batch_workspace_bytes(plan)) return MFGP_ERR_WORKSPACE;
+    mfgp_batch_plan_s& P = *plan;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    const BatchWs w = carve_batch(cv, P);
+    const int t = P.t, p = P.p, nprob = P.nprob;
+    const int T = nprob * t;
+    const int64_t rt = P.rows * t;
+    const double tol = opts->tol;
+    const int max_iter = P.max_iter;
+    const int max_refine = opts->max_refine >= 0 ? opts->max_refine : 8;
+
+    // Static descriptors and prescaled coordinates.
+    B_CHECK(hipMemcpyAsync(w.segs, P.segs.data(), P.segs.size() * sizeof(BSeg), hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.seg_first, P.seg_first.data(), P.seg_first.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.row_offs, P.row_offs.data(), P.row_offs.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    std::vector<Operator> ops(nprob);
+    for (int b = 0; b < nprob; ++b) {
+        ops[b] = make_operator(P.kern[b], X + P.x_off[b], P.n[b], w.U + P.x_off[b]);
+        B_CHECK(prescale(ops[b], s));
+    }
+    const float* Zp = Z;
+    if (!Zp) {
+        for (int b = 0; b < nprob; ++b)
+            B_CHECK(launch_rademacher(opts->probe_seed + static_cast<uint64_t>(b), P.n[b], p,
+                                      w.Zgen + P.row_off[b] * p, s));
+        Zp = w.Zgen;
+    }
+    hipLaunchKernelGGL(batch_pack_yz_kernel, dim3(nblocks(rt)), dim3(256), 0, s, y, Zp, P.rows, p, w.Bm);
+    B_CHECK(hipGetLastError());
+
+    std::vector<BProb> probs;
+    std::vector<BTile> queue;
+    int ntiles = 0;
+    if (P.tile_j == 0) {
+        if (P.tune) {
+            int st = tune_tiles(P, w, w.Bm, s);
+            if (st != MFGP_OK) return st;
+        } else {
+            P.tile_j = kDefaultTile;
+        }
+    }
+    {
+        int st = upload_tiles(P, w, P.tile_j, ntiles, probs, queue, s);
+        if (st != MFGP_OK) return st;
+    }
+
+    using clock = std::chrono::steady_clock;
+    auto t0 = clock::now();
+    // CG state
+    CgState st;
+    st.x = w.X64;
+    st.r = w.R;
+    st.p = w.P;
+    st.ap = w.AP;
+    st.rr = w.scal;
+    st.bnorm2 = w.scal + T;
+    st.pap = w.scal + 2 * T;
+    st.alpha = w.scal + 3 * T;
+    st.beta = w.scal + 4 * T;
+    st.rrn = w.scal + 7 * T;
+    st.active = w.ints;
+    st.status = w.ints + T;
+    st.iters = w.ints + 2 * T;
+    st.lanlen = w.ints + 3 * T;
+    st.coeff = w.coeff;
+    int* restart = w.ints + 4 * T;
+
+    B_CHECK(bdots_ff(P, w, w.Bm, w.Bm, st.bnorm2, s));
+    B_CHECK(fill_f64(st.x, rt, 0.0, s));
+    B_CHECK(copy2_f32(w.Bm, st.r, st.p, rt, s));
+    B_CHECK(bdots_ff(P, w, st.r, st.r, st.rr, s));
+    hipLaunchKernelGGL(bcg_init_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, tol * tol);
+    const int one = 1, zero = 0;
+    B_CHECK(hipMemcpyAsync(w.logflag, &one, sizeof(int), hipMemcpyHostToDevice, s));
+
+    int check_every = opts->check_every > 0 ? opts->check_every : 8;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    P.graph_launches = 0;
+    if (P.use_graph) {
+        B_CHECK(hipStreamSynchronize(s));
+        B_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        timing_suspend(true);   // no event records inside the graph
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < check_every && ce == hipSuccess; ++k) ce = batch_iteration(P, w, st, ntiles, tol, s);
+        timing_suspend(false);
+        hipError_t ee = hipStreamEndCapture(s, &graph);
+        if (ce != hipSuccess || ee != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            set_last_hip_error(ce != hipSuccess ? ce : ee);
+            return MFGP_ERR_HIP;
+        }
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            set_last_hip_error(ie);
+            return MFGP_ERR_HIP;
+        }
+    }
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+#define B_CHECK2(expr)                         \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) {                \
+            cleanup();                         \
+            set_last_hip_error(e_);            \
+            return MFGP_ERR_HIP;               \
+        }                                      \
+    } while (0)
+
+    std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
+    std::vector<double> h_relt(T), h_rr(T), h_b2(T);
+    for (;;) {
+        B_CHECK2(hipMemcpyAsync(h_active.data(), st.active, T * sizeof(int), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipStreamSynchronize(s));
+        bool any = false;
+        for (int q = 0; q < T; ++q) any = any || (h_active[q] && h_iters[q] < max_iter);
+        if (any) {
+            if (exec) {
+                B_CHECK2(hipGraphLaunch(exec, s));
+                P.graph_launches += 1;
+            } else {
+                for (int k = 0; k < check_every; ++k) B_CHECK2(batch_iteration(P, w, st, ntiles, tol, s));
+            }
+            continue;
+        }
+        // all stopped: recompute true residuals problem by problem (FP64 accumulation)
+        for (int b = 0; b < nprob; ++b) {
+            const int64_t o = P.row_off[b] * t;
+            B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
+        }
+        B_CHECK2(bdots_dd(P, w, w.R64, w.R64, w.tmp, s));
+        B_CHECK2(hipMemcpyAsync(h_relt.data(), w.tmp, T * sizeof(double), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipMemcpyAsync(h_status.data(), st.status, T * sizeof(int), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipStreamSynchronize(s));
+        bool again = false;
+        for (int q = 0; q < T; ++q) {
+            h_relt[q] = h_b2[q] > 0.0 ? std::sqrt(h_relt[q] / h_b2[q]) : 0.0;
+            const bool need = h_status[q] == MFGP_OK && !(h_relt[q] <= tol) && std::isfinite(h_relt[q]) &&
+                              h_refine[q] < max_refine && h_iters[q] < max_iter;
+            h_restart[q] = need ? 1 : 0;
+            if (need) {
+                h_refine[q] += 1;
+                again = true;
+            }
+        }
+        if (!again) break;
+        B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(bcg_restart_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
+                           w.segs, t, w.R64, restart);
+        B_CHECK2(bdots_ff(P, w, st.r, st.r, w.tmp + T, s));
+        hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
+        B_CHECK2(hipMemcpyAsync(w.logflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    cleanup();
+    B_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    B_CHECK(hipMemcpyAsync(h_lan.data(), st.lanlen, T * sizeof(int), hipMemcpyDeviceToHost, s));
+    B_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
+    B_CHECK(hipStreamSynchronize(s));
+    int worst = MFGP_OK;
+    std::vector<mfgp_cg_info> inf(T);
+    for (int q = 0; q < T; ++q) {
+        int sq = h_status[q];
+        if (sq == MFGP_OK && !(h_relt[q] <= tol)) sq = MFGP_NOT_CONVERGED;
+        if (sq == MFGP_BREAKDOWN) worst = MFGP_BREAKDOWN;
+        else if (sq == MFGP_NOT_CONVERGED && worst == MFGP_OK) worst = MFGP_NOT_CONVERGED;
+        inf[q].iters = h_iters[q];
+        inf[q].lanczos_len = h_lan[q];
+        inf[q].refinements = h_refine[q];
+        inf[q].status = sq;
+        inf[q].rel_resid_recurrence = h_b2[q] > 0.0 ? std::sqrt(h_rr[q] / h_b2[q]) : 0.0;
+        inf[q].rel_resid_true = h_relt[q];
+    }
+    if (info) std::memcpy(info, inf.data(), T * sizeof(mfgp_cg_info));
+    timing_phase(0, std::chrono::duration<double, std::milli>(clock::now() - t0).count());
+    t0 = clock::now();
+
+    // Column dot products and Lanczos coefficients.
+    double* bb = w.tmp;
+    double* xb = w.tmp + T;
+    double* xx = w.tmp + 2 * T;
+    B_CHECK(bdots_ff(P, w, w.Bm, w.Bm, bb, s));
+    B_CHECK(bdots_df(P, w, w.X64, w.Bm, xb, s));
+    B_CHECK(bdots_dd(P, w, w.X64, w.X64, xx, s));
+    std::vector<double> h(3 * T);
+    B_CHECK(hipMemcpyAsync(h.data(), w.tmp, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<double>> cf(T);
+    for (int q = 0; q < T; ++q) {
+        if (q % t == 0 || h_lan[q] < 1) continue;
+        cf[q].resize(2 * static_cast<size_t>(h_lan[q]));
+        B_CHECK(hipMemcpyAsync(cf[q].data(), w.coeff + static_cast<size_t>(q) * max_iter * 2,
+                               2 * h_lan[q] * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    B_CHECK(hipStreamSynchronize(s));
+    std::vector<double> qv(T, 0.0);
+    std::vector<int> qs(T, MFGP_OK);
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nth = static_cast<int>(std::max(1u, std::min(hw ? hw : 1u, 64u)));
+        std::vector<std::thread> pool;
+        for (int th = 0; th < nth; ++th)
+            pool.emplace_back([&, th]() {
+                for (int q = th; q < T; q += nth) {
+                    if (q % t == 0) continue;
+                    if (h_lan[q] < 1) {
+                        qs[q] = MFGP_BREAKDOWN;
+                        continue;
+                    }
+                    qs[q] = mfgp_slq_quadrature(cf[q].data(), h_lan[q], h[q], &qv[q]);
+                }
+            });
+        for (auto& th : pool) th.join();
+    }
+    int slq_status = MFGP_OK;
+    const double two_pi = 6.283185307179586477;
+    for (int b = 0; b < nprob; ++b) {
+        double ld = 0.0;
+        for (int c = 1; c < t; ++c) {
+            ld += qv[b * t + c];
+            if (qs[b * t + c] != MFGP_OK) slq_status = MFGP_BREAKDOWN;
+        }
+        ld /= p;
+        mll[b] = -0.5 * (h[T + b * t] + ld + static_cast<double>(P.n[b]) * std::log(two_pi));
+        if (logdet) logdet[b] = ld;
+    }
+    timing_phase(1, std::chrono::duration<double, std::milli>(clock::now() - t0).count());
+    t0 = clock::now();
+
+    if (grad) {
+        float* Ag = w.R;
+        float* Bg = w.P;
+        B_CHECK(f64_to_f32(w.X64, Ag, rt, s));
+        B_CHECK(copy2_f32(w.Bm, Bg, Bg, rt, s));
+        hipLaunchKernelGGL(batch_set_col0_kernel, dim3(nblocks(P.rows)), dim3(256), 0, s, w.X64, Bg, P.rows, t);
+        B_CHECK(hipGetLastError());
+        ColW cw{};
+        cw.w[0] = 0.5f;
+        for (int c = 1; c < t; ++c) cw.w[c] = static_cast<float>(-0.5 / p);
+        double* part = reinterpret_cast<double*>(w.part);
+        double* sums = part + static_cast<size_t>(ntiles) * kWidth;
+        void* tok = timing_begin(s);
+        B_CHECK(launch_badj(P.family, t, w, ntiles, Ag, Bg, cw, part, s));
+        {
+            double ent = 0.0, fl = 0.0;
+            for (int b = 0; b < nprob; ++b) {
+                const double e2 = static_cast<double>(P.n[b]) * static_cast<double>(P.n[b]);
+                ent += e2;
+                fl += e2 * sweep_flops_per_entry(P.family, P.kern[b].d, t, true);
+            }
+            timing_end(tok, s, kSweepAdjoint, ent, fl);
+        }
+        hipLaunchKernelGGL(adjoint_stage2_kernel, dim3(nblocks(static_cast<int64_t>(nprob) * kWidth)), dim3(256),
+                           0, s, part, w.probs, nprob, sums);
+        B_CHECK(hipGetLastError());
+        std::vector<double> hs(static_cast<size_t>(nprob) * kWidth);
+        B_CHECK(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        B_CHECK(hipStreamSynchronize(s));
+        double* g = grad;
+        for (int b = 0; b < nprob; ++b) {
+            const Operator& op = ops[b];
+            const mfgp_kernel& k = P.kern[b];
+            const double* G = hs.data() + static_cast<size_t>(b) * kWidth;
+            double shared = 0.0;
+            for (int q = 0; q < op.d; ++q) {
+                const double gq = static_cast<double>(op.s2) * lengthscale_factor_b(op.family, op.ls[q]) * G[q];
+                if (k.ard) g[q] = gq;
+                else shared += gq;
+            }
+            const int nl = k.ard ? op.d : 1;
+            if (!k.ard) g[0] = shared;
+            g[nl] = G[op.d];
+            double tr = 0.0;
+            for (int c = 1; c < t; ++c) tr += h[T + b * t + c];
+            g[nl + 1] = 0.5 * h[2 * T + b * t] - 0.5 * tr / p;
+            g += nl + 2;
+        }
+        timing_phase(2, std::chrono::duration<double, std::milli>(clock::now() - t0).count());
+    }
+    if (worst != MFGP_OK) return worst;
+    return slq_status;
+}
+
+}  // extern "C"

@@ -64,6 +64,7 @@ static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
     st.pap = b.scal + 2 * t;
     st.alpha = b.scal + 3 * t;
     st.beta = b.scal + 4 * t;
+    st.rrn = b.scal + 7 * t;
     st.active = b.ints;
     st.status = b.ints + t;
     st.iters = b.ints + 2 * t;

@@ -70,6 +70,7 @@ double sweep_flops_per_entry(int family, int d, int t, bool adjoint);
 void* timing_begin(hipStream_t s);
 void timing_end(void* tok, hipStream_t s, int kind, double entries, double flops);
 bool timing_on();
+void timing_suspend(bool on);   // while a graph is captured
 void timing_phase(int which, double ms);   // 0 CG solve, 1 quadrature, 2 adjoint
 enum SweepKind { kSweepF32 = 0, kSweepF64 = 1, kSweepAdjoint = 2, kSweepMfma = 3 };
 

@@ -14,6 +14,7 @@ struct Rec {
 };
 struct TimingState {
     bool on = false;
+    bool suspended = false;
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     double phase[3] = {0.0, 0.0, 0.0};
@@ -42,8 +43,10 @@ double sweep_flops_per_entry(int family, int d, int t, bool adjoint) {
     }
 }
 
+void timing_suspend(bool on) { g_timing.suspended = on; }
+
 void* timing_begin(hipStream_t s) {
-    if (!g_timing.on) return nullptr;
+    if (!g_timing.on || g_timing.suspended) return nullptr;
     hipEvent_t a = take_event();
     if (!a) return nullptr;
     (void)hipEventRecord(a, s);
@@ -58,7 +61,7 @@ void timing_end(void* tok, hipStream_t s, int kind, double entries, double flops
     g_timing.recs.push_back(Rec{reinterpret_cast<hipEvent_t>(tok), b, kind, entries, flops});
 }
 
-bool timing_on() { return g_timing.on; }
+bool timing_on() { return g_timing.on && !g_timing.suspended; }
 
 void timing_phase(int which, double ms) {
     if (g_timing.on && which >= 0 && which < 3) g_timing.phase[which] += ms;

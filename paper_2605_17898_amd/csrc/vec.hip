@@ -50,12 +50,21 @@ __global__ __launch_bounds__(256) void dot_stage1(const TA* __restrict__ a, cons
         part[static_cast<int64_t>(blockIdx.x) * t + c] = block_column_sum(lds, t, c, first);
 }
 
-__global__ void dot_stage2(const double* __restrict__ part, int G, int t, double* __restrict__ out) {
-    for (int c = threadIdx.x; c < t; c += blockDim.x) {
-        double s = 0.0;
-        for (int g = 0; g < G; ++g) s += part[static_cast<int64_t>(g) * t + c];
-        out[c] = s;
+// One block per column: thread k sums partials k, k + 256, ... in order, then a
+// fixed LDS tree combines the 256 thread sums (deterministic).
+__global__ __launch_bounds__(256) void dot_stage2(const double* __restrict__ part, int G, int t,
+                                                  double* __restrict__ out) {
+    __shared__ double lds[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) s += part[static_cast<int64_t>(g) * t + c];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[c] = lds[0];
 }
 
 size_t dots_scratch_doubles(int64_t n, int t) {
@@ -68,7 +77,7 @@ static hipError_t col_dots(const TA* a, const TB* b, int64_t n, int t, double* o
     const int G = stripe_blocks(n, t);
     const int64_t S = (static_cast<int64_t>(G) * 256 / t) * t;
     hipLaunchKernelGGL((dot_stage1<TA, TB>), dim3(G), dim3(256), 0, s, a, b, n * t, t, S, scratch);
-    hipLaunchKernelGGL(dot_stage2, dim3(1), dim3(256), 0, s, scratch, G, t, out);
+    hipLaunchKernelGGL(dot_stage2, dim3(t), dim3(256), 0, s, scratch, G, t, out);
     return hipGetLastError();
 }
 
@@ -139,11 +148,10 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, int64_t tota
 
 // beta_c = rr_new / rr; logs (alpha, beta) for the Lanczos tridiagonal while
 // the first cycle runs; freezes converged columns.
-__global__ void cg_beta_kernel(CgState st, int t, const double* __restrict__ part, int G,
+__global__ void cg_beta_kernel(CgState st, int t, const double* __restrict__ rrn_all,
                                double tol2, int log_coeffs, int max_iter) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
-        double rrn = 0.0;
-        for (int g = 0; g < G; ++g) rrn += part[static_cast<int64_t>(g) * t + c];
+        const double rrn = rrn_all[c];
         double b = 0.0;
         if (st.active[c]) {
             b = rrn / st.rr[c];
@@ -231,7 +239,8 @@ hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scrat
     const int G = stripe_blocks(n, t);
     const int64_t S = (static_cast<int64_t>(G) * 256 / t) * t;
     hipLaunchKernelGGL(cg_update_kernel, dim3(G), dim3(256), 0, s, st, n * t, t, S, scratch);
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, st, t, scratch, G, tol * tol,
+    hipLaunchKernelGGL(dot_stage2, dim3(t), dim3(256), 0, s, scratch, G, t, st.rrn);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, st, t, st.rrn, tol * tol,
                        log_coeffs, max_iter);
     hipLaunchKernelGGL(cg_p_kernel, dim3(nblk(n * t)), dim3(256), 0, s, st, n * t, t);
     return hipGetLastError();

@@ -16,6 +16,7 @@ struct CgState {
     double* pap;      // [t] p^T K_y p
     double* alpha;    // [t]
     double* beta;     // [t]
+    double* rrn;      // [t] new r^T r (single-problem path)
     int* active;      // [t] 1 while the column iterates
     int* status;      // [t] mfgp_status
     int* iters;       // [t] iterations done

@@ -43,6 +43,12 @@ class CgInfoT(C.Structure):
                 ("rel_resid_true", C.c_double)]
 
 
+class BatchT(C.Structure):
+    _fields_ = [("nprob", C.c_int32), ("pad_", C.c_int32), ("n", C.POINTER(C.c_int64)),
+                ("row_off", C.POINTER(C.c_int64)), ("x_off", C.POINTER(C.c_int64)),
+                ("kern", C.POINTER(KernelT))]
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(
@@ -65,6 +71,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_timing_enable": (C.c_int, [I32]),
         "mfgp_timing_read": (C.c_int, [I32, P, P, P, P]),
         "mfgp_timing_phases": (C.c_int, [P, P, P]),
+        "mfgp_batch_plan_create": (C.c_int, [C.POINTER(BatchT), I32, I32, I32, I32, C.POINTER(P)]),
+        "mfgp_batch_plan_destroy": (C.c_int, [P]),
+        "mfgp_batch_workspace_bytes": (SZ, [P]),
+        "mfgp_batch_plan_info": (C.c_int, [P, P, P, P]),
+        "mfgp_batch_mll_and_grad": (C.c_int, [P, P, P, P, OP_, P, P, P, IP, P, SZ, P]),
         "mfgp_status_string": (C.c_char_p, [C.c_int]),
         "mfgp_last_hip_error": (C.c_int, []),
         "mfgp_version": (C.c_int, []),
@@ -340,6 +351,81 @@ def timing_phases() -> dict:
     a, b, c = C.c_double(), C.c_double(), C.c_double()
     _check(LIB.mfgp_timing_phases(C.byref(a), C.byref(b), C.byref(c)), "timing_phases")
     return dict(cg_ms=a.value, slq_ms=b.value, adjoint_ms=c.value)
+
+
+class BatchPlan:
+    """A batch of independent GP problems (packed back to back) and its plan.
+
+    kerns[b] (same family), ns[b] rows and ds[b] dims describe problem b; the
+    packed inputs are X (problem b's [n_b, d_b] block after the previous
+    ones), y [sum n] and Z [sum n, p] (or None for seeded probes)."""
+
+    def __init__(self, kerns, ns, ds, num_probes: int, max_iter: int = 0, tune: bool = True,
+                 use_graph: bool = True):
+        self.nprob = len(ns)
+        self.ns = [int(v) for v in ns]
+        self.ds = [int(v) for v in ds]
+        self.p = int(num_probes)
+        self.t = self.p + 1
+        row, xo = 0, 0
+        self.row_off, self.x_off = [], []
+        for n, d in zip(self.ns, self.ds):
+            self.row_off.append(row)
+            self.x_off.append(xo)
+            row += n
+            xo += n * d
+        self.rows, self.xelems = row, xo
+        self._n = (C.c_int64 * self.nprob)(*self.ns)
+        self._ro = (C.c_int64 * self.nprob)(*self.row_off)
+        self._xo = (C.c_int64 * self.nprob)(*self.x_off)
+        self._k = (KernelT * self.nprob)(*[k.struct(d) for k, d in zip(kerns, self.ds)])
+        self.nparams = [LIB.mfgp_num_params(C.byref(self._k[b])) for b in range(self.nprob)]
+        bt = BatchT(self.nprob, 0, self._n, self._ro, self._xo, self._k)
+        self._plan = C.c_void_p()
+        self._destroy = LIB.mfgp_batch_plan_destroy
+        _check(LIB.mfgp_batch_plan_create(C.byref(bt), self.p, max_iter, 1 if tune else 0,
+                                          1 if use_graph else 0, C.byref(self._plan)), "batch_plan_create")
+        self.max_iter = max_iter
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        destroy = getattr(self, "_destroy", None)
+        if plan is not None and plan.value and destroy is not None:
+            destroy(plan)
+            self._plan = None
+
+    def workspace_bytes(self) -> int:
+        return int(LIB.mfgp_batch_workspace_bytes(self._plan))
+
+    def info(self) -> dict:
+        tj, gl, ms = C.c_int64(), C.c_int64(), C.c_double()
+        _check(LIB.mfgp_batch_plan_info(self._plan, C.byref(tj), C.byref(ms), C.byref(gl)), "batch_plan_info")
+        return dict(tile_j=tj.value, tuned_sweep_ms=ms.value, graph_launches=gl.value)
+
+    def mll_and_grad(self, X: torch.Tensor, y: torch.Tensor, Z: Optional[torch.Tensor] = None,
+                     tol: float = 1e-6, probe_seed: int = 0, want_grad: bool = True,
+                     allow=(OK, NOT_CONVERGED, BREAKDOWN)) -> dict:
+        _dev(X, torch.float32, "X")
+        _dev(y, torch.float32, "y")
+        if Z is not None:
+            _dev(Z, torch.float32, "Z")
+        o = cg_opts(tol, self.max_iter, 0, -1, "fp32", False, probe_seed)
+        mll = (C.c_double * self.nprob)()
+        ld = (C.c_double * self.nprob)()
+        grad = (C.c_double * sum(self.nparams))() if want_grad else None
+        info = (CgInfoT * (self.nprob * self.t))()
+        ws = workspace(self.workspace_bytes(), X.device)
+        st = LIB.mfgp_batch_mll_and_grad(self._plan, _ptr(X), _ptr(y), _ptr(Z), C.byref(o), mll, ld, grad,
+                                         info, _ptr(ws), ws.numel(), _stream())
+        _check(st, "batch_mll_and_grad", allow)
+        grads, off = [], 0
+        if grad is not None:
+            for npar in self.nparams:
+                grads.append(list(grad[off:off + npar]))
+                off += npar
+        infos = _info_list(info, self.nprob * self.t)
+        return dict(mll=list(mll), logdet=list(ld), grad=grads if want_grad else None,
+                    info=[infos[b * self.t:(b + 1) * self.t] for b in range(self.nprob)], status=st)
 
 
 LOG_2PI = math.log(2.0 * math.pi)
