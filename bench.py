@@ -58,12 +58,14 @@ def cpu_baseline(w, rows: int) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--mode", default="step", choices=["step", "kernel"])
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the single BF16-x2 comparison step")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -174,6 +176,34 @@ def main() -> int:
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
         },
     }
+    if args.precision == "fp32" and not args.no_compare:
+        # The same step with the K-tile x V contraction in BF16-x2 on MFMA (FP32
+        # entries, FP64-accumulated residual refinement to the same 1e-6).
+        print("[bench] bf16x2 comparison step", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        mfgp.timing_enable(True)
+        t1 = time.perf_counter()
+        rb = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision="bf16x2", want_alpha=True)
+        mfgp.predict_mean(kern, X, Xs, rb["alpha"].float())
+        torch.cuda.synchronize()
+        eb = time.perf_counter() - t1
+        ab = mfgp.timing_read(-1)
+        mb = mfgp.timing_read(mfgp.SWEEP_MFMA)
+        phb = mfgp.timing_phases()
+        mfgp.timing_enable(False)
+        line["bf16x2"] = {
+            "ms_per_step": eb * 1e3,
+            "entries_per_s": ab["entries"] / eb,
+            "cg_solve_s": phb["cg_ms"] * 1e-3,
+            "mll_grad_s": (phb["cg_ms"] + phb["slq_ms"] + phb["adjoint_ms"]) * 1e-3,
+            "cg_iters_max": max(i["iters"] for i in rb["info"]),
+            "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
+            "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
+            "mfma_sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
+            "mfma_sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
+            "mll": rb["mll"],
+            "logdet": rb["logdet"],
+        }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
