@@ -39,6 +39,7 @@ UNITS = [
     ("abi.hip", "abi.o", []),
     ("timing.hip", "timing.o", []),
     ("batch.hip", "batch.o", []),
+    ("hybrid.hip", "hybrid.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]
 

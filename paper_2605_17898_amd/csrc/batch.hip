@@ -384,6 +384,13 @@ struct mfgp_batch_plan_s {
     std::vector<BSeg> segs;
     std::vector<int> seg_first;
     std::vector<int64_t> row_offs;   // prefix [nprob + 1]
+    // Capture stream (default priority, non-blocking): the caller's stream may
+    // be the legacy NULL stream, which cannot be captured; the graph recorded
+    // here is then launched on the caller's stream.
+    hipStream_t cap_stream = nullptr;
+    ~mfgp_batch_plan_s() {
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace mfgp {
@@ -446,10 +453,12 @@ struct BatchWs {
     double* R64; double* scal; int* ints; double* dpart; double* tmp; double* resid; char* part;
     BTile* queue; BProb* probs; BSeg* segs; int* seg_first; int64_t* row_offs; int* counter;
     int* logflag;
+    int cus;          // compute units of the device (host value)
 };
 
 static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     BatchWs w;
+    w.cus = 256;
     const size_t rt = static_cast<size_t>(P.rows) * P.t;
     const size_t T = static_cast<size_t>(P.nprob) * P.t;
     const int64_t nt = max_tiles(P);
@@ -482,22 +491,16 @@ static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     return w;
 }
 
-// Resident workgroups of the persistent kernels: 8 per CU.
-static int persistent_grid(int ntiles) {
-    static thread_local int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    }
+// Resident workgroups of the persistent kernels: 8 per CU (the CU count is
+// read by the caller before any graph capture begins).
+static int persistent_grid(int ntiles, int cus) {
     return static_cast<int>(std::min<int64_t>(ntiles, static_cast<int64_t>(cus) * 8));
 }
 
 template <int FAM>
 static hipError_t launch_bsweep_f(int tb, const BatchWs& w, int ntiles, const float* V, float* part,
                                   hipStream_t s) {
-    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles));
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
     switch (tb) {
 #define MFGP_C(TBV)                                                                                 \
@@ -524,7 +527,7 @@ static hipError_t launch_bsweep(int family, int tb, const BatchWs& w, int ntiles
 template <int FAM>
 static hipError_t launch_badj_f(int tb, const BatchWs& w, int ntiles, const float* A, const float* B,
                                 const ColW& cw, double* part, hipStream_t s) {
-    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles));
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
     switch (tb) {
 #define MFGP_C(TBV)                                                                                   \
@@ -781,7 +784,13 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     mfgp_batch_plan_s& P = *plan;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    const BatchWs w = carve_batch(cv, P);
+    BatchWs w = carve_batch(cv, P);
+    {
+        int dev = 0;
+        w.cus = 256;
+        B_CHECK(hipGetDevice(&dev));
+        B_CHECK(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     const int t = P.t, p = P.p, nprob = P.nprob;
     const int T = nprob * t;
     const int64_t rt = P.rows * t;
@@ -861,12 +870,14 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     P.graph_launches = 0;
     if (P.use_graph) {
         B_CHECK(hipStreamSynchronize(s));
-        B_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        if (!P.cap_stream) B_CHECK(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = P.cap_stream;
+        B_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         timing_suspend(true);   // no event records inside the graph
         hipError_t ce = hipSuccess;
-        for (int k = 0; k < check_every && ce == hipSuccess; ++k) ce = batch_iteration(P, w, st, ntiles, tol, s);
+        for (int k = 0; k < check_every && ce == hipSuccess; ++k) ce = batch_iteration(P, w, st, ntiles, tol, cs);
         timing_suspend(false);
-        hipError_t ee = hipStreamEndCapture(s, &graph);
+        hipError_t ee = hipStreamEndCapture(cs, &graph);
         if (ce != hipSuccess || ee != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             set_last_hip_error(ce != hipSuccess ? ce : ee);

@@ -4,6 +4,7 @@
 #include "common.hpp"
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mfgp {
@@ -224,6 +225,20 @@ hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float
         c0 += tb;
     }
     return hipSuccess;
+}
+
+size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, bool allow_mfma) {
+    size_t b = apply_scratch_floats(m, n, t) * sizeof(float);
+    if (allow_mfma && hybrid_supported(t)) b = std::max(b, hybrid_scratch_bytes(m, n, t));
+    return b;
+}
+
+hipError_t apply_fp32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                      float* out, bool with_noise, const float* Vself, void* scratch, bool allow_mfma,
+                      hipStream_t s) {
+    if (allow_mfma && hybrid_supported(t))
+        return apply_hybrid(op, Ur, m, V, t, out, with_noise, Vself, scratch, s);
+    return apply_f32(op, Ur, m, V, t, out, with_noise, Vself, static_cast<float*>(scratch), s);
 }
 
 size_t resid_scratch_doubles(int64_t n, int t) {

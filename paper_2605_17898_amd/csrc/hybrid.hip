@@ -1,0 +1,245 @@
+// FP32 entry sweep with the K-tile x V contraction on the FP32 matrix cores.
+//
+// For many right-hand sides the contraction (2t FLOP per entry) dominates the
+// VALU sweep.  Here the columns split into NT tiles of 16 contracted with
+// v_mfma_f32_16x16x4_f32 (FP32 inputs, FP32 accumulation: the same
+// arithmetic class as the VALU FMAs) and TV leftover columns (t = 16 NT + TV,
+// e.g. the y column of [y, probes]) that stay on the VALU.  The VALU only
+// generates entries, directly in the MFMA A-operand layout.
+//
+// v_mfma_f32_16x16x4_f32 (one wave, 64 lanes): lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator register r holds C[4 (l / 16) + r][l % 16].
+// With A = K(16 rows, 4 consecutive j) each lane generates exactly one entry
+// per MFMA step: row l % 16 of the tile, column j0 + l / 16.
+//
+// A wave owns RT = 4 row tiles (64 rows), a block 4 waves (256 rows), with the
+// same block -> (row block, j-chunk) split and fixed-order partial reduction
+// as the other sweeps.  V is repacked once per product into per-step
+// fragments: for step q (4 j's) and lane l, NT values V[4q + l/16][TV + 16 w +
+// l%16] followed by the TV leftover values V[4q + l/16][0..TV), so a lane
+// fetches all its right-hand-side operands of a step with one load.
+#include "internal.hpp"
+#include "sweep_kernels.hpp"
+
+namespace mfgp {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kHRT = 4;     // row tiles of 16 per wave
+constexpr int kHK = 4;      // j per MFMA step
+
+__global__ void pack_hfrag_kernel(const float* __restrict__ V, int64_t n, int t, int nt, int tv,
+                                  int64_t nsteps, float* __restrict__ F) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int W = nt + tv;
+    if (idx >= nsteps * 64 * W) return;
+    const int w = static_cast<int>(idx % W);
+    const int64_t lq = idx / W;
+    const int l = static_cast<int>(lq % 64);
+    const int64_t q = lq / 64;
+    const int64_t j = q * kHK + l / 16;
+    const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
+    F[idx] = (j < n) ? V[j * t + c] : 0.0f;
+}
+
+template <int FAM, int D, int NT, int TV>
+__global__ __launch_bounds__(kBlock) void sweep_hyb_kernel(
+    const float* __restrict__ Ur, const float* __restrict__ Uc, const float* __restrict__ F,
+    int64_t m, int64_t n, int t, int chunks, int64_t jchunk, float* __restrict__ partial) {
+    constexpr int W = NT + TV;
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane >> 4;       // which of the 4 j's of a step this lane generates
+    const int r16 = lane & 15;
+    const int64_t row0 = static_cast<int64_t>(rb) * kBlock + wave * (kHRT * 16);
+
+    float ui[kHRT][D];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        int64_t i = row0 + r * 16 + r16;
+        i = i < m ? i : m - 1;
+#pragma unroll
+        for (int k = 0; k < D; ++k) ui[r][k] = Ur[i * D + k];
+    }
+    f32x4 acc[kHRT][NT > 0 ? NT : 1], tot[kHRT][NT > 0 ? NT : 1];
+    float sv[kHRT][TV > 0 ? TV : 1], tv_tot[kHRT][TV > 0 ? TV : 1];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[r][c][q] = 0.0f;
+                tot[r][c][q] = 0.0f;
+            }
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            sv[r][c] = 0.0f;
+            tv_tot[r][c] = 0.0f;
+        }
+    }
+
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;          // multiple of kHK
+    int64_t j1 = j0 + jchunk;
+    const int64_t npad = (n + kHK - 1) / kHK * kHK;
+    j1 = j1 < npad ? j1 : npad;
+    int64_t seg_end = j0 + kSeg;
+    for (int64_t jb = j0; jb < j1; jb += kHK) {
+        const int64_t q = jb / kHK;
+        float fr[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) fr[w] = F[(q * 64 + lane) * W + w];
+        int64_t j = jb + grp;
+        j = j < n ? j : n - 1;    // padded j carry V = 0
+        float uj[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) uj[k] = Uc[j * D + k];
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+            const float e = kentry<FAM>(sqdist<D>(ui[r], uj));
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, fr[c], acc[r][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < TV; ++c) sv[r][c] = fmaf(e, fr[NT + c], sv[r][c]);
+        }
+        if (jb + kHK >= seg_end) {
+            // two-level accumulation, as in the VALU sweeps
+            seg_end += kSeg;
+#pragma unroll
+            for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        tot[r][c][qq] += acc[r][c][qq];
+                        acc[r][c][qq] = 0.0f;
+                    }
+#pragma unroll
+                for (int c = 0; c < TV; ++c) {
+                    tv_tot[r][c] += sv[r][c];
+                    sv[r][c] = 0.0f;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        // MFMA columns: register qq of lane l -> row 4 (l/16) + qq, column l % 16
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int64_t i = row0 + r * 16 + 4 * grp + qq;
+                const float v = tot[r][c][qq] + acc[r][c][qq];
+                if (i < m) partial[(static_cast<int64_t>(ch) * m + i) * t + TV + 16 * c + r16] = v;
+            }
+        // VALU columns: sum the 4 lane groups (j offsets) of row r16
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            float v = tv_tot[r][c] + sv[r][c];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int64_t i = row0 + r * 16 + r16;
+            if (grp == 0 && i < m) partial[(static_cast<int64_t>(ch) * m + i) * t + c] = v;
+        }
+    }
+}
+
+// (NT, TV) pairs with a compiled kernel: t = 16 NT + TV.
+static bool hybrid_shape(int t, int& nt, int& tv) {
+    nt = t / 16;
+    tv = t % 16;
+    return nt >= 1 && nt <= 4 && tv <= 1;
+}
+
+bool hybrid_supported(int t) {
+    int nt, tv;
+    return hybrid_shape(t, nt, tv);
+}
+
+static SweepPlan plan_hybrid(int64_t m, int64_t n) {
+    SweepPlan p = plan_sweep(m, n);
+    p.jchunk = (p.jchunk + kHK - 1) / kHK * kHK;
+    return p;
+}
+
+size_t hybrid_scratch_bytes(int64_t m, int64_t n, int t) {
+    int nt, tv;
+    if (!hybrid_shape(t, nt, tv)) return 0;
+    const SweepPlan p = plan_hybrid(m, n);
+    const int64_t nsteps = (n + kHK - 1) / kHK;
+    const size_t frag = static_cast<size_t>(nsteps) * 64 * (nt + tv) * sizeof(float);
+    const size_t part = static_cast<size_t>(p.chunks) * m * t * sizeof(float);
+    return frag + part + 1024;
+}
+
+template <int FAM, int D>
+static hipError_t hyb_fd(int nt, int tv, const float* Ur, const float* Uc, const float* F, int64_t m,
+                         int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+#define MFGP_H(NTV, TVV)                                                                          \
+    if (nt == NTV && tv == TVV) {                                                                 \
+        hipLaunchKernelGGL((sweep_hyb_kernel<FAM, D, NTV, TVV>), grid, dim3(kBlock), 0, s, Ur, Uc, \
+                           F, m, n, t, p.chunks, p.jchunk, partial);                              \
+        return hipGetLastError();                                                                 \
+    }
+    MFGP_H(1, 0) MFGP_H(1, 1) MFGP_H(2, 0) MFGP_H(2, 1) MFGP_H(3, 0) MFGP_H(3, 1) MFGP_H(4, 0) MFGP_H(4, 1)
+#undef MFGP_H
+    return hipErrorInvalidValue;
+}
+
+template <int FAM>
+static hipError_t hyb_f(int D, int nt, int tv, const float* Ur, const float* Uc, const float* F, int64_t m,
+                        int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
+    switch (D) {
+        case 1: return hyb_fd<FAM, 1>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 2: return hyb_fd<FAM, 2>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 3: return hyb_fd<FAM, 3>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 4: return hyb_fd<FAM, 4>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 5: return hyb_fd<FAM, 5>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 6: return hyb_fd<FAM, 6>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 7: return hyb_fd<FAM, 7>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        case 8: return hyb_fd<FAM, 8>(nt, tv, Ur, Uc, F, m, n, t, p, partial, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, float s2,
+                           float sig2, const float* Vself, float* out, hipStream_t s);
+
+hipError_t apply_hybrid(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                        float* out, bool with_noise, const float* Vself, void* scratch, hipStream_t s) {
+    int nt, tv;
+    if (!hybrid_shape(t, nt, tv)) return hipErrorNotSupported;
+    const int64_t n = op.n;
+    const int64_t nsteps = (n + kHK - 1) / kHK;
+    const SweepPlan p = plan_hybrid(m, n);
+    char* base = static_cast<char*>(scratch);
+    float* F = reinterpret_cast<float*>(base);
+    const size_t frag = static_cast<size_t>(nsteps) * 64 * (nt + tv) * sizeof(float);
+    float* partial = reinterpret_cast<float*>(base + ((frag + 255) / 256) * 256);
+    const int64_t total = nsteps * 64 * (nt + tv);
+    hipLaunchKernelGGL(pack_hfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                       s, V, n, t, nt, tv, nsteps, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* tok = timing_begin(s);
+    switch (op.family) {
+        case MFGP_RBF: e = hyb_f<MFGP_RBF>(op.d, nt, tv, Ur, op.U, F, m, n, t, p, partial, s); break;
+        case MFGP_MATERN12: e = hyb_f<MFGP_MATERN12>(op.d, nt, tv, Ur, op.U, F, m, n, t, p, partial, s); break;
+        case MFGP_MATERN32: e = hyb_f<MFGP_MATERN32>(op.d, nt, tv, Ur, op.U, F, m, n, t, p, partial, s); break;
+        default: e = hyb_f<MFGP_MATERN52>(op.d, nt, tv, Ur, op.U, F, m, n, t, p, partial, s); break;
+    }
+    {
+        const double ent = static_cast<double>(m) * static_cast<double>(n);
+        timing_end(tok, s, kSweepF32, ent, ent * sweep_flops_per_entry(op.family, op.d, t, false));
+    }
+    if (e != hipSuccess) return e;
+    return reduce_partials(partial, p.chunks, m, t, op.s2, with_noise ? op.sig2 : 0.0f,
+                           with_noise ? Vself : nullptr, out, s);
+}
+
+}  // namespace mfgp

@@ -39,6 +39,17 @@ size_t resid_scratch_doubles(int64_t n, int t);
 hipError_t residual_f64(const Operator& op, const float* B, const double* X64, int t, double* R,
                         double* scratch, hipStream_t s);
 
+// FP32 sweep with the contraction on FP32 MFMA (t = 16 NT + TV, NT 1..4, TV 0..1).
+bool hybrid_supported(int t);
+size_t hybrid_scratch_bytes(int64_t m, int64_t n, int t);
+hipError_t apply_hybrid(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                        float* out, bool with_noise, const float* Vself, void* scratch, hipStream_t s);
+// FP32 product choosing the MFMA-contraction form when allowed and supported.
+size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, bool allow_mfma);
+hipError_t apply_fp32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
+                      float* out, bool with_noise, const float* Vself, void* scratch, bool allow_mfma,
+                      hipStream_t s);
+
 // BF16-MFMA tile products (precision x1 / x2).
 bool precision_supported(int precision);
 size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision);

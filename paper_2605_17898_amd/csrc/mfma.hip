@@ -28,7 +28,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 constexpr int kRT = 2;      // row tiles (of 32 rows) per wave
 constexpr int kJT = 16;     // j per MFMA step
 
-bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_BF16X2; }
+bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_FP32_VALU; }
 
 static inline int col_tiles(int t) { return (t + 31) / 32; }
 
@@ -158,7 +158,8 @@ size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
     const int64_t njt = (n + kJT - 1) / kJT;
     const size_t frag = static_cast<size_t>(njt) * col_tiles(t) * 64 * sizeof(bf16x8);
     const size_t part = static_cast<size_t>(p.chunks) * m * t * sizeof(float);
-    return 2 * frag + part + 4096 + (precision == MFGP_BF16X2 ? 0 : 0);
+    (void)precision;
+    return 2 * frag + part + 4096;
 }
 
 template <int FAM, int D>

@@ -57,6 +57,21 @@ def test_matvec_column_counts(mf, t):
     assert col_rel_err(out, ref).max() <= TOL
 
 
+@pytest.mark.parametrize("t", [16, 17, 33, 49, 64])
+@pytest.mark.parametrize("family", ["rbf", "matern52"])
+def test_matvec_mfma_contraction_and_valu_forms(mf, t, family):
+    # FP32 moves 16-column tiles of the contraction onto FP32 MFMA for these t;
+    # the explicit VALU-only form must agree with the oracle just the same.
+    banner(f"matvec fp32 (MFMA contraction) and fp32_valu family={family} t={t} n=2113")
+    w = inputs.random_problem(60 + t, 2113, 4, family, ard=True, noise=0.02)
+    V = inputs.gaussian_rhs(t + 1, w.n, t)
+    ref = gp.ky_matvec(okern(w), w.X, V)
+    a = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="fp32"))
+    b = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="fp32_valu"))
+    assert col_rel_err(a, ref).max() <= TOL
+    assert col_rel_err(b, ref).max() <= TOL
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 255, 256, 257, 4097])
 @pytest.mark.parametrize("kind", ["normal", "ones", "smooth"])
 def test_matvec_ragged_sizes(mf, n, kind):
