@@ -12,7 +12,12 @@
 // Every `check_every` iterations the host reads the active flags.  When no
 // column is active the true residual B - K_y X is recomputed with FP64
 // accumulation (X is FP64), and columns above tolerance restart from it
-// (iterative refinement).  The FP64 solution is what lets the recomputed
+// (iterative refinement).  While iterating, a column whose recurrence
+// residual has fallen tenfold since its last true residual has r replaced by
+// the recomputed true residual, its search direction kept (residual
+// replacement, van der Vorst & Ye 2000): this bounds the drift between the
+// recurrence and the true residual that an inexact product (FP32, and more so
+// the BF16 forms) causes, without discarding the Krylov space as a restart does.  The FP64 solution is what lets the recomputed
 // residual reach 1e-6: an FP32-rounded solution alone floors at a few 1e-6.
 #include "cg.hpp"
 
@@ -119,15 +124,32 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     CG_CHECK(hipGetLastError());
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
-    std::vector<double> h_relt(t), h_rr(t), h_b2(t);
+    std::vector<double> h_relt(t), h_rr(t), h_b2(t), h_rep(t, 0.0);
+    std::vector<int> h_flag(t, 0);
     int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
+    CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
 
     for (;;) {
         CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
-        bool any = false;
-        for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
+        bool any = false, replace = false;
+        for (int c = 0; c < t; ++c) {
+            const bool act = h_active[c] && h_iters[c] < max_iter;
+            any = any || act;
+            h_flag[c] = (act && h_rr[c] <= 0.01 * h_rep[c]) ? 1 : 0;
+            replace = replace || h_flag[c];
+        }
+        if (replace) {
+            CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+            CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
+            CG_CHECK(cg_replace(st, b.R64, n, t, restart, b.dots, tmp, s));
+            CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_CHECK(hipStreamSynchronize(s));
+            for (int c = 0; c < t; ++c)
+                if (h_flag[c]) h_rep[c] = h_rr[c];
+        }
         if (any) {
             for (int k = 0; k < check_every; ++k) {
                 CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b.apply, s));
@@ -160,6 +182,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(cg_restart(st, b.R64, n, t, restart, s));
         CG_CHECK(col_dots_ff(st.r, st.r, n, t, tmp, b.dots, s));
         CG_CHECK(cg_activate(st, t, restart, tmp, s));
+        CG_CHECK(hipMemcpyAsync(h_rep.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
         log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
     }
 

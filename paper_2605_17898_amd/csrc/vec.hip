@@ -196,6 +196,20 @@ __global__ void cg_restart_kernel(CgState st, const double* __restrict__ R64, in
     st.p[idx] = r;
 }
 
+// Residual replacement: r = fl32(R64) for flagged columns, search direction kept.
+__global__ void cg_replace_kernel(CgState st, const double* __restrict__ R64, int64_t total, int t,
+                                  const int* __restrict__ flag) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    if (flag[idx % t]) st.r[idx] = static_cast<float>(R64[idx]);
+}
+
+__global__ void cg_set_rr_kernel(CgState st, int t, const int* __restrict__ flag,
+                                 const double* __restrict__ rr_new) {
+    for (int c = threadIdx.x; c < t; c += blockDim.x)
+        if (flag[c]) st.rr[c] = rr_new[c];
+}
+
 // Re-activate restarted columns with their new residual norm.
 __global__ void cg_activate_kernel(CgState st, int t, const int* __restrict__ restart,
                                    const double* __restrict__ rr_new) {
@@ -256,6 +270,15 @@ hipError_t cg_restart(const CgState& st, const double* R64, int64_t n, int t, co
 hipError_t cg_activate(const CgState& st, int t, const int* restart, const double* rr_new,
                        hipStream_t s) {
     hipLaunchKernelGGL(cg_activate_kernel, dim3(1), dim3(256), 0, s, st, t, restart, rr_new);
+    return hipGetLastError();
+}
+
+hipError_t cg_replace(const CgState& st, const double* R64, int64_t n, int t, const int* flag,
+                      double* scratch, double* rr_tmp, hipStream_t s) {
+    hipLaunchKernelGGL(cg_replace_kernel, dim3(nblk(n * t)), dim3(256), 0, s, st, R64, n * t, t, flag);
+    hipError_t e = col_dots_ff(st.r, st.r, n, t, rr_tmp, scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cg_set_rr_kernel, dim3(1), dim3(256), 0, s, st, t, flag, rr_tmp);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ hipError_t cg_restart(const CgState& st, const double* R64, int64_t n, int t, co
                       hipStream_t s);
 hipError_t cg_activate(const CgState& st, int t, const int* restart, const double* rr_new,
                        hipStream_t s);
+hipError_t cg_replace(const CgState& st, const double* R64, int64_t n, int t, const int* flag,
+                      double* scratch, double* rr_tmp, hipStream_t s);
 hipError_t fill_f64(double* x, int64_t total, double v, hipStream_t s);
 hipError_t copy2_f32(const float* src, float* a, float* b, int64_t total, hipStream_t s);
 hipError_t f64_to_f32(const double* src, float* dst, int64_t total, hipStream_t s);
