@@ -171,7 +171,8 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": None,
-            "kernel": "sweep_f32_kernel<RBF, d=4, t=33>" if args.precision == "fp32" else "mfma sweep",
+            "kernel": ("sweep_hyb_kernel<RBF, d=4, NT=2, TV=1> (FP32 entries on the VALU, "
+                       "contraction on v_mfma_f32_16x16x4_f32)") if args.precision == "fp32" else "mfma sweep",
             "flop_per_entry": 3 * 4 + 1 + 2 * 33,
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
         },

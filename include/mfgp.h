@@ -102,7 +102,8 @@ typedef struct {
 /* Conjugate-gradient options (host struct). */
 typedef struct {
     double tol;           /* per column ||b - K_y x||_2 / ||b||_2 target, > 0 (e.g. 1e-6)      */
-    int32_t max_iter;     /* CG iterations per column over all refinement cycles; 0 = min(n, 20000) */
+    int32_t max_iter;     /* CG iterations per column over all refinement cycles;
+                             0 = min(max(2n, 64), 20000)                                   */
     int32_t check_every;  /* iterations between host convergence checks; 0 = automatic       */
     int32_t max_refine;   /* residual recomputations / restarts allowed; < 0 = default 8      */
     int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries, FP64 sums) */

@@ -101,9 +101,14 @@ static int check_precision_cols(int precision, int t) {
     return MFGP_OK;
 }
 
+// Default CG iteration cap: 2n (at least 64, at most 20000).  Exact CG ends in
+// n steps; in FP32 a well-conditioned small system may need a few more.
 static int default_max_iter(int64_t n, int max_iter) {
     if (max_iter > 0) return max_iter;
-    return static_cast<int>(n < 20000 ? n : 20000);
+    int64_t m = 2 * n;
+    if (m < 64) m = 64;
+    if (m > 20000) m = 20000;
+    return static_cast<int>(m);
 }
 
 static int hip_fail(hipError_t e) {

@@ -724,7 +724,8 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
         maxn = std::max(maxn, n);
     }
     P->max_n = maxn;
-    P->max_iter = max_iter > 0 ? max_iter : static_cast<int>(std::min<int64_t>(maxn, 20000));
+    P->max_iter = max_iter > 0 ? max_iter
+                               : static_cast<int>(std::min<int64_t>(std::max<int64_t>(2 * maxn, 64), 20000));
     // segments of <= kSegRows rows within one problem, and row-offset prefix
     P->seg_first.push_back(0);
     for (int b = 0; b < P->nprob; ++b) {

@@ -134,12 +134,15 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
+        // A column whose residual norm fell tenfold since its last true residual
+        // triggers a replacement; every active column that fell at least 1.5x
+        // joins it, so the columns of a block share the recomputations.
         bool any = false, replace = false;
         for (int c = 0; c < t; ++c) {
             const bool act = h_active[c] && h_iters[c] < max_iter;
             any = any || act;
-            h_flag[c] = (act && h_rr[c] <= 0.01 * h_rep[c]) ? 1 : 0;
-            replace = replace || h_flag[c];
+            replace = replace || (act && h_rr[c] <= 0.01 * h_rep[c]);
+            h_flag[c] = (act && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
         }
         if (replace) {
             CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));

@@ -56,7 +56,7 @@ int column_block(int t) {
 }
 
 int column_block64(int t) {
-    static const int sizes[] = {8, 4, 2, 1};
+    static const int sizes[] = {33, 32, 17, 16, 8, 4, 2, 1};
     for (int s : sizes)
         if (s <= t) return s;
     return 1;

@@ -85,46 +85,61 @@ __global__ __launch_bounds__(kBlock) void sweep_hyb_kernel(
     int64_t j1 = j0 + jchunk;
     const int64_t npad = (n + kHK - 1) / kHK * kHK;
     j1 = j1 < npad ? j1 : npad;
-    int64_t seg_end = j0 + kSeg;
-    for (int64_t jb = j0; jb < j1; jb += kHK) {
-        const int64_t q = jb / kHK;
-        float fr[W];
+    const int64_t q0 = j0 / kHK;
+    const int64_t nst = j0 < j1 ? (j1 - j0) / kHK : 0;     // MFMA steps of this chunk
+
+    // Operands of one step: this lane's fragment of V and u_j (j = 4 q + grp).
+    auto load_step = [&](int64_t st, float (&f)[W], float (&u)[D]) {
+        const int64_t q = q0 + st;
 #pragma unroll
-        for (int w = 0; w < W; ++w) fr[w] = F[(q * 64 + lane) * W + w];
-        int64_t j = jb + grp;
+        for (int w = 0; w < W; ++w) f[w] = F[(q * 64 + lane) * W + w];
+        int64_t j = q * kHK + grp;
         j = j < n ? j : n - 1;    // padded j carry V = 0
-        float uj[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) uj[k] = Uc[j * D + k];
+        for (int k = 0; k < D; ++k) u[k] = Uc[j * D + k];
+    };
+    auto compute_step = [&](const float (&f)[W], const float (&u)[D]) {
 #pragma unroll
         for (int r = 0; r < kHRT; ++r) {
-            const float e = kentry<FAM>(sqdist<D>(ui[r], uj));
+            const float e = kentry<FAM>(sqdist<D>(ui[r], u));
 #pragma unroll
             for (int c = 0; c < NT; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, fr[c], acc[r][c], 0, 0, 0);
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, f[c], acc[r][c], 0, 0, 0);
 #pragma unroll
-            for (int c = 0; c < TV; ++c) sv[r][c] = fmaf(e, fr[NT + c], sv[r][c]);
+            for (int c = 0; c < TV; ++c) sv[r][c] = fmaf(e, f[NT + c], sv[r][c]);
         }
-        if (jb + kHK >= seg_end) {
-            // two-level accumulation, as in the VALU sweeps
-            seg_end += kSeg;
+    };
+    auto flush = [&]() {   // two-level accumulation, as in the VALU sweeps
 #pragma unroll
-            for (int r = 0; r < kHRT; ++r) {
+        for (int r = 0; r < kHRT; ++r) {
 #pragma unroll
-                for (int c = 0; c < NT; ++c)
+            for (int c = 0; c < NT; ++c)
 #pragma unroll
-                    for (int qq = 0; qq < 4; ++qq) {
-                        tot[r][c][qq] += acc[r][c][qq];
-                        acc[r][c][qq] = 0.0f;
-                    }
-#pragma unroll
-                for (int c = 0; c < TV; ++c) {
-                    tv_tot[r][c] += sv[r][c];
-                    sv[r][c] = 0.0f;
+                for (int qq = 0; qq < 4; ++qq) {
+                    tot[r][c][qq] += acc[r][c][qq];
+                    acc[r][c][qq] = 0.0f;
                 }
+#pragma unroll
+            for (int c = 0; c < TV; ++c) {
+                tv_tot[r][c] += sv[r][c];
+                sv[r][c] = 0.0f;
             }
         }
+    };
+
+    // Ping-pong over two operand sets: the loads of one step are in flight
+    // while the other step's entries and MFMAs run.
+    float fa[W], ua[D], fb[W], ub[D];
+    if (nst > 0) load_step(0, fa, ua);
+    int64_t st = 0;
+    for (; st + 1 < nst; st += 2) {
+        load_step(st + 1, fb, ub);
+        compute_step(fa, ua);
+        load_step(st + 2 < nst ? st + 2 : nst - 1, fa, ua);
+        compute_step(fb, ub);
+        if (((st + 2) & (kSeg / kHK - 1)) == 0) flush();
     }
+    if (st < nst) compute_step(fa, ua);
 #pragma unroll
     for (int r = 0; r < kHRT; ++r) {
         // MFMA columns: register qq of lane l -> row 4 (l/16) + qq, column l % 16

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f64acc_kernel(
 }
 
 #define MFGP_TB_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(16) X(17) X(32) X(33)
-#define MFGP_TB64_LIST(X) X(1) X(2) X(4) X(8)
+#define MFGP_TB64_LIST(X) X(1) X(2) X(4) X(8) X(16) X(17) X(32) X(33)
 
 template <int FAM, int D>
 hipError_t sweep_f32_fd(int tb, const SweepArgs& a, hipStream_t s) {

@@ -239,7 +239,7 @@ def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, 
     n, d = X.shape
     t = _cols(B)
     o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None)
-    mi = max_iter if max_iter > 0 else min(n, 20000)
+    mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device) if x0 is None else \
         _dev(x0, torch.float64, "x0").clone()
     lan = torch.empty((t, mi, 2), dtype=torch.float64, device=B.device) if want_lanczos else None
@@ -290,7 +290,7 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
         num_probes = Z.shape[1]
     t = num_probes + 1
     o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed)
-    mi = max_iter if max_iter > 0 else min(n, 20000)
+    mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     ws = workspace(workspace_bytes(OP_MLL, n, d, t, o.precision, mi), X.device)
     ks = kern.struct(d)
     npar = LIB.mfgp_num_params(C.byref(ks))
@@ -426,6 +426,66 @@ class BatchPlan:
         infos = _info_list(info, self.nprob * self.t)
         return dict(mll=list(mll), logdet=list(ld), grad=grads if want_grad else None,
                     info=[infos[b * self.t:(b + 1) * self.t] for b in range(self.nprob)], status=st)
+
+
+# ---------------------------------------------------------------- autograd
+
+def _kernel_from_params(family: str, params: torch.Tensor, d: int, ard: bool) -> Kernel:
+    th = [float(v) for v in params.detach().cpu().tolist()]
+    nl = d if ard else 1
+    ls = th[:nl] if ard else th[0]
+    return Kernel(family, ls, th[nl], th[nl + 1])
+
+
+class KernelMatvec(torch.autograd.Function):
+    """KV = K_y(theta) V with gradients for V and theta.
+
+    params: CPU float64 tensor [l_1..l_d (or l), s2, sigma^2].  backward:
+    grad_V = K_y G (K_y is symmetric) and grad_theta[p] = sum_c G_c^T
+    (dK_y/dtheta_p) V_c, both computed by the library (matrix-free product and
+    adjoint sweep)."""
+
+    @staticmethod
+    def forward(ctx, V: torch.Tensor, X: torch.Tensor, params: torch.Tensor, family: str, ard: bool):
+        kern = _kernel_from_params(family, params, X.shape[1], ard)
+        ctx.save_for_backward(V, X)
+        ctx.kern = kern
+        ctx.params_meta = (params.dtype, params.device, params.shape)
+        return kernel_matvec(kern, X, V.contiguous())
+
+    @staticmethod
+    def backward(ctx, G: torch.Tensor):
+        V, X = ctx.saved_tensors
+        G = G.contiguous()
+        gV = kernel_matvec(ctx.kern, X, G) if ctx.needs_input_grad[0] else None
+        gp = None
+        if ctx.needs_input_grad[2]:
+            t = 1 if V.dim() == 1 else V.shape[1]
+            g = kernel_adjoint(ctx.kern, X, G.reshape(V.shape[0], t).contiguous(),
+                               V.reshape(V.shape[0], t).contiguous(), [1.0] * t)
+            dt, dv, shp = ctx.params_meta
+            gp = torch.tensor(g, dtype=dt, device=dv).reshape(shp)
+        return gV, None, gp, None, None
+
+
+class MarginalLogLikelihood(torch.autograd.Function):
+    """log p(y | X, theta) by CG + stochastic Lanczos, differentiable in theta.
+
+    params: CPU float64 tensor [l.. , s2, sigma^2]; Z: probes [n, p] (GPU).
+    forward returns a float64 scalar; backward returns grad_out times the
+    library's adjoint-sweep gradient (same probes)."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, X: torch.Tensor, y: torch.Tensor, Z: torch.Tensor,
+                family: str, ard: bool, tol: float = 1e-6):
+        kern = _kernel_from_params(family, params, X.shape[1], ard)
+        r = mll_and_grad(kern, X, y, Z=Z, tol=tol)
+        ctx.grad = torch.tensor(r["grad"], dtype=params.dtype, device=params.device).reshape(params.shape)
+        return torch.tensor(r["mll"], dtype=torch.float64, device=params.device)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return g.to(ctx.grad.dtype) * ctx.grad, None, None, None, None, None, None
 
 
 LOG_2PI = math.log(2.0 * math.pi)

@@ -53,7 +53,7 @@ SIZES = [(1, 2), (255, 1), (257, 3), (700, 6), (1200, 2), (64, 5), (1500, 4), (9
 
 def test_batch_matches_single_and_oracle(mf):
     banner("batch of 8 uneven problems vs single-problem runs and oracle")
-    p = 8
+    p = 7
     probs = make_batch(SIZES, p)
     X, y, Z = pack(probs)
     plan = plan_for(mf, probs, p, tune=False)
