@@ -110,6 +110,14 @@ typedef struct {
     int32_t warm_start;   /* nonzero: Xsol holds the initial guess x0 on entry                */
     int32_t pad_;
     uint64_t probe_seed;  /* seed of the SplitMix64 probes when Z == NULL (mll_and_grad)      */
+    /* Optional progress callback (may be NULL), called from the calling thread
+     * at host convergence checks whenever the largest per-column iteration
+     * count has advanced by progress_every (0 = 100) since the last call:
+     * progress(progress_user, iterations, worst ||r||/||b|| of the recurrence). */
+    void (*progress)(void* user, int32_t iterations, double rel_resid);
+    void* progress_user;
+    int32_t progress_every;
+    int32_t pad2_;
 } mfgp_cg_opts;
 
 /* Per-column CG report (host array, one entry per column). */

@@ -128,6 +128,9 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     std::vector<int> h_flag(t, 0);
     int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int report_every = o.progress_every > 0 ? o.progress_every : 100;
+    int next_report = report_every;
 
     for (;;) {
         CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -152,6 +155,18 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             CG_CHECK(hipStreamSynchronize(s));
             for (int c = 0; c < t; ++c)
                 if (h_flag[c]) h_rep[c] = h_rr[c];
+        }
+        if (o.progress) {
+            int itmax = 0;
+            double worst = 0.0;
+            for (int c = 0; c < t; ++c) {
+                itmax = std::max(itmax, h_iters[c]);
+                if (h_b2[c] > 0.0) worst = std::max(worst, std::sqrt(h_rr[c] / h_b2[c]));
+            }
+            if (itmax >= next_report) {
+                o.progress(o.progress_user, itmax, worst);
+                while (next_report <= itmax) next_report += report_every;
+            }
         }
         if (any) {
             for (int k = 0; k < check_every; ++k) {

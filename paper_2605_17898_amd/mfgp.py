@@ -31,10 +31,14 @@ class KernelT(C.Structure):
                 ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float)]
 
 
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_double)
+
+
 class CgOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("max_refine", C.c_int32), ("precision", C.c_int32), ("warm_start", C.c_int32),
-                ("pad_", C.c_int32), ("probe_seed", C.c_uint64)]
+                ("pad_", C.c_int32), ("probe_seed", C.c_uint64), ("progress", PROGRESS_FN),
+                ("progress_user", C.c_void_p), ("progress_every", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class CgInfoT(C.Structure):
@@ -212,8 +216,15 @@ def residual(kern: Kernel, X: torch.Tensor, B: torch.Tensor, Xsol: torch.Tensor)
 
 
 def cg_opts(tol: float = 1e-6, max_iter: int = 0, check_every: int = 0, max_refine: int = -1,
-            precision: str = "fp32", warm_start: bool = False, probe_seed: int = 0) -> CgOptsT:
+            precision: str = "fp32", warm_start: bool = False, probe_seed: int = 0,
+            progress=None, progress_every: int = 0) -> CgOptsT:
+    """CG options; progress(iterations, rel_resid) is called during long solves."""
     o = CgOptsT()
+    if progress is not None:
+        cb = PROGRESS_FN(lambda _u, it, rr: progress(int(it), float(rr)))
+        o.progress = cb
+        o._cb_ref = cb   # keep the ctypes thunk alive with the options
+        o.progress_every = progress_every
     o.tol = tol
     o.max_iter = max_iter
     o.check_every = check_every
@@ -232,13 +243,14 @@ def _info_list(info, t):
 
 def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,
              precision: str = "fp32", x0: Optional[torch.Tensor] = None, want_lanczos: bool = False,
-             check_every: int = 0, max_refine: int = -1, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+             check_every: int = 0, max_refine: int = -1, allow=(OK, NOT_CONVERGED, BREAKDOWN),
+             progress=None):
     """Solve K_y X = B.  Returns (Xsol float64, info list, lanczos or None, status)."""
     _dev(X, torch.float32, "X")
     _dev(B, torch.float32, "B")
     n, d = X.shape
     t = _cols(B)
-    o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None)
+    o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None, progress=progress)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device) if x0 is None else \
         _dev(x0, torch.float64, "x0").clone()
@@ -280,7 +292,7 @@ def slq_quadrature(coeffs: Sequence[Sequence[float]], znorm2: float) -> float:
 def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int = 16,
                  Z: Optional[torch.Tensor] = None, tol: float = 1e-6, max_iter: int = 0,
                  precision: str = "fp32", probe_seed: int = 0, want_grad: bool = True,
-                 want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+                 want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None):
     """Returns dict(mll, logdet, grad, alpha, info, status)."""
     _dev(X, torch.float32, "X")
     _dev(y, torch.float32, "y")
@@ -289,7 +301,7 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
         _dev(Z, torch.float32, "Z")
         num_probes = Z.shape[1]
     t = num_probes + 1
-    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed)
+    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed, progress=progress)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     ws = workspace(workspace_bytes(OP_MLL, n, d, t, o.precision, mi), X.device)
     ks = kern.struct(d)
