@@ -23,6 +23,7 @@
 
 #include "adjoint_kernels.hpp"
 #include "cg.hpp"
+#include "hybrid_kernels.hpp"
 #include "internal.hpp"
 
 int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q);
@@ -33,7 +34,8 @@ struct BProb {
     int64_t n;          // rows
     int64_t row_off;    // first packed row
     int64_t u_off;      // element offset of U_b (= x_off)
-    int64_t jchunk;     // j-range length of this problem's tiles
+    int64_t jchunk;     // j-range length of this problem's tiles (a multiple of 4)
+    int64_t f_off;      // float offset of this problem's MFMA fragments of V
     int d;
     int chunks;         // j-ranges per row block
     int tile_base;      // first tile id of this problem
@@ -143,6 +145,61 @@ __global__ __launch_bounds__(kBlock) void batch_adjoint_kernel(
         }
         __syncthreads();   // red is reused by the next tile
     }
+}
+
+// Persistent batched sweep with the contraction on FP32 MFMA (t = 16 NT + TV):
+// the same tile queue, each tile running the shared hybrid block body.
+template <int FAM, int NT, int TV>
+__global__ __launch_bounds__(kBlock) void batch_hyb_kernel(
+    const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
+    const float* __restrict__ U, const float* __restrict__ F, int t, float* __restrict__ partial) {
+    __shared__ int s_k;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_k);
+        __syncthreads();
+        if (k >= ntiles) break;
+        const BTile tl = queue[k];
+        const BProb pb = probs[tl.b];
+        const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;
+        const float* Ub = U + pb.u_off;
+        const float* Fb = F + pb.f_off;
+        float* out = partial + static_cast<int64_t>(tl.id) * kBlock * t;
+        const int64_t rbase = static_cast<int64_t>(tl.rb) * kBlock;
+        switch (pb.d) {
+#define MFGP_HCASE(DV) \
+    case DV: hyb_block<FAM, DV, NT, TV>(Ub, Ub, Fb, pb.n, pb.n, t, rbase, j0, j0 + pb.jchunk, out); break;
+            MFGP_HCASE(1) MFGP_HCASE(2) MFGP_HCASE(3) MFGP_HCASE(4)
+            MFGP_HCASE(5) MFGP_HCASE(6) MFGP_HCASE(7) MFGP_HCASE(8)
+#undef MFGP_HCASE
+            default: break;
+        }
+    }
+}
+
+// Fragments of every problem's packed V block (layout as in the single-problem
+// hybrid sweep), problem found by binary search over the fragment offsets.
+__global__ void batch_pack_hfrag_kernel(const float* __restrict__ V, const BProb* __restrict__ probs,
+                                        const int64_t* __restrict__ foffs, int nprob, int t, int nt,
+                                        int tv, float* __restrict__ F) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= foffs[nprob]) return;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (foffs[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    const BProb pb = probs[lo];
+    const int W = nt + tv;
+    const int64_t loc = idx - foffs[lo];
+    const int w = static_cast<int>(loc % W);
+    const int64_t lq = loc / W;
+    const int l = static_cast<int>(lq % 64);
+    const int64_t q = lq / 64;
+    const int64_t j = q * kHK + l / 16;
+    const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
+    F[idx] = (j < pb.n) ? V[(pb.row_off + j) * t + c] : 0.0f;
 }
 
 // ---------------------------------------------------------------- batched reductions
@@ -261,6 +318,21 @@ __global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg
             st.p[e] = r;
         }
     }
+}
+
+// Residual replacement: r = fl32(R64) for flagged (problem, column), p kept.
+__global__ __launch_bounds__(256) void bcg_replace_kernel(CgState st, const BSeg* __restrict__ segs, int t,
+                                                          const double* __restrict__ R64,
+                                                          const int* __restrict__ flag) {
+    const BSeg sg = segs[blockIdx.x];
+    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256)
+        if (flag[sg.b * t + static_cast<int>(e % t)]) st.r[e] = static_cast<float>(R64[e]);
+}
+
+__global__ void bcg_set_rr_kernel(CgState st, int T, const int* __restrict__ flag,
+                                  const double* __restrict__ rr_new) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < T && flag[q]) st.rr[q] = rr_new[q];
 }
 
 __global__ void bcg_init_kernel(CgState st, int T, double tol2) {
@@ -384,6 +456,9 @@ struct mfgp_batch_plan_s {
     std::vector<BSeg> segs;
     std::vector<int> seg_first;
     std::vector<int64_t> row_offs;   // prefix [nprob + 1]
+    std::vector<int64_t> frag_off;   // prefix [nprob + 1] of the MFMA fragments (floats)
+    int hyb_nt = 0, hyb_tv = 0;      // t = 16 nt + tv with an MFMA-contraction kernel
+    bool hybrid = false;
     // Capture stream (default priority, non-blocking): the caller's stream may
     // be the legacy NULL stream, which cannot be captured; the graph recorded
     // here is then launched on the caller's stream.
@@ -412,8 +487,9 @@ static void build_tiles(const mfgp_batch_plan_s& P, int64_t J, std::vector<BProb
         pb.d = P.kern[b].d;
         pb.rowblocks = static_cast<int>((pb.n + kBlock - 1) / kBlock);
         pb.chunks = static_cast<int>((pb.n + J - 1) / J);
-        pb.jchunk = (pb.n + pb.chunks - 1) / pb.chunks;
+        pb.jchunk = ((pb.n + pb.chunks - 1) / pb.chunks + kHK - 1) / kHK * kHK;
         pb.tile_base = base;
+        pb.f_off = P.frag_off[b];
         pb.s2 = op.s2;
         pb.sig2 = op.sig2;
         base += pb.rowblocks * pb.chunks;
@@ -453,6 +529,8 @@ struct BatchWs {
     double* R64; double* scal; int* ints; double* dpart; double* tmp; double* resid; char* part;
     BTile* queue; BProb* probs; BSeg* segs; int* seg_first; int64_t* row_offs; int* counter;
     int* logflag;
+    float* frag;      // MFMA fragments of the product's right-hand sides
+    int64_t* foffs;   // [nprob + 1] fragment offsets
     int cus;          // compute units of the device (host value)
 };
 
@@ -488,6 +566,8 @@ static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     w.row_offs = cv.take<int64_t>(P.nprob + 1);
     w.counter = cv.take<int>(64);
     w.logflag = cv.take<int>(64);
+    w.frag = cv.take<float>(P.frag_off.empty() ? 0 : P.frag_off.back());
+    w.foffs = cv.take<int64_t>(P.nprob + 1);
     return w;
 }
 
@@ -511,6 +591,38 @@ static hipError_t launch_bsweep_f(int tb, const BatchWs& w, int ntiles, const fl
         MFGP_TB_LIST(MFGP_C)
 #undef MFGP_C
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <int FAM>
+static hipError_t launch_bhyb_f(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, float* part,
+                                hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
+#define MFGP_HB(NTV, TVV)                                                                           \
+    if (P.hyb_nt == NTV && P.hyb_tv == TVV) {                                                       \
+        hipLaunchKernelGGL((batch_hyb_kernel<FAM, NTV, TVV>), dim3(grid), dim3(kBlock), 0, s, w.queue, \
+                           ntiles, w.counter, w.probs, w.U, w.frag, P.t, part);                     \
+        return hipGetLastError();                                                                   \
+    }
+    MFGP_HB(1, 0) MFGP_HB(1, 1) MFGP_HB(2, 0) MFGP_HB(2, 1)
+#undef MFGP_HB
+    return hipErrorInvalidValue;
+}
+
+// Pack the fragments of V for all problems, then run the persistent hybrid sweep.
+static hipError_t launch_bhyb(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, const float* V,
+                              float* part, hipStream_t s) {
+    const int64_t total = P.frag_off.back();
+    hipLaunchKernelGGL(batch_pack_hfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                       s, V, w.probs, w.foffs, P.nprob, P.t, P.hyb_nt, P.hyb_tv, w.frag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (P.family) {
+        case MFGP_RBF: return launch_bhyb_f<MFGP_RBF>(P, w, ntiles, part, s);
+        case MFGP_MATERN12: return launch_bhyb_f<MFGP_MATERN12>(P, w, ntiles, part, s);
+        case MFGP_MATERN32: return launch_bhyb_f<MFGP_MATERN32>(P, w, ntiles, part, s);
+        default: return launch_bhyb_f<MFGP_MATERN52>(P, w, ntiles, part, s);
     }
 }
 
@@ -555,7 +667,8 @@ static hipError_t launch_badj(int family, int tb, const BatchWs& w, int ntiles, 
 static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
                               const float* V, float* out, hipStream_t s) {
     void* tok = timing_begin(s);
-    hipError_t e = launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+    hipError_t e = P.hybrid ? launch_bhyb(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s)
+                            : launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
     if (e != hipSuccess) return e;
     double ent = 0.0, fl = 0.0;
     if (timing_on())
@@ -649,10 +762,13 @@ static int tune_tiles(mfgp_batch_plan_s& P, const BatchWs& w, const float* V, hi
         int ntiles = 0;
         int st = upload_tiles(P, w, J, ntiles, probs, queue, s);
         if (st != MFGP_OK) return st;
-        B_CHECK(launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s));  // warm
+        auto sweep = [&]() {
+            return P.hybrid ? launch_bhyb(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s)
+                            : launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+        };
+        B_CHECK(sweep());  // warm
         B_CHECK(hipEventRecord(a, s));
-        for (int r = 0; r < 2; ++r)
-            B_CHECK(launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s));
+        for (int r = 0; r < 2; ++r) B_CHECK(sweep());
         B_CHECK(hipEventRecord(b, s));
         B_CHECK(hipEventSynchronize(b));
         float ms = 0.0f;
@@ -750,6 +866,15 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
         acc_rows += P->n[b];
     }
     P->row_offs.push_back(acc_rows);
+    P->hybrid = hybrid_supported(t);
+    P->hyb_nt = t / 16;
+    P->hyb_tv = t % 16;
+    int64_t facc = 0;
+    for (int b = 0; b < P->nprob; ++b) {
+        P->frag_off.push_back(facc);
+        if (P->hybrid) facc += (P->n[b] + kHK - 1) / kHK * 64 * (P->hyb_nt + P->hyb_tv);
+    }
+    P->frag_off.push_back(facc);
     *plan = P;
     return MFGP_OK;
 }
@@ -804,6 +929,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     B_CHECK(hipMemcpyAsync(w.seg_first, P.seg_first.data(), P.seg_first.size() * sizeof(int),
                            hipMemcpyHostToDevice, s));
     B_CHECK(hipMemcpyAsync(w.row_offs, P.row_offs.data(), P.row_offs.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.foffs, P.frag_off.data(), P.frag_off.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     std::vector<Operator> ops(nprob);
     for (int b = 0; b < nprob; ++b) {
@@ -908,13 +1035,41 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     } while (0)
 
     std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
-    std::vector<double> h_relt(T), h_rr(T), h_b2(T);
+    std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T);
+    B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     for (;;) {
         B_CHECK2(hipMemcpyAsync(h_active.data(), st.active, T * sizeof(int), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
+        B_CHECK2(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipStreamSynchronize(s));
-        bool any = false;
-        for (int q = 0; q < T; ++q) any = any || (h_active[q] && h_iters[q] < max_iter);
+        // Residual replacement (as in the single-problem solver): a tenfold drop
+        // since the last true residual triggers it; active columns that fell at
+        // least 1.5x join; only problems with a flagged column recompute.
+        bool any = false, replace = false;
+        for (int q = 0; q < T; ++q) {
+            const bool act = h_active[q] && h_iters[q] < max_iter;
+            any = any || act;
+            replace = replace || (act && h_rr[q] <= 0.01 * h_rep[q]);
+            h_restart[q] = (act && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
+        }
+        if (replace) {
+            for (int b = 0; b < nprob; ++b) {
+                bool need = false;
+                for (int c = 0; c < t; ++c) need = need || h_restart[b * t + c];
+                if (!need) continue;
+                const int64_t o = P.row_off[b] * t;
+                B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
+            }
+            B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(bcg_replace_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
+                               w.segs, t, w.R64, restart);
+            B_CHECK2(bdots_ff(P, w, st.r, st.r, w.tmp + T, s));
+            hipLaunchKernelGGL(bcg_set_rr_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
+            B_CHECK2(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
+            B_CHECK2(hipStreamSynchronize(s));
+            for (int q = 0; q < T; ++q)
+                if (h_restart[q]) h_rep[q] = h_rr[q];
+        }
         if (any) {
             if (exec) {
                 B_CHECK2(hipGraphLaunch(exec, s));
@@ -952,6 +1107,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         B_CHECK2(bdots_ff(P, w, st.r, st.r, w.tmp + T, s));
         hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
         B_CHECK2(hipMemcpyAsync(w.logflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+        B_CHECK2(hipMemcpyAsync(h_rep.data(), w.tmp + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     cleanup();
     B_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
