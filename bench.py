@@ -17,6 +17,10 @@ python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x2] [--no-cpu-bas
 python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the step's
     dominant product, K_y V at t = 33, then a 1 GiB device copy whose FETCH_SIZE /
     WRITE_SIZE calibrate the HBM-traffic counters)
+python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ U{1..6},
+    ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
+python bench.py --mode rbf500k [--precision fp32|bf16x2]   (N = 500000, d = 2, RBF
+    l = 0.05, 16 probes: one MLL + gradient, FP32 or BF16-x2)
 """
 
 from __future__ import annotations
@@ -55,6 +59,72 @@ def cpu_baseline(w, rows: int) -> dict:
                       f"uses the reported threads"}
 
 
+def batch_leg(args) -> int:
+    """MLL + gradient of the 64-problem batch (one tuned persistent-launch call)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    probs = inputs.batch64(probes=16)
+    X = torch.from_numpy(np.concatenate([w.X.reshape(-1) for w in probs])).cuda()
+    y = torch.from_numpy(np.concatenate([w.y for w in probs])).cuda()
+    Z = torch.from_numpy(np.concatenate([w.Z for w in probs])).cuda()
+    plan = mfgp.BatchPlan([mfgp.Kernel(w.family, [float(v) for v in w.lengthscale], w.outputscale, w.noise)
+                           for w in probs], [w.n for w in probs], [w.d for w in probs], 16, tune=True)
+    print("[bench] batch warm-up call (tunes the tile length)", file=sys.stderr, flush=True)
+    plan.mll_and_grad(X, y, Z)
+    torch.cuda.synchronize()
+    mfgp.timing_enable(True)
+    t0 = time.perf_counter()
+    r = plan.mll_and_grad(X, y, Z)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ph = mfgp.timing_phases()
+    mfgp.timing_enable(False)
+    entries = sum(float(w.n) ** 2 for w in probs)
+    print(json.dumps({"mode": "batch", "workload": "batch64", "problems": len(probs),
+                      "rows": int(sum(w.n for w in probs)), "entries_per_product": entries,
+                      "mll_grad_s": el, "cg_s": ph["cg_ms"] * 1e-3, "slq_s": ph["slq_ms"] * 1e-3,
+                      "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"], "plan": plan.info(),
+                      "cg_iters_max": max(max(i["iters"] for i in inf) for inf in r["info"]),
+                      "rel_resid_true_max": max(max(i["rel_resid_true"] for i in inf) for inf in r["info"])}))
+    return 0
+
+
+def rbf500k_leg(args) -> int:
+    """One MLL + gradient on N = 500000 (16 probes), FP32 or BF16-x2, with solver progress."""
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    w = inputs.rbf500k()
+    kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
+    X = torch.from_numpy(w.X).cuda()
+    y = torch.from_numpy(w.y).cuda()
+    Z = torch.from_numpy(w.Z).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def progress(it, rr):
+        print(f"[bench] rbf500k {args.precision}: {it} iterations, worst recurrence residual {rr:.2e}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    mfgp.timing_enable(True)
+    r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=args.precision, progress=progress)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ph = mfgp.timing_phases()
+    allk = mfgp.timing_read(-1)
+    mfgp.timing_enable(False)
+    print(json.dumps({"mode": "rbf500k", "precision": args.precision, "n": w.n, "probes": 16,
+                      "mll_grad_s": el, "cg_s": ph["cg_ms"] * 1e-3, "slq_s": ph["slq_ms"] * 1e-3,
+                      "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"],
+                      "cg_iters_max": max(i["iters"] for i in r["info"]),
+                      "rel_resid_true_max": max(i["rel_resid_true"] for i in r["info"]),
+                      "entries_per_s": allk["entries"] / el, "mll": r["mll"], "logdet": r["logdet"],
+                      "grad": r["grad"]}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +133,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--mode", default="step", choices=["step", "kernel"])
+    ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k"])
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the single BF16-x2 comparison step")
     ap.add_argument("--reps", type=int, default=3)
@@ -79,6 +149,10 @@ def main() -> int:
     from paper_2605_17898_amd import inputs, mfgp
 
     torch.cuda.set_device(0)
+    if args.mode == "batch":
+        return batch_leg(args)
+    if args.mode == "rbf500k":
+        return rbf500k_leg(args)
     w = inputs.rbf100k()
     kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
     X = torch.from_numpy(w.X).cuda()
