@@ -21,6 +21,12 @@ python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ 
     ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
 python bench.py --mode rbf500k [--precision fp32|bf16x2]   (N = 500000, d = 2, RBF
     l = 0.05, 16 probes: one MLL + gradient, FP32 or BF16-x2)
+python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and 33 in
+    every precision, and N = 2k..50k at t = 1; HIP events around the whole call,
+    median of 5 after one warm-up)
+python bench.py --mode small   (end-to-end latency of the 1024-point RBF and the
+    20000-point Matern-5/2 workloads: solve, MLL + gradient, predictive mean; the
+    oracle's dense Cholesky route timed beside them)
 """
 
 from __future__ import annotations
@@ -125,6 +131,98 @@ def rbf500k_leg(args) -> int:
     return 0
 
 
+def _median_call_ms(fn, reps: int = 5) -> float:
+    """Median wall time of fn() bracketed by events on torch's current stream (one warm-up)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def matvec_leg(args) -> int:
+    """Entries/s of the whole K_y V call (prescale, packing, sweep, reduction)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    rows = []
+    full = inputs.rbf100k()
+    kern = mfgp.Kernel(full.family, full.lengthscale, full.outputscale, full.noise)
+    Xf = torch.from_numpy(full.X).cuda()
+    Vall = torch.from_numpy(np.concatenate([full.y[:, None], full.Z], axis=1)).cuda()
+    cases = [(full.n, t, prec) for t in (1, 33) for prec in ("fp32", "fp32_valu", "bf16x1", "bf16x2")]
+    cases += [(n, 1, "fp32") for n in (2000, 5000, 10000, 20000, 50000)]
+    for n, t, prec in cases:
+        X = Xf[:n].contiguous()
+        V = Vall[:n, :t].contiguous()
+        out = torch.empty_like(V)
+        ms = _median_call_ms(lambda: mfgp.kernel_matvec(kern, X, V, precision=prec, out=out))
+        rows.append({"n": n, "t": t, "precision": prec, "ms": ms, "entries_per_s": n * n / (ms * 1e-3),
+                     "rhs_products_per_s": n * n * t / (ms * 1e-3),
+                     "tflops": n * n * (3 * 4 + 1 + 2 * t) / (ms * 1e-3) / 1e12})
+        print(f"[bench] matvec n={n} t={t} {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "matvec", "workload": "rbf100k geometry (d=4, RBF l=0.3)", "rows": rows}))
+    return 0
+
+
+def small_leg(args) -> int:
+    """End-to-end latency at N = 1024 (RBF) and N = 20000 (Matern-5/2), oracle beside."""
+    import numpy as np
+    import torch
+
+    from oracle import gp
+    from paper_2605_17898_amd import inputs, mfgp
+    out = []
+    for name, w in (("exact1k", inputs.exact1k(probes=16)), ("matern20k", inputs.matern20k(probes=16))):
+        kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
+        X = torch.from_numpy(w.X).cuda()
+        y = torch.from_numpy(w.y).cuda()
+        Z = torch.from_numpy(w.Z).cuda()
+        Xs = torch.from_numpy(w.Xs).cuda() if w.Xs is not None else X
+        box = {}
+
+        def solve():
+            box["x"], box["info"] = mfgp.cg_solve(kern, X, y, tol=1e-6)
+
+        def mll():
+            box["m"] = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6)
+
+        def mean():
+            mfgp.predict_mean(kern, X, Xs, box["x"].float())
+
+        rec = {"workload": name, "n": w.n, "d": w.d, "family": w.family, "probes": int(Z.shape[1]),
+               "solve_ms": _median_call_ms(solve), "solve_iters": box["info"][0]["iters"],
+               "solve_rel_resid_true": box["info"][0]["rel_resid_true"],
+               "mll_grad_ms": _median_call_ms(mll), "predict_mean_ms": _median_call_ms(mean),
+               "test_points": int(Xs.shape[0])}
+        print(f"[bench] {name} GPU done; oracle", file=sys.stderr, flush=True)
+        k = gp.Kern(w.family, w.lengthscale, w.outputscale, w.noise)
+        t0 = time.perf_counter()
+        ch = gp.cholesky(k, w.X)
+        alpha = gp.solve(k, w.X, w.y, chol=ch)
+        ld = gp.logdet(k, w.X, chol=ch)
+        rec["oracle_solve_logdet_s"] = time.perf_counter() - t0
+        rec["oracle_route"] = "FP64 dense K_y, Cholesky, two triangular solves, log-det"
+        rec["alpha_rel_err_vs_oracle"] = float(np.linalg.norm(box["x"].cpu().numpy().ravel() - alpha) /
+                                               np.linalg.norm(alpha))
+        rec["logdet_oracle"] = float(ld)
+        rec["logdet_slq"] = box["m"]["logdet"]
+        out.append(rec)
+        print(f"[bench] {name} oracle done", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "small", "rows": out}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +231,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k"])
+    ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k", "matvec", "small"])
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the single BF16-x2 comparison step")
     ap.add_argument("--reps", type=int, default=3)
@@ -153,6 +251,10 @@ def main() -> int:
         return batch_leg(args)
     if args.mode == "rbf500k":
         return rbf500k_leg(args)
+    if args.mode == "matvec":
+        return matvec_leg(args)
+    if args.mode == "small":
+        return small_leg(args)
     w = inputs.rbf100k()
     kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
     X = torch.from_numpy(w.X).cuda()
