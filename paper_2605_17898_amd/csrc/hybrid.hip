@@ -80,14 +80,15 @@ template <int FAM, int D>
 static hipError_t hyb_fd(int nt, int tv, const float* Ur, const float* Uc, const float* F, int64_t m,
                          int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
-#define MFGP_H(NTV, TVV)                                                                          \
+#define MFGP_HYB_CASE(NTV, TVV)                                                                   \
     if (nt == NTV && tv == TVV) {                                                                 \
         hipLaunchKernelGGL((sweep_hyb_kernel<FAM, D, NTV, TVV>), grid, dim3(kBlock), 0, s, Ur, Uc, \
                            F, m, n, t, p.chunks, p.jchunk, partial);                              \
         return hipGetLastError();                                                                 \
     }
-    MFGP_H(1, 0) MFGP_H(1, 1) MFGP_H(2, 0) MFGP_H(2, 1) MFGP_H(3, 0) MFGP_H(3, 1) MFGP_H(4, 0) MFGP_H(4, 1)
-#undef MFGP_H
+    MFGP_HYB_CASE(1, 0) MFGP_HYB_CASE(1, 1) MFGP_HYB_CASE(2, 0) MFGP_HYB_CASE(2, 1)
+    MFGP_HYB_CASE(3, 0) MFGP_HYB_CASE(3, 1) MFGP_HYB_CASE(4, 0) MFGP_HYB_CASE(4, 1)
+#undef MFGP_HYB_CASE
     return hipErrorInvalidValue;
 }
 
