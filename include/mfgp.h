@@ -243,7 +243,14 @@ typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
 /* Creates a plan for batches of this shape with p = num_probes probes
  * (t = p + 1 columns, which must be one of 1..8, 16, 17, 32, 33).  tune: 1 =
  * time the candidate tile lengths on the first mfgp_batch_mll_and_grad call,
- * 0 = use the built-in default.  use_graph: capture CG iterations.  Host only. */
+ * 0 = use the built-in default.  use_graph: capture CG iterations.  max_iter 0
+ * selects min(max(2 max_b n_b, 64), 20000).  Host only: it validates before
+ * touching the device.  Errors: MFGP_ERR_ARG for a NULL pointer, nprob < 1,
+ * num_probes < 1, max_iter < 0, n_b < 1, d_b outside 1..MFGP_MAX_D, a family
+ * differing from kern[0].family, a non-finite or non-positive lengthscale,
+ * outputscale or noise, a negative offset, or row_off that is not the prefix
+ * sum of n (rows must be packed back to back in problem order);
+ * MFGP_UNSUPPORTED for a column count without a compiled kernel. */
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
                            int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
 int mfgp_batch_plan_destroy(mfgp_batch_plan plan);
