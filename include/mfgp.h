@@ -265,8 +265,10 @@ int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sw
  * gradient exactly as mfgp_mll_and_grad defines them, computed for the whole
  * batch at once.  Host outputs: mll [nprob], logdet [nprob] (optional), grad
  * (optional, problem b's n_theta entries packed one problem after another),
- * info (optional, [nprob][p+1]).  opts->precision must be MFGP_FP32.
- * Synchronises.  Returns the worst status over all problems. */
+ * info (optional, [nprob][p+1]).  opts->precision must be MFGP_FP32;
+ * opts->progress, if set, reports the largest iteration count and the worst
+ * recurrence residual over the whole batch.  Synchronises.  Returns the
+ * worst status over all problems. */
 int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
                             const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
                             mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream);

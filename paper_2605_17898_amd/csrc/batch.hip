@@ -1037,6 +1037,9 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
     std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T);
     B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
+    int next_report = report_every;
     for (;;) {
         B_CHECK2(hipMemcpyAsync(h_active.data(), st.active, T * sizeof(int), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1069,6 +1072,18 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
             B_CHECK2(hipStreamSynchronize(s));
             for (int q = 0; q < T; ++q)
                 if (h_restart[q]) h_rep[q] = h_rr[q];
+        }
+        if (opts->progress) {
+            int itmax = 0;
+            double worst = 0.0;
+            for (int q = 0; q < T; ++q) {
+                itmax = std::max(itmax, h_iters[q]);
+                if (h_b2[q] > 0.0) worst = std::max(worst, std::sqrt(h_rr[q] / h_b2[q]));
+            }
+            if (itmax >= next_report) {
+                opts->progress(opts->progress_user, itmax, worst);
+                while (next_report <= itmax) next_report += report_every;
+            }
         }
         if (any) {
             if (exec) {

@@ -416,12 +416,12 @@ class BatchPlan:
 
     def mll_and_grad(self, X: torch.Tensor, y: torch.Tensor, Z: Optional[torch.Tensor] = None,
                      tol: float = 1e-6, probe_seed: int = 0, want_grad: bool = True,
-                     allow=(OK, NOT_CONVERGED, BREAKDOWN)) -> dict:
+                     allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None) -> dict:
         _dev(X, torch.float32, "X")
         _dev(y, torch.float32, "y")
         if Z is not None:
             _dev(Z, torch.float32, "Z")
-        o = cg_opts(tol, self.max_iter, 0, -1, "fp32", False, probe_seed)
+        o = cg_opts(tol, self.max_iter, 0, -1, "fp32", False, probe_seed, progress=progress)
         mll = (C.c_double * self.nprob)()
         ld = (C.c_double * self.nprob)()
         grad = (C.c_double * sum(self.nparams))() if want_grad else None
