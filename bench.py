@@ -42,6 +42,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (packed FP32 FMA)
+# HBM bytes per launch of the FP32 step's dominant kernel (RBF, d = 4, t = 33,
+# N = 100000), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy's
+# reading of the same counters (summary in profiles/).  Valid only for the
+# kernel named below; None for any other.
+HYB_TRAFFIC_BYTES = 2.660e8
+HYB_KERNEL = "sweep_hyb_kernel<RBF, d=4, NT=2, TV=1>"
 METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
 
 
@@ -346,9 +352,10 @@ def main() -> int:
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
-            "kernel": ("sweep_hyb_kernel<RBF, d=4, NT=2, TV=1> (FP32 entries on the VALU, "
-                       "contraction on v_mfma_f32_16x16x4_f32)") if args.precision == "fp32" else "mfma sweep",
+            "traffic": HYB_TRAFFIC_BYTES if args.precision == "fp32" else None,
+            "traffic_unit": "bytes per launch",
+            "kernel": (HYB_KERNEL + " (FP32 entries on the VALU, contraction on "
+                       "v_mfma_f32_16x16x4_f32)") if args.precision == "fp32" else "mfma sweep",
             "flop_per_entry": 3 * 4 + 1 + 2 * 33,
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
         },

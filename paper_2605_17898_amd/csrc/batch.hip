@@ -320,13 +320,19 @@ __global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg
     }
 }
 
-// Residual replacement: r = fl32(R64) for flagged (problem, column), p kept.
+// Residual replacement for flagged (problem, column): r_new = fl32(R64) and
+// p += r_new - r_old, i.e. p = r_new + beta p_prev (as in the single-problem
+// solver: the direction must be formed from the residual it is paired with).
 __global__ __launch_bounds__(256) void bcg_replace_kernel(CgState st, const BSeg* __restrict__ segs, int t,
                                                           const double* __restrict__ R64,
                                                           const int* __restrict__ flag) {
     const BSeg sg = segs[blockIdx.x];
     for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256)
-        if (flag[sg.b * t + static_cast<int>(e % t)]) st.r[e] = static_cast<float>(R64[e]);
+        if (flag[sg.b * t + static_cast<int>(e % t)]) {
+            const float rn = static_cast<float>(R64[e]);
+            st.p[e] += rn - st.r[e];
+            st.r[e] = rn;
+        }
 }
 
 __global__ void bcg_set_rr_kernel(CgState st, int T, const int* __restrict__ flag,

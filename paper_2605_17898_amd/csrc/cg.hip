@@ -14,11 +14,13 @@
 // accumulation (X is FP64), and columns above tolerance restart from it
 // (iterative refinement).  While iterating, a column whose recurrence
 // residual has fallen tenfold since its last true residual has r replaced by
-// the recomputed true residual, its search direction kept (residual
-// replacement, van der Vorst & Ye 2000): this bounds the drift between the
-// recurrence and the true residual that an inexact product (FP32, and more so
-// the BF16 forms) causes, without discarding the Krylov space as a restart does.  The FP64 solution is what lets the recomputed
-// residual reach 1e-6: an FP32-rounded solution alone floors at a few 1e-6.
+// the recomputed true residual (residual replacement, van der Vorst & Ye
+// 2000), and its direction re-formed from it: p = r_new + beta p_prev.  This
+// bounds the drift between the recurrence and the true residual that an
+// inexact product (FP32, and more so the BF16 forms) causes, without
+// discarding the Krylov space as a restart does.  The FP64 solution is what
+// lets the recomputed residual reach 1e-6: an FP32-rounded solution alone
+// floors at a few 1e-6.
 #include "cg.hpp"
 
 #include <algorithm>

@@ -196,12 +196,21 @@ __global__ void cg_restart_kernel(CgState st, const double* __restrict__ R64, in
     st.p[idx] = r;
 }
 
-// Residual replacement: r = fl32(R64) for flagged columns, search direction kept.
+// Residual replacement for flagged columns: r_new = fl32(R64).  The direction
+// was already formed from the old residual, p = r_old + beta p_prev; it is
+// rebuilt as p = r_new + beta p_prev (p += r_new - r_old), so that the next
+// step length rr/(p^T A p) stays consistent with r_new^T p = r_new^T r_new.
+// Keeping p while swapping r makes that step wrong by as much as the
+// recurrence had drifted from the true residual, which can diverge.
 __global__ void cg_replace_kernel(CgState st, const double* __restrict__ R64, int64_t total, int t,
                                   const int* __restrict__ flag) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    if (flag[idx % t]) st.r[idx] = static_cast<float>(R64[idx]);
+    if (flag[idx % t]) {
+        const float rn = static_cast<float>(R64[idx]);
+        st.p[idx] += rn - st.r[idx];
+        st.r[idx] = rn;
+    }
 }
 
 __global__ void cg_set_rr_kernel(CgState st, int t, const int* __restrict__ flag,

@@ -128,8 +128,12 @@ def test_batch64_full_with_tuning(mf):
     banner("batch64 full size, 16 probes, autotuned tiles")
     probs = inputs.batch64(probes=16)
     X, y, Z = pack(probs)
-    plan = plan_for(mf, probs, 16, tune=True)
-    r = plan.mll_and_grad(X, y, Z, tol=1e-6)
+    plan = plan_for(mf, probs, 16, tune=True, max_iter=8000)
+
+    def progress(it, rr):
+        print(f"batch64: {it} iterations, worst recurrence residual {rr:.2e}", flush=True)
+
+    r = plan.mll_and_grad(X, y, Z, tol=1e-6, progress=progress)
     info = plan.info()
     print("plan:", info, "status", r["status"])
     assert r["status"] == mf.OK
