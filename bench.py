@@ -13,13 +13,13 @@ time, the MLL+grad time, the roofline of the dominant kernel (the FP32
 entry sweep, timed live with HIP events on its launch stream) and the
 oracle's host throughput on a bounded sample.
 
-python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x2] [--no-cpu-baseline]
+python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x1|bf16x2|bf16x3] [--no-cpu-baseline]
 python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the step's
     dominant product, K_y V at t = 33, then a 1 GiB device copy whose FETCH_SIZE /
     WRITE_SIZE calibrate the HBM-traffic counters)
 python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ U{1..6},
     ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
-python bench.py --mode rbf500k [--precision fp32|bf16x2]   (N = 500000, d = 2, RBF
+python bench.py --mode rbf500k [--precision fp32|bf16x2|bf16x3]   (N = 500000, d = 2, RBF
     l = 0.05, 16 probes: one MLL + gradient, FP32 or BF16-x2)
 python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and 33 in
     every precision, and N = 2k..50k at t = 1; HIP events around the whole call,
@@ -166,7 +166,7 @@ def matvec_leg(args) -> int:
     kern = mfgp.Kernel(full.family, full.lengthscale, full.outputscale, full.noise)
     Xf = torch.from_numpy(full.X).cuda()
     Vall = torch.from_numpy(np.concatenate([full.y[:, None], full.Z], axis=1)).cuda()
-    cases = [(full.n, t, prec) for t in (1, 33) for prec in ("fp32", "fp32_valu", "bf16x1", "bf16x2")]
+    cases = [(full.n, t, prec) for t in (1, 33) for prec in ("fp32", "fp32_valu", "bf16x1", "bf16x2", "bf16x3")]
     cases += [(n, 1, "fp32") for n in (2000, 5000, 10000, 20000, 50000)]
     for n, t, prec in cases:
         X = Xf[:n].contiguous()
@@ -234,7 +234,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k", "matvec", "small"])
@@ -361,33 +361,35 @@ def main() -> int:
         },
     }
     if args.precision == "fp32" and not args.no_compare:
-        # The same step with the K-tile x V contraction in BF16-x2 on MFMA (FP32
-        # entries, FP64-accumulated residual refinement to the same 1e-6).
-        print("[bench] bf16x2 comparison step", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        mfgp.timing_enable(True)
-        t1 = time.perf_counter()
-        rb = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision="bf16x2", want_alpha=True)
-        mfgp.predict_mean(kern, X, Xs, rb["alpha"].float())
-        torch.cuda.synchronize()
-        eb = time.perf_counter() - t1
-        ab = mfgp.timing_read(-1)
-        mb = mfgp.timing_read(mfgp.SWEEP_MFMA)
-        phb = mfgp.timing_phases()
-        mfgp.timing_enable(False)
-        line["bf16x2"] = {
-            "ms_per_step": eb * 1e3,
-            "entries_per_s": ab["entries"] / eb,
-            "cg_solve_s": phb["cg_ms"] * 1e-3,
-            "mll_grad_s": (phb["cg_ms"] + phb["slq_ms"] + phb["adjoint_ms"]) * 1e-3,
-            "cg_iters_max": max(i["iters"] for i in rb["info"]),
-            "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
-            "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
-            "mfma_sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
-            "mfma_sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
-            "mll": rb["mll"],
-            "logdet": rb["logdet"],
-        }
+        # The same step with the K-tile x V contraction on the bf16 matrix cores
+        # (FP32 entries, FP64-accumulated residual replacement and refinement to
+        # the same 1e-6): the hi/lo split (x2) and the exact three-way split (x3).
+        for form in ("bf16x2", "bf16x3"):
+            print(f"[bench] {form} comparison step", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            mfgp.timing_enable(True)
+            t1 = time.perf_counter()
+            rb = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=form, want_alpha=True)
+            mfgp.predict_mean(kern, X, Xs, rb["alpha"].float())
+            torch.cuda.synchronize()
+            eb = time.perf_counter() - t1
+            ab = mfgp.timing_read(-1)
+            mb = mfgp.timing_read(mfgp.SWEEP_MFMA)
+            phb = mfgp.timing_phases()
+            mfgp.timing_enable(False)
+            line[form] = {
+                "ms_per_step": eb * 1e3,
+                "entries_per_s": ab["entries"] / eb,
+                "cg_solve_s": phb["cg_ms"] * 1e-3,
+                "mll_grad_s": (phb["cg_ms"] + phb["slq_ms"] + phb["adjoint_ms"]) * 1e-3,
+                "cg_iters_max": max(i["iters"] for i in rb["info"]),
+                "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
+                "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
+                "mfma_sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
+                "mfma_sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
+                "mll": rb["mll"],
+                "logdet": rb["logdet"],
+            }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)

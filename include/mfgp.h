@@ -63,11 +63,16 @@ typedef enum {
     MFGP_FP32 = 0,    /* FP32 vector ALU, FP32 accumulation                        */
     MFGP_BF16X1 = 1,  /* entries and V rounded to bf16, MFMA, FP32 accumulation    */
     MFGP_BF16X2 = 2,  /* bf16 hi/lo split of both operands (3 MFMA products)        */
-    MFGP_FP32_VALU = 3 /* FP32 with the contraction kept on the vector ALU; MFGP_FP32
+    MFGP_FP32_VALU = 3, /* FP32 with the contraction kept on the vector ALU; MFGP_FP32
                           itself moves 16-column tiles of the contraction onto FP32
                           MFMA (v_mfma_f32_16x16x4_f32) when t = 16 k or 16 k + 1,
                           k = 1..4                                                    */
+    MFGP_BF16X3 = 4    /* exact three-way bf16 split of both operands, 6 of the 9
+                          MFMA products (the dropped ones are < 2^-23 |K V|):
+                          binary32-class products on the bf16 matrix cores        */
 } mfgp_precision;
+/* The bf16 forms take t <= 65 columns; for t = 32 k + 1 column 0 (y of a
+ * [y, probes] block) is contracted on the vector ALU in FP32. */
 
 typedef enum {
     MFGP_OK = 0,

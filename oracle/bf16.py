@@ -13,7 +13,15 @@ to bfloat16 and the products are accumulated exactly:
     x2 :  sum_j [bf(k_ij) bf(v_j) + bf(k_ij) bf(v_j - bf(v_j)) + bf(k_ij - bf(k_ij)) bf(v_j)]
 
 (hi/lo split: a = hi + lo with hi = bf(a), lo = bf(a - hi); the lo*lo term is
-dropped).  LightGP itself is float32 only (Sec. 5, "Limitations"); these forms
+dropped), and with a three-way split a = h + m + l (h = bf(a), m = bf(a - h),
+l = bf(a - h - m); each difference is exact in binary32, and h + m + l equals
+a exactly for normal binary32 values, since each bfloat16 piece with its sign
+carries 8 significant bits of the 24):
+
+    x3 :  sum_j [hh + hm + mh + hl + lh + mm]   (products of the pieces of k and v)
+
+The three dropped products (ml, lm, ll) are below 2^-23 of |k v|, so x3 is as
+accurate as a binary32 product.  LightGP itself is float32 only (Sec. 5, "Limitations"); these forms
 are the precision extension and are judged by the end-to-end residual.
 """
 
@@ -48,3 +56,19 @@ def tile_product_x2(K32: np.ndarray, V32: np.ndarray) -> np.ndarray:
     vh, vl = split_bf16(V32)
     kh, kl, vh, vl = (x.astype(np.float64) for x in (kh, kl, vh, vl))
     return kh @ vh + kh @ vl + kl @ vh
+
+
+def split3_bf16(a):
+    """h = bf(a), m = bf(a - h), l = bf(a - h - m), differences in float32."""
+    a = np.asarray(a, dtype=np.float32)
+    h = round_bf16(a)
+    r = (a - h).astype(np.float32)
+    m = round_bf16(r)
+    l = round_bf16((r - m).astype(np.float32))
+    return h, m, l
+
+
+def tile_product_x3(K32: np.ndarray, V32: np.ndarray) -> np.ndarray:
+    kh, km, kl = (x.astype(np.float64) for x in split3_bf16(K32))
+    vh, vm, vl = (x.astype(np.float64) for x in split3_bf16(V32))
+    return kh @ vh + kh @ vm + km @ vh + kh @ vl + kl @ vh + km @ vm

@@ -23,6 +23,11 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     # no packed FP32 (v_pk_*_f32) anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: with AGPR accumulators the compiler
+    # copied them between the two register files inside the sweep loops
+    # (about 20 of 120 VALU slots per step), and on gfx950 every VALU slot adds
+    # to the sweep time because the FP32 MFMA pipe does not overlap the VALU.
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 

@@ -90,14 +90,15 @@ static int check_opts(const mfgp_cg_opts* o) {
     if (!o) return MFGP_ERR_ARG;
     if (!std::isfinite(o->tol) || !(o->tol > 0.0)) return MFGP_ERR_ARG;
     if (o->max_iter < 0) return MFGP_ERR_ARG;
-    if (o->precision < MFGP_FP32 || o->precision > MFGP_FP32_VALU) return MFGP_ERR_ARG;
+    if (o->precision < MFGP_FP32 || o->precision > MFGP_BF16X3) return MFGP_ERR_ARG;
     if (!precision_supported(o->precision)) return MFGP_UNSUPPORTED;
     return MFGP_OK;
 }
 
 // The BF16-MFMA sweeps hold at most two 32-column tiles.
 static int check_precision_cols(int precision, int t) {
-    if ((precision == MFGP_BF16X1 || precision == MFGP_BF16X2) && t > 64) return MFGP_UNSUPPORTED;
+    if ((precision == MFGP_BF16X1 || precision == MFGP_BF16X2 || precision == MFGP_BF16X3) && t > 65)
+        return MFGP_UNSUPPORTED;
     return MFGP_OK;
 }
 
@@ -248,7 +249,7 @@ int mfgp_num_params(const mfgp_kernel* k) {
 size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
                             int32_t max_iter) {
     if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1) return 0;
-    if (precision < MFGP_FP32 || precision > MFGP_FP32_VALU) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return 0;
     Carver cv(nullptr);
     switch (op) {
         case MFGP_OP_MATVEC: carve_matvec(cv, n, d, t, precision); break;
@@ -274,7 +275,7 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !V || !KV || !ws || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
-    if (precision < MFGP_FP32 || precision > MFGP_FP32_VALU) return MFGP_ERR_ARG;
+    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return MFGP_ERR_ARG;
     if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
     if ((st = check_precision_cols(precision, t)) != MFGP_OK) return st;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, precision, 0))

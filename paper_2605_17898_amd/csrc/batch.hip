@@ -320,19 +320,25 @@ __global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg
     }
 }
 
-// Residual replacement for flagged (problem, column): r_new = fl32(R64) and
-// p += r_new - r_old, i.e. p = r_new + beta p_prev (as in the single-problem
-// solver: the direction must be formed from the residual it is paired with).
+// Residual replacement per (problem, column), as in the single-problem
+// solver: flag 1 sets r = fl32(R64) and p += r_new - r_old (the direction
+// re-formed from the replaced residual); flag 2 (true residual more than twice
+// the recurrence one) restarts the direction, p = r_new, and stops the
+// column's Lanczos log.
 __global__ __launch_bounds__(256) void bcg_replace_kernel(CgState st, const BSeg* __restrict__ segs, int t,
                                                           const double* __restrict__ R64,
                                                           const int* __restrict__ flag) {
     const BSeg sg = segs[blockIdx.x];
-    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256)
-        if (flag[sg.b * t + static_cast<int>(e % t)]) {
+    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256) {
+        const int q = sg.b * t + static_cast<int>(e % t);
+        const int f = flag[q];
+        if (f) {
             const float rn = static_cast<float>(R64[e]);
-            st.p[e] += rn - st.r[e];
+            st.p[e] = f == 2 ? rn : st.p[e] + (rn - st.r[e]);
             st.r[e] = rn;
+            if (f == 2) st.logon[q] = 0;   // same value from every thread of the column
         }
+    }
 }
 
 __global__ void bcg_set_rr_kernel(CgState st, int T, const int* __restrict__ flag,
@@ -349,6 +355,7 @@ __global__ void bcg_init_kernel(CgState st, int T, double tol2) {
     st.status[q] = finite ? MFGP_OK : MFGP_BREAKDOWN;
     st.iters[q] = 0;
     st.lanlen[q] = 0;
+    st.logon[q] = 1;
     st.alpha[q] = 0.0;
     st.beta[q] = 0.0;
 }
@@ -377,7 +384,7 @@ __global__ void bcg_beta_kernel(CgState st, int T, const double* __restrict__ rr
     double b = 0.0;
     if (st.active[q]) {
         b = rrn / st.rr[q];
-        if (*log_coeffs && st.lanlen[q] < max_iter) {
+        if (*log_coeffs && st.logon[q] && st.lanlen[q] < max_iter) {
             double* cf = st.coeff + (static_cast<int64_t>(q) * max_iter + st.lanlen[q]) * 2;
             cf[0] = st.alpha[q];
             cf[1] = b;
@@ -987,6 +994,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     st.status = w.ints + T;
     st.iters = w.ints + 2 * T;
     st.lanlen = w.ints + 3 * T;
+    st.logon = w.ints + 5 * T;
     st.coeff = w.coeff;
     int* restart = w.ints + 4 * T;
 
@@ -1069,6 +1077,12 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                 const int64_t o = P.row_off[b] * t;
                 B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
             }
+            // true residual norms of the recomputed problems (others are not read)
+            B_CHECK2(bdots_dd(P, w, w.R64, w.R64, w.tmp, s));
+            B_CHECK2(hipMemcpyAsync(h_relt.data(), w.tmp, T * sizeof(double), hipMemcpyDeviceToHost, s));
+            B_CHECK2(hipStreamSynchronize(s));
+            for (int q = 0; q < T; ++q)
+                if (h_restart[q] && !(h_relt[q] <= 4.0 * h_rr[q])) h_restart[q] = 2;
             B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(bcg_replace_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
                                w.segs, t, w.R64, restart);

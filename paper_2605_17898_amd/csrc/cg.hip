@@ -37,6 +37,7 @@ __global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
         st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
         st.iters[c] = 0;
         st.lanlen[c] = 0;
+        st.logon[c] = 1;
         st.alpha[c] = 0.0;
         st.beta[c] = 0.0;
     }
@@ -76,6 +77,7 @@ static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
     st.status = b.ints + t;
     st.iters = b.ints + 2 * t;
     st.lanlen = b.ints + 3 * t;
+    st.logon = b.ints + 5 * t;
     st.coeff = coeff;
     return st;
 }
@@ -105,7 +107,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     int check_every = o.check_every;
     if (check_every <= 0) {
         const double work = static_cast<double>(n) * static_cast<double>(n) * t;
-        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 16);
+        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
     }
     CgState st = make_state(b, X, t, coeff);
     double* tmp = b.scal + 5 * t;     // [t] scratch scalars
@@ -151,6 +153,13 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         }
         if (replace) {
             CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+            // true residual norms: a column whose true residual exceeds twice
+            // the recurrence one restarts its direction instead
+            CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
+            CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_CHECK(hipStreamSynchronize(s));
+            for (int c = 0; c < t; ++c)
+                if (h_flag[c] && !(h_relt[c] <= 4.0 * h_rr[c])) h_flag[c] = 2;
             CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
             CG_CHECK(cg_replace(st, b.R64, n, t, restart, b.dots, tmp, s));
             CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));

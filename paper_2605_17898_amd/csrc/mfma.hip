@@ -6,6 +6,9 @@
 //
 //   x1:  acc += bf(K) bf(V)
 //   x2:  acc += bf(K) bf(V) + bf(K) lo(V) + lo(K) bf(V),  lo(a) = bf(a - bf(a))
+//   x3:  a = h + m + l exactly (h = bf(a), m = bf(a - h), l = bf(a - h - m));
+//        acc += hh + hm + mh + hl + lh + mm over the pieces of K and V, which
+//        drops only terms below 2^-23 |K V|: binary32-class products.
 //
 // Operand layout of v_mfma_f32_32x32x16_bf16 (one wave, 64 lanes): lane l
 // holds A[l % 32][8 (l / 32) + q] and B[8 (l / 32) + q][l % 32] for q = 0..7,
@@ -16,7 +19,11 @@
 // same block -> (row block, j-chunk) split and partial-sum reduction as the
 // FP32 sweeps).  V is converted once per product into "B fragments": for
 // j-tile jt and column tile ct, lane l's 8 bf16 values contiguous (16 bytes),
-// so a fragment is one 16-byte load per lane.
+// so a fragment is one 16-byte load per lane.  When t = 32 k + 1 (the
+// [y, probes] blocks with 32 k probes) column 0 stays on the VALU in FP32
+// (one FMA per entry) and the probes fill k whole column tiles.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "sweep_kernels.hpp"
 
@@ -28,41 +35,53 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 constexpr int kRT = 2;      // row tiles (of 32 rows) per wave
 constexpr int kJT = 16;     // j per MFMA step
 
-bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_FP32_VALU; }
+bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_BF16X3; }
 
-static inline int col_tiles(int t) { return (t + 31) / 32; }
+// Column 0 on the VALU when the rest fills whole 32-column tiles.
+static inline int vec_cols(int t) { return (t > 1 && t % 32 == 1) ? 1 : 0; }
+static inline int col_tiles(int t) { return (t - vec_cols(t) + 31) / 32; }
+static inline int split_of(int precision) {
+    return precision == MFGP_BF16X3 ? 2 : (precision == MFGP_BF16X2 ? 1 : 0);
+}
 
-// Vb[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + 8(l/32) + q][ct*32 + l%32]
-// (hi part, and lo part in Vlo when split); zero outside [n) x [t).
-__global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t, int nt_tiles,
-                                  int64_t njt, int split, bf16x8* __restrict__ Vhi,
-                                  bf16x8* __restrict__ Vlo) {
+// Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + 8(l/32) + q][tv + ct*32 + l%32]
+// (the first piece; Vm and Vl the second and third when split); zero outside
+// [n) x [t).  With tv = 1, Vy[j] = V[j][0] in FP32 (zero for j >= n).
+__global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t, int tv, int nt_tiles,
+                                  int64_t njt, int split, bf16x8* __restrict__ Vh,
+                                  bf16x8* __restrict__ Vm, bf16x8* __restrict__ Vl,
+                                  float* __restrict__ Vy) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t total = njt * nt_tiles * 64;
+    if (tv && idx < njt * kJT) Vy[idx] = idx < n ? V[idx * t] : 0.0f;
     if (idx >= total) return;
     const int l = static_cast<int>(idx % 64);
     const int64_t f = idx / 64;
     const int ct = static_cast<int>(f % nt_tiles);
     const int64_t jt = f / nt_tiles;
-    const int c = ct * 32 + (l % 32);
-    bf16x8 hi, lo;
+    const int c = tv + ct * 32 + (l % 32);
+    bf16x8 h8, m8, l8;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int64_t j = jt * kJT + 8 * (l / 32) + q;
         const float v = (j < n && c < t) ? V[j * t + c] : 0.0f;
         const __bf16 h = static_cast<__bf16>(v);
-        hi[q] = h;
-        lo[q] = static_cast<__bf16>(v - static_cast<float>(h));
+        const float r = v - static_cast<float>(h);
+        const __bf16 mm = static_cast<__bf16>(r);
+        h8[q] = h;
+        m8[q] = mm;
+        l8[q] = static_cast<__bf16>(r - static_cast<float>(mm));
     }
-    Vhi[idx] = hi;
-    if (split) Vlo[idx] = lo;
+    Vh[idx] = h8;
+    if (split >= 1) Vm[idx] = m8;
+    if (split >= 2) Vl[idx] = l8;
 }
 
-template <int FAM, int D, int NT, int SPLIT>
+template <int FAM, int D, int NT, int SPLIT, int TV>
 __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
-    const float* __restrict__ Ur, const float* __restrict__ Uc, const bf16x8* __restrict__ Vhi,
-    const bf16x8* __restrict__ Vlo, int64_t m, int64_t n, int t, int chunks, int64_t jchunk,
-    float* __restrict__ partial) {
+    const float* __restrict__ Ur, const float* __restrict__ Uc, const bf16x8* __restrict__ Vh,
+    const bf16x8* __restrict__ Vm, const bf16x8* __restrict__ Vl, const float* __restrict__ Vy,
+    int64_t m, int64_t n, int t, int chunks, int64_t jchunk, float* __restrict__ partial) {
     int rb, ch;
     map_block(blockIdx.x, chunks, rb, ch);
     const int lane = threadIdx.x & 63;
@@ -80,12 +99,15 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
         for (int k = 0; k < D; ++k) ui[r][k] = Ur[i * D + k];
     }
     f32x16 acc[kRT][NT];
+    float sv[kRT];
 #pragma unroll
-    for (int r = 0; r < kRT; ++r)
+    for (int r = 0; r < kRT; ++r) {
+        sv[r] = 0.0f;
 #pragma unroll
         for (int c = 0; c < NT; ++c)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
+    }
 
     const int64_t j0 = static_cast<int64_t>(ch) * jchunk;       // multiple of 16
     int64_t j1 = j0 + jchunk;
@@ -93,11 +115,17 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
     j1 = j1 < npad ? j1 : npad;
     for (int64_t jb = j0; jb < j1; jb += kJT) {
         const int64_t jt = jb / kJT;
-        bf16x8 bh[NT], bl[NT];
+        bf16x8 bh[NT], bm[NT], bl[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            bh[c] = Vhi[(jt * NT + c) * 64 + lane];
-            if (SPLIT) bl[c] = Vlo[(jt * NT + c) * 64 + lane];
+            bh[c] = Vh[(jt * NT + c) * 64 + lane];
+            if (SPLIT >= 1) bm[c] = Vm[(jt * NT + c) * 64 + lane];
+            if (SPLIT >= 2) bl[c] = Vl[(jt * NT + c) * 64 + lane];
+        }
+        float y8[8];
+        if (TV) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) y8[q] = Vy[jb + 8 * half + q];
         }
         // u_j of this lane's 8 j's (clamped: padded j carry V = 0)
         float uj[8][D];
@@ -110,30 +138,42 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
         }
 #pragma unroll
         for (int r = 0; r < kRT; ++r) {
-            bf16x8 ah, al;
+            bf16x8 ah, am, al;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const float e = kentry<FAM>(sqdist<D>(ui[r], uj[q]));
+                if (TV) sv[r] = fmaf(e, y8[q], sv[r]);
                 const __bf16 h = static_cast<__bf16>(e);
                 ah[q] = h;
-                if (SPLIT) al[q] = static_cast<__bf16>(e - static_cast<float>(h));
+                if (SPLIT >= 1) {
+                    const float rm = e - static_cast<float>(h);
+                    const __bf16 mm = static_cast<__bf16>(rm);
+                    am[q] = mm;
+                    if (SPLIT >= 2) al[q] = static_cast<__bf16>(rm - static_cast<float>(mm));
+                }
             }
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
-                acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[c], acc[r][c], 0, 0, 0);
-                if (SPLIT) {
+                // smallest terms first
+                if (SPLIT >= 2) {
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm[c], acc[r][c], 0, 0, 0);
                     acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[c], acc[r][c], 0, 0, 0);
                     acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[c], acc[r][c], 0, 0, 0);
                 }
+                if (SPLIT >= 1) {
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm[c], acc[r][c], 0, 0, 0);
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh[c], acc[r][c], 0, 0, 0);
+                }
+                acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[c], acc[r][c], 0, 0, 0);
             }
         }
     }
     // C layout: register q of lane l -> row 8(q/4) + 4(l/32) + q%4, column l%32.
 #pragma unroll
-    for (int r = 0; r < kRT; ++r)
+    for (int r = 0; r < kRT; ++r) {
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            const int col = c * 32 + (lane & 31);
+            const int col = TV + c * 32 + (lane & 31);
             if (col >= t) continue;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -141,6 +181,13 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
                 if (i < m) partial[(static_cast<int64_t>(ch) * m + i) * t + col] = acc[r][c][q];
             }
         }
+        if (TV) {
+            // VALU column: the two lane halves hold the two 8-j halves of row l % 32
+            const float v = sv[r] + __shfl_xor(sv[r], 32, 64);
+            const int64_t i = row0 + r * 32 + row_in_tile;
+            if (half == 0 && i < m) partial[(static_cast<int64_t>(ch) * m + i) * t] = v;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -152,45 +199,50 @@ static SweepPlan plan_mfma(int64_t m, int64_t n) {
     return p;
 }
 
-size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
-    if (t > 64) t = 64;
+// Scratch: three fragment arrays (one per split piece), the FP32 column-0
+// copy, and the split-j partial sums.
+static void mfma_layout(int64_t m, int64_t n, int t, size_t& frag, size_t& ybytes, size_t& part) {
     const SweepPlan p = plan_mfma(m, n);
     const int64_t njt = (n + kJT - 1) / kJT;
-    const size_t frag = static_cast<size_t>(njt) * col_tiles(t) * 64 * sizeof(bf16x8);
-    const size_t part = static_cast<size_t>(p.chunks) * m * t * sizeof(float);
+    frag = (static_cast<size_t>(njt) * col_tiles(t) * 64 * sizeof(bf16x8) + 255) / 256 * 256;
+    ybytes = (static_cast<size_t>(njt) * kJT * sizeof(float) + 255) / 256 * 256;
+    part = static_cast<size_t>(p.chunks) * m * t * sizeof(float);
+}
+
+size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
+    if (t > 65) t = 65;
+    size_t frag, ybytes, part;
+    mfma_layout(m, n, t, frag, ybytes, part);
     (void)precision;
-    return 2 * frag + part + 4096;
+    return 3 * frag + ybytes + part + 4096;
 }
 
 template <int FAM, int D>
-static hipError_t mfma_fd(int nt, int split, const float* Ur, const float* Uc, const bf16x8* Vhi,
-                          const bf16x8* Vlo, int64_t m, int64_t n, int t, const SweepPlan& p,
-                          float* partial, hipStream_t s) {
+static hipError_t mfma_fd(int nt, int split, int tv, const float* Ur, const float* Uc, const bf16x8* Vh,
+                          const bf16x8* Vm, const bf16x8* Vl, const float* Vy, int64_t m, int64_t n, int t,
+                          const SweepPlan& p, float* partial, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
-#define MFGP_MF(NTV, SPV)                                                                          \
-    if (nt == NTV && split == SPV) {                                                               \
-        hipLaunchKernelGGL((sweep_mfma_kernel<FAM, D, NTV, SPV>), grid, dim3(kBlock), 0, s, Ur, Uc, \
-                           Vhi, Vlo, m, n, t, p.chunks, p.jchunk, partial);                        \
-        return hipGetLastError();                                                                  \
+#define MFGP_MF(NTV, SPV, TVV)                                                                          \
+    if (nt == NTV && split == SPV && tv == TVV) {                                                       \
+        hipLaunchKernelGGL((sweep_mfma_kernel<FAM, D, NTV, SPV, TVV>), grid, dim3(kBlock), 0, s, Ur, Uc, \
+                           Vh, Vm, Vl, Vy, m, n, t, p.chunks, p.jchunk, partial);                       \
+        return hipGetLastError();                                                                       \
     }
-    MFGP_MF(1, 0) MFGP_MF(1, 1) MFGP_MF(2, 0) MFGP_MF(2, 1)
+    MFGP_MF(1, 0, 0) MFGP_MF(1, 1, 0) MFGP_MF(1, 2, 0) MFGP_MF(2, 0, 0) MFGP_MF(2, 1, 0) MFGP_MF(2, 2, 0)
+    MFGP_MF(1, 0, 1) MFGP_MF(1, 1, 1) MFGP_MF(1, 2, 1) MFGP_MF(2, 0, 1) MFGP_MF(2, 1, 1) MFGP_MF(2, 2, 1)
 #undef MFGP_MF
     return hipErrorInvalidValue;
 }
 
 template <int FAM>
-static hipError_t mfma_f(int D, int nt, int split, const float* Ur, const float* Uc,
-                         const bf16x8* Vhi, const bf16x8* Vlo, int64_t m, int64_t n, int t,
-                         const SweepPlan& p, float* partial, hipStream_t s) {
+static hipError_t mfma_f(int D, int nt, int split, int tv, const float* Ur, const float* Uc,
+                         const bf16x8* Vh, const bf16x8* Vm, const bf16x8* Vl, const float* Vy, int64_t m,
+                         int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
     switch (D) {
-        case 1: return mfma_fd<FAM, 1>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 2: return mfma_fd<FAM, 2>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 3: return mfma_fd<FAM, 3>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 4: return mfma_fd<FAM, 4>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 5: return mfma_fd<FAM, 5>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 6: return mfma_fd<FAM, 6>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 7: return mfma_fd<FAM, 7>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
-        case 8: return mfma_fd<FAM, 8>(nt, split, Ur, Uc, Vhi, Vlo, m, n, t, p, partial, s);
+#define MFGP_MD(DV) \
+        case DV: return mfma_fd<FAM, DV>(nt, split, tv, Ur, Uc, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+        MFGP_MD(1) MFGP_MD(2) MFGP_MD(3) MFGP_MD(4) MFGP_MD(5) MFGP_MD(6) MFGP_MD(7) MFGP_MD(8)
+#undef MFGP_MD
         default: return hipErrorInvalidValue;
     }
 }
@@ -201,28 +253,41 @@ hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, f
 hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
                       float* out, bool with_noise, const float* Vself, int precision,
                       void* scratch, hipStream_t s) {
-    if (t > 64) return hipErrorNotSupported;
+    if (t > 65) return hipErrorNotSupported;
+    const int tv = vec_cols(t);
     const int nt = col_tiles(t);
-    const int split = precision == MFGP_BF16X2 ? 1 : 0;
+    if (nt < 1 || nt > 2) return hipErrorNotSupported;
+    const int split = split_of(precision);
     const int64_t n = op.n;
     const int64_t njt = (n + kJT - 1) / kJT;
     const SweepPlan p = plan_mfma(m, n);
+    size_t frag, ybytes, part;
+    mfma_layout(m, n, t, frag, ybytes, part);
     char* base = static_cast<char*>(scratch);
-    const size_t frag = static_cast<size_t>(njt) * nt * 64 * sizeof(bf16x8);
-    bf16x8* Vhi = reinterpret_cast<bf16x8*>(base);
-    bf16x8* Vlo = reinterpret_cast<bf16x8*>(base + frag);
-    float* partial = reinterpret_cast<float*>(base + 2 * frag);
-    const int64_t total = njt * nt * 64;
+    bf16x8* Vh = reinterpret_cast<bf16x8*>(base);
+    bf16x8* Vm = reinterpret_cast<bf16x8*>(base + frag);
+    bf16x8* Vl = reinterpret_cast<bf16x8*>(base + 2 * frag);
+    float* Vy = reinterpret_cast<float*>(base + 3 * frag);
+    float* partial = reinterpret_cast<float*>(base + 3 * frag + ybytes);
+    const int64_t total = std::max<int64_t>(njt * nt * 64, njt * kJT);
     hipLaunchKernelGGL(pack_vfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
-                       0, s, V, n, t, nt, njt, split, Vhi, Vlo);
+                       0, s, V, n, t, tv, nt, njt, split, Vh, Vm, Vl, Vy);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* tok = timing_begin(s);
     switch (op.family) {
-        case MFGP_RBF: e = mfma_f<MFGP_RBF>(op.d, nt, split, Ur, op.U, Vhi, Vlo, m, n, t, p, partial, s); break;
-        case MFGP_MATERN12: e = mfma_f<MFGP_MATERN12>(op.d, nt, split, Ur, op.U, Vhi, Vlo, m, n, t, p, partial, s); break;
-        case MFGP_MATERN32: e = mfma_f<MFGP_MATERN32>(op.d, nt, split, Ur, op.U, Vhi, Vlo, m, n, t, p, partial, s); break;
-        default: e = mfma_f<MFGP_MATERN52>(op.d, nt, split, Ur, op.U, Vhi, Vlo, m, n, t, p, partial, s); break;
+        case MFGP_RBF:
+            e = mfma_f<MFGP_RBF>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+            break;
+        case MFGP_MATERN12:
+            e = mfma_f<MFGP_MATERN12>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+            break;
+        case MFGP_MATERN32:
+            e = mfma_f<MFGP_MATERN32>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+            break;
+        default:
+            e = mfma_f<MFGP_MATERN52>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+            break;
     }
     {
         const double ent = static_cast<double>(m) * static_cast<double>(n);

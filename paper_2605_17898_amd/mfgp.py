@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libmfgp.so")
 
 MAX_D = 8
 FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3}
-PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3}
+PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
 OP_MATVEC, OP_CG, OP_PREDICT, OP_MLL, OP_ADJOINT, OP_RESIDUAL = range(6)
 

@@ -13,6 +13,9 @@ bf16) is held to the oracle's x1 model within 1e-4 (the two differ only where
 an FP32 entry sits on a bf16 rounding tie) and reported against the exact
 product.  Solves in x2 with FP32-entry FP64
 residual refinement must reach the same 1e-6 recomputed residual as FP32.
+x3 (exact three-way split, six products) is held to the FP32 bar itself,
+1e-5 against the exact product.  For t = 32 k + 1 column 0 is contracted in
+FP32 on the vector ALU, so the models treat it as the FP32-entry product.
 """
 
 import numpy as np
@@ -48,11 +51,16 @@ def test_x2_matvec_vs_oracle(mf, family, t):
 def x2_model(k, X, V, rows=None, block=512):
     """Oracle model of the x2 product with the noise term, optionally on sampled rows."""
     rows = np.arange(X.shape[0]) if rows is None else rows
-    out = np.empty((len(rows), V.shape[1]))
+    t = V.shape[1]
+    vec0 = t > 1 and t % 32 == 1
+    out = np.empty((len(rows), t))
     for b in range(0, len(rows), block):
         rb = rows[b:b + block]
         K32 = gp.kernel_matrix(k, X[rb], X).astype(np.float32)
         out[b:b + block] = bf16.tile_product_x2(K32, V) + k.noise * V[rb].astype(np.float64)
+        if vec0:
+            out[b:b + block, 0] = K32.astype(np.float64) @ V[:, 0].astype(np.float64) + \
+                k.noise * V[rb, 0].astype(np.float64)
     return out
 
 
@@ -134,6 +142,55 @@ def test_x1_cg_reports_status(mf):
 def test_bf16_rejects_wide_blocks(mf):
     banner("bf16 column limit")
     w = inputs.exact1k(n=300)
-    V = inputs.gaussian_rhs(1, w.n, 65)
-    with pytest.raises(mf.MfgpError):
-        mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x2")
+    V = inputs.gaussian_rhs(1, w.n, 66)
+    for form in ("bf16x1", "bf16x2", "bf16x3"):
+        with pytest.raises(mf.MfgpError):
+            mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision=form)
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+@pytest.mark.parametrize("t", [1, 5, 17, 32, 33, 64, 65])
+def test_x3_matvec_meets_fp32_bar(mf, family, t):
+    banner(f"bf16x3 matvec family={family} t={t} n=1537 d=3")
+    w = inputs.random_problem(131 + t, 1537, 3, family, ard=True, noise=0.01)
+    V = inputs.gaussian_rhs(t + 7, w.n, t)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x3"))
+    ref = gp.ky_matvec(okern(w), w.X, V)
+    assert col_rel_err(out, ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 8])
+def test_x3_dims_ragged_and_special(mf, d):
+    banner(f"bf16x3 matvec rbf d={d} n=1001, ones and smooth right-hand sides")
+    w = inputs.random_problem(200 + d, 1001, d, "rbf", ard=True, noise=0.02)
+    V = np.concatenate([np.ones((w.n, 1), np.float32), np.sin(3.0 * w.X[:, :1]),
+                        inputs.gaussian_rhs(d, w.n, 31)], axis=1).astype(np.float32)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x3"))
+    assert col_rel_err(out, gp.ky_matvec(okern(w), w.X, V)).max() <= 1e-5
+
+
+def test_x3_full_rbf100k_sampled_rows(mf):
+    banner("bf16x3 matvec rbf100k full size t=33, 1024 sampled rows")
+    w = inputs.rbf100k()
+    V = np.concatenate([w.y[:, None], w.Z], axis=1)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x3"))
+    rows = np.random.default_rng(9).choice(w.n, size=1024, replace=False)
+    assert col_rel_err(out[rows], gp.ky_matvec_rows(okern(w), w.X, V, rows)).max() <= 1e-5
+
+
+def test_x3_cg_and_mll(mf):
+    banner("bf16x3 CG and mll+grad exact1k p=16 vs oracle")
+    from oracle import krylov
+    w = inputs.exact1k(probes=16)
+    k = okern(w)
+    B = np.concatenate([w.y[:, None], w.Z], axis=1)
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(B), tol=1e-6, precision="bf16x3")
+    assert st == mf.OK, info
+    assert max(i["rel_resid_true"] for i in info) <= 1e-6
+    assert col_rel_err(host(x), gp.solve(k, w.X, B)).max() <= 1e-4
+    r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6, precision="bf16x3")
+    assert r["status"] == mf.OK
+    ld = float(krylov.quadform_log(gp.ky_matrix(k, w.X), w.Z).mean())
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    g = gp.same_probe_grad(k, w.X, w.y, w.Z)
+    assert np.linalg.norm(np.array(r["grad"]) - g) / np.linalg.norm(g) <= 1e-3

@@ -325,3 +325,34 @@ def test_bf16_rounding():
     np.testing.assert_array_equal(bf16.round_bf16(a), lib)
     hi, lo = bf16.split_bf16(a)
     assert np.all(np.abs(a - hi - lo) <= np.abs(a) * 2.0 ** -15)
+
+
+def test_bf16_three_way_split_is_exact():
+    # Normal binary32 values over 52 binades: h + m + l reproduces a exactly,
+    # each piece is a bfloat16 value, and the pieces shrink by >= 2^8.
+    rng = np.random.default_rng(4)
+    a = (rng.standard_normal(200000) * np.exp(rng.uniform(-18, 18, 200000))).astype(np.float32)
+    h, m, l = bf16.split3_bf16(a)
+    for x in (h, m, l):
+        np.testing.assert_array_equal(bf16.round_bf16(x), x)
+    np.testing.assert_array_equal(h.astype(np.float64) + m + l, a.astype(np.float64))
+    assert np.all(np.abs(m) <= np.abs(h) * 2.0 ** -8)
+    assert np.all(np.abs(l) <= np.abs(m) * 2.0 ** -8)
+    # 1 + 2^-8 + 2^-16 + 2^-23 (24 significant bits) splits as 1 + 2^-8 + (2^-16 + 2^-23)
+    v = np.float32(1.0 + 2.0 ** -9 + 2.0 ** -17 + 2.0 ** -23)
+    hv, mv, lv = bf16.split3_bf16(np.array([v]))
+    assert float(hv[0]) + float(mv[0]) + float(lv[0]) == float(v)
+
+
+def test_bf16_x3_tile_product_is_binary32_accurate():
+    # The six-product x3 model is within a few binary32 roundings of the exact
+    # product; x2 is not (its pieces keep 16 bits).
+    rng = np.random.default_rng(5)
+    K = rng.uniform(0, 1, (64, 512)).astype(np.float32)
+    V = rng.standard_normal((512, 8)).astype(np.float32)
+    exact = K.astype(np.float64) @ V.astype(np.float64)
+    absk = np.abs(K).astype(np.float64) @ np.abs(V).astype(np.float64)
+    e3 = np.abs(bf16.tile_product_x3(K, V) - exact) / absk
+    e2 = np.abs(bf16.tile_product_x2(K, V) - exact) / absk
+    assert e3.max() <= 2.0 ** -26     # measured 2^-29.8 here
+    assert e2.max() > 2.0 ** -24      # measured 2^-20.4 here
