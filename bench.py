@@ -20,7 +20,7 @@ python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the 
 python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ U{1..6},
     ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
 python bench.py --mode rbf500k [--precision fp32|bf16x2|bf16x3]   (N = 500000, d = 2, RBF
-    l = 0.05, 16 probes: one MLL + gradient, FP32 or BF16-x2)
+    l = 0.05, 16 probes: one MLL + gradient in the chosen precision)
 python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and 33 in
     every precision, and N = 2k..50k at t = 1; HIP events around the whole call,
     median of 5 after one warm-up)
@@ -83,12 +83,16 @@ def batch_leg(args) -> int:
     Z = torch.from_numpy(np.concatenate([w.Z for w in probs])).cuda()
     plan = mfgp.BatchPlan([mfgp.Kernel(w.family, [float(v) for v in w.lengthscale], w.outputscale, w.noise)
                            for w in probs], [w.n for w in probs], [w.d for w in probs], 16, tune=True)
+    def progress(it, rr):
+        print(f"[bench] batch64: {it} iterations, worst recurrence residual {rr:.2e}",
+              file=sys.stderr, flush=True)
+
     print("[bench] batch warm-up call (tunes the tile length)", file=sys.stderr, flush=True)
-    plan.mll_and_grad(X, y, Z)
+    plan.mll_and_grad(X, y, Z, progress=progress)
     torch.cuda.synchronize()
     mfgp.timing_enable(True)
     t0 = time.perf_counter()
-    r = plan.mll_and_grad(X, y, Z)
+    r = plan.mll_and_grad(X, y, Z, progress=progress)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ph = mfgp.timing_phases()

@@ -53,6 +53,9 @@ struct BSeg {
 };
 
 constexpr int kSegRows = 2048;
+// Residual replacement keeps the direction only while |r_true - r_rec|^2 <=
+// 0.01 |r_true|^2 (as in the single-problem solver).
+constexpr double kMaxDrift2 = 0.01;
 constexpr int kWidth = MFGP_MAX_D + 1;   // adjoint partial width
 
 // ---------------------------------------------------------------- persistent kernels
@@ -320,25 +323,19 @@ __global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg
     }
 }
 
-// Residual replacement per (problem, column), as in the single-problem
-// solver: flag 1 sets r = fl32(R64) and p += r_new - r_old (the direction
-// re-formed from the replaced residual); flag 2 (true residual more than twice
-// the recurrence one) restarts the direction, p = r_new, and stops the
-// column's Lanczos log.
+// Residual replacement for flagged (problem, column), as in the single-problem
+// solver: r = fl32(R64) and p += r_new - r_old (the direction re-formed from
+// the replaced residual); only columns with small drift are flagged.
 __global__ __launch_bounds__(256) void bcg_replace_kernel(CgState st, const BSeg* __restrict__ segs, int t,
                                                           const double* __restrict__ R64,
                                                           const int* __restrict__ flag) {
     const BSeg sg = segs[blockIdx.x];
-    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256) {
-        const int q = sg.b * t + static_cast<int>(e % t);
-        const int f = flag[q];
-        if (f) {
+    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256)
+        if (flag[sg.b * t + static_cast<int>(e % t)]) {
             const float rn = static_cast<float>(R64[e]);
-            st.p[e] = f == 2 ? rn : st.p[e] + (rn - st.r[e]);
+            st.p[e] += rn - st.r[e];
             st.r[e] = rn;
-            if (f == 2) st.logon[q] = 0;   // same value from every thread of the column
         }
-    }
 }
 
 __global__ void bcg_set_rr_kernel(CgState st, int T, const int* __restrict__ flag,
@@ -355,7 +352,6 @@ __global__ void bcg_init_kernel(CgState st, int T, double tol2) {
     st.status[q] = finite ? MFGP_OK : MFGP_BREAKDOWN;
     st.iters[q] = 0;
     st.lanlen[q] = 0;
-    st.logon[q] = 1;
     st.alpha[q] = 0.0;
     st.beta[q] = 0.0;
 }
@@ -384,7 +380,7 @@ __global__ void bcg_beta_kernel(CgState st, int T, const double* __restrict__ rr
     double b = 0.0;
     if (st.active[q]) {
         b = rrn / st.rr[q];
-        if (*log_coeffs && st.logon[q] && st.lanlen[q] < max_iter) {
+        if (*log_coeffs && st.lanlen[q] < max_iter) {
             double* cf = st.coeff + (static_cast<int64_t>(q) * max_iter + st.lanlen[q]) * 2;
             cf[0] = st.alpha[q];
             cf[1] = b;
@@ -994,7 +990,6 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     st.status = w.ints + T;
     st.iters = w.ints + 2 * T;
     st.lanlen = w.ints + 3 * T;
-    st.logon = w.ints + 5 * T;
     st.coeff = w.coeff;
     int* restart = w.ints + 4 * T;
 
@@ -1049,7 +1044,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     } while (0)
 
     std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
-    std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T);
+    std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T), h_cross(T);
+    std::vector<int> h_norepl(T, 0);
     B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
     const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
@@ -1066,8 +1062,9 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         for (int q = 0; q < T; ++q) {
             const bool act = h_active[q] && h_iters[q] < max_iter;
             any = any || act;
-            replace = replace || (act && h_rr[q] <= 0.01 * h_rep[q]);
-            h_restart[q] = (act && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
+            const bool can = act && !h_norepl[q];
+            replace = replace || (can && h_rr[q] <= 0.01 * h_rep[q]);
+            h_restart[q] = (can && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
         }
         if (replace) {
             for (int b = 0; b < nprob; ++b) {
@@ -1077,12 +1074,21 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                 const int64_t o = P.row_off[b] * t;
                 B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
             }
-            // true residual norms of the recomputed problems (others are not read)
+            // drift of the recomputed problems (others are not read):
+            // |r_true - r_rec|^2 = |r_true|^2 + |r_rec|^2 - 2 r_true^T r_rec
             B_CHECK2(bdots_dd(P, w, w.R64, w.R64, w.tmp, s));
+            B_CHECK2(bdots_df(P, w, w.R64, st.r, w.tmp + 2 * T, s));
             B_CHECK2(hipMemcpyAsync(h_relt.data(), w.tmp, T * sizeof(double), hipMemcpyDeviceToHost, s));
+            B_CHECK2(hipMemcpyAsync(h_cross.data(), w.tmp + 2 * T, T * sizeof(double), hipMemcpyDeviceToHost, s));
             B_CHECK2(hipStreamSynchronize(s));
-            for (int q = 0; q < T; ++q)
-                if (h_restart[q] && !(h_relt[q] <= 4.0 * h_rr[q])) h_restart[q] = 2;
+            for (int q = 0; q < T; ++q) {
+                if (!h_restart[q]) continue;
+                const double drift2 = h_relt[q] + h_rr[q] - 2.0 * h_cross[q];
+                if (!(drift2 <= kMaxDrift2 * h_relt[q])) {
+                    h_restart[q] = 0;     // run this cycle out and refine instead
+                    h_norepl[q] = 1;
+                }
+            }
             B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(bcg_replace_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
                                w.segs, t, w.R64, restart);
@@ -1143,6 +1149,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
         B_CHECK2(hipMemcpyAsync(w.logflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
         B_CHECK2(hipMemcpyAsync(h_rep.data(), w.tmp + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
+        for (int q = 0; q < T; ++q)
+            if (h_restart[q]) h_norepl[q] = 0;   // a fresh cycle starts without drift
     }
     cleanup();
     B_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -18,7 +18,10 @@
 // 2000), and its direction re-formed from it: p = r_new + beta p_prev.  This
 // bounds the drift between the recurrence and the true residual that an
 // inexact product (FP32, and more so the BF16 forms) causes, without
-// discarding the Krylov space as a restart does.  The FP64 solution is what
+// discarding the Krylov space as a restart does.  It is only sound while the
+// drift is small: a column whose recurrence has moved more than 10% away from
+// its true residual (very ill-conditioned operators, where FP32 drift grows
+// by about eps * cond per step) is left to finish its cycle and is refined.  The FP64 solution is what
 // lets the recomputed residual reach 1e-6: an FP32-rounded solution alone
 // floors at a few 1e-6.
 #include "cg.hpp"
@@ -29,6 +32,10 @@
 
 namespace mfgp {
 
+// Residual replacement keeps the direction only while the recurrence residual
+// is within 10% of the true one: |r_true - r_rec|^2 <= 0.01 |r_true|^2.
+constexpr double kMaxDrift2 = 0.01;
+
 __global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
         const bool finite = isfinite(st.bnorm2[c]) && isfinite(st.rr[c]);
@@ -37,7 +44,6 @@ __global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
         st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
         st.iters[c] = 0;
         st.lanlen[c] = 0;
-        st.logon[c] = 1;
         st.alpha[c] = 0.0;
         st.beta[c] = 0.0;
     }
@@ -77,7 +83,6 @@ static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
     st.status = b.ints + t;
     st.iters = b.ints + 2 * t;
     st.lanlen = b.ints + 3 * t;
-    st.logon = b.ints + 5 * t;
     st.coeff = coeff;
     return st;
 }
@@ -129,7 +134,8 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
     std::vector<double> h_relt(t), h_rr(t), h_b2(t), h_rep(t, 0.0);
-    std::vector<int> h_flag(t, 0);
+    std::vector<int> h_flag(t, 0), h_norepl(t, 0);
+    std::vector<double> h_cross(t);
     int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
     CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -148,18 +154,26 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         for (int c = 0; c < t; ++c) {
             const bool act = h_active[c] && h_iters[c] < max_iter;
             any = any || act;
-            replace = replace || (act && h_rr[c] <= 0.01 * h_rep[c]);
-            h_flag[c] = (act && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
+            const bool can = act && !h_norepl[c];
+            replace = replace || (can && h_rr[c] <= 0.01 * h_rep[c]);
+            h_flag[c] = (can && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
         }
         if (replace) {
             CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
-            // true residual norms: a column whose true residual exceeds twice
-            // the recurrence one restarts its direction instead
+            // drift d = r_true - r_rec: |d|^2 = |r_true|^2 + |r_rec|^2 - 2 r_true^T r_rec
             CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
+            CG_CHECK(col_dots_df(b.R64, st.r, n, t, tmp + t, b.dots, s));
             CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_CHECK(hipMemcpyAsync(h_cross.data(), tmp + t, t * sizeof(double), hipMemcpyDeviceToHost, s));
             CG_CHECK(hipStreamSynchronize(s));
-            for (int c = 0; c < t; ++c)
-                if (h_flag[c] && !(h_relt[c] <= 4.0 * h_rr[c])) h_flag[c] = 2;
+            for (int c = 0; c < t; ++c) {
+                if (!h_flag[c]) continue;
+                const double drift2 = h_relt[c] + h_rr[c] - 2.0 * h_cross[c];
+                if (!(drift2 <= kMaxDrift2 * h_relt[c])) {
+                    h_flag[c] = 0;          // the recurrence has left the true residual:
+                    h_norepl[c] = 1;        // run this cycle out and refine instead
+                }
+            }
             CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
             CG_CHECK(cg_replace(st, b.R64, n, t, restart, b.dots, tmp, s));
             CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -212,6 +226,8 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(col_dots_ff(st.r, st.r, n, t, tmp, b.dots, s));
         CG_CHECK(cg_activate(st, t, restart, tmp, s));
         CG_CHECK(hipMemcpyAsync(h_rep.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        for (int c = 0; c < t; ++c)
+            if (h_restart[c]) h_norepl[c] = 0;   // a fresh cycle starts without drift
         log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
     }
 

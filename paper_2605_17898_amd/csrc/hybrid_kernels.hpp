@@ -57,9 +57,24 @@ __device__ __forceinline__ void hyb_block(const float* __restrict__ Ur, const fl
     j1 = j1 < npad ? j1 : npad;
     const int64_t q0 = j0 / kHK;
     const int64_t nst = j0 < j1 ? (j1 - j0) / kHK : 0;     // MFMA steps of this chunk
+    // Steps whose four j are all < n need no clamping; at most the last step
+    // of the last chunk is ragged.
+    const int64_t qfull = n / kHK;
+    int64_t nfull = qfull - q0;
+    nfull = nfull < 0 ? 0 : (nfull < nst ? nfull : nst);
 
-    // Operands of one step: this lane's fragment of V and u_j (j = 4 q + grp).
+    // Operands of one step: this lane's fragment of V and u_j (j = 4 q + grp),
+    // addressed as a wave-uniform base plus a fixed per-lane offset.
     auto load_step = [&](int64_t st, float (&f)[W], float (&u)[D]) {
+        const int64_t q = q0 + st;
+        const float* Fq = F + q * (64 * W);
+#pragma unroll
+        for (int w = 0; w < W; ++w) f[w] = Fq[lane * W + w];
+        const float* Uq = Uc + q * (kHK * D);
+#pragma unroll
+        for (int k = 0; k < D; ++k) u[k] = Uq[grp * D + k];
+    };
+    auto load_step_clamped = [&](int64_t st, float (&f)[W], float (&u)[D]) {
         const int64_t q = q0 + st;
 #pragma unroll
         for (int w = 0; w < W; ++w) f[w] = F[(q * 64 + lane) * W + w];
@@ -100,16 +115,23 @@ __device__ __forceinline__ void hyb_block(const float* __restrict__ Ur, const fl
     // Ping-pong over two operand sets: the loads of one step are in flight
     // while the other step's entries and MFMAs run.
     float fa[W], ua[D], fb[W], ub[D];
-    if (nst > 0) load_step(0, fa, ua);
+    if (nfull > 0) load_step(0, fa, ua);
     int64_t st = 0;
-    for (; st + 1 < nst; st += 2) {
+    for (; st + 1 < nfull; st += 2) {
         load_step(st + 1, fb, ub);
         compute_step(fa, ua);
-        load_step(st + 2 < nst ? st + 2 : nst - 1, fa, ua);
+        load_step(st + 2 < nfull ? st + 2 : nfull - 1, fa, ua);
         compute_step(fb, ub);
         if (((st + 2) & (kSeg / kHK - 1)) == 0) flush();
     }
-    if (st < nst) compute_step(fa, ua);
+    if (st < nfull) {
+        compute_step(fa, ua);
+        ++st;
+    }
+    for (; st < nst; ++st) {     // the ragged tail (at most one step)
+        load_step_clamped(st, fa, ua);
+        compute_step(fa, ua);
+    }
 #pragma unroll
     for (int r = 0; r < kHRT; ++r) {
         // MFMA columns: register qq of lane l -> row 4 (l/16) + qq, column l % 16

@@ -155,7 +155,7 @@ __global__ void cg_beta_kernel(CgState st, int t, const double* __restrict__ rrn
         double b = 0.0;
         if (st.active[c]) {
             b = rrn / st.rr[c];
-            if (log_coeffs && st.coeff && st.logon[c] && st.lanlen[c] < max_iter) {
+            if (log_coeffs && st.coeff && st.lanlen[c] < max_iter) {
                 double* cf = st.coeff + (static_cast<int64_t>(c) * max_iter + st.lanlen[c]) * 2;
                 cf[0] = st.alpha[c];
                 cf[1] = b;
@@ -196,25 +196,19 @@ __global__ void cg_restart_kernel(CgState st, const double* __restrict__ R64, in
     st.p[idx] = r;
 }
 
-// Residual replacement, per column: flag 1 replaces r by r_new = fl32(R64)
-// and re-forms the direction, which was built from the old residual
-// (p = r_old + beta p_prev), as p = r_new + beta p_prev (p += r_new - r_old),
-// so the next step length rr / p^T A p stays consistent.  That holds while the
-// drift r_new - r_old is small next to r_new; flag 2 (the host saw the true
-// residual exceed twice the recurrence one) restarts the direction, p = r_new,
-// and the column's Lanczos log stops, since its Krylov recurrence no longer
-// describes the operator.
+// Residual replacement for flagged columns: r_new = fl32(R64).  The direction
+// was already formed from the old residual (p = r_old + beta p_prev); it is
+// re-formed as p = r_new + beta p_prev (p += r_new - r_old), so that the next
+// step length rr / p^T A p matches r_new.  The host flags only columns whose
+// recurrence still agrees with the true residual (small drift).
 __global__ void cg_replace_kernel(CgState st, const double* __restrict__ R64, int64_t total, int t,
                                   const int* __restrict__ flag) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const int c = static_cast<int>(idx % t);
-    const int f = flag[c];
-    if (f) {
+    if (flag[idx % t]) {
         const float rn = static_cast<float>(R64[idx]);
-        st.p[idx] = f == 2 ? rn : st.p[idx] + (rn - st.r[idx]);
+        st.p[idx] += rn - st.r[idx];
         st.r[idx] = rn;
-        if (f == 2) st.logon[c] = 0;   // same value from every thread of the column
     }
 }
 

@@ -21,7 +21,6 @@ struct CgState {
     int* status;      // [t] mfgp_status
     int* iters;       // [t] iterations done
     int* lanlen;      // [t] logged Lanczos length
-    int* logon;       // [t] 1 while the column's (alpha, beta) are logged
     double* coeff;    // [t][max_iter][2] (alpha, beta) log, may be null
 };
 

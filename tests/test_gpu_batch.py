@@ -62,7 +62,10 @@ def test_batch_matches_single_and_oracle(mf):
     for b, w in enumerate(probs):
         assert max(i["rel_resid_true"] for i in r["info"][b]) <= 1e-6
         s = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6)
-        assert r["mll"][b] == pytest.approx(s["mll"], rel=1e-6, abs=1e-6)
+        # The batch and the single solver take the same steps except where
+        # residual replacement fires (a trigger anywhere in the batch lets every
+        # column that fell 1.5x join), so their SLQ tridiagonals differ slightly.
+        assert r["mll"][b] == pytest.approx(s["mll"], rel=1e-5, abs=1e-6)
         np.testing.assert_allclose(r["grad"][b], s["grad"], rtol=1e-4, atol=1e-6 * np.abs(s["grad"]).max())
         if w.n >= 64:
             k = okern(w)
