@@ -134,6 +134,9 @@ typedef struct {
     double rel_resid_recurrence;  /* ||r_k||/||b|| carried by the recurrence at exit        */
     double rel_resid_true;        /* recomputed ||b - K_y x||/||b||, K_y with FP32 entries,
                                      FP64 accumulation, x in FP64                          */
+    int32_t replacements;         /* residual replacements applied (small drift only)       */
+    int32_t drift_skips;          /* replacements refused because the recurrence had
+                                     drifted more than 1% from the true residual            */
 } mfgp_cg_info;
 
 /* Bytes of workspace a call needs.  op: mfgp_op; n rows; d dims; t columns

@@ -54,8 +54,8 @@ struct BSeg {
 
 constexpr int kSegRows = 2048;
 // Residual replacement keeps the direction only while |r_true - r_rec|^2 <=
-// 0.01 |r_true|^2 (as in the single-problem solver).
-constexpr double kMaxDrift2 = 0.01;
+// 1e-4 |r_true|^2 (as in the single-problem solver).
+constexpr double kMaxDrift2 = 1e-4;
 constexpr int kWidth = MFGP_MAX_D + 1;   // adjoint partial width
 
 // ---------------------------------------------------------------- persistent kernels
@@ -1045,7 +1045,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
 
     std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
     std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T), h_cross(T);
-    std::vector<int> h_norepl(T, 0);
+    std::vector<int> h_norepl(T, 0), h_nrep(T, 0), h_skips(T, 0);
     B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
     const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
@@ -1058,19 +1058,22 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         // Residual replacement (as in the single-problem solver): a tenfold drop
         // since the last true residual triggers it; active columns that fell at
         // least 1.5x join; only problems with a flagged column recompute.
+        // Triggers and joiners are per problem, exactly as in the single-problem
+        // solver, so a problem's replacements do not depend on the others.
         bool any = false, replace = false;
+        std::vector<char> trig(nprob, 0);
         for (int q = 0; q < T; ++q) {
             const bool act = h_active[q] && h_iters[q] < max_iter;
             any = any || act;
             const bool can = act && !h_norepl[q];
-            replace = replace || (can && h_rr[q] <= 0.01 * h_rep[q]);
+            if (can && h_rr[q] <= 0.01 * h_rep[q]) trig[q / t] = 1;
             h_restart[q] = (can && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
         }
+        for (int q = 0; q < T; ++q) h_restart[q] = trig[q / t] ? h_restart[q] : 0;
+        for (int b = 0; b < nprob; ++b) replace = replace || trig[b];
         if (replace) {
             for (int b = 0; b < nprob; ++b) {
-                bool need = false;
-                for (int c = 0; c < t; ++c) need = need || h_restart[b * t + c];
-                if (!need) continue;
+                if (!trig[b]) continue;
                 const int64_t o = P.row_off[b] * t;
                 B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
             }
@@ -1087,6 +1090,9 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                 if (!(drift2 <= kMaxDrift2 * h_relt[q])) {
                     h_restart[q] = 0;     // run this cycle out and refine instead
                     h_norepl[q] = 1;
+                    h_skips[q] += 1;
+                } else {
+                    h_nrep[q] += 1;
                 }
             }
             B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1170,6 +1176,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         inf[q].status = sq;
         inf[q].rel_resid_recurrence = h_b2[q] > 0.0 ? std::sqrt(h_rr[q] / h_b2[q]) : 0.0;
         inf[q].rel_resid_true = h_relt[q];
+        inf[q].replacements = h_nrep[q];
+        inf[q].drift_skips = h_skips[q];
     }
     if (info) std::memcpy(info, inf.data(), T * sizeof(mfgp_cg_info));
     timing_phase(0, std::chrono::duration<double, std::milli>(clock::now() - t0).count());

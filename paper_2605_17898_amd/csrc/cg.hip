@@ -19,7 +19,7 @@
 // bounds the drift between the recurrence and the true residual that an
 // inexact product (FP32, and more so the BF16 forms) causes, without
 // discarding the Krylov space as a restart does.  It is only sound while the
-// drift is small: a column whose recurrence has moved more than 10% away from
+// drift is small: a column whose recurrence has moved more than 1% away from
 // its true residual (very ill-conditioned operators, where FP32 drift grows
 // by about eps * cond per step) is left to finish its cycle and is refined.  The FP64 solution is what
 // lets the recomputed residual reach 1e-6: an FP32-rounded solution alone
@@ -33,8 +33,8 @@
 namespace mfgp {
 
 // Residual replacement keeps the direction only while the recurrence residual
-// is within 10% of the true one: |r_true - r_rec|^2 <= 0.01 |r_true|^2.
-constexpr double kMaxDrift2 = 0.01;
+// is within 1% of the true one: |r_true - r_rec|^2 <= 1e-4 |r_true|^2.
+constexpr double kMaxDrift2 = 1e-4;
 
 __global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
@@ -134,7 +134,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
     std::vector<double> h_relt(t), h_rr(t), h_b2(t), h_rep(t, 0.0);
-    std::vector<int> h_flag(t, 0), h_norepl(t, 0);
+    std::vector<int> h_flag(t, 0), h_norepl(t, 0), h_nrep(t, 0), h_skips(t, 0);
     std::vector<double> h_cross(t);
     int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -172,6 +172,9 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
                 if (!(drift2 <= kMaxDrift2 * h_relt[c])) {
                     h_flag[c] = 0;          // the recurrence has left the true residual:
                     h_norepl[c] = 1;        // run this cycle out and refine instead
+                    h_skips[c] += 1;
+                } else {
+                    h_nrep[c] += 1;
                 }
             }
             CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
@@ -251,6 +254,8 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             info[c].status = stc;
             info[c].rel_resid_recurrence = h_b2[c] > 0.0 ? std::sqrt(h_rr[c] / h_b2[c]) : 0.0;
             info[c].rel_resid_true = h_relt[c];
+            info[c].replacements = h_nrep[c];
+            info[c].drift_skips = h_skips[c];
         }
     }
     return worst;

@@ -44,7 +44,8 @@ class CgOptsT(C.Structure):
 class CgInfoT(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lanczos_len", C.c_int32), ("refinements", C.c_int32),
                 ("status", C.c_int32), ("rel_resid_recurrence", C.c_double),
-                ("rel_resid_true", C.c_double)]
+                ("rel_resid_true", C.c_double), ("replacements", C.c_int32),
+                ("drift_skips", C.c_int32)]
 
 
 class BatchT(C.Structure):
@@ -238,7 +239,8 @@ def cg_opts(tol: float = 1e-6, max_iter: int = 0, check_every: int = 0, max_refi
 def _info_list(info, t):
     return [dict(iters=info[c].iters, lanczos_len=info[c].lanczos_len, refinements=info[c].refinements,
                  status=info[c].status, rel_resid_recurrence=info[c].rel_resid_recurrence,
-                 rel_resid_true=info[c].rel_resid_true) for c in range(t)]
+                 rel_resid_true=info[c].rel_resid_true, replacements=info[c].replacements,
+                 drift_skips=info[c].drift_skips) for c in range(t)]
 
 
 def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,

@@ -151,3 +151,29 @@ def test_host_slq_special_cases(m):
             continue
         ref = 3.0 * float(np.sum(Q[0] ** 2 * np.log(w)))
         assert m.slq_quadrature(list(zip(al, be)), 3.0) == pytest.approx(ref, rel=1e-10, abs=1e-12)
+
+
+def test_struct_layouts_match_the_header(m, tmp_path):
+    # Compile a C probe against include/mfgp.h and compare sizes and offsets
+    # with the ctypes mirrors the binding passes across the ABI.
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "probe.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "mfgp.h"\n'
+        'int main(void) {\n'
+        '  printf("%zu %zu %zu %zu\\n", sizeof(mfgp_kernel), sizeof(mfgp_cg_opts), sizeof(mfgp_cg_info),'
+        ' sizeof(mfgp_batch));\n'
+        '  printf("%zu %zu %zu\\n", offsetof(mfgp_cg_opts, probe_seed), offsetof(mfgp_cg_opts, progress),'
+        ' offsetof(mfgp_cg_info, replacements));\n'
+        '  return 0;\n}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    sizes = [int(v) for v in out]
+    assert sizes[:4] == [C.sizeof(m.KernelT), C.sizeof(m.CgOptsT), C.sizeof(m.CgInfoT), C.sizeof(m.BatchT)]
+    assert sizes[4] == m.CgOptsT.probe_seed.offset
+    assert sizes[5] == m.CgOptsT.progress.offset
+    assert sizes[6] == m.CgInfoT.replacements.offset
