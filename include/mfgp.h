@@ -113,7 +113,8 @@ typedef struct {
     int32_t max_refine;   /* residual recomputations / restarts allowed; < 0 = default 8      */
     int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries, FP64 sums) */
     int32_t warm_start;   /* nonzero: Xsol holds the initial guess x0 on entry                */
-    int32_t pad_;
+    int32_t no_replacement; /* nonzero: no residual replacement while iterating (restarts
+                             from the recomputed residual after each cycle only)          */
     uint64_t probe_seed;  /* seed of the SplitMix64 probes when Z == NULL (mll_and_grad)      */
     /* Optional progress callback (may be NULL), called from the calling thread
      * at host convergence checks whenever the largest per-column iteration

@@ -1065,7 +1065,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         for (int q = 0; q < T; ++q) {
             const bool act = h_active[q] && h_iters[q] < max_iter;
             any = any || act;
-            const bool can = act && !h_norepl[q];
+            const bool can = act && !h_norepl[q] && !opts->no_replacement;
             if (can && h_rr[q] <= 0.01 * h_rep[q]) trig[q / t] = 1;
             h_restart[q] = (can && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
         }

@@ -154,7 +154,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         for (int c = 0; c < t; ++c) {
             const bool act = h_active[c] && h_iters[c] < max_iter;
             any = any || act;
-            const bool can = act && !h_norepl[c];
+            const bool can = act && !h_norepl[c] && !o.no_replacement;
             replace = replace || (can && h_rr[c] <= 0.01 * h_rep[c]);
             h_flag[c] = (can && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
         }

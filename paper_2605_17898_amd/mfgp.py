@@ -37,7 +37,7 @@ PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_double)
 class CgOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("max_refine", C.c_int32), ("precision", C.c_int32), ("warm_start", C.c_int32),
-                ("pad_", C.c_int32), ("probe_seed", C.c_uint64), ("progress", PROGRESS_FN),
+                ("no_replacement", C.c_int32), ("probe_seed", C.c_uint64), ("progress", PROGRESS_FN),
                 ("progress_user", C.c_void_p), ("progress_every", C.c_int32), ("pad2_", C.c_int32)]
 
 
@@ -218,9 +218,10 @@ def residual(kern: Kernel, X: torch.Tensor, B: torch.Tensor, Xsol: torch.Tensor)
 
 def cg_opts(tol: float = 1e-6, max_iter: int = 0, check_every: int = 0, max_refine: int = -1,
             precision: str = "fp32", warm_start: bool = False, probe_seed: int = 0,
-            progress=None, progress_every: int = 0) -> CgOptsT:
+            progress=None, progress_every: int = 0, replacement: bool = True) -> CgOptsT:
     """CG options; progress(iterations, rel_resid) is called during long solves."""
     o = CgOptsT()
+    o.no_replacement = 0 if replacement else 1
     if progress is not None:
         cb = PROGRESS_FN(lambda _u, it, rr: progress(int(it), float(rr)))
         o.progress = cb
@@ -246,13 +247,14 @@ def _info_list(info, t):
 def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,
              precision: str = "fp32", x0: Optional[torch.Tensor] = None, want_lanczos: bool = False,
              check_every: int = 0, max_refine: int = -1, allow=(OK, NOT_CONVERGED, BREAKDOWN),
-             progress=None):
+             progress=None, replacement: bool = True):
     """Solve K_y X = B.  Returns (Xsol float64, info list, lanczos or None, status)."""
     _dev(X, torch.float32, "X")
     _dev(B, torch.float32, "B")
     n, d = X.shape
     t = _cols(B)
-    o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None, progress=progress)
+    o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None, progress=progress,
+                replacement=replacement)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device) if x0 is None else \
         _dev(x0, torch.float64, "x0").clone()
@@ -294,7 +296,8 @@ def slq_quadrature(coeffs: Sequence[Sequence[float]], znorm2: float) -> float:
 def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int = 16,
                  Z: Optional[torch.Tensor] = None, tol: float = 1e-6, max_iter: int = 0,
                  precision: str = "fp32", probe_seed: int = 0, want_grad: bool = True,
-                 want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None):
+                 want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None,
+                 replacement: bool = True):
     """Returns dict(mll, logdet, grad, alpha, info, status)."""
     _dev(X, torch.float32, "X")
     _dev(y, torch.float32, "y")
@@ -303,7 +306,8 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
         _dev(Z, torch.float32, "Z")
         num_probes = Z.shape[1]
     t = num_probes + 1
-    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed, progress=progress)
+    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed, progress=progress,
+                replacement=replacement)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     ws = workspace(workspace_bytes(OP_MLL, n, d, t, o.precision, mi), X.device)
     ks = kern.struct(d)
@@ -418,12 +422,14 @@ class BatchPlan:
 
     def mll_and_grad(self, X: torch.Tensor, y: torch.Tensor, Z: Optional[torch.Tensor] = None,
                      tol: float = 1e-6, probe_seed: int = 0, want_grad: bool = True,
-                     allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None) -> dict:
+                     allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None,
+                     replacement: bool = True, check_every: int = 0) -> dict:
         _dev(X, torch.float32, "X")
         _dev(y, torch.float32, "y")
         if Z is not None:
             _dev(Z, torch.float32, "Z")
-        o = cg_opts(tol, self.max_iter, 0, -1, "fp32", False, probe_seed, progress=progress)
+        o = cg_opts(tol, self.max_iter, check_every, -1, "fp32", False, probe_seed, progress=progress,
+                    replacement=replacement)
         mll = (C.c_double * self.nprob)()
         ld = (C.c_double * self.nprob)()
         grad = (C.c_double * sum(self.nparams))() if want_grad else None
