@@ -114,7 +114,10 @@ typedef struct {
     int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries, FP64 sums) */
     int32_t warm_start;   /* nonzero: Xsol holds the initial guess x0 on entry                */
     int32_t no_replacement; /* nonzero: no residual replacement while iterating (restarts
-                             from the recomputed residual after each cycle only)          */
+                             from the recomputed residual after each cycle only).  Even
+                             when zero, replacement runs only if the host checks at
+                             least every other iteration (check_every <= 2; automatic
+                             for products of >= 1e9 entry-columns)                      */
     uint64_t probe_seed;  /* seed of the SplitMix64 probes when Z == NULL (mll_and_grad)      */
     /* Optional progress callback (may be NULL), called from the calling thread
      * at host convergence checks whenever the largest per-column iteration

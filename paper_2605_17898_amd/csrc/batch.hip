@@ -56,6 +56,7 @@ constexpr int kSegRows = 2048;
 // Residual replacement keeps the direction only while |r_true - r_rec|^2 <=
 // 1e-4 |r_true|^2 (as in the single-problem solver).
 constexpr double kMaxDrift2 = 1e-4;
+constexpr int kMaxReplaceGap = 2;   // largest check interval with replacement
 constexpr int kWidth = MFGP_MAX_D + 1;   // adjoint partial width
 
 // ---------------------------------------------------------------- persistent kernels
@@ -1002,6 +1003,10 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     B_CHECK(hipMemcpyAsync(w.logflag, &one, sizeof(int), hipMemcpyHostToDevice, s));
 
     int check_every = opts->check_every > 0 ? opts->check_every : 8;
+    // Residual replacement only with a check at least every other iteration
+    // (as in the single-problem solver); the default graph of 8 iterations
+    // runs plain cycles with refinement.
+    const bool may_replace = !opts->no_replacement && check_every <= kMaxReplaceGap;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     P.graph_launches = 0;
@@ -1065,7 +1070,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         for (int q = 0; q < T; ++q) {
             const bool act = h_active[q] && h_iters[q] < max_iter;
             any = any || act;
-            const bool can = act && !h_norepl[q] && !opts->no_replacement;
+            const bool can = act && !h_norepl[q] && may_replace;
             if (can && h_rr[q] <= 0.01 * h_rep[q]) trig[q / t] = 1;
             h_restart[q] = (can && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
         }

@@ -35,6 +35,7 @@ namespace mfgp {
 // Residual replacement keeps the direction only while the recurrence residual
 // is within 1% of the true one: |r_true - r_rec|^2 <= 1e-4 |r_true|^2.
 constexpr double kMaxDrift2 = 1e-4;
+constexpr int kMaxReplaceGap = 2;   // largest check interval with replacement
 
 __global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
@@ -114,6 +115,11 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         const double work = static_cast<double>(n) * static_cast<double>(n) * t;
         check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
     }
+    // Residual replacement only when the host sees every iteration or every
+    // other one: with longer gaps it destabilised FP32 CG on ill-conditioned
+    // 1-d problems (cond ~ 1e6) even at 1% drift, while plain cycles with
+    // refinement converged in as many iterations.
+    const bool may_replace = !o.no_replacement && check_every <= kMaxReplaceGap;
     CgState st = make_state(b, X, t, coeff);
     double* tmp = b.scal + 5 * t;     // [t] scratch scalars
     double* relt = b.scal + 6 * t;    // [t] true relative residual
@@ -154,7 +160,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         for (int c = 0; c < t; ++c) {
             const bool act = h_active[c] && h_iters[c] < max_iter;
             any = any || act;
-            const bool can = act && !h_norepl[c] && !o.no_replacement;
+            const bool can = act && !h_norepl[c] && may_replace;
             replace = replace || (can && h_rr[c] <= 0.01 * h_rep[c]);
             h_flag[c] = (can && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
         }
