@@ -277,7 +277,9 @@ int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sw
  * gradient exactly as mfgp_mll_and_grad defines them, computed for the whole
  * batch at once.  Host outputs: mll [nprob], logdet [nprob] (optional), grad
  * (optional, problem b's n_theta entries packed one problem after another),
- * info (optional, [nprob][p+1]).  opts->precision must be MFGP_FP32;
+ * info (optional, [nprob][p+1]).  opts->precision: MFGP_FP32 (the FP32-MFMA
+ * contraction where t = 16 k + {0,1}), MFGP_FP32_VALU, or the bf16 forms
+ * MFGP_BF16X1/X2/X3 (tile lengths are re-tuned when the precision changes);
  * opts->progress, if set, reports the largest iteration count and the worst
  * recurrence residual over the whole batch.  Synchronises.  Returns the
  * worst status over all problems. */

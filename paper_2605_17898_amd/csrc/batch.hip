@@ -24,6 +24,7 @@
 #include "adjoint_kernels.hpp"
 #include "cg.hpp"
 #include "hybrid_kernels.hpp"
+#include "mfma_kernels.hpp"
 #include "internal.hpp"
 
 int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q);
@@ -35,7 +36,9 @@ struct BProb {
     int64_t row_off;    // first packed row
     int64_t u_off;      // element offset of U_b (= x_off)
     int64_t jchunk;     // j-range length of this problem's tiles (a multiple of 4)
-    int64_t f_off;      // float offset of this problem's MFMA fragments of V
+    int64_t f_off;      // float offset of this problem's FP32-MFMA fragments of V
+    int64_t g_off;      // bf16x8 offset of this problem's BF16 fragments of V
+    int64_t y_off;      // float offset of this problem's FP32 column-0 copy
     int d;
     int chunks;         // j-ranges per row block
     int tile_base;      // first tile id of this problem
@@ -204,6 +207,77 @@ __global__ void batch_pack_hfrag_kernel(const float* __restrict__ V, const BProb
     const int64_t j = q * kHK + l / 16;
     const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
     F[idx] = (j < pb.n) ? V[(pb.row_off + j) * t + c] : 0.0f;
+}
+
+// Persistent batched sweep with the contraction on the bf16 matrix cores
+// (the x1 / x2 / x3 forms of the single-problem BF16 sweep, same tile body).
+template <int FAM, int NT, int SPLIT, int TV>
+__global__ __launch_bounds__(kBlock) void batch_mfma_kernel(
+    const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
+    const float* __restrict__ U, const bf16x8* __restrict__ Gh, const bf16x8* __restrict__ Gm,
+    const bf16x8* __restrict__ Gl, const float* __restrict__ Gy, int t, float* __restrict__ partial) {
+    __shared__ int s_k;
+    for (;;) {
+        if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane(s_k);
+        __syncthreads();
+        if (k >= ntiles) break;
+        const BTile tl = queue[k];
+        const BProb pb = probs[tl.b];
+        const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;   // multiple of 16
+        const float* Ub = U + pb.u_off;
+        float* out = partial + static_cast<int64_t>(tl.id) * kBlock * t;
+        const int64_t rbase = static_cast<int64_t>(tl.rb) * kBlock;
+        switch (pb.d) {
+#define MFGP_GCASE(DV)                                                                                  \
+    case DV:                                                                                            \
+        mfma_block<FAM, DV, NT, SPLIT, TV>(Ub, Ub, Gh + pb.g_off, Gm + pb.g_off, Gl + pb.g_off,          \
+                                           Gy + pb.y_off, pb.n, pb.n, t, rbase, j0, j0 + pb.jchunk, out); \
+        break;
+            MFGP_GCASE(1) MFGP_GCASE(2) MFGP_GCASE(3) MFGP_GCASE(4)
+            MFGP_GCASE(5) MFGP_GCASE(6) MFGP_GCASE(7) MFGP_GCASE(8)
+#undef MFGP_GCASE
+            default: break;
+        }
+    }
+}
+
+// Largest b with offs[b] <= idx (offs ascending, offs[0] = 0).
+__device__ __forceinline__ int find_slot(const int64_t* __restrict__ offs, int nprob, int64_t idx) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// BF16 fragments of every problem's packed V block (layout of the single-
+// problem BF16 sweep) and, when tv, the FP32 copy of column 0.
+__global__ void batch_pack_bfrag_kernel(const float* __restrict__ V, const BProb* __restrict__ probs,
+                                        const int64_t* __restrict__ goffs, const int64_t* __restrict__ yoffs,
+                                        int nprob, int t, int tv, int nt, int split, bf16x8* __restrict__ Gh,
+                                        bf16x8* __restrict__ Gm, bf16x8* __restrict__ Gl,
+                                        float* __restrict__ Gy) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tv && idx < yoffs[nprob]) {
+        const BProb pb = probs[find_slot(yoffs, nprob, idx)];
+        const int64_t j = idx - pb.y_off;
+        Gy[idx] = j < pb.n ? V[(pb.row_off + j) * t] : 0.0f;
+    }
+    if (idx >= goffs[nprob]) return;
+    const BProb pb = probs[find_slot(goffs, nprob, idx)];
+    const int64_t loc = idx - pb.g_off;
+    const int l = static_cast<int>(loc % 64);
+    const int64_t f = loc / 64;
+    const int ct = static_cast<int>(f % nt);
+    const int64_t jt = f / nt;
+    bf16x8 h8, m8, l8;
+    vfrag(V + pb.row_off * t, pb.n, t, tv, jt, ct, l, h8, m8, l8);
+    Gh[idx] = h8;
+    if (split >= 1) Gm[idx] = m8;
+    if (split >= 2) Gl[idx] = l8;
 }
 
 // ---------------------------------------------------------------- batched reductions
@@ -469,6 +543,9 @@ struct mfgp_batch_plan_s {
     std::vector<int64_t> frag_off;   // prefix [nprob + 1] of the MFMA fragments (floats)
     int hyb_nt = 0, hyb_tv = 0;      // t = 16 nt + tv with an MFMA-contraction kernel
     bool hybrid = false;
+    std::vector<int64_t> gfrag_off;  // prefix [nprob + 1] of the BF16 fragments (bf16x8)
+    std::vector<int64_t> y_off;      // prefix [nprob + 1] of the FP32 column-0 copies
+    int precision = MFGP_FP32;       // precision of the current call's products
     // Capture stream (default priority, non-blocking): the caller's stream may
     // be the legacy NULL stream, which cannot be captured; the graph recorded
     // here is then launched on the caller's stream.
@@ -497,9 +574,12 @@ static void build_tiles(const mfgp_batch_plan_s& P, int64_t J, std::vector<BProb
         pb.d = P.kern[b].d;
         pb.rowblocks = static_cast<int>((pb.n + kBlock - 1) / kBlock);
         pb.chunks = static_cast<int>((pb.n + J - 1) / J);
-        pb.jchunk = ((pb.n + pb.chunks - 1) / pb.chunks + kHK - 1) / kHK * kHK;
+        // whole MFMA steps of every form (4 j for FP32, 16 j for bf16)
+        pb.jchunk = ((pb.n + pb.chunks - 1) / pb.chunks + kJT - 1) / kJT * kJT;
         pb.tile_base = base;
         pb.f_off = P.frag_off[b];
+        pb.g_off = P.gfrag_off[b];
+        pb.y_off = P.y_off[b];
         pb.s2 = op.s2;
         pb.sig2 = op.sig2;
         base += pb.rowblocks * pb.chunks;
@@ -541,6 +621,10 @@ struct BatchWs {
     int* logflag;
     float* frag;      // MFMA fragments of the product's right-hand sides
     int64_t* foffs;   // [nprob + 1] fragment offsets
+    bf16x8* gh; bf16x8* gm; bf16x8* gl;   // BF16 fragments (three split pieces)
+    float* gy;        // FP32 column 0 of the BF16 products
+    int64_t* goffs;   // [nprob + 1] BF16 fragment offsets
+    int64_t* yoffs;   // [nprob + 1] column-0 offsets
     int cus;          // compute units of the device (host value)
 };
 
@@ -578,6 +662,13 @@ static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     w.logflag = cv.take<int>(64);
     w.frag = cv.take<float>(P.frag_off.empty() ? 0 : P.frag_off.back());
     w.foffs = cv.take<int64_t>(P.nprob + 1);
+    const size_t g = P.gfrag_off.empty() ? 0 : static_cast<size_t>(P.gfrag_off.back());
+    w.gh = cv.take<bf16x8>(g);
+    w.gm = cv.take<bf16x8>(g);
+    w.gl = cv.take<bf16x8>(g);
+    w.gy = cv.take<float>(P.y_off.empty() ? 0 : static_cast<size_t>(P.y_off.back()));
+    w.goffs = cv.take<int64_t>(P.nprob + 1);
+    w.yoffs = cv.take<int64_t>(P.nprob + 1);
     return w;
 }
 
@@ -674,11 +765,55 @@ static hipError_t launch_badj(int family, int tb, const BatchWs& w, int ntiles, 
 }
 
 // One batched product AP = K_y P (persistent sweep + fixed-order reduce), timed.
+template <int FAM>
+static hipError_t launch_bmfma_f(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, int nt, int split,
+                                 int tv, float* part, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
+#define MFGP_GB(NTV, SPV, TVV)                                                                        \
+    if (nt == NTV && split == SPV && tv == TVV) {                                                     \
+        hipLaunchKernelGGL((batch_mfma_kernel<FAM, NTV, SPV, TVV>), dim3(grid), dim3(kBlock), 0, s,   \
+                           w.queue, ntiles, w.counter, w.probs, w.U, w.gh, w.gm, w.gl, w.gy, P.t, part); \
+        return hipGetLastError();                                                                     \
+    }
+    MFGP_GB(1, 0, 0) MFGP_GB(1, 1, 0) MFGP_GB(1, 2, 0) MFGP_GB(1, 0, 1) MFGP_GB(1, 1, 1) MFGP_GB(1, 2, 1)
+#undef MFGP_GB
+    return hipErrorInvalidValue;
+}
+
+// Pack the BF16 fragments of all problems, then run the persistent BF16 sweep.
+static hipError_t launch_bmfma(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, const float* V,
+                               float* part, hipStream_t s) {
+    const int tv = vec_cols(P.t), nt = col_tiles(P.t), split = split_of(P.precision);
+    const int64_t total = std::max<int64_t>(P.gfrag_off.back(), P.y_off.back());
+    hipLaunchKernelGGL(batch_pack_bfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                       s, V, w.probs, w.goffs, w.yoffs, P.nprob, P.t, tv, nt, split, w.gh, w.gm, w.gl, w.gy);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (P.family) {
+        case MFGP_RBF: return launch_bmfma_f<MFGP_RBF>(P, w, ntiles, nt, split, tv, part, s);
+        case MFGP_MATERN12: return launch_bmfma_f<MFGP_MATERN12>(P, w, ntiles, nt, split, tv, part, s);
+        case MFGP_MATERN32: return launch_bmfma_f<MFGP_MATERN32>(P, w, ntiles, nt, split, tv, part, s);
+        default: return launch_bmfma_f<MFGP_MATERN52>(P, w, ntiles, nt, split, tv, part, s);
+    }
+}
+
+static bool is_bf16(int precision) {
+    return precision == MFGP_BF16X1 || precision == MFGP_BF16X2 || precision == MFGP_BF16X3;
+}
+
+// One batched entry sweep in the precision of the current call.
+static hipError_t launch_batched_sweep(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
+                                       const float* V, float* part, hipStream_t s) {
+    if (is_bf16(P.precision)) return launch_bmfma(P, w, ntiles, V, part, s);
+    if (P.hybrid && P.precision == MFGP_FP32) return launch_bhyb(P, w, ntiles, V, part, s);
+    return launch_bsweep(P.family, P.t, w, ntiles, V, part, s);
+}
+
 static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
                               const float* V, float* out, hipStream_t s) {
     void* tok = timing_begin(s);
-    hipError_t e = P.hybrid ? launch_bhyb(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s)
-                            : launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+    hipError_t e = launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
     if (e != hipSuccess) return e;
     double ent = 0.0, fl = 0.0;
     if (timing_on())
@@ -687,7 +822,7 @@ static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int 
             ent += e2;
             fl += e2 * sweep_flops_per_entry(P.family, P.kern[b].d, P.t, false);
         }
-    timing_end(tok, s, kSweepF32, ent, fl);
+    timing_end(tok, s, is_bf16(P.precision) ? kSweepMfma : kSweepF32, ent, fl);
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(nblocks(P.rows * P.t)), dim3(256), 0, s,
                        reinterpret_cast<const float*>(w.part), w.probs, w.row_offs, P.nprob, P.rows, P.t,
                        V, out);
@@ -773,8 +908,7 @@ static int tune_tiles(mfgp_batch_plan_s& P, const BatchWs& w, const float* V, hi
         int st = upload_tiles(P, w, J, ntiles, probs, queue, s);
         if (st != MFGP_OK) return st;
         auto sweep = [&]() {
-            return P.hybrid ? launch_bhyb(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s)
-                            : launch_bsweep(P.family, P.t, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+            return launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
         };
         B_CHECK(sweep());  // warm
         B_CHECK(hipEventRecord(a, s));
@@ -885,6 +1019,16 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
         if (P->hybrid) facc += (P->n[b] + kHK - 1) / kHK * 64 * (P->hyb_nt + P->hyb_tv);
     }
     P->frag_off.push_back(facc);
+    int64_t gacc = 0, yacc = 0;
+    for (int b = 0; b < P->nprob; ++b) {
+        const int64_t njt = (P->n[b] + kJT - 1) / kJT;
+        P->gfrag_off.push_back(gacc);
+        P->y_off.push_back(yacc);
+        gacc += njt * col_tiles(t) * 64;
+        yacc += njt * kJT;
+    }
+    P->gfrag_off.push_back(gacc);
+    P->y_off.push_back(yacc);
     *plan = P;
     return MFGP_OK;
 }
@@ -915,7 +1059,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                             mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || !X || !y || !opts || !mll || !ws) return MFGP_ERR_ARG;
     if (!std::isfinite(opts->tol) || !(opts->tol > 0.0) || opts->max_iter < 0) return MFGP_ERR_ARG;
-    if (opts->precision != MFGP_FP32) return MFGP_UNSUPPORTED;
+    if (opts->precision < MFGP_FP32 || opts->precision > MFGP_BF16X3) return MFGP_ERR_ARG;
+    if (is_bf16(opts->precision) && col_tiles(plan->t) != 1) return MFGP_UNSUPPORTED;
     if (ws_bytes < mfgp_batch_workspace_bytes(plan)) return MFGP_ERR_WORKSPACE;
     mfgp_batch_plan_s& P = *plan;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -942,6 +1087,14 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                            hipMemcpyHostToDevice, s));
     B_CHECK(hipMemcpyAsync(w.foffs, P.frag_off.data(), P.frag_off.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.goffs, P.gfrag_off.data(), P.gfrag_off.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    B_CHECK(hipMemcpyAsync(w.yoffs, P.y_off.data(), P.y_off.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    if (P.precision != opts->precision) {
+        P.precision = opts->precision;
+        P.tile_j = 0;   // tile lengths are tuned per precision
+    }
     std::vector<Operator> ops(nprob);
     for (int b = 0; b < nprob; ++b) {
         ops[b] = make_operator(P.kern[b], X + P.x_off[b], P.n[b], w.U + P.x_off[b]);

@@ -25,24 +25,11 @@
 #include <algorithm>
 
 #include "internal.hpp"
-#include "sweep_kernels.hpp"
+#include "mfma_kernels.hpp"
 
 namespace mfgp {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
-
-constexpr int kRT = 2;      // row tiles (of 32 rows) per wave
-constexpr int kJT = 16;     // j per MFMA step
-
 bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_BF16X3; }
-
-// Column 0 on the VALU when the rest fills whole 32-column tiles.
-static inline int vec_cols(int t) { return (t > 1 && t % 32 == 1) ? 1 : 0; }
-static inline int col_tiles(int t) { return (t - vec_cols(t) + 31) / 32; }
-static inline int split_of(int precision) {
-    return precision == MFGP_BF16X3 ? 2 : (precision == MFGP_BF16X2 ? 1 : 0);
-}
 
 // Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + 8(l/32) + q][tv + ct*32 + l%32]
 // (the first piece; Vm and Vl the second and third when split); zero outside
@@ -59,19 +46,8 @@ __global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t,
     const int64_t f = idx / 64;
     const int ct = static_cast<int>(f % nt_tiles);
     const int64_t jt = f / nt_tiles;
-    const int c = tv + ct * 32 + (l % 32);
     bf16x8 h8, m8, l8;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int64_t j = jt * kJT + 8 * (l / 32) + q;
-        const float v = (j < n && c < t) ? V[j * t + c] : 0.0f;
-        const __bf16 h = static_cast<__bf16>(v);
-        const float r = v - static_cast<float>(h);
-        const __bf16 mm = static_cast<__bf16>(r);
-        h8[q] = h;
-        m8[q] = mm;
-        l8[q] = static_cast<__bf16>(r - static_cast<float>(mm));
-    }
+    vfrag(V, n, t, tv, jt, ct, l, h8, m8, l8);
     Vh[idx] = h8;
     if (split >= 1) Vm[idx] = m8;
     if (split >= 2) Vl[idx] = l8;
@@ -84,110 +60,10 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
     int64_t m, int64_t n, int t, int chunks, int64_t jchunk, float* __restrict__ partial) {
     int rb, ch;
     map_block(blockIdx.x, chunks, rb, ch);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int half = lane >> 5;     // which 8 of the 16 j's this lane generates
-    const int row_in_tile = lane & 31;
-    const int64_t row0 = static_cast<int64_t>(rb) * kBlock + wave * (kRT * 32);
-
-    float ui[kRT][D];
-#pragma unroll
-    for (int r = 0; r < kRT; ++r) {
-        int64_t i = row0 + r * 32 + row_in_tile;
-        i = i < m ? i : m - 1;
-#pragma unroll
-        for (int k = 0; k < D; ++k) ui[r][k] = Ur[i * D + k];
-    }
-    f32x16 acc[kRT][NT];
-    float sv[kRT];
-#pragma unroll
-    for (int r = 0; r < kRT; ++r) {
-        sv[r] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < NT; ++c)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
-    }
-
     const int64_t j0 = static_cast<int64_t>(ch) * jchunk;       // multiple of 16
-    int64_t j1 = j0 + jchunk;
-    const int64_t npad = (n + kJT - 1) / kJT * kJT;
-    j1 = j1 < npad ? j1 : npad;
-    for (int64_t jb = j0; jb < j1; jb += kJT) {
-        const int64_t jt = jb / kJT;
-        bf16x8 bh[NT], bm[NT], bl[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            bh[c] = Vh[(jt * NT + c) * 64 + lane];
-            if (SPLIT >= 1) bm[c] = Vm[(jt * NT + c) * 64 + lane];
-            if (SPLIT >= 2) bl[c] = Vl[(jt * NT + c) * 64 + lane];
-        }
-        float y8[8];
-        if (TV) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) y8[q] = Vy[jb + 8 * half + q];
-        }
-        // u_j of this lane's 8 j's (clamped: padded j carry V = 0)
-        float uj[8][D];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int64_t j = jb + 8 * half + q;
-            j = j < n ? j : n - 1;
-#pragma unroll
-            for (int k = 0; k < D; ++k) uj[q][k] = Uc[j * D + k];
-        }
-#pragma unroll
-        for (int r = 0; r < kRT; ++r) {
-            bf16x8 ah, am, al;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float e = kentry<FAM>(sqdist<D>(ui[r], uj[q]));
-                if (TV) sv[r] = fmaf(e, y8[q], sv[r]);
-                const __bf16 h = static_cast<__bf16>(e);
-                ah[q] = h;
-                if (SPLIT >= 1) {
-                    const float rm = e - static_cast<float>(h);
-                    const __bf16 mm = static_cast<__bf16>(rm);
-                    am[q] = mm;
-                    if (SPLIT >= 2) al[q] = static_cast<__bf16>(rm - static_cast<float>(mm));
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                // smallest terms first
-                if (SPLIT >= 2) {
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm[c], acc[r][c], 0, 0, 0);
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[c], acc[r][c], 0, 0, 0);
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[c], acc[r][c], 0, 0, 0);
-                }
-                if (SPLIT >= 1) {
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm[c], acc[r][c], 0, 0, 0);
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh[c], acc[r][c], 0, 0, 0);
-                }
-                acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[c], acc[r][c], 0, 0, 0);
-            }
-        }
-    }
-    // C layout: register q of lane l -> row 8(q/4) + 4(l/32) + q%4, column l%32.
-#pragma unroll
-    for (int r = 0; r < kRT; ++r) {
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const int col = TV + c * 32 + (lane & 31);
-            if (col >= t) continue;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int64_t i = row0 + r * 32 + 8 * (q / 4) + 4 * half + (q % 4);
-                if (i < m) partial[(static_cast<int64_t>(ch) * m + i) * t + col] = acc[r][c][q];
-            }
-        }
-        if (TV) {
-            // VALU column: the two lane halves hold the two 8-j halves of row l % 32
-            const float v = sv[r] + __shfl_xor(sv[r], 32, 64);
-            const int64_t i = row0 + r * 32 + row_in_tile;
-            if (half == 0 && i < m) partial[(static_cast<int64_t>(ch) * m + i) * t] = v;
-        }
-    }
+    const int64_t row_base = static_cast<int64_t>(rb) * kBlock;
+    mfma_block<FAM, D, NT, SPLIT, TV>(Ur, Uc, Vh, Vm, Vl, Vy, m, n, t, row_base, j0, j0 + jchunk,
+                                      partial + static_cast<int64_t>(ch) * m * t + row_base * t);
 }
 
 // ---------------------------------------------------------------- host side

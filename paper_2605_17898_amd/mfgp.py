@@ -423,12 +423,12 @@ class BatchPlan:
     def mll_and_grad(self, X: torch.Tensor, y: torch.Tensor, Z: Optional[torch.Tensor] = None,
                      tol: float = 1e-6, probe_seed: int = 0, want_grad: bool = True,
                      allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None,
-                     replacement: bool = True, check_every: int = 0) -> dict:
+                     replacement: bool = True, check_every: int = 0, precision: str = "fp32") -> dict:
         _dev(X, torch.float32, "X")
         _dev(y, torch.float32, "y")
         if Z is not None:
             _dev(Z, torch.float32, "Z")
-        o = cg_opts(tol, self.max_iter, check_every, -1, "fp32", False, probe_seed, progress=progress,
+        o = cg_opts(tol, self.max_iter, check_every, -1, precision, False, probe_seed, progress=progress,
                     replacement=replacement)
         mll = (C.c_double * self.nprob)()
         ld = (C.c_double * self.nprob)()

@@ -148,3 +148,23 @@ def test_batch64_full_with_tuning(mf):
     k = okern(w)
     g = gp.same_probe_grad(k, w.X, w.y, w.Z)
     assert np.linalg.norm(np.array(r["grad"][b]) - g) / np.linalg.norm(g) <= 1e-3
+
+
+@pytest.mark.parametrize("form", ["bf16x2", "bf16x3"])
+def test_batch_bf16_forms_match_single(mf, form):
+    # The batched BF16 sweep shares the single-problem tile body: every problem
+    # must reach the 1e-6 recomputed residual and agree with its own
+    # single-problem run in the same form (same estimator, same probes).
+    banner(f"batch of 6 uneven problems, {form}, p=16 (t=17)")
+    p = 16
+    probs = make_batch(SIZES[1:7], p, seed=5)
+    X, y, Z = pack(probs)
+    plan = plan_for(mf, probs, p, tune=False)
+    r = plan.mll_and_grad(X, y, Z, tol=1e-6, precision=form)
+    assert r["status"] == mf.OK
+    for b, w in enumerate(probs):
+        assert max(i["rel_resid_true"] for i in r["info"][b]) <= 1e-6
+        s = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6, precision=form)
+        assert r["mll"][b] == pytest.approx(s["mll"], rel=1e-5, abs=1e-5)
+        g, gs = np.array(r["grad"][b]), np.array(s["grad"])
+        assert np.linalg.norm(g - gs) / np.linalg.norm(gs) <= 1e-3
