@@ -46,7 +46,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # N = 100000), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy's
 # reading of the same counters (summary in profiles/).  Valid only for the
 # kernel named below; None for any other.
-HYB_TRAFFIC_BYTES = 2.660e8
+HYB_TRAFFIC_BYTES = 2.664e8
 HYB_KERNEL = "sweep_hyb_kernel<RBF, d=4, NT=2, TV=1>"
 METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
 
@@ -202,7 +202,7 @@ def small_leg(args) -> int:
         box = {}
 
         def solve():
-            box["x"], box["info"] = mfgp.cg_solve(kern, X, y, tol=1e-6)
+            box["x"], box["info"], _, _ = mfgp.cg_solve(kern, X, y, tol=1e-6)
 
         def mll():
             box["m"] = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6)
