@@ -19,6 +19,8 @@ krylov   plain FP64 conjugate gradients, Lanczos with full
 brute    pure-Python double loops for tiny inputs.
 probes   the counter-based Rademacher probe generator (SplitMix64).
 bf16     round-to-nearest-even bfloat16 and the BF16 tile-product models.
+precond  rank-k pivoted Cholesky, the Woodbury preconditioner, preconditioned
+         CG and the preconditioned log-determinant and gradient estimators.
 """
 
-from . import gp, krylov, brute, probes, bf16  # noqa: F401
+from . import gp, krylov, brute, probes, bf16, precond  # noqa: F401
