@@ -50,6 +50,7 @@ extern "C" {
 
 #define MFGP_MAX_D 8
 #define MFGP_MAX_T 64
+#define MFGP_MAX_RANK 1024   /* largest pivoted-Cholesky preconditioner rank */
 
 typedef enum {
     MFGP_RBF = 0,
@@ -91,7 +92,11 @@ typedef enum {
     MFGP_OP_PREDICT = 2,
     MFGP_OP_MLL = 3,
     MFGP_OP_ADJOINT = 4,
-    MFGP_OP_RESIDUAL = 5
+    MFGP_OP_RESIDUAL = 5,
+    MFGP_OP_PCHOL = 6,     /* mfgp_pivoted_cholesky (mfgp_precond_workspace_bytes)  */
+    MFGP_OP_PAPPLY = 7,    /* mfgp_precond_apply                                     */
+    MFGP_OP_PCG = 8,       /* mfgp_precond_cg_solve                                  */
+    MFGP_OP_PMLL = 9       /* mfgp_precond_mll_and_grad                              */
 } mfgp_op;
 
 /* Kernel hyperparameters (host struct, passed by pointer). */
@@ -286,6 +291,59 @@ int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sw
 int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
                             const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
                             mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- preconditioning
+ * LightGP's CG is unpreconditioned; Sec. 5 ("Limitations") names the
+ * comparison system's pivoted-Cholesky-preconditioned, batched CG as what it
+ * lacks.  These calls add that preconditioner (the construction of Gardner et
+ * al. 2018 with the greedy pivoted Cholesky of Harbrecht, Peters & Schneider
+ * 2012) to the same matrix-free operator:
+ *   P = L L^T + sigma^2 I, L the rank-k pivoted Cholesky factor of the
+ *   noise-free s2 k(X, X) (entries generated as in the sweeps), applied by the
+ *   Woodbury identity (k x k system factored in FP64);
+ *   preconditioned CG with the stopping rule, FP64 solution and refinement of
+ *   mfgp_cg_solve (no residual replacement);
+ *   log|K_y| = log|P| + SLQ of P^{-1/2} K_y P^{-1/2} with probes z ~ N(0, P);
+ *   tr(K_y^{-1} dK) ~ (1/p) sum_c (K_y^{-1} z_c)^T dK (P^{-1} z_c).
+ * L is a device array [rank][n] float32 (row q holds column q of the factor),
+ * caller-owned; it is built by mfgp_pivoted_cholesky and read by the others.
+ * Workspace sizes come from mfgp_precond_workspace_bytes. */
+
+/* Bytes of workspace of a preconditioned call: op MFGP_OP_PCHOL / PAPPLY /
+ * PCG / PMLL; t right-hand sides (probes + 1 for PMLL); rank k <= min(n,
+ * MFGP_MAX_RANK); precision and max_iter as in mfgp_cg_opts.  0 if invalid. */
+size_t mfgp_precond_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t rank,
+                                    int32_t precision, int32_t max_iter);
+/* Rank-k pivoted Cholesky of s2 k(X, X): L [rank][n] and the pivot indices
+ * piv [rank] (device outputs).  Greedy pivot = largest remaining diagonal
+ * (ties: smallest index); columns past the numerical rank (remaining diagonal
+ * <= 1e-6 s2) are zero.  Asynchronous. */
+int mfgp_pivoted_cholesky(const mfgp_kernel* kern, const float* X, int64_t n, int32_t rank, float* L,
+                          int32_t* piv, void* ws, size_t ws_bytes, void* stream);
+/* Probes z_c ~ N(0, P) from standard normal draws: Z = L^T-factor E +
+ * sqrt(noise) G, i.e. Z[j][c] = sum_q L[q][j] E[q][c] + sqrt(noise) G[j][c];
+ * E [rank][p], G [n][p], Z [n][p] device.  Asynchronous. */
+int mfgp_precond_probes(const float* L, int64_t n, int32_t rank, float noise, const float* E,
+                        const float* G, int32_t p, float* Z, void* stream);
+/* Zout = P^{-1} R for R [n][t] (device); logdet (host, optional) = log|P|.
+ * Synchronises (the k x k factorisation runs on the host).  MFGP_BREAKDOWN if
+ * sigma^2 I + L^T L is not positive definite. */
+int mfgp_precond_apply(const float* L, int64_t n, int32_t rank, float noise, const float* R, int32_t t,
+                       float* Zout, double* logdet, void* ws, size_t ws_bytes, void* stream);
+/* Preconditioned CG on K_y Xsol = B (as mfgp_cg_solve; opts->warm_start and
+ * residual replacement are not used).  lanczos (optional, device
+ * [t][max_iter][2]) receives the first cycle's (alpha, beta).  Synchronises. */
+int mfgp_precond_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const float* B, int32_t t,
+                          double* Xsol, const float* L, int32_t rank, const mfgp_cg_opts* opts,
+                          mfgp_cg_info* info, double* lanczos, void* ws, size_t ws_bytes, void* stream);
+/* Log marginal likelihood and gradient as mfgp_mll_and_grad, with the
+ * preconditioned solver and estimators above.  Z [n][p] (device) must be
+ * probes drawn from N(0, P) (e.g. by mfgp_precond_probes).  Synchronises. */
+int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const float* y,
+                              int32_t num_probes, const float* Z, const float* L, int32_t rank,
+                              const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
+                              double* alpha_out, mfgp_cg_info* info, void* ws, size_t ws_bytes,
+                              void* stream);
 
 /* Kernel timing (for benchmarks).  While enabled on the calling thread, every
  * entry-sweep launch (the fused K-tile kernels) is bracketed by HIP events

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "cg.hpp"
+#include "precond.hpp"
 #include "internal.hpp"
 
 namespace mfgp {
@@ -188,6 +189,36 @@ static MllWs carve_mll(Carver& cv, int64_t n, int d, int t, int precision, int m
     w.tmp = cv.take<double>(4 * static_cast<size_t>(t) + 8);
     w.b = carve_cg(cv, n, t, precision);
     w.adj = cv.take<double>(adjoint_scratch_doubles(n, d, t));
+    return w;
+}
+
+// Preconditioned operations (rank-k pivoted Cholesky, Woodbury apply, PCG, MLL).
+struct PcholWs { float* U; double* scratch; };
+static PcholWs carve_pchol(Carver& cv, int64_t n, int d) {
+    PcholWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.scratch = cv.take<double>(pchol_scratch_doubles(n));
+    return w;
+}
+struct PapplyWs { double* pc; };
+static PapplyWs carve_papply(Carver& cv, int64_t n, int k, int t) {
+    PapplyWs w;
+    w.pc = cv.take<double>(pc_scratch_doubles(n, k, t));
+    return w;
+}
+struct PcgWs { float* U; CgBufs b; PcgBufs pb; };
+static PcgWs carve_pcgws(Carver& cv, int64_t n, int d, int k, int t, int precision) {
+    PcgWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.b = carve_cg(cv, n, t, precision);
+    w.pb = carve_pcg(cv, n, k, t);
+    return w;
+}
+struct PmllWs { MllWs m; PcgBufs pb; };
+static PmllWs carve_pmll(Carver& cv, int64_t n, int d, int k, int t, int precision, int max_iter) {
+    PmllWs w;
+    w.m = carve_mll(cv, n, d, t, precision, max_iter);
+    w.pb = carve_pcg(cv, n, k, t);
     return w;
 }
 
@@ -506,6 +537,236 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
         double tr = 0.0;
         for (int c = 1; c < t; ++c) tr += h[t + c];
         grad[(kern->ard ? kern->d : 1) + 1] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
+        timing_phase(2, ms_since(t0));
+    }
+    if (cg_status != MFGP_OK) return cg_status;
+    return slq_status;
+}
+
+// ---------------------------------------------------------------- preconditioned solves
+
+size_t mfgp_precond_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t rank,
+                                    int32_t precision, int32_t max_iter) {
+    if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1 || rank < 0 || rank > n || rank > MFGP_MAX_RANK) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return 0;
+    Carver cv(nullptr);
+    switch (op) {
+        case MFGP_OP_PCHOL: carve_pchol(cv, n, d); break;
+        case MFGP_OP_PAPPLY: carve_papply(cv, n, rank, t); break;
+        case MFGP_OP_PCG: carve_pcgws(cv, n, d, rank, t, precision); break;
+        case MFGP_OP_PMLL:
+            if (t < 2) return 0;
+            carve_pmll(cv, n, d, rank, t, precision, default_max_iter(n, max_iter));
+            break;
+        default: return 0;
+    }
+    return cv.off + 256;
+}
+
+int mfgp_pivoted_cholesky(const mfgp_kernel* kern, const float* X, int64_t n, int32_t rank, float* L,
+                          int32_t* piv, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !L || !piv || !ws || n < 1 || rank < 1 || rank > n || rank > MFGP_MAX_RANK) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCHOL, n, kern->d, 1, rank, MFGP_FP32, 0))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    PcholWs w = carve_pchol(cv, n, kern->d);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    ABI_CHECK(pivoted_cholesky(op, rank, L, piv, w.scratch, s));
+    return MFGP_OK;
+}
+
+int mfgp_precond_probes(const float* L, int64_t n, int32_t rank, float noise, const float* E, const float* G,
+                        int32_t p, float* Z, void* stream) {
+    if (!G || !Z || n < 1 || p < 1 || rank < 0 || rank > n || (rank > 0 && (!L || !E)) ||
+        !(std::isfinite(noise) && noise > 0.0f))
+        return MFGP_ERR_ARG;
+    ABI_CHECK(pc_probes(L, rank, n, noise, E, G, p, Z, static_cast<hipStream_t>(stream)));
+    return MFGP_OK;
+}
+
+int mfgp_precond_apply(const float* L, int64_t n, int32_t rank, float noise, const float* R, int32_t t,
+                       float* Zout, double* logdet, void* ws, size_t ws_bytes, void* stream) {
+    if (!R || !Zout || !ws || n < 1 || t < 1 || rank < 0 || rank > n || rank > MFGP_MAX_RANK ||
+        (rank > 0 && !L) || !(std::isfinite(noise) && noise > 0.0f))
+        return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PAPPLY, n, 1, t, rank, MFGP_FP32, 0))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    PapplyWs w = carve_papply(cv, n, rank, t);
+    Precond pc;
+    pc.L = L;
+    pc.k = rank;
+    pc.n = n;
+    pc.s2n = noise;
+    hipError_t e = pc_setup(pc, w.pc, s);
+    if (e == hipErrorInvalidValue) return MFGP_BREAKDOWN;
+    ABI_CHECK(e);
+    if (logdet) *logdet = pc.logdet;
+    ABI_CHECK(pc_apply(pc, R, t, Zout, w.pc, s));
+    return MFGP_OK;
+}
+
+int mfgp_precond_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const float* B, int32_t t,
+                          double* Xsol, const float* L, int32_t rank, const mfgp_cg_opts* opts,
+                          mfgp_cg_info* info, double* lanczos, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !B || !Xsol || !ws || n < 1 || t < 1 || rank < 0 || rank > n || rank > MFGP_MAX_RANK ||
+        (rank > 0 && !L))
+        return MFGP_ERR_ARG;
+    if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCG, n, kern->d, t, rank, opts->precision, opts->max_iter))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    PcgWs w = carve_pcgws(cv, n, kern->d, rank, t, opts->precision);
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    Precond pc;
+    pc.L = L;
+    pc.k = rank;
+    pc.n = n;
+    pc.s2n = kern->noise;
+    hipError_t e = pc_setup(pc, w.pb.pc, s);
+    if (e == hipErrorInvalidValue) return MFGP_BREAKDOWN;
+    ABI_CHECK(e);
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    return pcg_run(op, pc, B, t, Xsol, *opts, info, lanczos, max_iter, w.b, w.pb, s);
+}
+
+int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const float* y,
+                              int32_t num_probes, const float* Z, const float* L, int32_t rank,
+                              const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
+                              double* alpha_out, mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !y || !Z || !mll || !ws || n < 1 || num_probes < 1 || rank < 0 || rank > n ||
+        rank > MFGP_MAX_RANK || (rank > 0 && !L))
+        return MFGP_ERR_ARG;
+    const int p = num_probes;
+    const int t = p + 1;
+    if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PMLL, n, kern->d, t, rank, opts->precision, max_iter))
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    PmllWs W = carve_pmll(cv, n, kern->d, rank, t, opts->precision, max_iter);
+    MllWs& w = W.m;
+    Operator op = make_operator(*kern, X, n, w.U);
+    ABI_CHECK(prescale(op, s));
+    hipLaunchKernelGGL(pack_yz_kernel, dim3(nb(n * t)), dim3(256), 0, s, y, Z, n, p, w.Bm);
+    ABI_CHECK(hipGetLastError());
+    Precond pc;
+    pc.L = L;
+    pc.k = rank;
+    pc.n = n;
+    pc.s2n = kern->noise;
+    {
+        hipError_t e = pc_setup(pc, W.pb.pc, s);
+        if (e == hipErrorInvalidValue) return MFGP_BREAKDOWN;
+        ABI_CHECK(e);
+    }
+
+    using clock = std::chrono::steady_clock;
+    auto ms_since = [](clock::time_point a) {
+        return std::chrono::duration<double, std::milli>(clock::now() - a).count();
+    };
+    if (timing_on()) ABI_CHECK(hipStreamSynchronize(s));
+    auto t0 = clock::now();
+    std::vector<mfgp_cg_info> inf(t);
+    mfgp_cg_opts o = *opts;
+    o.warm_start = 0;
+    const int cg_status = pcg_run(op, pc, w.Bm, t, w.X64, o, inf.data(), w.coeff, max_iter, w.b, W.pb, s);
+    timing_phase(0, ms_since(t0));
+    t0 = clock::now();
+    if (cg_status == MFGP_ERR_HIP || cg_status == MFGP_ERR_ARG) return cg_status;
+    if (info) std::memcpy(info, inf.data(), t * sizeof(mfgp_cg_info));
+
+    // FP64 column dots: x_c^T b_c and x_c^T x_c; b^T P^{-1} b of the probes.
+    double* xb = w.tmp;
+    double* xx = w.tmp + t;
+    ABI_CHECK(col_dots_df(w.X64, w.Bm, n, t, xb, w.b.dots, s));
+    ABI_CHECK(col_dots_dd(w.X64, w.X64, n, t, xx, w.b.dots, s));
+    std::vector<double> h(2 * t), rz0(t);
+    ABI_CHECK(hipMemcpyAsync(h.data(), w.tmp, 2 * t * sizeof(double), hipMemcpyDeviceToHost, s));
+    ABI_CHECK(hipMemcpyAsync(rz0.data(), W.pb.rz0, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<double>> cf(t);
+    for (int c = 1; c < t; ++c) {
+        cf[c].resize(2 * static_cast<size_t>(inf[c].lanczos_len > 0 ? inf[c].lanczos_len : 1));
+        if (inf[c].lanczos_len > 0)
+            ABI_CHECK(hipMemcpyAsync(cf[c].data(), w.coeff + static_cast<size_t>(c) * max_iter * 2,
+                                     2 * inf[c].lanczos_len * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (alpha_out) {
+        hipLaunchKernelGGL(copy_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, alpha_out, n, t);
+        ABI_CHECK(hipGetLastError());
+    }
+    ABI_CHECK(hipStreamSynchronize(s));
+
+    // log|K_y| = log|P| + (1/p) sum_c (z_c^T P^{-1} z_c) e_1^T log(T_c) e_1.
+    std::vector<double> q(t, 0.0);
+    std::vector<int> qs(t, MFGP_OK);
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
+        std::vector<std::thread> pool;
+        for (int th = 0; th < nth; ++th) {
+            pool.emplace_back([&, th]() {
+                for (int c = 1 + th; c < t; c += nth) {
+                    if (inf[c].lanczos_len < 1) {
+                        qs[c] = MFGP_BREAKDOWN;
+                        continue;
+                    }
+                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, rz0[c], &q[c]);
+                }
+            });
+        }
+        for (auto& th : pool) th.join();
+    }
+    double ld = 0.0;
+    int slq_status = MFGP_OK;
+    for (int c = 1; c < t; ++c) {
+        ld += q[c];
+        if (qs[c] != MFGP_OK) slq_status = MFGP_BREAKDOWN;
+    }
+    ld = pc.logdet + ld / p;
+    timing_phase(1, ms_since(t0));
+    t0 = clock::now();
+    const double two_pi = 6.283185307179586477;
+    *mll = -0.5 * (h[0] + ld + static_cast<double>(n) * std::log(two_pi));
+    if (logdet) *logdet = ld;
+
+    if (grad) {
+        // A = fl32([alpha, U]), B = [fl32(alpha), P^{-1} Z]: the trace term pairs
+        // u_c = K_y^{-1} z_c with w_c = P^{-1} z_c.
+        float* Ag = w.b.R;
+        float* Bg = w.b.P;
+        ABI_CHECK(f64_to_f32(w.X64, Ag, n * t, s));
+        ABI_CHECK(pc_apply(pc, w.Bm, t, Bg, W.pb.pc, s));
+        hipLaunchKernelGGL(set_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, Bg, n, t);
+        ABI_CHECK(hipGetLastError());
+        std::vector<double> colw(t, -0.5 / p);
+        colw[0] = 0.5;
+        double sums[MFGP_MAX_D + 1];
+        ABI_CHECK(adjoint_sums(op, Ag, Bg, t, colw.data(), sums, w.adj, s));
+        grad_from_sums(op, kern->ard, sums, grad);
+        // d/d sigma^2: dK_y = I, so 1/2 a^T a - 1/2 (1/p) sum_c u_c^T w_c (FP64 dots)
+        double* uw = w.tmp;
+        ABI_CHECK(col_dots_df(w.X64, Bg, n, t, uw, w.b.dots, s));
+        std::vector<double> huw(t);
+        ABI_CHECK(hipMemcpyAsync(huw.data(), uw, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        ABI_CHECK(hipStreamSynchronize(s));
+        double tr = 0.0;
+        for (int c = 1; c < t; ++c) tr += huw[c];
+        grad[(kern->ard ? kern->d : 1) + 1] = 0.5 * h[t + 0] - 0.5 * tr / p;
         timing_phase(2, ms_since(t0));
     }
     if (cg_status != MFGP_OK) return cg_status;

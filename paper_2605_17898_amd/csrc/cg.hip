@@ -25,6 +25,7 @@
 // lets the recomputed residual reach 1e-6: an FP32-rounded solution alone
 // floors at a few 1e-6.
 #include "cg.hpp"
+#include "precond.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -262,6 +263,214 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             info[c].rel_resid_true = h_relt[c];
             info[c].replacements = h_nrep[c];
             info[c].drift_skips = h_skips[c];
+        }
+    }
+    return worst;
+}
+
+
+// ---------------------------------------------------------------- preconditioned CG
+
+static inline unsigned nblk(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
+
+// rz = r^T z (the PCG inner product) drives alpha and beta; rr = r^T r the
+// stopping rule.  st.rr holds rz so that cg_alpha_kernel computes rz / p^T A p.
+__global__ void pcg_beta_kernel(CgState st, int t, const double* __restrict__ rzn_all,
+                                const double* __restrict__ rrn_all, double tol2, int log_coeffs, int max_iter) {
+    for (int c = threadIdx.x; c < t; c += blockDim.x) {
+        double b = 0.0;
+        if (st.active[c]) {
+            const double rzn = rzn_all[c], rrn = rrn_all[c];
+            b = rzn / st.rr[c];
+            if (log_coeffs && st.coeff && st.lanlen[c] < max_iter) {
+                double* cf = st.coeff + (static_cast<int64_t>(c) * max_iter + st.lanlen[c]) * 2;
+                cf[0] = st.alpha[c];
+                cf[1] = b;
+                st.lanlen[c] += 1;
+            }
+            st.iters[c] += 1;
+            st.rr[c] = rzn;
+            st.rrn[c] = rrn;
+            if (!isfinite(rzn) || !isfinite(rrn)) {
+                st.status[c] = MFGP_BREAKDOWN;
+                st.active[c] = 0;
+            } else if (rrn <= tol2 * st.bnorm2[c] || st.iters[c] >= max_iter) {
+                st.active[c] = 0;
+            }
+        }
+        st.beta[c] = b;
+    }
+}
+
+// p = z + beta p for active columns (all columns when `all`, with beta 0: p = z).
+__global__ void pcg_p_kernel(CgState st, const float* __restrict__ Z, int64_t total, int t,
+                             const int* __restrict__ only) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int c = static_cast<int>(idx % t);
+    if (only) {
+        if (only[c]) st.p[idx] = Z[idx];
+        return;
+    }
+    if (!st.active[c]) return;
+    st.p[idx] = fmaf(static_cast<float>(st.beta[c]), st.p[idx], Z[idx]);
+}
+
+__global__ void pcg_init_kernel(CgState st, int t, double tol2, const double* __restrict__ rr0,
+                                double* __restrict__ rz0) {
+    for (int c = threadIdx.x; c < t; c += blockDim.x) {
+        const bool finite = isfinite(st.bnorm2[c]) && isfinite(st.rr[c]) && isfinite(rr0[c]);
+        const bool go = finite && st.bnorm2[c] > 0.0 && rr0[c] > tol2 * st.bnorm2[c];
+        st.active[c] = go ? 1 : 0;
+        st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
+        st.iters[c] = 0;
+        st.lanlen[c] = 0;
+        st.alpha[c] = 0.0;
+        st.beta[c] = 0.0;
+        st.rrn[c] = rr0[c];
+        rz0[c] = st.rr[c];
+    }
+}
+
+// Refinement restart of flagged columns: rz = rz_new, rr = rr_new, active again.
+__global__ void pcg_activate_kernel(CgState st, int t, const int* __restrict__ restart,
+                                    const double* __restrict__ rz_new, const double* __restrict__ rr_new) {
+    for (int c = threadIdx.x; c < t; c += blockDim.x) {
+        if (restart[c]) {
+            st.active[c] = rr_new[c] > 0.0 ? 1 : 0;
+            st.rr[c] = rz_new[c];
+            st.rrn[c] = rr_new[c];
+        }
+    }
+}
+
+PcgBufs carve_pcg(Carver& cv, int64_t n, int k, int t) {
+    PcgBufs pb;
+    pb.Zv = cv.take<float>(static_cast<size_t>(n) * t);
+    pb.pc = cv.take<double>(pc_scratch_doubles(n, k, t));
+    pb.rz0 = cv.take<double>(static_cast<size_t>(t));
+    return pb;
+}
+
+int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double* X, const mfgp_cg_opts& o,
+            mfgp_cg_info* info, double* coeff, int max_iter, const CgBufs& b, const PcgBufs& pb, hipStream_t s) {
+    const int64_t n = op.n;
+    const int64_t nt = n * t;
+    const double tol = o.tol;
+    const int max_refine = o.max_refine >= 0 ? o.max_refine : 8;
+    int check_every = o.check_every;
+    if (check_every <= 0) {
+        const double work = static_cast<double>(n) * static_cast<double>(n) * t;
+        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
+    }
+    CgState st = make_state(b, X, t, coeff);
+    double* rzn = b.scal + 5 * t;     // [t] new r^T z
+    double* rrn = b.scal + 6 * t;     // [t] new r^T r (st.rrn holds the current one)
+    int* restart = b.ints + 4 * t;
+
+    CG_CHECK(col_dots_ff(B, B, n, t, st.bnorm2, b.dots, s));
+    CG_CHECK(fill_f64(X, nt, 0.0, s));
+    CG_CHECK(copy2_f32(B, st.r, st.r, nt, s));
+    CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
+    CG_CHECK(col_dots_ff(st.r, pb.Zv, n, t, st.rr, b.dots, s));
+    CG_CHECK(col_dots_ff(st.r, st.r, n, t, rrn, b.dots, s));
+    hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol, rrn, pb.rz0);
+    CG_CHECK(hipGetLastError());
+    // the first direction is z itself for every column
+    CG_CHECK(hipMemcpyAsync(st.p, pb.Zv, nt * sizeof(float), hipMemcpyDeviceToDevice, s));
+
+    std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
+    std::vector<double> h_relt(t), h_rr(t), h_b2(t);
+    int log_coeffs = coeff ? 1 : 0;
+    CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int report_every = o.progress_every > 0 ? o.progress_every : 100;
+    int next_report = report_every;
+
+    for (;;) {
+        CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
+        if (o.progress) {
+            int itmax = 0;
+            double worst = 0.0;
+            for (int c = 0; c < t; ++c) {
+                itmax = std::max(itmax, h_iters[c]);
+                if (h_b2[c] > 0.0) worst = std::max(worst, std::sqrt(h_rr[c] / h_b2[c]));
+            }
+            if (itmax >= next_report) {
+                o.progress(o.progress_user, itmax, worst);
+                while (next_report <= itmax) next_report += report_every;
+            }
+        }
+        if (any) {
+            for (int k = 0; k < check_every; ++k) {
+                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b.apply, s));
+                CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
+                CG_CHECK(cg_alpha(st, t, s));
+                CG_CHECK(cg_update_rr(st, n, t, b.dots, rrn, s));
+                CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
+                CG_CHECK(col_dots_ff(st.r, pb.Zv, n, t, rzn, b.dots, s));
+                hipLaunchKernelGGL(pcg_beta_kernel, dim3(1), dim3(256), 0, s, st, t, rzn, rrn, tol * tol,
+                                   log_coeffs, max_iter);
+                hipLaunchKernelGGL(pcg_p_kernel, dim3(nblk(nt)), dim3(256), 0, s, st, pb.Zv, nt, t, nullptr);
+                CG_CHECK(hipGetLastError());
+            }
+            continue;
+        }
+        // Every column stopped: recompute the true residual in FP64 and refine.
+        double* tmp = rzn;
+        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
+        CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipMemcpyAsync(h_status.data(), st.status, t * sizeof(int), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipStreamSynchronize(s));
+        bool again = false;
+        for (int c = 0; c < t; ++c) {
+            h_relt[c] = h_b2[c] > 0.0 ? std::sqrt(h_relt[c] / h_b2[c]) : 0.0;
+            const bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
+                              h_refine[c] < max_refine && h_iters[c] < max_iter;
+            h_restart[c] = need ? 1 : 0;
+            if (need) {
+                h_refine[c] += 1;
+                again = true;
+            }
+        }
+        if (!again) break;
+        CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
+        CG_CHECK(cg_restart(st, b.R64, n, t, restart, s));            // r = fl32(R64) (and p = r)
+        CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
+        hipLaunchKernelGGL(pcg_p_kernel, dim3(nblk(nt)), dim3(256), 0, s, st, pb.Zv, nt, t, restart);
+        CG_CHECK(col_dots_ff(st.r, pb.Zv, n, t, rzn, b.dots, s));
+        CG_CHECK(col_dots_ff(st.r, st.r, n, t, rrn, b.dots, s));
+        hipLaunchKernelGGL(pcg_activate_kernel, dim3(1), dim3(256), 0, s, st, t, restart, rzn, rrn);
+        CG_CHECK(hipGetLastError());
+        log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
+    }
+
+    CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_lan.data(), st.lanlen, t * sizeof(int), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipStreamSynchronize(s));
+    int worst = MFGP_OK;
+    for (int c = 0; c < t; ++c) {
+        int stc = h_status[c];
+        if (stc == MFGP_OK && !(h_relt[c] <= tol)) stc = MFGP_NOT_CONVERGED;
+        if (stc == MFGP_BREAKDOWN)
+            worst = MFGP_BREAKDOWN;
+        else if (stc == MFGP_NOT_CONVERGED && worst == MFGP_OK)
+            worst = MFGP_NOT_CONVERGED;
+        if (info) {
+            info[c].iters = h_iters[c];
+            info[c].lanczos_len = h_lan[c];
+            info[c].refinements = h_refine[c];
+            info[c].status = stc;
+            info[c].rel_resid_recurrence = h_b2[c] > 0.0 ? std::sqrt(h_rr[c] / h_b2[c]) : 0.0;
+            info[c].rel_resid_true = h_relt[c];
+            info[c].replacements = 0;
+            info[c].drift_skips = 0;
         }
     }
     return worst;

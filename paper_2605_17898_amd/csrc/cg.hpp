@@ -24,4 +24,18 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision);
 int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_opts& o,
            mfgp_cg_info* info, double* coeff, int max_iter, const CgBufs& b, hipStream_t s);
 
+struct Precond;
+// Extra buffers of the preconditioned solver: z = P^{-1} r and the Woodbury scratch.
+struct PcgBufs {
+    float* Zv = nullptr;       // [n, t]
+    double* pc = nullptr;      // pc_scratch_doubles(n, k, t)
+    double* rz0 = nullptr;     // [t] b^T P^{-1} b of the first cycle
+};
+PcgBufs carve_pcg(Carver& cv, int64_t n, int k, int t);
+// Preconditioned CG (x0 = 0) with the same stopping rule, FP64 solution and
+// refinement as cg_run; logs the (alpha, beta) of the first cycle, which give
+// the Lanczos tridiagonal of P^{-1/2} K_y P^{-1/2}.
+int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double* X, const mfgp_cg_opts& o,
+            mfgp_cg_info* info, double* coeff, int max_iter, const CgBufs& b, const PcgBufs& pb, hipStream_t s);
+
 }  // namespace mfgp

@@ -268,6 +268,14 @@ hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scrat
     return hipGetLastError();
 }
 
+hipError_t cg_update_rr(const CgState& st, int64_t n, int t, double* scratch, double* rr_out, hipStream_t s) {
+    const int G = stripe_blocks(n, t);
+    const int64_t S = (static_cast<int64_t>(G) * 256 / t) * t;
+    hipLaunchKernelGGL(cg_update_kernel, dim3(G), dim3(256), 0, s, st, n * t, t, S, scratch);
+    hipLaunchKernelGGL(dot_stage2, dim3(t), dim3(256), 0, s, scratch, G, t, rr_out);
+    return hipGetLastError();
+}
+
 hipError_t cg_restart(const CgState& st, const double* R64, int64_t n, int t, const int* restart,
                       hipStream_t s) {
     hipLaunchKernelGGL(cg_restart_kernel, dim3(nblk(n * t)), dim3(256), 0, s, st, R64, n * t, t,

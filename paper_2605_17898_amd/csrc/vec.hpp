@@ -28,6 +28,8 @@ int stripe_blocks(int64_t n, int t);
 hipError_t cg_alpha(const CgState& st, int t, hipStream_t s);
 hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scratch, double tol,
                               int log_coeffs, int max_iter, hipStream_t s);
+// x += alpha p, r -= alpha A p for active columns; rr_out[c] = r_c^T r_c (FP64).
+hipError_t cg_update_rr(const CgState& st, int64_t n, int t, double* scratch, double* rr_out, hipStream_t s);
 hipError_t cg_restart(const CgState& st, const double* R64, int64_t n, int t, const int* restart,
                       hipStream_t s);
 hipError_t cg_activate(const CgState& st, int t, const int* restart, const double* rr_new,

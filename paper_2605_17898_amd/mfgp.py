@@ -24,6 +24,7 @@ FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3}
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
 OP_MATVEC, OP_CG, OP_PREDICT, OP_MLL, OP_ADJOINT, OP_RESIDUAL = range(6)
+OP_PCHOL, OP_PAPPLY, OP_PCG, OP_PMLL = range(6, 10)
 
 
 class KernelT(C.Structure):
@@ -81,6 +82,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_batch_workspace_bytes": (SZ, [P]),
         "mfgp_batch_plan_info": (C.c_int, [P, P, P, P]),
         "mfgp_batch_mll_and_grad": (C.c_int, [P, P, P, P, OP_, P, P, P, IP, P, SZ, P]),
+        "mfgp_precond_workspace_bytes": (SZ, [I32, I64, I32, I32, I32, I32, I32]),
+        "mfgp_pivoted_cholesky": (C.c_int, [KP, P, I64, I32, P, P, P, SZ, P]),
+        "mfgp_precond_probes": (C.c_int, [P, I64, I32, C.c_float, P, P, I32, P, P]),
+        "mfgp_precond_apply": (C.c_int, [P, I64, I32, C.c_float, P, I32, P, P, P, SZ, P]),
+        "mfgp_precond_cg_solve": (C.c_int, [KP, P, I64, P, I32, P, P, I32, OP_, IP, P, P, SZ, P]),
+        "mfgp_precond_mll_and_grad": (C.c_int, [KP, P, I64, P, I32, P, P, I32, OP_, P, P, P, P, IP, P, SZ, P]),
         "mfgp_status_string": (C.c_char_p, [C.c_int]),
         "mfgp_last_hip_error": (C.c_int, []),
         "mfgp_version": (C.c_int, []),
@@ -346,6 +353,105 @@ def rademacher(seed: int, n: int, p: int, device="cuda") -> torch.Tensor:
     Z = torch.empty((n, p), dtype=torch.float32, device=device)
     _check(LIB.mfgp_rademacher(seed, n, p, _ptr(Z), _stream()), "rademacher")
     return Z
+
+
+# ---------------------------------------------------------------- preconditioning
+
+def precond_workspace_bytes(op: int, n: int, d: int, t: int, rank: int, precision: int = 0,
+                            max_iter: int = 0) -> int:
+    return int(LIB.mfgp_precond_workspace_bytes(op, n, d, t, rank, precision, max_iter))
+
+
+def pivoted_cholesky(kern: Kernel, X: torch.Tensor, rank: int):
+    """Rank-k pivoted Cholesky of s^2 k(X, X): (L [rank, n] float32, pivots [rank] int32)."""
+    _dev(X, torch.float32, "X")
+    n, d = X.shape
+    L = torch.empty((rank, n), dtype=torch.float32, device=X.device)
+    piv = torch.empty(rank, dtype=torch.int32, device=X.device)
+    ws = workspace(precond_workspace_bytes(OP_PCHOL, n, d, 1, rank), X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_pivoted_cholesky(C.byref(ks), _ptr(X), n, rank, _ptr(L), _ptr(piv), _ptr(ws), ws.numel(),
+                                     _stream()), "pivoted_cholesky")
+    return L, piv
+
+
+def precond_probes(L: torch.Tensor, noise: float, E: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
+    """z_c = L^T-factor e_c + sqrt(noise) g_c: probes from N(0, P) (E [rank, p], G [n, p])."""
+    _dev(L, torch.float32, "L")
+    _dev(E, torch.float32, "E")
+    _dev(G, torch.float32, "G")
+    k, n = L.shape
+    p = G.shape[1]
+    Z = torch.empty((n, p), dtype=torch.float32, device=G.device)
+    _check(LIB.mfgp_precond_probes(_ptr(L), n, k, noise, _ptr(E), _ptr(G), p, _ptr(Z), _stream()),
+           "precond_probes")
+    return Z
+
+
+def precond_apply(L: torch.Tensor, noise: float, R: torch.Tensor):
+    """(P^{-1} R, log|P|) for P = L^T-factor L + noise I."""
+    _dev(L, torch.float32, "L")
+    _dev(R, torch.float32, "R")
+    k, n = L.shape
+    t = _cols(R)
+    out = torch.empty_like(R)
+    ld = C.c_double()
+    ws = workspace(precond_workspace_bytes(OP_PAPPLY, n, 1, t, k), R.device)
+    _check(LIB.mfgp_precond_apply(_ptr(L), n, k, noise, _ptr(R), t, _ptr(out), C.byref(ld), _ptr(ws), ws.numel(),
+                                  _stream()), "precond_apply")
+    return out, ld.value
+
+
+def precond_cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, L: torch.Tensor, tol: float = 1e-6,
+                     max_iter: int = 0, precision: str = "fp32", want_lanczos: bool = False,
+                     check_every: int = 0, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None):
+    """Preconditioned CG on K_y X = B.  Returns (Xsol float64, info list, lanczos or None, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(B, torch.float32, "B")
+    _dev(L, torch.float32, "L")
+    n, d = X.shape
+    k = L.shape[0]
+    t = _cols(B)
+    o = cg_opts(tol, max_iter, check_every, -1, precision, False, progress=progress)
+    mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
+    Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
+    lan = torch.empty((t, mi, 2), dtype=torch.float64, device=B.device) if want_lanczos else None
+    info = (CgInfoT * t)()
+    ws = workspace(precond_workspace_bytes(OP_PCG, n, d, t, k, o.precision, max_iter), X.device)
+    ks = kern.struct(d)
+    st = LIB.mfgp_precond_cg_solve(C.byref(ks), _ptr(X), n, _ptr(B), t, _ptr(Xsol), _ptr(L), k, C.byref(o), info,
+                                   _ptr(lan), _ptr(ws), ws.numel(), _stream())
+    _check(st, "precond_cg_solve", allow)
+    return Xsol, _info_list(info, t), lan, st
+
+
+def precond_mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, Z: torch.Tensor, L: torch.Tensor,
+                         tol: float = 1e-6, max_iter: int = 0, precision: str = "fp32", want_grad: bool = True,
+                         want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None):
+    """MLL, log-det and gradient with the pivoted-Cholesky preconditioner; Z ~ N(0, P)."""
+    _dev(X, torch.float32, "X")
+    _dev(y, torch.float32, "y")
+    _dev(Z, torch.float32, "Z")
+    _dev(L, torch.float32, "L")
+    n, d = X.shape
+    k = L.shape[0]
+    p = Z.shape[1]
+    t = p + 1
+    o = cg_opts(tol, max_iter, 0, -1, precision, False, progress=progress)
+    mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
+    ws = workspace(precond_workspace_bytes(OP_PMLL, n, d, t, k, o.precision, mi), X.device)
+    ks = kern.struct(d)
+    npar = LIB.mfgp_num_params(C.byref(ks))
+    mll, ld = C.c_double(), C.c_double()
+    grad = (C.c_double * npar)() if want_grad else None
+    alpha = torch.empty(n, dtype=torch.float64, device=X.device) if want_alpha else None
+    info = (CgInfoT * t)()
+    st = LIB.mfgp_precond_mll_and_grad(C.byref(ks), _ptr(X), n, _ptr(y), p, _ptr(Z), _ptr(L), k, C.byref(o),
+                                       C.byref(mll), C.byref(ld), grad, _ptr(alpha), info, _ptr(ws), ws.numel(),
+                                       _stream())
+    _check(st, "precond_mll_and_grad", allow)
+    return dict(mll=mll.value, logdet=ld.value, grad=None if grad is None else list(grad),
+                alpha=alpha, info=_info_list(info, t), status=st)
 
 
 def timing_enable(on: bool = True) -> None:
