@@ -145,7 +145,7 @@ typedef struct {
                                      FP64 accumulation, x in FP64                          */
     int32_t replacements;         /* residual replacements applied (small drift only)       */
     int32_t drift_skips;          /* replacements refused because the recurrence had
-                                     drifted more than 1% from the true residual            */
+                                     drifted more than 10% from the true residual           */
 } mfgp_cg_info;
 
 /* Bytes of workspace a call needs.  op: mfgp_op; n rows; d dims; t columns

@@ -57,8 +57,8 @@ struct BSeg {
 
 constexpr int kSegRows = 2048;
 // Residual replacement keeps the direction only while |r_true - r_rec|^2 <=
-// 1e-4 |r_true|^2 (as in the single-problem solver).
-constexpr double kMaxDrift2 = 1e-4;
+// 1e-2 |r_true|^2 (as in the single-problem solver).
+constexpr double kMaxDrift2 = 1e-2;
 constexpr int kMaxReplaceGap = 2;   // largest check interval with replacement
 constexpr int kWidth = MFGP_MAX_D + 1;   // adjoint partial width
 
