@@ -245,6 +245,8 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the single BF16-x2 comparison step")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--pc-rank", type=int, default=256,
+                    help="rank of the preconditioned comparison step (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -394,6 +396,39 @@ def main() -> int:
                 "mll": rb["mll"],
                 "logdet": rb["logdet"],
             }
+    if args.precision == "fp32" and not args.no_compare and args.pc_rank > 0:
+        # The same MLL + gradient with the rank-k pivoted-Cholesky preconditioner
+        # (factor build, probes z ~ N(0, P), preconditioned CG, SLQ, adjoint):
+        # what the unpreconditioned CG of the paper lacks.
+        print(f"[bench] preconditioned step, rank {args.pc_rank}", file=sys.stderr, flush=True)
+        k = args.pc_rank
+        E = torch.from_numpy(inputs.gaussian_rhs(401, k, Z.shape[1])).cuda()
+        G = torch.from_numpy(inputs.gaussian_rhs(402, w.n, Z.shape[1])).cuda()
+        torch.cuda.synchronize()
+        mfgp.timing_enable(True)
+        t1 = time.perf_counter()
+        L, _ = mfgp.pivoted_cholesky(kern, X, k)
+        Zp = mfgp.precond_probes(L, w.noise, E, G)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t1
+        rp = mfgp.precond_mll_and_grad(kern, X, y, Zp, L, tol=1e-6, want_alpha=True)
+        mfgp.predict_mean(kern, X, Xs, rp["alpha"].float())
+        torch.cuda.synchronize()
+        ep = time.perf_counter() - t1
+        php = mfgp.timing_phases()
+        mfgp.timing_enable(False)
+        line[f"pcg_rank{k}"] = {
+            "ms_per_step": ep * 1e3,
+            "factor_s": tb,
+            "cg_solve_s": php["cg_ms"] * 1e-3,
+            "mll_grad_s": (php["cg_ms"] + php["slq_ms"] + php["adjoint_ms"]) * 1e-3,
+            "cg_iters_max": max(i["iters"] for i in rp["info"]),
+            "cg_refinements_max": max(i["refinements"] for i in rp["info"]),
+            "rel_resid_true_max": max(i["rel_resid_true"] for i in rp["info"]),
+            "mll": rp["mll"],
+            "logdet": rp["logdet"],
+            "probes": "z ~ N(0, P) (Gaussian), not the Rademacher probes of the FP32 step",
+        }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
