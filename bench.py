@@ -245,7 +245,7 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the single BF16-x2 comparison step")
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--pc-rank", type=int, default=256,
+    ap.add_argument("--pc-rank", type=int, default=1024,
                     help="rank of the preconditioned comparison step (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:

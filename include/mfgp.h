@@ -17,7 +17,8 @@
  *            "host".  The library never allocates: scratch comes from the
  *            caller's workspace `ws` of `ws_bytes` bytes (size it with
  *            mfgp_workspace_bytes; 256-byte alignment is handled inside).  No
- *            pointer is kept after a call returns.
+ *            pointer is kept after a call returns.  (Exception: the
+ *            preconditioned calls' rocBLAS handle, see "preconditioning".)
  * Streams    `stream` is a hipStream_t (NULL = the default stream).  Calls
  *            that return only device results are asynchronous on it; calls
  *            that return host values synchronise it before returning.
@@ -36,7 +37,8 @@
  * Gradients  are with respect to the positive parameters in the order
  *            [l_1 .. l_d] (ard) or [l] (shared), then s2, then sigma^2.
  * Threads    The library is reentrant: no mutable globals besides the
- *            thread-local last HIP error.
+ *            thread-local last HIP error and the preconditioned calls'
+ *            thread-local rocBLAS handles.
  */
 #ifndef MFGP_H
 #define MFGP_H
@@ -307,7 +309,12 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
  *   tr(K_y^{-1} dK) ~ (1/p) sum_c (K_y^{-1} z_c)^T dK (P^{-1} z_c).
  * L is a device array [rank][n] float32 (row q holds column q of the factor),
  * caller-owned; it is built by mfgp_pivoted_cholesky and read by the others.
- * Workspace sizes come from mfgp_precond_workspace_bytes. */
+ * Workspace sizes come from mfgp_precond_workspace_bytes.
+ * The Woodbury products run as rocBLAS FP64 GEMMs and triangular solves
+ * (atomics off: reproducible).  The first call of mfgp_precond_apply,
+ * _cg_solve or _mll_and_grad on a device from a host thread creates a rocBLAS
+ * handle for that pair and keeps it until the process ends; rocBLAS
+ * allocates its own device memory for it then.  Every later call reuses it. */
 
 /* Bytes of workspace of a preconditioned call: op MFGP_OP_PCHOL / PAPPLY /
  * PCG / PMLL; t right-hand sides (probes + 1 for PMLL); rank k <= min(n,

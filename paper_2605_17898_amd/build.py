@@ -79,7 +79,8 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
                 print(r.stdout, r.stderr, file=sys.stderr)
     objs = [os.path.join(BUILD, o) for _, o, _ in UNITS] + [os.path.join(BUILD, o) for _, o in HOST_UNITS]
     tmp = LIB + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas",
+          "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -13,7 +13,8 @@ struct Precond {
     int64_t n = 0;
     double s2n = 0.0;       // sigma^2
     double logdet = 0.0;    // log|P|
-    double* C = nullptr;    // device [k][k]: lower Cholesky factor of S = s2n I + L^T L
+    double* C = nullptr;    // device [k x k] column-major: lower Cholesky factor of S = s2n I + L^T L
+    double* L64 = nullptr;  // device FP64 copy of L (column-major n x k)
 };
 
 // Device scratch (doubles) of pivoted_cholesky for n rows.
@@ -25,8 +26,8 @@ hipError_t pivoted_cholesky(const Operator& op, int k, float* L, int* piv, doubl
 
 // Device scratch (doubles) of the Woodbury data and one application to t columns.
 size_t pc_scratch_doubles(int64_t n, int k, int t);
-// Forms S = s2n I + L^T L, factors it on the host (FP64), uploads C and sets
-// logdet.  Synchronises the stream.  Returns hipErrorInvalidValue if S is not
+// Copies L to FP64, forms S = s2n I + L^T L (dgemm), factors it on the host
+// (FP64), uploads C and sets logdet.  Synchronises the stream.  Returns hipErrorInvalidValue if S is not
 // positive definite.
 hipError_t pc_setup(Precond& pc, double* scratch, hipStream_t s);
 // Z = P^{-1} R for [n, t] blocks (Woodbury, FP64 accumulation).

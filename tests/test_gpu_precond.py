@@ -53,21 +53,21 @@ def test_pivoted_cholesky_ragged_and_rank_floor(mf):
 
 @pytest.mark.parametrize("rank", [0, 1, 17, 64])
 def test_precond_apply_probes_and_logdet(mf, rank):
-    banner(f"Woodbury apply and probes, rank {rank}, n=1500, t=9")
-    w = inputs.random_problem(503, 1500, 3, "matern32", ard=True, noise=0.03)
+    banner(f"Woodbury apply and probes, rank {rank}, n=1537 (ragged split), t=9")
+    w = inputs.random_problem(503, 1537, 3, "matern32", ard=True, noise=0.03)
     if rank:
         L, _ = mf.pivoted_cholesky(mkern(w), dev(w.X), rank)
     else:
-        L = dev(np.zeros((0, 1500), np.float32))
+        L = dev(np.zeros((0, 1537), np.float32))
     L64 = host(L).T.astype(np.float64)
     s2n = float(np.float32(w.noise))     # the library holds sigma^2 in binary32
-    R = inputs.gaussian_rhs(7, 1500, 9)
+    R = inputs.gaussian_rhs(7, 1537, 9)
     Z, ld = mf.precond_apply(L, w.noise, dev(R))
     ref = precond.precond_solve(L64, s2n, R.astype(np.float64))
     assert col_rel_err(host(Z), ref).max() <= 1e-5
-    assert ld == pytest.approx(precond.precond_logdet(L64, s2n, 1500), rel=1e-10)
+    assert ld == pytest.approx(precond.precond_logdet(L64, s2n, 1537), rel=1e-10)
     E = inputs.gaussian_rhs(8, max(rank, 1), 5)[:rank] if rank else np.zeros((0, 5), np.float32)
-    G = inputs.gaussian_rhs(9, 1500, 5)
+    G = inputs.gaussian_rhs(9, 1537, 5)
     Zp = mf.precond_probes(L, w.noise, dev(np.ascontiguousarray(E)), dev(G))
     np.testing.assert_allclose(host(Zp), precond.precond_probes(L64, s2n, E, G), rtol=1e-5, atol=1e-5)
 
