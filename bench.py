@@ -47,7 +47,14 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # reading of the same counters (summary in profiles/).  Valid only for the
 # kernel named below; None for any other.
 HYB_TRAFFIC_BYTES = 2.664e8
-HYB_KERNEL = "sweep_hyb_kernel<RBF, d=4, NT=2, TV=1>"
+GRAM_TRAFFIC_BYTES = None
+# Dominant kernel of the step per precision: (name, bound, HBM bytes per launch).
+STEP_KERNELS = {
+    "fp32": ("sweep_gram_kernel<d=4, NT=2, TV=1> (RBF squared distances and the K-tile x V "
+             "contraction on v_mfma_f32_16x16x4_f32, exp2 on the VALU)", "mfma", GRAM_TRAFFIC_BYTES),
+    "fp32_direct": ("sweep_hyb_kernel<RBF, d=4, NT=2, TV=1> (FP32 entries from direct differences on "
+                    "the VALU, contraction on v_mfma_f32_16x16x4_f32)", "alu", HYB_TRAFFIC_BYTES),
+}
 METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
 
 
@@ -170,8 +177,9 @@ def matvec_leg(args) -> int:
     kern = mfgp.Kernel(full.family, full.lengthscale, full.outputscale, full.noise)
     Xf = torch.from_numpy(full.X).cuda()
     Vall = torch.from_numpy(np.concatenate([full.y[:, None], full.Z], axis=1)).cuda()
-    cases = [(full.n, t, prec) for t in (1, 33) for prec in ("fp32", "fp32_valu", "bf16x1", "bf16x2", "bf16x3")]
-    cases += [(n, 1, "fp32") for n in (2000, 5000, 10000, 20000, 50000)]
+    cases = [(full.n, t, prec) for t in (1, 33)
+             for prec in ("fp32", "fp32_direct", "fp32_valu", "bf16x1", "bf16x2", "bf16x3")]
+    cases += [(n, 1, prec) for n in (2000, 5000, 10000, 20000, 50000) for prec in ("fp32_gram", "fp32_direct")]
     for n, t, prec in cases:
         X = Xf[:n].contiguous()
         V = Vall[:n, :t].contiguous()
@@ -238,12 +246,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x1", "bf16x2", "bf16x3"])
+    ap.add_argument("--precision", default="fp32",
+                    choices=["fp32", "fp32_direct", "fp32_valu", "bf16x1", "bf16x2", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k", "matvec", "small"])
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the single BF16-x2 comparison step")
+                    help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--pc-rank", type=int, default=1024,
                     help="rank of the preconditioned comparison step (0 skips it)")
@@ -321,7 +330,7 @@ def main() -> int:
 
     r = results[-1][0]
     info = r["info"]
-    dom = mfma if args.precision != "fp32" else f32
+    dom = f32 if args.precision.startswith("fp32") else mfma
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12 if dom["ms"] > 0 else 0.0
     line = {
         "metric": METRIC,
@@ -353,15 +362,14 @@ def main() -> int:
         "matvec_entries_per_s": f32["entries"] / (f32["ms"] * 1e-3) if f32["ms"] > 0 else 0.0,
         "sweep_ms": {"fp32": f32["ms"], "fp64acc": f64["ms"], "adjoint": adj["ms"], "mfma": mfma["ms"]},
         "roofline": {
-            "bound": "alu",
+            "bound": STEP_KERNELS.get(args.precision, ("", "mfma", None))[1],
             "achieved": achieved,
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": HYB_TRAFFIC_BYTES if args.precision == "fp32" else None,
+            "traffic": STEP_KERNELS.get(args.precision, ("", "", None))[2],
             "traffic_unit": "bytes per launch",
-            "kernel": (HYB_KERNEL + " (FP32 entries on the VALU, contraction on "
-                       "v_mfma_f32_16x16x4_f32)") if args.precision == "fp32" else "mfma sweep",
+            "kernel": STEP_KERNELS.get(args.precision, ("bf16 mfma sweep", "", None))[0],
             "flop_per_entry": 3 * 4 + 1 + 2 * 33,
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
         },
@@ -370,7 +378,7 @@ def main() -> int:
         # The same step with the K-tile x V contraction on the bf16 matrix cores
         # (FP32 entries, FP64-accumulated residual replacement and refinement to
         # the same 1e-6): the hi/lo split (x2) and the exact three-way split (x3).
-        for form in ("bf16x2", "bf16x3"):
+        for form in ("fp32_direct", "bf16x2", "bf16x3"):
             print(f"[bench] {form} comparison step", file=sys.stderr, flush=True)
             torch.cuda.synchronize()
             mfgp.timing_enable(True)
@@ -380,7 +388,7 @@ def main() -> int:
             torch.cuda.synchronize()
             eb = time.perf_counter() - t1
             ab = mfgp.timing_read(-1)
-            mb = mfgp.timing_read(mfgp.SWEEP_MFMA)
+            mb = mfgp.timing_read(mfgp.SWEEP_F32 if form.startswith("fp32") else mfgp.SWEEP_MFMA)
             phb = mfgp.timing_phases()
             mfgp.timing_enable(False)
             line[form] = {
@@ -391,8 +399,8 @@ def main() -> int:
                 "cg_iters_max": max(i["iters"] for i in rb["info"]),
                 "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
                 "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
-                "mfma_sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
-                "mfma_sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
+                "sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
+                "sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
                 "mll": rb["mll"],
                 "logdet": rb["logdet"],
             }

@@ -61,18 +61,32 @@ typedef enum {
     MFGP_MATERN52 = 3
 } mfgp_family;
 
-/* Arithmetic of the K-tile x V contraction (kernel entries are always float32). */
+/* Arithmetic of the product (kernel entries are always float32).  The
+ * FP32-class forms (0, 3, 5, 6) are held to the FP32 bar (per-column
+ * relative error <= 1e-5 against FP64); the bf16 forms are described below. */
 typedef enum {
-    MFGP_FP32 = 0,    /* FP32 vector ALU, FP32 accumulation                        */
+    MFGP_FP32 = 0,    /* FP32, fastest form that applies:
+                         - square RBF products with n >= 16384 and t = 1 or
+                           16 k + {0, 1} (k = 1..4): squared distances from the
+                           Gram form |g_i|^2 + |g_j|^2 - 2 g_i.g_j on FP32 MFMA
+                           (g = prescaled points minus their mean), checked on
+                           the device: where max |g|^2 > 64 the launch uses
+                           direct differences instead (the form's error grows
+                           with |g|^2);
+                         - else, for t = 16 k + {0, 1}: direct differences, the
+                           16-column tiles of the contraction on FP32 MFMA
+                           (v_mfma_f32_16x16x4_f32);
+                         - else the vector ALU (MFGP_FP32_VALU).             */
     MFGP_BF16X1 = 1,  /* entries and V rounded to bf16, MFMA, FP32 accumulation    */
     MFGP_BF16X2 = 2,  /* bf16 hi/lo split of both operands (3 MFMA products)        */
-    MFGP_FP32_VALU = 3, /* FP32 with the contraction kept on the vector ALU; MFGP_FP32
-                          itself moves 16-column tiles of the contraction onto FP32
-                          MFMA (v_mfma_f32_16x16x4_f32) when t = 16 k or 16 k + 1,
-                          k = 1..4                                                    */
-    MFGP_BF16X3 = 4    /* exact three-way bf16 split of both operands, 6 of the 9
+    MFGP_FP32_VALU = 3, /* FP32 direct differences, contraction on the vector ALU   */
+    MFGP_BF16X3 = 4,  /* exact three-way bf16 split of both operands, 6 of the 9
                           MFMA products (the dropped ones are < 2^-23 |K V|):
                           binary32-class products on the bf16 matrix cores        */
+    MFGP_FP32_DIRECT = 5, /* MFGP_FP32 without the Gram form                       */
+    MFGP_FP32_GRAM = 6    /* MFGP_FP32 with the Gram form at any n (square RBF
+                             products; otherwise as MFGP_FP32_DIRECT).  Not
+                             offered by the batched calls (MFGP_UNSUPPORTED).   */
 } mfgp_precision;
 /* The bf16 forms take t <= 65 columns; for t = 32 k + 1 column 0 (y of a
  * [y, probes] block) is contracted on the vector ALU in FP32. */
@@ -118,7 +132,8 @@ typedef struct {
                              0 = min(max(2n, 64), 20000)                                   */
     int32_t check_every;  /* iterations between host convergence checks; 0 = automatic       */
     int32_t max_refine;   /* residual recomputations / restarts allowed; < 0 = default 8      */
-    int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries, FP64 sums) */
+    int32_t precision;    /* mfgp_precision of the CG matvec (residuals always FP32 entries from
+                             direct differences, FP64 sums) */
     int32_t warm_start;   /* nonzero: Xsol holds the initial guess x0 on entry                */
     int32_t no_replacement; /* nonzero: no residual replacement while iterating (restarts
                              from the recomputed residual after each cycle only).  Even

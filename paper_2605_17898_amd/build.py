@@ -45,6 +45,7 @@ UNITS = [
     ("timing.hip", "timing.o", []),
     ("batch.hip", "batch.o", []),
     ("hybrid.hip", "hybrid.o", []),
+    ("gram.hip", "gram.o", []),
     ("precond.hip", "precond.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]

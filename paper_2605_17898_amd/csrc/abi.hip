@@ -91,7 +91,7 @@ static int check_opts(const mfgp_cg_opts* o) {
     if (!o) return MFGP_ERR_ARG;
     if (!std::isfinite(o->tol) || !(o->tol > 0.0)) return MFGP_ERR_ARG;
     if (o->max_iter < 0) return MFGP_ERR_ARG;
-    if (o->precision < MFGP_FP32 || o->precision > MFGP_BF16X3) return MFGP_ERR_ARG;
+    if (o->precision < MFGP_FP32 || o->precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
     if (!precision_supported(o->precision)) return MFGP_UNSUPPORTED;
     return MFGP_OK;
 }
@@ -130,8 +130,8 @@ struct MatvecWs { float* U; void* scratch; };
 static MatvecWs carve_matvec(Carver& cv, int64_t n, int d, int t, int precision) {
     MatvecWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
-    if (precision == MFGP_FP32 || precision == MFGP_FP32_VALU)
-        w.scratch = cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision == MFGP_FP32));
+    if (is_fp32_class(precision))
+        w.scratch = cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision));
     else
         w.scratch = cv.take<char>(mfma_scratch_bytes(n, n, t, precision));
     return w;
@@ -160,7 +160,7 @@ static PredictWs carve_predict(Carver& cv, int64_t n, int d, int64_t m, int t) {
     PredictWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
     w.Us = cv.take<float>(static_cast<size_t>(m) * d);
-    w.scratch = cv.take<char>(apply_fp32_scratch_bytes(m, n, t, true));
+    w.scratch = cv.take<char>(apply_fp32_scratch_bytes(m, n, t, MFGP_FP32));
     return w;
 }
 
@@ -280,7 +280,7 @@ int mfgp_num_params(const mfgp_kernel* k) {
 size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
                             int32_t max_iter) {
     if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1) return 0;
-    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return 0;
     Carver cv(nullptr);
     switch (op) {
         case MFGP_OP_MATVEC: carve_matvec(cv, n, d, t, precision); break;
@@ -306,7 +306,7 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !V || !KV || !ws || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
-    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return MFGP_ERR_ARG;
+    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
     if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
     if ((st = check_precision_cols(precision, t)) != MFGP_OK) return st;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, precision, 0))
@@ -316,8 +316,8 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     MatvecWs w = carve_matvec(cv, n, kern->d, t, precision);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
-    if (precision == MFGP_FP32 || precision == MFGP_FP32_VALU)
-        ABI_CHECK(apply_fp32(op, op.U, n, V, t, KV, true, V, w.scratch, precision == MFGP_FP32, s));
+    if (is_fp32_class(precision))
+        ABI_CHECK(apply_fp32(op, op.U, n, V, t, KV, true, V, w.scratch, precision, s));
     else
         ABI_CHECK(apply_mfma(op, op.U, n, V, t, KV, true, V, precision, w.scratch, s));
     return MFGP_OK;
@@ -382,7 +382,7 @@ int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const 
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     ABI_CHECK(launch_prescale(Xs, m, kern->d, op.fac, w.Us, s));
-    ABI_CHECK(apply_fp32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, true, s));
+    ABI_CHECK(apply_fp32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, MFGP_FP32, s));
     return MFGP_OK;
 }
 
@@ -548,7 +548,7 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
 size_t mfgp_precond_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t rank,
                                     int32_t precision, int32_t max_iter) {
     if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1 || rank < 0 || rank > n || rank > MFGP_MAX_RANK) return 0;
-    if (precision < MFGP_FP32 || precision > MFGP_BF16X3) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return 0;
     Carver cv(nullptr);
     switch (op) {
         case MFGP_OP_PCHOL: carve_pchol(cv, n, d); break;

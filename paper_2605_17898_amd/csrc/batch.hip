@@ -806,7 +806,8 @@ static bool is_bf16(int precision) {
 static hipError_t launch_batched_sweep(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
                                        const float* V, float* part, hipStream_t s) {
     if (is_bf16(P.precision)) return launch_bmfma(P, w, ntiles, V, part, s);
-    if (P.hybrid && P.precision == MFGP_FP32) return launch_bhyb(P, w, ntiles, V, part, s);
+    if (P.hybrid && (P.precision == MFGP_FP32 || P.precision == MFGP_FP32_DIRECT))
+        return launch_bhyb(P, w, ntiles, V, part, s);
     return launch_bsweep(P.family, P.t, w, ntiles, V, part, s);
 }
 
@@ -1059,7 +1060,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                             mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || !X || !y || !opts || !mll || !ws) return MFGP_ERR_ARG;
     if (!std::isfinite(opts->tol) || !(opts->tol > 0.0) || opts->max_iter < 0) return MFGP_ERR_ARG;
-    if (opts->precision < MFGP_FP32 || opts->precision > MFGP_BF16X3) return MFGP_ERR_ARG;
+    if (opts->precision < MFGP_FP32 || opts->precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
+    if (opts->precision == MFGP_FP32_GRAM) return MFGP_UNSUPPORTED;   // batched sweeps: direct differences
     if (is_bf16(opts->precision) && col_tiles(plan->t) != 1) return MFGP_UNSUPPORTED;
     if (ws_bytes < mfgp_batch_workspace_bytes(plan)) return MFGP_ERR_WORKSPACE;
     mfgp_batch_plan_s& P = *plan;

@@ -62,8 +62,8 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
     b.ints = cv.take<int>(6 * static_cast<size_t>(t));
     b.dots = cv.take<double>(dots_scratch_doubles(n, t));
     b.resid = cv.take<double>(resid_scratch_doubles(n, t));
-    if (precision == MFGP_FP32 || precision == MFGP_FP32_VALU)
-        b.apply = reinterpret_cast<float*>(cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision == MFGP_FP32)));
+    if (is_fp32_class(precision))
+        b.apply = reinterpret_cast<float*>(cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision)));
     else
         b.apply = reinterpret_cast<float*>(cv.take<char>(mfma_scratch_bytes(n, n, t, precision)));
     return b;
@@ -91,8 +91,7 @@ static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
 
 static hipError_t apply_op(const Operator& op, const float* V, int t, float* out, int precision,
                            float* scratch, hipStream_t s) {
-    if (precision == MFGP_FP32 || precision == MFGP_FP32_VALU)
-        return apply_fp32(op, op.U, op.n, V, t, out, true, V, scratch, precision == MFGP_FP32, s);
+    if (is_fp32_class(precision)) return apply_fp32(op, op.U, op.n, V, t, out, true, V, scratch, precision, s);
     return apply_mfma(op, op.U, op.n, V, t, out, true, V, precision, scratch, s);
 }
 

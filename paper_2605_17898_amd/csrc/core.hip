@@ -227,16 +227,32 @@ hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float
     return hipSuccess;
 }
 
-size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, bool allow_mfma) {
+// Form selection of the FP32-class products.  MFGP_FP32 takes the Gram form
+// for square RBF products of at least kGramMinN rows (below that the
+// preparation launches are a visible share of a sweep), else the MFMA-
+// contraction form where t = 16 k + {0, 1}, else the VALU form;
+// MFGP_FP32_GRAM takes the Gram form at any size, MFGP_FP32_DIRECT never.
+constexpr int64_t kGramMinN = 16384;
+
+static bool use_gram(const Operator& op, const float* Ur, int64_t m, int t, int precision) {
+    if (precision != MFGP_FP32 && precision != MFGP_FP32_GRAM) return false;
+    if (op.family != MFGP_RBF || Ur != op.U || m != op.n || !gram_supported(t)) return false;
+    return precision == MFGP_FP32_GRAM || op.n >= kGramMinN;
+}
+
+size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
     size_t b = apply_scratch_floats(m, n, t) * sizeof(float);
-    if (allow_mfma && hybrid_supported(t)) b = std::max(b, hybrid_scratch_bytes(m, n, t));
+    if (precision != MFGP_FP32_VALU && hybrid_supported(t)) b = std::max(b, hybrid_scratch_bytes(m, n, t));
+    if ((precision == MFGP_FP32 || precision == MFGP_FP32_GRAM) && m == n && gram_supported(t))
+        b = std::max(b, gram_scratch_bytes(n, t));
     return b;
 }
 
 hipError_t apply_fp32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
-                      float* out, bool with_noise, const float* Vself, void* scratch, bool allow_mfma,
+                      float* out, bool with_noise, const float* Vself, void* scratch, int precision,
                       hipStream_t s) {
-    if (allow_mfma && hybrid_supported(t))
+    if (use_gram(op, Ur, m, t, precision)) return apply_gram(op, V, t, out, with_noise, Vself, scratch, s);
+    if (precision != MFGP_FP32_VALU && hybrid_supported(t))
         return apply_hybrid(op, Ur, m, V, t, out, with_noise, Vself, scratch, s);
     return apply_f32(op, Ur, m, V, t, out, with_noise, Vself, static_cast<float*>(scratch), s);
 }

@@ -1,0 +1,268 @@
+// FP32 RBF sweep with the squared distances on FP32 MFMA (the Gram form).
+//
+// The hybrid sweep (hybrid.hip) spends d subtractions and d FMAs per entry on
+// the distance, most of its vector-ALU work.  For the RBF kernel, whose entry
+// 2^(-r2) is smooth in r2, the squared distance can instead come from
+//   r2 = |g_i|^2 + |g_j|^2 - 2 g_i . g_j,     g = u - mean(u),
+// with the dot products of a 16 x 16 tile in one v_mfma_f32_16x16x4_f32
+// (d <= 4; two for d <= 8) and the norms as its accumulator input, leaving
+// the vector ALU one add and one exp2 per entry (the operand layout is in
+// gram_kernels.hpp).  Translating all points by their mean leaves every
+// distance unchanged and keeps the norms small.
+//
+// Accuracy.  The form cancels: r2 carries an absolute rounding error of a
+// few ulp of max |g|^2, where the direct differences err relative to r2
+// itself.  In a simulation of the FP32 arithmetic the per-column relative
+// matvec error against FP64 was 8.8e-7 at max |g|^2 = 30 (N = 1e5, d = 4,
+// l = 0.3) and 3.5e-6 at 144 (N = 5e5, d = 2, l = 0.05).  Every launch
+// therefore checks max |g|^2 (computed on the device before the sweep, no
+// host round trip) against kGramMaxNorm = 64 and, above it, runs the
+// direct-difference body of the hybrid sweep on the same fragments instead.
+// A slightly negative r2 from the cancellation (i ~ j) gives an entry a few
+// ulp above 1: within the same error, so r2 is not clamped.
+//
+// The operator stays symmetric: the entry of (i, j) and of (j, i) adds the
+// same two norms and the same products (-2 g_j[k]) g_i[k] = (-2 g_i[k]) g_j[k]
+// (the factor 2 is exact) in the same order.
+#include <algorithm>
+
+#include "gram_kernels.hpp"
+#include "internal.hpp"
+
+namespace mfgp {
+
+namespace {
+
+constexpr float kGramMaxNorm = 64.0f;
+constexpr int kMeanBlocks = 64;
+
+// Per-block column sums of U [n][d] over a contiguous row range (FP64).
+__global__ __launch_bounds__(256) void gram_mean_stage1(const float* __restrict__ U, int64_t n, int d,
+                                                        double* __restrict__ part) {
+    __shared__ double red[256];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    for (int k = 0; k < d; ++k) {
+        double acc = 0.0;
+        for (int64_t j = r0 + threadIdx.x; j < r1; j += 256) acc += static_cast<double>(U[j * d + k]);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x * MFGP_MAX_D + k] = red[0];
+        __syncthreads();
+    }
+}
+
+// mu[k] = mean of column k (fixed order over the block sums); clears the
+// running maximum of the norms.
+__global__ void gram_mean_stage2(const double* __restrict__ part, int nb, int d, int64_t n,
+                                 float* __restrict__ mu, unsigned* __restrict__ gmax) {
+    const int k = threadIdx.x;
+    if (k < d) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b * MFGP_MAX_D + k];
+        mu[k] = static_cast<float>(s / static_cast<double>(n));
+    }
+    if (k == 0) *gmax = 0u;
+}
+
+// G[j] = -2 (u_j - mu) zero-padded to DG, nrm[j] = |u_j - mu|^2, and the
+// maximum norm (as the bits of a non-negative float, which order like the
+// values) into gmax.
+template <int DG>
+__global__ __launch_bounds__(256) void gram_prep_kernel(const float* __restrict__ U, int64_t n, int d,
+                                                        const float* __restrict__ mu, float* __restrict__ G,
+                                                        float* __restrict__ nrm, unsigned* __restrict__ gmax) {
+    __shared__ float red[256];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    float nj = 0.0f;
+    if (j < n) {
+#pragma unroll
+        for (int k = 0; k < DG; ++k) {
+            const float g = k < d ? U[j * d + k] - mu[k] : 0.0f;
+            nj = fmaf(g, g, nj);
+            G[j * DG + k] = -2.0f * g;
+        }
+        nrm[j] = nj;
+    }
+    red[threadIdx.x] = nj;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(gmax, __float_as_uint(red[0]));
+}
+
+// Fragments of the hybrid sweep (step q, lane l: V[4 q + l / 16][...]) with
+// |g_j|^2 behind them; steps cover j < n rounded up to 16.
+__global__ void pack_gfrag_kernel(const float* __restrict__ V, const float* __restrict__ nrm, int64_t n,
+                                  int t, int nt, int tv, int64_t nsteps, float* __restrict__ F) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int WS = nt + tv + 1;
+    if (idx >= nsteps * 64 * WS) return;
+    const int w = static_cast<int>(idx % WS);
+    const int64_t lq = idx / WS;
+    const int l = static_cast<int>(lq % 64);
+    const int64_t q = lq / 64;
+    const int64_t j = q * kHK + l / 16;
+    if (w < nt + tv) {
+        const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
+        F[idx] = (j < n) ? V[j * t + c] : 0.0f;
+    } else {
+        F[idx] = nrm[j < n ? j : n - 1];
+    }
+}
+
+template <int D, int NT, int TV>
+__global__ __launch_bounds__(kBlock) void sweep_gram_kernel(const float* __restrict__ U, const float* __restrict__ G,
+                                                            const float* __restrict__ nrm,
+                                                            const unsigned* __restrict__ gmax,
+                                                            const float* __restrict__ F, int64_t n, int t,
+                                                            int chunks, int64_t jchunk, float* __restrict__ partial) {
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;   // multiple of 16
+    const int64_t rbase = static_cast<int64_t>(rb) * kBlock;
+    float* out = partial + static_cast<int64_t>(ch) * n * t + rbase * t;
+    if (__uint_as_float(*gmax) <= kGramMaxNorm)
+        gram_block<D <= 4 ? 4 : 8, NT, TV>(G, nrm, F, n, t, rbase, j0, j0 + jchunk, out);
+    else
+        hyb_block<MFGP_RBF, D, NT, TV, NT + TV + 1>(U, U, F, n, n, t, rbase, j0, j0 + jchunk, out);
+}
+
+bool gram_shape(int t, int& nt, int& tv) {
+    if (t == 1) {
+        nt = 0;
+        tv = 1;
+        return true;
+    }
+    nt = t / 16;
+    tv = t % 16;
+    return nt >= 1 && nt <= 4 && tv <= 1;
+}
+
+SweepPlan plan_gram(int64_t n) {
+    SweepPlan p = plan_sweep(n, n);
+    p.jchunk = (p.jchunk + kGJ - 1) / kGJ * kGJ;
+    return p;
+}
+
+struct GramLayout {
+    size_t frag, part, g, nrm, mpart, mu, gmax, total;
+};
+
+inline size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+GramLayout gram_layout(int64_t n, int t) {
+    int nt = 0, tv = 0;
+    gram_shape(t, nt, tv);
+    const SweepPlan p = plan_gram(n);
+    const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
+    GramLayout L{};
+    size_t off = 0;
+    L.frag = off;
+    off += up256(static_cast<size_t>(nsteps) * 64 * (nt + tv + 1) * sizeof(float));
+    L.part = off;
+    off += up256(static_cast<size_t>(p.chunks) * n * t * sizeof(float));
+    L.g = off;
+    off += up256(static_cast<size_t>(n) * 8 * sizeof(float));
+    L.nrm = off;
+    off += up256(static_cast<size_t>(n) * sizeof(float));
+    L.mpart = off;
+    off += up256(static_cast<size_t>(kMeanBlocks) * MFGP_MAX_D * sizeof(double));
+    L.mu = off;
+    off += 256;
+    L.gmax = off;
+    off += 256;
+    L.total = off;
+    return L;
+}
+
+template <int D>
+hipError_t launch_gram_d(int nt, int tv, const float* U, const float* G, const float* nrm, const unsigned* gmax,
+                         const float* F, int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+#define MFGP_GRAM_CASE(NTV, TVV)                                                                        \
+    if (nt == NTV && tv == TVV) {                                                                       \
+        hipLaunchKernelGGL((sweep_gram_kernel<D, NTV, TVV>), grid, dim3(kBlock), 0, s, U, G, nrm, gmax, F, \
+                           n, t, p.chunks, p.jchunk, partial);                                          \
+        return hipGetLastError();                                                                       \
+    }
+    MFGP_GRAM_CASE(0, 1)
+    MFGP_GRAM_CASE(1, 0) MFGP_GRAM_CASE(1, 1) MFGP_GRAM_CASE(2, 0) MFGP_GRAM_CASE(2, 1)
+    MFGP_GRAM_CASE(3, 0) MFGP_GRAM_CASE(3, 1) MFGP_GRAM_CASE(4, 0) MFGP_GRAM_CASE(4, 1)
+#undef MFGP_GRAM_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool gram_supported(int t) {
+    int nt, tv;
+    return gram_shape(t, nt, tv);
+}
+
+size_t gram_scratch_bytes(int64_t n, int t) {
+    if (!gram_supported(t)) return 0;
+    return gram_layout(n, t).total + 1024;
+}
+
+hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, float s2,
+                           float sig2, const float* Vself, float* out, hipStream_t s);
+
+hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, bool with_noise, const float* Vself,
+                      void* scratch, hipStream_t s) {
+    int nt, tv;
+    if (op.family != MFGP_RBF || op.d < 1 || op.d > 8 || !gram_shape(t, nt, tv)) return hipErrorNotSupported;
+    const int64_t n = op.n;
+    const SweepPlan p = plan_gram(n);
+    const GramLayout L = gram_layout(n, t);
+    char* base = static_cast<char*>(scratch);
+    float* F = reinterpret_cast<float*>(base + L.frag);
+    float* partial = reinterpret_cast<float*>(base + L.part);
+    float* G = reinterpret_cast<float*>(base + L.g);
+    float* nrm = reinterpret_cast<float*>(base + L.nrm);
+    double* mpart = reinterpret_cast<double*>(base + L.mpart);
+    float* mu = reinterpret_cast<float*>(base + L.mu);
+    unsigned* gmax = reinterpret_cast<unsigned*>(base + L.gmax);
+    const int nb = static_cast<int>(std::min<int64_t>(kMeanBlocks, (n + 255) / 256));
+
+    hipLaunchKernelGGL(gram_mean_stage1, dim3(nb), dim3(256), 0, s, op.U, n, op.d, mpart);
+    hipLaunchKernelGGL(gram_mean_stage2, dim3(1), dim3(64), 0, s, mpart, nb, op.d, n, mu, gmax);
+    const unsigned pblocks = static_cast<unsigned>((n + 255) / 256);
+    if (op.d <= 4)
+        hipLaunchKernelGGL(gram_prep_kernel<4>, dim3(pblocks), dim3(256), 0, s, op.U, n, op.d, mu, G, nrm, gmax);
+    else
+        hipLaunchKernelGGL(gram_prep_kernel<8>, dim3(pblocks), dim3(256), 0, s, op.U, n, op.d, mu, G, nrm, gmax);
+    const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
+    const int64_t total = nsteps * 64 * (nt + tv + 1);
+    hipLaunchKernelGGL(pack_gfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, V, nrm,
+                       n, t, nt, tv, nsteps, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* tok = timing_begin(s);
+    switch (op.d) {
+        case 1: e = launch_gram_d<1>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 2: e = launch_gram_d<2>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 3: e = launch_gram_d<3>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 4: e = launch_gram_d<4>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 5: e = launch_gram_d<5>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 6: e = launch_gram_d<6>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        case 7: e = launch_gram_d<7>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+        default: e = launch_gram_d<8>(nt, tv, op.U, G, nrm, gmax, F, n, t, p, partial, s); break;
+    }
+    {
+        const double ent = static_cast<double>(n) * static_cast<double>(n);
+        timing_end(tok, s, kSweepF32, ent, ent * sweep_flops_per_entry(op.family, op.d, t, false));
+    }
+    if (e != hipSuccess) return e;
+    return reduce_partials(partial, p.chunks, n, t, op.s2, with_noise ? op.sig2 : 0.0f, with_noise ? Vself : nullptr,
+                           out, s);
+}
+
+}  // namespace mfgp

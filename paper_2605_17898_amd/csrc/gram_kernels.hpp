@@ -1,0 +1,159 @@
+// Device body of the FP32 RBF sweep with the squared distances on FP32 MFMA
+// (the Gram form; see gram.hip for the operand layout and the accuracy guard).
+#pragma once
+
+#include "hybrid_kernels.hpp"
+
+namespace mfgp {
+
+constexpr int kGJ = 16;   // j per Gram block (one 16 x 16 distance tile per row tile)
+
+// Rows [row_base, row_base + 256) of the n x n RBF product over j in [j0, j1)
+// (j0 a multiple of 16).  G [n][DG] holds -2 g_j (g = u - mean(u), zero-padded
+// to DG = 4 or 8 dimensions), nrm [n] holds |g_j|^2 and F the V fragments of
+// the hybrid sweep with |g_j|^2 as one more value behind the NT + TV
+// right-hand-side values of each lane and step (stride WS = NT + TV + 1).
+//
+// Per 16-j block and row tile of 16 rows one v_mfma_f32_16x16x4_f32 (two for
+// DG = 8) produces the 16 x 16 squared distances
+//   r2 = |g_i|^2 + |g_j|^2 + sum_k (-2 g_j[k]) g_i[k]
+// with the norms as the accumulator input.  Its A operand (16 j x 4 dims)
+// takes the block's j in the order pi(row) = 4 (row % 4) + row / 4, so that
+// accumulator register s of lane l holds the entry of row i = l % 16 and
+// j = j0 + 4 s + l / 16 -- exactly the A operand of contraction step s of the
+// hybrid sweep (lane l: row l % 16, j = 4 q + l / 16).  The entries then go
+// through the contraction MFMAs (and the TV VALU columns) unchanged.
+template <int DG, int NT, int TV>
+__device__ __forceinline__ void gram_block(const float* __restrict__ G, const float* __restrict__ nrm,
+                                           const float* __restrict__ F, int64_t n, int t, int64_t row_base,
+                                           int64_t j0, int64_t j1, float* __restrict__ out) {
+    constexpr int W = NT + TV;
+    constexpr int WS = W + 1;
+    constexpr int H = DG / 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane >> 4;
+    const int r16 = lane & 15;
+    const int64_t row0 = row_base + wave * (kHRT * 16);
+
+    // B operand of the distance MFMA: lane l holds g_i[4 h + l / 16], i = row l % 16.
+    float bi[kHRT][H], ni[kHRT];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        int64_t i = row0 + r * 16 + r16;
+        i = i < n ? i : n - 1;
+#pragma unroll
+        for (int h = 0; h < H; ++h) bi[r][h] = -0.5f * G[i * DG + 4 * h + grp];
+        ni[r] = nrm[i];
+    }
+    f32x4 acc[kHRT][NT > 0 ? NT : 1], tot[kHRT][NT > 0 ? NT : 1];
+    float sv[kHRT][TV > 0 ? TV : 1], tv_tot[kHRT][TV > 0 ? TV : 1];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[r][c][q] = 0.0f;
+                tot[r][c][q] = 0.0f;
+            }
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            sv[r][c] = 0.0f;
+            tv_tot[r][c] = 0.0f;
+        }
+    }
+
+    const int64_t npad = (n + kGJ - 1) / kGJ * kGJ;
+    j1 = j1 < npad ? j1 : npad;
+    const int64_t nblk = j0 < j1 ? (j1 - j0) / kGJ : 0;
+    // this lane's j of the A operand within a block (the pi order above)
+    const int ja = 4 * (r16 & 3) + (r16 >> 2);
+
+    // Operands of block b: the A operand of the distance MFMA(s) and the four
+    // steps' fragments (values behind j >= n are zero, their norms and points
+    // those of row n - 1, so every entry stays finite).
+    auto load_block = [&](int64_t b, float (&a)[H], float (&f)[4][WS]) {
+        const int64_t jb = j0 + b * kGJ;
+        int64_t j = jb + ja;
+        j = j < n ? j : n - 1;
+#pragma unroll
+        for (int h = 0; h < H; ++h) a[h] = G[j * DG + 4 * h + grp];
+        const float* Fb = F + (jb / kHK) * (64 * WS);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int w = 0; w < WS; ++w) f[s][w] = Fb[(s * 64 + lane) * WS + w];
+    };
+    auto compute_block = [&](const float (&a)[H], const float (&f)[4][WS]) {
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+            f32x4 d2;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) d2[s] = ni[r] + f[s][W];
+#pragma unroll
+            for (int h = 0; h < H; ++h) d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h], bi[r][h], d2, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float e = kentry<MFGP_RBF>(d2[s]);
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, f[s][c], acc[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < TV; ++c) sv[r][c] = fmaf(e, f[s][NT + c], sv[r][c]);
+            }
+        }
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    tot[r][c][qq] += acc[r][c][qq];
+                    acc[r][c][qq] = 0.0f;
+                }
+#pragma unroll
+            for (int c = 0; c < TV; ++c) {
+                tv_tot[r][c] += sv[r][c];
+                sv[r][c] = 0.0f;
+            }
+        }
+    };
+
+    // Ping-pong over two operand sets, one block ahead.
+    float aa[H], ab[H], fa[4][WS], fb[4][WS];
+    if (nblk > 0) load_block(0, aa, fa);
+    int64_t b = 0;
+    for (; b + 1 < nblk; b += 2) {
+        load_block(b + 1, ab, fb);
+        compute_block(aa, fa);
+        load_block(b + 2 < nblk ? b + 2 : nblk - 1, aa, fa);
+        compute_block(ab, fb);
+        if (((b + 2) & (kSeg / kGJ - 1)) == 0) flush();
+    }
+    if (b < nblk) compute_block(aa, fa);
+
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int64_t i = row0 + r * 16 + 4 * grp + qq;
+                const float v = tot[r][c][qq] + acc[r][c][qq];
+                if (i < n) out[(i - row_base) * t + TV + 16 * c + r16] = v;
+            }
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            float v = tv_tot[r][c] + sv[r][c];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int64_t i = row0 + r * 16 + r16;
+            if (grp == 0 && i < n) out[(i - row_base) * t + c] = v;
+        }
+    }
+}
+
+}  // namespace mfgp

@@ -14,8 +14,9 @@ constexpr int kHK = 4;      // j per MFMA step
 // One block's share of the hybrid sweep: rows [row_base, row_base + 256) of
 // an m x n product over j in [j0, j1) (j0 a multiple of 4); the partial sums of
 // row i go to out[(i - row_base) * t + c].  Shared by the single-problem and
-// the batched (persistent) kernels.
-template <int FAM, int D, int NT, int TV>
+// the batched (persistent) kernels.  WS is the per-lane stride of a step's
+// fragment (NT + TV, or more when a caller packs extra values behind them).
+template <int FAM, int D, int NT, int TV, int WS = NT + TV>
 __device__ __forceinline__ void hyb_block(const float* __restrict__ Ur, const float* __restrict__ Uc,
                                           const float* __restrict__ F, int64_t m, int64_t n, int t,
                                           int64_t row_base, int64_t j0, int64_t j1,
@@ -67,9 +68,9 @@ __device__ __forceinline__ void hyb_block(const float* __restrict__ Ur, const fl
     // addressed as a wave-uniform base plus a fixed per-lane offset.
     auto load_step = [&](int64_t st, float (&f)[W], float (&u)[D]) {
         const int64_t q = q0 + st;
-        const float* Fq = F + q * (64 * W);
+        const float* Fq = F + q * (64 * WS);
 #pragma unroll
-        for (int w = 0; w < W; ++w) f[w] = Fq[lane * W + w];
+        for (int w = 0; w < W; ++w) f[w] = Fq[lane * WS + w];
         const float* Uq = Uc + q * (kHK * D);
 #pragma unroll
         for (int k = 0; k < D; ++k) u[k] = Uq[grp * D + k];
@@ -77,7 +78,7 @@ __device__ __forceinline__ void hyb_block(const float* __restrict__ Ur, const fl
     auto load_step_clamped = [&](int64_t st, float (&f)[W], float (&u)[D]) {
         const int64_t q = q0 + st;
 #pragma unroll
-        for (int w = 0; w < W; ++w) f[w] = F[(q * 64 + lane) * W + w];
+        for (int w = 0; w < W; ++w) f[w] = F[(q * 64 + lane) * WS + w];
         int64_t j = q * kHK + grp;
         j = j < n ? j : n - 1;    // padded j carry V = 0
 #pragma unroll

@@ -44,11 +44,24 @@ bool hybrid_supported(int t);
 size_t hybrid_scratch_bytes(int64_t m, int64_t n, int t);
 hipError_t apply_hybrid(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
                         float* out, bool with_noise, const float* Vself, void* scratch, hipStream_t s);
-// FP32 product choosing the MFMA-contraction form when allowed and supported.
-size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, bool allow_mfma);
+// FP32 RBF sweep with the squared distances on FP32 MFMA (square products,
+// t = 1 or 16 k + {0, 1}; falls back in-kernel to direct differences when the
+// centred norms are too large for the form's accuracy).
+bool gram_supported(int t);
+size_t gram_scratch_bytes(int64_t n, int t);
+hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, bool with_noise, const float* Vself,
+                      void* scratch, hipStream_t s);
+// FP32-class product for precision MFGP_FP32 / _FP32_VALU / _FP32_DIRECT /
+// _FP32_GRAM: the Gram form, the MFMA-contraction form or the VALU form as
+// the precision, the family, the shape and the size allow (see core.hip).
+size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, int precision);
 hipError_t apply_fp32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
-                      float* out, bool with_noise, const float* Vself, void* scratch, bool allow_mfma,
+                      float* out, bool with_noise, const float* Vself, void* scratch, int precision,
                       hipStream_t s);
+inline bool is_fp32_class(int precision) {
+    return precision == MFGP_FP32 || precision == MFGP_FP32_VALU || precision == MFGP_FP32_DIRECT ||
+           precision == MFGP_FP32_GRAM;
+}
 
 // BF16-MFMA tile products (precision x1 / x2).
 bool precision_supported(int precision);

@@ -29,7 +29,7 @@
 
 namespace mfgp {
 
-bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_BF16X3; }
+bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_FP32_GRAM; }
 
 // Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + 8(l/32) + q][tv + ct*32 + l%32]
 // (the first piece; Vm and Vl the second and third when split); zero outside

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libmfgp.so")
 
 MAX_D = 8
 FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3}
-PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4}
+PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4, "fp32_direct": 5,
+              "fp32_gram": 6}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
 OP_MATVEC, OP_CG, OP_PREDICT, OP_MLL, OP_ADJOINT, OP_RESIDUAL = range(6)
 OP_PCHOL, OP_PAPPLY, OP_PCG, OP_PMLL = range(6, 10)

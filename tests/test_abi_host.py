@@ -93,7 +93,7 @@ def test_matvec_argument_checks(m):
     assert L.mfgp_kernel_matvec(C.byref(k), d, 0, d, 1, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
     assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 0, C.c_void_p(32), 0, d, 1 << 20, None) == m.ERR_ARG
     assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, d, 0, d, 1 << 20, None) == m.ERR_ARG   # KV aliases V
-    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, C.c_void_p(32), 5, d, 1 << 20, None) == m.ERR_ARG
+    assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, C.c_void_p(32), 7, d, 1 << 20, None) == m.ERR_ARG   # no precision 7
     assert L.mfgp_kernel_matvec(C.byref(k), d, 10, d, 1, C.c_void_p(32), 0, d, 16, None) == m.ERR_WORKSPACE
 
 
