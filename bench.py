@@ -42,12 +42,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (packed FP32 FMA)
-# HBM bytes per launch of the FP32 step's dominant kernel (RBF, d = 4, t = 33,
+# HBM bytes per launch of the step's dominant kernel (RBF, d = 4, t = 33,
 # N = 100000), from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy's
-# reading of the same counters (summary in profiles/).  Valid only for the
-# kernel named below; None for any other.
+# reading of the same counters (summaries in profiles/).  Valid only for the
+# kernels named below.
 HYB_TRAFFIC_BYTES = 2.664e8
-GRAM_TRAFFIC_BYTES = None
+GRAM_TRAFFIC_BYTES = 7.129e8
 # Dominant kernel of the step per precision: (name, bound, HBM bytes per launch).
 STEP_KERNELS = {
     "fp32": ("sweep_gram_kernel<d=4, NT=2, TV=1> (RBF squared distances and the K-tile x V "
