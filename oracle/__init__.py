@@ -21,6 +21,8 @@ probes   the counter-based Rademacher probe generator (SplitMix64).
 bf16     round-to-nearest-even bfloat16 and the BF16 tile-product models.
 precond  rank-k pivoted Cholesky, the Woodbury preconditioner, preconditioned
          CG and the preconditioned log-determinant and gradient estimators.
+variance the exact predictive variance and its stochastic diagonal
+         estimator (Rademacher probes).
 """
 
-from . import gp, krylov, brute, probes, bf16, precond  # noqa: F401
+from . import gp, krylov, brute, probes, bf16, precond, variance  # noqa: F401
