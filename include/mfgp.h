@@ -66,7 +66,7 @@ typedef enum {
  * relative error <= 1e-5 against FP64); the bf16 forms are described below. */
 typedef enum {
     MFGP_FP32 = 0,    /* FP32, fastest form that applies:
-                         - square RBF products with n >= 16384 and t = 1 or
+                         - square RBF products with n >= 32768 and t = 1 or
                            16 k + {0, 1} (k = 1..4): squared distances from the
                            Gram form |g_i|^2 + |g_j|^2 - 2 g_i.g_j on FP32 MFMA
                            (g = prescaled points minus their mean), checked on
@@ -308,6 +308,30 @@ int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sw
 int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
                             const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
                             mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- predictive variance
+ * The latent predictive variance diag(Sigma_*) of Sec. 2,
+ *   Sigma_* = K_** - K_*f K_y^{-1} K_f*,
+ * on the CG path by the stochastic diagonal estimator (Bekas, Kokiopoulou &
+ * Saad 2007; the Rademacher-probe estimator of the accuracy section): with
+ * probe columns z_c over the m test points and A = K_*f K_y^{-1} K_f*,
+ *   var[q] = s2 - sum_c Z[q][c] (A Z)[q][c] / sum_c Z[q][c]^2.
+ * A Z is two rectangular FP32 sweeps around one CG solve with p right-hand
+ * sides (mfgp_cg_solve's solver, stopping rule and refinement).  Unbiased
+ * for Rademacher probes; exact for Z = the m x m identity (p = m).  The
+ * noise variance of a new observation is not added. */
+
+/* Workspace bytes of mfgp_predict_variance (0 if invalid). */
+size_t mfgp_variance_workspace_bytes(int64_t n, int32_t d, int64_t m, int32_t p, int32_t precision);
+/* X [n][d] training inputs, Xs [m][d] test inputs, Z [m][p] probes (device;
+ * NULL: Rademacher probes from opts->probe_seed, laid out as mfgp_rademacher
+ * with n = m).  var [m] (device, float32) receives the estimate; info
+ * (optional, host [p]) the CG result per probe column.  Synchronises.
+ * Returns the CG status (MFGP_NOT_CONVERGED / MFGP_BREAKDOWN still write
+ * var from the best iterate). */
+int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs, int64_t m,
+                          int32_t p, const float* Z, const mfgp_cg_opts* opts, float* var, mfgp_cg_info* info,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- preconditioning
  * LightGP's CG is unpreconditioned; Sec. 5 ("Limitations") names the

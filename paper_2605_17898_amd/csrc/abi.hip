@@ -1,5 +1,6 @@
 // C-ABI entry points (declared in include/mfgp.h): argument validation on the
 // host, workspace carving, and orchestration of the kernels.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -7,6 +8,7 @@
 #include <vector>
 
 #include "cg.hpp"
+#include "vec.hpp"
 #include "precond.hpp"
 #include "internal.hpp"
 
@@ -384,6 +386,65 @@ int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const 
     ABI_CHECK(launch_prescale(Xs, m, kern->d, op.fac, w.Us, s));
     ABI_CHECK(apply_fp32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, MFGP_FP32, s));
     return MFGP_OK;
+}
+
+struct VarWs { float* U; float* Us; float* Z; float* W; double* X64; float* U32; float* Q; CgBufs b; void* scratch; };
+static VarWs carve_variance(Carver& cv, int64_t n, int d, int64_t m, int p, int precision) {
+    VarWs w;
+    w.U = cv.take<float>(static_cast<size_t>(n) * d);
+    w.Us = cv.take<float>(static_cast<size_t>(m) * d);
+    w.Z = cv.take<float>(static_cast<size_t>(m) * p);
+    w.W = cv.take<float>(static_cast<size_t>(n) * p);
+    w.X64 = cv.take<double>(static_cast<size_t>(n) * p);
+    w.U32 = cv.take<float>(static_cast<size_t>(n) * p);
+    w.Q = cv.take<float>(static_cast<size_t>(m) * p);
+    w.b = carve_cg(cv, n, p, precision);
+    w.scratch = cv.take<char>(std::max(apply_fp32_scratch_bytes(n, m, p, MFGP_FP32),
+                                       apply_fp32_scratch_bytes(m, n, p, MFGP_FP32)));
+    return w;
+}
+
+size_t mfgp_variance_workspace_bytes(int64_t n, int32_t d, int64_t m, int32_t p, int32_t precision) {
+    if (n < 1 || m < 1 || p < 1 || d < 1 || d > MFGP_MAX_D) return 0;
+    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return 0;
+    Carver cv(nullptr);
+    carve_variance(cv, n, d, m, p, precision);
+    return cv.off + 256;
+}
+
+int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs, int64_t m,
+                          int32_t p, const float* Z, const mfgp_cg_opts* opts, float* var, mfgp_cg_info* info,
+                          void* ws, size_t ws_bytes, void* stream) {
+    int st = check_kernel(kern, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !Xs || !var || !ws || n < 1 || m < 1 || p < 1) return MFGP_ERR_ARG;
+    if ((st = check_precision_cols(opts->precision, p)) != MFGP_OK) return st;
+    if (m > 0x7fffffff) return MFGP_UNSUPPORTED;
+    if (ws_bytes < mfgp_variance_workspace_bytes(n, kern->d, m, p, opts->precision)) return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    VarWs w = carve_variance(cv, n, kern->d, m, p, opts->precision);
+    Operator op = make_operator(*kern, X, n, w.U);
+    Operator ops = make_operator(*kern, Xs, m, w.Us);
+    ABI_CHECK(prescale(op, s));
+    ABI_CHECK(prescale(ops, s));
+    const float* Zp = Z;
+    if (!Zp) {
+        ABI_CHECK(launch_rademacher(opts->probe_seed, m, p, w.Z, s));
+        Zp = w.Z;
+    }
+    // W = K(X, Xs) Z (rows: training points, columns: test points)
+    ABI_CHECK(apply_fp32(ops, op.U, n, Zp, p, w.W, false, nullptr, w.scratch, MFGP_FP32, s));
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    const int cst = cg_run(op, w.W, p, w.X64, *opts, info, nullptr, max_iter, w.b, s);
+    if (cst == MFGP_ERR_HIP) return cst;
+    ABI_CHECK(f64_to_f32(w.X64, w.U32, n * p, s));
+    // Q = K(Xs, X) K_y^{-1} W
+    ABI_CHECK(apply_fp32(op, ops.U, m, w.U32, p, w.Q, false, nullptr, w.scratch, MFGP_FP32, s));
+    ABI_CHECK(diag_variance(Zp, w.Q, m, p, static_cast<double>(kern->outputscale), var, s));
+    ABI_CHECK(hipStreamSynchronize(s));
+    return cst;
 }
 
 int mfgp_slq_quadrature(const double* coeffs, int32_t m, double znorm2, double* q) {

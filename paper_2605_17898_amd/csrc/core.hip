@@ -228,11 +228,12 @@ hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float
 }
 
 // Form selection of the FP32-class products.  MFGP_FP32 takes the Gram form
-// for square RBF products of at least kGramMinN rows (below that the
-// preparation launches are a visible share of a sweep), else the MFMA-
+// for square RBF products of at least kGramMinN rows (below that its four
+// preparation launches cost about what it saves: 0.130 against 0.126 ms at
+// n = 20000, t = 1; 0.51 against 0.60 ms at n = 50000), else the MFMA-
 // contraction form where t = 16 k + {0, 1}, else the VALU form;
 // MFGP_FP32_GRAM takes the Gram form at any size, MFGP_FP32_DIRECT never.
-constexpr int64_t kGramMinN = 16384;
+constexpr int64_t kGramMinN = 32768;
 
 static bool use_gram(const Operator& op, const float* Ur, int64_t m, int t, int precision) {
     if (precision != MFGP_FP32 && precision != MFGP_FP32_GRAM) return false;

@@ -251,6 +251,21 @@ __global__ void f64_to_f32_kernel(const double* __restrict__ src, float* __restr
 
 static inline unsigned nblk(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
 
+// var[q] = s2 - sum_c Z[q][c] Q[q][c] / sum_c Z[q][c]^2 (FP64 sums; 0 probe
+// weight gives the prior s2).
+__global__ void diag_variance_kernel(const float* __restrict__ Z, const float* __restrict__ Q, int64_t m, int p,
+                                     double s2, float* __restrict__ var) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < p; ++c) {
+        const double z = static_cast<double>(Z[q * p + c]);
+        num = fma(z, static_cast<double>(Q[q * p + c]), num);
+        den = fma(z, z, den);
+    }
+    var[q] = static_cast<float>(den > 0.0 ? s2 - num / den : s2);
+}
+
 hipError_t cg_alpha(const CgState& st, int t, hipStream_t s) {
     hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(256), 0, s, st, t);
     return hipGetLastError();
@@ -305,6 +320,11 @@ hipError_t fill_f64(double* x, int64_t total, double v, hipStream_t s) {
 
 hipError_t copy2_f32(const float* src, float* a, float* b, int64_t total, hipStream_t s) {
     hipLaunchKernelGGL(copy_f32_kernel, dim3(nblk(total)), dim3(256), 0, s, src, a, b, total);
+    return hipGetLastError();
+}
+
+hipError_t diag_variance(const float* Z, const float* Q, int64_t m, int p, double s2, float* var, hipStream_t s) {
+    hipLaunchKernelGGL(diag_variance_kernel, dim3(nblk(m)), dim3(256), 0, s, Z, Q, m, p, s2, var);
     return hipGetLastError();
 }
 

@@ -39,5 +39,8 @@ hipError_t cg_replace(const CgState& st, const double* R64, int64_t n, int t, co
 hipError_t fill_f64(double* x, int64_t total, double v, hipStream_t s);
 hipError_t copy2_f32(const float* src, float* a, float* b, int64_t total, hipStream_t s);
 hipError_t f64_to_f32(const double* src, float* dst, int64_t total, hipStream_t s);
+// Stochastic diagonal estimate of the predictive variance from probes Z and
+// Q = K_*f K_y^{-1} K_f* Z ([m][p] each): var = s2 - sum_c Z Q / sum_c Z^2.
+hipError_t diag_variance(const float* Z, const float* Q, int64_t m, int p, double s2, float* var, hipStream_t s);
 
 }  // namespace mfgp

@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_residual": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
         "mfgp_cg_solve": (C.c_int, [KP, P, I64, P, I32, P, OP_, IP, P, P, SZ, P]),
         "mfgp_predict_mean": (C.c_int, [KP, P, I64, P, I64, P, I32, P, P, SZ, P]),
+        "mfgp_variance_workspace_bytes": (SZ, [I64, I32, I64, I32, I32]),
+        "mfgp_predict_variance": (C.c_int, [KP, P, I64, P, I64, I32, P, OP_, P, IP, P, SZ, P]),
         "mfgp_slq_quadrature": (C.c_int, [P, I32, D, P]),
         "mfgp_mll_and_grad": (C.c_int, [KP, P, I64, P, I32, P, OP_, P, P, P, P, IP, P, SZ, P]),
         "mfgp_kernel_adjoint": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
@@ -290,6 +292,34 @@ def predict_mean(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, A: torch.Tenso
     _check(LIB.mfgp_predict_mean(C.byref(ks), _ptr(X), n, _ptr(Xs), m, _ptr(A), t, _ptr(mu), _ptr(ws),
                                  ws.numel(), _stream()), "predict_mean")
     return mu
+
+
+def predict_variance(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, Z: Optional[torch.Tensor] = None,
+                     num_probes: int = 64, seed: int = 0, tol: float = 1e-6, max_iter: int = 0,
+                     precision: str = "fp32", allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+    """Latent predictive variance at Xs by the stochastic diagonal estimator on the CG path.
+
+    Z [m, p] probes (None: seeded Rademacher, p = num_probes).  Returns
+    (var float32 [m], info list, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(Xs, torch.float32, "Xs")
+    n, d = X.shape
+    m = Xs.shape[0]
+    if Z is not None:
+        _dev(Z, torch.float32, "Z")
+        p = _cols(Z)
+    else:
+        p = num_probes
+    o = cg_opts(tol, max_iter, 0, -1, precision, False)
+    o.probe_seed = seed
+    var = torch.empty(m, dtype=torch.float32, device=X.device)
+    info = (CgInfoT * p)()
+    ws = workspace(LIB.mfgp_variance_workspace_bytes(n, d, m, p, o.precision), X.device)
+    ks = kern.struct(d)
+    st = LIB.mfgp_predict_variance(C.byref(ks), _ptr(X), n, _ptr(Xs), m, p, _ptr(Z), C.byref(o), _ptr(var),
+                                   info, _ptr(ws), ws.numel(), _stream())
+    _check(st, "predict_variance", allow)
+    return var, _info_list(info, p), st
 
 
 def slq_quadrature(coeffs: Sequence[Sequence[float]], znorm2: float) -> float:

@@ -177,3 +177,34 @@ def test_struct_layouts_match_the_header(m, tmp_path):
     assert sizes[4] == m.CgOptsT.probe_seed.offset
     assert sizes[5] == m.CgOptsT.progress.offset
     assert sizes[6] == m.CgInfoT.replacements.offset
+
+
+def test_variance_argument_checks(m):
+    # every rejection happens on the host, before any launch
+    k = _kern(m)
+    d = C.c_void_p(16)
+    L = m.LIB
+    o = m.cg_opts(1e-6, 0, 0, -1, "fp32", False)
+    nb = L.mfgp_variance_workspace_bytes(100, 2, 10, 4, 0)
+    assert nb > 0
+    assert L.mfgp_variance_workspace_bytes(100, 2, 0, 4, 0) == 0
+    assert L.mfgp_variance_workspace_bytes(100, 2, 10, 0, 0) == 0
+    assert L.mfgp_variance_workspace_bytes(100, 2, 10, 4, 7) == 0
+    # O(n + m) workspace: 10x the training points -> about 10x the bytes
+    assert L.mfgp_variance_workspace_bytes(100000, 2, 10, 4, 0) < 12 * L.mfgp_variance_workspace_bytes(10000, 2, 10, 4, 0)
+    args = lambda **kw: dict(dict(kern=C.byref(k), X=d, n=100, Xs=d, m=10, p=4, Z=None, opts=C.byref(o),
+                                  var=d, info=None, ws=d, wsb=nb, s=None), **kw)
+    call = lambda a: L.mfgp_predict_variance(a["kern"], a["X"], a["n"], a["Xs"], a["m"], a["p"], a["Z"],
+                                             a["opts"], a["var"], a["info"], a["ws"], a["wsb"], a["s"])
+    assert call(args(kern=None)) == m.ERR_ARG
+    assert call(args(X=None)) == m.ERR_ARG
+    assert call(args(Xs=None)) == m.ERR_ARG
+    assert call(args(var=None)) == m.ERR_ARG
+    assert call(args(n=0)) == m.ERR_ARG
+    assert call(args(m=0)) == m.ERR_ARG
+    assert call(args(p=0)) == m.ERR_ARG
+    assert call(args(opts=None)) == m.ERR_ARG
+    assert call(args(wsb=16)) == m.ERR_WORKSPACE
+    bad = m.cg_opts(1e-6, 0, 0, -1, "fp32", False)
+    bad.tol = -1.0
+    assert call(args(opts=C.byref(bad))) == m.ERR_ARG

@@ -89,10 +89,10 @@ def test_gram_symmetric_operator(mf):
 
 
 def test_gram_is_the_fp32_default_at_large_n(mf):
-    # n >= 16384: MFGP_FP32 takes the Gram form for RBF; same result as
+    # n >= 32768: MFGP_FP32 takes the Gram form for RBF; same result as
     # forcing it, bitwise, and within the bar of the direct form.
-    banner("matvec rbf100k n=20000 t=33: fp32 == fp32_gram, vs fp32_direct")
-    w = inputs.rbf100k(n=20000, probes=32)
+    banner("matvec rbf100k n=40000 t=33: fp32 == fp32_gram, vs fp32_direct")
+    w = inputs.rbf100k(n=40000, probes=32)
     V = np.concatenate([w.y[:, None], w.Z], axis=1)
     k = mkern(w)
     a = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32"))
