@@ -19,7 +19,7 @@ python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the 
     WRITE_SIZE calibrate the HBM-traffic counters)
 python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ U{1..6},
     ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
-python bench.py --mode rbf500k [--precision fp32|bf16x2|bf16x3]   (N = 500000, d = 2, RBF
+python bench.py --mode rbf500k [--precision fp32|bf16x2|bf16x3] [--precond K]   (N = 500000, d = 2, RBF
     l = 0.05, 16 probes: one MLL + gradient in the chosen precision)
 python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and 33 in
     every precision, and N = 2k..50k at t = 1; HIP events around the whole call,
@@ -47,7 +47,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # reading of the same counters (summaries in profiles/).  Valid only for the
 # kernels named below.
 HYB_TRAFFIC_BYTES = 2.664e8
-GRAM_TRAFFIC_BYTES = 7.129e8
+GRAM_TRAFFIC_BYTES = 6.520e8
 # Dominant kernel of the step per precision: (name, bound, HBM bytes per launch).
 STEP_KERNELS = {
     "fp32": ("sweep_gram_kernel<d=4, NT=2, TV=1> (RBF squared distances and the K-tile x V "
@@ -132,13 +132,26 @@ def rbf500k_leg(args) -> int:
               f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     mfgp.timing_enable(True)
-    r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=args.precision, progress=progress)
+    factor_s = None
+    if args.precond > 0:
+        # rank-k pivoted-Cholesky preconditioner; probes z ~ N(0, P) from
+        # standard normal draws (the preconditioned estimator's probes)
+        L, _ = mfgp.pivoted_cholesky(kern, X, args.precond)
+        E = torch.from_numpy(inputs.gaussian_rhs(411, args.precond, Z.shape[1])).cuda()
+        G = torch.from_numpy(inputs.gaussian_rhs(412, w.n, Z.shape[1])).cuda()
+        Zp = mfgp.precond_probes(L, w.noise, E, G)
+        torch.cuda.synchronize()
+        factor_s = time.perf_counter() - t0
+        r = mfgp.precond_mll_and_grad(kern, X, y, Zp, L, tol=1e-6, precision=args.precision, progress=progress)
+    else:
+        r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=args.precision, progress=progress)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ph = mfgp.timing_phases()
     allk = mfgp.timing_read(-1)
     mfgp.timing_enable(False)
     print(json.dumps({"mode": "rbf500k", "precision": args.precision, "n": w.n, "probes": 16,
+                      "precond_rank": args.precond, "factor_s": factor_s,
                       "mll_grad_s": el, "cg_s": ph["cg_ms"] * 1e-3, "slq_s": ph["slq_ms"] * 1e-3,
                       "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"],
                       "cg_iters_max": max(i["iters"] for i in r["info"]),
@@ -254,6 +267,8 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--precond", type=int, default=0,
+                    help="rbf500k mode: rank of a pivoted-Cholesky preconditioner (0: plain CG)")
     ap.add_argument("--pc-rank", type=int, default=1024,
                     help="rank of the preconditioned comparison step (0 skips it)")
     args = ap.parse_args()
