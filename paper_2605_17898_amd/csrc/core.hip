@@ -233,7 +233,6 @@ hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float
 // n = 20000, t = 1; 0.51 against 0.60 ms at n = 50000), else the MFMA-
 // contraction form where t = 16 k + {0, 1}, else the VALU form;
 // MFGP_FP32_GRAM takes the Gram form at any size, MFGP_FP32_DIRECT never.
-constexpr int64_t kGramMinN = 32768;
 
 static bool use_gram(const Operator& op, const float* Ur, int64_t m, int t, int precision) {
     if (precision != MFGP_FP32 && precision != MFGP_FP32_GRAM) return false;

@@ -33,7 +33,6 @@ namespace mfgp {
 
 namespace {
 
-constexpr float kGramMaxNorm = 64.0f;
 constexpr int kMeanBlocks = 64;
 
 // Per-block column sums of U [n][d] over a contiguous row range (FP64).
@@ -72,18 +71,20 @@ __global__ void gram_mean_stage2(const double* __restrict__ part, int nb, int d,
 
 // G[j] = -2 (u_j - mu) zero-padded to DG, nrm[j] = |u_j - mu|^2, and the
 // maximum norm (as the bits of a non-negative float, which order like the
-// values) into gmax.
+// values) into gmax.  Rows n .. npad - 1 repeat row n - 1, so that the sweeps
+// read whole distance tiles without clamping (the V behind them is zero).
 template <int DG>
-__global__ __launch_bounds__(256) void gram_prep_kernel(const float* __restrict__ U, int64_t n, int d,
-                                                        const float* __restrict__ mu, float* __restrict__ G,
+__global__ __launch_bounds__(256) void gram_prep_kernel(const float* __restrict__ U, int64_t n, int64_t npad,
+                                                        int d, const float* __restrict__ mu, float* __restrict__ G,
                                                         float* __restrict__ nrm, unsigned* __restrict__ gmax) {
     __shared__ float red[256];
     const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     float nj = 0.0f;
-    if (j < n) {
+    if (j < npad) {
+        const int64_t js = j < n ? j : n - 1;
 #pragma unroll
         for (int k = 0; k < DG; ++k) {
-            const float g = k < d ? U[j * d + k] - mu[k] : 0.0f;
+            const float g = k < d ? U[js * d + k] - mu[k] : 0.0f;
             nj = fmaf(g, g, nj);
             G[j * DG + k] = -2.0f * g;
         }
@@ -153,10 +154,36 @@ SweepPlan plan_gram(int64_t n) {
 }
 
 struct GramLayout {
-    size_t frag, part, g, nrm, mpart, mu, gmax, total;
+    size_t frag, part, prep, total;
 };
 
 inline size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Preparation region: G [n][8], nrm [n], column-mean partials, mu, gmax.
+struct PrepLayout {
+    size_t g, nrm, mpart, mu, gmax, total;
+};
+
+// Rows of the preparation arrays: n rounded up to 64 (whole distance tiles).
+int64_t prep_rows(int64_t n) { return (n + 63) / 64 * 64; }
+
+PrepLayout prep_layout(int64_t n) {
+    n = prep_rows(n);
+    PrepLayout L{};
+    size_t off = 0;
+    L.g = off;
+    off += up256(static_cast<size_t>(n) * 8 * sizeof(float));
+    L.nrm = off;
+    off += up256(static_cast<size_t>(n) * sizeof(float));
+    L.mpart = off;
+    off += up256(static_cast<size_t>(kMeanBlocks) * MFGP_MAX_D * sizeof(double));
+    L.mu = off;
+    off += 256;
+    L.gmax = off;
+    off += 256;
+    L.total = off;
+    return L;
+}
 
 GramLayout gram_layout(int64_t n, int t) {
     int nt = 0, tv = 0;
@@ -169,16 +196,8 @@ GramLayout gram_layout(int64_t n, int t) {
     off += up256(static_cast<size_t>(nsteps) * 64 * (nt + tv + 1) * sizeof(float));
     L.part = off;
     off += up256(static_cast<size_t>(p.chunks) * n * t * sizeof(float));
-    L.g = off;
-    off += up256(static_cast<size_t>(n) * 8 * sizeof(float));
-    L.nrm = off;
-    off += up256(static_cast<size_t>(n) * sizeof(float));
-    L.mpart = off;
-    off += up256(static_cast<size_t>(kMeanBlocks) * MFGP_MAX_D * sizeof(double));
-    L.mu = off;
-    off += 256;
-    L.gmax = off;
-    off += 256;
+    L.prep = off;
+    off += prep_layout(n).total;
     L.total = off;
     return L;
 }
@@ -212,6 +231,33 @@ size_t gram_scratch_bytes(int64_t n, int t) {
     return gram_layout(n, t).total + 1024;
 }
 
+size_t gram_prep_bytes(int64_t n) { return prep_layout(n).total; }
+
+hipError_t gram_prepare(const Operator& op, void* scratch, GramPrep& g, hipStream_t s) {
+    const int64_t n = op.n;
+    if (op.d < 1 || op.d > 8) return hipErrorNotSupported;
+    const PrepLayout L = prep_layout(n);
+    char* base = static_cast<char*>(scratch);
+    g.G = reinterpret_cast<float*>(base + L.g);
+    g.nrm = reinterpret_cast<float*>(base + L.nrm);
+    g.gmax = reinterpret_cast<unsigned*>(base + L.gmax);
+    g.dg = op.d <= 4 ? 4 : 8;
+    double* mpart = reinterpret_cast<double*>(base + L.mpart);
+    float* mu = reinterpret_cast<float*>(base + L.mu);
+    const int nb = static_cast<int>(std::min<int64_t>(kMeanBlocks, (n + 255) / 256));
+    hipLaunchKernelGGL(gram_mean_stage1, dim3(nb), dim3(256), 0, s, op.U, n, op.d, mpart);
+    hipLaunchKernelGGL(gram_mean_stage2, dim3(1), dim3(64), 0, s, mpart, nb, op.d, n, mu, g.gmax);
+    const int64_t npad = prep_rows(n);
+    const unsigned pblocks = static_cast<unsigned>((npad + 255) / 256);
+    if (g.dg == 4)
+        hipLaunchKernelGGL(gram_prep_kernel<4>, dim3(pblocks), dim3(256), 0, s, op.U, n, npad, op.d, mu, g.G, g.nrm,
+                           g.gmax);
+    else
+        hipLaunchKernelGGL(gram_prep_kernel<8>, dim3(pblocks), dim3(256), 0, s, op.U, n, npad, op.d, mu, g.G, g.nrm,
+                           g.gmax);
+    return hipGetLastError();
+}
+
 hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, float s2,
                            float sig2, const float* Vself, float* out, hipStream_t s);
 
@@ -225,25 +271,17 @@ hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, boo
     char* base = static_cast<char*>(scratch);
     float* F = reinterpret_cast<float*>(base + L.frag);
     float* partial = reinterpret_cast<float*>(base + L.part);
-    float* G = reinterpret_cast<float*>(base + L.g);
-    float* nrm = reinterpret_cast<float*>(base + L.nrm);
-    double* mpart = reinterpret_cast<double*>(base + L.mpart);
-    float* mu = reinterpret_cast<float*>(base + L.mu);
-    unsigned* gmax = reinterpret_cast<unsigned*>(base + L.gmax);
-    const int nb = static_cast<int>(std::min<int64_t>(kMeanBlocks, (n + 255) / 256));
-
-    hipLaunchKernelGGL(gram_mean_stage1, dim3(nb), dim3(256), 0, s, op.U, n, op.d, mpart);
-    hipLaunchKernelGGL(gram_mean_stage2, dim3(1), dim3(64), 0, s, mpart, nb, op.d, n, mu, gmax);
-    const unsigned pblocks = static_cast<unsigned>((n + 255) / 256);
-    if (op.d <= 4)
-        hipLaunchKernelGGL(gram_prep_kernel<4>, dim3(pblocks), dim3(256), 0, s, op.U, n, op.d, mu, G, nrm, gmax);
-    else
-        hipLaunchKernelGGL(gram_prep_kernel<8>, dim3(pblocks), dim3(256), 0, s, op.U, n, op.d, mu, G, nrm, gmax);
+    GramPrep gp;
+    hipError_t e = gram_prepare(op, base + L.prep, gp, s);
+    if (e != hipSuccess) return e;
+    float* G = gp.G;
+    float* nrm = gp.nrm;
+    unsigned* gmax = gp.gmax;
     const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
     const int64_t total = nsteps * 64 * (nt + tv + 1);
     hipLaunchKernelGGL(pack_gfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, V, nrm,
                        n, t, nt, tv, nsteps, F);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* tok = timing_begin(s);
     switch (op.d) {

@@ -71,14 +71,13 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     const int ja = 4 * (r16 & 3) + (r16 >> 2);
 
     // Operands of block b: the A operand of the distance MFMA(s) and the four
-    // steps' fragments (values behind j >= n are zero, their norms and points
-    // those of row n - 1, so every entry stays finite).
+    // steps' fragments (values behind j >= n are zero; G, nrm and the packed
+    // norms repeat row n - 1 there, so every entry stays finite).
     auto load_block = [&](int64_t b, float (&a)[H], float (&f)[4][WS]) {
         const int64_t jb = j0 + b * kGJ;
-        int64_t j = jb + ja;
-        j = j < n ? j : n - 1;
+        const float* Gj = G + (jb + ja) * DG + grp;   // rows past n repeat row n - 1
 #pragma unroll
-        for (int h = 0; h < H; ++h) a[h] = G[j * DG + 4 * h + grp];
+        for (int h = 0; h < H; ++h) a[h] = Gj[4 * h];
         const float* Fb = F + (jb / kHK) * (64 * WS);
 #pragma unroll
         for (int s = 0; s < 4; ++s)

@@ -48,6 +48,22 @@ hipError_t apply_hybrid(const Operator& op, const float* Ur, int64_t m, const fl
 // t = 1 or 16 k + {0, 1}; falls back in-kernel to direct differences when the
 // centred norms are too large for the form's accuracy).
 bool gram_supported(int t);
+// Shared preparation of the Gram forms (FP32 and bf16 sweeps): the column
+// mean mu of U, G [n][dg] = -2 (u - mu) zero-padded to dg = 4 (d <= 4) or 8,
+// nrm [n] = |u - mu|^2 (both with rows n .. roundup(n, 64) - 1 repeating row
+// n - 1) and the largest norm's float bits in *gmax; the sweeps take the Gram
+// branch only while that maximum is at most kGramMaxNorm.
+constexpr float kGramMaxNorm = 64.0f;
+// Smallest n for which MFGP_FP32 and the bf16 forms take the Gram form.
+constexpr int64_t kGramMinN = 32768;
+struct GramPrep {
+    float* G = nullptr;
+    float* nrm = nullptr;
+    unsigned* gmax = nullptr;
+    int dg = 4;
+};
+size_t gram_prep_bytes(int64_t n);
+hipError_t gram_prepare(const Operator& op, void* scratch, GramPrep& g, hipStream_t s);
 size_t gram_scratch_bytes(int64_t n, int t);
 hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, bool with_noise, const float* Vself,
                       void* scratch, hipStream_t s);

@@ -31,11 +31,11 @@ namespace mfgp {
 
 bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_FP32_GRAM; }
 
-// Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + 8(l/32) + q][tv + ct*32 + l%32]
+// Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + tile_j(l/32, q, perm)][tv + ct*32 + l%32]
 // (the first piece; Vm and Vl the second and third when split); zero outside
 // [n) x [t).  With tv = 1, Vy[j] = V[j][0] in FP32 (zero for j >= n).
 __global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t, int tv, int nt_tiles,
-                                  int64_t njt, int split, bf16x8* __restrict__ Vh,
+                                  int64_t njt, int split, int perm, bf16x8* __restrict__ Vh,
                                   bf16x8* __restrict__ Vm, bf16x8* __restrict__ Vl,
                                   float* __restrict__ Vy) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -47,7 +47,7 @@ __global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t,
     const int ct = static_cast<int>(f % nt_tiles);
     const int64_t jt = f / nt_tiles;
     bf16x8 h8, m8, l8;
-    vfrag(V, n, t, tv, jt, ct, l, h8, m8, l8);
+    vfrag(V, n, t, tv, jt, ct, l, h8, m8, l8, perm != 0);
     Vh[idx] = h8;
     if (split >= 1) Vm[idx] = m8;
     if (split >= 2) Vl[idx] = l8;
@@ -66,20 +66,44 @@ __global__ __launch_bounds__(kBlock) void sweep_mfma_kernel(
                                       partial + static_cast<int64_t>(ch) * m * t + row_base * t);
 }
 
+// The Gram form for square RBF products (distances on v_mfma_f32_32x32x2_f32,
+// see gram_mfma_block): the launch reads the largest centred norm and runs
+// the direct-difference body on the same (permuted) fragments above the
+// form's accuracy bound.
+template <int D, int NT, int SPLIT, int TV>
+__global__ __launch_bounds__(kBlock) void sweep_gmfma_kernel(
+    const float* __restrict__ U, const float* __restrict__ G, const float* __restrict__ nrm,
+    const unsigned* __restrict__ gmax, const bf16x8* __restrict__ Vh, const bf16x8* __restrict__ Vm,
+    const bf16x8* __restrict__ Vl, const float* __restrict__ Vy, int64_t n, int t, int chunks, int64_t jchunk,
+    float* __restrict__ partial) {
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;       // multiple of 32
+    const int64_t row_base = static_cast<int64_t>(rb) * kBlock;
+    float* out = partial + static_cast<int64_t>(ch) * n * t + row_base * t;
+    if (__uint_as_float(*gmax) <= kGramMaxNorm)
+        gram_mfma_block<D <= 4 ? 4 : 8, NT, SPLIT, TV>(G, nrm, Vh, Vm, Vl, Vy, n, t, row_base, j0, j0 + jchunk, out);
+    else
+        mfma_block<MFGP_RBF, D, NT, SPLIT, TV, true>(U, U, Vh, Vm, Vl, Vy, n, n, t, row_base, j0, j0 + jchunk, out);
+}
+
 // ---------------------------------------------------------------- host side
 
 static SweepPlan plan_mfma(int64_t m, int64_t n) {
     SweepPlan p = plan_sweep(m, n);
-    // j-ranges in whole 16-wide MFMA steps
-    p.jchunk = (p.jchunk + kJT - 1) / kJT * kJT;
+    // j-ranges in whole 32-j distance tiles (two 16-wide MFMA steps)
+    p.jchunk = (p.jchunk + kGB - 1) / kGB * kGB;
     return p;
 }
+
+// 16-j tiles covering n rounded up to 32 (the Gram form's distance tiles)
+static int64_t mfma_njt(int64_t n) { return (n + kGB - 1) / kGB * (kGB / kJT); }
 
 // Scratch: three fragment arrays (one per split piece), the FP32 column-0
 // copy, and the split-j partial sums.
 static void mfma_layout(int64_t m, int64_t n, int t, size_t& frag, size_t& ybytes, size_t& part) {
     const SweepPlan p = plan_mfma(m, n);
-    const int64_t njt = (n + kJT - 1) / kJT;
+    const int64_t njt = mfma_njt(n);
     frag = (static_cast<size_t>(njt) * col_tiles(t) * 64 * sizeof(bf16x8) + 255) / 256 * 256;
     ybytes = (static_cast<size_t>(njt) * kJT * sizeof(float) + 255) / 256 * 256;
     part = static_cast<size_t>(p.chunks) * m * t * sizeof(float);
@@ -90,7 +114,7 @@ size_t mfma_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
     size_t frag, ybytes, part;
     mfma_layout(m, n, t, frag, ybytes, part);
     (void)precision;
-    return 3 * frag + ybytes + part + 4096;
+    return 3 * frag + ybytes + ((part + 255) / 256 * 256) + gram_prep_bytes(n) + 4096;
 }
 
 template <int FAM, int D>
@@ -107,6 +131,23 @@ static hipError_t mfma_fd(int nt, int split, int tv, const float* Ur, const floa
     MFGP_MF(1, 0, 0) MFGP_MF(1, 1, 0) MFGP_MF(1, 2, 0) MFGP_MF(2, 0, 0) MFGP_MF(2, 1, 0) MFGP_MF(2, 2, 0)
     MFGP_MF(1, 0, 1) MFGP_MF(1, 1, 1) MFGP_MF(1, 2, 1) MFGP_MF(2, 0, 1) MFGP_MF(2, 1, 1) MFGP_MF(2, 2, 1)
 #undef MFGP_MF
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+static hipError_t gmfma_d(int nt, int split, int tv, const float* U, const GramPrep& g, const bf16x8* Vh,
+                          const bf16x8* Vm, const bf16x8* Vl, const float* Vy, int64_t n, int t, const SweepPlan& p,
+                          float* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+#define MFGP_GMF(NTV, SPV, TVV)                                                                        \
+    if (nt == NTV && split == SPV && tv == TVV) {                                                      \
+        hipLaunchKernelGGL((sweep_gmfma_kernel<D, NTV, SPV, TVV>), grid, dim3(kBlock), 0, s, U, g.G, g.nrm, \
+                           g.gmax, Vh, Vm, Vl, Vy, n, t, p.chunks, p.jchunk, partial);                 \
+        return hipGetLastError();                                                                      \
+    }
+    MFGP_GMF(1, 0, 0) MFGP_GMF(1, 1, 0) MFGP_GMF(1, 2, 0) MFGP_GMF(2, 0, 0) MFGP_GMF(2, 1, 0) MFGP_GMF(2, 2, 0)
+    MFGP_GMF(1, 0, 1) MFGP_GMF(1, 1, 1) MFGP_GMF(1, 2, 1) MFGP_GMF(2, 0, 1) MFGP_GMF(2, 1, 1) MFGP_GMF(2, 2, 1)
+#undef MFGP_GMF
     return hipErrorInvalidValue;
 }
 
@@ -135,7 +176,7 @@ hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const floa
     if (nt < 1 || nt > 2) return hipErrorNotSupported;
     const int split = split_of(precision);
     const int64_t n = op.n;
-    const int64_t njt = (n + kJT - 1) / kJT;
+    const int64_t njt = mfma_njt(n);
     const SweepPlan p = plan_mfma(m, n);
     size_t frag, ybytes, part;
     mfma_layout(m, n, t, frag, ybytes, part);
@@ -145,25 +186,44 @@ hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const floa
     bf16x8* Vl = reinterpret_cast<bf16x8*>(base + 2 * frag);
     float* Vy = reinterpret_cast<float*>(base + 3 * frag);
     float* partial = reinterpret_cast<float*>(base + 3 * frag + ybytes);
+    void* prep = base + 3 * frag + ybytes + (part + 255) / 256 * 256;
+    // Gram-form distances for square RBF products at n >= kGramMinN (as the
+    // FP32 form), with the fragments in the distance tiles' j order.
+    const bool gram = op.family == MFGP_RBF && Ur == op.U && m == n && n >= kGramMinN && op.d >= 1 && op.d <= 8;
+    GramPrep gp;
+    if (gram) {
+        hipError_t ge = gram_prepare(op, prep, gp, s);
+        if (ge != hipSuccess) return ge;
+    }
     const int64_t total = std::max<int64_t>(njt * nt * 64, njt * kJT);
     hipLaunchKernelGGL(pack_vfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
-                       0, s, V, n, t, tv, nt, njt, split, Vh, Vm, Vl, Vy);
+                       0, s, V, n, t, tv, nt, njt, split, gram ? 1 : 0, Vh, Vm, Vl, Vy);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* tok = timing_begin(s);
-    switch (op.family) {
-        case MFGP_RBF:
-            e = mfma_f<MFGP_RBF>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
-            break;
-        case MFGP_MATERN12:
-            e = mfma_f<MFGP_MATERN12>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
-            break;
-        case MFGP_MATERN32:
-            e = mfma_f<MFGP_MATERN32>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
-            break;
-        default:
-            e = mfma_f<MFGP_MATERN52>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
-            break;
+    if (gram) {
+        switch (op.d) {
+#define MFGP_GD(DV) \
+            case DV: e = gmfma_d<DV>(nt, split, tv, op.U, gp, Vh, Vm, Vl, Vy, n, t, p, partial, s); break;
+            MFGP_GD(1) MFGP_GD(2) MFGP_GD(3) MFGP_GD(4) MFGP_GD(5) MFGP_GD(6) MFGP_GD(7) MFGP_GD(8)
+#undef MFGP_GD
+            default: e = hipErrorInvalidValue;
+        }
+    } else {
+        switch (op.family) {
+            case MFGP_RBF:
+                e = mfma_f<MFGP_RBF>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+                break;
+            case MFGP_MATERN12:
+                e = mfma_f<MFGP_MATERN12>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+                break;
+            case MFGP_MATERN32:
+                e = mfma_f<MFGP_MATERN32>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+                break;
+            default:
+                e = mfma_f<MFGP_MATERN52>(op.d, nt, split, tv, Ur, op.U, Vh, Vm, Vl, Vy, m, n, t, p, partial, s);
+                break;
+        }
     }
     {
         const double ent = static_cast<double>(m) * static_cast<double>(n);

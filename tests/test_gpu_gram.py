@@ -115,3 +115,49 @@ def test_gram_cg_solve_exact1k(mf):
     assert st == mf.OK, info
     assert max(i["rel_resid_true"] for i in info) <= 1e-6
     assert col_rel_err(host(x), gp.solve(okern(w), w.X, B)).max() <= 1e-4
+
+
+# ---------------------------------------------------------------- bf16 forms
+# n >= 32768 square RBF products of the bf16 forms take the same Gram form
+# (distances on v_mfma_f32_32x32x2_f32, entries then split into bf16 pieces).
+# Bars as for the direct-difference bf16 forms: x3 the FP32 bar, x2 3e-5, x1
+# the bf16 bound 1e-2 (its floor is ~1e-3).
+BF16_BARS = {"bf16x1": 1e-2, "bf16x2": 3e-5, "bf16x3": 1e-5}
+
+
+@pytest.mark.parametrize("form", ["bf16x1", "bf16x2", "bf16x3"])
+@pytest.mark.parametrize("t", [17, 33, 64, 65])
+def test_gram_bf16_forms_sampled_rows(mf, form, t):
+    # n = 40003: a ragged last 32-j distance tile and row block
+    banner(f"matvec {form} Gram form rbf d=4 n=40003 t={t}, 384 sampled rows")
+    w = inputs.random_problem(630, 40003, 4, "rbf", ard=True)
+    V = inputs.gaussian_rhs(631 + t, 40003, t)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision=form))
+    rows = np.random.default_rng(632).choice(w.n, size=384, replace=False)
+    ref = gp.ky_matvec_rows(okern(w), w.X, V, rows)
+    err = col_rel_err(out[rows], ref).max()
+    print(f"{form} t={t}: max column error {err:.2e}")
+    assert err <= BF16_BARS[form]
+    assert np.isfinite(out).all()
+
+
+@pytest.mark.parametrize("d", [1, 6])
+def test_gram_bf16_dims(mf, d):
+    # d = 1: one distance MFMA of two (one zero) dims; d = 6: four (DG = 8)
+    banner(f"matvec bf16x3 Gram form rbf d={d} n=33000 t=33")
+    w = inputs.random_problem(633 + d, 33000, d, "rbf", ard=True)
+    V = inputs.gaussian_rhs(634, 33000, 33)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x3"))
+    rows = np.random.default_rng(635).choice(w.n, size=256, replace=False)
+    assert col_rel_err(out[rows], gp.ky_matvec_rows(okern(w), w.X, V, rows)).max() <= 1e-5
+
+
+def test_gram_bf16_guard_falls_back(mf):
+    # l = 0.02 on [0, 1]^2: max |g|^2 ~ 900, every block takes the direct
+    # branch on the permuted fragments; x3 must still meet the FP32 bar
+    banner("matvec bf16x3 Gram guard: rbf d=2 l=0.02 n=36000 t=33")
+    w = inputs.random_problem(636, 36000, 2, "rbf", lengthscale=0.02)
+    V = inputs.gaussian_rhs(637, 36000, 33)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="bf16x3"))
+    rows = np.random.default_rng(638).choice(w.n, size=256, replace=False)
+    assert col_rel_err(out[rows], gp.ky_matvec_rows(okern(w), w.X, V, rows)).max() <= 1e-5
