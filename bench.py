@@ -95,17 +95,17 @@ def batch_leg(args) -> int:
               file=sys.stderr, flush=True)
 
     print("[bench] batch warm-up call (tunes the tile length)", file=sys.stderr, flush=True)
-    plan.mll_and_grad(X, y, Z, progress=progress)
+    plan.mll_and_grad(X, y, Z, progress=progress, precision=args.precision)
     torch.cuda.synchronize()
     mfgp.timing_enable(True)
     t0 = time.perf_counter()
-    r = plan.mll_and_grad(X, y, Z, progress=progress)
+    r = plan.mll_and_grad(X, y, Z, progress=progress, precision=args.precision)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ph = mfgp.timing_phases()
     mfgp.timing_enable(False)
     entries = sum(float(w.n) ** 2 for w in probs)
-    print(json.dumps({"mode": "batch", "workload": "batch64", "problems": len(probs),
+    print(json.dumps({"mode": "batch", "workload": "batch64", "precision": args.precision, "problems": len(probs),
                       "rows": int(sum(w.n for w in probs)), "entries_per_product": entries,
                       "mll_grad_s": el, "cg_s": ph["cg_ms"] * 1e-3, "slq_s": ph["slq_ms"] * 1e-3,
                       "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"], "plan": plan.info(),

@@ -242,8 +242,16 @@ hipError_t gram_prepare(const Operator& op, void* scratch, GramPrep& g, hipStrea
     g.nrm = reinterpret_cast<float*>(base + L.nrm);
     g.gmax = reinterpret_cast<unsigned*>(base + L.gmax);
     g.dg = op.d <= 4 ? 4 : 8;
-    double* mpart = reinterpret_cast<double*>(base + L.mpart);
-    float* mu = reinterpret_cast<float*>(base + L.mu);
+    return gram_prepare_into(op, g, base + L.mpart, s);
+}
+
+size_t gram_mean_bytes() { return static_cast<size_t>(kMeanBlocks) * MFGP_MAX_D * sizeof(double) + 256; }
+
+hipError_t gram_prepare_into(const Operator& op, const GramPrep& g, void* mean_scratch, hipStream_t s) {
+    const int64_t n = op.n;
+    if (op.d < 1 || op.d > 8) return hipErrorNotSupported;
+    double* mpart = static_cast<double*>(mean_scratch);
+    float* mu = reinterpret_cast<float*>(mpart + kMeanBlocks * MFGP_MAX_D);
     const int nb = static_cast<int>(std::min<int64_t>(kMeanBlocks, (n + 255) / 256));
     hipLaunchKernelGGL(gram_mean_stage1, dim3(nb), dim3(256), 0, s, op.U, n, op.d, mpart);
     hipLaunchKernelGGL(gram_mean_stage2, dim3(1), dim3(64), 0, s, mpart, nb, op.d, n, mu, g.gmax);

@@ -64,6 +64,12 @@ struct GramPrep {
 };
 size_t gram_prep_bytes(int64_t n);
 hipError_t gram_prepare(const Operator& op, void* scratch, GramPrep& g, hipStream_t s);
+// Rows of G and nrm for n points (n rounded up to 64).
+inline int64_t gram_rows(int64_t n) { return (n + 63) / 64 * 64; }
+// The same into caller-placed G (gram_rows(n) x g.dg), nrm and gmax, with
+// gram_mean_bytes() of scratch for the column means.
+size_t gram_mean_bytes();
+hipError_t gram_prepare_into(const Operator& op, const GramPrep& g, void* mean_scratch, hipStream_t s);
 size_t gram_scratch_bytes(int64_t n, int t);
 hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, bool with_noise, const float* Vself,
                       void* scratch, hipStream_t s);
