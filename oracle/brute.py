@@ -11,7 +11,13 @@ from __future__ import annotations
 import math
 
 
-def entry(family: str, xi, xj, ls, s2: float) -> float:
+def entry(family: str, xi, xj, ls, s2: float, period: float = 1.0) -> float:
+    if family == "periodic":
+        a = 0.0
+        for k in range(len(xi)):
+            sk = math.sin(math.pi * (float(xi[k]) - float(xj[k])) / period)
+            a += 2.0 * sk * sk / (float(ls[k]) * float(ls[k]))
+        return s2 * math.exp(-a)
     r2 = 0.0
     for k in range(len(xi)):
         t = (float(xi[k]) - float(xj[k])) / float(ls[k])

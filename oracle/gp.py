@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.linalg import cho_factor, cho_solve
 
-FAMILIES = ("rbf", "matern12", "matern32", "matern52")
+FAMILIES = ("rbf", "matern12", "matern32", "matern52", "periodic")
 
 
 @dataclass
@@ -42,6 +42,7 @@ class Kern:
     lengthscale: object  # float (shared) or sequence of length d (ARD)
     outputscale: float = 1.0
     noise: float = 0.01
+    period: float = 1.0  # the periodic family's period p (unused otherwise)
     ard: bool = field(init=False)
 
     def __post_init__(self):
@@ -56,17 +57,22 @@ class Kern:
         return np.full(d, float(ls)) if ls.ndim == 0 else ls.astype(np.float64)
 
     def n_params(self, d: int) -> int:
-        return (d if self.ard else 1) + 2
+        return (d if self.ard else 1) + (3 if self.family == "periodic" else 2)
 
     def with_params(self, theta) -> "Kern":
         """New kernel from a parameter vector in gradient order."""
         theta = np.asarray(theta, dtype=np.float64)
-        nl = len(theta) - 2
+        extra = 3 if self.family == "periodic" else 2
+        nl = len(theta) - extra
         ls = theta[:nl] if self.ard else float(theta[0])
+        if self.family == "periodic":
+            return Kern(self.family, ls, float(theta[nl + 1]), float(theta[nl + 2]), period=float(theta[nl]))
         return Kern(self.family, ls, float(theta[nl]), float(theta[nl + 1]))
 
     def params(self, d: int) -> np.ndarray:
         ls = self.ls_vec(d) if self.ard else np.array([float(self.lengthscale)])
+        if self.family == "periodic":
+            return np.concatenate([ls, [self.period, self.outputscale, self.noise]])
         return np.concatenate([ls, [self.outputscale, self.noise]])
 
 
@@ -128,9 +134,27 @@ def dshape_factor(family: str, r2: np.ndarray) -> np.ndarray:
     raise ValueError(family)
 
 
+def periodic_sum(X1: np.ndarray, X2: np.ndarray, ls: np.ndarray, period: float) -> np.ndarray:
+    """S_ij = sum_k 2 sin^2(pi (X1_ik - X2_jk) / p) / l_k^2 (the periodic exponent)."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    S = np.zeros((X1.shape[0], X2.shape[0]))
+    for k in range(X1.shape[1]):
+        sk = np.sin(np.pi * (X1[:, k, None] - X2[None, :, k]) / period)
+        S += 2.0 * sk * sk / ls[k] ** 2
+    return S
+
+
 def kernel_matrix(kern: Kern, X1: np.ndarray, X2: np.ndarray) -> np.ndarray:
-    """K(X1, X2) with outputscale, no noise (Sec. 2: K_ff or K_*f)."""
+    """K(X1, X2) with outputscale, no noise (Sec. 2: K_ff or K_*f).
+
+    Periodic (Sec. 3 names it; the reading is the standard exp-sine-squared
+    form with ARD lengthscales and one period, as in MacKay 1998 / Rasmussen
+    & Williams eq. 4.31): k = s^2 exp(-sum_k 2 sin^2(pi (x_k - x'_k) / p) / l_k^2).
+    """
     d = np.asarray(X1).shape[1]
+    if kern.family == "periodic":
+        return kern.outputscale * np.exp(-periodic_sum(X1, X2, kern.ls_vec(d), kern.period))
     r2 = scaled_sqdist(X1, X2, kern.ls_vec(d))
     return kern.outputscale * shape_from_r2(kern.family, r2)
 
@@ -215,10 +239,28 @@ def dky_matrices(kern: Kern, X: np.ndarray):
     d/dl_k : s^2 g(r^2) Delta_k^2 / l_k^3   (summed over k for a shared l)
     d/ds^2 : K / s^2 = f(r^2)
     d/dsigma^2 : I
+    The periodic family has d/dp between the lengthscales and s^2.
     """
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
     ls = kern.ls_vec(d)
+    if kern.family == "periodic":
+        # k = s^2 exp(-S), S = sum_k 2 sin^2(pi D_k / p) / l_k^2:
+        # dk/dl_k = k 4 sin^2(pi D_k / p) / l_k^3
+        # dk/dp   = k sum_k (2 pi D_k / (p^2 l_k^2)) sin(2 pi D_k / p)
+        p = kern.period
+        K = kernel_matrix(kern, X, X)
+        per_dim, dp = [], np.zeros((n, n))
+        for k in range(d):
+            dk = X[:, k, None] - X[None, :, k]
+            sk = np.sin(np.pi * dk / p)
+            per_dim.append(K * 4.0 * sk * sk / ls[k] ** 3)
+            dp += 2.0 * np.pi * dk / (p * p * ls[k] ** 2) * np.sin(2.0 * np.pi * dk / p)
+        mats = per_dim if kern.ard else [sum(per_dim)]
+        mats.append(K * dp)
+        mats.append(K / kern.outputscale)
+        mats.append(np.eye(n))
+        return mats
     r2 = scaled_sqdist(X, X, ls)
     g = kern.outputscale * dshape_factor(kern.family, r2)
     per_dim = []
