@@ -202,7 +202,28 @@ def matvec_leg(args) -> int:
                      "rhs_products_per_s": n * n * t / (ms * 1e-3),
                      "tflops": n * n * (3 * 4 + 1 + 2 * t) / (ms * 1e-3) / 1e12})
         print(f"[bench] matvec n={n} t={t} {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
-    print(json.dumps({"mode": "matvec", "workload": "rbf100k geometry (d=4, RBF l=0.3)", "rows": rows}))
+    # the periodic family on the same points: RBF sweeps over its 8 circle features
+    pk = mfgp.Kernel("periodic", 1.0, full.outputscale, full.noise, period=0.5)
+    prow = []
+    for t, prec in ((1, "fp32"), (33, "fp32"), (33, "fp32_direct"), (33, "bf16x2")):
+        V = Vall[:, :t].contiguous()
+        out = torch.empty_like(V)
+        ms = _median_call_ms(lambda: mfgp.kernel_matvec(pk, Xf, V, precision=prec, out=out))
+        n = full.n
+        prow.append({"n": n, "t": t, "precision": prec, "ms": ms, "entries_per_s": n * n / (ms * 1e-3),
+                     "tflops": n * n * (3 * 8 + 1 + 2 * t) / (ms * 1e-3) / 1e12})
+        print(f"[bench] periodic matvec n={n} t={t} {prec}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    # one adjoint sweep (t = 33: [alpha, 32 probes]) per family: the periodic
+    # sweep adds the period term to the paired lengthscale terms
+    A = Vall.contiguous()
+    arow = []
+    for name, k in (("rbf", kern), ("periodic", pk)):
+        ms = _median_call_ms(lambda: mfgp.kernel_adjoint(k, Xf, A, A, [0.5] + [-0.5 / 32] * 32))
+        arow.append({"family": name, "n": full.n, "t": 33, "ms": ms})
+        print(f"[bench] adjoint {name} n={full.n} t=33: {ms:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "matvec", "workload": "rbf100k geometry (d=4, RBF l=0.3)", "rows": rows,
+                      "periodic": {"kernel": "periodic d=4 l=1.0 p=0.5 (8 features)", "rows": prow},
+                      "adjoint": arow}))
     return 0
 
 

@@ -30,12 +30,21 @@
  *                   MATERN12:    k = s2 exp(-rho)
  *                   MATERN32:    k = s2 (1 + sqrt3 rho) exp(-sqrt3 rho)
  *                   MATERN52:    k = s2 (1 + sqrt5 rho + 5 rho^2 / 3) exp(-sqrt5 rho)
+ *                   PERIODIC:    k = s2 exp(-sum_k 2 sin^2(pi (x_k - x'_k) / p) / l_k^2)
  *            with r^2 = sum_k ((x_k - x'_k) / l_k)^2, rho = sqrt(r^2), one
  *            lengthscale per dimension when `ard` is set and lengthscale[0]
- *            for all dimensions otherwise (the families of Sec. 3 "Kernels";
- *            s2 is the Scale variance, sigma^2 the noise variance of Sec. 2).
+ *            for all dimensions otherwise, and one period p (the families of
+ *            Sec. 3 "Kernels"; s2 is the Scale variance, sigma^2 the noise
+ *            variance of Sec. 2).  PERIODIC is evaluated as RBF with unit
+ *            lengthscales on the 2d features (cos 2 pi x_k / p, sin 2 pi x_k / p) / l_k,
+ *            whose squared distance is sum_k 4 sin^2(pi (x_k - x'_k) / p) / l_k^2;
+ *            every product form of RBF applies to it.
  * Gradients  are with respect to the positive parameters in the order
- *            [l_1 .. l_d] (ard) or [l] (shared), then s2, then sigma^2.
+ *            [l_1 .. l_d] (ard) or [l] (shared), then p (PERIODIC only), then
+ *            s2, then sigma^2 (mfgp_num_params of them).
+ * Feature dimension  the d argument of the workspace-size queries is the
+ *            kernel's feature dimension mfgp_feature_dim(kern): the input
+ *            dimension, twice it for PERIODIC.
  * Threads    The library is reentrant: no mutable globals besides the
  *            thread-local last HIP error and the preconditioned calls'
  *            thread-local rocBLAS handles.
@@ -58,7 +67,8 @@ typedef enum {
     MFGP_RBF = 0,
     MFGP_MATERN12 = 1,
     MFGP_MATERN32 = 2,
-    MFGP_MATERN52 = 3
+    MFGP_MATERN52 = 3,
+    MFGP_PERIODIC = 4     /* d <= MFGP_MAX_D / 2; not offered by the batched calls */
 } mfgp_family;
 
 /* Arithmetic of the product (kernel entries are always float32).  The
@@ -123,6 +133,7 @@ typedef struct {
     float lengthscale[MFGP_MAX_D];        /* > 0, finite; [0] only when ard == 0        */
     float outputscale;                    /* s2 > 0                                     */
     float noise;                          /* sigma^2 >= 0 (> 0 for solves)              */
+    float period;                         /* PERIODIC: p > 0, finite; ignored otherwise  */
 } mfgp_kernel;
 
 /* Conjugate-gradient options (host struct). */
@@ -165,7 +176,11 @@ typedef struct {
                                      drifted more than 10% from the true residual           */
 } mfgp_cg_info;
 
-/* Bytes of workspace a call needs.  op: mfgp_op; n rows; d dims; t columns
+/* Feature dimension of a kernel (the d of the workspace-size queries): kern->d,
+ * 2 kern->d for MFGP_PERIODIC; 0 for a NULL kernel or kern->d < 1. */
+int mfgp_feature_dim(const mfgp_kernel* kern);
+
+/* Bytes of workspace a call needs.  op: mfgp_op; n rows; d = mfgp_feature_dim; t columns
  * (matvec/cg/adjoint/residual), test points m for MFGP_OP_PREDICT passed in t
  * as the column count of alpha and in max_iter as m; number of probes + 1 for
  * MFGP_OP_MLL; max_iter as passed in mfgp_cg_opts (0 = default).  Returns 0 for
@@ -284,7 +299,8 @@ typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
  * differing from kern[0].family, a non-finite or non-positive lengthscale,
  * outputscale or noise, a negative offset, or row_off that is not the prefix
  * sum of n (rows must be packed back to back in problem order);
- * MFGP_UNSUPPORTED for a column count without a compiled kernel. */
+ * MFGP_UNSUPPORTED for a column count without a compiled kernel or the
+ * MFGP_PERIODIC family. */
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
                            int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
 int mfgp_batch_plan_destroy(mfgp_batch_plan plan);
@@ -407,7 +423,7 @@ int mfgp_timing_read(int32_t kind, double* sweep_ms, int64_t* launches, double* 
                      double* flops);
 int mfgp_timing_phases(double* cg_ms, double* slq_ms, double* adjoint_ms);
 
-/* Number of gradient entries for a kernel: (ard ? d : 1) + 2. */
+/* Number of gradient entries for a kernel: (ard ? d : 1) + 2, + 1 for MFGP_PERIODIC. */
 int mfgp_num_params(const mfgp_kernel* kern);
 
 const char* mfgp_status_string(int status);

@@ -77,9 +77,13 @@ static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
 static int check_kernel(const mfgp_kernel* k, bool need_noise) {
     if (!k) return MFGP_ERR_ARG;
-    if (k->family < MFGP_RBF || k->family > MFGP_MATERN52) return MFGP_ERR_ARG;
+    if (k->family < MFGP_RBF || k->family > MFGP_PERIODIC) return MFGP_ERR_ARG;
     if (k->d < 1) return MFGP_ERR_ARG;
     if (k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;
+    if (k->family == MFGP_PERIODIC) {
+        if (!finite_pos(k->period)) return MFGP_ERR_ARG;
+        if (2 * k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;   // 2 d circle features
+    }
     const int nl = k->ard ? k->d : 1;
     for (int q = 0; q < nl; ++q)
         if (!finite_pos(k->lengthscale[q])) return MFGP_ERR_ARG;
@@ -235,8 +239,38 @@ static double lengthscale_factor(int family, double l) {
     }
 }
 
-// grad[0..nl-1] lengthscales, grad[nl] s2 from the adjoint sums G_k, G_s.
+// Index of d/d sigma^2 in the gradient: after the lengthscales, the period
+// (periodic family) and s2.
+static int noise_index(const mfgp_kernel* k) {
+    return (k->ard ? k->d : 1) + (k->family == MFGP_PERIODIC ? 2 : 1);
+}
+
+// Feature dimension of the prescaled coordinates (the d of the size queries).
+static int feature_dim(const mfgp_kernel* k) { return k->family == MFGP_PERIODIC ? 2 * k->d : k->d; }
+
+// grad[0..nl-1] lengthscales, grad[nl] s2 from the adjoint sums G_k, G_s;
+// periodic family: grad[0..nl-1] lengthscales, grad[nl] the period, grad[nl+1]
+// s2 from G_l, G_s, G_p (see adjoint_periodic_kernel): with c the RBF scale,
+//   dk/dl_k = s2 G_l[k] / (c^2 l_k),  dk/dp = s2 (2 pi / (p^2 c^2)) G_p.
 static void grad_from_sums(const Operator& op, int ard, const double* G, double* grad) {
+    if (op.periodic) {
+        const int din = op.din;
+        const double c = family_scale(MFGP_RBF);
+        double shared = 0.0;
+        for (int k = 0; k < din; ++k) {
+            const double gk = static_cast<double>(op.s2) * G[k] / (c * c * op.ls[2 * k]);
+            if (ard)
+                grad[k] = gk;
+            else
+                shared += gk;
+        }
+        const int nl = ard ? din : 1;
+        if (!ard) grad[0] = shared;
+        const double two_pi = 6.283185307179586477;
+        grad[nl] = static_cast<double>(op.s2) * two_pi / (op.period * op.period * c * c) * G[din + 1];
+        grad[nl + 1] = G[din];
+        return;
+    }
     const int d = op.d;
     double shared = 0.0;
     for (int k = 0; k < d; ++k) {
@@ -276,7 +310,12 @@ const char* mfgp_status_string(int status) {
 
 int mfgp_num_params(const mfgp_kernel* k) {
     if (!k || k->d < 1) return 0;
-    return (k->ard ? k->d : 1) + 2;
+    return noise_index(k) + 1;
+}
+
+int mfgp_feature_dim(const mfgp_kernel* k) {
+    if (!k || k->d < 1) return 0;
+    return feature_dim(k);
 }
 
 size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
@@ -311,11 +350,11 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
     if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
     if ((st = check_precision_cols(precision, t)) != MFGP_OK) return st;
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, precision, 0))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, feature_dim(kern), t, precision, 0))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    MatvecWs w = carve_matvec(cv, n, kern->d, t, precision);
+    MatvecWs w = carve_matvec(cv, n, feature_dim(kern), t, precision);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     if (is_fp32_class(precision))
@@ -331,11 +370,11 @@ int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !B || !Xsol || !R || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_RESIDUAL, n, kern->d, t, 0, 0))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_RESIDUAL, n, feature_dim(kern), t, 0, 0))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    ResidWs w = carve_resid(cv, n, kern->d, t);
+    ResidWs w = carve_resid(cv, n, feature_dim(kern), t);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     ABI_CHECK(residual_f64(op, B, Xsol, t, R, w.scratch, s));
@@ -358,11 +397,11 @@ int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     if ((st = check_opts(opts)) != MFGP_OK) return st;
     if (!X || !B || !Xsol || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
     if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_CG, n, kern->d, t, opts->precision, opts->max_iter))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_CG, n, feature_dim(kern), t, opts->precision, opts->max_iter))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    CgWs w = carve_cgws(cv, n, kern->d, t, opts->precision);
+    CgWs w = carve_cgws(cv, n, feature_dim(kern), t, opts->precision);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     const int max_iter = default_max_iter(n, opts->max_iter);
@@ -375,15 +414,16 @@ int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const 
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !Xs || !A || !MU || !ws || n < 1 || m < 1 || t < 1) return MFGP_ERR_ARG;
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_PREDICT, n, kern->d, t, 0, static_cast<int32_t>(m)))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_PREDICT, n, feature_dim(kern), t, 0, static_cast<int32_t>(m)))
         return MFGP_ERR_WORKSPACE;
     if (m > 0x7fffffff) return MFGP_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    PredictWs w = carve_predict(cv, n, kern->d, m, t);
+    PredictWs w = carve_predict(cv, n, feature_dim(kern), m, t);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
-    ABI_CHECK(launch_prescale(Xs, m, kern->d, op.fac, w.Us, s));
+    Operator ops = make_operator(*kern, Xs, m, w.Us);
+    ABI_CHECK(prescale(ops, s));
     ABI_CHECK(apply_fp32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, MFGP_FP32, s));
     return MFGP_OK;
 }
@@ -421,10 +461,10 @@ int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, co
     if (!X || !Xs || !var || !ws || n < 1 || m < 1 || p < 1) return MFGP_ERR_ARG;
     if ((st = check_precision_cols(opts->precision, p)) != MFGP_OK) return st;
     if (m > 0x7fffffff) return MFGP_UNSUPPORTED;
-    if (ws_bytes < mfgp_variance_workspace_bytes(n, kern->d, m, p, opts->precision)) return MFGP_ERR_WORKSPACE;
+    if (ws_bytes < mfgp_variance_workspace_bytes(n, feature_dim(kern), m, p, opts->precision)) return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    VarWs w = carve_variance(cv, n, kern->d, m, p, opts->precision);
+    VarWs w = carve_variance(cv, n, feature_dim(kern), m, p, opts->precision);
     Operator op = make_operator(*kern, X, n, w.U);
     Operator ops = make_operator(*kern, Xs, m, w.Us);
     ABI_CHECK(prescale(op, s));
@@ -464,11 +504,11 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !A || !B || !colw || !grad || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_ADJOINT, n, kern->d, t, 0, 0))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_ADJOINT, n, feature_dim(kern), t, 0, 0))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    AdjWs w = carve_adjoint(cv, n, kern->d, t);
+    AdjWs w = carve_adjoint(cv, n, feature_dim(kern), t);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     double sums[MFGP_MAX_D + 1];
@@ -480,7 +520,7 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
     grad_from_sums(op, kern->ard, sums, grad);
     double sn = 0.0;
     for (int c = 0; c < t; ++c) sn += colw[c] * ab[c];
-    grad[(kern->ard ? kern->d : 1) + 1] = sn;
+    grad[noise_index(kern)] = sn;
     return MFGP_OK;
 }
 
@@ -496,11 +536,11 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     const int t = p + 1;
     if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
     const int max_iter = default_max_iter(n, opts->max_iter);
-    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MLL, n, kern->d, t, opts->precision, max_iter))
+    if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MLL, n, feature_dim(kern), t, opts->precision, max_iter))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    MllWs w = carve_mll(cv, n, kern->d, t, opts->precision, max_iter);
+    MllWs w = carve_mll(cv, n, feature_dim(kern), t, opts->precision, max_iter);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     const float* Zp = Z;
@@ -597,7 +637,7 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
         grad_from_sums(op, kern->ard, sums, grad);
         double tr = 0.0;
         for (int c = 1; c < t; ++c) tr += h[t + c];
-        grad[(kern->ard ? kern->d : 1) + 1] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
+        grad[noise_index(kern)] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
         timing_phase(2, ms_since(t0));
     }
     if (cg_status != MFGP_OK) return cg_status;
@@ -629,11 +669,11 @@ int mfgp_pivoted_cholesky(const mfgp_kernel* kern, const float* X, int64_t n, in
     int st = check_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !L || !piv || !ws || n < 1 || rank < 1 || rank > n || rank > MFGP_MAX_RANK) return MFGP_ERR_ARG;
-    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCHOL, n, kern->d, 1, rank, MFGP_FP32, 0))
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCHOL, n, feature_dim(kern), 1, rank, MFGP_FP32, 0))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    PcholWs w = carve_pchol(cv, n, kern->d);
+    PcholWs w = carve_pchol(cv, n, feature_dim(kern));
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     ABI_CHECK(pivoted_cholesky(op, rank, L, piv, w.scratch, s));
@@ -682,11 +722,11 @@ int mfgp_precond_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, co
         (rank > 0 && !L))
         return MFGP_ERR_ARG;
     if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
-    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCG, n, kern->d, t, rank, opts->precision, opts->max_iter))
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCG, n, feature_dim(kern), t, rank, opts->precision, opts->max_iter))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    PcgWs w = carve_pcgws(cv, n, kern->d, rank, t, opts->precision);
+    PcgWs w = carve_pcgws(cv, n, feature_dim(kern), rank, t, opts->precision);
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
     Precond pc;
@@ -715,11 +755,11 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
     const int t = p + 1;
     if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
     const int max_iter = default_max_iter(n, opts->max_iter);
-    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PMLL, n, kern->d, t, rank, opts->precision, max_iter))
+    if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PMLL, n, feature_dim(kern), t, rank, opts->precision, max_iter))
         return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    PmllWs W = carve_pmll(cv, n, kern->d, rank, t, opts->precision, max_iter);
+    PmllWs W = carve_pmll(cv, n, feature_dim(kern), rank, t, opts->precision, max_iter);
     MllWs& w = W.m;
     Operator op = make_operator(*kern, X, n, w.U);
     ABI_CHECK(prescale(op, s));
@@ -827,7 +867,7 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
         ABI_CHECK(hipStreamSynchronize(s));
         double tr = 0.0;
         for (int c = 1; c < t; ++c) tr += huw[c];
-        grad[(kern->ard ? kern->d : 1) + 1] = 0.5 * h[t + 0] - 0.5 * tr / p;
+        grad[noise_index(kern)] = 0.5 * h[t + 0] - 0.5 * tr / p;
         timing_phase(2, ms_since(t0));
     }
     if (cg_status != MFGP_OK) return cg_status;

@@ -77,6 +77,113 @@ static hipError_t adjoint_fd(int tb, const float* U, const float* A, int lda, in
     }
 }
 
+// Periodic family (RBF on the circle features u = c (cos th, sin th) / l,
+// th = 2 pi x / p, see make_operator).  Per entry, with du = u_i - u_j over the
+// 2 DIN features and k^ = 2^(-|du|^2):
+//   G_l[k] += W_ij k^ (du_2k^2 + du_2k+1^2)   (both features of input k scale with 1/l_k)
+//   G_s    += W_ij k^
+//   G_p    += W_ij k^ sum_k (x_ik - x_jk) (u_i,2k+1 u_j,2k - u_i,2k u_j,2k+1)
+// The last bracket is (c / l_k)^2 sin(th_ik - th_jk), so that
+//   dk/dp = s2 k^ sum_k (2 pi (x_ik - x_jk) / (p^2 l_k^2)) sin(2 pi (x_ik - x_jk) / p)
+// is s2 (2 pi / (p^2 c^2)) times the G_p term; the host applies the factors.
+template <int DIN, int TB>
+__global__ __launch_bounds__(kBlock) void adjoint_periodic_kernel(
+    const float* __restrict__ X, const float* __restrict__ U, const float* __restrict__ A, int lda, int c0,
+    ColW w, const float* __restrict__ B, int64_t n, int chunks, int64_t jchunk, double* __restrict__ partial) {
+    constexpr int D = 2 * DIN;
+    constexpr int W = DIN + 2;
+    __shared__ double red[W * (kBlock / 64)];
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int64_t i = static_cast<int64_t>(rb) * kBlock + threadIdx.x;
+    const int64_t ii = i < n ? i : n - 1;
+    float ui[D], xi[DIN], ai[TB];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ui[k] = U[ii * D + k];
+#pragma unroll
+    for (int k = 0; k < DIN; ++k) xi[k] = X[ii * DIN + k];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) ai[c] = i < n ? A[ii * lda + c0 + c] * w.w[c] : 0.0f;
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
+    const int64_t jend = j0 + jchunk < n ? j0 + jchunk : n;
+    const int cnt = j0 < jend ? static_cast<int>(jend - j0) : 0;
+    const float* uc = U + j0 * D;
+    const float* xc = X + j0 * DIN;
+    const float* bc = B + j0 * TB;
+    // two-level FP32 sums (kSeg entries per level-one segment), FP64 at the end
+    float g[W], tg[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        g[k] = 0.0f;
+        tg[k] = 0.0f;
+    }
+    for (int q = 0; q < cnt; ++q) {
+        if (q % kSeg == 0 && q > 0) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                tg[k] += g[k];
+                g[k] = 0.0f;
+            }
+        }
+        const float* uj = uc + q * D;
+        float df[D];
+        float d2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            df[k] = ui[k] - uj[k];
+            d2 = fmaf(df[k], df[k], d2);
+        }
+        const float kv = __builtin_amdgcn_exp2f(-d2);
+        float wij = 0.0f;
+#pragma unroll
+        for (int c = 0; c < TB; ++c) wij = fmaf(ai[c], bc[q * TB + c], wij);
+        const float wk = wij * kv;
+        float h = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIN; ++k) {
+            g[k] = fmaf(wk, fmaf(df[2 * k], df[2 * k], df[2 * k + 1] * df[2 * k + 1]), g[k]);
+            const float cr = fmaf(ui[2 * k + 1], uj[2 * k], -ui[2 * k] * uj[2 * k + 1]);
+            h = fmaf(xi[k] - xc[q * DIN + k], cr, h);
+        }
+        g[DIN] += wk;
+        g[DIN + 1] = fmaf(wk, h, g[DIN + 1]);
+    }
+    double v[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = static_cast<double>(tg[k]) + static_cast<double>(g[k]);
+    block_sum_write<W>(v, red, partial + static_cast<int64_t>(blockIdx.x) * W);
+}
+
+template <int DIN>
+static hipError_t adjoint_periodic_d(int tb, const float* X, const float* U, const float* A, int lda, int c0,
+                                     const ColW& w, const float* B, int64_t n, const SweepPlan& p,
+                                     double* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+    switch (tb) {
+#define MFGP_CASE(TBV)                                                                                    \
+    case TBV:                                                                                             \
+        hipLaunchKernelGGL((adjoint_periodic_kernel<DIN, TBV>), grid, dim3(kBlock), 0, s, X, U, A, lda, c0, \
+                           w, B, n, p.chunks, p.jchunk, partial);                                        \
+        return hipGetLastError();
+        MFGP_TB_LIST(MFGP_CASE)
+#undef MFGP_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t adjoint_periodic(int din, int tb, const float* X, const float* U, const float* A, int lda,
+                                   int c0, const ColW& w, const float* B, int64_t n, const SweepPlan& p,
+                                   double* partial, hipStream_t s) {
+    switch (din) {
+        case 1: return adjoint_periodic_d<1>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
+        case 2: return adjoint_periodic_d<2>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
+        case 3: return adjoint_periodic_d<3>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
+        case 4: return adjoint_periodic_d<4>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int FAM>
 static hipError_t adjoint_f(int D, int tb, const float* U, const float* A, int lda, int c0,
                             const ColW& w, const float* B, int64_t n, const SweepPlan& p,
@@ -102,11 +209,14 @@ size_t adjoint_scratch_doubles(int64_t n, int d, int t) {
     return part + pack + 2 * (d + 1) + 128;
 }
 
-// sums_host[0..d-1] = G_k, sums_host[d] = G_s (see the file comment).
+// sums_host[0..d-1] = G_k, sums_host[d] = G_s (see the file comment); for the
+// periodic family sums_host[0..din-1] = G_l, [din] = G_s, [din+1] = G_p (see
+// adjoint_periodic_kernel).
 hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int t,
                         const double* colw_host, double* sums_host, double* scratch,
                         hipStream_t s) {
     const int d = op.d;
+    const int width = op.periodic ? op.din + 2 : d + 1;
     const int64_t n = op.n;
     const SweepPlan p = plan_sweep(n, n);
     const int nblocks = p.rowblocks * p.chunks;
@@ -126,7 +236,9 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
         }
         hipError_t e;
         void* tok = timing_begin(s);
-        switch (op.family) {
+        if (op.periodic) {
+            e = adjoint_periodic(op.din, tb, op.X, op.U, A, t, c0, w, bb, n, p, partial, s);
+        } else switch (op.family) {
             case MFGP_RBF: e = adjoint_f<MFGP_RBF>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
             case MFGP_MATERN12: e = adjoint_f<MFGP_MATERN12>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
             case MFGP_MATERN32: e = adjoint_f<MFGP_MATERN32>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
@@ -137,14 +249,14 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
             timing_end(tok, s, kSweepAdjoint, ent, ent * sweep_flops_per_entry(op.family, d, tb, true));
         }
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(adjoint_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, d + 1,
+        hipLaunchKernelGGL(adjoint_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, width,
                            total, first ? 0 : 1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         first = 0;
         c0 += tb;
     }
-    hipError_t e = hipMemcpyAsync(sums_host, total, (d + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(sums_host, total, width * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
 }

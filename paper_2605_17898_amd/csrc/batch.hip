@@ -956,6 +956,8 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
 #undef MFGP_T
     if (!tb_ok) return MFGP_UNSUPPORTED;
     const int fam = batch->kern[0].family;
+    if (fam == MFGP_PERIODIC) return MFGP_UNSUPPORTED;
+    if (fam < MFGP_RBF || fam > MFGP_MATERN52) return MFGP_ERR_ARG;
     auto* P = new mfgp_batch_plan_s();
     P->nprob = batch->nprob;
     P->p = num_probes;

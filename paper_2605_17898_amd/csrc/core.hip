@@ -166,24 +166,51 @@ hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, f
 
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
     Operator op;
-    op.family = k.family;
-    op.d = k.d;
+    op.periodic = k.family == MFGP_PERIODIC;
+    op.family = op.periodic ? MFGP_RBF : k.family;
+    op.din = k.d;
+    op.d = op.periodic ? 2 * k.d : k.d;
+    op.period = op.periodic ? static_cast<double>(k.period) : 0.0;
     op.n = n;
     op.s2 = k.outputscale;
     op.sig2 = k.noise;
     op.X = X;
     op.U = U;
-    const double c = family_scale(k.family);
-    for (int q = 0; q < k.d; ++q) {
-        const double l = k.ard ? k.lengthscale[q] : k.lengthscale[0];
+    const double c = family_scale(op.family);
+    for (int q = 0; q < op.d; ++q) {
+        const int in = op.periodic ? q / 2 : q;   // both features of input k share l_k
+        const double l = k.ard ? k.lengthscale[in] : k.lengthscale[0];
         op.fac[q] = static_cast<float>(c / l);
         op.ls[q] = l;
     }
     return op;
 }
 
+// U[i, 2k] = fac_2k cos(2 pi x_ik / p), U[i, 2k+1] = fac_2k+1 sin(2 pi x_ik / p):
+// the periodic family's features.  The phase x / p is reduced to [-1/2, 1/2]
+// and the circle functions evaluated in FP64, so the features carry only the
+// final rounding to FP32.
+__global__ void periodic_features_kernel(const float* __restrict__ X, int64_t n, int din,
+                                         double p, Fac fac, float* __restrict__ U) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * din) return;
+    const int k = static_cast<int>(idx % din);
+    double ph = static_cast<double>(X[idx]) / p;
+    ph -= rint(ph);
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    U[2 * idx] = static_cast<float>(static_cast<double>(fac.f[2 * k]) * cs);
+    U[2 * idx + 1] = static_cast<float>(static_cast<double>(fac.f[2 * k + 1]) * sn);
+}
+
 hipError_t prescale(const Operator& op, hipStream_t s) {
-    return launch_prescale(op.X, op.n, op.d, op.fac, op.U, s);
+    if (!op.periodic) return launch_prescale(op.X, op.n, op.d, op.fac, op.U, s);
+    Fac f{};
+    for (int q = 0; q < op.d; ++q) f.f[q] = op.fac[q];
+    const int64_t total = op.n * op.din;
+    hipLaunchKernelGGL(periodic_features_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                       0, s, op.X, op.n, op.din, op.period, f, op.U);
+    return hipGetLastError();
 }
 
 size_t apply_scratch_floats(int64_t m, int64_t n, int t) {

@@ -7,9 +7,15 @@ namespace mfgp {
 
 // A kernel operator bound to its training inputs: family, prescale factors
 // and the prescaled coordinates U (device, [n, d]) that the sweeps read.
+// The periodic family is held as RBF on its d = 2 din circle features
+// u = c (cos 2 pi x / p, sin 2 pi x / p) / l (periodic = 1, din the input
+// dimension, period p); for the other families din = d.
 struct Operator {
     int family = 0;
     int d = 0;
+    int din = 0;
+    int periodic = 0;
+    double period = 0.0;
     int64_t n = 0;
     float s2 = 1.0f;
     float sig2 = 0.0f;

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfgp.so")
 
 MAX_D = 8
-FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3}
+FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3, "periodic": 4}
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4, "fp32_direct": 5,
               "fp32_gram": 6}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
@@ -30,7 +30,8 @@ OP_PCHOL, OP_PAPPLY, OP_PCG, OP_PMLL = range(6, 10)
 
 class KernelT(C.Structure):
     _fields_ = [("family", C.c_int32), ("d", C.c_int32), ("ard", C.c_int32),
-                ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float)]
+                ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float),
+                ("period", C.c_float)]
 
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_double)
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_kernel_adjoint": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
         "mfgp_rademacher": (C.c_int, [C.c_uint64, I64, I32, P, P]),
         "mfgp_num_params": (C.c_int, [KP]),
+        "mfgp_feature_dim": (C.c_int, [KP]),
         "mfgp_timing_enable": (C.c_int, [I32]),
         "mfgp_timing_read": (C.c_int, [I32, P, P, P, P]),
         "mfgp_timing_phases": (C.c_int, [P, P, P]),
@@ -122,12 +124,14 @@ def _check(status: int, where: str, allow=(OK,)):
 
 @dataclass
 class Kernel:
-    """Kernel hyperparameters: family, lengthscale (float or per-dimension), s^2, sigma^2."""
+    """Kernel hyperparameters: family, lengthscale (float or per-dimension), s^2, sigma^2
+    and, for the periodic family, the period."""
 
     family: str
     lengthscale: object
     outputscale: float = 1.0
     noise: float = 0.01
+    period: float = 1.0
 
     def struct(self, d: int) -> KernelT:
         k = KernelT()
@@ -146,10 +150,15 @@ class Kernel:
             k.lengthscale[0] = float(ls)
         k.outputscale = float(self.outputscale)
         k.noise = float(self.noise)
+        k.period = float(self.period)
         return k
 
     def n_params(self, d: int) -> int:
         return LIB.mfgp_num_params(C.byref(self.struct(d)))
+
+    def feature_dim(self, d: int) -> int:
+        """The d of the workspace-size queries (2 d for the periodic family)."""
+        return LIB.mfgp_feature_dim(C.byref(self.struct(d)))
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -200,7 +209,7 @@ def kernel_matvec(kern: Kernel, X: torch.Tensor, V: torch.Tensor, precision: str
     t = _cols(V)
     out = torch.empty_like(V) if out is None else _dev(out, torch.float32, "out")
     pr = PRECISIONS[precision]
-    nb = workspace_bytes(OP_MATVEC, n, d, t, pr)
+    nb = workspace_bytes(OP_MATVEC, n, kern.feature_dim(d), t, pr)
     if nb == 0:
         raise MfgpError(ERR_ARG, "kernel_matvec")
     ws = workspace(nb, X.device)
@@ -219,7 +228,7 @@ def residual(kern: Kernel, X: torch.Tensor, B: torch.Tensor, Xsol: torch.Tensor)
     t = _cols(B)
     R = torch.empty(B.shape, dtype=torch.float64, device=B.device)
     rel = (C.c_double * t)()
-    ws = workspace(workspace_bytes(OP_RESIDUAL, n, d, t), X.device)
+    ws = workspace(workspace_bytes(OP_RESIDUAL, n, kern.feature_dim(d), t), X.device)
     ks = kern.struct(d)
     _check(LIB.mfgp_residual(C.byref(ks), _ptr(X), n, _ptr(B), _ptr(Xsol), t, _ptr(R), rel,
                              _ptr(ws), ws.numel(), _stream()), "residual")
@@ -270,7 +279,7 @@ def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, 
         _dev(x0, torch.float64, "x0").clone()
     lan = torch.empty((t, mi, 2), dtype=torch.float64, device=B.device) if want_lanczos else None
     info = (CgInfoT * t)()
-    ws = workspace(workspace_bytes(OP_CG, n, d, t, o.precision, max_iter), X.device)
+    ws = workspace(workspace_bytes(OP_CG, n, kern.feature_dim(d), t, o.precision, max_iter), X.device)
     ks = kern.struct(d)
     st = LIB.mfgp_cg_solve(C.byref(ks), _ptr(X), n, _ptr(B), t, _ptr(Xsol), C.byref(o), info,
                            _ptr(lan), _ptr(ws), ws.numel(), _stream())
@@ -287,7 +296,7 @@ def predict_mean(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, A: torch.Tenso
     m = Xs.shape[0]
     t = _cols(A)
     mu = torch.empty((m,) if A.dim() == 1 else (m, t), dtype=torch.float32, device=X.device)
-    ws = workspace(workspace_bytes(OP_PREDICT, n, d, t, 0, m), X.device)
+    ws = workspace(workspace_bytes(OP_PREDICT, n, kern.feature_dim(d), t, 0, m), X.device)
     ks = kern.struct(d)
     _check(LIB.mfgp_predict_mean(C.byref(ks), _ptr(X), n, _ptr(Xs), m, _ptr(A), t, _ptr(mu), _ptr(ws),
                                  ws.numel(), _stream()), "predict_mean")
@@ -314,7 +323,7 @@ def predict_variance(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, Z: Optiona
     o.probe_seed = seed
     var = torch.empty(m, dtype=torch.float32, device=X.device)
     info = (CgInfoT * p)()
-    ws = workspace(LIB.mfgp_variance_workspace_bytes(n, d, m, p, o.precision), X.device)
+    ws = workspace(LIB.mfgp_variance_workspace_bytes(n, kern.feature_dim(d), m, p, o.precision), X.device)
     ks = kern.struct(d)
     st = LIB.mfgp_predict_variance(C.byref(ks), _ptr(X), n, _ptr(Xs), m, p, _ptr(Z), C.byref(o), _ptr(var),
                                    info, _ptr(ws), ws.numel(), _stream())
@@ -347,7 +356,7 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
     o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed, progress=progress,
                 replacement=replacement)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
-    ws = workspace(workspace_bytes(OP_MLL, n, d, t, o.precision, mi), X.device)
+    ws = workspace(workspace_bytes(OP_MLL, n, kern.feature_dim(d), t, o.precision, mi), X.device)
     ks = kern.struct(d)
     npar = LIB.mfgp_num_params(C.byref(ks))
     mll, ld = C.c_double(), C.c_double()
@@ -374,7 +383,7 @@ def kernel_adjoint(kern: Kernel, X: torch.Tensor, A: torch.Tensor, B: torch.Tens
     ks = kern.struct(d)
     npar = LIB.mfgp_num_params(C.byref(ks))
     g = (C.c_double * npar)()
-    ws = workspace(workspace_bytes(OP_ADJOINT, n, d, t), X.device)
+    ws = workspace(workspace_bytes(OP_ADJOINT, n, kern.feature_dim(d), t), X.device)
     _check(LIB.mfgp_kernel_adjoint(C.byref(ks), _ptr(X), n, _ptr(A), _ptr(B), t, w, g, _ptr(ws),
                                    ws.numel(), _stream()), "kernel_adjoint")
     return list(g)
@@ -399,7 +408,7 @@ def pivoted_cholesky(kern: Kernel, X: torch.Tensor, rank: int):
     n, d = X.shape
     L = torch.empty((rank, n), dtype=torch.float32, device=X.device)
     piv = torch.empty(rank, dtype=torch.int32, device=X.device)
-    ws = workspace(precond_workspace_bytes(OP_PCHOL, n, d, 1, rank), X.device)
+    ws = workspace(precond_workspace_bytes(OP_PCHOL, n, kern.feature_dim(d), 1, rank), X.device)
     ks = kern.struct(d)
     _check(LIB.mfgp_pivoted_cholesky(C.byref(ks), _ptr(X), n, rank, _ptr(L), _ptr(piv), _ptr(ws), ws.numel(),
                                      _stream()), "pivoted_cholesky")
@@ -448,7 +457,7 @@ def precond_cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, L: torch.Te
     Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
     lan = torch.empty((t, mi, 2), dtype=torch.float64, device=B.device) if want_lanczos else None
     info = (CgInfoT * t)()
-    ws = workspace(precond_workspace_bytes(OP_PCG, n, d, t, k, o.precision, max_iter), X.device)
+    ws = workspace(precond_workspace_bytes(OP_PCG, n, kern.feature_dim(d), t, k, o.precision, max_iter), X.device)
     ks = kern.struct(d)
     st = LIB.mfgp_precond_cg_solve(C.byref(ks), _ptr(X), n, _ptr(B), t, _ptr(Xsol), _ptr(L), k, C.byref(o), info,
                                    _ptr(lan), _ptr(ws), ws.numel(), _stream())
@@ -470,7 +479,7 @@ def precond_mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, Z: torc
     t = p + 1
     o = cg_opts(tol, max_iter, 0, -1, precision, False, progress=progress)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
-    ws = workspace(precond_workspace_bytes(OP_PMLL, n, d, t, k, o.precision, mi), X.device)
+    ws = workspace(precond_workspace_bytes(OP_PMLL, n, kern.feature_dim(d), t, k, o.precision, mi), X.device)
     ks = kern.struct(d)
     npar = LIB.mfgp_num_params(C.byref(ks))
     mll, ld = C.c_double(), C.c_double()
@@ -591,13 +600,15 @@ def _kernel_from_params(family: str, params: torch.Tensor, d: int, ard: bool) ->
     th = [float(v) for v in params.detach().cpu().tolist()]
     nl = d if ard else 1
     ls = th[:nl] if ard else th[0]
+    if family == "periodic":
+        return Kernel(family, ls, th[nl + 1], th[nl + 2], period=th[nl])
     return Kernel(family, ls, th[nl], th[nl + 1])
 
 
 class KernelMatvec(torch.autograd.Function):
     """KV = K_y(theta) V with gradients for V and theta.
 
-    params: CPU float64 tensor [l_1..l_d (or l), s2, sigma^2].  backward:
+    params: CPU float64 tensor [l_1..l_d (or l), (period,) s2, sigma^2].  backward:
     grad_V = K_y G (K_y is symmetric) and grad_theta[p] = sum_c G_c^T
     (dK_y/dtheta_p) V_c, both computed by the library (matrix-free product and
     adjoint sweep)."""
@@ -628,7 +639,7 @@ class KernelMatvec(torch.autograd.Function):
 class MarginalLogLikelihood(torch.autograd.Function):
     """log p(y | X, theta) by CG + stochastic Lanczos, differentiable in theta.
 
-    params: CPU float64 tensor [l.. , s2, sigma^2]; Z: probes [n, p] (GPU).
+    params: CPU float64 tensor [l.. , (period,) s2, sigma^2]; Z: probes [n, p] (GPU).
     forward returns a float64 scalar; backward returns grad_out times the
     library's adjoint-sweep gradient (same probes)."""
 

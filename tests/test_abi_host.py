@@ -51,6 +51,27 @@ def test_num_params(m):
     assert m.Kernel("matern52", [0.3, 0.2, 0.5]).n_params(3) == 5
 
 
+def test_periodic_params_and_feature_dim(m):
+    # [l.., p, s2, sigma^2]; the size queries take the 2 d circle features
+    assert m.Kernel("periodic", 0.3, period=0.5).n_params(2) == 4
+    assert m.Kernel("periodic", [0.3, 0.2, 0.5], period=0.5).n_params(3) == 6
+    assert m.Kernel("periodic", 0.3).feature_dim(3) == 6
+    assert m.Kernel("matern32", 0.3).feature_dim(3) == 3
+    assert m.LIB.mfgp_feature_dim(None) == 0
+
+
+@pytest.mark.parametrize("period,d,want", [
+    (0.0, 2, 1), (-1.0, 2, 1), (float("nan"), 2, 1), (float("inf"), 2, 1),
+    (0.5, 5, 6),     # 10 features > MFGP_MAX_D
+    (0.5, 4, 3),     # valid: stops at the workspace check
+])
+def test_periodic_kernel_checks_before_launch(m, period, d, want):
+    k = m.Kernel("periodic", 0.3, 1.0, 0.01, period=period).struct(d)
+    dummy = C.c_void_p(16)
+    st = m.LIB.mfgp_kernel_matvec(C.byref(k), dummy, 10, dummy, 1, C.c_void_p(32), 0, dummy, 16, None)
+    assert st == want
+
+
 def test_workspace_sizes(m):
     for op in range(6):
         t = 2 if op != m.OP_PREDICT else 3

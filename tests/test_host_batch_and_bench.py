@@ -49,6 +49,8 @@ def test_batch_plan_validation(m):
     assert _create(m, [100, 50], [2, 3], [k, k], row_off=[50, 0]) == m.ERR_ARG      # reordered
     st = m.LIB.mfgp_batch_plan_create(None, 7, 0, 0, 0, C.byref(C.c_void_p()))
     assert st == m.ERR_ARG
+    kp = m.Kernel("periodic", 0.3, 1.0, 0.01, period=0.5)
+    assert _create(m, [100, 50], [2, 3], [kp, kp]) == m.UNSUPPORTED                 # not batched
 
 
 def test_bench_refuses_more_than_one_gpu():
