@@ -47,7 +47,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # reading of the same counters (summaries in profiles/).  Valid only for the
 # kernels named below.
 HYB_TRAFFIC_BYTES = 2.664e8
-GRAM_TRAFFIC_BYTES = 6.520e8
+GRAM_TRAFFIC_BYTES = 6.574e8
 # Dominant kernel of the step per precision: (name, bound, HBM bytes per launch).
 STEP_KERNELS = {
     "fp32": ("sweep_gram_kernel<d=4, NT=2, TV=1> (RBF squared distances and the K-tile x V "
