@@ -12,6 +12,11 @@ import math
 
 
 def entry(family: str, xi, xj, ls, s2: float, period: float = 1.0) -> float:
+    if family == "linear":
+        a = 0.0
+        for k in range(len(xi)):
+            a += float(xi[k]) * float(xj[k])
+        return s2 * a
     if family == "periodic":
         a = 0.0
         for k in range(len(xi)):

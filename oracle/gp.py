@@ -21,6 +21,15 @@ Distances are formed by direct differences, never by the ||x||^2 + ||x'||^2 -
 
 Gradient order everywhere: [l_1 .. l_d] (ARD) or [l] (shared), then s^2, then
 sigma^2, as derivatives with respect to these positive parameters.
+
+Linear (Sec. 3 names it among the concrete kernels; no formula is printed):
+the dot-product kernel k = s^2 x.x' (Rasmussen & Williams, ch. 4), whose only
+parameter is s^2, so its gradient order is [s^2, sigma^2].
+
+Sums (Sec. 3: the ``+`` composition of ``Scale``d kernels): SumKern holds
+terms k_t, each with its own parameters and s_t^2, and one noise variance;
+k = sum_t k_t, and its gradient order is each term's parameters without
+sigma^2, in term order, then sigma^2.
 """
 
 from __future__ import annotations
@@ -31,7 +40,7 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy.linalg import cho_factor, cho_solve
 
-FAMILIES = ("rbf", "matern12", "matern32", "matern52", "periodic")
+FAMILIES = ("rbf", "matern12", "matern32", "matern52", "periodic", "linear")
 
 
 @dataclass
@@ -57,11 +66,15 @@ class Kern:
         return np.full(d, float(ls)) if ls.ndim == 0 else ls.astype(np.float64)
 
     def n_params(self, d: int) -> int:
+        if self.family == "linear":
+            return 2
         return (d if self.ard else 1) + (3 if self.family == "periodic" else 2)
 
     def with_params(self, theta) -> "Kern":
         """New kernel from a parameter vector in gradient order."""
         theta = np.asarray(theta, dtype=np.float64)
+        if self.family == "linear":
+            return Kern("linear", self.lengthscale, float(theta[0]), float(theta[1]))
         extra = 3 if self.family == "periodic" else 2
         nl = len(theta) - extra
         ls = theta[:nl] if self.ard else float(theta[0])
@@ -70,10 +83,46 @@ class Kern:
         return Kern(self.family, ls, float(theta[nl]), float(theta[nl + 1]))
 
     def params(self, d: int) -> np.ndarray:
+        if self.family == "linear":
+            return np.array([self.outputscale, self.noise])
         ls = self.ls_vec(d) if self.ard else np.array([float(self.lengthscale)])
         if self.family == "periodic":
             return np.concatenate([ls, [self.period, self.outputscale, self.noise]])
         return np.concatenate([ls, [self.outputscale, self.noise]])
+
+
+class SumKern:
+    """k = sum_t k_t with one noise variance (the ``+`` of Sec. 3 "Kernels").
+
+    Each term is a Kern whose own noise is ignored.  Gradient order: the
+    terms' parameters without sigma^2, in term order, then sigma^2."""
+
+    family = "sum"
+
+    def __init__(self, terms, noise: float):
+        self.terms = list(terms)
+        self.noise = float(noise)
+
+    def n_params(self, d: int) -> int:
+        return sum(t.n_params(d) - 1 for t in self.terms) + 1
+
+    def params(self, d: int) -> np.ndarray:
+        return np.concatenate([t.params(d)[:-1] for t in self.terms] + [[self.noise]])
+
+    def with_params(self, theta) -> "SumKern":
+        theta = np.asarray(theta, dtype=np.float64)
+        out, off = [], 0
+        for t in self.terms:
+            m = len(t.params(_term_dim(t))) - 1
+            out.append(t.with_params(np.concatenate([theta[off:off + m], [0.0]])))
+            off += m
+        return SumKern(out, float(theta[off]))
+
+
+def _term_dim(t: Kern) -> int:
+    """Input dimension implied by a term's lengthscales (1 for shared / linear)."""
+    ls = np.asarray(t.lengthscale)
+    return ls.shape[0] if ls.ndim == 1 else 1
 
 
 # --------------------------------------------------------------------------
@@ -153,6 +202,10 @@ def kernel_matrix(kern: Kern, X1: np.ndarray, X2: np.ndarray) -> np.ndarray:
     & Williams eq. 4.31): k = s^2 exp(-sum_k 2 sin^2(pi (x_k - x'_k) / p) / l_k^2).
     """
     d = np.asarray(X1).shape[1]
+    if kern.family == "sum":
+        return sum(kernel_matrix(t, X1, X2) for t in kern.terms)
+    if kern.family == "linear":
+        return kern.outputscale * (np.asarray(X1, dtype=np.float64) @ np.asarray(X2, dtype=np.float64).T)
     if kern.family == "periodic":
         return kern.outputscale * np.exp(-periodic_sum(X1, X2, kern.ls_vec(d), kern.period))
     r2 = scaled_sqdist(X1, X2, kern.ls_vec(d))
@@ -243,6 +296,16 @@ def dky_matrices(kern: Kern, X: np.ndarray):
     """
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
+    if kern.family == "sum":
+        # d(sum_t k_t)/d theta_t = d k_t / d theta_t; sigma^2 once at the end
+        mats = []
+        for t in kern.terms:
+            mats += dky_matrices(t, X)[:-1]
+        mats.append(np.eye(n))
+        return mats
+    if kern.family == "linear":
+        # k = s^2 x.x': d/ds^2 = x.x'
+        return [X @ X.T, np.eye(n)]
     ls = kern.ls_vec(d)
     if kern.family == "periodic":
         # k = s^2 exp(-S), S = sum_k 2 sin^2(pi D_k / p) / l_k^2:
