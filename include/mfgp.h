@@ -31,6 +31,7 @@
  *                   MATERN32:    k = s2 (1 + sqrt3 rho) exp(-sqrt3 rho)
  *                   MATERN52:    k = s2 (1 + sqrt5 rho + 5 rho^2 / 3) exp(-sqrt5 rho)
  *                   PERIODIC:    k = s2 exp(-sum_k 2 sin^2(pi (x_k - x'_k) / p) / l_k^2)
+ *                   LINEAR:      k = s2 sum_k x_k x'_k
  *            with r^2 = sum_k ((x_k - x'_k) / l_k)^2, rho = sqrt(r^2), one
  *            lengthscale per dimension when `ard` is set and lengthscale[0]
  *            for all dimensions otherwise, and one period p (the families of
@@ -39,12 +40,23 @@
  *            lengthscales on the 2d features (cos 2 pi x_k / p, sin 2 pi x_k / p) / l_k,
  *            whose squared distance is sum_k 4 sin^2(pi (x_k - x'_k) / p) / l_k^2;
  *            every product form of RBF applies to it.
+ * Sums       (the `+` of Sec. 3 "Kernels"): a kernel whose `next` is non-NULL
+ *            is the sum of the chain's terms k = sum_t s2_t k_t(x, x'), at most
+ *            MFGP_MAX_TERMS of them, each with its own family, lengthscales,
+ *            period and s2 (the `Scale` of each term), all with the head's d;
+ *            sigma^2 is the head's noise (the other terms' noise is ignored).
+ *            Each term runs its own product form; the terms after the first
+ *            add into the result.  Not offered by the batched or preconditioned
+ *            calls.  LINEAR terms are rank-d products s2 X (X^T V) with FP64
+ *            sums.
  * Gradients  are with respect to the positive parameters in the order
  *            [l_1 .. l_d] (ard) or [l] (shared), then p (PERIODIC only), then
- *            s2, then sigma^2 (mfgp_num_params of them).
+ *            s2 (LINEAR: s2 only), then sigma^2; for a sum, every term's
+ *            parameters without sigma^2 in chain order, then sigma^2
+ *            (mfgp_num_params of them).
  * Feature dimension  the d argument of the workspace-size queries is the
  *            kernel's feature dimension mfgp_feature_dim(kern): the input
- *            dimension, twice it for PERIODIC.
+ *            dimension, twice it for PERIODIC, summed over a sum's terms.
  * Threads    The library is reentrant: no mutable globals besides the
  *            thread-local last HIP error and the preconditioned calls'
  *            thread-local rocBLAS handles.
@@ -62,13 +74,16 @@ extern "C" {
 #define MFGP_MAX_D 8
 #define MFGP_MAX_T 64
 #define MFGP_MAX_RANK 1024   /* largest pivoted-Cholesky preconditioner rank */
+#define MFGP_MAX_TERMS 4     /* terms of a kernel sum (mfgp_kernel.next chain) */
 
 typedef enum {
     MFGP_RBF = 0,
     MFGP_MATERN12 = 1,
     MFGP_MATERN32 = 2,
     MFGP_MATERN52 = 3,
-    MFGP_PERIODIC = 4     /* d <= MFGP_MAX_D / 2; not offered by the batched calls */
+    MFGP_PERIODIC = 4,    /* d <= MFGP_MAX_D / 2; not offered by the batched calls */
+    MFGP_LINEAR = 5       /* k = s2 x.x'; no lengthscale; not offered by the batched
+                             or preconditioned calls                               */
 } mfgp_family;
 
 /* Arithmetic of the product (kernel entries are always float32).  The
@@ -126,7 +141,7 @@ typedef enum {
 } mfgp_op;
 
 /* Kernel hyperparameters (host struct, passed by pointer). */
-typedef struct {
+typedef struct mfgp_kernel_s {
     int32_t family;                       /* mfgp_family                               */
     int32_t d;                            /* input dimension, 1..MFGP_MAX_D             */
     int32_t ard;                          /* nonzero: one lengthscale per dimension     */
@@ -134,6 +149,7 @@ typedef struct {
     float outputscale;                    /* s2 > 0                                     */
     float noise;                          /* sigma^2 >= 0 (> 0 for solves)              */
     float period;                         /* PERIODIC: p > 0, finite; ignored otherwise  */
+    const struct mfgp_kernel_s* next;     /* host: next term of a sum, or NULL          */
 } mfgp_kernel;
 
 /* Conjugate-gradient options (host struct). */
@@ -177,7 +193,8 @@ typedef struct {
 } mfgp_cg_info;
 
 /* Feature dimension of a kernel (the d of the workspace-size queries): kern->d,
- * 2 kern->d for MFGP_PERIODIC; 0 for a NULL kernel or kern->d < 1. */
+ * 2 kern->d for MFGP_PERIODIC, summed over the terms of a sum; 0 for a NULL
+ * kernel or kern->d < 1. */
 int mfgp_feature_dim(const mfgp_kernel* kern);
 
 /* Bytes of workspace a call needs.  op: mfgp_op; n rows; d = mfgp_feature_dim; t columns
@@ -299,8 +316,8 @@ typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
  * differing from kern[0].family, a non-finite or non-positive lengthscale,
  * outputscale or noise, a negative offset, or row_off that is not the prefix
  * sum of n (rows must be packed back to back in problem order);
- * MFGP_UNSUPPORTED for a column count without a compiled kernel or the
- * MFGP_PERIODIC family. */
+ * MFGP_UNSUPPORTED for a column count without a compiled kernel, the
+ * MFGP_PERIODIC or MFGP_LINEAR family, or a kernel sum (next != NULL). */
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
                            int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
 int mfgp_batch_plan_destroy(mfgp_batch_plan plan);
@@ -364,7 +381,9 @@ int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, co
  *   tr(K_y^{-1} dK) ~ (1/p) sum_c (K_y^{-1} z_c)^T dK (P^{-1} z_c).
  * L is a device array [rank][n] float32 (row q holds column q of the factor),
  * caller-owned; it is built by mfgp_pivoted_cholesky and read by the others.
- * Workspace sizes come from mfgp_precond_workspace_bytes.
+ * Workspace sizes come from mfgp_precond_workspace_bytes.  The kernel calls
+ * (pivoted Cholesky, PCG, PMLL) take one stationary or periodic term:
+ * MFGP_LINEAR and kernel sums return MFGP_UNSUPPORTED.
  * The Woodbury products run as rocBLAS FP64 GEMMs and triangular solves
  * (atomics off: reproducible).  The first call of mfgp_precond_apply,
  * _cg_solve or _mll_and_grad on a device from a host thread creates a rocBLAS
@@ -423,7 +442,9 @@ int mfgp_timing_read(int32_t kind, double* sweep_ms, int64_t* launches, double* 
                      double* flops);
 int mfgp_timing_phases(double* cg_ms, double* slq_ms, double* adjoint_ms);
 
-/* Number of gradient entries for a kernel: (ard ? d : 1) + 2, + 1 for MFGP_PERIODIC. */
+/* Number of gradient entries for a kernel: (ard ? d : 1) + 2, + 1 for
+ * MFGP_PERIODIC, 2 for MFGP_LINEAR; for a sum, the terms' counts less one
+ * each, plus one (sigma^2). */
 int mfgp_num_params(const mfgp_kernel* kern);
 
 const char* mfgp_status_string(int status);

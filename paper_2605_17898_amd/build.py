@@ -46,6 +46,7 @@ UNITS = [
     ("batch.hip", "batch.o", []),
     ("hybrid.hip", "hybrid.o", []),
     ("gram.hip", "gram.o", []),
+    ("sum.hip", "sum.o", []),
     ("precond.hip", "precond.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]

@@ -75,21 +75,43 @@ static inline unsigned nb(int64_t total) { return static_cast<unsigned>((total +
 
 static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
-static int check_kernel(const mfgp_kernel* k, bool need_noise) {
-    if (!k) return MFGP_ERR_ARG;
-    if (k->family < MFGP_RBF || k->family > MFGP_PERIODIC) return MFGP_ERR_ARG;
-    if (k->d < 1) return MFGP_ERR_ARG;
-    if (k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;
+// One term of a kernel (the head's d is every term's d).
+static int check_term(const mfgp_kernel* k, int d) {
+    if (k->family < MFGP_RBF || k->family > MFGP_LINEAR) return MFGP_ERR_ARG;
+    if (k->d != d) return MFGP_ERR_ARG;
     if (k->family == MFGP_PERIODIC) {
         if (!finite_pos(k->period)) return MFGP_ERR_ARG;
         if (2 * k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;   // 2 d circle features
     }
-    const int nl = k->ard ? k->d : 1;
-    for (int q = 0; q < nl; ++q)
-        if (!finite_pos(k->lengthscale[q])) return MFGP_ERR_ARG;
+    if (k->family != MFGP_LINEAR) {
+        const int nl = k->ard ? k->d : 1;
+        for (int q = 0; q < nl; ++q)
+            if (!finite_pos(k->lengthscale[q])) return MFGP_ERR_ARG;
+    }
     if (!finite_pos(k->outputscale)) return MFGP_ERR_ARG;
+    return MFGP_OK;
+}
+
+static int check_kernel(const mfgp_kernel* k, bool need_noise) {
+    if (!k) return MFGP_ERR_ARG;
+    if (k->d < 1) return MFGP_ERR_ARG;
+    if (k->d > MFGP_MAX_D) return MFGP_UNSUPPORTED;
+    int terms = 0;
+    for (const mfgp_kernel* q = k; q; q = q->next) {
+        if (++terms > MFGP_MAX_TERMS) return MFGP_UNSUPPORTED;
+        const int st = check_term(q, k->d);
+        if (st != MFGP_OK) return st;
+    }
     if (!std::isfinite(k->noise) || k->noise < 0.0f) return MFGP_ERR_ARG;
     if (need_noise && !(k->noise > 0.0f)) return MFGP_ERR_ARG;
+    return MFGP_OK;
+}
+
+// The preconditioned calls take one stationary or periodic term.
+static int check_precond_kernel(const mfgp_kernel* k, bool need_noise) {
+    const int st = check_kernel(k, need_noise);
+    if (st != MFGP_OK) return st;
+    if (k->next || k->family == MFGP_LINEAR) return MFGP_UNSUPPORTED;
     return MFGP_OK;
 }
 
@@ -132,7 +154,7 @@ static int hip_fail(hipError_t e) {
 
 // ---------------------------------------------------------------- carving (shared by size queries)
 
-struct MatvecWs { float* U; void* scratch; };
+struct MatvecWs { float* U; void* scratch; void* sum; };
 static MatvecWs carve_matvec(Carver& cv, int64_t n, int d, int t, int precision) {
     MatvecWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
@@ -140,14 +162,16 @@ static MatvecWs carve_matvec(Carver& cv, int64_t n, int d, int t, int precision)
         w.scratch = cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision));
     else
         w.scratch = cv.take<char>(mfma_scratch_bytes(n, n, t, precision));
+    w.sum = cv.take<char>(sum_scratch_bytes(n, t));
     return w;
 }
 
-struct ResidWs { float* U; double* scratch; double* dots; double* tmp; };
+struct ResidWs { float* U; double* scratch; double* dots; double* tmp; void* sum; };
 static ResidWs carve_resid(Carver& cv, int64_t n, int d, int t) {
     ResidWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
     w.scratch = cv.take<double>(resid_scratch_doubles(n, t));
+    w.sum = cv.take<char>(sum_scratch_bytes(n, t));
     w.dots = cv.take<double>(dots_scratch_doubles(n, t));
     w.tmp = cv.take<double>(2 * static_cast<size_t>(t));
     return w;
@@ -161,20 +185,22 @@ static CgWs carve_cgws(Carver& cv, int64_t n, int d, int t, int precision) {
     return w;
 }
 
-struct PredictWs { float* U; float* Us; void* scratch; };
+struct PredictWs { float* U; float* Us; void* scratch; void* sum; };
 static PredictWs carve_predict(Carver& cv, int64_t n, int d, int64_t m, int t) {
     PredictWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
     w.Us = cv.take<float>(static_cast<size_t>(m) * d);
     w.scratch = cv.take<char>(apply_fp32_scratch_bytes(m, n, t, MFGP_FP32));
+    w.sum = cv.take<char>(sum_scratch_bytes(m, t));
     return w;
 }
 
-struct AdjWs { float* U; double* scratch; double* dots; double* tmp; };
+struct AdjWs { float* U; double* scratch; double* dots; double* tmp; void* sum; };
 static AdjWs carve_adjoint(Carver& cv, int64_t n, int d, int t) {
     AdjWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
     w.scratch = cv.take<double>(adjoint_scratch_doubles(n, d, t));
+    w.sum = cv.take<char>(sum_scratch_bytes(n, t));
     w.dots = cv.take<double>(dots_scratch_doubles(n, t));
     w.tmp = cv.take<double>(2 * static_cast<size_t>(t) + 8);
     return w;
@@ -228,62 +254,15 @@ static PmllWs carve_pmll(Carver& cv, int64_t n, int d, int k, int t, int precisi
     return w;
 }
 
-// Lengthscale factor F_k of the adjoint sums (see adjoint.hip).
-static double lengthscale_factor(int family, double l) {
-    const double c = family_scale(family);
-    switch (family) {
-        case MFGP_RBF: return 1.0 / (c * c * l);
-        case MFGP_MATERN12: return 1.0 / (c * l);
-        case MFGP_MATERN32: return 3.0 / (c * c * l);
-        default: return (5.0 / 3.0) / (c * c * l);
-    }
-}
-
-// Index of d/d sigma^2 in the gradient: after the lengthscales, the period
-// (periodic family) and s2.
+// Index of d/d sigma^2 in the gradient: after every term's parameters.
 static int noise_index(const mfgp_kernel* k) {
-    return (k->ard ? k->d : 1) + (k->family == MFGP_PERIODIC ? 2 : 1);
+    int n = 0;
+    for (const mfgp_kernel* q = k; q; q = q->next) n += term_params(*q);
+    return n;
 }
 
 // Feature dimension of the prescaled coordinates (the d of the size queries).
-static int feature_dim(const mfgp_kernel* k) { return k->family == MFGP_PERIODIC ? 2 * k->d : k->d; }
-
-// grad[0..nl-1] lengthscales, grad[nl] s2 from the adjoint sums G_k, G_s;
-// periodic family: grad[0..nl-1] lengthscales, grad[nl] the period, grad[nl+1]
-// s2 from G_l, G_s, G_p (see adjoint_periodic_kernel): with c the RBF scale,
-//   dk/dl_k = s2 G_l[k] / (c^2 l_k),  dk/dp = s2 (2 pi / (p^2 c^2)) G_p.
-static void grad_from_sums(const Operator& op, int ard, const double* G, double* grad) {
-    if (op.periodic) {
-        const int din = op.din;
-        const double c = family_scale(MFGP_RBF);
-        double shared = 0.0;
-        for (int k = 0; k < din; ++k) {
-            const double gk = static_cast<double>(op.s2) * G[k] / (c * c * op.ls[2 * k]);
-            if (ard)
-                grad[k] = gk;
-            else
-                shared += gk;
-        }
-        const int nl = ard ? din : 1;
-        if (!ard) grad[0] = shared;
-        const double two_pi = 6.283185307179586477;
-        grad[nl] = static_cast<double>(op.s2) * two_pi / (op.period * op.period * c * c) * G[din + 1];
-        grad[nl + 1] = G[din];
-        return;
-    }
-    const int d = op.d;
-    double shared = 0.0;
-    for (int k = 0; k < d; ++k) {
-        const double gk = static_cast<double>(op.s2) * lengthscale_factor(op.family, op.ls[k]) * G[k];
-        if (ard)
-            grad[k] = gk;
-        else
-            shared += gk;
-    }
-    const int nl = ard ? d : 1;
-    if (!ard) grad[0] = shared;
-    grad[nl] = G[d];
-}
+static int feature_dim(const mfgp_kernel* k) { return chain_feature_dim(*k); }
 
 }  // namespace mfgp
 
@@ -320,7 +299,7 @@ int mfgp_feature_dim(const mfgp_kernel* k) {
 
 size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t precision,
                             int32_t max_iter) {
-    if (n < 1 || d < 1 || d > MFGP_MAX_D || t < 1) return 0;
+    if (n < 1 || d < 1 || d > MFGP_MAX_TERMS * MFGP_MAX_D || t < 1) return 0;
     if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return 0;
     Carver cv(nullptr);
     switch (op) {
@@ -355,12 +334,11 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     MatvecWs w = carve_matvec(cv, n, feature_dim(kern), t, precision);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
-    if (is_fp32_class(precision))
-        ABI_CHECK(apply_fp32(op, op.U, n, V, t, KV, true, V, w.scratch, precision, s));
-    else
-        ABI_CHECK(apply_mfma(op, op.U, n, V, t, KV, true, V, precision, w.scratch, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    ABI_CHECK(apply_sum(op, nullptr, n, V, t, KV, true, V, w.scratch, w.sum, precision, s));
     return MFGP_OK;
 }
 
@@ -375,9 +353,11 @@ int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     ResidWs w = carve_resid(cv, n, feature_dim(kern), t);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
-    ABI_CHECK(residual_f64(op, B, Xsol, t, R, w.scratch, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    ABI_CHECK(residual_sum(op, B, Xsol, t, R, w.scratch, w.sum, s));
     if (rel) {
         ABI_CHECK(col_dots_dd(R, R, n, t, w.tmp, w.dots, s));
         ABI_CHECK(col_dots_ff(B, B, n, t, w.tmp + t, w.dots, s));
@@ -402,8 +382,10 @@ int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     CgWs w = carve_cgws(cv, n, feature_dim(kern), t, opts->precision);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
     const int max_iter = default_max_iter(n, opts->max_iter);
     return cg_run(op, B, t, Xsol, *opts, info, lanczos, max_iter, w.b, s);
 }
@@ -420,15 +402,18 @@ int mfgp_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     PredictWs w = carve_predict(cv, n, feature_dim(kern), m, t);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
-    Operator ops = make_operator(*kern, Xs, m, w.Us);
-    ABI_CHECK(prescale(ops, s));
-    ABI_CHECK(apply_fp32(op, w.Us, m, A, t, MU, false, nullptr, w.scratch, MFGP_FP32, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    OpChain chs;
+    make_chain(chs, *kern, Xs, m, w.Us);
+    ABI_CHECK(prescale_chain(chs, s));
+    ABI_CHECK(apply_sum(op, &chs.head(), m, A, t, MU, false, nullptr, w.scratch, w.sum, MFGP_FP32, s));
     return MFGP_OK;
 }
 
-struct VarWs { float* U; float* Us; float* Z; float* W; double* X64; float* U32; float* Q; CgBufs b; void* scratch; };
+struct VarWs { float* U; float* Us; float* Z; float* W; double* X64; float* U32; float* Q; CgBufs b; void* scratch; void* sum; };
 static VarWs carve_variance(Carver& cv, int64_t n, int d, int64_t m, int p, int precision) {
     VarWs w;
     w.U = cv.take<float>(static_cast<size_t>(n) * d);
@@ -441,11 +426,12 @@ static VarWs carve_variance(Carver& cv, int64_t n, int d, int64_t m, int p, int 
     w.b = carve_cg(cv, n, p, precision);
     w.scratch = cv.take<char>(std::max(apply_fp32_scratch_bytes(n, m, p, MFGP_FP32),
                                        apply_fp32_scratch_bytes(m, n, p, MFGP_FP32)));
+    w.sum = cv.take<char>(sum_scratch_bytes(std::max(n, m), p));
     return w;
 }
 
 size_t mfgp_variance_workspace_bytes(int64_t n, int32_t d, int64_t m, int32_t p, int32_t precision) {
-    if (n < 1 || m < 1 || p < 1 || d < 1 || d > MFGP_MAX_D) return 0;
+    if (n < 1 || m < 1 || p < 1 || d < 1 || d > MFGP_MAX_TERMS * MFGP_MAX_D) return 0;
     if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return 0;
     Carver cv(nullptr);
     carve_variance(cv, n, d, m, p, precision);
@@ -465,24 +451,28 @@ int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, co
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     VarWs w = carve_variance(cv, n, feature_dim(kern), m, p, opts->precision);
-    Operator op = make_operator(*kern, X, n, w.U);
-    Operator ops = make_operator(*kern, Xs, m, w.Us);
-    ABI_CHECK(prescale(op, s));
-    ABI_CHECK(prescale(ops, s));
+    OpChain ch, chs;
+    make_chain(ch, *kern, X, n, w.U);
+    make_chain(chs, *kern, Xs, m, w.Us);
+    const Operator& op = ch.head();
+    const Operator& ops = chs.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    ABI_CHECK(prescale_chain(chs, s));
     const float* Zp = Z;
     if (!Zp) {
         ABI_CHECK(launch_rademacher(opts->probe_seed, m, p, w.Z, s));
         Zp = w.Z;
     }
     // W = K(X, Xs) Z (rows: training points, columns: test points)
-    ABI_CHECK(apply_fp32(ops, op.U, n, Zp, p, w.W, false, nullptr, w.scratch, MFGP_FP32, s));
+    ABI_CHECK(apply_sum(ops, &op, n, Zp, p, w.W, false, nullptr, w.scratch, w.sum, MFGP_FP32, s));
     const int max_iter = default_max_iter(n, opts->max_iter);
     const int cst = cg_run(op, w.W, p, w.X64, *opts, info, nullptr, max_iter, w.b, s);
     if (cst == MFGP_ERR_HIP) return cst;
     ABI_CHECK(f64_to_f32(w.X64, w.U32, n * p, s));
     // Q = K(Xs, X) K_y^{-1} W
-    ABI_CHECK(apply_fp32(op, ops.U, m, w.U32, p, w.Q, false, nullptr, w.scratch, MFGP_FP32, s));
-    ABI_CHECK(diag_variance(Zp, w.Q, m, p, static_cast<double>(kern->outputscale), var, s));
+    ABI_CHECK(apply_sum(op, &ops, m, w.U32, p, w.Q, false, nullptr, w.scratch, w.sum, MFGP_FP32, s));
+    ABI_CHECK(diag_variance(Zp, w.Q, m, p, stationary_prior(op), var, s));
+    ABI_CHECK(add_linear_prior(ops, m, var, s));
     ABI_CHECK(hipStreamSynchronize(s));
     return cst;
 }
@@ -509,15 +499,15 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     AdjWs w = carve_adjoint(cv, n, feature_dim(kern), t);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
-    double sums[MFGP_MAX_D + 1];
-    ABI_CHECK(adjoint_sums(op, A, B, t, colw, sums, w.scratch, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    ABI_CHECK(chain_gradient(op, A, B, t, colw, grad, w.scratch, w.sum, s));
     ABI_CHECK(col_dots_ff(A, B, n, t, w.tmp, w.dots, s));
     std::vector<double> ab(t);
     ABI_CHECK(hipMemcpyAsync(ab.data(), w.tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
     ABI_CHECK(hipStreamSynchronize(s));
-    grad_from_sums(op, kern->ard, sums, grad);
     double sn = 0.0;
     for (int c = 0; c < t; ++c) sn += colw[c] * ab[c];
     grad[noise_index(kern)] = sn;
@@ -541,8 +531,10 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     MllWs w = carve_mll(cv, n, feature_dim(kern), t, opts->precision, max_iter);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
     const float* Zp = Z;
     if (!Zp) {
         ABI_CHECK(launch_rademacher(opts->probe_seed, n, p, w.Zgen, s));
@@ -632,9 +624,7 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
         ABI_CHECK(hipGetLastError());
         std::vector<double> colw(t, -0.5 / p);
         colw[0] = 0.5;
-        double sums[MFGP_MAX_D + 1];
-        ABI_CHECK(adjoint_sums(op, Ag, Bg, t, colw.data(), sums, w.adj, s));
-        grad_from_sums(op, kern->ard, sums, grad);
+        ABI_CHECK(chain_gradient(op, Ag, Bg, t, colw.data(), grad, w.adj, w.b.sum, s));
         double tr = 0.0;
         for (int c = 1; c < t; ++c) tr += h[t + c];
         grad[noise_index(kern)] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
@@ -666,7 +656,7 @@ size_t mfgp_precond_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t,
 
 int mfgp_pivoted_cholesky(const mfgp_kernel* kern, const float* X, int64_t n, int32_t rank, float* L,
                           int32_t* piv, void* ws, size_t ws_bytes, void* stream) {
-    int st = check_kernel(kern, false);
+    int st = check_precond_kernel(kern, false);
     if (st != MFGP_OK) return st;
     if (!X || !L || !piv || !ws || n < 1 || rank < 1 || rank > n || rank > MFGP_MAX_RANK) return MFGP_ERR_ARG;
     if (ws_bytes < mfgp_precond_workspace_bytes(MFGP_OP_PCHOL, n, feature_dim(kern), 1, rank, MFGP_FP32, 0))
@@ -674,8 +664,10 @@ int mfgp_pivoted_cholesky(const mfgp_kernel* kern, const float* X, int64_t n, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     PcholWs w = carve_pchol(cv, n, feature_dim(kern));
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
     ABI_CHECK(pivoted_cholesky(op, rank, L, piv, w.scratch, s));
     return MFGP_OK;
 }
@@ -715,7 +707,7 @@ int mfgp_precond_apply(const float* L, int64_t n, int32_t rank, float noise, con
 int mfgp_precond_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const float* B, int32_t t,
                           double* Xsol, const float* L, int32_t rank, const mfgp_cg_opts* opts,
                           mfgp_cg_info* info, double* lanczos, void* ws, size_t ws_bytes, void* stream) {
-    int st = check_kernel(kern, true);
+    int st = check_precond_kernel(kern, true);
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
     if (!X || !B || !Xsol || !ws || n < 1 || t < 1 || rank < 0 || rank > n || rank > MFGP_MAX_RANK ||
@@ -727,8 +719,10 @@ int mfgp_precond_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, co
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
     PcgWs w = carve_pcgws(cv, n, feature_dim(kern), rank, t, opts->precision);
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
     Precond pc;
     pc.L = L;
     pc.k = rank;
@@ -745,7 +739,7 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
                               int32_t num_probes, const float* Z, const float* L, int32_t rank,
                               const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,
                               double* alpha_out, mfgp_cg_info* info, void* ws, size_t ws_bytes, void* stream) {
-    int st = check_kernel(kern, true);
+    int st = check_precond_kernel(kern, true);
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
     if (!X || !y || !Z || !mll || !ws || n < 1 || num_probes < 1 || rank < 0 || rank > n ||
@@ -761,8 +755,10 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
     Carver cv(ws);
     PmllWs W = carve_pmll(cv, n, feature_dim(kern), rank, t, opts->precision, max_iter);
     MllWs& w = W.m;
-    Operator op = make_operator(*kern, X, n, w.U);
-    ABI_CHECK(prescale(op, s));
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
     hipLaunchKernelGGL(pack_yz_kernel, dim3(nb(n * t)), dim3(256), 0, s, y, Z, n, p, w.Bm);
     ABI_CHECK(hipGetLastError());
     Precond pc;
@@ -856,9 +852,7 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
         ABI_CHECK(hipGetLastError());
         std::vector<double> colw(t, -0.5 / p);
         colw[0] = 0.5;
-        double sums[MFGP_MAX_D + 1];
-        ABI_CHECK(adjoint_sums(op, Ag, Bg, t, colw.data(), sums, w.adj, s));
-        grad_from_sums(op, kern->ard, sums, grad);
+        ABI_CHECK(chain_gradient(op, Ag, Bg, t, colw.data(), grad, w.adj, w.b.sum, s));
         // d/d sigma^2: dK_y = I, so 1/2 a^T a - 1/2 (1/p) sum_c u_c^T w_c (FP64 dots)
         double* uw = w.tmp;
         ABI_CHECK(col_dots_df(w.X64, Bg, n, t, uw, w.b.dots, s));

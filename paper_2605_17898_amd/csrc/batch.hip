@@ -956,7 +956,7 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
 #undef MFGP_T
     if (!tb_ok) return MFGP_UNSUPPORTED;
     const int fam = batch->kern[0].family;
-    if (fam == MFGP_PERIODIC) return MFGP_UNSUPPORTED;
+    if (fam == MFGP_PERIODIC || fam == MFGP_LINEAR) return MFGP_UNSUPPORTED;
     if (fam < MFGP_RBF || fam > MFGP_MATERN52) return MFGP_ERR_ARG;
     auto* P = new mfgp_batch_plan_s();
     P->nprob = batch->nprob;
@@ -969,6 +969,10 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
     for (int b = 0; b < batch->nprob; ++b) {
         const mfgp_kernel& k = batch->kern[b];
         const int64_t n = batch->n[b];
+        if (k.next) {
+            delete P;
+            return MFGP_UNSUPPORTED;   // kernel sums are not batched
+        }
         bool ok = n >= 1 && k.family == fam && k.d >= 1 && k.d <= MFGP_MAX_D && std::isfinite(k.outputscale) &&
                   k.outputscale > 0.0f && std::isfinite(k.noise) && k.noise > 0.0f &&
                   batch->row_off[b] >= 0 && batch->x_off[b] >= 0;

@@ -66,6 +66,7 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
         b.apply = reinterpret_cast<float*>(cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision)));
     else
         b.apply = reinterpret_cast<float*>(cv.take<char>(mfma_scratch_bytes(n, n, t, precision)));
+    b.sum = cv.take<char>(sum_scratch_bytes(n, t));
     return b;
 }
 
@@ -90,9 +91,8 @@ static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
 }
 
 static hipError_t apply_op(const Operator& op, const float* V, int t, float* out, int precision,
-                           float* scratch, hipStream_t s) {
-    if (is_fp32_class(precision)) return apply_fp32(op, op.U, op.n, V, t, out, true, V, scratch, precision, s);
-    return apply_mfma(op, op.U, op.n, V, t, out, true, V, precision, scratch, s);
+                           const CgBufs& b, hipStream_t s) {
+    return apply_sum(op, nullptr, op.n, V, t, out, true, V, b.apply, b.sum, precision, s);
 }
 
 #define CG_CHECK(expr)                         \
@@ -127,7 +127,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
 
     CG_CHECK(col_dots_ff(B, B, n, t, st.bnorm2, b.dots, s));
     if (o.warm_start) {
-        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(residual_sum(op, B, X, t, b.R64, b.resid, b.sum, s));
         CG_CHECK(f64_to_f32(b.R64, st.r, nt, s));
         CG_CHECK(copy2_f32(st.r, st.r, st.p, nt, s));
     } else {
@@ -165,7 +165,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             h_flag[c] = (can && h_rr[c] <= 0.44 * h_rep[c]) ? 1 : 0;
         }
         if (replace) {
-            CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+            CG_CHECK(residual_sum(op, B, X, t, b.R64, b.resid, b.sum, s));
             // drift d = r_true - r_rec: |d|^2 = |r_true|^2 + |r_rec|^2 - 2 r_true^T r_rec
             CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
             CG_CHECK(col_dots_df(b.R64, st.r, n, t, tmp + t, b.dots, s));
@@ -204,7 +204,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         }
         if (any) {
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b.apply, s));
+                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, s));
@@ -212,7 +212,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             continue;
         }
         // Every column stopped: recompute the true residual in FP64.
-        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(residual_sum(op, B, X, t, b.R64, b.resid, b.sum, s));
         CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
         CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -406,7 +406,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         }
         if (any) {
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b.apply, s));
+                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_rr(st, n, t, b.dots, rrn, s));
@@ -421,7 +421,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         }
         // Every column stopped: recompute the true residual in FP64 and refine.
         double* tmp = rzn;
-        CG_CHECK(residual_f64(op, B, X, t, b.R64, b.resid, s));
+        CG_CHECK(residual_sum(op, B, X, t, b.R64, b.resid, b.sum, s));
         CG_CHECK(col_dots_dd(b.R64, b.R64, n, t, tmp, b.dots, s));
         CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_status.data(), st.status, t * sizeof(int), hipMemcpyDeviceToHost, s));

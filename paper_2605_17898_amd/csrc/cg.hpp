@@ -16,6 +16,7 @@ struct CgBufs {
     double* dots = nullptr;
     double* resid = nullptr;
     float* apply = nullptr;
+    void* sum = nullptr;      // sum_scratch_bytes(n, t): the terms of a kernel sum
 };
 
 CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision);

@@ -166,6 +166,23 @@ hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, f
 
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
     Operator op;
+    op.ard = k.ard ? 1 : 0;
+    if (k.family == MFGP_LINEAR) {
+        // the raw inputs, copied into U by prescale
+        op.linear = 1;
+        op.family = MFGP_LINEAR;
+        op.d = op.din = k.d;
+        op.n = n;
+        op.s2 = k.outputscale;
+        op.sig2 = k.noise;
+        op.X = X;
+        op.U = U;
+        for (int q = 0; q < op.d; ++q) {
+            op.fac[q] = 1.0f;
+            op.ls[q] = 1.0;
+        }
+        return op;
+    }
     op.periodic = k.family == MFGP_PERIODIC;
     op.family = op.periodic ? MFGP_RBF : k.family;
     op.din = k.d;
@@ -201,6 +218,42 @@ __global__ void periodic_features_kernel(const float* __restrict__ X, int64_t n,
     sincospi(2.0 * ph, &sn, &cs);
     U[2 * idx] = static_cast<float>(static_cast<double>(fac.f[2 * k]) * cs);
     U[2 * idx + 1] = static_cast<float>(static_cast<double>(fac.f[2 * k + 1]) * sn);
+}
+
+int term_feature_dim(const mfgp_kernel& k) { return k.family == MFGP_PERIODIC ? 2 * k.d : k.d; }
+
+int chain_feature_dim(const mfgp_kernel& k) {
+    int f = 0;
+    for (const mfgp_kernel* t = &k; t; t = t->next) f += term_feature_dim(*t);
+    return f;
+}
+
+int term_params(const mfgp_kernel& k) {
+    if (k.family == MFGP_LINEAR) return 1;
+    return (k.ard ? k.d : 1) + (k.family == MFGP_PERIODIC ? 2 : 1);
+}
+
+void make_chain(OpChain& ch, const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    ch.count = 0;
+    int64_t off = 0;
+    for (const mfgp_kernel* t = &k; t && ch.count < MFGP_MAX_TERMS; t = t->next) {
+        Operator& op = ch.t[ch.count];
+        op = make_operator(*t, X, n, U ? U + off * n : nullptr);
+        if (ch.count > 0) {
+            op.sig2 = 0.0f;   // the head's noise is the sum's
+            ch.t[ch.count - 1].next = &op;
+        }
+        off += term_feature_dim(*t);
+        ++ch.count;
+    }
+}
+
+hipError_t prescale_chain(const OpChain& ch, hipStream_t s) {
+    for (int q = 0; q < ch.count; ++q) {
+        hipError_t e = prescale(ch.t[q], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t prescale(const Operator& op, hipStream_t s) {
@@ -288,6 +341,39 @@ size_t resid_scratch_doubles(int64_t n, int t) {
     const SweepPlan p = plan_sweep(n, n);
     const int tb = column_block64(t);
     return static_cast<size_t>(p.chunks) * n * tb + 64;
+}
+
+// R[i, c0 + c] -= s2 * sum_s partial[s][i][c]   (FP64; a later term of a sum)
+__global__ void reduce_resid_sub_kernel(const double* __restrict__ partial, int chunks, int64_t m, int tb,
+                                        double s2, int ld, int c0, double* __restrict__ R) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= m * tb) return;
+    const int64_t i = idx / tb;
+    const int c = static_cast<int>(idx % tb);
+    double acc = 0.0;
+    for (int s = 0; s < chunks; ++s) acc += partial[s * m * tb + idx];
+    R[i * ld + c0 + c] -= s2 * acc;
+}
+
+hipError_t residual_f64_sub(const Operator& op, const double* X64, int t, double* R, double* scratch,
+                            hipStream_t s) {
+    const SweepPlan plan = plan_sweep(op.n, op.n);
+    for (int c0 = 0; c0 < t;) {
+        const int tb = column_block64(t - c0);
+        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan};
+        void* tok = timing_begin(s);
+        hipError_t e = launch_sweep_f64acc(op.family, op.d, tb, a, s);
+        const double ent = static_cast<double>(op.n) * static_cast<double>(op.n);
+        timing_end(tok, s, kSweepF64, ent, ent * sweep_flops_per_entry(op.family, op.d, tb, false));
+        if (e != hipSuccess) return e;
+        const int64_t total = op.n * tb;
+        hipLaunchKernelGGL(reduce_resid_sub_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                           0, s, scratch, plan.chunks, op.n, tb, static_cast<double>(op.s2), t, c0, R);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        c0 += tb;
+    }
+    return hipSuccess;
 }
 
 hipError_t residual_f64(const Operator& op, const float* B, const double* X64, int t, double* R,

@@ -10,12 +10,17 @@ namespace mfgp {
 // The periodic family is held as RBF on its d = 2 din circle features
 // u = c (cos 2 pi x / p, sin 2 pi x / p) / l (periodic = 1, din the input
 // dimension, period p); for the other families din = d.
+// A linear term (linear = 1) keeps the raw inputs in U (d = din, factors 1).
+// Terms of a kernel sum are linked through next (see OpChain).
 struct Operator {
     int family = 0;
     int d = 0;
     int din = 0;
     int periodic = 0;
+    int linear = 0;
+    int ard = 0;
     double period = 0.0;
+    const Operator* next = nullptr;
     int64_t n = 0;
     float s2 = 1.0f;
     float sig2 = 0.0f;
@@ -27,6 +32,47 @@ struct Operator {
 
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U);
 hipError_t prescale(const Operator& op, hipStream_t s);
+
+// The terms of a kernel (one, or a sum chained by mfgp_kernel.next) bound to
+// the same points: term q reads U + n * (feature dims of the terms before it).
+// Not copyable: the terms point at each other.
+struct OpChain {
+    Operator t[MFGP_MAX_TERMS];
+    int count = 0;
+    OpChain() = default;
+    OpChain(const OpChain&) = delete;
+    OpChain& operator=(const OpChain&) = delete;
+    const Operator& head() const { return t[0]; }
+};
+// Feature dimension of one term (2 d periodic, d otherwise) and of the chain.
+int term_feature_dim(const mfgp_kernel& k);
+int chain_feature_dim(const mfgp_kernel& k);
+void make_chain(OpChain& ch, const mfgp_kernel& k, const float* X, int64_t n, float* U);
+hipError_t prescale_chain(const OpChain& ch, hipStream_t s);
+// Gradient entries of one term without sigma^2.
+int term_params(const mfgp_kernel& k);
+
+// Products and residuals of a (possibly multi-term) operator.  scratch is
+// the single-term scratch of the precision (apply_fp32_scratch_bytes or
+// mfma_scratch_bytes; resid_scratch_doubles for the residual) and sum_scratch
+// sum_scratch_bytes(max(m, n), t) more: the FP32 buffer of the terms after
+// the first and the FP64 partials of the linear terms.  rows = NULL for the
+// square product (rows are the columns' points).
+size_t sum_scratch_bytes(int64_t m, int t);
+hipError_t apply_sum(const Operator& cols, const Operator* rows, int64_t m, const float* V, int t,
+                     float* out, bool with_noise, const float* Vself, void* scratch, void* sum_scratch,
+                     int precision, hipStream_t s);
+hipError_t residual_sum(const Operator& op, const float* B, const double* X64, int t, double* R,
+                        double* scratch, void* sum_scratch, hipStream_t s);
+// Gradient of every term's parameters, sum_c w_c A_c^T (dK/dtheta) B_c, into
+// grad[0 ..) in chain order (sigma^2 excluded).
+hipError_t chain_gradient(const Operator& op, const float* A, const float* B, int t, const double* colw_host,
+                          double* grad, double* adj_scratch, void* sum_scratch, hipStream_t s);
+// var[q] += s2_t |x_q|^2 for every linear term (the prior variance of a
+// linear term at the test points U of the rows operator).
+hipError_t add_linear_prior(const Operator& rows, int64_t m, float* var, hipStream_t s);
+// Sum of the outputscales of the stationary terms (their prior variance).
+double stationary_prior(const Operator& op);
 
 int column_block64(int t);
 hipError_t launch_pack_cols(const float* src, int lds, int c0, int tb, int64_t n, float* dst,
@@ -44,6 +90,9 @@ size_t resid_scratch_doubles(int64_t n, int t);
 // R = B - K_y X64 with FP32 entries and FP64 accumulation.
 hipError_t residual_f64(const Operator& op, const float* B, const double* X64, int t, double* R,
                         double* scratch, hipStream_t s);
+// R -= s2 k(U, U) X64 (a later term of a sum; no noise), same arithmetic.
+hipError_t residual_f64_sub(const Operator& op, const double* X64, int t, double* R, double* scratch,
+                            hipStream_t s);
 
 // FP32 sweep with the contraction on FP32 MFMA (t = 16 NT + TV, NT 1..4, TV 0..1).
 bool hybrid_supported(int t);

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfgp.so")
 
 MAX_D = 8
-FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3, "periodic": 4}
+FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3, "periodic": 4, "linear": 5}
+MAX_TERMS = 4
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4, "fp32_direct": 5,
               "fp32_gram": 6}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
@@ -29,9 +30,12 @@ OP_PCHOL, OP_PAPPLY, OP_PCG, OP_PMLL = range(6, 10)
 
 
 class KernelT(C.Structure):
-    _fields_ = [("family", C.c_int32), ("d", C.c_int32), ("ard", C.c_int32),
-                ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float),
-                ("period", C.c_float)]
+    pass
+
+
+KernelT._fields_ = [("family", C.c_int32), ("d", C.c_int32), ("ard", C.c_int32),
+                    ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float),
+                    ("period", C.c_float), ("next", C.POINTER(KernelT))]
 
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_double)
@@ -158,6 +162,44 @@ class Kernel:
 
     def feature_dim(self, d: int) -> int:
         """The d of the workspace-size queries (2 d for the periodic family)."""
+        return LIB.mfgp_feature_dim(C.byref(self.struct(d)))
+
+    def __add__(self, other) -> "KernelSum":
+        return KernelSum(self.terms() + other.terms())
+
+    def terms(self) -> list:
+        return [self]
+
+
+class KernelSum:
+    """Sum of kernels (each with its own parameters and outputscale); the noise
+    is the first term's.  Passed to the library as a chain of KernelT."""
+
+    def __init__(self, terms):
+        self._terms = list(terms)
+
+    def terms(self) -> list:
+        return list(self._terms)
+
+    def __add__(self, other) -> "KernelSum":
+        return KernelSum(self.terms() + other.terms())
+
+    @property
+    def noise(self) -> float:
+        return self._terms[0].noise
+
+    def struct(self, d: int) -> KernelT:
+        arr = (KernelT * len(self._terms))(*[k.struct(d) for k in self._terms])
+        for q in range(len(self._terms) - 1):
+            arr[q].next = C.pointer(arr[q + 1])
+        head = arr[0]
+        head._chain_ref = arr   # the chain lives as long as the head
+        return head
+
+    def n_params(self, d: int) -> int:
+        return LIB.mfgp_num_params(C.byref(self.struct(d)))
+
+    def feature_dim(self, d: int) -> int:
         return LIB.mfgp_feature_dim(C.byref(self.struct(d)))
 
 

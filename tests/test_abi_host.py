@@ -72,13 +72,42 @@ def test_periodic_kernel_checks_before_launch(m, period, d, want):
     assert st == want
 
 
+def test_sum_and_linear_params_and_checks(m):
+    rbf, per, lin = m.Kernel("rbf", [0.4, 0.9], 1.1, 0.04), m.Kernel("periodic", 0.7, 0.6, period=0.45), \
+        m.Kernel("linear", 1.0, 0.3)
+    assert lin.n_params(2) == 2 and lin.feature_dim(2) == 2
+    ksum = rbf + per + lin
+    assert ksum.n_params(2) == 8          # [l1, l2, s2 | l, p, s2 | s2 | sigma^2]
+    assert ksum.feature_dim(2) == 8
+    dummy = C.c_void_p(16)
+    L = m.LIB
+
+    def matvec(k, d=2, ws=16):
+        return L.mfgp_kernel_matvec(C.byref(k), dummy, 10, dummy, 1, C.c_void_p(32), 0, dummy, ws, None)
+
+    assert matvec(ksum.struct(2)) == m.ERR_WORKSPACE     # valid chain: stops at the size check
+    five = rbf + rbf + rbf + rbf + rbf
+    assert matvec(five.struct(2)) == m.UNSUPPORTED        # more than MFGP_MAX_TERMS
+    bad = ksum.struct(2)
+    bad._chain_ref[1].d = 3                                # terms must share d
+    assert matvec(bad) == m.ERR_ARG
+    neg = (rbf + m.Kernel("linear", 1.0, -0.3)).struct(2)
+    assert matvec(neg) == m.ERR_ARG
+    # the preconditioned calls take one stationary or periodic term
+    for k in (ksum.struct(2), lin.struct(2)):
+        assert L.mfgp_pivoted_cholesky(C.byref(k), dummy, 10, 2, dummy, dummy, dummy, 1 << 20, None) == m.UNSUPPORTED
+    # feature dimensions above MFGP_MAX_D are valid for sums in the size queries
+    assert m.workspace_bytes(m.OP_CG, 1000, 12, 3) > 0
+    assert m.workspace_bytes(m.OP_CG, 1000, 33, 3) == 0
+
+
 def test_workspace_sizes(m):
     for op in range(6):
         t = 2 if op != m.OP_PREDICT else 3
         mi = 100 if op == m.OP_PREDICT else 0
         assert m.workspace_bytes(op, 1000, 3, t, 0, mi) > 0
     assert m.workspace_bytes(m.OP_MATVEC, 0, 3, 1) == 0
-    assert m.workspace_bytes(m.OP_MATVEC, 10, 9, 1) == 0      # d > MFGP_MAX_D
+    assert m.workspace_bytes(m.OP_MATVEC, 10, 33, 1) == 0     # d > MFGP_MAX_TERMS * MFGP_MAX_D
     assert m.workspace_bytes(m.OP_MATVEC, 10, 2, 0) == 0
     assert m.workspace_bytes(m.OP_MLL, 10, 2, 1) == 0         # needs >= 1 probe
     # O(n) workspace: 10x the points -> about 10x the bytes

@@ -51,6 +51,10 @@ def test_batch_plan_validation(m):
     assert st == m.ERR_ARG
     kp = m.Kernel("periodic", 0.3, 1.0, 0.01, period=0.5)
     assert _create(m, [100, 50], [2, 3], [kp, kp]) == m.UNSUPPORTED                 # not batched
+    kl = m.Kernel("linear", 1.0, 1.0, 0.01)
+    assert _create(m, [100, 50], [2, 3], [kl, kl]) == m.UNSUPPORTED
+    ks = k + k
+    assert _create(m, [100, 50], [2, 3], [ks, ks]) == m.UNSUPPORTED
 
 
 def test_bench_refuses_more_than_one_gpu():
