@@ -30,6 +30,11 @@ Sums (Sec. 3: the ``+`` composition of ``Scale``d kernels): SumKern holds
 terms k_t, each with its own parameters and s_t^2, and one noise variance;
 k = sum_t k_t, and its gradient order is each term's parameters without
 sigma^2, in term order, then sigma^2.
+
+Products (Sec. 3: ``*``): ProdKern holds factors k_f with unit outputscale
+and one s^2 for the product, k = s^2 prod_f k_f; its gradient order is each
+factor's parameters without s^2 and sigma^2, in factor order, then s^2, then
+sigma^2.
 """
 
 from __future__ import annotations
@@ -119,8 +124,41 @@ class SumKern:
         return SumKern(out, float(theta[off]))
 
 
-def _term_dim(t: Kern) -> int:
+class ProdKern:
+    """k = s^2 prod_f k_f (the ``*`` of Sec. 3 "Kernels"), factors at unit scale.
+
+    A factor's own outputscale and noise are ignored.  Gradient order: every
+    factor's parameters without s^2 and sigma^2, in factor order, then s^2,
+    then sigma^2."""
+
+    family = "prod"
+
+    def __init__(self, factors, outputscale: float, noise: float):
+        self.factors = [f.with_params(np.concatenate([f.params(_term_dim(f))[:-2], [1.0, 0.0]]))
+                        for f in factors]
+        self.outputscale = float(outputscale)
+        self.noise = float(noise)
+
+    def n_params(self, d: int) -> int:
+        return sum(f.n_params(d) - 2 for f in self.factors) + 2
+
+    def params(self, d: int) -> np.ndarray:
+        return np.concatenate([f.params(d)[:-2] for f in self.factors] + [[self.outputscale, self.noise]])
+
+    def with_params(self, theta) -> "ProdKern":
+        theta = np.asarray(theta, dtype=np.float64)
+        out, off = [], 0
+        for f in self.factors:
+            m = len(f.params(_term_dim(f))) - 2
+            out.append(f.with_params(np.concatenate([theta[off:off + m], [1.0, 0.0]])))
+            off += m
+        return ProdKern(out, float(theta[off]), float(theta[off + 1]))
+
+
+def _term_dim(t) -> int:
     """Input dimension implied by a term's lengthscales (1 for shared / linear)."""
+    if hasattr(t, "factors"):
+        return max(_term_dim(f) for f in t.factors)
     ls = np.asarray(t.lengthscale)
     return ls.shape[0] if ls.ndim == 1 else 1
 
@@ -204,6 +242,11 @@ def kernel_matrix(kern: Kern, X1: np.ndarray, X2: np.ndarray) -> np.ndarray:
     d = np.asarray(X1).shape[1]
     if kern.family == "sum":
         return sum(kernel_matrix(t, X1, X2) for t in kern.terms)
+    if kern.family == "prod":
+        K = kern.outputscale * np.ones((np.asarray(X1).shape[0], np.asarray(X2).shape[0]))
+        for f in kern.factors:
+            K = K * kernel_matrix(f, X1, X2)
+        return K
     if kern.family == "linear":
         return kern.outputscale * (np.asarray(X1, dtype=np.float64) @ np.asarray(X2, dtype=np.float64).T)
     if kern.family == "periodic":
@@ -301,6 +344,22 @@ def dky_matrices(kern: Kern, X: np.ndarray):
         mats = []
         for t in kern.terms:
             mats += dky_matrices(t, X)[:-1]
+        mats.append(np.eye(n))
+        return mats
+    if kern.family == "prod":
+        # d(s^2 prod_f k_f)/d theta_f = s^2 (d k_f / d theta_f) prod_{g != f} k_g
+        Ks = [kernel_matrix(f, X, X) for f in kern.factors]
+        mats = []
+        for i, f in enumerate(kern.factors):
+            others = np.ones((n, n))
+            for j, Kg in enumerate(Ks):
+                if j != i:
+                    others = others * Kg
+            mats += [kern.outputscale * dK * others for dK in dky_matrices(f, X)[:-2]]
+        prod = np.ones((n, n))
+        for Kg in Ks:
+            prod = prod * Kg
+        mats.append(prod)
         mats.append(np.eye(n))
         return mats
     if kern.family == "linear":
