@@ -49,11 +49,22 @@
  *            add into the result.  Not offered by the batched or preconditioned
  *            calls.  LINEAR terms are rank-d products s2 X (X^T V) with FP64
  *            sums.
+ * Products   (the `*` of Sec. 3): a term whose `times` is non-NULL is the
+ *            product s2 prod_f k_f of the factor chain (that struct, then its
+ *            `times` chain), s2 being the first factor's outputscale (the
+ *            other factors' outputscale, noise and `next` are ignored).
+ *            Factors are RBF or PERIODIC (at most one PERIODIC), at most
+ *            MFGP_MAX_TERMS of them, each with the head's d and with at most
+ *            MFGP_MAX_D features in all (d per RBF factor, 2d for the
+ *            periodic one): such a product is RBF with unit lengthscales on
+ *            the concatenated features and runs every RBF product form.
+ *            Other factor families return MFGP_UNSUPPORTED.
  * Gradients  are with respect to the positive parameters in the order
  *            [l_1 .. l_d] (ard) or [l] (shared), then p (PERIODIC only), then
- *            s2 (LINEAR: s2 only), then sigma^2; for a sum, every term's
- *            parameters without sigma^2 in chain order, then sigma^2
- *            (mfgp_num_params of them).
+ *            s2 (LINEAR: s2 only), then sigma^2; for a product term, every
+ *            factor's lengthscales (and p) in factor order, then s2; for a
+ *            sum, every term's parameters without sigma^2 in chain order,
+ *            then sigma^2 (mfgp_num_params of them).
  * Feature dimension  the d argument of the workspace-size queries is the
  *            kernel's feature dimension mfgp_feature_dim(kern): the input
  *            dimension, twice it for PERIODIC, summed over a sum's terms.
@@ -150,6 +161,7 @@ typedef struct mfgp_kernel_s {
     float noise;                          /* sigma^2 >= 0 (> 0 for solves)              */
     float period;                         /* PERIODIC: p > 0, finite; ignored otherwise  */
     const struct mfgp_kernel_s* next;     /* host: next term of a sum, or NULL          */
+    const struct mfgp_kernel_s* times;    /* host: next factor of a product, or NULL    */
 } mfgp_kernel;
 
 /* Conjugate-gradient options (host struct). */
@@ -317,7 +329,8 @@ typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
  * outputscale or noise, a negative offset, or row_off that is not the prefix
  * sum of n (rows must be packed back to back in problem order);
  * MFGP_UNSUPPORTED for a column count without a compiled kernel, the
- * MFGP_PERIODIC or MFGP_LINEAR family, or a kernel sum (next != NULL). */
+ * MFGP_PERIODIC or MFGP_LINEAR family, or a kernel sum or product (next or
+ * times != NULL). */
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
                            int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
 int mfgp_batch_plan_destroy(mfgp_batch_plan plan);
@@ -382,8 +395,8 @@ int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, co
  * L is a device array [rank][n] float32 (row q holds column q of the factor),
  * caller-owned; it is built by mfgp_pivoted_cholesky and read by the others.
  * Workspace sizes come from mfgp_precond_workspace_bytes.  The kernel calls
- * (pivoted Cholesky, PCG, PMLL) take one stationary or periodic term:
- * MFGP_LINEAR and kernel sums return MFGP_UNSUPPORTED.
+ * (pivoted Cholesky, PCG, PMLL) take one stationary, periodic or product
+ * term: MFGP_LINEAR and kernel sums return MFGP_UNSUPPORTED.
  * The Woodbury products run as rocBLAS FP64 GEMMs and triangular solves
  * (atomics off: reproducible).  The first call of mfgp_precond_apply,
  * _cg_solve or _mll_and_grad on a device from a host thread creates a rocBLAS
@@ -443,8 +456,9 @@ int mfgp_timing_read(int32_t kind, double* sweep_ms, int64_t* launches, double* 
 int mfgp_timing_phases(double* cg_ms, double* slq_ms, double* adjoint_ms);
 
 /* Number of gradient entries for a kernel: (ard ? d : 1) + 2, + 1 for
- * MFGP_PERIODIC, 2 for MFGP_LINEAR; for a sum, the terms' counts less one
- * each, plus one (sigma^2). */
+ * MFGP_PERIODIC, 2 for MFGP_LINEAR; a product term counts its factors'
+ * lengthscales and period, s2 and sigma^2; for a sum, the terms' counts less
+ * one each, plus one (sigma^2). */
 int mfgp_num_params(const mfgp_kernel* kern);
 
 const char* mfgp_status_string(int status);

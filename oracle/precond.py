@@ -45,7 +45,10 @@ def pivoted_cholesky(kern: gp.Kern, X: np.ndarray, k: int):
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     k = min(k, n)
-    noise_free = gp.Kern(kern.family, kern.lengthscale, kern.outputscale, 0.0, period=kern.period)
+    if kern.family == "prod":
+        noise_free = gp.ProdKern(kern.factors, kern.outputscale, 0.0)
+    else:
+        noise_free = gp.Kern(kern.family, kern.lengthscale, kern.outputscale, 0.0, period=kern.period)
     d = np.full(n, float(kern.outputscale))
     L = np.zeros((n, k))
     piv = []

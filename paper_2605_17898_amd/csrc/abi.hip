@@ -75,8 +75,36 @@ static inline unsigned nb(int64_t total) { return static_cast<unsigned>((total +
 
 static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
+// A product term: RBF factors and at most one periodic factor within
+// MFGP_MAX_D features (other families are valid but not provided).
+static int check_product(const mfgp_kernel* k, int d) {
+    int nf = 0, nper = 0, feats = 0;
+    for (const mfgp_kernel* q = k; q; q = q->times) {
+        if (++nf > MFGP_MAX_TERMS) return MFGP_UNSUPPORTED;
+        if (q->family < MFGP_RBF || q->family > MFGP_LINEAR) return MFGP_ERR_ARG;
+        if (q->d != d) return MFGP_ERR_ARG;
+        if (q->family == MFGP_PERIODIC) {
+            if (!finite_pos(q->period)) return MFGP_ERR_ARG;
+            ++nper;
+            feats += 2 * d;
+        } else {
+            feats += d;
+        }
+        if (q->family == MFGP_LINEAR) continue;
+        const int nl = q->ard ? d : 1;
+        for (int j = 0; j < nl; ++j)
+            if (!finite_pos(q->lengthscale[j])) return MFGP_ERR_ARG;
+    }
+    for (const mfgp_kernel* q = k; q; q = q->times)
+        if (q->family != MFGP_RBF && q->family != MFGP_PERIODIC) return MFGP_UNSUPPORTED;
+    if (nper > 1 || feats > MFGP_MAX_D) return MFGP_UNSUPPORTED;
+    if (!finite_pos(k->outputscale)) return MFGP_ERR_ARG;
+    return MFGP_OK;
+}
+
 // One term of a kernel (the head's d is every term's d).
 static int check_term(const mfgp_kernel* k, int d) {
+    if (k->times) return check_product(k, d);
     if (k->family < MFGP_RBF || k->family > MFGP_LINEAR) return MFGP_ERR_ARG;
     if (k->d != d) return MFGP_ERR_ARG;
     if (k->family == MFGP_PERIODIC) {

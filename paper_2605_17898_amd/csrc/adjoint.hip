@@ -86,12 +86,16 @@ static hipError_t adjoint_fd(int tb, const float* U, const float* A, int lda, in
 // The last bracket is (c / l_k)^2 sin(th_ik - th_jk), so that
 //   dk/dp = s2 k^ sum_k (2 pi (x_ik - x_jk) / (p^2 l_k^2)) sin(2 pi (x_ik - x_jk) / p)
 // is s2 (2 pi / (p^2 c^2)) times the G_p term; the host applies the factors.
-template <int DIN, int TB>
+// A product term with RBF factors carries DEX more features after the 2 DIN
+// periodic ones (entries 2^(-|du|^2) over all of them); their per-feature
+// sums G_x[q] += W_ij k^ du_q^2 follow G_l.  Output: [G_l (DIN), G_x (DEX),
+// G_s, G_p].
+template <int DIN, int DEX, int TB>
 __global__ __launch_bounds__(kBlock) void adjoint_periodic_kernel(
     const float* __restrict__ X, const float* __restrict__ U, const float* __restrict__ A, int lda, int c0,
     ColW w, const float* __restrict__ B, int64_t n, int chunks, int64_t jchunk, double* __restrict__ partial) {
-    constexpr int D = 2 * DIN;
-    constexpr int W = DIN + 2;
+    constexpr int D = 2 * DIN + DEX;
+    constexpr int W = DIN + DEX + 2;
     __shared__ double red[W * (kBlock / 64)];
     int rb, ch;
     map_block(blockIdx.x, chunks, rb, ch);
@@ -145,8 +149,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_periodic_kernel(
             const float cr = fmaf(ui[2 * k + 1], uj[2 * k], -ui[2 * k] * uj[2 * k + 1]);
             h = fmaf(xi[k] - xc[q * DIN + k], cr, h);
         }
-        g[DIN] += wk;
-        g[DIN + 1] = fmaf(wk, h, g[DIN + 1]);
+#pragma unroll
+        for (int e = 0; e < DEX; ++e) g[DIN + e] = fmaf(wk * df[2 * DIN + e], df[2 * DIN + e], g[DIN + e]);
+        g[DIN + DEX] += wk;
+        g[DIN + DEX + 1] = fmaf(wk, h, g[DIN + DEX + 1]);
     }
     double v[W];
 #pragma unroll
@@ -154,16 +160,16 @@ __global__ __launch_bounds__(kBlock) void adjoint_periodic_kernel(
     block_sum_write<W>(v, red, partial + static_cast<int64_t>(blockIdx.x) * W);
 }
 
-template <int DIN>
+template <int DIN, int DEX>
 static hipError_t adjoint_periodic_d(int tb, const float* X, const float* U, const float* A, int lda, int c0,
                                      const ColW& w, const float* B, int64_t n, const SweepPlan& p,
                                      double* partial, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
     switch (tb) {
-#define MFGP_CASE(TBV)                                                                                    \
-    case TBV:                                                                                             \
-        hipLaunchKernelGGL((adjoint_periodic_kernel<DIN, TBV>), grid, dim3(kBlock), 0, s, X, U, A, lda, c0, \
-                           w, B, n, p.chunks, p.jchunk, partial);                                        \
+#define MFGP_CASE(TBV)                                                                                         \
+    case TBV:                                                                                                  \
+        hipLaunchKernelGGL((adjoint_periodic_kernel<DIN, DEX, TBV>), grid, dim3(kBlock), 0, s, X, U, A, lda, c0, \
+                           w, B, n, p.chunks, p.jchunk, partial);                                             \
         return hipGetLastError();
         MFGP_TB_LIST(MFGP_CASE)
 #undef MFGP_CASE
@@ -172,16 +178,24 @@ static hipError_t adjoint_periodic_d(int tb, const float* X, const float* U, con
     }
 }
 
-static hipError_t adjoint_periodic(int din, int tb, const float* X, const float* U, const float* A, int lda,
-                                   int c0, const ColW& w, const float* B, int64_t n, const SweepPlan& p,
+// (DIN, DEX): the periodic term alone (DEX = 0) and the products with up to
+// three RBF factors of DIN features each within MFGP_MAX_D features.
+static hipError_t adjoint_periodic(int din, int dex, int tb, const float* X, const float* U, const float* A,
+                                   int lda, int c0, const ColW& w, const float* B, int64_t n, const SweepPlan& p,
                                    double* partial, hipStream_t s) {
-    switch (din) {
-        case 1: return adjoint_periodic_d<1>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
-        case 2: return adjoint_periodic_d<2>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
-        case 3: return adjoint_periodic_d<3>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
-        case 4: return adjoint_periodic_d<4>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
-        default: return hipErrorInvalidValue;
-    }
+#define MFGP_PD(DI, DE) \
+    if (din == DI && dex == DE) return adjoint_periodic_d<DI, DE>(tb, X, U, A, lda, c0, w, B, n, p, partial, s);
+    MFGP_PD(1, 0)
+    MFGP_PD(1, 1)
+    MFGP_PD(1, 2)
+    MFGP_PD(1, 3)
+    MFGP_PD(2, 0)
+    MFGP_PD(2, 2)
+    MFGP_PD(2, 4)
+    MFGP_PD(3, 0)
+    MFGP_PD(4, 0)
+#undef MFGP_PD
+    return hipErrorInvalidValue;
 }
 
 template <int FAM>
@@ -210,13 +224,13 @@ size_t adjoint_scratch_doubles(int64_t n, int d, int t) {
 }
 
 // sums_host[0..d-1] = G_k, sums_host[d] = G_s (see the file comment); for the
-// periodic family sums_host[0..din-1] = G_l, [din] = G_s, [din+1] = G_p (see
-// adjoint_periodic_kernel).
+// periodic family (alone or in a product) sums_host[0..din-1] = G_l, then the
+// dextra G_x, then G_s, G_p (see adjoint_periodic_kernel).
 hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int t,
                         const double* colw_host, double* sums_host, double* scratch,
                         hipStream_t s) {
     const int d = op.d;
-    const int width = op.periodic ? op.din + 2 : d + 1;
+    const int width = op.periodic ? op.din + op.dextra + 2 : d + 1;
     const int64_t n = op.n;
     const SweepPlan p = plan_sweep(n, n);
     const int nblocks = p.rowblocks * p.chunks;
@@ -237,7 +251,7 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
         hipError_t e;
         void* tok = timing_begin(s);
         if (op.periodic) {
-            e = adjoint_periodic(op.din, tb, op.X, op.U, A, t, c0, w, bb, n, p, partial, s);
+            e = adjoint_periodic(op.din, op.dextra, tb, op.X, op.U, A, t, c0, w, bb, n, p, partial, s);
         } else switch (op.family) {
             case MFGP_RBF: e = adjoint_f<MFGP_RBF>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;
             case MFGP_MATERN12: e = adjoint_f<MFGP_MATERN12>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;

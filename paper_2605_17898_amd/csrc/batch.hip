@@ -969,9 +969,9 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
     for (int b = 0; b < batch->nprob; ++b) {
         const mfgp_kernel& k = batch->kern[b];
         const int64_t n = batch->n[b];
-        if (k.next) {
+        if (k.next || k.times) {
             delete P;
-            return MFGP_UNSUPPORTED;   // kernel sums are not batched
+            return MFGP_UNSUPPORTED;   // kernel sums and products are not batched
         }
         bool ok = n >= 1 && k.family == fam && k.d >= 1 && k.d <= MFGP_MAX_D && std::isfinite(k.outputscale) &&
                   k.outputscale > 0.0f && std::isfinite(k.noise) && k.noise > 0.0f &&

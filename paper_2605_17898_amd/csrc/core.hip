@@ -164,7 +164,56 @@ hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, f
 
 // ---------------------------------------------------------------- operator products
 
+// A product term of RBF factors and at most one periodic factor (the checks
+// are the caller's): RBF with unit lengthscales on the concatenated features,
+// the periodic block first.
+static Operator make_product(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    Operator op;
+    op.family = MFGP_RBF;
+    op.din = k.d;
+    op.n = n;
+    op.s2 = k.outputscale;
+    op.sig2 = k.noise;
+    op.X = X;
+    op.U = U;
+    const double c = family_scale(MFGP_RBF);
+    int f0 = 0;
+    for (const mfgp_kernel* f = &k; f; f = f->times) {
+        if (f->family != MFGP_PERIODIC) continue;
+        op.periodic = 1;
+        op.period = static_cast<double>(f->period);
+        for (int q = 0; q < 2 * k.d; ++q) {
+            const double l = f->ard ? f->lengthscale[q / 2] : f->lengthscale[0];
+            op.fac[q] = static_cast<float>(c / l);
+            op.ls[q] = l;
+        }
+        f0 = 2 * k.d;
+    }
+    int nf = 0;
+    for (const mfgp_kernel* f = &k; f && nf < MFGP_MAX_TERMS; f = f->times, ++nf) {
+        Operator::Factor& fi = op.factor[nf];
+        fi.periodic = f->family == MFGP_PERIODIC;
+        fi.ard = f->ard ? 1 : 0;
+        if (fi.periodic) {
+            fi.f0 = 0;
+            continue;
+        }
+        fi.f0 = f0;
+        for (int q = 0; q < k.d; ++q) {
+            const double l = f->ard ? f->lengthscale[q] : f->lengthscale[0];
+            op.fac[f0 + q] = static_cast<float>(c / l);
+            op.ls[f0 + q] = l;
+        }
+        f0 += k.d;
+    }
+    op.nfactors = nf;
+    op.d = f0;
+    op.dextra = op.periodic ? f0 - 2 * k.d : 0;
+    return op;
+}
+
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    if (k.times) return make_product(k, X, n, U);
     Operator op;
     op.ard = k.ard ? 1 : 0;
     if (k.family == MFGP_LINEAR) {
@@ -208,19 +257,37 @@ Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U
 // and the circle functions evaluated in FP64, so the features carry only the
 // final rounding to FP32.
 __global__ void periodic_features_kernel(const float* __restrict__ X, int64_t n, int din,
-                                         double p, Fac fac, float* __restrict__ U) {
+                                         double p, Fac fac, float* __restrict__ U, int ldu) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n * din) return;
-    const int k = static_cast<int>(idx % din);
+    const int64_t i = idx / din;
+    const int k = static_cast<int>(idx - i * din);
     double ph = static_cast<double>(X[idx]) / p;
     ph -= rint(ph);
     double sn, cs;
     sincospi(2.0 * ph, &sn, &cs);
-    U[2 * idx] = static_cast<float>(static_cast<double>(fac.f[2 * k]) * cs);
-    U[2 * idx + 1] = static_cast<float>(static_cast<double>(fac.f[2 * k + 1]) * sn);
+    U[i * ldu + 2 * k] = static_cast<float>(static_cast<double>(fac.f[2 * k]) * cs);
+    U[i * ldu + 2 * k + 1] = static_cast<float>(static_cast<double>(fac.f[2 * k + 1]) * sn);
 }
 
-int term_feature_dim(const mfgp_kernel& k) { return k.family == MFGP_PERIODIC ? 2 * k.d : k.d; }
+// U[i, f0 + k] = X[i, k] fac_f0+k for k < din (an RBF factor of a product term)
+__global__ void prescale_cols_kernel(const float* __restrict__ X, int64_t n, int din, Fac fac, int f0,
+                                     float* __restrict__ U, int ldu) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * din) return;
+    const int64_t i = idx / din;
+    const int k = static_cast<int>(idx - i * din);
+    U[i * ldu + f0 + k] = X[idx] * fac.f[f0 + k];
+}
+
+int term_feature_dim(const mfgp_kernel& k) {
+    if (k.times) {
+        int f = 0;
+        for (const mfgp_kernel* q = &k; q; q = q->times) f += q->family == MFGP_PERIODIC ? 2 * k.d : k.d;
+        return f;
+    }
+    return k.family == MFGP_PERIODIC ? 2 * k.d : k.d;
+}
 
 int chain_feature_dim(const mfgp_kernel& k) {
     int f = 0;
@@ -229,6 +296,12 @@ int chain_feature_dim(const mfgp_kernel& k) {
 }
 
 int term_params(const mfgp_kernel& k) {
+    if (k.times) {
+        int p = 1;   // s2
+        for (const mfgp_kernel* q = &k; q; q = q->times)
+            p += (q->ard ? k.d : 1) + (q->family == MFGP_PERIODIC ? 1 : 0);
+        return p;
+    }
     if (k.family == MFGP_LINEAR) return 1;
     return (k.ard ? k.d : 1) + (k.family == MFGP_PERIODIC ? 2 : 1);
 }
@@ -257,12 +330,19 @@ hipError_t prescale_chain(const OpChain& ch, hipStream_t s) {
 }
 
 hipError_t prescale(const Operator& op, hipStream_t s) {
-    if (!op.periodic) return launch_prescale(op.X, op.n, op.d, op.fac, op.U, s);
+    if (!op.periodic && op.nfactors == 0) return launch_prescale(op.X, op.n, op.d, op.fac, op.U, s);
     Fac f{};
     for (int q = 0; q < op.d; ++q) f.f[q] = op.fac[q];
     const int64_t total = op.n * op.din;
-    hipLaunchKernelGGL(periodic_features_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
-                       0, s, op.X, op.n, op.din, op.period, f, op.U);
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    if (op.periodic)
+        hipLaunchKernelGGL(periodic_features_kernel, dim3(blocks), dim3(256), 0, s, op.X, op.n, op.din, op.period, f,
+                           op.U, op.d);
+    for (int q = 0; q < op.nfactors; ++q) {
+        if (op.factor[q].periodic) continue;
+        hipLaunchKernelGGL(prescale_cols_kernel, dim3(blocks), dim3(256), 0, s, op.X, op.n, op.din, f,
+                           op.factor[q].f0, op.U, op.d);
+    }
     return hipGetLastError();
 }
 

@@ -11,14 +11,26 @@ namespace mfgp {
 // u = c (cos 2 pi x / p, sin 2 pi x / p) / l (periodic = 1, din the input
 // dimension, period p); for the other families din = d.
 // A linear term (linear = 1) keeps the raw inputs in U (d = din, factors 1).
-// Terms of a kernel sum are linked through next (see OpChain).
+// Terms of a kernel sum are linked through next (see OpChain).  A product
+// term (nfactors > 0) of RBF factors and at most one periodic factor is RBF
+// on the concatenated features: the periodic factor's 2 din features first
+// (periodic = 1), then dextra features of the RBF factors; factor[] keeps
+// the caller's factor order with each factor's first feature f0.
 struct Operator {
+    struct Factor {
+        int periodic = 0;
+        int ard = 0;
+        int f0 = 0;
+    };
     int family = 0;
     int d = 0;
     int din = 0;
+    int dextra = 0;
     int periodic = 0;
     int linear = 0;
     int ard = 0;
+    int nfactors = 0;
+    Factor factor[MFGP_MAX_TERMS];
     double period = 0.0;
     const Operator* next = nullptr;
     int64_t n = 0;

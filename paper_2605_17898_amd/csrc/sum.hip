@@ -127,9 +127,43 @@ double lengthscale_factor(int family, double l) {
 // periodic family: grad[0..nl-1] lengthscales, grad[nl] the period, grad[nl+1]
 // s2 from G_l, G_s, G_p (see adjoint_periodic_kernel): with c the RBF scale,
 //   dk/dl_k = s2 G_l[k] / (c^2 l_k),  dk/dp = s2 (2 pi / (p^2 c^2)) G_p.
+// Product term (RBF on concatenated features): G holds [G_q per feature, G_s]
+// without a periodic factor and [G_l (din), G_x (dextra), G_s, G_p] with one;
+// each factor's lengthscales take s2 G / (c^2 l) of its features (the two of
+// each input for the periodic factor), in the caller's factor order.
+int grad_from_product(const Operator& op, const double* G, double* grad) {
+    const double c = family_scale(MFGP_RBF);
+    const int din = op.din;
+    // index of feature q's sum in G (periodic features pair into G_l)
+    auto gsum = [&](int q) { return op.periodic ? G[din + (q - 2 * din)] : G[q]; };
+    int off = 0;
+    for (int f = 0; f < op.nfactors; ++f) {
+        const Operator::Factor& fi = op.factor[f];
+        const int nl = fi.ard ? din : 1;
+        for (int k = 0; k < nl; ++k) grad[off + k] = 0.0;
+        for (int k = 0; k < din; ++k) {
+            double gk;
+            if (fi.periodic)
+                gk = static_cast<double>(op.s2) * G[k] / (c * c * op.ls[2 * k]);
+            else
+                gk = static_cast<double>(op.s2) * gsum(fi.f0 + k) / (c * c * op.ls[fi.f0 + k]);
+            grad[off + (fi.ard ? k : 0)] += gk;
+        }
+        off += nl;
+        if (fi.periodic) {
+            const double two_pi = 6.283185307179586477;
+            grad[off++] = static_cast<double>(op.s2) * two_pi / (op.period * op.period * c * c) *
+                          G[din + op.dextra + 1];
+        }
+    }
+    grad[off++] = op.periodic ? G[din + op.dextra] : G[op.d];
+    return off;
+}
+
 // Returns the number of entries written.
 int grad_from_sums(const Operator& op, const double* G, double* grad) {
     const int ard = op.ard;
+    if (op.nfactors > 0) return grad_from_product(op, G, grad);
     if (op.periodic) {
         const int din = op.din;
         const double c = family_scale(MFGP_RBF);

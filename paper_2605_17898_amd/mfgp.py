@@ -35,7 +35,7 @@ class KernelT(C.Structure):
 
 KernelT._fields_ = [("family", C.c_int32), ("d", C.c_int32), ("ard", C.c_int32),
                     ("lengthscale", C.c_float * MAX_D), ("outputscale", C.c_float), ("noise", C.c_float),
-                    ("period", C.c_float), ("next", C.POINTER(KernelT))]
+                    ("period", C.c_float), ("next", C.POINTER(KernelT)), ("times", C.POINTER(KernelT))]
 
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_double)
@@ -167,8 +167,53 @@ class Kernel:
     def __add__(self, other) -> "KernelSum":
         return KernelSum(self.terms() + other.terms())
 
+    def __mul__(self, other) -> "KernelProd":
+        return KernelProd(self.factors() + other.factors())
+
     def terms(self) -> list:
         return [self]
+
+    def factors(self) -> list:
+        return [self]
+
+
+class KernelProd:
+    """Product of kernels s2 prod_f k_f: s2 and the noise are the first
+    factor's (the others' outputscale and noise are ignored).  Passed to the
+    library as a chain of KernelT linked by `times`."""
+
+    def __init__(self, factors):
+        self._factors = list(factors)
+
+    def terms(self) -> list:
+        return [self]
+
+    def factors(self) -> list:
+        return list(self._factors)
+
+    def __add__(self, other) -> "KernelSum":
+        return KernelSum(self.terms() + other.terms())
+
+    def __mul__(self, other) -> "KernelProd":
+        return KernelProd(self.factors() + other.factors())
+
+    @property
+    def noise(self) -> float:
+        return self._factors[0].noise
+
+    def struct(self, d: int) -> KernelT:
+        arr = (KernelT * len(self._factors))(*[k.struct(d) for k in self._factors])
+        for q in range(len(self._factors) - 1):
+            arr[q].times = C.pointer(arr[q + 1])
+        head = arr[0]
+        head._chain_ref = arr
+        return head
+
+    def n_params(self, d: int) -> int:
+        return LIB.mfgp_num_params(C.byref(self.struct(d)))
+
+    def feature_dim(self, d: int) -> int:
+        return LIB.mfgp_feature_dim(C.byref(self.struct(d)))
 
 
 class KernelSum:
@@ -184,16 +229,20 @@ class KernelSum:
     def __add__(self, other) -> "KernelSum":
         return KernelSum(self.terms() + other.terms())
 
+    def factors(self) -> list:
+        raise TypeError("a product of a sum is not provided; expand it into a sum of products")
+
     @property
     def noise(self) -> float:
         return self._terms[0].noise
 
     def struct(self, d: int) -> KernelT:
-        arr = (KernelT * len(self._terms))(*[k.struct(d) for k in self._terms])
+        heads = [k.struct(d) for k in self._terms]
+        arr = (KernelT * len(self._terms))(*heads)
         for q in range(len(self._terms) - 1):
             arr[q].next = C.pointer(arr[q + 1])
         head = arr[0]
-        head._chain_ref = arr   # the chain lives as long as the head
+        head._chain_ref = (arr, heads)   # the chains (and product factors) live as long as the head
         return head
 
     def n_params(self, d: int) -> int:

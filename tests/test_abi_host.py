@@ -89,7 +89,7 @@ def test_sum_and_linear_params_and_checks(m):
     five = rbf + rbf + rbf + rbf + rbf
     assert matvec(five.struct(2)) == m.UNSUPPORTED        # more than MFGP_MAX_TERMS
     bad = ksum.struct(2)
-    bad._chain_ref[1].d = 3                                # terms must share d
+    bad._chain_ref[0][1].d = 3                             # terms must share d
     assert matvec(bad) == m.ERR_ARG
     neg = (rbf + m.Kernel("linear", 1.0, -0.3)).struct(2)
     assert matvec(neg) == m.ERR_ARG
@@ -99,6 +99,34 @@ def test_sum_and_linear_params_and_checks(m):
     # feature dimensions above MFGP_MAX_D are valid for sums in the size queries
     assert m.workspace_bytes(m.OP_CG, 1000, 12, 3) > 0
     assert m.workspace_bytes(m.OP_CG, 1000, 33, 3) == 0
+
+
+def test_product_params_and_checks(m):
+    rbf, per, lin = m.Kernel("rbf", [0.6, 1.4], 1.3, 0.05), m.Kernel("periodic", 0.8, period=0.45), \
+        m.Kernel("linear", 1.0, 0.3)
+    prod = rbf * per
+    assert prod.n_params(2) == 6          # [l1, l2 | l, p | s2 | sigma^2]
+    assert prod.feature_dim(2) == 6
+    assert (prod + lin).n_params(2) == 7
+    assert (m.Kernel("rbf", 0.5) * m.Kernel("rbf", 0.7)).feature_dim(4) == 8
+    dummy = C.c_void_p(16)
+    L = m.LIB
+
+    def matvec(k, ws=16):
+        return L.mfgp_kernel_matvec(C.byref(k), dummy, 10, dummy, 1, C.c_void_p(32), 0, dummy, ws, None)
+
+    assert matvec(prod.struct(2)) == m.ERR_WORKSPACE
+    assert matvec((prod + lin).struct(2)) == m.ERR_WORKSPACE
+    assert matvec((per * per).struct(1)) == m.UNSUPPORTED                 # two periodic factors
+    assert matvec((rbf * m.Kernel("matern32", 0.5)).struct(2)) == m.UNSUPPORTED
+    assert matvec((rbf * lin).struct(2)) == m.UNSUPPORTED
+    big = m.Kernel("rbf", 0.5, 1.0, 0.1) * m.Kernel("periodic", 0.5, period=1.0)
+    assert matvec(big.struct(3)) == m.UNSUPPORTED                          # 9 features > MFGP_MAX_D
+    bad = (rbf * m.Kernel("periodic", 0.8, period=-1.0)).struct(2)
+    assert matvec(bad) == m.ERR_ARG
+    # a product term alone is valid for the preconditioner
+    assert L.mfgp_pivoted_cholesky(C.byref(prod.struct(2)), dummy, 10, 2, dummy, dummy, dummy, 16, None) \
+        == m.ERR_WORKSPACE
 
 
 def test_workspace_sizes(m):

@@ -55,6 +55,8 @@ def test_batch_plan_validation(m):
     assert _create(m, [100, 50], [2, 3], [kl, kl]) == m.UNSUPPORTED
     ks = k + k
     assert _create(m, [100, 50], [2, 3], [ks, ks]) == m.UNSUPPORTED
+    kx = k * k
+    assert _create(m, [100, 50], [2, 3], [kx, kx]) == m.UNSUPPORTED
 
 
 def test_bench_refuses_more_than_one_gpu():
