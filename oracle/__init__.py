@@ -23,6 +23,8 @@ precond  rank-k pivoted Cholesky, the Woodbury preconditioner, preconditioned
          CG and the preconditioned log-determinant and gradient estimators.
 variance the exact predictive variance and its stochastic diagonal
          estimator (Rademacher probes).
+ski      structured kernel interpolation: the regular grid, cubic
+         convolution weights and the dense W K_UU W^T products.
 """
 
-from . import gp, krylov, brute, probes, bf16, precond, variance  # noqa: F401
+from . import gp, krylov, brute, probes, bf16, precond, variance, ski  # noqa: F401
