@@ -22,8 +22,11 @@ python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ 
 python bench.py --mode rbf500k [--precision fp32|bf16x2|bf16x3] [--precond K]   (N = 500000, d = 2, RBF
     l = 0.05, 16 probes: one MLL + gradient in the chosen precision)
 python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and 33 in
-    every precision, and N = 2k..50k at t = 1; HIP events around the whole call,
-    median of 5 after one warm-up)
+    every precision, and N = 2k..50k at t = 1; the periodic family, one adjoint
+    sweep per family, and kernel sums / products / Linear on the same points;
+    HIP events around the whole call, median of 5 after one warm-up)
+python bench.py --mode composite   (one MLL + gradient of Scale(RBF) + Scale(Periodic)
+    on the 100k points, 32 probes)
 python bench.py --mode small   (end-to-end latency of the 1024-point RBF and the
     20000-point Matern-5/2 workloads: solve, MLL + gradient, predictive mean; the
     oracle's dense Cholesky route timed beside them)
@@ -161,6 +164,43 @@ def rbf500k_leg(args) -> int:
     return 0
 
 
+def composite_leg(args) -> int:
+    """One MLL + gradient of Scale(RBF) + Scale(Periodic) on the rbf100k points
+    ([y, 32 probes], tol 1e-6): the paper's composition example at N = 1e5."""
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    w = inputs.rbf100k()
+    kern = (mfgp.Kernel("rbf", w.lengthscale, w.outputscale, w.noise)
+            + mfgp.Kernel("periodic", 1.0, 0.5 * w.outputscale, period=0.5))
+    X = torch.from_numpy(w.X).cuda()
+    y = torch.from_numpy(w.y).cuda()
+    Z = torch.from_numpy(w.Z).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def progress(it, rr):
+        print(f"[bench] composite: {it} iterations, worst recurrence residual {rr:.2e}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    mfgp.timing_enable(True)
+    r = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, progress=progress)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ph = mfgp.timing_phases()
+    f32 = mfgp.timing_read(mfgp.SWEEP_F32)
+    adj = mfgp.timing_read(mfgp.SWEEP_ADJOINT)
+    mfgp.timing_enable(False)
+    print(json.dumps({"mode": "composite", "kernel": "rbf(l=0.3) + periodic(l=1, p=0.5, s2/2)", "n": w.n,
+                      "probes": int(Z.shape[1]), "mll_grad_s": el, "cg_s": ph["cg_ms"] * 1e-3,
+                      "slq_s": ph["slq_ms"] * 1e-3, "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"],
+                      "cg_iters_max": max(i["iters"] for i in r["info"]),
+                      "rel_resid_true_max": max(i["rel_resid_true"] for i in r["info"]),
+                      "sweep_launches": f32["launches"], "sweep_ms_avg": f32["ms"] / max(f32["launches"], 1),
+                      "adjoint_sweep_ms": adj["ms"], "mll": r["mll"], "logdet": r["logdet"], "grad": r["grad"]}))
+    return 0
+
+
 def _median_call_ms(fn, reps: int = 5) -> float:
     """Median wall time of fn() bracketed by events on torch's current stream (one warm-up)."""
     import torch
@@ -221,9 +261,23 @@ def matvec_leg(args) -> int:
         ms = _median_call_ms(lambda: mfgp.kernel_adjoint(k, Xf, A, A, [0.5] + [-0.5 / 32] * 32))
         arow.append({"family": name, "n": full.n, "t": 33, "ms": ms})
         print(f"[bench] adjoint {name} n={full.n} t=33: {ms:.3f} ms", file=sys.stderr, flush=True)
+    # compositions (the paper's Scale(RBF) + Scale(Periodic), a product of two
+    # RBF factors, Linear) on the same points
+    comps = (("rbf(l=0.3) + periodic(l=1, p=0.5)", kern + pk, (1, 33)),
+             ("rbf(l=0.3) * rbf(l=0.8) (8 features)",
+              mfgp.Kernel("rbf", 0.3, full.outputscale, full.noise) * mfgp.Kernel("rbf", 0.8), (1, 33)),
+             ("linear", mfgp.Kernel("linear", 1.0, 1.0, full.noise), (1, 33)))
+    crow = []
+    for name, k, ts in comps:
+        for t in ts:
+            V = Vall[:, :t].contiguous()
+            out = torch.empty_like(V)
+            ms = _median_call_ms(lambda: mfgp.kernel_matvec(k, Xf, V, out=out))
+            crow.append({"kernel": name, "n": full.n, "t": t, "ms": ms})
+            print(f"[bench] {name} matvec n={full.n} t={t}: {ms:.3f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"mode": "matvec", "workload": "rbf100k geometry (d=4, RBF l=0.3)", "rows": rows,
                       "periodic": {"kernel": "periodic d=4 l=1.0 p=0.5 (8 features)", "rows": prow},
-                      "adjoint": arow}))
+                      "adjoint": arow, "compositions": crow}))
     return 0
 
 
@@ -284,7 +338,8 @@ def main() -> int:
                     choices=["fp32", "fp32_direct", "fp32_valu", "bf16x1", "bf16x2", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--mode", default="step", choices=["step", "kernel", "batch", "rbf500k", "matvec", "small"])
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite"])
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
@@ -308,6 +363,8 @@ def main() -> int:
         return batch_leg(args)
     if args.mode == "rbf500k":
         return rbf500k_leg(args)
+    if args.mode == "composite":
+        return composite_leg(args)
     if args.mode == "matvec":
         return matvec_leg(args)
     if args.mode == "small":
