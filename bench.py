@@ -27,6 +27,8 @@ python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and
     HIP events around the whole call, median of 5 after one warm-up)
 python bench.py --mode composite   (one MLL + gradient of Scale(RBF) + Scale(Periodic)
     on the 100k points, 32 probes)
+python bench.py --mode ski   (structured kernel interpolation at N = 200000, D = 1 and 2:
+    K_y V at t = 1 and 33, and a CG solve)
 python bench.py --mode small   (end-to-end latency of the 1024-point RBF and the
     20000-point Matern-5/2 workloads: solve, MLL + gradient, predictive mean; the
     oracle's dense Cholesky route timed beside them)
@@ -161,6 +163,41 @@ def rbf500k_leg(args) -> int:
                       "rel_resid_true_max": max(i["rel_resid_true"] for i in r["info"]),
                       "entries_per_s": allk["entries"] / el, "mll": r["mll"], "logdet": r["logdet"],
                       "grad": r["grad"]}))
+    return 0
+
+
+def ski_leg(args) -> int:
+    """Structured kernel interpolation at N = 200000 (D = 1, and D = 2 on a
+    280 x 280 grid): the whole K_y V call at t = 1 and 33, and a CG solve of y
+    to 1e-6."""
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    rows = []
+    for d, grids in ((1, ([10000], [100000])), (2, ([280, 280],))):
+        w = inputs.ski200k(d=d)
+        kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
+        X = torch.from_numpy(w.X).cuda()
+        y = torch.from_numpy(w.y).cuda()
+        for m in grids:
+            g = mfgp.ski_grid(m)
+            for t in (1, 33):
+                V = torch.randn(w.n, t, device="cuda") if t > 1 else y.clone()
+                out = torch.empty_like(V)
+                ms = _median_call_ms(lambda: mfgp.ski_matvec(kern, X, V, g, out=out))
+                rows.append({"d": d, "m": m, "n": w.n, "t": t, "matvec_ms": ms})
+                print(f"[bench] ski matvec d={d} m={m} t={t}: {ms:.3f} ms", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info, st = mfgp.ski_cg_solve(kern, X, y, g, tol=1e-6)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rows.append({"d": d, "m": m, "n": w.n, "cg_solve_s": el, "iters": info[0]["iters"],
+                         "rel_resid_true": info[0]["rel_resid_true"], "status": st})
+            print(f"[bench] ski cg d={d} m={m}: {el:.3f} s, {info[0]['iters']} iterations", file=sys.stderr,
+                  flush=True)
+    print(json.dumps({"mode": "ski", "workload": "ski200k (uniform [0,1]^d, RBF l=0.05, sigma^2=0.01)",
+                      "rows": rows}))
     return 0
 
 
@@ -339,7 +376,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--mode", default="step",
-                    choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite"])
+                    choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite", "ski"])
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
@@ -363,6 +400,8 @@ def main() -> int:
         return batch_leg(args)
     if args.mode == "rbf500k":
         return rbf500k_leg(args)
+    if args.mode == "ski":
+        return ski_leg(args)
     if args.mode == "composite":
         return composite_leg(args)
     if args.mode == "matvec":

@@ -290,6 +290,54 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
  * clear, else -1 (Steele, Lea & Flood 2014).  Asynchronous. */
 int mfgp_rademacher(uint64_t seed, int64_t n, int32_t p, float* Z, void* stream);
 
+/* ---------------------------------------------------------------- structured kernel interpolation
+ * SKI / KISS-GP (Sec. 2 "Structured kernel interpolation"; Sec. 3 "Inference":
+ * SKI with FFT), the method of Wilson & Nickisch (2015):
+ *   K_y V ~ W K_UU W^T V + sigma^2 V,   mu_* ~ W_* K_UU W^T A,   K_UU = s2 k(U, U),
+ * U a regular grid (D <= 3), W local cubic convolution interpolation (Keys
+ * 1981, a = -1/2; 4^D weights per point), K_UU applied through the FFT (FP64,
+ * hipFFT) of its circulant embedding (2 m_k per dimension).  Grid per
+ * dimension k: the data range [min_k, max_k] (the points' own, or the
+ * caller's when explicit_range is set), r_k = max_k - min_k (1 if zero),
+ * spacing h_k = r_k / (m_k - 4), nodes lo_k + j h_k with lo_k = min_k - h_k,
+ * j < m_k; weights of nodes off the grid (points outside the range) are
+ * dropped.  Products accumulate in FP64 (atomic scatter: the last bits vary
+ * between runs) and round once.  Kernels: one term of family RBF, MATERN*
+ * or PERIODIC (no sums, products or LINEAR: MFGP_UNSUPPORTED), d <= 3.
+ * The first call with a grid shape and column count on a device from a host
+ * thread creates hipFFT plans for it and keeps them until the process ends
+ * (hipFFT allocates their device memory then); later calls reuse them. */
+typedef struct {
+    int32_t m[3];            /* grid nodes per dimension (first d used), >= 5;
+                                prod (2 m_k) < 2^31                                 */
+    int32_t explicit_range;  /* nonzero: lo / hi give the data range                */
+    float lo[3];             /* explicit_range: min_k (finite)                      */
+    float hi[3];             /* explicit_range: max_k (finite, >= lo[k])            */
+} mfgp_ski_grid;
+
+/* Bytes of workspace of a SKI call: op MFGP_OP_MATVEC / MFGP_OP_CG /
+ * MFGP_OP_PREDICT, n points, d dims, t columns, the grid (host); 0 if invalid. */
+size_t mfgp_ski_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, const mfgp_ski_grid* grid);
+
+/* KV = W K_UU W^T V + sigma^2 V on the grid of X (or the explicit range).
+ * X [n,d], V [n,t], KV [n,t] (must not alias V).  Asynchronous. */
+int mfgp_ski_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                    const float* V, int32_t t, float* KV, void* ws, size_t ws_bytes, void* stream);
+
+/* Solve (W K_UU W^T + sigma^2 I) Xsol = B by the CG of mfgp_cg_solve (same
+ * options, refinement against the FP64 SKI residual; opts->precision is not
+ * used: the SKI product is FP64).  Synchronises. */
+int mfgp_ski_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                      const float* B, int32_t t, double* Xsol, const mfgp_cg_opts* opts, mfgp_cg_info* info,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* MU = W_* K_UU W^T A: the SKI predictive mean at Xs [m,d] from A [n,t]
+ * (the solve's result), on the grid of X and Xs together (or the explicit
+ * range; use the same grid as the solve).  Asynchronous. */
+int mfgp_ski_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs, int64_t m,
+                          const mfgp_ski_grid* grid, const float* A, int32_t t, float* MU, void* ws,
+                          size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent GP problems solved together (LightGP Sec. 5 names batched
  * solves as the missing piece of its CG).  Problem b has n[b] rows, its own

@@ -47,6 +47,7 @@ UNITS = [
     ("hybrid.hip", "hybrid.o", []),
     ("gram.hip", "gram.o", []),
     ("sum.hip", "sum.o", []),
+    ("ski.hip", "ski.o", []),
     ("precond.hip", "precond.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]
@@ -81,7 +82,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
                 print(r.stdout, r.stderr, file=sys.stderr)
     objs = [os.path.join(BUILD, o) for _, o, _ in UNITS] + [os.path.join(BUILD, o) for _, o in HOST_UNITS]
     tmp = LIB + ".tmp"
-    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas",
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas", "-lhipfft",
           "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB

@@ -662,6 +662,101 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     return slq_status;
 }
 
+// ---------------------------------------------------------------- structured kernel interpolation
+
+static int check_ski(const mfgp_kernel* kern, const mfgp_ski_grid* grid, bool need_noise) {
+    int st = check_kernel(kern, need_noise);
+    if (st != MFGP_OK) return st;
+    if (!grid) return MFGP_ERR_ARG;
+    if (kern->next || kern->times || kern->family == MFGP_LINEAR || kern->d > 3) return MFGP_UNSUPPORTED;
+    int64_t lr = 1;
+    for (int k = 0; k < kern->d; ++k) {
+        if (grid->m[k] < 5) return MFGP_ERR_ARG;
+        lr *= 2 * static_cast<int64_t>(grid->m[k]);
+        if (lr >= (int64_t(1) << 31)) return MFGP_UNSUPPORTED;
+        if (grid->explicit_range &&
+            !(std::isfinite(grid->lo[k]) && std::isfinite(grid->hi[k]) && grid->hi[k] >= grid->lo[k]))
+            return MFGP_ERR_ARG;
+    }
+    return MFGP_OK;
+}
+
+size_t mfgp_ski_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, const mfgp_ski_grid* grid) {
+    if (n < 1 || d < 1 || d > 3 || t < 1 || !grid) return 0;
+    for (int k = 0; k < d; ++k)
+        if (grid->m[k] < 5) return 0;
+    Carver cv(nullptr);
+    cv.take<char>(ski_scratch_bytes(d, grid->m, t));
+    if (op == MFGP_OP_CG)
+        carve_cg_vectors(cv, n, t);
+    else if (op != MFGP_OP_MATVEC && op != MFGP_OP_PREDICT)
+        return 0;
+    return cv.off + 256;
+}
+
+int mfgp_ski_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                    const float* V, int32_t t, float* KV, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_ski(kern, grid, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !V || !KV || !ws || n < 1 || t < 1 || t > MFGP_MAX_T || KV == V) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    SkiOp sk;
+    const bool ex = grid->explicit_range != 0;
+    ABI_CHECK(ski_setup(sk, *kern, X, n, nullptr, 0, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
+                        sk_scratch, s));
+    ABI_CHECK(ski_apply(sk, X, n, X, n, V, t, KV, true, kern->noise, V, s));
+    return MFGP_OK;
+}
+
+int mfgp_ski_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                      const float* B, int32_t t, double* Xsol, const mfgp_cg_opts* opts, mfgp_cg_info* info,
+                      void* ws, size_t ws_bytes, void* stream) {
+    int st = check_ski(kern, grid, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !B || !Xsol || !ws || n < 1 || t < 1 || t > MFGP_MAX_T) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_CG, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    CgBufs b = carve_cg_vectors(cv, n, t);
+    SkiOp sk;
+    const bool ex = grid->explicit_range != 0;
+    ABI_CHECK(ski_setup(sk, *kern, X, n, nullptr, 0, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
+                        sk_scratch, s));
+    Operator op;
+    op.family = kern->family;
+    op.d = op.din = kern->d;
+    op.n = n;
+    op.s2 = kern->outputscale;
+    op.sig2 = kern->noise;
+    op.X = X;
+    op.ski = &sk;
+    const int max_iter = default_max_iter(n, opts->max_iter);
+    return cg_run(op, B, t, Xsol, *opts, info, nullptr, max_iter, b, s);
+}
+
+int mfgp_ski_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs, int64_t m,
+                          const mfgp_ski_grid* grid, const float* A, int32_t t, float* MU, void* ws,
+                          size_t ws_bytes, void* stream) {
+    int st = check_ski(kern, grid, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !Xs || !A || !MU || !ws || n < 1 || m < 1 || t < 1 || t > MFGP_MAX_T) return MFGP_ERR_ARG;
+    if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_PREDICT, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    SkiOp sk;
+    const bool ex = grid->explicit_range != 0;
+    ABI_CHECK(ski_setup(sk, *kern, X, n, Xs, m, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
+                        sk_scratch, s));
+    ABI_CHECK(ski_apply(sk, X, n, Xs, m, A, t, MU, false, 0.0f, nullptr, s));
+    return MFGP_OK;
+}
+
 // ---------------------------------------------------------------- preconditioned solves
 
 size_t mfgp_precond_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t rank,

@@ -70,6 +70,19 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
     return b;
 }
 
+CgBufs carve_cg_vectors(Carver& cv, int64_t n, int t) {
+    CgBufs b;
+    const size_t nt = static_cast<size_t>(n) * t;
+    b.R = cv.take<float>(nt);
+    b.P = cv.take<float>(nt);
+    b.AP = cv.take<float>(nt);
+    b.R64 = cv.take<double>(nt);
+    b.scal = cv.take<double>(8 * static_cast<size_t>(t));
+    b.ints = cv.take<int>(6 * static_cast<size_t>(t));
+    b.dots = cv.take<double>(dots_scratch_doubles(n, t));
+    return b;
+}
+
 static CgState make_state(const CgBufs& b, double* X, int t, double* coeff) {
     CgState st;
     st.x = X;

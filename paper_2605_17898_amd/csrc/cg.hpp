@@ -20,6 +20,9 @@ struct CgBufs {
 };
 
 CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision);
+// The CG vectors only (no product or residual scratch): for operators that
+// bring their own (structured kernel interpolation).
+CgBufs carve_cg_vectors(Carver& cv, int64_t n, int t);
 
 // Runs CG on K_y X = B (op prescaled, U filled).  Returns the worst column status.
 int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_opts& o,

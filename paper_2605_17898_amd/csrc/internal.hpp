@@ -10,6 +10,35 @@ namespace mfgp {
 // The periodic family is held as RBF on its d = 2 din circle features
 // u = c (cos 2 pi x / p, sin 2 pi x / p) / l (periodic = 1, din the input
 // dimension, period p); for the other families din = d.
+// Structured kernel interpolation (ski.hip): the regular grid of D <= 3
+// dimensions (m_k nodes, circulant embedding L_k = 2 m_k), the device grid
+// geometry geo = [lo_0..2, h_0..2], the FP64 spectrum of the embedded grid
+// kernel (lam, complex [Lc]) and the product buffers for t columns.
+struct SkiGeomH {
+    int d;
+    int m[3];
+    int L[3];
+    int64_t Lr;   // prod L
+    int64_t Lc;   // (L0 / 2 + 1) L1 L2
+};
+struct SkiOp {
+    SkiGeomH g{};
+    double* geo = nullptr;
+    void* lam = nullptr;
+    double* grid = nullptr;   // [t][Lr]
+    void* spec = nullptr;     // [t][Lc] complex
+    float* part = nullptr;
+    int t = 0;
+};
+size_t ski_scratch_bytes(int d, const int32_t* m, int t);
+// lo, hi: the caller's data range, or null for the range of X (and Xs).
+hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n, const float* Xs, int64_t ms,
+                     const int32_t* m, const float* lo, const float* hi, int t, void* scratch, hipStream_t s);
+hipError_t ski_apply(const SkiOp& op, const float* Xc, int64_t nc, const float* Xr, int64_t nr, const float* V, int t,
+                     float* out, bool with_noise, float sig2, const float* Vself, hipStream_t s);
+hipError_t ski_residual(const SkiOp& op, const float* X, int64_t n, const float* B, const double* X64, int t,
+                        float sig2, double* R, hipStream_t s);
+
 // A linear term (linear = 1) keeps the raw inputs in U (d = din, factors 1).
 // Terms of a kernel sum are linked through next (see OpChain).  A product
 // term (nfactors > 0) of RBF factors and at most one periodic factor is RBF
@@ -33,6 +62,7 @@ struct Operator {
     Factor factor[MFGP_MAX_TERMS];
     double period = 0.0;
     const Operator* next = nullptr;
+    const SkiOp* ski = nullptr;   // non-null: products by structured kernel interpolation
     int64_t n = 0;
     float s2 = 1.0f;
     float sig2 = 0.0f;

@@ -1,0 +1,384 @@
+// Structured kernel interpolation (SKI / KISS-GP; LightGP Sec. 2 "Structured
+// kernel interpolation", Sec. 3 "Inference": SKI with FFT for O(N log N)
+// products).  Following Wilson & Nickisch (2015):
+//   K_XX ~ W K_UU W^T,   K_y V ~ W K_UU W^T V + sigma^2 V,
+// U a regular grid of m_0 x .. x m_{D-1} points (D <= 3), W the local cubic
+// convolution interpolation of Keys (1981, a = -1/2): 4 nodes per dimension.
+//
+// Grid (per dimension k): data range [min_k, max_k] (from the points, or the
+// caller's), r_k = max_k - min_k (1 if zero), spacing h_k = r_k / (m_k - 4),
+// first node lo_k = min_k - h_k, so a point's stencil b - 1 .. b + 2 of its
+// cell b lies on the grid; nodes off the grid (points outside the range)
+// are skipped.
+//
+// K_UU is multilevel Toeplitz for a stationary kernel; its product is taken
+// through the D-dimensional circulant embedding of size L_k = 2 m_k: the
+// first column holds k(o h) at offsets o_k = j_k (j_k < m_k), L_k - j_k
+// (j_k > m_k) and 0 at j_k = m_k; its FFT (FP64, hipFFT D2Z) is the
+// spectrum.  One product: zero the padded grid [t][L], scatter W^T V into
+// it (FP64 atomics), FFT, multiply by the spectrum / prod L, inverse FFT,
+// gather W (.) in FP64 and round once.
+#include "internal.hpp"
+
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <map>
+#include <tuple>
+
+namespace mfgp {
+
+namespace {
+
+constexpr int kBoundBlocks = 256;
+
+using SkiGeom = SkiGeomH;
+
+struct KParams {
+    int family;
+    double inv_l[3];
+    double s2;
+    double period;
+};
+
+__device__ __forceinline__ void keys4(double f, double w[4]) {
+    // distances 1 + f, f, 1 - f, 2 - f of nodes b - 1 .. b + 2 (a = -1/2)
+    const double s0 = 1.0 + f, s1 = f, s2 = 1.0 - f, s3 = 2.0 - f;
+    w[0] = ((-0.5 * s0 + 2.5) * s0 - 4.0) * s0 + 2.0;
+    w[1] = (1.5 * s1 - 2.5) * s1 * s1 + 1.0;
+    w[2] = (1.5 * s2 - 2.5) * s2 * s2 + 1.0;
+    w[3] = ((-0.5 * s3 + 2.5) * s3 - 4.0) * s3 + 2.0;
+}
+
+// Stencil of a point: base node per dimension (b - 1) and the 4 weights;
+// false for a non-finite coordinate.
+__device__ __forceinline__ bool stencil(const float* __restrict__ x, const double* __restrict__ geo,
+                                        const SkiGeom& g, int base[3], double w[3][4]) {
+    for (int k = 0; k < g.d; ++k) {
+        double t = (static_cast<double>(x[k]) - geo[k]) / geo[3 + k];
+        if (!(t == t) || isinf(t)) return false;
+        t = fmin(fmax(t, -4.0), static_cast<double>(g.m[k]) + 4.0);
+        const double b = floor(t);
+        base[k] = static_cast<int>(b) - 1;
+        keys4(t - b, w[k]);
+    }
+    return true;
+}
+
+__global__ void ski_bounds_stage1(const float* __restrict__ X, int64_t n, const float* __restrict__ Xs, int64_t ms,
+                                  int d, float* __restrict__ part) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t total = n + ms;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const float* x = i < n ? X + i * d : Xs + (i - n) * d;
+        for (int k = 0; k < d; ++k) {
+            mn[k] = fminf(mn[k], x[k]);
+            mx[k] = fmaxf(mx[k], x[k]);
+        }
+    }
+    __shared__ float smn[3][256], smx[3][256];
+    for (int k = 0; k < 3; ++k) {
+        smn[k][threadIdx.x] = mn[k];
+        smx[k][threadIdx.x] = mx[k];
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 3; ++k) {
+                smn[k][threadIdx.x] = fminf(smn[k][threadIdx.x], smn[k][threadIdx.x + off]);
+                smx[k][threadIdx.x] = fmaxf(smx[k][threadIdx.x], smx[k][threadIdx.x + off]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        part[blockIdx.x * 6 + threadIdx.x] = smn[threadIdx.x][0];
+        part[blockIdx.x * 6 + 3 + threadIdx.x] = smx[threadIdx.x][0];
+    }
+}
+
+// geo[k] = lo_k, geo[3 + k] = h_k from the block minima / maxima (auto) or the
+// caller's range (explicit: lo/hi arguments).
+__global__ void ski_geo_kernel(const float* __restrict__ part, int nb, int explicit_range, SkiGeom g, float lo0,
+                               float lo1, float lo2, float hi0, float hi1, float hi2, double* __restrict__ geo) {
+    const int k = threadIdx.x;
+    if (k >= g.d) return;
+    float mn, mx;
+    if (explicit_range) {
+        mn = k == 0 ? lo0 : (k == 1 ? lo1 : lo2);
+        mx = k == 0 ? hi0 : (k == 1 ? hi1 : hi2);
+    } else {
+        mn = INFINITY;
+        mx = -INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            mn = fminf(mn, part[b * 6 + k]);
+            mx = fmaxf(mx, part[b * 6 + 3 + k]);
+        }
+    }
+    double r = static_cast<double>(mx) - static_cast<double>(mn);
+    if (!(r > 0.0)) r = 1.0;
+    const double h = r / static_cast<double>(g.m[k] - 4);
+    geo[k] = static_cast<double>(mn) - h;
+    geo[3 + k] = h;
+}
+
+// First column of the circulant embedding (s2 k at the wrapped offsets).
+__global__ void ski_column_kernel(SkiGeom g, const double* __restrict__ geo, KParams kp, double* __restrict__ c) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= g.Lr) return;
+    int64_t rest = q;
+    double r2 = 0.0, sp = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const int j = static_cast<int>(rest % g.L[k]);
+        rest /= g.L[k];
+        if (k >= g.d) continue;
+        int o;
+        if (j < g.m[k]) {
+            o = j;
+        } else if (j == g.m[k]) {
+            c[q] = 0.0;
+            return;
+        } else {
+            o = g.L[k] - j;
+        }
+        const double delta = o * geo[3 + k];
+        const double u = delta * kp.inv_l[k];
+        r2 += u * u;
+        if (kp.family == MFGP_PERIODIC) {
+            const double sn = sin(3.14159265358979323846 * delta / kp.period) * kp.inv_l[k];
+            sp += 2.0 * sn * sn;
+        }
+    }
+    double v;
+    const double r = sqrt(r2);
+    switch (kp.family) {
+        case MFGP_RBF: v = exp(-0.5 * r2); break;
+        case MFGP_MATERN12: v = exp(-r); break;
+        case MFGP_MATERN32: v = (1.0 + sqrt(3.0) * r) * exp(-sqrt(3.0) * r); break;
+        case MFGP_MATERN52: v = (1.0 + sqrt(5.0) * r + 5.0 * r2 / 3.0) * exp(-sqrt(5.0) * r); break;
+        default: v = exp(-sp); break;
+    }
+    c[q] = kp.s2 * v;
+}
+
+__global__ void fill0_kernel(double* __restrict__ a, int64_t total) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx < total) a[idx] = 0.0;
+}
+
+// grid[c][node] += w V[i, c] over the stencil of point i (thread per (i, c)).
+template <typename T>
+__global__ void ski_scatter_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
+                                   const T* __restrict__ V, int t, double* __restrict__ grid) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * t) return;
+    const int64_t i = idx / t;
+    const int c = static_cast<int>(idx - i * t);
+    int base[3] = {0, 0, 0};
+    double w[3][4] = {{1, 0, 0, 0}, {1, 0, 0, 0}, {1, 0, 0, 0}};
+    if (!stencil(X + i * g.d, geo, g, base, w)) return;
+    const double v = static_cast<double>(V[idx]);
+    double* gc = grid + static_cast<int64_t>(c) * g.Lr;
+    const int n1 = g.d > 1 ? 4 : 1, n2 = g.d > 2 ? 4 : 1;
+    for (int a2 = 0; a2 < n2; ++a2) {
+        const int j2 = base[2] + a2;
+        if (g.d > 2 && (j2 < 0 || j2 >= g.m[2])) continue;
+        for (int a1 = 0; a1 < n1; ++a1) {
+            const int j1 = base[1] + a1;
+            if (g.d > 1 && (j1 < 0 || j1 >= g.m[1])) continue;
+            const double w12 = (g.d > 2 ? w[2][a2] : 1.0) * (g.d > 1 ? w[1][a1] : 1.0);
+            const int64_t row = (g.d > 1 ? j1 : 0) * static_cast<int64_t>(g.L[0]) +
+                                (g.d > 2 ? j2 : 0) * static_cast<int64_t>(g.L[0]) * g.L[1];
+            for (int a0 = 0; a0 < 4; ++a0) {
+                const int j0 = base[0] + a0;
+                if (j0 < 0 || j0 >= g.m[0]) continue;
+                atomicAdd(gc + row + j0, w12 * w[0][a0] * v);
+            }
+        }
+    }
+}
+
+// out = sum over the stencil of w grid[c][node] (FP64); then either
+// OUT float: out[i, c] = that + sig2 Vself[i, c] (Vself may be null), or
+// residual:  R[i, c] = B[i, c] - (that + sig2 X64[i, c]).
+__global__ void ski_gather_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
+                                  const double* __restrict__ grid, int t, double sig2, const float* __restrict__ Vself,
+                                  float* __restrict__ out, const float* __restrict__ B,
+                                  const double* __restrict__ X64, double* __restrict__ R) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * t) return;
+    const int64_t i = idx / t;
+    const int c = static_cast<int>(idx - i * t);
+    int base[3] = {0, 0, 0};
+    double w[3][4] = {{1, 0, 0, 0}, {1, 0, 0, 0}, {1, 0, 0, 0}};
+    double acc = 0.0;
+    if (stencil(X + i * g.d, geo, g, base, w)) {
+        const double* gc = grid + static_cast<int64_t>(c) * g.Lr;
+        const int n1 = g.d > 1 ? 4 : 1, n2 = g.d > 2 ? 4 : 1;
+        for (int a2 = 0; a2 < n2; ++a2) {
+            const int j2 = base[2] + a2;
+            if (g.d > 2 && (j2 < 0 || j2 >= g.m[2])) continue;
+            for (int a1 = 0; a1 < n1; ++a1) {
+                const int j1 = base[1] + a1;
+                if (g.d > 1 && (j1 < 0 || j1 >= g.m[1])) continue;
+                const double w12 = (g.d > 2 ? w[2][a2] : 1.0) * (g.d > 1 ? w[1][a1] : 1.0);
+                const int64_t row = (g.d > 1 ? j1 : 0) * static_cast<int64_t>(g.L[0]) +
+                                    (g.d > 2 ? j2 : 0) * static_cast<int64_t>(g.L[0]) * g.L[1];
+                for (int a0 = 0; a0 < 4; ++a0) {
+                    const int j0 = base[0] + a0;
+                    if (j0 < 0 || j0 >= g.m[0]) continue;
+                    acc = fma(w12 * w[0][a0], gc[row + j0], acc);
+                }
+            }
+        }
+    }
+    if (R) {
+        R[idx] = static_cast<double>(B[idx]) - (acc + sig2 * X64[idx]);
+    } else {
+        if (Vself) acc += sig2 * static_cast<double>(Vself[idx]);
+        out[idx] = static_cast<float>(acc);
+    }
+}
+
+__global__ void ski_spectral_mul_kernel(hipfftDoubleComplex* __restrict__ spec, const hipfftDoubleComplex* __restrict__ lam,
+                                        int64_t Lc, int t, double scale) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= Lc * t) return;
+    const hipfftDoubleComplex a = spec[idx];
+    const hipfftDoubleComplex b = lam[idx % Lc];
+    spec[idx] = make_hipDoubleComplex((a.x * b.x - a.y * b.y) * scale, (a.x * b.y + a.y * b.x) * scale);
+}
+
+inline unsigned nblk(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
+
+SkiGeom make_geom(int d, const int32_t* m) {
+    SkiGeom g{};
+    g.d = d;
+    g.Lr = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.m[k] = k < d ? m[k] : 1;
+        g.L[k] = k < d ? 2 * m[k] : 1;
+        g.Lr *= g.L[k];
+    }
+    g.Lc = static_cast<int64_t>(g.L[0] / 2 + 1) * g.L[1] * g.L[2];
+    return g;
+}
+
+// hipFFT plans by (device, rank, sizes, batch, direction), kept per host thread.
+hipfftHandle fft_plan(const SkiGeom& g, int batch, bool forward, hipError_t& err) {
+    thread_local std::map<std::tuple<int, int, int, int, int, int, int>, hipfftHandle> plans;
+    int dev = 0;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return nullptr;
+    const auto key = std::make_tuple(dev, g.d, g.L[0], g.L[1], g.L[2], batch, forward ? 1 : 0);
+    auto it = plans.find(key);
+    if (it != plans.end()) return it->second;
+    int nn[3];
+    for (int k = 0; k < g.d; ++k) nn[k] = g.L[g.d - 1 - k];   // slowest first
+    hipfftHandle p = nullptr;
+    if (hipfftPlanMany(&p, g.d, nn, nullptr, 1, static_cast<int>(g.Lr), nullptr, 1, static_cast<int>(g.Lc),
+                       forward ? HIPFFT_D2Z : HIPFFT_Z2D, batch) != HIPFFT_SUCCESS) {
+        err = hipErrorUnknown;
+        return nullptr;
+    }
+    plans.emplace(key, p);
+    return p;
+}
+
+}  // namespace
+
+size_t ski_scratch_bytes(int d, const int32_t* m, int t) {
+    const SkiGeom g = make_geom(d, m);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return al(6 * sizeof(double)) + al(g.Lc * sizeof(hipfftDoubleComplex)) +
+           al(static_cast<size_t>(t) * g.Lr * sizeof(double)) +
+           al(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)) + al(kBoundBlocks * 6 * sizeof(float)) + 256;
+}
+
+// Grid geometry and spectrum for the kernel: the range from X (and Xs) or the
+// caller's lo / hi; t the column count of the products that follow.
+hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n, const float* Xs, int64_t ms,
+                     const int32_t* m, const float* lo, const float* hi, int t, void* scratch, hipStream_t s) {
+    op.g = make_geom(k.d, m);
+    op.t = t;
+    char* p = static_cast<char*>(scratch);
+    auto take = [&](size_t b) {
+        char* r = p;
+        p += (b + 255) / 256 * 256;
+        return r;
+    };
+    op.geo = reinterpret_cast<double*>(take(6 * sizeof(double)));
+    op.lam = take(op.g.Lc * sizeof(hipfftDoubleComplex));
+    op.grid = reinterpret_cast<double*>(take(static_cast<size_t>(t) * op.g.Lr * sizeof(double)));
+    op.spec = take(static_cast<size_t>(t) * op.g.Lc * sizeof(hipfftDoubleComplex));
+    op.part = reinterpret_cast<float*>(take(kBoundBlocks * 6 * sizeof(float)));
+    const bool expl = lo && hi;
+    if (!expl) {
+        hipLaunchKernelGGL(ski_bounds_stage1, dim3(kBoundBlocks), dim3(256), 0, s, X, n, Xs, Xs ? ms : 0, k.d, op.part);
+    }
+    float l3[3] = {0, 0, 0}, h3[3] = {0, 0, 0};
+    for (int q = 0; q < k.d && expl; ++q) {
+        l3[q] = lo[q];
+        h3[q] = hi[q];
+    }
+    hipLaunchKernelGGL(ski_geo_kernel, dim3(1), dim3(64), 0, s, op.part, kBoundBlocks, expl ? 1 : 0, op.g, l3[0],
+                       l3[1], l3[2], h3[0], h3[1], h3[2], op.geo);
+    KParams kp{};
+    kp.family = k.family;
+    kp.s2 = k.outputscale;
+    kp.period = k.period;
+    for (int q = 0; q < 3; ++q) kp.inv_l[q] = q < k.d ? 1.0 / (k.ard ? k.lengthscale[q] : k.lengthscale[0]) : 0.0;
+    // the column in grid slot 0, its transform in lam
+    hipLaunchKernelGGL(ski_column_kernel, dim3(nblk(op.g.Lr)), dim3(256), 0, s, op.g, op.geo, kp, op.grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipfftHandle f1 = fft_plan(op.g, 1, true, e);
+    if (!f1) return e;
+    if (hipfftSetStream(f1, s) != HIPFFT_SUCCESS ||
+        hipfftExecD2Z(f1, op.grid, static_cast<hipfftDoubleComplex*>(op.lam)) != HIPFFT_SUCCESS)
+        return hipErrorUnknown;
+    return hipGetLastError();
+}
+
+// One SKI product W_r K_UU W_c^T V over the columns' points Xc [nc] and the
+// rows' points Xr [nr]; writes out (float, + sig2 Vself) or the FP64
+// residual R = B - (product + sig2 X64) when R is non-null (then V = X64).
+template <typename T>
+static hipError_t ski_product(const SkiOp& op, const float* Xc, int64_t nc, const float* Xr, int64_t nr,
+                              const T* V, int t, double sig2, const float* Vself, float* out, const float* B,
+                              const double* X64, double* R, hipStream_t s) {
+    if (t > op.t) return hipErrorInvalidValue;
+    const int64_t tot = op.g.Lr * t;
+    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, op.grid, tot);
+    hipLaunchKernelGGL((ski_scatter_kernel<T>), dim3(nblk(nc * t)), dim3(256), 0, s, Xc, nc, op.g, op.geo, V, t,
+                       op.grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipfftHandle fwd = fft_plan(op.g, t, true, e);
+    if (!fwd) return e;
+    hipfftHandle inv = fft_plan(op.g, t, false, e);
+    if (!inv) return e;
+    auto* spec = static_cast<hipfftDoubleComplex*>(op.spec);
+    if (hipfftSetStream(fwd, s) != HIPFFT_SUCCESS || hipfftExecD2Z(fwd, op.grid, spec) != HIPFFT_SUCCESS)
+        return hipErrorUnknown;
+    hipLaunchKernelGGL(ski_spectral_mul_kernel, dim3(nblk(op.g.Lc * t)), dim3(256), 0, s, spec,
+                       static_cast<const hipfftDoubleComplex*>(op.lam), op.g.Lc, t, 1.0 / static_cast<double>(op.g.Lr));
+    if (hipfftSetStream(inv, s) != HIPFFT_SUCCESS || hipfftExecZ2D(inv, spec, op.grid) != HIPFFT_SUCCESS)
+        return hipErrorUnknown;
+    hipLaunchKernelGGL(ski_gather_kernel, dim3(nblk(nr * t)), dim3(256), 0, s, Xr, nr, op.g, op.geo, op.grid, t, sig2,
+                       Vself, out, B, X64, R);
+    return hipGetLastError();
+}
+
+hipError_t ski_apply(const SkiOp& op, const float* Xc, int64_t nc, const float* Xr, int64_t nr, const float* V, int t,
+                     float* out, bool with_noise, float sig2, const float* Vself, hipStream_t s) {
+    return ski_product<float>(op, Xc, nc, Xr, nr, V, t, with_noise ? static_cast<double>(sig2) : 0.0,
+                              with_noise ? Vself : nullptr, out, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t ski_residual(const SkiOp& op, const float* X, int64_t n, const float* B, const double* X64, int t,
+                        float sig2, double* R, hipStream_t s) {
+    return ski_product<double>(op, X, n, X, n, X64, t, static_cast<double>(sig2), nullptr, nullptr, B, X64, R, s);
+}
+
+}  // namespace mfgp

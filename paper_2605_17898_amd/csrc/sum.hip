@@ -206,6 +206,10 @@ size_t sum_scratch_bytes(int64_t m, int t) {
 hipError_t apply_sum(const Operator& cols, const Operator* rows, int64_t m, const float* V, int t, float* out,
                      bool with_noise, const float* Vself, void* scratch, void* sum_scratch, int precision,
                      hipStream_t s) {
+    if (cols.ski) {
+        const Operator* rr = rows ? rows : &cols;
+        return ski_apply(*cols.ski, cols.X, cols.n, rr->X, m, V, t, out, with_noise, cols.sig2, Vself, s);
+    }
     double* part = static_cast<double*>(sum_scratch);
     double* xtv = part + static_cast<size_t>(kLinBlocks) * MFGP_MAX_D * t;
     float* tmp = reinterpret_cast<float*>(static_cast<char*>(sum_scratch) + align256(lin_doubles(t) * sizeof(double)));
@@ -241,6 +245,7 @@ hipError_t apply_sum(const Operator& cols, const Operator* rows, int64_t m, cons
 
 hipError_t residual_sum(const Operator& op, const float* B, const double* X64, int t, double* R, double* scratch,
                         void* sum_scratch, hipStream_t s) {
+    if (op.ski) return ski_residual(*op.ski, op.X, op.n, B, X64, t, op.sig2, R, s);
     double* part = static_cast<double*>(sum_scratch);
     double* xtv = part + static_cast<size_t>(kLinBlocks) * MFGP_MAX_D * t;
     bool first = true;

@@ -141,6 +141,15 @@ def rbf500k(n: int = 500000, probes: int = 16) -> Workload:
     return w
 
 
+def ski200k(n: int = 200000, d: int = 1) -> Workload:
+    """N = 200000 points for the structured-interpolation path (the paper's SKI
+    scale, D = 1): uniform on [0, 1]^d, a smooth signal plus noise, RBF."""
+    rng = np.random.default_rng(106)
+    X = rng.uniform(0.0, 1.0, size=(n, d))
+    y = np.sin(8 * np.pi * X).sum(axis=1) + 0.1 * rng.standard_normal(n)
+    return Workload(f"ski200k_d{d}", X.astype(np.float32), y.astype(np.float32), "rbf", 0.05, 1.0, 0.01)
+
+
 def random_problem(seed: int, n: int, d: int, family: str = "rbf", ard: bool = False,
                    dist: str = "uniform", lengthscale=None, outputscale: float = 1.3,
                    noise: float = 0.05) -> Workload:

@@ -61,6 +61,10 @@ class BatchT(C.Structure):
                 ("kern", C.POINTER(KernelT))]
 
 
+class SkiGridT(C.Structure):
+    _fields_ = [("m", C.c_int32 * 3), ("explicit_range", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(
@@ -97,6 +101,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_precond_apply": (C.c_int, [P, I64, I32, C.c_float, P, I32, P, P, P, SZ, P]),
         "mfgp_precond_cg_solve": (C.c_int, [KP, P, I64, P, I32, P, P, I32, OP_, IP, P, P, SZ, P]),
         "mfgp_precond_mll_and_grad": (C.c_int, [KP, P, I64, P, I32, P, P, I32, OP_, P, P, P, P, IP, P, SZ, P]),
+        "mfgp_ski_workspace_bytes": (SZ, [I32, I64, I32, I32, C.POINTER(SkiGridT)]),
+        "mfgp_ski_matvec": (C.c_int, [KP, P, I64, C.POINTER(SkiGridT), P, I32, P, P, SZ, P]),
+        "mfgp_ski_cg_solve": (C.c_int, [KP, P, I64, C.POINTER(SkiGridT), P, I32, P, OP_, IP, P, SZ, P]),
+        "mfgp_ski_predict_mean": (C.c_int, [KP, P, I64, P, I64, C.POINTER(SkiGridT), P, I32, P, P, SZ, P]),
         "mfgp_status_string": (C.c_char_p, [C.c_int]),
         "mfgp_last_hip_error": (C.c_int, []),
         "mfgp_version": (C.c_int, []),
@@ -484,6 +492,70 @@ def rademacher(seed: int, n: int, p: int, device="cuda") -> torch.Tensor:
     Z = torch.empty((n, p), dtype=torch.float32, device=device)
     _check(LIB.mfgp_rademacher(seed, n, p, _ptr(Z), _stream()), "rademacher")
     return Z
+
+
+# ---------------------------------------------------------------- structured kernel interpolation
+
+def ski_grid(m, lo=None, hi=None) -> SkiGridT:
+    """Grid of m[k] nodes per dimension over the points' range, or over [lo, hi]."""
+    g = SkiGridT()
+    for k, v in enumerate(m):
+        g.m[k] = int(v)
+    if lo is not None:
+        g.explicit_range = 1
+        for k in range(len(m)):
+            g.lo[k] = float(lo[k])
+            g.hi[k] = float(hi[k])
+    return g
+
+
+def ski_matvec(kern: Kernel, X: torch.Tensor, V: torch.Tensor, grid: SkiGridT,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """(W K_UU W^T + sigma^2 I) V by structured kernel interpolation."""
+    _dev(X, torch.float32, "X")
+    _dev(V, torch.float32, "V")
+    n, d = X.shape
+    t = _cols(V)
+    out = torch.empty_like(V) if out is None else _dev(out, torch.float32, "out")
+    ws = workspace(LIB.mfgp_ski_workspace_bytes(OP_MATVEC, n, d, t, C.byref(grid)), X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_ski_matvec(C.byref(ks), _ptr(X), n, C.byref(grid), _ptr(V), t, _ptr(out), _ptr(ws),
+                               ws.numel(), _stream()), "ski_matvec")
+    return out
+
+
+def ski_cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, grid: SkiGridT, tol: float = 1e-6,
+                 max_iter: int = 0, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+    """CG on the SKI operator.  Returns (Xsol float64, info list, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(B, torch.float32, "B")
+    n, d = X.shape
+    t = _cols(B)
+    o = cg_opts(tol, max_iter)
+    Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device)
+    info = (CgInfoT * t)()
+    ws = workspace(LIB.mfgp_ski_workspace_bytes(OP_CG, n, d, t, C.byref(grid)), X.device)
+    ks = kern.struct(d)
+    st = LIB.mfgp_ski_cg_solve(C.byref(ks), _ptr(X), n, C.byref(grid), _ptr(B), t, _ptr(Xsol), C.byref(o), info,
+                               _ptr(ws), ws.numel(), _stream())
+    _check(st, "ski_cg_solve", allow)
+    return Xsol, _info_list(info, t), st
+
+
+def ski_predict_mean(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, A: torch.Tensor, grid: SkiGridT) -> torch.Tensor:
+    """W_* K_UU W^T A (the SKI predictive mean)."""
+    _dev(X, torch.float32, "X")
+    _dev(Xs, torch.float32, "Xs")
+    _dev(A, torch.float32, "A")
+    n, d = X.shape
+    m = Xs.shape[0]
+    t = _cols(A)
+    mu = torch.empty((m,) if A.dim() == 1 else (m, t), dtype=torch.float32, device=X.device)
+    ws = workspace(LIB.mfgp_ski_workspace_bytes(OP_PREDICT, n, d, t, C.byref(grid)), X.device)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_ski_predict_mean(C.byref(ks), _ptr(X), n, _ptr(Xs), m, C.byref(grid), _ptr(A), t, _ptr(mu),
+                                     _ptr(ws), ws.numel(), _stream()), "ski_predict_mean")
+    return mu
 
 
 # ---------------------------------------------------------------- preconditioning

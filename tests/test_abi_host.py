@@ -129,6 +129,32 @@ def test_product_params_and_checks(m):
         == m.ERR_WORKSPACE
 
 
+def test_ski_checks_before_launch(m):
+    dummy = C.c_void_p(16)
+    L = m.LIB
+    g = m.ski_grid([64, 32])
+
+    def matvec(k, grid, d=2, ws=16):
+        return L.mfgp_ski_matvec(C.byref(k.struct(d)), dummy, 10, C.byref(grid), dummy, 1, C.c_void_p(32), dummy,
+                                 ws, None)
+
+    rbf = m.Kernel("rbf", 0.3, 1.0, 0.1)
+    assert matvec(rbf, g) == m.ERR_WORKSPACE
+    assert matvec(m.Kernel("periodic", 0.3, period=0.5), g) == m.ERR_WORKSPACE
+    assert matvec(rbf + rbf, g) == m.UNSUPPORTED
+    assert matvec(m.Kernel("linear", 1.0), g) == m.UNSUPPORTED
+    assert matvec(rbf, m.ski_grid([64, 32, 8]), d=4) == m.UNSUPPORTED          # d > 3
+    assert matvec(rbf, m.ski_grid([64, 4])) == m.ERR_ARG                        # m_k < 5
+    assert matvec(rbf, m.ski_grid([64, 32], lo=[0.0, 1.0], hi=[1.0, 0.5])) == m.ERR_ARG   # hi < lo
+    assert matvec(rbf, m.ski_grid([40000, 40000])) == m.UNSUPPORTED             # 2^31 embedded nodes
+    assert L.mfgp_ski_matvec(C.byref(rbf.struct(2)), dummy, 10, None, dummy, 1, C.c_void_p(32), dummy, 16,
+                             None) == m.ERR_ARG
+    a = L.mfgp_ski_workspace_bytes(m.OP_CG, 10000, 1, 3, C.byref(m.ski_grid([1000])))
+    b = L.mfgp_ski_workspace_bytes(m.OP_CG, 100000, 1, 3, C.byref(m.ski_grid([1000])))
+    assert 0 < a < b < 11 * a
+    assert L.mfgp_ski_workspace_bytes(m.OP_ADJOINT, 100, 1, 3, C.byref(m.ski_grid([100]))) == 0
+
+
 def test_workspace_sizes(m):
     for op in range(6):
         t = 2 if op != m.OP_PREDICT else 3

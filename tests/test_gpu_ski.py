@@ -1,0 +1,132 @@
+"""Structured kernel interpolation on the HIP path against the FP64 oracle
+(oracle/ski.py: dense W K_UU W^T on the same grid).
+
+The HIP products are FP64 throughout (FFT of the circulant embedding, atomic
+scatter, gather) and rounded once to FP32, so the bar for a product is a
+per-column relative error of 1e-6 (FP32 output rounding plus the atomic
+order); solves are checked by the oracle's dense FP64 residual of the
+returned solution (<= 2e-6 for a 1e-6 target) and means against the oracle
+applied to the same coefficients.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import gp, ski
+from tests.gpu_util import banner, col_rel_err, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_2605_17898_amd import mfgp
+    return mfgp
+
+
+def kerns(mf, family, d, noise=0.1):
+    ls = [0.15, 0.3, 0.45][:d]
+    if family == "periodic":
+        return gp.Kern("periodic", np.array(ls) * 3, 1.2, noise, period=0.6), \
+            mf.Kernel("periodic", [v * 3 for v in ls], 1.2, noise, period=0.6)
+    return gp.Kern(family, np.array(ls), 1.2, noise), mf.Kernel(family, ls, 1.2, noise)
+
+
+CASES = [(1, [300], 3000), (2, [40, 32], 1500), (3, [14, 12, 10], 700)]
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern32", "periodic"])
+@pytest.mark.parametrize("d,m,n", CASES)
+def test_ski_matvec_vs_oracle(mf, family, d, m, n):
+    banner(f"ski matvec {family} d={d} m={m} n={n} t=5")
+    rng = np.random.default_rng(1300 + d)
+    X = rng.uniform(-1.0, 2.0, (n, d)).astype(np.float32)
+    V = rng.standard_normal((n, 5)).astype(np.float32)
+    o, k = kerns(mf, family, d)
+    out = mf.ski_matvec(k, dev(X), dev(V), mf.ski_grid(m))
+    lo, h = ski.grid([X], m)
+    ref = ski.ski_matvec(o, X, V, lo, h, m)
+    err = col_rel_err(host(out), ref).max()
+    print(f"max per-column relative error {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_ski_explicit_range_and_t1(mf):
+    banner("ski matvec explicit range, t=1, points at the range ends, d=1")
+    X = np.concatenate([[[0.0], [1.0]], np.random.default_rng(1310).uniform(0, 1, (997, 1))]).astype(np.float32)
+    V = np.random.default_rng(1311).standard_normal(999).astype(np.float32)
+    o, k = kerns(mf, "rbf", 1)
+    g = mf.ski_grid([128], lo=[-0.25], hi=[1.5])
+    out = mf.ski_matvec(k, dev(X), dev(V), g)
+    lo, h = ski.grid([np.array([[-0.25], [1.5]])], [128])
+    ref = ski.ski_matvec(o, X, V, lo, h, [128])
+    assert np.linalg.norm(host(out) - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+def test_ski_approximates_exact_kernel(mf):
+    # a fine grid: the SKI product approaches the exact K_y V (cubic interpolation)
+    banner("ski vs exact K_y V, d=1 n=4000 m=2000")
+    rng = np.random.default_rng(1320)
+    X = rng.uniform(0, 1, (4000, 1)).astype(np.float32)
+    V = rng.standard_normal((4000, 2)).astype(np.float32)
+    o, k = kerns(mf, "rbf", 1)
+    out = mf.ski_matvec(k, dev(X), dev(V), mf.ski_grid([2000]))
+    ref = gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64))
+    err = col_rel_err(host(out), ref).max()
+    print(f"SKI vs exact: {err:.2e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("d,m,n", [(1, [256], 2500), (2, [36, 30], 1200)])
+def test_ski_cg_and_predict(mf, d, m, n):
+    banner(f"ski CG + predictive mean d={d} m={m} n={n}")
+    rng = np.random.default_rng(1330 + d)
+    X = rng.uniform(-1.0, 2.0, (n, d)).astype(np.float32)
+    Xs = rng.uniform(-1.0, 2.0, (211, d)).astype(np.float32)
+    y = (np.sin(3 * X).sum(axis=1) + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    B = np.stack([y, rng.standard_normal(n).astype(np.float32)], axis=1)
+    o, k = kerns(mf, "matern52", d, noise=0.05)
+    lo_r, hi_r = np.minimum(X.min(0), Xs.min(0)), np.maximum(X.max(0), Xs.max(0))
+    g = mf.ski_grid(m, lo=lo_r, hi=hi_r)
+    x, info, st = mf.ski_cg_solve(k, dev(X), dev(B), g, tol=1e-6)
+    assert st == mf.OK, info
+    lo, h = ski.grid([np.stack([lo_r, hi_r])], m)
+    xh = host(x)
+    A = ski.ski_matrix(o, X, X, lo, h, m)
+    A[np.diag_indices_from(A)] += o.noise
+    res = np.linalg.norm(B - A @ xh, axis=0) / np.linalg.norm(B, axis=0)
+    print("oracle residual of the SKI solution", res)
+    assert res.max() <= 2e-6
+    mu = mf.ski_predict_mean(k, dev(X), dev(Xs), x.float(), g)
+    ref = ski.ski_matrix(o, Xs, X, lo, h, m) @ host(x.float()).astype(np.float64)
+    assert col_rel_err(host(mu), ref).max() <= 1e-6
+
+
+def test_ski_predict_auto_grid_covers_test_points(mf):
+    banner("ski predictive mean, grid from X and Xs together, d=2")
+    rng = np.random.default_rng(1340)
+    X = rng.uniform(0, 1, (900, 2)).astype(np.float32)
+    Xs = rng.uniform(-0.5, 1.5, (150, 2)).astype(np.float32)
+    A = rng.standard_normal(900).astype(np.float32)
+    o, k = kerns(mf, "rbf", 2)
+    mu = mf.ski_predict_mean(k, dev(X), dev(Xs), dev(A), mf.ski_grid([40, 40]))
+    lo, h = ski.grid([X, Xs], [40, 40])
+    ref = ski.ski_matrix(o, Xs, X, lo, h, [40, 40]) @ A.astype(np.float64)
+    assert np.linalg.norm(host(mu) - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+def test_ski_degenerate_inputs(mf):
+    # one point; all points equal (zero range: spacing 1 / (m - 4))
+    banner("ski degenerate: n=1, identical points")
+    o, k = kerns(mf, "rbf", 1)
+    X1 = np.array([[0.3]], np.float32)
+    V1 = np.array([2.0], np.float32)
+    out = host(mf.ski_matvec(k, dev(X1), dev(V1), mf.ski_grid([8])))
+    lo, h = ski.grid([X1], [8])
+    np.testing.assert_allclose(out, ski.ski_matvec(o, X1, V1, lo, h, [8]), rtol=1e-6)
+    Xe = np.full((50, 1), 0.7, np.float32)
+    Ve = np.random.default_rng(1350).standard_normal(50).astype(np.float32)
+    out = host(mf.ski_matvec(k, dev(Xe), dev(Ve), mf.ski_grid([9])))
+    lo, h = ski.grid([Xe], [9])
+    ref = ski.ski_matvec(o, Xe, Ve, lo, h, [9])
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= 1e-6
