@@ -96,3 +96,50 @@ def ski_solve(kern: gp.Kern, X, B, lo, h, m) -> np.ndarray:
     A = ski_matrix(kern, X, X, lo, h, m)
     A[np.diag_indices_from(A)] += kern.noise
     return np.linalg.solve(A, np.asarray(B, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Log marginal likelihood of the SKI model and its gradient (Sec. 2, the
+# log p(y|X) formula, with K_ff replaced by W K_UU W^T on a fixed grid)
+# --------------------------------------------------------------------------
+
+def ski_ky(kern: gp.Kern, X, lo, h, m) -> np.ndarray:
+    A = ski_matrix(kern, X, X, lo, h, m)
+    A[np.diag_indices_from(A)] += kern.noise
+    return A
+
+
+def ski_mll(kern: gp.Kern, X, y, lo, h, m) -> float:
+    """-1/2 [y^T A^{-1} y + log|A| + N log 2 pi], A = W K_UU W^T + sigma^2 I."""
+    y = np.asarray(y, dtype=np.float64)
+    L = np.linalg.cholesky(ski_ky(kern, X, lo, h, m))
+    a = np.linalg.solve(L.T, np.linalg.solve(L, y))
+    return -0.5 * (float(y @ a) + 2.0 * float(np.sum(np.log(np.diag(L)))) + len(y) * np.log(2.0 * np.pi))
+
+
+def ski_dky(kern: gp.Kern, X, lo, h, m):
+    """dA/dtheta in the kernel's gradient order: W (dK_UU/dtheta) W^T, then I."""
+    W = interp_matrix(X, lo, h, m)
+    U = grid_points(lo, h, m)
+    mats = [W @ M @ W.T for M in gp.dky_matrices(kern, U)[:-1]]
+    mats.append(np.eye(W.shape[0]))
+    return mats
+
+
+def ski_mll_grad(kern: gp.Kern, X, y, lo, h, m) -> np.ndarray:
+    """Exact gradient: 1/2 a^T dA a - 1/2 tr(A^{-1} dA)."""
+    A = ski_ky(kern, X, lo, h, m)
+    a = np.linalg.solve(A, np.asarray(y, dtype=np.float64))
+    Ainv = np.linalg.inv(A)
+    return np.array([0.5 * float(a @ M @ a) - 0.5 * float(np.sum(Ainv * M)) for M in ski_dky(kern, X, lo, h, m)])
+
+
+def ski_same_probe_grad(kern: gp.Kern, X, y, Z, lo, h, m) -> np.ndarray:
+    """1/2 a^T dA a - 1/2 (1/p) sum_c u_c^T dA z_c with u_c = A^{-1} z_c (exact solves)."""
+    A = ski_ky(kern, X, lo, h, m)
+    Z = np.asarray(Z, dtype=np.float64)
+    a = np.linalg.solve(A, np.asarray(y, dtype=np.float64))
+    U = np.linalg.solve(A, Z)
+    p = Z.shape[1]
+    return np.array([0.5 * float(a @ M @ a) - 0.5 / p * float(np.sum(U * (M @ Z)))
+                     for M in ski_dky(kern, X, lo, h, m)])

@@ -72,3 +72,37 @@ def test_ski_error_falls_cubically(family):
         errs.append(np.abs(ski.ski_matrix(k, X, X, lo, h, [m]) - K).max())
     # h halves (about) at each step: an O(h^3) scheme gains about 8x
     assert errs[1] < errs[0] / 5 and errs[2] < errs[1] / 5
+
+
+@pytest.mark.parametrize("family,ard", [("rbf", True), ("matern32", False), ("matern52", True),
+                                        ("matern12", False), ("periodic", True)])
+def test_ski_mll_gradient_central_differences(family, ard):
+    # the grid is fixed by the data, so the SKI MLL is a smooth function of theta
+    rng = np.random.default_rng(11)
+    X = rng.uniform(0.0, 1.0, (45, 2))
+    y = np.sin(4 * X[:, 0]) + 0.1 * rng.standard_normal(45)
+    ls = np.array([0.3, 0.5]) if ard else 0.4
+    k = gp.Kern(family, ls, 1.1, 0.05, period=0.7)
+    lo, h = ski.grid([X], [14, 12])
+    g = ski.ski_mll_grad(k, X, y, lo, h, [14, 12])
+    th = k.params(2)
+    for q in range(len(th)):
+        e = 1e-6 * th[q]
+        tp, tm = th.copy(), th.copy()
+        tp[q] += e
+        tm[q] -= e
+        fd = (ski.ski_mll(k.with_params(tp), X, y, lo, h, [14, 12])
+              - ski.ski_mll(k.with_params(tm), X, y, lo, h, [14, 12])) / (2 * e)
+        assert g[q] == pytest.approx(fd, rel=1e-5, abs=1e-7 * np.abs(g).max())
+
+
+def test_ski_same_probe_grad_exact_mode_is_exact():
+    # probes sqrt(N) e_c make the Hutchinson trace exact
+    rng = np.random.default_rng(12)
+    X = rng.uniform(0.0, 1.0, (30, 1))
+    y = rng.standard_normal(30)
+    k = gp.Kern("rbf", 0.2, 1.0, 0.1)
+    lo, h = ski.grid([X], [40])
+    Z = np.sqrt(30) * np.eye(30)
+    np.testing.assert_allclose(ski.ski_same_probe_grad(k, X, y, Z, lo, h, [40]),
+                               ski.ski_mll_grad(k, X, y, lo, h, [40]), rtol=1e-9)
