@@ -316,7 +316,8 @@ typedef struct {
 } mfgp_ski_grid;
 
 /* Bytes of workspace of a SKI call: op MFGP_OP_MATVEC / MFGP_OP_CG /
- * MFGP_OP_PREDICT, n points, d dims, t columns, the grid (host); 0 if invalid. */
+ * MFGP_OP_PREDICT / MFGP_OP_MLL (t = probes + 1), n points, d dims, t
+ * columns, the grid (host); 0 if invalid. */
 size_t mfgp_ski_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, const mfgp_ski_grid* grid);
 
 /* KV = W K_UU W^T V + sigma^2 V on the grid of X (or the explicit range).
@@ -337,6 +338,18 @@ int mfgp_ski_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const 
 int mfgp_ski_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, const float* Xs, int64_t m,
                           const mfgp_ski_grid* grid, const float* A, int32_t t, float* MU, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* Log marginal likelihood of the SKI model and its gradient: as
+ * mfgp_mll_and_grad with K_ff replaced by W K_UU W^T on the grid (CG on the
+ * SKI operator, stochastic Lanczos log-determinant over the probes, the
+ * gradient 1/2 a^T dK a - 1/(2p) sum_c u_c^T dK z_c with dK = W (dK_UU) W^T:
+ * one spectral product of W^T [a, Z] per parameter).  num_probes + 1 <=
+ * MFGP_MAX_T; opts->max_iter must be 0 (the default cap, which the workspace
+ * query MFGP_OP_MLL with t = num_probes + 1 assumes).  Synchronises. */
+int mfgp_ski_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                          const float* y, int32_t num_probes, const float* Z, const mfgp_cg_opts* opts, double* mll,
+                          double* logdet, double* grad, mfgp_cg_info* info, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent GP problems solved together (LightGP Sec. 5 names batched

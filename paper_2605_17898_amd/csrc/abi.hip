@@ -542,6 +542,58 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
     return MFGP_OK;
 }
 
+}  // extern "C"
+
+// log|K_y| ~ (1/p) sum over the probe columns c = 1 .. t-1 of ||z_c||^2
+// e_1^T log(T_c) e_1 (stochastic Lanczos quadrature, Sec. 3 "Inference"),
+// T_c from the CG coefficients in coeff [t][max_iter][2] (device); bnorm2
+// (host, [t]) holds ||z_c||^2.  The quadratures run in parallel host threads.
+// *slq_status is MFGP_BREAKDOWN if a probe's quadrature failed.
+static hipError_t probe_logdet(const std::vector<mfgp_cg_info>& inf, const double* coeff, int max_iter,
+                               const double* bnorm2, int t, double* ld, int* slq_status, hipStream_t s) {
+    const int p = t - 1;
+    std::vector<std::vector<double>> cf(t);
+    for (int c = 1; c < t; ++c) {
+        cf[c].resize(2 * static_cast<size_t>(inf[c].lanczos_len > 0 ? inf[c].lanczos_len : 1));
+        if (inf[c].lanczos_len > 0) {
+            hipError_t e = hipMemcpyAsync(cf[c].data(), coeff + static_cast<size_t>(c) * max_iter * 2,
+                                          2 * inf[c].lanczos_len * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::vector<double> q(t, 0.0);
+    std::vector<int> qs(t, MFGP_OK);
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
+        std::vector<std::thread> pool;
+        for (int th = 0; th < nth; ++th) {
+            pool.emplace_back([&, th]() {
+                for (int c = 1 + th; c < t; c += nth) {
+                    if (inf[c].lanczos_len < 1) {
+                        qs[c] = MFGP_BREAKDOWN;
+                        continue;
+                    }
+                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, bnorm2[c], &q[c]);
+                }
+            });
+        }
+        for (auto& th : pool) th.join();
+    }
+    double sum = 0.0;
+    *slq_status = MFGP_OK;
+    for (int c = 1; c < t; ++c) {
+        sum += q[c];
+        if (qs[c] != MFGP_OK) *slq_status = MFGP_BREAKDOWN;
+    }
+    *ld = sum / p;
+    return hipSuccess;
+}
+
+extern "C" {
+
 int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const float* y,
                       int32_t num_probes, const float* Z, const mfgp_cg_opts* opts, double* mll,
                       double* logdet, double* grad, double* alpha_out, mfgp_cg_info* info,
@@ -595,47 +647,13 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     ABI_CHECK(col_dots_dd(w.X64, w.X64, n, t, xx, w.b.dots, s));
     std::vector<double> h(3 * t);
     ABI_CHECK(hipMemcpyAsync(h.data(), w.tmp, 3 * t * sizeof(double), hipMemcpyDeviceToHost, s));
-    // Lanczos coefficients of the probe columns.
-    std::vector<std::vector<double>> cf(t);
-    for (int c = 1; c < t; ++c) {
-        cf[c].resize(2 * static_cast<size_t>(inf[c].lanczos_len > 0 ? inf[c].lanczos_len : 1));
-        if (inf[c].lanczos_len > 0)
-            ABI_CHECK(hipMemcpyAsync(cf[c].data(), w.coeff + static_cast<size_t>(c) * max_iter * 2,
-                                     2 * inf[c].lanczos_len * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
     if (alpha_out) {
         hipLaunchKernelGGL(copy_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, alpha_out, n, t);
         ABI_CHECK(hipGetLastError());
     }
-    ABI_CHECK(hipStreamSynchronize(s));
-
-    // Stochastic Lanczos quadrature per probe, in parallel host threads.
-    std::vector<double> q(t, 0.0);
-    std::vector<int> qs(t, MFGP_OK);
-    {
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
-        std::vector<std::thread> pool;
-        for (int th = 0; th < nth; ++th) {
-            pool.emplace_back([&, th]() {
-                for (int c = 1 + th; c < t; c += nth) {
-                    if (inf[c].lanczos_len < 1) {
-                        qs[c] = MFGP_BREAKDOWN;
-                        continue;
-                    }
-                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, h[c], &q[c]);
-                }
-            });
-        }
-        for (auto& th : pool) th.join();
-    }
     double ld = 0.0;
     int slq_status = MFGP_OK;
-    for (int c = 1; c < t; ++c) {
-        ld += q[c];
-        if (qs[c] != MFGP_OK) slq_status = MFGP_BREAKDOWN;
-    }
-    ld /= p;
+    ABI_CHECK(probe_logdet(inf, w.coeff, max_iter, h.data(), t, &ld, &slq_status, s));
     timing_phase(1, ms_since(t0));
     t0 = clock::now();
     const double two_pi = 6.283185307179586477;
@@ -681,11 +699,32 @@ static int check_ski(const mfgp_kernel* kern, const mfgp_ski_grid* grid, bool ne
     return MFGP_OK;
 }
 
+struct SkiMllWs { void* sk; void* gs; CgBufs b; float* Bm; double* X64; float* Zgen; double* coeff; double* tmp; };
+static SkiMllWs carve_ski_mll(Carver& cv, int64_t n, int d, const int32_t* m, int t, int max_iter) {
+    SkiMllWs w;
+    const size_t nt = static_cast<size_t>(n) * t;
+    w.sk = cv.take<char>(ski_scratch_bytes(d, m, t));
+    w.gs = cv.take<char>(ski_grad_scratch_bytes(d, m, t));
+    w.b = carve_cg_vectors(cv, n, t);
+    w.Bm = cv.take<float>(nt);
+    w.X64 = cv.take<double>(nt);
+    w.Zgen = cv.take<float>(static_cast<size_t>(n) * (t - 1));
+    w.coeff = cv.take<double>(static_cast<size_t>(t) * max_iter * 2);
+    w.tmp = cv.take<double>(4 * static_cast<size_t>(t) + 8);
+    return w;
+}
+
 size_t mfgp_ski_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, const mfgp_ski_grid* grid) {
     if (n < 1 || d < 1 || d > 3 || t < 1 || !grid) return 0;
     for (int k = 0; k < d; ++k)
         if (grid->m[k] < 5) return 0;
     Carver cv(nullptr);
+    if (op == MFGP_OP_MLL) {
+        // t = probes + 1; the CG iteration cap as mfgp_ski_mll_and_grad takes it (default)
+        if (t < 2) return 0;
+        carve_ski_mll(cv, n, d, grid->m, t, default_max_iter(n, 0));
+        return cv.off + 256;
+    }
     cv.take<char>(ski_scratch_bytes(d, grid->m, t));
     if (op == MFGP_OP_CG)
         carve_cg_vectors(cv, n, t);
@@ -755,6 +794,81 @@ int mfgp_ski_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, co
                         sk_scratch, s));
     ABI_CHECK(ski_apply(sk, X, n, Xs, m, A, t, MU, false, 0.0f, nullptr, s));
     return MFGP_OK;
+}
+
+int mfgp_ski_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const mfgp_ski_grid* grid,
+                          const float* y, int32_t num_probes, const float* Z, const mfgp_cg_opts* opts, double* mll,
+                          double* logdet, double* grad, mfgp_cg_info* info, void* ws, size_t ws_bytes,
+                          void* stream) {
+    int st = check_ski(kern, grid, true);
+    if (st != MFGP_OK) return st;
+    if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if (!X || !y || !mll || !ws || n < 1 || num_probes < 1 || num_probes + 1 > MFGP_MAX_T) return MFGP_ERR_ARG;
+    if (opts->max_iter != 0) return MFGP_ERR_ARG;   // the workspace query assumes the default cap
+    const int p = num_probes;
+    const int t = p + 1;
+    const int max_iter = default_max_iter(n, 0);
+    if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_MLL, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    SkiMllWs w = carve_ski_mll(cv, n, kern->d, grid->m, t, max_iter);
+    SkiOp sk;
+    const bool ex = grid->explicit_range != 0;
+    ABI_CHECK(ski_setup(sk, *kern, X, n, nullptr, 0, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
+                        w.sk, s));
+    Operator op;
+    op.family = kern->family;
+    op.d = op.din = kern->d;
+    op.n = n;
+    op.s2 = kern->outputscale;
+    op.sig2 = kern->noise;
+    op.X = X;
+    op.ski = &sk;
+    const float* Zp = Z;
+    if (!Zp) {
+        ABI_CHECK(launch_rademacher(opts->probe_seed, n, p, w.Zgen, s));
+        Zp = w.Zgen;
+    }
+    hipLaunchKernelGGL(pack_yz_kernel, dim3(nb(n * t)), dim3(256), 0, s, y, Zp, n, p, w.Bm);
+    ABI_CHECK(hipGetLastError());
+    std::vector<mfgp_cg_info> inf(t);
+    mfgp_cg_opts o = *opts;
+    o.warm_start = 0;
+    const int cg_status = cg_run(op, w.Bm, t, w.X64, o, inf.data(), w.coeff, max_iter, w.b, s);
+    if (cg_status == MFGP_ERR_HIP || cg_status == MFGP_ERR_ARG) return cg_status;
+    if (info) std::memcpy(info, inf.data(), t * sizeof(mfgp_cg_info));
+    // b_c^T b_c, x_c^T b_c, x_c^T x_c in FP64
+    double* bb = w.tmp;
+    double* xb = w.tmp + t;
+    double* xx = w.tmp + 2 * t;
+    ABI_CHECK(col_dots_ff(w.Bm, w.Bm, n, t, bb, w.b.dots, s));
+    ABI_CHECK(col_dots_df(w.X64, w.Bm, n, t, xb, w.b.dots, s));
+    ABI_CHECK(col_dots_dd(w.X64, w.X64, n, t, xx, w.b.dots, s));
+    std::vector<double> h(3 * t);
+    ABI_CHECK(hipMemcpyAsync(h.data(), w.tmp, 3 * t * sizeof(double), hipMemcpyDeviceToHost, s));
+    double ld = 0.0;
+    int slq_status = MFGP_OK;
+    ABI_CHECK(probe_logdet(inf, w.coeff, max_iter, h.data(), t, &ld, &slq_status, s));
+    const double two_pi = 6.283185307179586477;
+    *mll = -0.5 * (h[t + 0] + ld + static_cast<double>(n) * std::log(two_pi));
+    if (logdet) *logdet = ld;
+    if (grad) {
+        // A = fl32([alpha, U]), B = [fl32(alpha), Z]; the CG vectors are free now
+        float* Ag = w.b.R;
+        float* Bg = w.b.P;
+        ABI_CHECK(f64_to_f32(w.X64, Ag, n * t, s));
+        ABI_CHECK(copy2_f32(w.Bm, Bg, Bg, n * t, s));
+        hipLaunchKernelGGL(set_col0_kernel, dim3(nb(n)), dim3(256), 0, s, w.X64, Bg, n, t);
+        ABI_CHECK(hipGetLastError());
+        std::vector<double> colw(t, -0.5 / p);
+        colw[0] = 0.5;
+        ABI_CHECK(ski_gradient(sk, *kern, X, n, Ag, Bg, t, colw.data(), grad, w.gs, s));
+        double tr = 0.0;
+        for (int c = 1; c < t; ++c) tr += h[t + c];
+        grad[noise_index(kern)] = 0.5 * h[2 * t + 0] - 0.5 * tr / p;
+    }
+    if (cg_status != MFGP_OK) return cg_status;
+    return slq_status;
 }
 
 // ---------------------------------------------------------------- preconditioned solves

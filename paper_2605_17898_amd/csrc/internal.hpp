@@ -38,6 +38,12 @@ hipError_t ski_apply(const SkiOp& op, const float* Xc, int64_t nc, const float* 
                      float* out, bool with_noise, float sig2, const float* Vself, hipStream_t s);
 hipError_t ski_residual(const SkiOp& op, const float* X, int64_t n, const float* B, const double* X64, int t,
                         float sig2, double* R, hipStream_t s);
+// Scratch of ski_gradient (beside the SkiOp's own buffers for t columns).
+size_t ski_grad_scratch_bytes(int d, const int32_t* m, int t);
+// grad[j] = sum_c colw_c (W^T A_c)^T (dK_UU/dtheta_j) (W^T B_c), the kernel's
+// parameters without sigma^2 in gradient order.  Synchronises.
+hipError_t ski_gradient(const SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n, const float* A,
+                        const float* B, int t, const double* colw, double* grad, void* gscratch, hipStream_t s);
 
 // A linear term (linear = 1) keeps the raw inputs in U (d = din, factors 1).
 // Terms of a kernel sum are linked through next (see OpChain).  A product

@@ -25,6 +25,7 @@
 #include <cmath>
 #include <map>
 #include <tuple>
+#include <vector>
 
 namespace mfgp {
 
@@ -159,6 +160,99 @@ __global__ void ski_column_kernel(SkiGeom g, const double* __restrict__ geo, KPa
         default: v = exp(-sp); break;
     }
     c[q] = kp.s2 * v;
+}
+
+// d c / d theta at the wrapped offsets for parameter `which` of the kernel's
+// gradient order without sigma^2: the lengthscales (one per dimension when
+// ard, else one shared), the period (periodic family), s2.  With u_k = D_k / l_k:
+//   RBF         d/dl_k = s2 exp(-r^2/2) u_k^2 / l_k
+//   Matern-1/2  d/dl_k = s2 exp(-r) u_k^2 / (r l_k)          (0 at r = 0)
+//   Matern-3/2  d/dl_k = s2 3 exp(-sqrt3 r) u_k^2 / l_k
+//   Matern-5/2  d/dl_k = s2 (5/3) (1 + sqrt5 r) exp(-sqrt5 r) u_k^2 / l_k
+//   Periodic    d/dl_k = s2 exp(-S) 4 sin^2(pi D_k / p) / l_k^3,
+//               d/dp   = s2 exp(-S) sum_k 2 pi D_k sin(2 pi D_k / p) / (p^2 l_k^2)
+//   d/ds2 = the unit-scale kernel.
+__global__ void ski_dcolumn_kernel(SkiGeom g, const double* __restrict__ geo, KParams kp, int ard, int which,
+                                   double* __restrict__ c) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= g.Lr) return;
+    const double pi = 3.14159265358979323846;
+    int64_t rest = q;
+    double delta[3] = {0, 0, 0}, u2[3] = {0, 0, 0};
+    double r2 = 0.0, sp = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const int j = static_cast<int>(rest % g.L[k]);
+        rest /= g.L[k];
+        if (k >= g.d) continue;
+        int o;
+        if (j < g.m[k]) {
+            o = j;
+        } else if (j == g.m[k]) {
+            c[q] = 0.0;
+            return;
+        } else {
+            o = g.L[k] - j;
+        }
+        delta[k] = o * geo[3 + k];
+        const double u = delta[k] * kp.inv_l[k];
+        u2[k] = u * u;
+        r2 += u2[k];
+        if (kp.family == MFGP_PERIODIC) {
+            const double sn = sin(pi * delta[k] / kp.period) * kp.inv_l[k];
+            sp += 2.0 * sn * sn;
+        }
+    }
+    const double r = sqrt(r2);
+    const int nl = ard ? g.d : 1;
+    double v = 0.0;
+    if (which < nl) {
+        for (int k = 0; k < g.d; ++k) {
+            if (ard && k != which) continue;
+            double f;
+            switch (kp.family) {
+                case MFGP_RBF: f = exp(-0.5 * r2) * u2[k]; break;
+                case MFGP_MATERN12: f = r > 0.0 ? exp(-r) * u2[k] / r : 0.0; break;
+                case MFGP_MATERN32: f = 3.0 * exp(-sqrt(3.0) * r) * u2[k]; break;
+                case MFGP_MATERN52: f = (5.0 / 3.0) * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r) * u2[k]; break;
+                default: {
+                    const double sn = sin(pi * delta[k] / kp.period);
+                    f = exp(-sp) * 4.0 * sn * sn * kp.inv_l[k] * kp.inv_l[k];
+                }
+            }
+            v += f * kp.inv_l[k];
+        }
+        v *= kp.s2;
+    } else if (kp.family == MFGP_PERIODIC && which == nl) {
+        double a = 0.0;
+        for (int k = 0; k < g.d; ++k)
+            a += 2.0 * pi * delta[k] * sin(2.0 * pi * delta[k] / kp.period) * kp.inv_l[k] * kp.inv_l[k];
+        v = kp.s2 * exp(-sp) * a / (kp.period * kp.period);
+    } else {
+        switch (kp.family) {
+            case MFGP_RBF: v = exp(-0.5 * r2); break;
+            case MFGP_MATERN12: v = exp(-r); break;
+            case MFGP_MATERN32: v = (1.0 + sqrt(3.0) * r) * exp(-sqrt(3.0) * r); break;
+            case MFGP_MATERN52: v = (1.0 + sqrt(5.0) * r + 5.0 * r2 / 3.0) * exp(-sqrt(5.0) * r); break;
+            default: v = exp(-sp); break;
+        }
+    }
+    c[q] = v;
+}
+
+// out[c] = sum_q a[c][q] b[c][q] (FP64, one block per column, fixed order)
+__global__ void ski_dot_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t len,
+                               double* __restrict__ out) {
+    const int64_t off = static_cast<int64_t>(blockIdx.x) * len;
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < len; q += blockDim.x) acc = fma(a[off + q], b[off + q], acc);
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 __global__ void fill0_kernel(double* __restrict__ a, int64_t total) {
@@ -379,6 +473,78 @@ hipError_t ski_apply(const SkiOp& op, const float* Xc, int64_t nc, const float* 
 hipError_t ski_residual(const SkiOp& op, const float* X, int64_t n, const float* B, const double* X64, int t,
                         float sig2, double* R, hipStream_t s) {
     return ski_product<double>(op, X, n, X, n, X64, t, static_cast<double>(sig2), nullptr, nullptr, B, X64, R, s);
+}
+
+size_t ski_grad_scratch_bytes(int d, const int32_t* m, int t) {
+    const SkiGeom g = make_geom(d, m);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    return al(static_cast<size_t>(t) * g.Lr * sizeof(double)) +
+           al(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)) + al(g.Lc * sizeof(hipfftDoubleComplex)) +
+           al(static_cast<size_t>(t) * sizeof(double)) + 256;
+}
+
+// grad[j] = sum_c w_c (W^T A_c)^T (dK_UU / dtheta_j) (W^T B_c) for the
+// kernel's parameters without sigma^2 (W^T A in the product grid, W^T B
+// transformed once, one spectral product per parameter).
+hipError_t ski_gradient(const SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n, const float* A,
+                        const float* B, int t, const double* colw, double* grad, void* gscratch, hipStream_t s) {
+    if (t > op.t) return hipErrorInvalidValue;
+    const SkiGeom& g = op.g;
+    char* p = static_cast<char*>(gscratch);
+    auto take = [&](size_t b) {
+        char* r = p;
+        p += (b + 255) / 256 * 256;
+        return r;
+    };
+    double* grid2 = reinterpret_cast<double*>(take(static_cast<size_t>(t) * g.Lr * sizeof(double)));
+    auto* spec2 = reinterpret_cast<hipfftDoubleComplex*>(take(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)));
+    auto* lamj = reinterpret_cast<hipfftDoubleComplex*>(take(g.Lc * sizeof(hipfftDoubleComplex)));
+    double* dots = reinterpret_cast<double*>(take(static_cast<size_t>(t) * sizeof(double)));
+    auto* spec = static_cast<hipfftDoubleComplex*>(op.spec);
+    const int64_t tot = g.Lr * t;
+    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, op.grid, tot);
+    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, grid2, tot);
+    hipLaunchKernelGGL((ski_scatter_kernel<float>), dim3(nblk(n * t)), dim3(256), 0, s, X, n, g, op.geo, A, t, op.grid);
+    hipLaunchKernelGGL((ski_scatter_kernel<float>), dim3(nblk(n * t)), dim3(256), 0, s, X, n, g, op.geo, B, t, grid2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipfftHandle fwd = fft_plan(g, t, true, e);
+    if (!fwd) return e;
+    hipfftHandle inv = fft_plan(g, t, false, e);
+    if (!inv) return e;
+    hipfftHandle f1 = fft_plan(g, 1, true, e);
+    if (!f1) return e;
+    if (hipfftSetStream(fwd, s) != HIPFFT_SUCCESS || hipfftExecD2Z(fwd, grid2, spec) != HIPFFT_SUCCESS)
+        return hipErrorUnknown;
+    KParams kp{};
+    kp.family = k.family;
+    kp.s2 = k.outputscale;
+    kp.period = k.period;
+    for (int q = 0; q < 3; ++q) kp.inv_l[q] = q < k.d ? 1.0 / (k.ard ? k.lengthscale[q] : k.lengthscale[0]) : 0.0;
+    const int np = (k.ard ? k.d : 1) + (k.family == MFGP_PERIODIC ? 1 : 0) + 1;
+    std::vector<double> h(t);
+    for (int j = 0; j < np; ++j) {
+        // the derivative column into grid2 slot 0, its spectrum into lamj
+        hipLaunchKernelGGL(ski_dcolumn_kernel, dim3(nblk(g.Lr)), dim3(256), 0, s, g, op.geo, kp, k.ard ? 1 : 0, j,
+                           grid2);
+        if (hipfftSetStream(f1, s) != HIPFFT_SUCCESS || hipfftExecD2Z(f1, grid2, lamj) != HIPFFT_SUCCESS)
+            return hipErrorUnknown;
+        e = hipMemcpyAsync(spec2, spec, static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex),
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ski_spectral_mul_kernel, dim3(nblk(g.Lc * t)), dim3(256), 0, s, spec2, lamj, g.Lc, t,
+                           1.0 / static_cast<double>(g.Lr));
+        if (hipfftSetStream(inv, s) != HIPFFT_SUCCESS || hipfftExecZ2D(inv, spec2, grid2) != HIPFFT_SUCCESS)
+            return hipErrorUnknown;
+        hipLaunchKernelGGL(ski_dot_kernel, dim3(t), dim3(256), 0, s, op.grid, grid2, g.Lr, dots);
+        e = hipMemcpyAsync(h.data(), dots, t * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        double gj = 0.0;
+        for (int c = 0; c < t; ++c) gj += colw[c] * h[c];
+        grad[j] = gj;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace mfgp

@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_ski_matvec": (C.c_int, [KP, P, I64, C.POINTER(SkiGridT), P, I32, P, P, SZ, P]),
         "mfgp_ski_cg_solve": (C.c_int, [KP, P, I64, C.POINTER(SkiGridT), P, I32, P, OP_, IP, P, SZ, P]),
         "mfgp_ski_predict_mean": (C.c_int, [KP, P, I64, P, I64, C.POINTER(SkiGridT), P, I32, P, P, SZ, P]),
+        "mfgp_ski_mll_and_grad": (C.c_int, [KP, P, I64, C.POINTER(SkiGridT), P, I32, P, OP_, P, P, P, IP, P, SZ, P]),
         "mfgp_status_string": (C.c_char_p, [C.c_int]),
         "mfgp_last_hip_error": (C.c_int, []),
         "mfgp_version": (C.c_int, []),
@@ -556,6 +557,32 @@ def ski_predict_mean(kern: Kernel, X: torch.Tensor, Xs: torch.Tensor, A: torch.T
     _check(LIB.mfgp_ski_predict_mean(C.byref(ks), _ptr(X), n, _ptr(Xs), m, C.byref(grid), _ptr(A), t, _ptr(mu),
                                      _ptr(ws), ws.numel(), _stream()), "ski_predict_mean")
     return mu
+
+
+def ski_mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, grid: SkiGridT, num_probes: int = 16,
+                     Z: Optional[torch.Tensor] = None, tol: float = 1e-6, probe_seed: int = 0,
+                     want_grad: bool = True, allow=(OK, NOT_CONVERGED, BREAKDOWN)):
+    """SKI log marginal likelihood, log-det and gradient.  Returns dict(mll, logdet, grad, info, status)."""
+    _dev(X, torch.float32, "X")
+    _dev(y, torch.float32, "y")
+    n, d = X.shape
+    if Z is not None:
+        _dev(Z, torch.float32, "Z")
+        num_probes = Z.shape[1]
+    t = num_probes + 1
+    o = cg_opts(tol, 0, 0, -1, "fp32", False, probe_seed)
+    ws = workspace(LIB.mfgp_ski_workspace_bytes(OP_MLL, n, d, t, C.byref(grid)), X.device)
+    ks = kern.struct(d)
+    npar = LIB.mfgp_num_params(C.byref(ks))
+    mll, ld = C.c_double(), C.c_double()
+    grad = (C.c_double * npar)() if want_grad else None
+    info = (CgInfoT * t)()
+    st = LIB.mfgp_ski_mll_and_grad(C.byref(ks), _ptr(X), n, C.byref(grid), _ptr(y), num_probes, _ptr(Z),
+                                   C.byref(o), C.byref(mll), C.byref(ld), grad, info, _ptr(ws), ws.numel(),
+                                   _stream())
+    _check(st, "ski_mll_and_grad", allow)
+    return dict(mll=mll.value, logdet=ld.value, grad=None if grad is None else list(grad),
+                info=_info_list(info, t), status=st)
 
 
 # ---------------------------------------------------------------- preconditioning

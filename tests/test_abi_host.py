@@ -153,6 +153,8 @@ def test_ski_checks_before_launch(m):
     b = L.mfgp_ski_workspace_bytes(m.OP_CG, 100000, 1, 3, C.byref(m.ski_grid([1000])))
     assert 0 < a < b < 11 * a
     assert L.mfgp_ski_workspace_bytes(m.OP_ADJOINT, 100, 1, 3, C.byref(m.ski_grid([100]))) == 0
+    assert L.mfgp_ski_workspace_bytes(m.OP_MLL, 100, 1, 9, C.byref(m.ski_grid([100]))) > 0
+    assert L.mfgp_ski_workspace_bytes(m.OP_MLL, 100, 1, 1, C.byref(m.ski_grid([100]))) == 0
 
 
 def test_workspace_sizes(m):

@@ -130,3 +130,57 @@ def test_ski_degenerate_inputs(mf):
     lo, h = ski.grid([Xe], [9])
     ref = ski.ski_matvec(o, Xe, Ve, lo, h, [9])
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+def _grad_ok(g, ref):
+    g, ref = np.asarray(g), np.asarray(ref)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    comp = np.all(np.abs(g - ref) <= 1e-3 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max()))
+    return rel <= 1e-3 and comp, rel
+
+
+@pytest.mark.parametrize("family,d,m", [("rbf", 1, [64]), ("matern32", 2, [24, 20]), ("periodic", 1, [48])])
+def test_ski_mll_same_probe(mf, family, d, m):
+    from oracle import krylov
+    banner(f"ski mll+grad same-probe {family} d={d} m={m} n=700 p=8")
+    rng = np.random.default_rng(1400 + d)
+    X = rng.uniform(0.0, 1.0, (700, d)).astype(np.float32)
+    y = (np.sin(5 * X).sum(axis=1) + 0.1 * rng.standard_normal(700)).astype(np.float32)
+    Z = np.where(rng.random((700, 8)) < 0.5, -1.0, 1.0).astype(np.float32)
+    o, k = kerns(mf, family, d, noise=0.05)
+    r = mf.ski_mll_and_grad(k, dev(X), dev(y), mf.ski_grid(m), Z=dev(Z), tol=1e-6)
+    assert r["status"] == mf.OK, r["info"]
+    lo, h = ski.grid([X], m)
+    A = ski.ski_ky(o, X, lo, h, m)
+    ld = float(krylov.quadform_log(A, Z).mean())
+    a = np.linalg.solve(A, y.astype(np.float64))
+    mll = -0.5 * (float(y.astype(np.float64) @ a) + ld + 700 * np.log(2 * np.pi))
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    assert r["mll"] == pytest.approx(mll, rel=1e-4)
+    ok, rel = _grad_ok(r["grad"], ski.ski_same_probe_grad(o, X, y, Z, lo, h, m))
+    assert ok, (r["grad"], rel)
+
+
+@pytest.mark.parametrize("family,ard", [("rbf", True), ("matern12", False), ("matern52", True),
+                                        ("periodic", True)])
+def test_ski_mll_exact_mode(mf, family, ard):
+    # probes sqrt(N) e_c: the log-det and the trace are exact (N = 60 <= MFGP_MAX_T - 1)
+    banner(f"ski mll+grad exact mode {family} ard={ard} n=60 d=2")
+    n = 60
+    rng = np.random.default_rng(1410)
+    X = rng.uniform(0.0, 1.0, (n, 2)).astype(np.float32)
+    y = (np.sin(4 * X[:, 0]) + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    o, k = kerns(mf, family, 2, noise=0.05)
+    if not ard:
+        o = gp.Kern(family, 0.3, 1.2, 0.05, period=0.6)
+        k = mf.Kernel(family, 0.3, 1.2, 0.05, period=0.6)
+    Z = (np.sqrt(n) * np.eye(n)).astype(np.float32)
+    m = [16, 14]
+    r = mf.ski_mll_and_grad(k, dev(X), dev(y), mf.ski_grid(m), Z=dev(Z), tol=1e-7)
+    assert r["status"] == mf.OK
+    lo, h = ski.grid([X], m)
+    A = ski.ski_ky(o, X, lo, h, m)
+    assert r["logdet"] == pytest.approx(np.linalg.slogdet(A)[1], rel=1e-4)
+    assert r["mll"] == pytest.approx(ski.ski_mll(o, X, y, lo, h, m), rel=1e-4)
+    ok, rel = _grad_ok(r["grad"], ski.ski_mll_grad(o, X, y, lo, h, m))
+    assert ok, (r["grad"], ski.ski_mll_grad(o, X, y, lo, h, m), rel)
