@@ -301,8 +301,9 @@ int mfgp_rademacher(uint64_t seed, int64_t n, int32_t p, float* Z, void* stream)
  * caller's when explicit_range is set), r_k = max_k - min_k (1 if zero),
  * spacing h_k = r_k / (m_k - 4), nodes lo_k + j h_k with lo_k = min_k - h_k,
  * j < m_k; weights of nodes off the grid (points outside the range) are
- * dropped.  Products accumulate in FP64 (atomic scatter: the last bits vary
- * between runs) and round once.  Kernels: one term of family RBF, MATERN*
+ * dropped.  Products accumulate in FP64 and round once (the points are
+ * bucketed by stencil cell with atomic placement, so the order of a cell's
+ * terms, and the last bits, may vary between runs).  Kernels: one term of family RBF, MATERN*
  * or PERIODIC (no sums, products or LINEAR: MFGP_UNSUPPORTED), d <= 3.
  * The first call with a grid shape and column count on a device from a host
  * thread creates hipFFT plans for it and keeps them until the process ends

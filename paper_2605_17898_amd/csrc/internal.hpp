@@ -21,6 +21,8 @@ struct SkiGeomH {
     int64_t Lr;   // prod L
     int64_t Lc;   // (L0 / 2 + 1) L1 L2
 };
+// The training points are bucketed once by the cell of their stencil
+// (cells b_k in [-2, m_k], ncell of them): offsets [ncell + 1] into perm [n].
 struct SkiOp {
     SkiGeomH g{};
     double* geo = nullptr;
@@ -28,9 +30,14 @@ struct SkiOp {
     double* grid = nullptr;   // [t][Lr]
     void* spec = nullptr;     // [t][Lc] complex
     float* part = nullptr;
+    int* counts = nullptr;    // [ncell + 1]
+    int* offsets = nullptr;   // [ncell + 1]
+    int* perm = nullptr;      // [n]
+    double* frac = nullptr;   // [n][d] fractional grid coordinates, in perm order
+    int64_t ncell = 0;
     int t = 0;
 };
-size_t ski_scratch_bytes(int d, const int32_t* m, int t);
+size_t ski_scratch_bytes(int d, const int32_t* m, int t, int64_t n);
 // lo, hi: the caller's data range, or null for the range of X (and Xs).
 hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n, const float* Xs, int64_t ms,
                      const int32_t* m, const float* lo, const float* hi, int t, void* scratch, hipStream_t s);

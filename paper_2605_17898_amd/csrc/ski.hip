@@ -15,9 +15,11 @@
 // through the D-dimensional circulant embedding of size L_k = 2 m_k: the
 // first column holds k(o h) at offsets o_k = j_k (j_k < m_k), L_k - j_k
 // (j_k > m_k) and 0 at j_k = m_k; its FFT (FP64, hipFFT D2Z) is the
-// spectrum.  One product: zero the padded grid [t][L], scatter W^T V into
-// it (FP64 atomics), FFT, multiply by the spectrum / prod L, inverse FFT,
-// gather W (.) in FP64 and round once.
+// spectrum.  The training points are bucketed once by the cell of their
+// stencil (counting sort).  One product: form the padded grid [t][L] =
+// W^T V without atomics (each grid entry sums over the points of the 4^D
+// cells that reach it, FP64), FFT, multiply by the spectrum / prod L,
+// inverse FFT, gather W (.) in FP64 and round once.
 #include "internal.hpp"
 
 #include <hipfft/hipfft.h>
@@ -255,41 +257,163 @@ __global__ void ski_dot_kernel(const double* __restrict__ a, const double* __res
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-__global__ void fill0_kernel(double* __restrict__ a, int64_t total) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx < total) a[idx] = 0.0;
+// Cell of a point's stencil: b_k + 2 per dimension (b_k the floor of its
+// grid coordinate), flattened with dimension 0 fastest over m_k + 3 values;
+// -1 for a non-finite point or one whose stencil misses the grid.
+__device__ __forceinline__ int64_t point_cell(const float* __restrict__ x, const double* __restrict__ geo,
+                                              const SkiGeom& g) {
+    int64_t cell = 0, stride = 1;
+    for (int k = 0; k < g.d; ++k) {
+        double t = (static_cast<double>(x[k]) - geo[k]) / geo[3 + k];
+        if (!(t == t) || isinf(t)) return -1;
+        t = fmin(fmax(t, -4.0), static_cast<double>(g.m[k]) + 4.0);
+        const int b = static_cast<int>(floor(t));
+        if (b < -2 || b > g.m[k]) return -1;
+        cell += (b + 2) * stride;
+        stride *= g.m[k] + 3;
+    }
+    return cell;
 }
 
-// grid[c][node] += w V[i, c] over the stencil of point i (thread per (i, c)).
-template <typename T>
-__global__ void ski_scatter_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
-                                   const T* __restrict__ V, int t, double* __restrict__ grid) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n * t) return;
-    const int64_t i = idx / t;
-    const int c = static_cast<int>(idx - i * t);
-    int base[3] = {0, 0, 0};
-    double w[3][4] = {{1, 0, 0, 0}, {1, 0, 0, 0}, {1, 0, 0, 0}};
-    if (!stencil(X + i * g.d, geo, g, base, w)) return;
-    const double v = static_cast<double>(V[idx]);
-    double* gc = grid + static_cast<int64_t>(c) * g.Lr;
-    const int n1 = g.d > 1 ? 4 : 1, n2 = g.d > 2 ? 4 : 1;
-    for (int a2 = 0; a2 < n2; ++a2) {
-        const int j2 = base[2] + a2;
-        if (g.d > 2 && (j2 < 0 || j2 >= g.m[2])) continue;
-        for (int a1 = 0; a1 < n1; ++a1) {
-            const int j1 = base[1] + a1;
-            if (g.d > 1 && (j1 < 0 || j1 >= g.m[1])) continue;
-            const double w12 = (g.d > 2 ? w[2][a2] : 1.0) * (g.d > 1 ? w[1][a1] : 1.0);
-            const int64_t row = (g.d > 1 ? j1 : 0) * static_cast<int64_t>(g.L[0]) +
-                                (g.d > 2 ? j2 : 0) * static_cast<int64_t>(g.L[0]) * g.L[1];
-            for (int a0 = 0; a0 < 4; ++a0) {
-                const int j0 = base[0] + a0;
-                if (j0 < 0 || j0 >= g.m[0]) continue;
-                atomicAdd(gc + row + j0, w12 * w[0][a0] * v);
-            }
-        }
+__global__ void ski_count_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
+                                 int* __restrict__ counts) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = point_cell(X + i * g.d, geo, g);
+    if (c >= 0) atomicAdd(counts + c, 1);
+}
+
+// offsets = exclusive prefix sum of counts [len], offsets[len] = total, in
+// three passes over tiles of kScanTile counts (tile sums; their prefix in one
+// block; each tile's prefix plus its offset); counts is cleared for use as
+// the placement cursor.
+constexpr int kScanTile = 1024;
+
+__global__ void ski_tile_sum_kernel(const int* __restrict__ counts, int64_t len, int* __restrict__ tsum) {
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    int v = 0;
+    for (int q = threadIdx.x; q < kScanTile; q += blockDim.x)
+        if (base + q < len) v += counts[base + q];
+    __shared__ int red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+        if (threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) tsum[blockIdx.x] = red[0];
+}
+
+__global__ void ski_tile_prefix_kernel(int* __restrict__ tsum, int64_t ntile, int* __restrict__ offsets, int64_t len) {
+    if (threadIdx.x != 0) return;
+    int run = 0;
+    for (int64_t b = 0; b < ntile; ++b) {
+        const int v = tsum[b];
+        tsum[b] = run;
+        run += v;
+    }
+    offsets[len] = run;
+}
+
+__global__ void ski_tile_scan_kernel(int* __restrict__ counts, int64_t len, const int* __restrict__ tsum,
+                                     int* __restrict__ offsets) {
+    // thread q holds entries base + 4 q .. base + 4 q + 3 (256 threads x 4 = one tile)
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + 4 * threadIdx.x;
+    int v[4], loc = 0;
+    for (int e = 0; e < 4; ++e) {
+        v[e] = base + e < len ? counts[base + e] : 0;
+        loc += v[e];
+    }
+    __shared__ int sc[256];
+    sc[threadIdx.x] = loc;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan
+        const int add = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = tsum[blockIdx.x] + sc[threadIdx.x] - loc;
+    for (int e = 0; e < 4; ++e) {
+        if (base + e < len) {
+            offsets[base + e] = run;
+            counts[base + e] = 0;
+        }
+        run += v[e];
+    }
+}
+
+// perm[pos] = i and frac[pos][k] = the fractional grid coordinate of point i
+// (t_k - floor t_k) at its place pos in its cell's range.
+__global__ void ski_place_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
+                                 const int* __restrict__ offsets, int* __restrict__ cursor, int* __restrict__ perm,
+                                 double* __restrict__ frac) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = point_cell(X + i * g.d, geo, g);
+    if (c < 0) return;
+    const int64_t pos = offsets[c] + atomicAdd(cursor + c, 1);
+    perm[pos] = static_cast<int>(i);
+    for (int k = 0; k < g.d; ++k) {
+        double t = (static_cast<double>(X[i * g.d + k]) - geo[k]) / geo[3 + k];
+        t = fmin(fmax(t, -4.0), static_cast<double>(g.m[k]) + 4.0);
+        frac[pos * g.d + k] = t - floor(t);
+    }
+}
+
+// Weight of stencil entry e (node b - 1 + e) at fractional coordinate f.
+__device__ __forceinline__ double keys1(double f, int e) {
+    double w[4];
+    keys4(f, w);
+    return w[e];
+}
+
+// The padded grid [t][Lr] = W^T V without atomics: thread per (grid entry,
+// column); an entry inside the node box sums w V[p, c] over the points p of
+// the 4^D cells whose stencils reach it (cells b_k + 2 = j_k .. j_k + 3), the
+// weight recomputed from the point exactly as in the gather; padding gets 0.
+template <typename T>
+__global__ void ski_transpose_kernel(SkiGeom g, const T* __restrict__ V, int t, const int* __restrict__ offsets,
+                                     const int* __restrict__ perm, const double* __restrict__ frac,
+                                     double* __restrict__ grid) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= g.Lr * t) return;
+    const int c = static_cast<int>(idx / g.Lr);
+    int64_t rest = idx - static_cast<int64_t>(c) * g.Lr;
+    int j[3];
+    bool inside = true;
+    for (int k = 0; k < 3; ++k) {
+        j[k] = static_cast<int>(rest % g.L[k]);
+        rest /= g.L[k];
+        if (k < g.d && j[k] >= g.m[k]) inside = false;
+    }
+    double acc = 0.0;
+    if (inside) {
+        const int n1 = g.d > 1 ? 4 : 1, n2 = g.d > 2 ? 4 : 1;
+        const int64_t s1 = g.m[0] + 3, s2 = s1 * (g.d > 1 ? g.m[1] + 3 : 1);
+        for (int a2 = 0; a2 < n2; ++a2)
+            for (int a1 = 0; a1 < n1; ++a1)
+                for (int a0 = 0; a0 < 4; ++a0) {
+                    // cell with b_k + 2 = j_k + a_k, i.e. node j_k is its stencil's entry 3 - a_k
+                    const int64_t cell = (j[0] + a0) + (g.d > 1 ? (j[1] + a1) * s1 : 0) +
+                                         (g.d > 2 ? (j[2] + a2) * s2 : 0);
+                    const int q0 = offsets[cell], q1 = offsets[cell + 1];
+                    for (int q = q0; q < q1; ++q) {
+                        const int pnt = perm[q];
+                        const double* fq = frac + static_cast<int64_t>(q) * g.d;
+                        double wt = keys1(fq[0], 3 - a0);
+                        if (g.d > 1) wt *= keys1(fq[1], 3 - a1);
+                        if (g.d > 2) wt *= keys1(fq[2], 3 - a2);
+                        acc = fma(wt, static_cast<double>(V[static_cast<int64_t>(pnt) * t + c]), acc);
+                    }
+                }
+    }
+    grid[idx] = acc;
+}
+
+__global__ void fill0i_kernel(int* __restrict__ a, int64_t total) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx < total) a[idx] = 0;
 }
 
 // out = sum over the stencil of w grid[c][node] (FP64); then either
@@ -381,12 +505,24 @@ hipfftHandle fft_plan(const SkiGeom& g, int batch, bool forward, hipError_t& err
 
 }  // namespace
 
-size_t ski_scratch_bytes(int d, const int32_t* m, int t) {
+static int64_t cell_count(const SkiGeom& g) {
+    int64_t c = 1;
+    for (int k = 0; k < g.d; ++k) c *= g.m[k] + 3;
+    return c;
+}
+
+static int64_t tile_count(int64_t ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+
+size_t ski_scratch_bytes(int d, const int32_t* m, int t, int64_t n) {
     const SkiGeom g = make_geom(d, m);
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t nc = static_cast<size_t>(cell_count(g)) + 1;
     return al(6 * sizeof(double)) + al(g.Lc * sizeof(hipfftDoubleComplex)) +
            al(static_cast<size_t>(t) * g.Lr * sizeof(double)) +
-           al(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)) + al(kBoundBlocks * 6 * sizeof(float)) + 256;
+           al(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)) + al(kBoundBlocks * 6 * sizeof(float)) +
+           2 * al(nc * sizeof(int)) + al(static_cast<size_t>(tile_count(nc)) * sizeof(int)) +
+           al(static_cast<size_t>(n) * sizeof(int)) +
+           al(static_cast<size_t>(n) * d * sizeof(double)) + 256;
 }
 
 // Grid geometry and spectrum for the kernel: the range from X (and Xs) or the
@@ -406,6 +542,12 @@ hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n,
     op.grid = reinterpret_cast<double*>(take(static_cast<size_t>(t) * op.g.Lr * sizeof(double)));
     op.spec = take(static_cast<size_t>(t) * op.g.Lc * sizeof(hipfftDoubleComplex));
     op.part = reinterpret_cast<float*>(take(kBoundBlocks * 6 * sizeof(float)));
+    op.ncell = cell_count(op.g);
+    op.counts = reinterpret_cast<int*>(take((op.ncell + 1) * sizeof(int)));
+    op.offsets = reinterpret_cast<int*>(take((op.ncell + 1) * sizeof(int)));
+    int* tsum = reinterpret_cast<int*>(take(static_cast<size_t>(tile_count(op.ncell + 1)) * sizeof(int)));
+    op.perm = reinterpret_cast<int*>(take(static_cast<size_t>(n) * sizeof(int)));
+    op.frac = reinterpret_cast<double*>(take(static_cast<size_t>(n) * k.d * sizeof(double)));
     const bool expl = lo && hi;
     if (!expl) {
         hipLaunchKernelGGL(ski_bounds_stage1, dim3(kBoundBlocks), dim3(256), 0, s, X, n, Xs, Xs ? ms : 0, k.d, op.part);
@@ -417,6 +559,17 @@ hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n,
     }
     hipLaunchKernelGGL(ski_geo_kernel, dim3(1), dim3(64), 0, s, op.part, kBoundBlocks, expl ? 1 : 0, op.g, l3[0],
                        l3[1], l3[2], h3[0], h3[1], h3[2], op.geo);
+    // bucket the training points by stencil cell (counting sort)
+    hipLaunchKernelGGL(fill0i_kernel, dim3(nblk(op.ncell + 1)), dim3(256), 0, s, op.counts, op.ncell + 1);
+    hipLaunchKernelGGL(ski_count_kernel, dim3(nblk(n)), dim3(256), 0, s, X, n, op.g, op.geo, op.counts);
+    const int64_t ntile = tile_count(op.ncell);
+    hipLaunchKernelGGL(ski_tile_sum_kernel, dim3(static_cast<unsigned>(ntile)), dim3(256), 0, s, op.counts, op.ncell,
+                       tsum);
+    hipLaunchKernelGGL(ski_tile_prefix_kernel, dim3(1), dim3(64), 0, s, tsum, ntile, op.offsets, op.ncell);
+    hipLaunchKernelGGL(ski_tile_scan_kernel, dim3(static_cast<unsigned>(ntile)), dim3(256), 0, s, op.counts, op.ncell,
+                       tsum, op.offsets);
+    hipLaunchKernelGGL(ski_place_kernel, dim3(nblk(n)), dim3(256), 0, s, X, n, op.g, op.geo, op.offsets, op.counts,
+                       op.perm, op.frac);
     KParams kp{};
     kp.family = k.family;
     kp.s2 = k.outputscale;
@@ -442,10 +595,11 @@ static hipError_t ski_product(const SkiOp& op, const float* Xc, int64_t nc, cons
                               const T* V, int t, double sig2, const float* Vself, float* out, const float* B,
                               const double* X64, double* R, hipStream_t s) {
     if (t > op.t) return hipErrorInvalidValue;
+    (void)Xc;   // the columns' points are the bucketed training points
+    (void)nc;
     const int64_t tot = op.g.Lr * t;
-    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, op.grid, tot);
-    hipLaunchKernelGGL((ski_scatter_kernel<T>), dim3(nblk(nc * t)), dim3(256), 0, s, Xc, nc, op.g, op.geo, V, t,
-                       op.grid);
+    hipLaunchKernelGGL((ski_transpose_kernel<T>), dim3(nblk(tot)), dim3(256), 0, s, op.g, V, t, op.offsets, op.perm,
+                       op.frac, op.grid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipfftHandle fwd = fft_plan(op.g, t, true, e);
@@ -502,10 +656,11 @@ hipError_t ski_gradient(const SkiOp& op, const mfgp_kernel& k, const float* X, i
     double* dots = reinterpret_cast<double*>(take(static_cast<size_t>(t) * sizeof(double)));
     auto* spec = static_cast<hipfftDoubleComplex*>(op.spec);
     const int64_t tot = g.Lr * t;
-    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, op.grid, tot);
-    hipLaunchKernelGGL(fill0_kernel, dim3(nblk(tot)), dim3(256), 0, s, grid2, tot);
-    hipLaunchKernelGGL((ski_scatter_kernel<float>), dim3(nblk(n * t)), dim3(256), 0, s, X, n, g, op.geo, A, t, op.grid);
-    hipLaunchKernelGGL((ski_scatter_kernel<float>), dim3(nblk(n * t)), dim3(256), 0, s, X, n, g, op.geo, B, t, grid2);
+    (void)n;
+    hipLaunchKernelGGL((ski_transpose_kernel<float>), dim3(nblk(tot)), dim3(256), 0, s, g, A, t, op.offsets, op.perm,
+                       op.frac, op.grid);
+    hipLaunchKernelGGL((ski_transpose_kernel<float>), dim3(nblk(tot)), dim3(256), 0, s, g, B, t, op.offsets, op.perm,
+                       op.frac, grid2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipfftHandle fwd = fft_plan(g, t, true, e);
