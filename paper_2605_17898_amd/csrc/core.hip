@@ -404,7 +404,7 @@ size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
     size_t b = apply_scratch_floats(m, n, t) * sizeof(float);
     if (precision != MFGP_FP32_VALU && hybrid_supported(t)) b = std::max(b, hybrid_scratch_bytes(m, n, t));
     if ((precision == MFGP_FP32 || precision == MFGP_FP32_GRAM) && m == n && gram_supported(t))
-        b = std::max(b, gram_scratch_bytes(n, t));
+        b = std::max(b, std::max(gram_scratch_bytes(n, t), gram2_scratch_bytes(n, t)));
     return b;
 }
 

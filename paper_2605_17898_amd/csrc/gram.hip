@@ -119,6 +119,42 @@ __global__ void pack_gfrag_kernel(const float* __restrict__ V, const float* __re
     }
 }
 
+// Fragments of the fused two-term sweep: the values and |g_j|^2 of both terms.
+__global__ void pack_gfrag2_kernel(const float* __restrict__ V, const float* __restrict__ nrmA,
+                                   const float* __restrict__ nrmB, int64_t n, int t, int nt, int tv, int64_t nsteps,
+                                   float* __restrict__ F) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int WS = nt + tv + 2;
+    if (idx >= nsteps * 64 * WS) return;
+    const int w = static_cast<int>(idx % WS);
+    const int64_t lq = idx / WS;
+    const int l = static_cast<int>(lq % 64);
+    const int64_t q = lq / 64;
+    const int64_t j = q * kHK + l / 16;
+    const int64_t js = j < n ? j : n - 1;
+    if (w < nt + tv) {
+        const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
+        F[idx] = (j < n) ? V[j * t + c] : 0.0f;
+    } else {
+        F[idx] = w == nt + tv ? nrmA[js] : nrmB[js];
+    }
+}
+
+template <int DGA, int DGB, int NT, int TV>
+__global__ __launch_bounds__(kBlock) void sweep_gram2_kernel(
+    const float* __restrict__ Ga, const float* __restrict__ nrmA, const unsigned* __restrict__ gmaxA,
+    const float* __restrict__ Gb, const float* __restrict__ nrmB, const unsigned* __restrict__ gmaxB,
+    const float* __restrict__ Ua, int da, const float* __restrict__ Ub, int db, float rb, const float* __restrict__ F,
+    int64_t n, int t, int chunks, int64_t jchunk, float* __restrict__ partial) {
+    int rb_, ch;
+    map_block(blockIdx.x, chunks, rb_, ch);
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;   // multiple of 16
+    const int64_t rbase = static_cast<int64_t>(rb_) * kBlock;
+    float* out = partial + static_cast<int64_t>(ch) * n * t + rbase * t;
+    const bool gram = __uint_as_float(*gmaxA) <= kGramMaxNorm && __uint_as_float(*gmaxB) <= kGramMaxNorm;
+    gram2_block<DGA, DGB, NT, TV>(Ga, nrmA, Gb, nrmB, Ua, da, Ub, db, gram, rb, F, n, t, rbase, j0, j0 + jchunk, out);
+}
+
 template <int D, int NT, int TV>
 __global__ __launch_bounds__(kBlock) void sweep_gram_kernel(const float* __restrict__ U, const float* __restrict__ G,
                                                             const float* __restrict__ nrm,
@@ -202,6 +238,41 @@ GramLayout gram_layout(int64_t n, int t) {
     return L;
 }
 
+GramLayout gram2_layout(int64_t n, int t) {
+    int nt = 0, tv = 0;
+    gram_shape(t, nt, tv);
+    const SweepPlan p = plan_gram(n);
+    const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
+    GramLayout L{};
+    size_t off = 0;
+    L.frag = off;
+    off += up256(static_cast<size_t>(nsteps) * 64 * (nt + tv + 2) * sizeof(float));
+    L.part = off;
+    off += up256(static_cast<size_t>(p.chunks) * n * t * sizeof(float));
+    L.prep = off;
+    off += 2 * prep_layout(n).total;
+    L.total = off;
+    return L;
+}
+
+template <int DGA, int DGB>
+hipError_t launch_gram2_dd(int nt, int tv, const GramPrep& a, const GramPrep& b, const float* Ua, int da,
+                           const float* Ub, int db, float rb, const float* F, int64_t n, int t, const SweepPlan& p,
+                           float* partial, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
+#define MFGP_GRAM2_CASE(NTV, TVV)                                                                             \
+    if (nt == NTV && tv == TVV) {                                                                             \
+        hipLaunchKernelGGL((sweep_gram2_kernel<DGA, DGB, NTV, TVV>), grid, dim3(kBlock), 0, s, a.G, a.nrm, a.gmax, \
+                           b.G, b.nrm, b.gmax, Ua, da, Ub, db, rb, F, n, t, p.chunks, p.jchunk, partial);        \
+        return hipGetLastError();                                                                             \
+    }
+    MFGP_GRAM2_CASE(0, 1)
+    MFGP_GRAM2_CASE(1, 0) MFGP_GRAM2_CASE(1, 1) MFGP_GRAM2_CASE(2, 0) MFGP_GRAM2_CASE(2, 1)
+    MFGP_GRAM2_CASE(3, 0) MFGP_GRAM2_CASE(3, 1) MFGP_GRAM2_CASE(4, 0) MFGP_GRAM2_CASE(4, 1)
+#undef MFGP_GRAM2_CASE
+    return hipErrorInvalidValue;
+}
+
 template <int D>
 hipError_t launch_gram_d(int nt, int tv, const float* U, const float* G, const float* nrm, const unsigned* gmax,
                          const float* F, int64_t n, int t, const SweepPlan& p, float* partial, hipStream_t s) {
@@ -232,6 +303,11 @@ size_t gram_scratch_bytes(int64_t n, int t) {
 }
 
 size_t gram_prep_bytes(int64_t n) { return prep_layout(n).total; }
+
+size_t gram2_scratch_bytes(int64_t n, int t) {
+    if (!gram_supported(t)) return 0;
+    return gram2_layout(n, t).total + 1024;
+}
 
 hipError_t gram_prepare(const Operator& op, void* scratch, GramPrep& g, hipStream_t s) {
     const int64_t n = op.n;
@@ -308,6 +384,53 @@ hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, boo
     }
     if (e != hipSuccess) return e;
     return reduce_partials(partial, p.chunks, n, t, op.s2, with_noise ? op.sig2 : 0.0f, with_noise ? Vself : nullptr,
+                           out, s);
+}
+
+// The fused sweep of a two-term sum s2_a k_a + s2_b k_b of RBF-class terms
+// (RBF, periodic or products of them, each on its own prescaled features):
+// both preparations, fragments with both norms, one sweep whose entries are
+// k_a + (s2_b / s2_a) k_b, and the reduction with s2_a (and the head's noise).
+hipError_t apply_gram2(const Operator& a, const Operator& b, const float* V, int t, float* out, bool with_noise,
+                       const float* Vself, void* scratch, hipStream_t s) {
+    int nt, tv;
+    if (a.family != MFGP_RBF || b.family != MFGP_RBF || a.d < 1 || a.d > 8 || b.d < 1 || b.d > 8 || a.n != b.n ||
+        !gram_shape(t, nt, tv))
+        return hipErrorNotSupported;
+    const int64_t n = a.n;
+    const SweepPlan p = plan_gram(n);
+    const GramLayout L = gram2_layout(n, t);
+    const size_t prep = prep_layout(n).total;
+    char* base = static_cast<char*>(scratch);
+    float* F = reinterpret_cast<float*>(base + L.frag);
+    float* partial = reinterpret_cast<float*>(base + L.part);
+    GramPrep ga, gb;
+    hipError_t e = gram_prepare(a, base + L.prep, ga, s);
+    if (e == hipSuccess) e = gram_prepare(b, base + L.prep + prep, gb, s);
+    if (e != hipSuccess) return e;
+    const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
+    const int64_t total = nsteps * 64 * (nt + tv + 2);
+    hipLaunchKernelGGL(pack_gfrag2_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, V,
+                       ga.nrm, gb.nrm, n, t, nt, tv, nsteps, F);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const float rb = static_cast<float>(static_cast<double>(b.s2) / static_cast<double>(a.s2));
+    void* tok = timing_begin(s);
+    if (ga.dg == 4 && gb.dg == 4)
+        e = launch_gram2_dd<4, 4>(nt, tv, ga, gb, a.U, a.d, b.U, b.d, rb, F, n, t, p, partial, s);
+    else if (ga.dg == 4)
+        e = launch_gram2_dd<4, 8>(nt, tv, ga, gb, a.U, a.d, b.U, b.d, rb, F, n, t, p, partial, s);
+    else if (gb.dg == 4)
+        e = launch_gram2_dd<8, 4>(nt, tv, ga, gb, a.U, a.d, b.U, b.d, rb, F, n, t, p, partial, s);
+    else
+        e = launch_gram2_dd<8, 8>(nt, tv, ga, gb, a.U, a.d, b.U, b.d, rb, F, n, t, p, partial, s);
+    {
+        const double ent = static_cast<double>(n) * static_cast<double>(n);
+        timing_end(tok, s, kSweepF32, ent,
+                   ent * (sweep_flops_per_entry(a.family, a.d, t, false) + 3.0 * b.d + 2.0));
+    }
+    if (e != hipSuccess) return e;
+    return reduce_partials(partial, p.chunks, n, t, a.s2, with_noise ? a.sig2 : 0.0f, with_noise ? Vself : nullptr,
                            out, s);
 }
 

@@ -163,4 +163,182 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     }
 }
 
+// Two RBF-class terms fused into one sweep (a kernel sum s2_a k_a + s2_b k_b
+// whose terms each are RBF on their own features): per 16-j block and row
+// tile, one distance MFMA chain per term (Ga / Gb with their norms, as in
+// gram_block), the entry e = 2^(-r2_a) + rb 2^(-r2_b) with rb = s2_b / s2_a,
+// and one contraction of e for both terms.  F carries |g_j|^2 of both terms
+// behind the values (stride WS = NT + TV + 2).  When a term's norms exceed
+// the Gram form's bound (gram = false) the squared distances come from
+// direct differences of the prescaled points Ua [n][da], Ub [n][db] instead,
+// for the same (i, j) of each lane, read from memory as needed.
+template <int DGA, int DGB, int NT, int TV>
+__device__ __forceinline__ void gram2_block(const float* __restrict__ Ga, const float* __restrict__ nrmA,
+                                            const float* __restrict__ Gb, const float* __restrict__ nrmB,
+                                            const float* __restrict__ Ua, int da, const float* __restrict__ Ub,
+                                            int db, bool gram, float rb, const float* __restrict__ F, int64_t n,
+                                            int t, int64_t row_base, int64_t j0, int64_t j1,
+                                            float* __restrict__ out) {
+    constexpr int W = NT + TV;
+    constexpr int WS = W + 2;
+    constexpr int HA = DGA / 4;
+    constexpr int HB = DGB / 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane >> 4;
+    const int r16 = lane & 15;
+    const int64_t row0 = row_base + wave * (kHRT * 16);
+
+    float ba[kHRT][HA], bb[kHRT][HB], nia[kHRT], nib[kHRT];
+    int64_t irow[kHRT];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        int64_t i = row0 + r * 16 + r16;
+        i = i < n ? i : n - 1;
+        irow[r] = i;
+#pragma unroll
+        for (int h = 0; h < HA; ++h) ba[r][h] = -0.5f * Ga[i * DGA + 4 * h + grp];
+#pragma unroll
+        for (int h = 0; h < HB; ++h) bb[r][h] = -0.5f * Gb[i * DGB + 4 * h + grp];
+        nia[r] = nrmA[i];
+        nib[r] = nrmB[i];
+    }
+    f32x4 acc[kHRT][NT > 0 ? NT : 1], tot[kHRT][NT > 0 ? NT : 1];
+    float sv[kHRT][TV > 0 ? TV : 1], tv_tot[kHRT][TV > 0 ? TV : 1];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[r][c][q] = 0.0f;
+                tot[r][c][q] = 0.0f;
+            }
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            sv[r][c] = 0.0f;
+            tv_tot[r][c] = 0.0f;
+        }
+    }
+
+    const int64_t npad = (n + kGJ - 1) / kGJ * kGJ;
+    j1 = j1 < npad ? j1 : npad;
+    const int64_t nblk = j0 < j1 ? (j1 - j0) / kGJ : 0;
+    const int ja = 4 * (r16 & 3) + (r16 >> 2);
+
+    auto load_block = [&](int64_t b, float (&aa)[HA], float (&ab)[HB], float (&f)[4][WS]) {
+        const int64_t jb = j0 + b * kGJ;
+        const float* Gja = Ga + (jb + ja) * DGA + grp;   // rows past n repeat row n - 1
+        const float* Gjb = Gb + (jb + ja) * DGB + grp;
+#pragma unroll
+        for (int h = 0; h < HA; ++h) aa[h] = Gja[4 * h];
+#pragma unroll
+        for (int h = 0; h < HB; ++h) ab[h] = Gjb[4 * h];
+        const float* Fb = F + (jb / kHK) * (64 * WS);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int w = 0; w < WS; ++w) f[s][w] = Fb[(s * 64 + lane) * WS + w];
+    };
+    auto compute_block = [&](int64_t b, const float (&aa)[HA], const float (&ab)[HB], const float (&f)[4][WS]) {
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+            f32x4 d2a, d2b;
+            if (gram) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    d2a[s] = nia[r] + f[s][W];
+                    d2b[s] = nib[r] + f[s][W + 1];
+                }
+#pragma unroll
+                for (int h = 0; h < HA; ++h)
+                    d2a = __builtin_amdgcn_mfma_f32_16x16x4f32(aa[h], ba[r][h], d2a, 0, 0, 0);
+#pragma unroll
+                for (int h = 0; h < HB; ++h)
+                    d2b = __builtin_amdgcn_mfma_f32_16x16x4f32(ab[h], bb[r][h], d2b, 0, 0, 0);
+            } else {
+                const int64_t jb = j0 + b * kGJ;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    int64_t j = jb + 4 * s + grp;
+                    j = j < n ? j : n - 1;
+                    float sa = 0.0f, sb = 0.0f;
+                    for (int k = 0; k < da; ++k) {
+                        const float dd = Ua[irow[r] * da + k] - Ua[j * da + k];
+                        sa = fmaf(dd, dd, sa);
+                    }
+                    for (int k = 0; k < db; ++k) {
+                        const float dd = Ub[irow[r] * db + k] - Ub[j * db + k];
+                        sb = fmaf(dd, dd, sb);
+                    }
+                    d2a[s] = sa;
+                    d2b[s] = sb;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float e = fmaf(rb, kentry<MFGP_RBF>(d2b[s]), kentry<MFGP_RBF>(d2a[s]));
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, f[s][c], acc[r][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < TV; ++c) sv[r][c] = fmaf(e, f[s][NT + c], sv[r][c]);
+            }
+        }
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    tot[r][c][qq] += acc[r][c][qq];
+                    acc[r][c][qq] = 0.0f;
+                }
+#pragma unroll
+            for (int c = 0; c < TV; ++c) {
+                tv_tot[r][c] += sv[r][c];
+                sv[r][c] = 0.0f;
+            }
+        }
+    };
+
+    float aa0[HA], ab0[HB], aa1[HA], ab1[HB], fa[4][WS], fb[4][WS];
+    if (nblk > 0) load_block(0, aa0, ab0, fa);
+    int64_t b = 0;
+    for (; b + 1 < nblk; b += 2) {
+        load_block(b + 1, aa1, ab1, fb);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_block(b, aa0, ab0, fa);
+        __builtin_amdgcn_sched_barrier(0);
+        load_block(b + 2 < nblk ? b + 2 : nblk - 1, aa0, ab0, fa);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_block(b + 1, aa1, ab1, fb);
+        __builtin_amdgcn_sched_barrier(0);
+        if (((b + 2) & (kSeg / kGJ - 1)) == 0) flush();
+    }
+    if (b < nblk) compute_block(b, aa0, ab0, fa);
+
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int64_t i = row0 + r * 16 + 4 * grp + qq;
+                const float v = tot[r][c][qq] + acc[r][c][qq];
+                if (i < n) out[(i - row_base) * t + TV + 16 * c + r16] = v;
+            }
+#pragma unroll
+        for (int c = 0; c < TV; ++c) {
+            float v = tv_tot[r][c] + sv[r][c];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int64_t i = row0 + r * 16 + r16;
+            if (grp == 0 && i < n) out[(i - row_base) * t + c] = v;
+        }
+    }
+}
+
 }  // namespace mfgp

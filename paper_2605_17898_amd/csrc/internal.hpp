@@ -183,6 +183,11 @@ hipError_t gram_prepare_into(const Operator& op, const GramPrep& g, void* mean_s
 size_t gram_scratch_bytes(int64_t n, int t);
 hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, bool with_noise, const float* Vself,
                       void* scratch, hipStream_t s);
+// The fused Gram-form sweep of a two-term sum of RBF-class terms (square;
+// t as gram_supported), and its scratch.
+size_t gram2_scratch_bytes(int64_t n, int t);
+hipError_t apply_gram2(const Operator& a, const Operator& b, const float* V, int t, float* out, bool with_noise,
+                       const float* Vself, void* scratch, hipStream_t s);
 // FP32-class product for precision MFGP_FP32 / _FP32_VALU / _FP32_DIRECT /
 // _FP32_GRAM: the Gram form, the MFMA-contraction form or the VALU form as
 // the precision, the family, the shape and the size allow (see core.hip).

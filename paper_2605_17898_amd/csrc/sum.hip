@@ -210,6 +210,12 @@ hipError_t apply_sum(const Operator& cols, const Operator* rows, int64_t m, cons
         const Operator* rr = rows ? rows : &cols;
         return ski_apply(*cols.ski, cols.X, cols.n, rr->X, m, V, t, out, with_noise, cols.sig2, Vself, s);
     }
+    // two RBF-class terms in the Gram form: one fused sweep (one contraction)
+    const Operator* nb = cols.next;
+    if (!rows && nb && !nb->next && !cols.linear && !nb->linear && cols.family == MFGP_RBF &&
+        nb->family == MFGP_RBF && cols.d <= 8 && nb->d <= 8 && gram_supported(t) &&
+        (precision == MFGP_FP32_GRAM || (precision == MFGP_FP32 && cols.n >= kGramMinN)))
+        return apply_gram2(cols, *nb, V, t, out, with_noise, Vself, scratch, s);
     double* part = static_cast<double*>(sum_scratch);
     double* xtv = part + static_cast<size_t>(kLinBlocks) * MFGP_MAX_D * t;
     float* tmp = reinterpret_cast<float*>(static_cast<char*>(sum_scratch) + align256(lin_doubles(t) * sizeof(double)));

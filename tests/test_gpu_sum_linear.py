@@ -234,3 +234,50 @@ def test_linear_head_sum_matvec_and_cg(mf):
     assert st == mf.OK, info
     alpha = gp.solve(o, Xd, y.astype(np.float64))
     assert np.linalg.norm(host(x) - alpha) / np.linalg.norm(alpha) <= 1e-4
+
+
+def two_term(mf, l_rbf=0.4, noise=0.05):
+    o = gp.SumKern([gp.Kern("rbf", np.array([l_rbf, 2 * l_rbf]), 1.1, 0.0),
+                    gp.Kern("periodic", 0.7, 0.6, 0.0, period=0.45)], noise)
+    k = mf.Kernel("rbf", [l_rbf, 2 * l_rbf], 1.1, noise) + mf.Kernel("periodic", 0.7, 0.6, period=0.45)
+    return o, k
+
+
+@pytest.mark.parametrize("t", [1, 17, 33])
+def test_fused_two_term_gram_matvec(mf, t):
+    # two RBF-class terms in the Gram form run as one fused sweep (one contraction)
+    banner(f"fused two-term sum rbf+periodic fp32_gram n=1537 t={t}")
+    X, _ = data(1600 + t, 1537)
+    o, k = two_term(mf)
+    V = np.random.default_rng(1601).standard_normal((1537, t)).astype(np.float32)
+    out = mf.kernel_matvec(k, dev(X), dev(V), precision="fp32_gram")
+    ref = gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64))
+    err = col_rel_err(host(out), ref).max()
+    print(f"max per-column relative error {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_fused_two_term_direct_fallback(mf):
+    # short RBF lengthscales push max |g|^2 past the Gram bound: the fused
+    # sweep takes direct differences for both terms
+    banner("fused two-term sum with |g|^2 > 64 (direct differences), n=1100 t=17")
+    X, _ = data(1610, 1100)
+    o, k = two_term(mf, l_rbf=0.05)
+    V = np.random.default_rng(1611).standard_normal((1100, 17)).astype(np.float32)
+    out = mf.kernel_matvec(k, dev(X), dev(V), precision="fp32_gram")
+    ref = gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64))
+    assert col_rel_err(host(out), ref).max() <= 1e-5
+
+
+def test_fused_two_term_mll(mf):
+    banner("fused two-term sum mll+grad fp32_gram n=1000 p=8 vs same-probe oracle")
+    X, y = data(1620, 1000)
+    o, k = two_term(mf, noise=0.08)
+    Z = inputs.rademacher(np.random.default_rng(1621), 1000, 8)
+    r = mf.mll_and_grad(k, dev(X), dev(y), Z=dev(Z), tol=1e-6, precision="fp32_gram")
+    assert r["status"] == mf.OK, r["info"]
+    Xd, yd = X.astype(np.float64), y.astype(np.float64)
+    ld = float(krylov.quadform_log(gp.ky_matrix(o, Xd), Z).mean())
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    ok_, rel = grad_ok(r["grad"], gp.same_probe_grad(o, Xd, yd, Z))
+    assert ok_, (r["grad"], rel)
