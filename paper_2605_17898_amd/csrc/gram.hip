@@ -151,8 +151,12 @@ __global__ __launch_bounds__(kBlock) void sweep_gram2_kernel(
     const int64_t j0 = static_cast<int64_t>(ch) * jchunk;   // multiple of 16
     const int64_t rbase = static_cast<int64_t>(rb_) * kBlock;
     float* out = partial + static_cast<int64_t>(ch) * n * t + rbase * t;
-    const bool gram = __uint_as_float(*gmaxA) <= kGramMaxNorm && __uint_as_float(*gmaxB) <= kGramMaxNorm;
-    gram2_block<DGA, DGB, NT, TV>(Ga, nrmA, Gb, nrmB, Ua, da, Ub, db, gram, rb, F, n, t, rbase, j0, j0 + jchunk, out);
+    if (__uint_as_float(*gmaxA) <= kGramMaxNorm && __uint_as_float(*gmaxB) <= kGramMaxNorm)
+        gram2_block<DGA, DGB, NT, TV, true>(Ga, nrmA, Gb, nrmB, Ua, da, Ub, db, rb, F, n, t, rbase, j0, j0 + jchunk,
+                                            out);
+    else
+        gram2_block<DGA, DGB, NT, TV, false>(Ga, nrmA, Gb, nrmB, Ua, da, Ub, db, rb, F, n, t, rbase, j0, j0 + jchunk,
+                                             out);
 }
 
 template <int D, int NT, int TV>

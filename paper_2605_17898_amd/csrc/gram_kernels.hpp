@@ -171,12 +171,13 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
 // behind the values (stride WS = NT + TV + 2).  When a term's norms exceed
 // the Gram form's bound (gram = false) the squared distances come from
 // direct differences of the prescaled points Ua [n][da], Ub [n][db] instead,
-// for the same (i, j) of each lane, read from memory as needed.
-template <int DGA, int DGB, int NT, int TV>
+// for the same (i, j) of each lane, read from memory as needed.  GRAM
+// selects the form for the whole launch (one branch per kernel).
+template <int DGA, int DGB, int NT, int TV, bool GRAM>
 __device__ __forceinline__ void gram2_block(const float* __restrict__ Ga, const float* __restrict__ nrmA,
                                             const float* __restrict__ Gb, const float* __restrict__ nrmB,
                                             const float* __restrict__ Ua, int da, const float* __restrict__ Ub,
-                                            int db, bool gram, float rb, const float* __restrict__ F, int64_t n,
+                                            int db, float rb, const float* __restrict__ F, int64_t n,
                                             int t, int64_t row_base, int64_t j0, int64_t j1,
                                             float* __restrict__ out) {
     constexpr int W = NT + TV;
@@ -244,7 +245,7 @@ __device__ __forceinline__ void gram2_block(const float* __restrict__ Ga, const 
 #pragma unroll
         for (int r = 0; r < kHRT; ++r) {
             f32x4 d2a, d2b;
-            if (gram) {
+            if constexpr (GRAM) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     d2a[s] = nia[r] + f[s][W];
