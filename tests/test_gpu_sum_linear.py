@@ -281,3 +281,28 @@ def test_fused_two_term_mll(mf):
     assert r["logdet"] == pytest.approx(ld, rel=1e-4)
     ok_, rel = grad_ok(r["grad"], gp.same_probe_grad(o, Xd, yd, Z))
     assert ok_, (r["grad"], rel)
+
+
+@pytest.mark.parametrize("case", ["periodic6+rbf3", "periodic8+periodic8"])
+def test_fused_two_term_operand_widths(mf, case):
+    # the fused sweep's instances by the terms' operand widths: DG = 8 then 4
+    # (6 circle features + 3 RBF features) and DG = 8 for both (d = 4 circles)
+    banner(f"fused two-term sum {case} fp32_gram n=1300 t=33")
+    if case == "periodic6+rbf3":
+        d = 3
+        o = gp.SumKern([gp.Kern("periodic", np.array([0.8, 1.1, 0.9]), 0.7, 0.0, period=0.5),
+                        gp.Kern("rbf", 0.6, 1.2, 0.0)], 0.05)
+        k = mf.Kernel("periodic", [0.8, 1.1, 0.9], 0.7, 0.05, period=0.5) + mf.Kernel("rbf", 0.6, 1.2)
+    else:
+        d = 4
+        o = gp.SumKern([gp.Kern("periodic", 1.0, 0.9, 0.0, period=0.45),
+                        gp.Kern("periodic", np.array([1.2, 0.9, 1.4, 1.1]), 0.4, 0.0, period=1.3)], 0.05)
+        k = mf.Kernel("periodic", 1.0, 0.9, 0.05, period=0.45) + \
+            mf.Kernel("periodic", [1.2, 0.9, 1.4, 1.1], 0.4, period=1.3)
+    X, _ = data(1630 + d, 1300, d)
+    V = np.random.default_rng(1631).standard_normal((1300, 33)).astype(np.float32)
+    out = mf.kernel_matvec(k, dev(X), dev(V), precision="fp32_gram")
+    ref = gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64))
+    err = col_rel_err(host(out), ref).max()
+    print(f"max per-column relative error {err:.2e}")
+    assert err <= 1e-5
