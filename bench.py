@@ -27,6 +27,8 @@ python bench.py --mode matvec   (K_y V entries/s: the 100k geometry at t = 1 and
     HIP events around the whole call, median of 5 after one warm-up)
 python bench.py --mode composite   (one MLL + gradient of Scale(RBF) + Scale(Periodic)
     on the 100k points, 32 probes)
+python bench.py --mode variance   (predictive variance on the 100k points at 2000 test
+    points, 32 probes)
 python bench.py --mode ski   (structured kernel interpolation at N = 200000, D = 1 and 2:
     K_y V at t = 1 and 33, and a CG solve)
 python bench.py --mode small   (end-to-end latency of the 1024-point RBF and the
@@ -198,6 +200,30 @@ def ski_leg(args) -> int:
                   flush=True)
     print(json.dumps({"mode": "ski", "workload": "ski200k (uniform [0,1]^d, RBF l=0.05, sigma^2=0.01)",
                       "rows": rows}))
+    return 0
+
+
+def variance_leg(args) -> int:
+    """Predictive variance on the rbf100k points at its 2000 test points with
+    32 seeded Rademacher probes (one CG solve of 32 columns between two
+    rectangular sweeps), FP32 and with the Gram-form solve."""
+    import torch
+
+    from paper_2605_17898_amd import inputs, mfgp
+    w = inputs.rbf100k()
+    kern = mfgp.Kernel(w.family, w.lengthscale, w.outputscale, w.noise)
+    X = torch.from_numpy(w.X).cuda()
+    Xs = torch.from_numpy(w.Xs).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    var, info, st = mfgp.predict_variance(kern, X, Xs, num_probes=32, seed=7, tol=1e-6)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    v = var.double()
+    print(json.dumps({"mode": "variance", "workload": "rbf100k, 2000 test points, 32 probes", "seconds": el,
+                      "status": st, "cg_iters_max": max(i["iters"] for i in info),
+                      "rel_resid_true_max": max(i["rel_resid_true"] for i in info),
+                      "var_min": float(v.min()), "var_mean": float(v.mean()), "var_max": float(v.max())}))
     return 0
 
 
@@ -376,7 +402,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--mode", default="step",
-                    choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite", "ski"])
+                    choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite", "ski",
+                             "variance"])
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
@@ -402,6 +429,8 @@ def main() -> int:
         return rbf500k_leg(args)
     if args.mode == "ski":
         return ski_leg(args)
+    if args.mode == "variance":
+        return variance_leg(args)
     if args.mode == "composite":
         return composite_leg(args)
     if args.mode == "matvec":
