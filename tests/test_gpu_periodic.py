@@ -186,3 +186,17 @@ def test_gram_guard_large_features(mf):
     out = mf.kernel_matvec(mk(mf, ok), dev(X), dev(V), precision="fp32_gram")
     ref = gp.ky_matvec(ok, X.astype(np.float64), V.astype(np.float64))
     assert col_rel_err(host(out), ref).max() <= 1e-5
+
+
+def test_periodic_default_fp32_at_gram_size(mf):
+    # n >= 32768: the default FP32 product takes the Gram form with DG = 8
+    # (d = 4, 8 circle features); sampled rows against the oracle
+    banner("periodic d=4 default fp32 n=40003 t=33 (Gram form, 8 features), sampled rows")
+    X, _, ok = problem(990, 40003, 4, ard=True)
+    V = np.random.default_rng(991).standard_normal((40003, 33)).astype(np.float32)
+    out = host(mf.kernel_matvec(mk(mf, ok), dev(X), dev(V)))
+    rows = np.random.default_rng(992).choice(40003, 200, replace=False)
+    ref = gp.ky_matvec_rows(ok, X.astype(np.float64), V.astype(np.float64), rows)
+    err = np.linalg.norm(out[rows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print(f"sampled-row relative error {err.max():.2e}")
+    assert err.max() <= 1e-5

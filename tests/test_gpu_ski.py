@@ -205,3 +205,15 @@ def test_ski_full_size_sampled_rows(mf, d, m, tol):
     err = np.linalg.norm(out[rows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
     print(f"sampled-row relative error {err.max():.2e}")
     assert err.max() <= tol
+
+
+def test_ski_d3_maximum_columns(mf):
+    # D = 3 and t = MFGP_MAX_T = 64 columns in one product
+    banner("ski matvec d=3 t=64 n=600 m=[10, 9, 8]")
+    rng = np.random.default_rng(1600)
+    X = rng.uniform(-1.0, 2.0, (600, 3)).astype(np.float32)
+    V = rng.standard_normal((600, 64)).astype(np.float32)
+    o, k = kerns(mf, "matern52", 3)
+    out = mf.ski_matvec(k, dev(X), dev(V), mf.ski_grid([10, 9, 8]))
+    lo, h = ski.grid([X], [10, 9, 8])
+    assert col_rel_err(host(out), ski.ski_matvec(o, X, V, lo, h, [10, 9, 8])).max() <= 1e-6

@@ -306,3 +306,36 @@ def test_fused_two_term_operand_widths(mf, case):
     err = col_rel_err(host(out), ref).max()
     print(f"max per-column relative error {err:.2e}")
     assert err <= 1e-5
+
+
+def test_four_term_sum_maximum(mf):
+    # MFGP_MAX_TERMS terms of four different kinds: matvec and adjoint
+    banner("sum of 4 terms (rbf, matern12, periodic, linear) n=900 t=5")
+    X, _ = data(1700, 900, 2)
+    o = gp.SumKern([gp.Kern("rbf", 0.4, 1.0, 0.0), gp.Kern("matern12", np.array([0.6, 0.9]), 0.5, 0.0),
+                    gp.Kern("periodic", 0.7, 0.4, 0.0, period=0.45), gp.Kern("linear", 1.0, 0.2, 0.0)], 0.05)
+    k = (mf.Kernel("rbf", 0.4, 1.0, 0.05) + mf.Kernel("matern12", [0.6, 0.9], 0.5)
+         + mf.Kernel("periodic", 0.7, 0.4, period=0.45) + mf.Kernel("linear", 1.0, 0.2))
+    V = np.random.default_rng(1701).standard_normal((900, 5)).astype(np.float32)
+    out = mf.kernel_matvec(k, dev(X), dev(V))
+    assert col_rel_err(host(out), gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64))).max() <= 1e-5
+    A = np.random.default_rng(1702).standard_normal((900, 2)).astype(np.float32)
+    B = np.random.default_rng(1703).standard_normal((900, 2)).astype(np.float32)
+    g = np.array(mf.kernel_adjoint(k, dev(X), dev(A), dev(B), [1.0, -0.5]))
+    ref = gp.adjoint_bilinear(o, X, A, B, [1.0, -0.5])
+    assert len(g) == o.n_params(2) == 10      # [l, s2 | l1, l2, s2 | l, p, s2 | s2 | sigma^2]
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+@pytest.mark.parametrize("which", ["sum", "prod"])
+def test_single_point_compositions(mf, which):
+    banner(f"{which} with n = 1")
+    X = np.array([[0.3, -0.2]], np.float32)
+    V = np.array([[1.5, -2.0]], np.float32)
+    if which == "sum":
+        o, k = sum_kernels(mf)
+    else:
+        o = gp.ProdKern([gp.Kern("rbf", 0.5, 1.0, 0.0), gp.Kern("periodic", 0.7, 1.0, 0.0, period=0.45)], 1.3, 0.05)
+        k = mf.Kernel("rbf", 0.5, 1.3, 0.05) * mf.Kernel("periodic", 0.7, period=0.45)
+    out = host(mf.kernel_matvec(k, dev(X), dev(V)))
+    np.testing.assert_allclose(out, gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64)), rtol=1e-6)
