@@ -703,7 +703,7 @@ struct SkiMllWs { void* sk; void* gs; CgBufs b; float* Bm; double* X64; float* Z
 static SkiMllWs carve_ski_mll(Carver& cv, int64_t n, int d, const int32_t* m, int t, int max_iter) {
     SkiMllWs w;
     const size_t nt = static_cast<size_t>(n) * t;
-    w.sk = cv.take<char>(ski_scratch_bytes(d, m, t));
+    w.sk = cv.take<char>(ski_scratch_bytes(d, m, t, n));
     w.gs = cv.take<char>(ski_grad_scratch_bytes(d, m, t));
     w.b = carve_cg_vectors(cv, n, t);
     w.Bm = cv.take<float>(nt);
@@ -725,7 +725,7 @@ size_t mfgp_ski_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, con
         carve_ski_mll(cv, n, d, grid->m, t, default_max_iter(n, 0));
         return cv.off + 256;
     }
-    cv.take<char>(ski_scratch_bytes(d, grid->m, t));
+    cv.take<char>(ski_scratch_bytes(d, grid->m, t, n));
     if (op == MFGP_OP_CG)
         carve_cg_vectors(cv, n, t);
     else if (op != MFGP_OP_MATVEC && op != MFGP_OP_PREDICT)
@@ -741,7 +741,7 @@ int mfgp_ski_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const mf
     if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_MATVEC, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t, n));
     SkiOp sk;
     const bool ex = grid->explicit_range != 0;
     ABI_CHECK(ski_setup(sk, *kern, X, n, nullptr, 0, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
@@ -760,7 +760,7 @@ int mfgp_ski_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const 
     if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_CG, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t, n));
     CgBufs b = carve_cg_vectors(cv, n, t);
     SkiOp sk;
     const bool ex = grid->explicit_range != 0;
@@ -787,7 +787,7 @@ int mfgp_ski_predict_mean(const mfgp_kernel* kern, const float* X, int64_t n, co
     if (ws_bytes < mfgp_ski_workspace_bytes(MFGP_OP_PREDICT, n, kern->d, t, grid)) return MFGP_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carver cv(ws);
-    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t));
+    void* sk_scratch = cv.take<char>(ski_scratch_bytes(kern->d, grid->m, t, n));
     SkiOp sk;
     const bool ex = grid->explicit_range != 0;
     ABI_CHECK(ski_setup(sk, *kern, X, n, Xs, m, grid->m, ex ? grid->lo : nullptr, ex ? grid->hi : nullptr, t,
