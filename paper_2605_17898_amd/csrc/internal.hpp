@@ -34,6 +34,7 @@ struct SkiOp {
     int* offsets = nullptr;   // [ncell + 1]
     int* perm = nullptr;      // [n]
     double* frac = nullptr;   // [n][d] fractional grid coordinates, in perm order
+    int* pcell = nullptr;     // [n] cell of each point, in perm order
     int64_t ncell = 0;
     int t = 0;
 };

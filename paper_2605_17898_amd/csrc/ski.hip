@@ -347,13 +347,14 @@ __global__ void ski_tile_scan_kernel(int* __restrict__ counts, int64_t len, cons
 // (t_k - floor t_k) at its place pos in its cell's range.
 __global__ void ski_place_kernel(const float* __restrict__ X, int64_t n, SkiGeom g, const double* __restrict__ geo,
                                  const int* __restrict__ offsets, int* __restrict__ cursor, int* __restrict__ perm,
-                                 double* __restrict__ frac) {
+                                 double* __restrict__ frac, int* __restrict__ pcell) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t c = point_cell(X + i * g.d, geo, g);
     if (c < 0) return;
     const int64_t pos = offsets[c] + atomicAdd(cursor + c, 1);
     perm[pos] = static_cast<int>(i);
+    pcell[pos] = static_cast<int>(c);
     for (int k = 0; k < g.d; ++k) {
         double t = (static_cast<double>(X[i * g.d + k]) - geo[k]) / geo[3 + k];
         t = fmin(fmax(t, -4.0), static_cast<double>(g.m[k]) + 4.0);
@@ -409,6 +410,50 @@ __global__ void ski_transpose_kernel(SkiGeom g, const T* __restrict__ V, int t, 
                 }
     }
     grid[idx] = acc;
+}
+
+// The same transpose with one wave per node entry and column (for launches
+// with few entries): the lanes stride over the points of each of the 4^(D-1)
+// cell rows (4 consecutive cells along dimension 0 each, one contiguous range
+// of perm), and a fixed butterfly sums the lanes.  Padding entries get 0.
+template <typename T>
+__global__ void ski_transpose_wave_kernel(SkiGeom g, const T* __restrict__ V, int t, const int* __restrict__ offsets,
+                                          const int* __restrict__ perm, const double* __restrict__ frac,
+                                          const int* __restrict__ pcell, double* __restrict__ grid) {
+    const int64_t idx = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (idx >= g.Lr * t) return;
+    const int c = static_cast<int>(idx / g.Lr);
+    int64_t rest = idx - static_cast<int64_t>(c) * g.Lr;
+    int j[3];
+    bool inside = true;
+    for (int k = 0; k < 3; ++k) {
+        j[k] = static_cast<int>(rest % g.L[k]);
+        rest /= g.L[k];
+        if (k < g.d && j[k] >= g.m[k]) inside = false;
+    }
+    double acc = 0.0;
+    if (inside) {
+        const int n1 = g.d > 1 ? 4 : 1, n2 = g.d > 2 ? 4 : 1;
+        const int64_t s1 = g.m[0] + 3, s2 = s1 * (g.d > 1 ? g.m[1] + 3 : 1);
+        for (int a2 = 0; a2 < n2; ++a2)
+            for (int a1 = 0; a1 < n1; ++a1) {
+                // cells (j0 + a0, j1 + a1, j2 + a2), a0 = 0..3: one contiguous range
+                const int64_t c0 = j[0] + (g.d > 1 ? (j[1] + a1) * s1 : 0) + (g.d > 2 ? (j[2] + a2) * s2 : 0);
+                const int q0 = offsets[c0], q1 = offsets[c0 + 4];
+                for (int q = q0 + lane; q < q1; q += 64) {
+                    const int a0 = static_cast<int>(pcell[q] - c0);   // 0..3 by construction
+                    const int pnt = perm[q];
+                    const double* fq = frac + static_cast<int64_t>(q) * g.d;
+                    double wt = keys1(fq[0], 3 - a0);
+                    if (g.d > 1) wt *= keys1(fq[1], 3 - a1);
+                    if (g.d > 2) wt *= keys1(fq[2], 3 - a2);
+                    acc = fma(wt, static_cast<double>(V[static_cast<int64_t>(pnt) * t + c]), acc);
+                }
+            }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) grid[idx] = acc;
 }
 
 __global__ void fill0i_kernel(int* __restrict__ a, int64_t total) {
@@ -522,7 +567,7 @@ size_t ski_scratch_bytes(int d, const int32_t* m, int t, int64_t n) {
            al(static_cast<size_t>(t) * g.Lc * sizeof(hipfftDoubleComplex)) + al(kBoundBlocks * 6 * sizeof(float)) +
            2 * al(nc * sizeof(int)) + al(static_cast<size_t>(tile_count(nc)) * sizeof(int)) +
            al(static_cast<size_t>(n) * sizeof(int)) +
-           al(static_cast<size_t>(n) * d * sizeof(double)) + 256;
+           al(static_cast<size_t>(n) * d * sizeof(double)) + al(static_cast<size_t>(n) * sizeof(int)) + 256;
 }
 
 // Grid geometry and spectrum for the kernel: the range from X (and Xs) or the
@@ -548,6 +593,7 @@ hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n,
     int* tsum = reinterpret_cast<int*>(take(static_cast<size_t>(tile_count(op.ncell + 1)) * sizeof(int)));
     op.perm = reinterpret_cast<int*>(take(static_cast<size_t>(n) * sizeof(int)));
     op.frac = reinterpret_cast<double*>(take(static_cast<size_t>(n) * k.d * sizeof(double)));
+    op.pcell = reinterpret_cast<int*>(take(static_cast<size_t>(n) * sizeof(int)));
     const bool expl = lo && hi;
     if (!expl) {
         hipLaunchKernelGGL(ski_bounds_stage1, dim3(kBoundBlocks), dim3(256), 0, s, X, n, Xs, Xs ? ms : 0, k.d, op.part);
@@ -569,7 +615,7 @@ hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n,
     hipLaunchKernelGGL(ski_tile_scan_kernel, dim3(static_cast<unsigned>(ntile)), dim3(256), 0, s, op.counts, op.ncell,
                        tsum, op.offsets);
     hipLaunchKernelGGL(ski_place_kernel, dim3(nblk(n)), dim3(256), 0, s, X, n, op.g, op.geo, op.offsets, op.counts,
-                       op.perm, op.frac);
+                       op.perm, op.frac, op.pcell);
     KParams kp{};
     kp.family = k.family;
     kp.s2 = k.outputscale;
@@ -587,6 +633,22 @@ hipError_t ski_setup(SkiOp& op, const mfgp_kernel& k, const float* X, int64_t n,
     return hipGetLastError();
 }
 
+// W^T V into the padded grid: a wave per entry while the launch is small
+// (few entries, many points each), else a thread per entry.
+constexpr int64_t kWaveEntries = int64_t(1) << 17;
+
+template <typename T>
+static hipError_t launch_transpose(const SkiOp& op, const T* V, int t, double* out, hipStream_t s) {
+    const int64_t tot = op.g.Lr * t;
+    if (tot <= kWaveEntries)
+        hipLaunchKernelGGL((ski_transpose_wave_kernel<T>), dim3(nblk(tot * 64)), dim3(256), 0, s, op.g, V, t,
+                           op.offsets, op.perm, op.frac, op.pcell, out);
+    else
+        hipLaunchKernelGGL((ski_transpose_kernel<T>), dim3(nblk(tot)), dim3(256), 0, s, op.g, V, t, op.offsets,
+                           op.perm, op.frac, out);
+    return hipGetLastError();
+}
+
 // One SKI product W_r K_UU W_c^T V over the columns' points Xc [nc] and the
 // rows' points Xr [nr]; writes out (float, + sig2 Vself) or the FP64
 // residual R = B - (product + sig2 X64) when R is non-null (then V = X64).
@@ -597,10 +659,7 @@ static hipError_t ski_product(const SkiOp& op, const float* Xc, int64_t nc, cons
     if (t > op.t) return hipErrorInvalidValue;
     (void)Xc;   // the columns' points are the bucketed training points
     (void)nc;
-    const int64_t tot = op.g.Lr * t;
-    hipLaunchKernelGGL((ski_transpose_kernel<T>), dim3(nblk(tot)), dim3(256), 0, s, op.g, V, t, op.offsets, op.perm,
-                       op.frac, op.grid);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_transpose<T>(op, V, t, op.grid, s);
     if (e != hipSuccess) return e;
     hipfftHandle fwd = fft_plan(op.g, t, true, e);
     if (!fwd) return e;
@@ -655,13 +714,9 @@ hipError_t ski_gradient(const SkiOp& op, const mfgp_kernel& k, const float* X, i
     auto* lamj = reinterpret_cast<hipfftDoubleComplex*>(take(g.Lc * sizeof(hipfftDoubleComplex)));
     double* dots = reinterpret_cast<double*>(take(static_cast<size_t>(t) * sizeof(double)));
     auto* spec = static_cast<hipfftDoubleComplex*>(op.spec);
-    const int64_t tot = g.Lr * t;
     (void)n;
-    hipLaunchKernelGGL((ski_transpose_kernel<float>), dim3(nblk(tot)), dim3(256), 0, s, g, A, t, op.offsets, op.perm,
-                       op.frac, op.grid);
-    hipLaunchKernelGGL((ski_transpose_kernel<float>), dim3(nblk(tot)), dim3(256), 0, s, g, B, t, op.offsets, op.perm,
-                       op.frac, grid2);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_transpose<float>(op, A, t, op.grid, s);
+    if (e == hipSuccess) e = launch_transpose<float>(op, B, t, grid2, s);
     if (e != hipSuccess) return e;
     hipfftHandle fwd = fft_plan(g, t, true, e);
     if (!fwd) return e;
