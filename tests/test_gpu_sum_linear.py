@@ -339,3 +339,22 @@ def test_single_point_compositions(mf, which):
         k = mf.Kernel("rbf", 0.5, 1.3, 0.05) * mf.Kernel("periodic", 0.7, period=0.45)
     out = host(mf.kernel_matvec(k, dev(X), dev(V)))
     np.testing.assert_allclose(out, gp.ky_matvec(o, X.astype(np.float64), V.astype(np.float64)), rtol=1e-6)
+
+
+def test_fused_composite_full_size_sampled_rows(mf):
+    # the composite leg's product: Scale(RBF) + Scale(Periodic) on the rbf100k
+    # points (N = 1e5, d = 4, t = 33), the default FP32 launch (fused Gram
+    # sweep), against the oracle on 256 sampled rows
+    banner("fused rbf+periodic rbf100k full size t=33, 256 sampled rows")
+    w = inputs.rbf100k()
+    o = gp.SumKern([gp.Kern("rbf", w.lengthscale, w.outputscale, 0.0),
+                    gp.Kern("periodic", 1.0, 0.5 * w.outputscale, 0.0, period=0.5)], w.noise)
+    k = (mf.Kernel("rbf", w.lengthscale, w.outputscale, w.noise)
+         + mf.Kernel("periodic", 1.0, 0.5 * w.outputscale, period=0.5))
+    V = np.concatenate([w.y[:, None], w.Z], axis=1).astype(np.float32)
+    out = host(mf.kernel_matvec(k, dev(w.X), dev(V)))
+    rows = np.random.default_rng(1800).choice(w.n, 256, replace=False)
+    ref = gp.ky_matvec_rows(o, w.X.astype(np.float64), V.astype(np.float64), rows)
+    err = np.linalg.norm(out[rows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print(f"sampled-row relative error {err.max():.2e}")
+    assert err.max() <= 1e-5
