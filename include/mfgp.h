@@ -102,7 +102,9 @@ typedef enum {
  * relative error <= 1e-5 against FP64); the bf16 forms are described below. */
 typedef enum {
     MFGP_FP32 = 0,    /* FP32, fastest form that applies:
-                         - square RBF products with n >= 32768 and t = 1 or
+                         - square products of RBF-class terms (RBF, PERIODIC,
+                           their products; a two-term sum of them as one fused
+                           sweep) with n >= 32768 and t = 1 or
                            16 k + {0, 1} (k = 1..4): squared distances from the
                            Gram form |g_i|^2 + |g_j|^2 - 2 g_i.g_j on FP32 MFMA
                            (g = prescaled points minus their mean), checked on
