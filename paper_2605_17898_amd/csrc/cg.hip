@@ -125,7 +125,13 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     const int max_refine = o.max_refine >= 0 ? o.max_refine : 8;
     int check_every = o.check_every;
     if (check_every <= 0) {
-        const double work = static_cast<double>(n) * static_cast<double>(n) * t;
+        // entry-columns of one product: N^2 t for the sweeps; for structured
+        // kernel interpolation its O(N 4^D + L log L) per column
+        double work = static_cast<double>(n) * static_cast<double>(n) * t;
+        if (op.ski) {
+            const double L = static_cast<double>(op.ski->g.Lr);
+            work = (static_cast<double>(n) * (1 << (2 * op.ski->g.d)) + L * std::log2(L)) * t;
+        }
         check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
     }
     // Residual replacement only when the host sees every iteration or every
