@@ -255,6 +255,90 @@ def kernel_matrix(kern: Kern, X1: np.ndarray, X2: np.ndarray) -> np.ndarray:
     return kern.outputscale * shape_from_r2(kern.family, r2)
 
 
+def kernel_matrix_f32(kern: Kern, X1: np.ndarray, X2: np.ndarray, prescaled: bool = False) -> np.ndarray:
+    """K(X1, X2) of an RBF or Matern kernel with every step of each entry in
+    binary32 arithmetic, returned as FP64.
+
+    prescaled=False evaluates the definition as written: differences, scaled
+    squares, their sum, the profile and the outputscale.  prescaled=True
+    evaluates the same kernel from coordinates scaled once per point, as an
+    implementation that prescales its inputs does: with exp(z) = 2^(z log2 e),
+    RBF is 2^(-|u - u'|^2) for u_k = x_k sqrt(log2(e) / 2) / l_k, and
+    Matern-nu's e^(-sqrt(2 nu) rho) is 2^(-q) for q = |u - u'| with
+    u_k = x_k sqrt(2 nu) log2(e) / l_k (its polynomial in sqrt(2 nu) rho =
+    q ln 2).  The difference of two scaled coordinates is then rounded
+    relative to the coordinates' magnitude, not the difference's, so its
+    entries carry the larger error when |u| >> |u - u'| (small lengthscales
+    against the data's range).
+
+    Not a reference value: it differs from kernel_matrix by the binary32
+    roundings of each entry, which is what an FP32 evaluation carries.  It
+    sizes the floor that FP32 entries leave in FP64 checks (residuals,
+    solutions, gradients) of an FP32-entry operator.
+    """
+    if kern.family not in ("rbf", "matern12", "matern32", "matern52"):
+        raise ValueError(kern.family)
+    f32 = np.float32
+    X1 = np.asarray(X1, dtype=f32)
+    X2 = np.asarray(X2, dtype=f32)
+    d = X1.shape[1]
+    ls = np.asarray(kern.ls_vec(d), dtype=np.float64)
+    log2e = 1.0 / math.log(2.0)
+    r2 = np.zeros((X1.shape[0], X2.shape[0]), dtype=f32)
+    if not prescaled:
+        ls32 = ls.astype(f32)
+        for k in range(d):
+            dk = (X1[:, k, None] - X2[None, :, k]) / ls32[k]
+            r2 += dk * dk
+        if kern.family == "rbf":
+            prof = np.exp(f32(-0.5) * r2)
+        else:
+            rho = np.sqrt(r2)
+            nu2 = {"matern12": 1.0, "matern32": 3.0, "matern52": 5.0}[kern.family]
+            a = f32(math.sqrt(nu2)) * rho
+            prof = _matern_poly32(kern.family, a) * np.exp(-a)
+    else:
+        c = math.sqrt(log2e / 2.0) if kern.family == "rbf" else \
+            math.sqrt({"matern12": 1.0, "matern32": 3.0, "matern52": 5.0}[kern.family]) * log2e
+        for k in range(d):
+            sk = f32(c / ls[k])
+            dk = X1[:, k, None] * sk - X2[None, :, k] * sk
+            r2 += dk * dk
+        if kern.family == "rbf":
+            prof = np.exp2(-r2)
+        else:
+            q = np.sqrt(r2)
+            prof = _matern_poly32(kern.family, q * f32(math.log(2.0))) * np.exp2(-q)
+    return (f32(kern.outputscale) * prof.astype(f32)).astype(np.float64)
+
+
+def _matern_poly32(family: str, a: np.ndarray) -> np.ndarray:
+    """Matern polynomial in a = sqrt(2 nu) rho, binary32."""
+    f32 = np.float32
+    if family == "matern12":
+        return np.ones_like(a)
+    if family == "matern32":
+        return f32(1.0) + a
+    return f32(1.0) + a + a * a / f32(3.0)
+
+
+def fp32_entry_floor(kern: Kern, X: np.ndarray, B: np.ndarray, Xsol: np.ndarray, rows, block: int = 256,
+                     prescaled: bool = True):
+    """Per column ||((K32 - K) Xsol)[rows]||_2 / ||B[rows]||_2: the part of an
+    FP64-entry residual of Xsol that comes from evaluating the entries in
+    binary32 (K32 from kernel_matrix_f32, by default in the prescaled form),
+    over sampled rows."""
+    X = np.asarray(X, dtype=np.float64)
+    S = np.asarray(Xsol, dtype=np.float64).reshape(len(X), -1)
+    Bm = np.asarray(B, dtype=np.float64).reshape(len(X), -1)
+    rows = np.asarray(rows, dtype=np.int64)
+    D = np.empty((len(rows), S.shape[1]))
+    for b in range(0, len(rows), block):
+        rb = rows[b:b + block]
+        D[b:b + block] = (kernel_matrix_f32(kern, X[rb], X, prescaled) - kernel_matrix(kern, X[rb], X)) @ S
+    return np.linalg.norm(D, axis=0) / np.linalg.norm(Bm[rows], axis=0)
+
+
 def ky_matrix(kern: Kern, X: np.ndarray) -> np.ndarray:
     """K_y = K_ff + sigma^2 I (Sec. 2)."""
     K = kernel_matrix(kern, X, X)

@@ -358,3 +358,134 @@ def test_bf16_x3_tile_product_is_binary32_accurate():
     e2 = np.abs(bf16.tile_product_x2(K, V) - exact) / absk
     assert e3.max() <= 2.0 ** -26     # measured 2^-29.8 here
     assert e2.max() > 2.0 ** -24      # measured 2^-20.4 here
+    # x2 keeps 16 bits of each operand: every term's error is at most
+    # |k v| (2^-16 for the dropped lo*lo product + 2 * 2^-17 for rounding the
+    # two lo pieces), so |e2| <= 2^-15 of sum |k||v| in the worst case; random
+    # data cancels far below that
+    assert e2.max() <= 2.0 ** -17
+    e1 = np.abs(bf16.tile_product_x1(K, V) - exact) / absk
+    assert 2.0 ** -12 < e1.max() <= 2.0 ** -7   # two RNE roundings of 2^-9 each
+
+
+def _bits(rng, shape, keep):
+    """float32 values with at most `keep` significant bits (exactly
+    representable in that many bits), magnitudes 2^-6..2^2."""
+    m = rng.integers(2 ** (keep - 1), 2 ** keep, size=shape).astype(np.float64)
+    e = rng.integers(-6 - keep, 3 - keep, size=shape).astype(np.float64)
+    s = rng.choice([-1.0, 1.0], size=shape)
+    return (s * m * 2.0 ** e).astype(np.float32)
+
+
+def test_bf16_tile_models_exact_on_short_operands():
+    # Operands with <= 8 significant bits are bfloat16 values: their lo pieces
+    # vanish and the models reduce to exact products.  With one operand of 8
+    # bits and the other of 16, hi + lo reproduces the 16-bit operand exactly,
+    # so x2 must be exact as well: each of its three products is needed (a
+    # model that dropped hi*lo or lo*hi would be off by ~2^-9 here).
+    rng = np.random.default_rng(17)
+    K8, V8 = _bits(rng, (48, 256), 8), _bits(rng, (256, 5), 8)
+    K16, V16 = _bits(rng, (48, 256), 16), _bits(rng, (256, 5), 16)
+    for K, V in ((K8, V8), (K8, V16), (K16, V8)):
+        exact = K.astype(np.float64) @ V.astype(np.float64)
+        np.testing.assert_array_equal(bf16.tile_product_x2(K, V), exact)
+        np.testing.assert_array_equal(bf16.tile_product_x3(K, V), exact)
+    np.testing.assert_array_equal(bf16.tile_product_x1(K8, V8), K8.astype(np.float64) @ V8.astype(np.float64))
+    # 16 x 16 bits: x2 misses exactly the lo*lo product, x3 nothing
+    kh, kl = bf16.split_bf16(K16)
+    vh, vl = bf16.split_bf16(V16)
+    np.testing.assert_array_equal(kh.astype(np.float64) + kl, K16.astype(np.float64))
+    exact = K16.astype(np.float64) @ V16.astype(np.float64)
+    np.testing.assert_allclose(bf16.tile_product_x2(K16, V16) + kl.astype(np.float64) @ vl.astype(np.float64),
+                               exact, rtol=0, atol=1e-15 * np.abs(exact).max())
+    np.testing.assert_array_equal(bf16.tile_product_x3(K16, V16), exact)
+
+
+def test_bf16_x2_bound_catches_a_dropped_cross_product():
+    # A model that loses one of x2's cross products fails the x2 bound above.
+    rng = np.random.default_rng(5)
+    K = rng.uniform(0, 1, (64, 512)).astype(np.float32)
+    V = rng.standard_normal((512, 8)).astype(np.float32)
+    exact = K.astype(np.float64) @ V.astype(np.float64)
+    absk = np.abs(K).astype(np.float64) @ np.abs(V).astype(np.float64)
+    kh, kl = (x.astype(np.float64) for x in bf16.split_bf16(K))
+    vh, vl = (x.astype(np.float64) for x in bf16.split_bf16(V))
+    for wrong in (kh @ vh + kh @ vl, kh @ vh + kl @ vh):
+        assert (np.abs(wrong - exact) / absk).max() > 2.0 ** -17
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+def test_kernel_matrix_f32_is_a_binary32_evaluation(family):
+    # Each entry is the FP64 entry up to a few binary32 roundings: the
+    # differences, squares and sum give r^2 a relative error of at most about
+    # (2d + 1) u (u = 2^-24), the profile turns that into (r^2 / 2) or rho
+    # times it, and the exponential and the products add a few u.
+    rng = np.random.default_rng(33)
+    d = 3
+    X = rng.uniform(0, 1, (120, d))
+    k = gp.Kern(family, np.array([0.3, 0.5, 0.2]), 1.7, 0.01)
+    K = gp.kernel_matrix(k, X, X)
+    K32 = gp.kernel_matrix_f32(k, X, X)
+    r2 = gp.scaled_sqdist(X, X, k.ls_vec(d))
+    u = 2.0 ** -24
+    bound = u * (8.0 + (2 * d + 1) * (r2 + 4.0 * np.sqrt(r2)))
+    rel = np.abs(K32 - K) / K
+    assert np.all(rel <= bound)
+    assert rel.max() > u / 4          # it is not the FP64 evaluation
+    np.testing.assert_array_equal(K32, K32.T)   # the same steps for (i, j) and (j, i)
+    np.testing.assert_allclose(np.diag(K32), 1.7 * np.float32(1.0), rtol=u)
+
+
+def _prescaled_profile(family, q2):
+    """Unit-scale kernel from q^2 = |u - u'|^2 of the prescaled coordinates, FP64."""
+    if family == "rbf":
+        return np.exp2(-q2)
+    q = np.sqrt(q2)
+    a = q * math.log(2.0)
+    poly = {"matern12": 1.0, "matern32": 1.0 + a, "matern52": 1.0 + a + a * a / 3.0}[family]
+    return poly * np.exp2(-q)
+
+
+@pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
+def test_kernel_matrix_f32_prescaled_form(family):
+    # The prescaled form is the same kernel: with u_k = x_k c / l_k (RBF
+    # c = sqrt(log2(e) / 2): 2^(-|u - u'|^2) = exp(-r^2 / 2); Matern-nu
+    # c = sqrt(2 nu) log2(e): 2^(-q) = exp(-sqrt(2 nu) rho)) -- an identity
+    # checked here in FP64.  In binary32 it is the exact kernel at the
+    # coordinates as rounded after scaling, up to the roundings of the
+    # differences, squares, sum and exponential; the rounding of each point's
+    # coordinates is shared by all its entries, so the errors of a product
+    # add up coherently: larger than the direct evaluation's.
+    rng = np.random.default_rng(34)
+    d = 2
+    n = 1500
+    X = rng.uniform(0, 1, (n, d))
+    ls = np.array([0.05, 0.07])
+    k = gp.Kern(family, ls, 1.0, 0.01)
+    log2e = 1.0 / math.log(2.0)
+    c = math.sqrt(log2e / 2.0) if family == "rbf" else \
+        math.sqrt({"matern12": 1.0, "matern32": 3.0, "matern52": 5.0}[family]) * log2e
+    rows = np.arange(0, n, 25)
+    # the identity, FP64
+    Ue = X * (c / ls)
+    q2e = ((Ue[rows, None, :] - Ue[None, :, :]) ** 2).sum(axis=2)
+    K = gp.kernel_matrix(k, X[rows], X)
+    np.testing.assert_allclose(_prescaled_profile(family, q2e), K, rtol=1e-12, atol=1e-300)
+    # binary32: the exact kernel at the rounded scaled coordinates
+    s32 = (c / ls).astype(np.float32)
+    U32 = (X.astype(np.float32) * s32).astype(np.float64)
+    q2 = ((U32[rows, None, :] - U32[None, :, :]) ** 2).sum(axis=2)
+    ref = _prescaled_profile(family, q2)
+    K32p = gp.kernel_matrix_f32(k, X[rows], X, prescaled=True)
+    keep = ref > 1e-6
+    u = 2.0 ** -24
+    bound = u * (8.0 + 8.0 * (q2 + np.sqrt(q2)))
+    rel = np.abs(K32p - ref)[keep] / ref[keep]
+    assert np.all(rel <= bound[keep])
+    # coherent errors: the product error exceeds the direct evaluation's
+    # (1.3-1.6x here with ~10 neighbours per row; about 6x at 5e5 points on
+    # [0, 1]^2 with l = 0.05, where each row has thousands)
+    K32d = gp.kernel_matrix_f32(k, X[rows], X)
+    x = rng.choice([-1.0, 1.0], n) * 100.0
+    ep = np.linalg.norm((K32p - K) @ x)
+    ed = np.linalg.norm((K32d - K) @ x)
+    assert ep > ed, (ep, ed)
