@@ -10,12 +10,16 @@ One step runs, on inputs already resident in HBM:
 `value` is kernel entries generated per second over the timed steps (every
 entry sweep counted once per launch).  The line also carries the CG solve
 time, the MLL+grad time, the roofline of the dominant kernel (the FP32
-entry sweep, timed live with HIP events on its launch stream) and the
-oracle's host throughput on a bounded sample.
+entry sweep, timed live with HIP events on its launch stream), the paper's
+Table 3 product (t = 1) on the same points with its own roofline, the same
+step in the other product forms (median of --compare-reps runs; the BF16
+forms with their VALU-generation and matrix-core contraction rooflines), the
+preconditioned step, and the oracle's host throughput on a bounded sample.
 
 python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x1|bf16x2|bf16x3] [--no-cpu-baseline]
-python bench.py --mode kernel [--reps R]   (profiling helper: R launches of the step's
-    dominant product, K_y V at t = 33, then a 1 GiB device copy whose FETCH_SIZE /
+python bench.py --mode kernel [--reps R] [--precision P] [--cols T]   (profiling helper: R
+    launches of the step's dominant product, K_y V at t = 33 (or the first T columns
+    of [y, probes]) in the chosen form, then a 1 GiB device copy whose FETCH_SIZE /
     WRITE_SIZE calibrate the HBM-traffic counters)
 python bench.py --mode batch   (64 uneven problems, N_b ~ U{2000..30000}, d_b ~ U{1..6},
     ARD RBF, 16 probes: MLL + gradient of every problem in one batched call)
@@ -55,6 +59,12 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # kernels named below.
 HYB_TRAFFIC_BYTES = 2.664e8
 GRAM_TRAFFIC_BYTES = 6.574e8
+TRAFFIC_SOURCE = {
+    "fp32": "profiles/sweep_gram_rbf_d4_t33_rbf100k.md (rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel, "
+            "scaled by a 1 GiB copy's counters; taken from that profile, not measured in this run)",
+    "fp32_direct": "profiles/sweep_hyb_rbf_d4_t33_rbf100k.md (same method; not measured in this run)",
+}
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 # Dominant kernel of the step per precision: (name, bound, HBM bytes per launch).
 STEP_KERNELS = {
     "fp32": ("sweep_gram_kernel<d=4, NT=2, TV=1> (RBF squared distances and the K-tile x V "
@@ -163,6 +173,9 @@ def rbf500k_leg(args) -> int:
                       "adjoint_s": ph["adjoint_ms"] * 1e-3, "status": r["status"],
                       "cg_iters_max": max(i["iters"] for i in r["info"]),
                       "rel_resid_true_max": max(i["rel_resid_true"] for i in r["info"]),
+                      "cg_refinements_max": max(i["refinements"] for i in r["info"]),
+                      "stalls_max": max(i["stalls"] for i in r["info"]),
+                      "precision_final": sorted({i["precision"] for i in r["info"]}),
                       "entries_per_s": allk["entries"] / el, "mll": r["mll"], "logdet": r["logdet"],
                       "grad": r["grad"]}))
     return 0
@@ -422,6 +435,10 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison steps (direct-difference FP32, BF16-x2, BF16-x3, preconditioned)")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--cols", type=int, default=33,
+                    help="kernel mode: right-hand sides of the product ([y, probes][:cols], 1..33)")
+    ap.add_argument("--compare-reps", type=int, default=5,
+                    help="runs of each comparison step (the median is reported)")
     ap.add_argument("--precond", type=int, default=0,
                     help="rbf500k mode: rank of a pivoted-Cholesky preconditioner (0: plain CG)")
     ap.add_argument("--pc-rank", type=int, default=1024,
@@ -461,7 +478,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     if args.mode == "kernel":
-        V = torch.cat([y[:, None], Z], dim=1).contiguous()
+        V = torch.cat([y[:, None], Z], dim=1)[:, :args.cols].contiguous()
         for i in range(args.reps):
             mfgp.kernel_matvec(kern, X, V, precision=args.precision)
             torch.cuda.synchronize()
@@ -545,41 +562,96 @@ def main() -> int:
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": STEP_KERNELS.get(args.precision, ("", "", None))[2],
             "traffic_unit": "bytes per launch",
+            "traffic_source": TRAFFIC_SOURCE.get(args.precision),
+            "peak_note": "MI355X FP32 peak (157.3 TFLOP/s, vector with packed FMA; the FP32 matrix cores have "
+                         "the same rate); the Gram form runs 78 of the 79 FLOP per entry on FP32 MFMA",
             "kernel": STEP_KERNELS.get(args.precision, ("bf16 mfma sweep", "", None))[0],
             "flop_per_entry": 3 * 4 + 1 + 2 * 33,
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
         },
     }
+    if args.precision == "fp32":
+        # The paper's Table 3 product on this geometry: K_y v with one
+        # right-hand side (RBF, d = 4, N = 1e5), median of 5 calls after one
+        # warm-up; the sweep kernel's own time from events on its stream.
+        v1 = y.reshape(-1, 1).contiguous()
+        o1 = torch.empty_like(v1)
+        mfgp.timing_enable(True)
+        ms1 = _median_call_ms(lambda: mfgp.kernel_matvec(kern, X, v1, out=o1))
+        k1 = mfgp.timing_read(mfgp.SWEEP_F32)
+        mfgp.timing_enable(False)
+        sw1 = k1["ms"] / max(k1["launches"], 1)
+        fl1 = 3 * w.d + 1 + 2
+        ach1 = float(w.n) * float(w.n) * fl1 / (sw1 * 1e-3) / 1e12
+        line["table3_t1"] = {
+            "workload": "rbf100k geometry at t = 1 (Table 3's product: RBF, D = 4, one right-hand side)",
+            "call_ms_median": ms1,
+            "entries_per_s": float(w.n) * float(w.n) / (ms1 * 1e-3),
+            "roofline": {"bound": "alu", "kernel": "sweep_gram_kernel<d=4, NT=0, TV=1> (squared distances on "
+                                                   "v_mfma_f32_16x16x4_f32; exp2 and the FMA on the VALU)",
+                         "flop_per_entry": fl1, "achieved": ach1, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach1 / FP32_VECTOR_PEAK_TFLOPS, "launch_avg_ms": sw1},
+        }
+        print(f"[bench] t=1 product: {ms1:.3f} ms per call, sweep {sw1:.3f} ms", file=sys.stderr, flush=True)
     if args.precision == "fp32" and not args.no_compare:
         # The same step with the K-tile x V contraction on the bf16 matrix cores
         # (FP32 entries, FP64-accumulated residual replacement and refinement to
-        # the same 1e-6): the hi/lo split (x2) and the exact three-way split (x3).
+        # the same 1e-6): the hi/lo split (x2) and the exact three-way split (x3);
+        # and the FP32 form with direct differences.  Median of --compare-reps
+        # runs of each (by step time).
         for form in ("fp32_direct", "bf16x2", "bf16x3"):
-            print(f"[bench] {form} comparison step", file=sys.stderr, flush=True)
-            torch.cuda.synchronize()
-            mfgp.timing_enable(True)
-            t1 = time.perf_counter()
-            rb = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=form, want_alpha=True)
-            mfgp.predict_mean(kern, X, Xs, rb["alpha"].float())
-            torch.cuda.synchronize()
-            eb = time.perf_counter() - t1
-            ab = mfgp.timing_read(-1)
-            mb = mfgp.timing_read(mfgp.SWEEP_F32 if form.startswith("fp32") else mfgp.SWEEP_MFMA)
-            phb = mfgp.timing_phases()
-            mfgp.timing_enable(False)
-            line[form] = {
-                "ms_per_step": eb * 1e3,
-                "entries_per_s": ab["entries"] / eb,
-                "cg_solve_s": phb["cg_ms"] * 1e-3,
-                "mll_grad_s": (phb["cg_ms"] + phb["slq_ms"] + phb["adjoint_ms"]) * 1e-3,
-                "cg_iters_max": max(i["iters"] for i in rb["info"]),
-                "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
-                "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
-                "sweep_ms_avg": mb["ms"] / max(mb["launches"], 1),
-                "sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
-                "mll": rb["mll"],
-                "logdet": rb["logdet"],
-            }
+            reps = []
+            for rep in range(args.compare_reps):
+                print(f"[bench] {form} comparison step {rep + 1}/{args.compare_reps}", file=sys.stderr, flush=True)
+                torch.cuda.synchronize()
+                mfgp.timing_enable(True)
+                t1 = time.perf_counter()
+                rb = mfgp.mll_and_grad(kern, X, y, Z=Z, tol=1e-6, precision=form, want_alpha=True)
+                mfgp.predict_mean(kern, X, Xs, rb["alpha"].float())
+                torch.cuda.synchronize()
+                eb = time.perf_counter() - t1
+                ab = mfgp.timing_read(-1)
+                mb = mfgp.timing_read(mfgp.SWEEP_F32 if form.startswith("fp32") else mfgp.SWEEP_MFMA)
+                phb = mfgp.timing_phases()
+                mfgp.timing_enable(False)
+                sweep_ms = mb["ms"] / max(mb["launches"], 1)
+                leg = {
+                    "ms_per_step": eb * 1e3,
+                    "entries_per_s": ab["entries"] / eb,
+                    "cg_solve_s": phb["cg_ms"] * 1e-3,
+                    "mll_grad_s": (phb["cg_ms"] + phb["slq_ms"] + phb["adjoint_ms"]) * 1e-3,
+                    "cg_iters_max": max(i["iters"] for i in rb["info"]),
+                    "cg_refinements_max": max(i["refinements"] for i in rb["info"]),
+                    "rel_resid_true_max": max(i["rel_resid_true"] for i in rb["info"]),
+                    "precision_final": sorted({i["precision"] for i in rb["info"]}),
+                    "sweep_ms_avg": sweep_ms,
+                    "sweep_entries_per_s": mb["entries"] / (mb["ms"] * 1e-3) if mb["ms"] > 0 else 0.0,
+                    "mll": rb["mll"],
+                    "logdet": rb["logdet"],
+                }
+                if form.startswith("bf16") and sweep_ms > 0:
+                    # entries on the VALU (3d + 1 FLOP, + 2 for the FP32 y column),
+                    # the 32 probe columns contracted on the bf16 matrix cores
+                    # (2 FLOP per entry and column), reported against each unit's peak
+                    ent = float(w.n) * float(w.n)
+                    gen = ent * (3 * w.d + 1 + 2) / (sweep_ms * 1e-3) / 1e12
+                    con = ent * 2 * 32 / (sweep_ms * 1e-3) / 1e12
+                    leg["roofline"] = {
+                        "kernel": f"sweep_gmfma_kernel ({form}: Gram distances on v_mfma_f32_32x32x2_f32, "
+                                  "exp2 and the bf16 split on the VALU, K-tile x V on v_mfma_f32_32x32x16_bf16)",
+                        "valu_generation": {"flop_per_entry": 3 * w.d + 3, "achieved": gen,
+                                            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                            "frac": gen / FP32_VECTOR_PEAK_TFLOPS},
+                        "contraction": {"flop_per_entry": 64, "achieved": con, "peak": BF16_MFMA_PEAK_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": con / BF16_MFMA_PEAK_TFLOPS},
+                        "launch_avg_ms": sweep_ms,
+                    }
+                reps.append(leg)
+            reps.sort(key=lambda d: d["ms_per_step"])
+            med = dict(reps[len(reps) // 2])
+            med["reps"] = len(reps)
+            med["ms_per_step_all"] = [d["ms_per_step"] for d in reps]
+            line[form] = med
     if args.precision == "fp32" and not args.no_compare and args.pc_rank > 0:
         # The same MLL + gradient with the rank-k pivoted-Cholesky preconditioner
         # (factor build, probes z ~ N(0, P), preconditioned CG, SLQ, adjoint):

@@ -17,8 +17,12 @@
  *            "host".  The library never allocates: scratch comes from the
  *            caller's workspace `ws` of `ws_bytes` bytes (size it with
  *            mfgp_workspace_bytes; 256-byte alignment is handled inside).  No
- *            pointer is kept after a call returns.  (Exception: the
- *            preconditioned calls' rocBLAS handle, see "preconditioning".)
+ *            pointer is kept after a call returns.  Exceptions, both cached
+ *            per host thread and device on first use: the preconditioned
+ *            calls' rocBLAS handle (see "preconditioning"), and the hipFFT
+ *            plans of the structured-interpolation calls, one per transform
+ *            shape, whose tables and work areas hipFFT allocates in device
+ *            memory; mfgp_release_thread_resources() frees both.
  * Streams    `stream` is a hipStream_t (NULL = the default stream).  Calls
  *            that return only device results are asynchronous on it; calls
  *            that return host values synchronise it before returning.
@@ -69,8 +73,8 @@
  *            kernel's feature dimension mfgp_feature_dim(kern): the input
  *            dimension, twice it for PERIODIC, summed over a sum's terms.
  * Threads    The library is reentrant: no mutable globals besides the
- *            thread-local last HIP error and the preconditioned calls'
- *            thread-local rocBLAS handles.
+ *            thread-local last HIP error and the thread-local rocBLAS handles
+ *            and hipFFT plans (see Memory).
  */
 #ifndef MFGP_H
 #define MFGP_H
@@ -204,6 +208,14 @@ typedef struct {
     int32_t replacements;         /* residual replacements applied (small drift only)       */
     int32_t drift_skips;          /* replacements refused because the recurrence had
                                      drifted more than 10% from the true residual           */
+    int32_t stalls;               /* cycles ended by stagnation: after falling tenfold, the
+                                     recurrence residual made no new minimum for
+                                     max(100, cycle length / 4) iterations                 */
+    int32_t precision;            /* mfgp_precision of the products of the last cycle: the
+                                     requested one, or a more accurate form taken after a
+                                     cycle that stagnated or cut the true residual by less
+                                     than 0.7x (x1 -> x2 -> x3 -> MFGP_FP32_DIRECT; the
+                                     batched solver keeps its form)                       */
 } mfgp_cg_info;
 
 /* Feature dimension of a kernel (the d of the workspace-size queries): kern->d,
@@ -225,6 +237,7 @@ size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t
 int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
                        int32_t t, float* KV, int32_t precision, void* ws, size_t ws_bytes,
                        void* stream);
+
 
 /* R = B - K_y Xsol with the library's FP32 kernel entries accumulated in FP64
  * (the recomputed residual of the solver).  B [n,t] float32, Xsol [n,t]
@@ -528,6 +541,13 @@ int mfgp_num_params(const mfgp_kernel* kern);
 const char* mfgp_status_string(int status);
 int mfgp_last_hip_error(void);
 int mfgp_version(void);
+
+/* Frees the calling thread's cached library resources on every device: the
+ * rocBLAS handles of the preconditioned calls and the hipFFT plans (with
+ * their device memory) of the structured-interpolation calls.  Later calls
+ * create them again.  Call it with no library work of this thread in flight.
+ * Returns MFGP_ERR_HIP if switching devices fails. */
+int mfgp_release_thread_resources(void);
 
 #ifdef __cplusplus
 }

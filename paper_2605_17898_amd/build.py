@@ -49,6 +49,7 @@ UNITS = [
     ("sum.hip", "sum.o", []),
     ("ski.hip", "ski.o", []),
     ("precond.hip", "precond.o", []),
+    ("prod.hip", "prod.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]
 

@@ -75,8 +75,9 @@ static inline unsigned nb(int64_t total) { return static_cast<unsigned>((total +
 
 static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
-// A product term: RBF factors and at most one periodic factor within
-// MFGP_MAX_D features (other families are valid but not provided).
+// A product term: factors of any family, at most one periodic, within
+// MFGP_MAX_D features in all (d per RBF, Matern or Linear factor, 2d for the
+// periodic one).
 static int check_product(const mfgp_kernel* k, int d) {
     int nf = 0, nper = 0, feats = 0;
     for (const mfgp_kernel* q = k; q; q = q->times) {
@@ -95,8 +96,6 @@ static int check_product(const mfgp_kernel* k, int d) {
         for (int j = 0; j < nl; ++j)
             if (!finite_pos(q->lengthscale[j])) return MFGP_ERR_ARG;
     }
-    for (const mfgp_kernel* q = k; q; q = q->times)
-        if (q->family != MFGP_RBF && q->family != MFGP_PERIODIC) return MFGP_UNSUPPORTED;
     if (nper > 1 || feats > MFGP_MAX_D) return MFGP_UNSUPPORTED;
     if (!finite_pos(k->outputscale)) return MFGP_ERR_ARG;
     return MFGP_OK;
@@ -135,11 +134,33 @@ static int check_kernel(const mfgp_kernel* k, bool need_noise) {
     return MFGP_OK;
 }
 
-// The preconditioned calls take one stationary or periodic term.
+// A product with a Matern or Linear factor: the general product of prod.hip,
+// evaluated by the FP32 VALU sweeps only.
+static bool general_product(const mfgp_kernel* k) {
+    if (!k->times) return false;
+    for (const mfgp_kernel* q = k; q; q = q->times)
+        if (q->family != MFGP_RBF && q->family != MFGP_PERIODIC) return true;
+    return false;
+}
+
+static bool any_general_product(const mfgp_kernel* k) {
+    for (const mfgp_kernel* q = k; q; q = q->next)
+        if (general_product(q)) return true;
+    return false;
+}
+
+// The preconditioned calls take one stationary or periodic term (or a product
+// of RBF and periodic factors).
 static int check_precond_kernel(const mfgp_kernel* k, bool need_noise) {
     const int st = check_kernel(k, need_noise);
     if (st != MFGP_OK) return st;
-    if (k->next || k->family == MFGP_LINEAR) return MFGP_UNSUPPORTED;
+    if (k->next || k->family == MFGP_LINEAR || general_product(k)) return MFGP_UNSUPPORTED;
+    return MFGP_OK;
+}
+
+// The bf16 product forms do not take general products.
+static int check_kernel_precision(const mfgp_kernel* k, int precision) {
+    if (!is_fp32_class(precision) && any_general_product(k)) return MFGP_UNSUPPORTED;
     return MFGP_OK;
 }
 
@@ -292,6 +313,32 @@ static int noise_index(const mfgp_kernel* k) {
 // Feature dimension of the prescaled coordinates (the d of the size queries).
 static int feature_dim(const mfgp_kernel* k) { return chain_feature_dim(*k); }
 
+static int check_matvec_args(const mfgp_kernel* kern, const float* X, int64_t n, const float* V, int t,
+                             const float* KV, int precision) {
+    int st = check_kernel(kern, false);
+    if (st != MFGP_OK) return st;
+    if (!X || !V || !KV || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
+    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
+    if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
+    if ((st = check_kernel_precision(kern, precision)) != MFGP_OK) return st;
+    return check_precision_cols(precision, t);
+}
+
+// The product on a workspace of at least mfgp_workspace_bytes(MFGP_OP_MATVEC)
+// bytes; every scratch value is written by a kernel of this call before it is
+// read, so the workspace needs no clearing between calls.
+static int matvec_into(const mfgp_kernel* kern, const float* X, int64_t n, const float* V, int t, float* KV,
+                       int precision, void* ws, hipStream_t s) {
+    Carver cv(ws);
+    MatvecWs w = carve_matvec(cv, n, feature_dim(kern), t, precision);
+    OpChain ch;
+    make_chain(ch, *kern, X, n, w.U);
+    const Operator& op = ch.head();
+    ABI_CHECK(prescale_chain(ch, s));
+    ABI_CHECK(apply_sum(op, nullptr, n, V, t, KV, true, V, w.scratch, w.sum, precision, s));
+    return MFGP_OK;
+}
+
 }  // namespace mfgp
 
 using namespace mfgp;
@@ -301,6 +348,13 @@ extern "C" {
 int mfgp_version(void) { return 100; }
 
 int mfgp_last_hip_error(void) { return g_last_hip; }
+
+int mfgp_release_thread_resources(void) {
+    hipError_t e = release_fft_plans();
+    const hipError_t e2 = release_blas_handles();
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? MFGP_OK : hip_fail(e);
+}
 
 const char* mfgp_status_string(int status) {
     switch (status) {
@@ -351,23 +405,12 @@ size_t mfgp_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t t, int32_t
 int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
                        int32_t t, float* KV, int32_t precision, void* ws, size_t ws_bytes,
                        void* stream) {
-    int st = check_kernel(kern, false);
+    int st = check_matvec_args(kern, X, n, V, t, KV, precision);
     if (st != MFGP_OK) return st;
-    if (!X || !V || !KV || !ws || n < 1 || t < 1 || KV == V) return MFGP_ERR_ARG;
-    if (precision < MFGP_FP32 || precision > MFGP_FP32_GRAM) return MFGP_ERR_ARG;
-    if (!precision_supported(precision)) return MFGP_UNSUPPORTED;
-    if ((st = check_precision_cols(precision, t)) != MFGP_OK) return st;
+    if (!ws) return MFGP_ERR_ARG;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, feature_dim(kern), t, precision, 0))
         return MFGP_ERR_WORKSPACE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Carver cv(ws);
-    MatvecWs w = carve_matvec(cv, n, feature_dim(kern), t, precision);
-    OpChain ch;
-    make_chain(ch, *kern, X, n, w.U);
-    const Operator& op = ch.head();
-    ABI_CHECK(prescale_chain(ch, s));
-    ABI_CHECK(apply_sum(op, nullptr, n, V, t, KV, true, V, w.scratch, w.sum, precision, s));
-    return MFGP_OK;
+    return matvec_into(kern, X, n, V, t, KV, precision, ws, static_cast<hipStream_t>(stream));
 }
 
 int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const float* B,
@@ -403,6 +446,7 @@ int mfgp_cg_solve(const mfgp_kernel* kern, const float* X, int64_t n, const floa
     int st = check_kernel(kern, true);
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if ((st = check_kernel_precision(kern, opts->precision)) != MFGP_OK) return st;
     if (!X || !B || !Xsol || !ws || n < 1 || t < 1) return MFGP_ERR_ARG;
     if ((st = check_precision_cols(opts->precision, t)) != MFGP_OK) return st;
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_CG, n, feature_dim(kern), t, opts->precision, opts->max_iter))
@@ -472,6 +516,7 @@ int mfgp_predict_variance(const mfgp_kernel* kern, const float* X, int64_t n, co
     int st = check_kernel(kern, true);
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if ((st = check_kernel_precision(kern, opts->precision)) != MFGP_OK) return st;
     if (!X || !Xs || !var || !ws || n < 1 || m < 1 || p < 1) return MFGP_ERR_ARG;
     if ((st = check_precision_cols(opts->precision, p)) != MFGP_OK) return st;
     if (m > 0x7fffffff) return MFGP_UNSUPPORTED;
@@ -601,6 +646,7 @@ int mfgp_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n, const 
     int st = check_kernel(kern, true);
     if (st != MFGP_OK) return st;
     if ((st = check_opts(opts)) != MFGP_OK) return st;
+    if ((st = check_kernel_precision(kern, opts->precision)) != MFGP_OK) return st;
     if (!X || !y || !mll || !ws || n < 1 || num_probes < 1) return MFGP_ERR_ARG;
     const int p = num_probes;
     const int t = p + 1;

@@ -215,12 +215,14 @@ static hipError_t adjoint_f(int D, int tb, const float* U, const float* A, int l
     }
 }
 
+// Per-block partial width: d + 1 sums for the single families, at most
+// d + 2 (a general product: per feature, G_s, G_p).
 size_t adjoint_scratch_doubles(int64_t n, int d, int t) {
     const SweepPlan p = plan_sweep(n, n);
-    const size_t part = static_cast<size_t>(p.rowblocks) * p.chunks * (d + 1);
+    const size_t part = static_cast<size_t>(p.rowblocks) * p.chunks * (d + 2);
     const int tb = column_block(t);
     const size_t pack = tb == t ? 0 : (static_cast<size_t>(n) * tb + 1) / 2 + 64;
-    return part + pack + 2 * (d + 1) + 128;
+    return part + pack + 2 * (d + 2) + 128;
 }
 
 // sums_host[0..d-1] = G_k, sums_host[d] = G_s (see the file comment); for the
@@ -230,13 +232,13 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
                         const double* colw_host, double* sums_host, double* scratch,
                         hipStream_t s) {
     const int d = op.d;
-    const int width = op.periodic ? op.din + op.dextra + 2 : d + 1;
+    const int width = op.general ? d + 2 : (op.periodic ? op.din + op.dextra + 2 : d + 1);
     const int64_t n = op.n;
     const SweepPlan p = plan_sweep(n, n);
     const int nblocks = p.rowblocks * p.chunks;
     double* partial = scratch;
-    double* total = scratch + static_cast<size_t>(nblocks) * (d + 1) + 64;
-    float* pack = reinterpret_cast<float*>(total + 2 * (d + 1) + 64);
+    double* total = scratch + static_cast<size_t>(nblocks) * (d + 2) + 64;
+    float* pack = reinterpret_cast<float*>(total + 2 * (d + 2) + 64);
     int first = 1;
     for (int c0 = 0; c0 < t;) {
         const int tb = column_block(t - c0);
@@ -250,7 +252,9 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
         }
         hipError_t e;
         void* tok = timing_begin(s);
-        if (op.periodic) {
+        if (op.general) {
+            e = adjoint_prod(op, tb, A, t, c0, w.w, bb, p, partial, s);
+        } else if (op.periodic) {
             e = adjoint_periodic(op.din, op.dextra, tb, op.X, op.U, A, t, c0, w, bb, n, p, partial, s);
         } else switch (op.family) {
             case MFGP_RBF: e = adjoint_f<MFGP_RBF>(d, tb, op.U, A, t, c0, w, bb, n, p, partial, s); break;

@@ -21,6 +21,7 @@
 #include <thread>
 #include <vector>
 
+#include "stall.hpp"
 #include "adjoint_kernels.hpp"
 #include "cg.hpp"
 #include "hybrid_kernels.hpp"
@@ -68,10 +69,25 @@ __global__ void reset_counter_kernel(int* counter) {
     if (threadIdx.x == 0) *counter = 0;
 }
 
+// A problem is live while any of its t columns is active in CG (`live` holds
+// the per-column active flags, problem b's at [b t, b t + t)).  The persistent
+// sweeps skip the tiles of problems that are not (nothing of theirs is read
+// afterwards: the CG update leaves inactive columns untouched); `live` is
+// NULL outside CG (autotuner), where every tile runs.  The flags were written
+// by the previous launch on the stream; the check is uniform over the
+// workgroup (the tile index is), so no barrier is skipped by part of it.
+__device__ __forceinline__ bool problem_live(const int* __restrict__ live, int b, int t) {
+    if (!live) return true;
+    int any = 0;
+    for (int c = 0; c < t; ++c) any |= live[b * t + c];
+    return any != 0;
+}
+
 template <int FAM, int TB>
 __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(
     const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
-    const float* __restrict__ U, const float* __restrict__ V, float* __restrict__ partial) {
+    const float* __restrict__ U, const float* __restrict__ V, float* __restrict__ partial,
+    const int* __restrict__ live) {
     __shared__ int s_k;
     for (;;) {
         if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
@@ -80,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(
         __syncthreads();
         if (k >= ntiles) break;
         const BTile tl = queue[k];
+        if (!problem_live(live, tl.b, TB)) continue;
         const BProb pb = probs[tl.b];
         const int64_t i = static_cast<int64_t>(tl.rb) * kBlock + threadIdx.x;
         const int64_t ii = i < pb.n ? i : pb.n - 1;
@@ -159,7 +176,8 @@ __global__ __launch_bounds__(kBlock) void batch_adjoint_kernel(
 template <int FAM, int NT, int TV>
 __global__ __launch_bounds__(kBlock) void batch_hyb_kernel(
     const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
-    const float* __restrict__ U, const float* __restrict__ F, int t, float* __restrict__ partial) {
+    const float* __restrict__ U, const float* __restrict__ F, int t, float* __restrict__ partial,
+    const int* __restrict__ live) {
     __shared__ int s_k;
     for (;;) {
         if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
@@ -168,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void batch_hyb_kernel(
         __syncthreads();
         if (k >= ntiles) break;
         const BTile tl = queue[k];
+        if (!problem_live(live, tl.b, t)) continue;
         const BProb pb = probs[tl.b];
         const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;
         const float* Ub = U + pb.u_off;
@@ -215,7 +234,8 @@ template <int FAM, int NT, int SPLIT, int TV>
 __global__ __launch_bounds__(kBlock) void batch_mfma_kernel(
     const BTile* __restrict__ queue, int ntiles, int* counter, const BProb* __restrict__ probs,
     const float* __restrict__ U, const bf16x8* __restrict__ Gh, const bf16x8* __restrict__ Gm,
-    const bf16x8* __restrict__ Gl, const float* __restrict__ Gy, int t, float* __restrict__ partial) {
+    const bf16x8* __restrict__ Gl, const float* __restrict__ Gy, int t, float* __restrict__ partial,
+    const int* __restrict__ live) {
     __shared__ int s_k;
     for (;;) {
         if (threadIdx.x == 0) s_k = atomicAdd(counter, 1);
@@ -224,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void batch_mfma_kernel(
         __syncthreads();
         if (k >= ntiles) break;
         const BTile tl = queue[k];
+        if (!problem_live(live, tl.b, t)) continue;
         const BProb pb = probs[tl.b];
         const int64_t j0 = static_cast<int64_t>(tl.ch) * pb.jchunk;   // multiple of 16
         const float* Ub = U + pb.u_off;
@@ -293,14 +314,18 @@ __device__ __forceinline__ int find_problem(const int64_t* __restrict__ row_offs
 }
 
 // out[r, c] = s2_b sum_ch partial[tile(b, rb, ch)][li][c] + sig2_b Vself[r, c]
+// Columns that are not active in CG (live non-NULL) are not needed: skipped.
 __global__ void batch_reduce_kernel(const float* __restrict__ partial, const BProb* __restrict__ probs,
                                     const int64_t* __restrict__ row_offs, int nprob, int64_t rows,
-                                    int t, const float* __restrict__ Vself, float* __restrict__ out) {
+                                    int t, const float* __restrict__ Vself, float* __restrict__ out,
+                                    const int* __restrict__ live) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= rows * t) return;
     const int64_t r = idx / t;
     const int c = static_cast<int>(idx % t);
-    const BProb pb = probs[find_problem(row_offs, nprob, r)];
+    const int b = find_problem(row_offs, nprob, r);
+    if (live && !live[b * t + c]) return;
+    const BProb pb = probs[b];
     const int64_t i = r - pb.row_off;
     const int64_t rb = i / kBlock;
     const int64_t li = i % kBlock;
@@ -680,14 +705,14 @@ static int persistent_grid(int ntiles, int cus) {
 
 template <int FAM>
 static hipError_t launch_bsweep_f(int tb, const BatchWs& w, int ntiles, const float* V, float* part,
-                                  hipStream_t s) {
+                                  const int* live, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
     switch (tb) {
 #define MFGP_C(TBV)                                                                                 \
     case TBV:                                                                                       \
         hipLaunchKernelGGL((batch_sweep_kernel<FAM, TBV>), dim3(grid), dim3(kBlock), 0, s, w.queue, \
-                           ntiles, w.counter, w.probs, w.U, V, part);                              \
+                           ntiles, w.counter, w.probs, w.U, V, part, live);                        \
         return hipGetLastError();
         MFGP_TB_LIST(MFGP_C)
 #undef MFGP_C
@@ -697,13 +722,13 @@ static hipError_t launch_bsweep_f(int tb, const BatchWs& w, int ntiles, const fl
 
 template <int FAM>
 static hipError_t launch_bhyb_f(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, float* part,
-                                hipStream_t s) {
+                                const int* live, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
 #define MFGP_HB(NTV, TVV)                                                                           \
     if (P.hyb_nt == NTV && P.hyb_tv == TVV) {                                                       \
         hipLaunchKernelGGL((batch_hyb_kernel<FAM, NTV, TVV>), dim3(grid), dim3(kBlock), 0, s, w.queue, \
-                           ntiles, w.counter, w.probs, w.U, w.frag, P.t, part);                     \
+                           ntiles, w.counter, w.probs, w.U, w.frag, P.t, part, live);               \
         return hipGetLastError();                                                                   \
     }
     MFGP_HB(1, 0) MFGP_HB(1, 1) MFGP_HB(2, 0) MFGP_HB(2, 1)
@@ -713,27 +738,27 @@ static hipError_t launch_bhyb_f(const mfgp_batch_plan_s& P, const BatchWs& w, in
 
 // Pack the fragments of V for all problems, then run the persistent hybrid sweep.
 static hipError_t launch_bhyb(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, const float* V,
-                              float* part, hipStream_t s) {
+                              float* part, const int* live, hipStream_t s) {
     const int64_t total = P.frag_off.back();
     hipLaunchKernelGGL(batch_pack_hfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
                        s, V, w.probs, w.foffs, P.nprob, P.t, P.hyb_nt, P.hyb_tv, w.frag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (P.family) {
-        case MFGP_RBF: return launch_bhyb_f<MFGP_RBF>(P, w, ntiles, part, s);
-        case MFGP_MATERN12: return launch_bhyb_f<MFGP_MATERN12>(P, w, ntiles, part, s);
-        case MFGP_MATERN32: return launch_bhyb_f<MFGP_MATERN32>(P, w, ntiles, part, s);
-        default: return launch_bhyb_f<MFGP_MATERN52>(P, w, ntiles, part, s);
+        case MFGP_RBF: return launch_bhyb_f<MFGP_RBF>(P, w, ntiles, part, live, s);
+        case MFGP_MATERN12: return launch_bhyb_f<MFGP_MATERN12>(P, w, ntiles, part, live, s);
+        case MFGP_MATERN32: return launch_bhyb_f<MFGP_MATERN32>(P, w, ntiles, part, live, s);
+        default: return launch_bhyb_f<MFGP_MATERN52>(P, w, ntiles, part, live, s);
     }
 }
 
 static hipError_t launch_bsweep(int family, int tb, const BatchWs& w, int ntiles, const float* V,
-                                float* part, hipStream_t s) {
+                                float* part, const int* live, hipStream_t s) {
     switch (family) {
-        case MFGP_RBF: return launch_bsweep_f<MFGP_RBF>(tb, w, ntiles, V, part, s);
-        case MFGP_MATERN12: return launch_bsweep_f<MFGP_MATERN12>(tb, w, ntiles, V, part, s);
-        case MFGP_MATERN32: return launch_bsweep_f<MFGP_MATERN32>(tb, w, ntiles, V, part, s);
-        default: return launch_bsweep_f<MFGP_MATERN52>(tb, w, ntiles, V, part, s);
+        case MFGP_RBF: return launch_bsweep_f<MFGP_RBF>(tb, w, ntiles, V, part, live, s);
+        case MFGP_MATERN12: return launch_bsweep_f<MFGP_MATERN12>(tb, w, ntiles, V, part, live, s);
+        case MFGP_MATERN32: return launch_bsweep_f<MFGP_MATERN32>(tb, w, ntiles, V, part, live, s);
+        default: return launch_bsweep_f<MFGP_MATERN52>(tb, w, ntiles, V, part, live, s);
     }
 }
 
@@ -767,13 +792,14 @@ static hipError_t launch_badj(int family, int tb, const BatchWs& w, int ntiles, 
 // One batched product AP = K_y P (persistent sweep + fixed-order reduce), timed.
 template <int FAM>
 static hipError_t launch_bmfma_f(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, int nt, int split,
-                                 int tv, float* part, hipStream_t s) {
+                                 int tv, float* part, const int* live, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>(persistent_grid(ntiles, w.cus));
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, w.counter);
 #define MFGP_GB(NTV, SPV, TVV)                                                                        \
     if (nt == NTV && split == SPV && tv == TVV) {                                                     \
         hipLaunchKernelGGL((batch_mfma_kernel<FAM, NTV, SPV, TVV>), dim3(grid), dim3(kBlock), 0, s,   \
-                           w.queue, ntiles, w.counter, w.probs, w.U, w.gh, w.gm, w.gl, w.gy, P.t, part); \
+                           w.queue, ntiles, w.counter, w.probs, w.U, w.gh, w.gm, w.gl, w.gy, P.t, part, \
+                           live);                                                                     \
         return hipGetLastError();                                                                     \
     }
     MFGP_GB(1, 0, 0) MFGP_GB(1, 1, 0) MFGP_GB(1, 2, 0) MFGP_GB(1, 0, 1) MFGP_GB(1, 1, 1) MFGP_GB(1, 2, 1)
@@ -783,7 +809,7 @@ static hipError_t launch_bmfma_f(const mfgp_batch_plan_s& P, const BatchWs& w, i
 
 // Pack the BF16 fragments of all problems, then run the persistent BF16 sweep.
 static hipError_t launch_bmfma(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, const float* V,
-                               float* part, hipStream_t s) {
+                               float* part, const int* live, hipStream_t s) {
     const int tv = vec_cols(P.t), nt = col_tiles(P.t), split = split_of(P.precision);
     const int64_t total = std::max<int64_t>(P.gfrag_off.back(), P.y_off.back());
     hipLaunchKernelGGL(batch_pack_bfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
@@ -791,10 +817,10 @@ static hipError_t launch_bmfma(const mfgp_batch_plan_s& P, const BatchWs& w, int
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (P.family) {
-        case MFGP_RBF: return launch_bmfma_f<MFGP_RBF>(P, w, ntiles, nt, split, tv, part, s);
-        case MFGP_MATERN12: return launch_bmfma_f<MFGP_MATERN12>(P, w, ntiles, nt, split, tv, part, s);
-        case MFGP_MATERN32: return launch_bmfma_f<MFGP_MATERN32>(P, w, ntiles, nt, split, tv, part, s);
-        default: return launch_bmfma_f<MFGP_MATERN52>(P, w, ntiles, nt, split, tv, part, s);
+        case MFGP_RBF: return launch_bmfma_f<MFGP_RBF>(P, w, ntiles, nt, split, tv, part, live, s);
+        case MFGP_MATERN12: return launch_bmfma_f<MFGP_MATERN12>(P, w, ntiles, nt, split, tv, part, live, s);
+        case MFGP_MATERN32: return launch_bmfma_f<MFGP_MATERN32>(P, w, ntiles, nt, split, tv, part, live, s);
+        default: return launch_bmfma_f<MFGP_MATERN52>(P, w, ntiles, nt, split, tv, part, live, s);
     }
 }
 
@@ -803,18 +829,19 @@ static bool is_bf16(int precision) {
 }
 
 // One batched entry sweep in the precision of the current call.
+// live: the CG active flags (tiles of finished problems are skipped), or NULL.
 static hipError_t launch_batched_sweep(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
-                                       const float* V, float* part, hipStream_t s) {
-    if (is_bf16(P.precision)) return launch_bmfma(P, w, ntiles, V, part, s);
+                                       const float* V, float* part, const int* live, hipStream_t s) {
+    if (is_bf16(P.precision)) return launch_bmfma(P, w, ntiles, V, part, live, s);
     if (P.hybrid && (P.precision == MFGP_FP32 || P.precision == MFGP_FP32_DIRECT))
-        return launch_bhyb(P, w, ntiles, V, part, s);
-    return launch_bsweep(P.family, P.t, w, ntiles, V, part, s);
+        return launch_bhyb(P, w, ntiles, V, part, live, s);
+    return launch_bsweep(P.family, P.t, w, ntiles, V, part, live, s);
 }
 
 static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles,
-                              const float* V, float* out, hipStream_t s) {
+                              const float* V, float* out, const int* live, hipStream_t s) {
     void* tok = timing_begin(s);
-    hipError_t e = launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+    hipError_t e = launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), live, s);
     if (e != hipSuccess) return e;
     double ent = 0.0, fl = 0.0;
     if (timing_on())
@@ -826,7 +853,7 @@ static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int 
     timing_end(tok, s, is_bf16(P.precision) ? kSweepMfma : kSweepF32, ent, fl);
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(nblocks(P.rows * P.t)), dim3(256), 0, s,
                        reinterpret_cast<const float*>(w.part), w.probs, w.row_offs, P.nprob, P.rows, P.t,
-                       V, out);
+                       V, out, live);
     return hipGetLastError();
 }
 
@@ -859,7 +886,7 @@ static hipError_t bdots_df(const mfgp_batch_plan_s& P, const BatchWs& w, const d
 static hipError_t batch_iteration(const mfgp_batch_plan_s& P, const BatchWs& w, const CgState& st,
                                   int ntiles, double tol, hipStream_t s) {
     const int T = P.nprob * P.t;
-    hipError_t e = batch_apply(P, w, ntiles, st.p, st.ap, s);
+    hipError_t e = batch_apply(P, w, ntiles, st.p, st.ap, st.active, s);
     if (e != hipSuccess) return e;
     e = bdots_ff(P, w, st.p, st.ap, st.pap, s);
     if (e != hipSuccess) return e;
@@ -909,7 +936,7 @@ static int tune_tiles(mfgp_batch_plan_s& P, const BatchWs& w, const float* V, hi
         int st = upload_tiles(P, w, J, ntiles, probs, queue, s);
         if (st != MFGP_OK) return st;
         auto sweep = [&]() {
-            return launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), s);
+            return launch_batched_sweep(P, w, ntiles, V, reinterpret_cast<float*>(w.part), nullptr, s);
         };
         B_CHECK(sweep());  // warm
         B_CHECK(hipEventRecord(a, s));
@@ -1212,8 +1239,14 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     std::vector<int> h_active(T), h_iters(T), h_status(T), h_restart(T), h_refine(T, 0), h_lan(T);
     std::vector<double> h_relt(T), h_rr(T), h_b2(T), h_rep(T), h_cross(T);
     std::vector<int> h_norepl(T, 0), h_nrep(T, 0), h_skips(T, 0);
+    // stagnation (stall.hpp): a stagnated cycle ends and is refined (the
+    // batched sweep keeps its precision: no fallback to another form)
+    std::vector<StallTracker> h_stall(T);
+    std::vector<int> h_nstall(T, 0);
     B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    B_CHECK2(hipStreamSynchronize(s));
+    for (int q = 0; q < T; ++q) h_stall[q].begin(0, h_rep[q]);
     const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
     int next_report = report_every;
     for (;;) {
@@ -1221,6 +1254,17 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         B_CHECK2(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipStreamSynchronize(s));
+        bool stop = false;
+        for (int q = 0; q < T; ++q) {
+            if (!h_active[q] || h_iters[q] >= max_iter) continue;
+            if (h_stall[q].update(h_iters[q], h_rr[q])) {
+                h_active[q] = 0;
+                h_nstall[q] += 1;
+                stop = true;
+            }
+        }
+        if (stop)
+            B_CHECK2(hipMemcpyAsync(st.active, h_active.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
         // Residual replacement (as in the single-problem solver): a tenfold drop
         // since the last true residual triggers it; active columns that fell at
         // least 1.5x join; only problems with a flagged column recompute.
@@ -1321,8 +1365,12 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
         B_CHECK2(hipMemcpyAsync(w.logflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
         B_CHECK2(hipMemcpyAsync(h_rep.data(), w.tmp + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
-        for (int q = 0; q < T; ++q)
-            if (h_restart[q]) h_norepl[q] = 0;   // a fresh cycle starts without drift
+        B_CHECK2(hipStreamSynchronize(s));
+        for (int q = 0; q < T; ++q) {
+            if (!h_restart[q]) continue;
+            h_norepl[q] = 0;   // a fresh cycle starts without drift
+            h_stall[q].begin(h_iters[q], h_rep[q]);
+        }
     }
     cleanup();
     B_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1344,6 +1392,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         inf[q].rel_resid_true = h_relt[q];
         inf[q].replacements = h_nrep[q];
         inf[q].drift_skips = h_skips[q];
+        inf[q].stalls = h_nstall[q];
+        inf[q].precision = opts->precision;
     }
     if (info) std::memcpy(info, inf.data(), T * sizeof(mfgp_cg_info));
     timing_phase(0, std::chrono::duration<double, std::milli>(clock::now() - t0).count());

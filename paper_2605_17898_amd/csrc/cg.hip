@@ -26,6 +26,7 @@
 // floors at a few 1e-6.
 #include "cg.hpp"
 #include "precond.hpp"
+#include "stall.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -62,10 +63,12 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
     b.ints = cv.take<int>(6 * static_cast<size_t>(t));
     b.dots = cv.take<double>(dots_scratch_doubles(n, t));
     b.resid = cv.take<double>(resid_scratch_doubles(n, t));
-    if (is_fp32_class(precision))
-        b.apply = reinterpret_cast<float*>(cv.take<char>(apply_fp32_scratch_bytes(n, n, t, precision)));
-    else
-        b.apply = reinterpret_cast<float*>(cv.take<char>(mfma_scratch_bytes(n, n, t, precision)));
+    // room for the product forms the solver may fall back to (stall.hpp)
+    size_t apply = 0;
+    for (int p = precision; p >= 0; p = more_accurate_precision(p))
+        apply = std::max(apply, is_fp32_class(p) ? apply_fp32_scratch_bytes(n, n, t, p)
+                                                 : mfma_scratch_bytes(n, n, t, p));
+    b.apply = reinterpret_cast<float*>(cv.take<char>(apply));
     b.sum = cv.take<char>(sum_scratch_bytes(n, t));
     return b;
 }
@@ -161,9 +164,20 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     std::vector<double> h_relt(t), h_rr(t), h_b2(t), h_rep(t, 0.0);
     std::vector<int> h_flag(t, 0), h_norepl(t, 0), h_nrep(t, 0), h_skips(t, 0);
     std::vector<double> h_cross(t);
+    // stagnation and precision fallback (stall.hpp): per-column trackers, the
+    // true residual at each cycle's start, cycles ended by stagnation
+    std::vector<StallTracker> h_stall(t);
+    std::vector<double> h_t0(t, 1.0);
+    std::vector<int> h_nstall(t, 0), h_gaveup(t, 0), h_stalled(t, 0);
+    int precision = o.precision;
     int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
     CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < t; ++c) {
+        h_stall[c].begin(0, h_rep[c]);
+        if (h_b2[c] > 0.0) h_t0[c] = std::sqrt(h_rep[c] / h_b2[c]);
+    }
     const int report_every = o.progress_every > 0 ? o.progress_every : 100;
     int next_report = report_every;
 
@@ -172,6 +186,19 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
+        // A column whose recurrence has stagnated ends its cycle here.
+        bool stop = false;
+        for (int c = 0; c < t; ++c) {
+            if (!h_active[c] || h_iters[c] >= max_iter) continue;
+            if (h_stall[c].update(h_iters[c], h_rr[c])) {
+                h_active[c] = 0;
+                h_nstall[c] += 1;
+                h_stalled[c] = 1;
+                stop = true;
+            }
+        }
+        if (stop)
+            CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         // A column whose residual norm fell tenfold since its last true residual
         // triggers a replacement; every active column that fell at least 1.5x
         // joins it, so the columns of a block share the recomputations.
@@ -223,7 +250,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         }
         if (any) {
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b, s));
+                CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, s));
@@ -237,11 +264,26 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_status.data(), st.status, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
-        bool again = false;
+        bool again = false, fallback = false;
+        const int next_form = op.ski ? -1 : more_accurate_precision(precision);
+        bool revive = false;
         for (int c = 0; c < t; ++c) {
             h_relt[c] = h_b2[c] > 0.0 ? std::sqrt(h_relt[c] / h_b2[c]) : 0.0;
-            const bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
-                              h_refine[c] < max_refine && h_iters[c] < max_iter;
+            // p^T K_y p <= 0 cannot happen for the SPD K_y: a breakdown with a
+            // finite iterate comes from an inexact product form, and the
+            // next more accurate form continues from that iterate
+            if (h_status[c] == MFGP_BREAKDOWN && next_form >= 0 && std::isfinite(h_relt[c]) &&
+                !(h_relt[c] <= tol) && h_refine[c] < max_refine && h_iters[c] < max_iter) {
+                h_status[c] = MFGP_OK;
+                fallback = revive = true;
+            }
+            bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
+                        h_refine[c] < max_refine && h_iters[c] < max_iter && !h_gaveup[c];
+            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c])) fallback = true;
+            if (need && next_form < 0 && cycle_gave_nothing(h_t0[c], h_relt[c])) {
+                h_gaveup[c] = 1;     // the last form cannot improve this column
+                need = false;
+            }
             h_restart[c] = need ? 1 : 0;
             if (need) {
                 h_refine[c] += 1;
@@ -249,13 +291,22 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             }
         }
         if (!again) break;
+        if (fallback) precision = next_form;
+        if (revive)
+            CG_CHECK(hipMemcpyAsync(st.status, h_status.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(cg_restart(st, b.R64, n, t, restart, s));
         CG_CHECK(col_dots_ff(st.r, st.r, n, t, tmp, b.dots, s));
         CG_CHECK(cg_activate(st, t, restart, tmp, s));
         CG_CHECK(hipMemcpyAsync(h_rep.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
-        for (int c = 0; c < t; ++c)
-            if (h_restart[c]) h_norepl[c] = 0;   // a fresh cycle starts without drift
+        CG_CHECK(hipStreamSynchronize(s));
+        for (int c = 0; c < t; ++c) {
+            if (!h_restart[c]) continue;
+            h_norepl[c] = 0;   // a fresh cycle starts without drift
+            h_stall[c].begin(h_iters[c], h_rep[c]);
+            h_t0[c] = h_relt[c];
+            h_stalled[c] = 0;
+        }
         log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
     }
 
@@ -281,6 +332,8 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             info[c].rel_resid_true = h_relt[c];
             info[c].replacements = h_nrep[c];
             info[c].drift_skips = h_skips[c];
+            info[c].stalls = h_nstall[c];
+            info[c].precision = precision;
         }
     }
     return worst;
@@ -399,8 +452,19 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
     std::vector<double> h_relt(t), h_rr(t), h_b2(t);
+    // stagnation and precision fallback, as in cg_run (stall.hpp)
+    std::vector<StallTracker> h_stall(t);
+    std::vector<double> h_t0(t, 1.0);
+    std::vector<int> h_nstall(t, 0), h_gaveup(t, 0), h_stalled(t, 0);
+    int precision = o.precision;
     int log_coeffs = coeff ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
+    CG_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < t; ++c) {
+        h_stall[c].begin(0, h_rr[c]);
+        if (h_b2[c] > 0.0) h_t0[c] = std::sqrt(h_rr[c] / h_b2[c]);
+    }
     const int report_every = o.progress_every > 0 ? o.progress_every : 100;
     int next_report = report_every;
 
@@ -409,6 +473,18 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
+        bool stop = false;
+        for (int c = 0; c < t; ++c) {
+            if (!h_active[c] || h_iters[c] >= max_iter) continue;
+            if (h_stall[c].update(h_iters[c], h_rr[c])) {
+                h_active[c] = 0;
+                h_nstall[c] += 1;
+                h_stalled[c] = 1;
+                stop = true;
+            }
+        }
+        if (stop)
+            CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         bool any = false;
         for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
         if (o.progress) {
@@ -425,7 +501,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         }
         if (any) {
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, o.precision, b, s));
+                CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_rr(st, n, t, b.dots, rrn, s));
@@ -445,11 +521,26 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_status.data(), st.status, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
-        bool again = false;
+        bool again = false, fallback = false;
+        const int next_form = op.ski ? -1 : more_accurate_precision(precision);
+        bool revive = false;
         for (int c = 0; c < t; ++c) {
             h_relt[c] = h_b2[c] > 0.0 ? std::sqrt(h_relt[c] / h_b2[c]) : 0.0;
-            const bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
-                              h_refine[c] < max_refine && h_iters[c] < max_iter;
+            // p^T K_y p <= 0 cannot happen for the SPD K_y: a breakdown with a
+            // finite iterate comes from an inexact product form, and the
+            // next more accurate form continues from that iterate
+            if (h_status[c] == MFGP_BREAKDOWN && next_form >= 0 && std::isfinite(h_relt[c]) &&
+                !(h_relt[c] <= tol) && h_refine[c] < max_refine && h_iters[c] < max_iter) {
+                h_status[c] = MFGP_OK;
+                fallback = revive = true;
+            }
+            bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
+                        h_refine[c] < max_refine && h_iters[c] < max_iter && !h_gaveup[c];
+            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c])) fallback = true;
+            if (need && next_form < 0 && cycle_gave_nothing(h_t0[c], h_relt[c])) {
+                h_gaveup[c] = 1;     // the last form cannot improve this column
+                need = false;
+            }
             h_restart[c] = need ? 1 : 0;
             if (need) {
                 h_refine[c] += 1;
@@ -457,6 +548,9 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
             }
         }
         if (!again) break;
+        if (fallback) precision = next_form;
+        if (revive)
+            CG_CHECK(hipMemcpyAsync(st.status, h_status.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(cg_restart(st, b.R64, n, t, restart, s));            // r = fl32(R64) (and p = r)
         CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
@@ -465,6 +559,14 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         CG_CHECK(col_dots_ff(st.r, st.r, n, t, rrn, b.dots, s));
         hipLaunchKernelGGL(pcg_activate_kernel, dim3(1), dim3(256), 0, s, st, t, restart, rzn, rrn);
         CG_CHECK(hipGetLastError());
+        CG_CHECK(hipMemcpyAsync(h_rr.data(), rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
+        CG_CHECK(hipStreamSynchronize(s));
+        for (int c = 0; c < t; ++c) {
+            if (!h_restart[c]) continue;
+            h_stall[c].begin(h_iters[c], h_rr[c]);
+            h_t0[c] = h_relt[c];
+            h_stalled[c] = 0;
+        }
         log_coeffs = 0;  // the Lanczos tridiagonal belongs to the first cycle only
     }
 
@@ -489,6 +591,8 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
             info[c].rel_resid_true = h_relt[c];
             info[c].replacements = 0;
             info[c].drift_skips = 0;
+            info[c].stalls = h_nstall[c];
+            info[c].precision = precision;
         }
     }
     return worst;

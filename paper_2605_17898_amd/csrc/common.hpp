@@ -88,6 +88,21 @@ SweepPlan plan_sweep(int64_t m, int64_t n);
 // Column-block sizes with a compiled register-resident kernel.
 int column_block(int t_remaining);
 
+// A product term with Matern or Linear factors (the general product, family
+// kFamProd): its prescaled features are the RBF-class ones (periodic circle
+// features, then RBF factors) in [0, nr), then each Matern or Linear factor's
+// own range [f0[f], f1[f]).  Unit-scale entry:
+//   prod_Matern P_nu(q_f) * prod_Linear (u_i . u_j)_f * 2^-(|du|^2_[0,nr) + sum_Matern q_f)
+// with q_f = |du| over the factor's features (see prod.hip).
+constexpr int kFamProd = 16;
+struct ProdDesc {
+    int nr = 0;                        // RBF-class features
+    int nspec = 0;                     // Matern / Linear factors
+    int kind[MFGP_MAX_TERMS] = {};     // MFGP_MATERN12/32/52 or MFGP_LINEAR
+    int f0[MFGP_MAX_TERMS] = {};
+    int f1[MFGP_MAX_TERMS] = {};
+};
+
 // Arguments of the FP32 entry sweep  out = s2 * k(Ur, Uc) V (+ sig2 * Vself).
 struct SweepArgs {
     const float* Ur;   // [m, D] prescaled rows
@@ -96,6 +111,7 @@ struct SweepArgs {
     int64_t m, n;
     float* partial;    // [chunks][m][tb] FP32 partial sums
     SweepPlan plan;
+    const ProdDesc* pd = nullptr;   // host: the general product's layout (family kFamProd)
 };
 
 // Launch the partial-sum sweep for one column block of width tb.
@@ -109,6 +125,7 @@ struct SweepArgs64 {
     int64_t m, n;
     double* partial;   // [chunks][m][tb]
     SweepPlan plan;
+    const ProdDesc* pd = nullptr;
 };
 hipError_t launch_sweep_f64acc(int family, int D, int tb, const SweepArgs64& a, hipStream_t s);
 

@@ -63,6 +63,7 @@ int column_block64(int t) {
 }
 
 hipError_t launch_sweep_f32(int family, int D, int tb, const SweepArgs& a, hipStream_t s) {
+    if (family == kFamProd) return sweep_prod_f32(D, tb, a, s);
     switch (family) {
         case MFGP_RBF: return sweep_f32_fam0(D, tb, a, s);
         case MFGP_MATERN12: return sweep_f32_fam1(D, tb, a, s);
@@ -73,6 +74,7 @@ hipError_t launch_sweep_f32(int family, int D, int tb, const SweepArgs& a, hipSt
 }
 
 hipError_t launch_sweep_f64acc(int family, int D, int tb, const SweepArgs64& a, hipStream_t s) {
+    if (family == kFamProd) return sweep_prod_f64(D, tb, a, s);
     switch (family) {
         case MFGP_RBF: return sweep_f64_fam0(D, tb, a, s);
         case MFGP_MATERN12: return sweep_f64_fam1(D, tb, a, s);
@@ -167,7 +169,67 @@ hipError_t reduce_partials(const float* partial, int chunks, int64_t m, int t, f
 // A product term of RBF factors and at most one periodic factor (the checks
 // are the caller's): RBF with unit lengthscales on the concatenated features,
 // the periodic block first.
+// A product with Matern or Linear factors (the general product, prod.hip):
+// features ordered RBF-class first (the periodic factor's circle features,
+// then the RBF factors'), then each Matern factor (x c_nu / l), then each
+// Linear factor (x itself); op.factor[] keeps the caller's factor order.
+static Operator make_general_product(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    Operator op;
+    op.family = kFamProd;
+    op.general = 1;
+    op.din = k.d;
+    op.n = n;
+    op.s2 = k.outputscale;
+    op.sig2 = k.noise;
+    op.X = X;
+    op.U = U;
+    int nf = 0;
+    for (const mfgp_kernel* f = &k; f && nf < MFGP_MAX_TERMS; f = f->times, ++nf) {
+        Operator::Factor& fi = op.factor[nf];
+        fi.family = f->family;
+        fi.periodic = f->family == MFGP_PERIODIC;
+        fi.ard = f->ard ? 1 : 0;
+    }
+    op.nfactors = nf;
+    // the four classes in layout order: periodic, RBF, Matern, Linear
+    int f0 = 0;
+    for (int cls = 0; cls < 4; ++cls) {
+        int q = 0;
+        for (const mfgp_kernel* f = &k; f && q < nf; f = f->times, ++q) {
+            const int fam = f->family;
+            const int fc = fam == MFGP_PERIODIC ? 0 : (fam == MFGP_RBF ? 1 : (fam == MFGP_LINEAR ? 3 : 2));
+            if (fc != cls) continue;
+            Operator::Factor& fi = op.factor[q];
+            fi.f0 = f0;
+            const int width = fi.periodic ? 2 * k.d : k.d;
+            const double c = fam == MFGP_LINEAR ? 1.0 : family_scale(fi.periodic ? MFGP_RBF : fam);
+            for (int e = 0; e < width; ++e) {
+                const int in = fi.periodic ? e / 2 : e;
+                const double l = fam == MFGP_LINEAR ? 1.0 : (f->ard ? f->lengthscale[in] : f->lengthscale[0]);
+                op.fac[f0 + e] = static_cast<float>(c / l);
+                op.ls[f0 + e] = l;
+            }
+            if (fi.periodic) {
+                op.periodic = 1;
+                op.period = static_cast<double>(f->period);
+            }
+            if (cls >= 2) {
+                const int sidx = op.pd.nspec++;
+                op.pd.kind[sidx] = fam;
+                op.pd.f0[sidx] = f0;
+                op.pd.f1[sidx] = f0 + width;
+            }
+            f0 += width;
+        }
+        if (cls == 1) op.pd.nr = f0;
+    }
+    op.d = f0;
+    return op;
+}
+
 static Operator make_product(const mfgp_kernel& k, const float* X, int64_t n, float* U) {
+    for (const mfgp_kernel* f = &k; f; f = f->times)
+        if (f->family != MFGP_RBF && f->family != MFGP_PERIODIC) return make_general_product(k, X, n, U);
     Operator op;
     op.family = MFGP_RBF;
     op.din = k.d;
@@ -299,7 +361,7 @@ int term_params(const mfgp_kernel& k) {
     if (k.times) {
         int p = 1;   // s2
         for (const mfgp_kernel* q = &k; q; q = q->times)
-            p += (q->ard ? k.d : 1) + (q->family == MFGP_PERIODIC ? 1 : 0);
+            if (q->family != MFGP_LINEAR) p += (q->ard ? k.d : 1) + (q->family == MFGP_PERIODIC ? 1 : 0);
         return p;
     }
     if (k.family == MFGP_LINEAR) return 1;
@@ -369,7 +431,7 @@ hipError_t apply_f32(const Operator& op, const float* Ur, int64_t m, const float
             if (e != hipSuccess) return e;
             vb = pack;
         }
-        SweepArgs a{Ur, op.U, vb, m, op.n, partial, plan};
+        SweepArgs a{Ur, op.U, vb, m, op.n, partial, plan, op.general ? &op.pd : nullptr};
         void* tok = timing_begin(s);
         hipError_t e = launch_sweep_f32(op.family, op.d, tb, a, s);
         const double ent = static_cast<double>(m) * static_cast<double>(op.n);
@@ -411,6 +473,7 @@ size_t apply_fp32_scratch_bytes(int64_t m, int64_t n, int t, int precision) {
 hipError_t apply_fp32(const Operator& op, const float* Ur, int64_t m, const float* V, int t,
                       float* out, bool with_noise, const float* Vself, void* scratch, int precision,
                       hipStream_t s) {
+    if (op.general) return apply_f32(op, Ur, m, V, t, out, with_noise, Vself, static_cast<float*>(scratch), s);
     if (use_gram(op, Ur, m, t, precision)) return apply_gram(op, V, t, out, with_noise, Vself, scratch, s);
     if (precision != MFGP_FP32_VALU && hybrid_supported(t))
         return apply_hybrid(op, Ur, m, V, t, out, with_noise, Vself, scratch, s);
@@ -440,7 +503,7 @@ hipError_t residual_f64_sub(const Operator& op, const double* X64, int t, double
     const SweepPlan plan = plan_sweep(op.n, op.n);
     for (int c0 = 0; c0 < t;) {
         const int tb = column_block64(t - c0);
-        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan};
+        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan, op.general ? &op.pd : nullptr};
         void* tok = timing_begin(s);
         hipError_t e = launch_sweep_f64acc(op.family, op.d, tb, a, s);
         const double ent = static_cast<double>(op.n) * static_cast<double>(op.n);
@@ -461,7 +524,7 @@ hipError_t residual_f64(const Operator& op, const float* B, const double* X64, i
     const SweepPlan plan = plan_sweep(op.n, op.n);
     for (int c0 = 0; c0 < t;) {
         const int tb = column_block64(t - c0);
-        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan};
+        SweepArgs64 a{op.U, op.U, X64 + c0, t, op.n, op.n, scratch, plan, op.general ? &op.pd : nullptr};
         void* tok = timing_begin(s);
         hipError_t e = launch_sweep_f64acc(op.family, op.d, tb, a, s);
         const double ent = static_cast<double>(op.n) * static_cast<double>(op.n);

@@ -5,10 +5,16 @@
 // 2^(-r2) is smooth in r2, the squared distance can instead come from
 //   r2 = |g_i|^2 + |g_j|^2 - 2 g_i . g_j,     g = u - mean(u),
 // with the dot products of a 16 x 16 tile in one v_mfma_f32_16x16x4_f32
-// (d <= 4; two for d <= 8) and the norms as its accumulator input, leaving
-// the vector ALU one add and one exp2 per entry (the operand layout is in
-// gram_kernels.hpp).  Translating all points by their mean leaves every
-// distance unchanged and keeps the norms small.
+// (d <= 4; two for d <= 8).  Translating all points by their mean leaves
+// every distance unchanged and keeps the norms small.  The entry is then
+// factored,
+//   2^(-r2) = 2^(-|g_i|^2) 2^(2 g_i . g_j) 2^(-|g_j|^2),
+// the column factor b_j = 2^(-|g_j|^2) is folded into the right-hand sides
+// when they are packed (V'_j = b_j V_j) and the row factor a_i into the row's
+// sums at the end, so per entry the vector ALU is left only the exp2 of the
+// MFMA's 2 g_i . g_j (operand layout in gram_kernels.hpp).  With
+// |g|^2 <= kGramMaxNorm = 62 every factor lies in [2^-124, 2^124], inside
+// binary32; a factored entry below 2^-126 is an entry below 2^-126.
 //
 // Accuracy.  The form cancels: r2 carries an absolute rounding error of a
 // few ulp of max |g|^2, where the direct differences err relative to r2
@@ -16,14 +22,16 @@
 // matvec error against FP64 was 8.8e-7 at max |g|^2 = 30 (N = 1e5, d = 4,
 // l = 0.3) and 3.5e-6 at 144 (N = 5e5, d = 2, l = 0.05).  Every launch
 // therefore checks max |g|^2 (computed on the device before the sweep, no
-// host round trip) against kGramMaxNorm = 64 and, above it, runs the
-// direct-difference body of the hybrid sweep on the same fragments instead.
+// host round trip) against kGramMaxNorm = 62 and, above it, runs the
+// direct-difference body of the hybrid sweep on the unscaled fragments
+// instead (the packing reads the same maximum and scales only below it).
 // A slightly negative r2 from the cancellation (i ~ j) gives an entry a few
 // ulp above 1: within the same error, so r2 is not clamped.
 //
-// The operator stays symmetric: the entry of (i, j) and of (j, i) adds the
-// same two norms and the same products (-2 g_j[k]) g_i[k] = (-2 g_i[k]) g_j[k]
-// (the factor 2 is exact) in the same order.
+// The operator is symmetric up to the rounding of the two factors: the
+// exponent of (i, j) and (j, i) is the same sum of the products
+// (-2 g_j[k]) g_i[k] = (-2 g_i[k]) g_j[k] (the factor 2 is exact), while a_i
+// and b_j are applied on different sides (about one ulp per entry).
 #include <algorithm>
 
 #include "gram_kernels.hpp"
@@ -100,9 +108,13 @@ __global__ __launch_bounds__(256) void gram_prep_kernel(const float* __restrict_
 }
 
 // Fragments of the hybrid sweep (step q, lane l: V[4 q + l / 16][...]) with
-// |g_j|^2 behind them; steps cover j < n rounded up to 16.
-__global__ void pack_gfrag_kernel(const float* __restrict__ V, const float* __restrict__ nrm, int64_t n,
-                                  int t, int nt, int tv, int64_t nsteps, float* __restrict__ F) {
+// |g_j|^2 behind them; steps cover j < n rounded up to 16.  While the launch
+// takes the Gram branch (max |g|^2 <= kGramMaxNorm, the test the sweep makes)
+// the values carry the column factor 2^(-|g_j|^2); otherwise they are V itself
+// for the direct-difference branch.
+__global__ void pack_gfrag_kernel(const float* __restrict__ V, const float* __restrict__ nrm,
+                                  const unsigned* __restrict__ gmax, int64_t n, int t, int nt, int tv,
+                                  int64_t nsteps, float* __restrict__ F) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int WS = nt + tv + 1;
     if (idx >= nsteps * 64 * WS) return;
@@ -111,11 +123,13 @@ __global__ void pack_gfrag_kernel(const float* __restrict__ V, const float* __re
     const int l = static_cast<int>(lq % 64);
     const int64_t q = lq / 64;
     const int64_t j = q * kHK + l / 16;
+    const float nj = nrm[j < n ? j : n - 1];
     if (w < nt + tv) {
         const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
-        F[idx] = (j < n) ? V[j * t + c] : 0.0f;
+        const float b = __uint_as_float(*gmax) <= kGramMaxNorm ? __builtin_amdgcn_exp2f(-nj) : 1.0f;
+        F[idx] = (j < n) ? V[j * t + c] * b : 0.0f;
     } else {
-        F[idx] = nrm[j < n ? j : n - 1];
+        F[idx] = nj;
     }
 }
 
@@ -368,7 +382,7 @@ hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, boo
     const int64_t nsteps = (n + kGJ - 1) / kGJ * (kGJ / kHK);
     const int64_t total = nsteps * 64 * (nt + tv + 1);
     hipLaunchKernelGGL(pack_gfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, V, nrm,
-                       n, t, nt, tv, nsteps, F);
+                       gmax, n, t, nt, tv, nsteps, F);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* tok = timing_begin(s);

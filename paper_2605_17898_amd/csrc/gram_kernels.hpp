@@ -15,9 +15,11 @@ constexpr int kGJ = 16;   // j per Gram block (one 16 x 16 distance tile per row
 // right-hand-side values of each lane and step (stride WS = NT + TV + 1).
 //
 // Per 16-j block and row tile of 16 rows one v_mfma_f32_16x16x4_f32 (two for
-// DG = 8) produces the 16 x 16 squared distances
-//   r2 = |g_i|^2 + |g_j|^2 + sum_k (-2 g_j[k]) g_i[k]
-// with the norms as the accumulator input.  Its A operand (16 j x 4 dims)
+// DG = 8) produces the 16 x 16 products
+//   -2 g_i . g_j = sum_k (-2 g_j[k]) g_i[k]
+// from a zero accumulator; the lane takes 2^(2 g_i . g_j) with one exp2, the
+// fragment values already carry 2^(-|g_j|^2), and the row's sums are scaled
+// by 2^(-|g_i|^2) when they are written (see gram.hip).  Its A operand (16 j x 4 dims)
 // takes the block's j in the order pi(row) = 4 (row % 4) + row / 4, so that
 // accumulator register s of lane l holds the entry of row i = l % 16 and
 // j = j0 + 4 s + l / 16 -- exactly the A operand of contraction step s of the
@@ -73,7 +75,7 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     // Operands of block b: the A operand of the distance MFMA(s) and the four
     // steps' fragments (values behind j >= n are zero; G, nrm and the packed
     // norms repeat row n - 1 there, so every entry stays finite).
-    auto load_block = [&](int64_t b, float (&a)[H], float (&f)[4][WS]) {
+    auto load_block = [&](int64_t b, float (&a)[H], float (&f)[4][W]) {
         const int64_t jb = j0 + b * kGJ;
         const float* Gj = G + (jb + ja) * DG + grp;   // rows past n repeat row n - 1
 #pragma unroll
@@ -82,14 +84,13 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int w = 0; w < WS; ++w) f[s][w] = Fb[(s * 64 + lane) * WS + w];
+            for (int w = 0; w < W; ++w) f[s][w] = Fb[(s * 64 + lane) * WS + w];
     };
-    auto compute_block = [&](const float (&a)[H], const float (&f)[4][WS]) {
+    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto compute_block = [&](const float (&a)[H], const float (&f)[4][W]) {
 #pragma unroll
         for (int r = 0; r < kHRT; ++r) {
-            f32x4 d2;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) d2[s] = ni[r] + f[s][W];
+            f32x4 d2 = zero4;
 #pragma unroll
             for (int h = 0; h < H; ++h) d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[h], bi[r][h], d2, 0, 0, 0);
 #pragma unroll
@@ -126,7 +127,7 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     // them the compiler sank the loads to their first use, so every block
     // waited out the L2 latency (6.58 -> 6.50 ms here, 7.68 -> 7.28 ms in the
     // direct-difference body, rbf100k t = 33).
-    float aa[H], ab[H], fa[4][WS], fb[4][WS];
+    float aa[H], ab[H], fa[4][W], fb[4][W];
     if (nblk > 0) load_block(0, aa, fa);
     int64_t b = 0;
     for (; b + 1 < nblk; b += 2) {
@@ -142,22 +143,27 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     }
     if (b < nblk) compute_block(aa, fa);
 
+    // row factors 2^(-|g_i|^2): of the rows 4 grp + qq of the contraction
+    // tiles, and of the lane's own row for the VALU columns
 #pragma unroll
     for (int r = 0; r < kHRT; ++r) {
 #pragma unroll
-        for (int c = 0; c < NT; ++c)
+        for (int qq = 0; qq < 4; ++qq) {
+            int64_t i = row0 + r * 16 + 4 * grp + qq;
+            const float ai = __builtin_amdgcn_exp2f(-nrm[i < n ? i : n - 1]);
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int64_t i = row0 + r * 16 + 4 * grp + qq;
-                const float v = tot[r][c][qq] + acc[r][c][qq];
+            for (int c = 0; c < NT; ++c) {
+                const float v = (tot[r][c][qq] + acc[r][c][qq]) * ai;
                 if (i < n) out[(i - row_base) * t + TV + 16 * c + r16] = v;
             }
+        }
 #pragma unroll
         for (int c = 0; c < TV; ++c) {
             float v = tv_tot[r][c] + sv[r][c];
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
             const int64_t i = row0 + r * 16 + r16;
+            v *= __builtin_amdgcn_exp2f(-ni[r]);
             if (grp == 0 && i < n) out[(i - row_base) * t + c] = v;
         }
     }

@@ -64,6 +64,7 @@ struct Operator {
         int periodic = 0;
         int ard = 0;
         int f0 = 0;
+        int family = 0;    // mfgp_family of the factor (general products)
     };
     int family = 0;
     int d = 0;
@@ -77,6 +78,8 @@ struct Operator {
     double period = 0.0;
     const Operator* next = nullptr;
     const SkiOp* ski = nullptr;   // non-null: products by structured kernel interpolation
+    int general = 0;              // a product with Matern or Linear factors (family kFamProd)
+    ProdDesc pd;                  // its feature layout
     int64_t n = 0;
     float s2 = 1.0f;
     float sig2 = 0.0f;
@@ -163,8 +166,9 @@ bool gram_supported(int t);
 // mean mu of U, G [n][dg] = -2 (u - mu) zero-padded to dg = 4 (d <= 4) or 8,
 // nrm [n] = |u - mu|^2 (both with rows n .. roundup(n, 64) - 1 repeating row
 // n - 1) and the largest norm's float bits in *gmax; the sweeps take the Gram
-// branch only while that maximum is at most kGramMaxNorm.
-constexpr float kGramMaxNorm = 64.0f;
+// branch only while that maximum is at most kGramMaxNorm (which also keeps
+// the factored entries 2^(2 g_i . g_j) <= 2^124 inside binary32, see gram.hip).
+constexpr float kGramMaxNorm = 62.0f;
 // Smallest n for which MFGP_FP32 and the bf16 forms take the Gram form.
 constexpr int64_t kGramMinN = 32768;
 struct GramPrep {
@@ -238,5 +242,20 @@ enum SweepKind { kSweepF32 = 0, kSweepF64 = 1, kSweepAdjoint = 2, kSweepMfma = 3
 
 // Thread-local last HIP error.
 void set_last_hip_error(hipError_t e);
+
+// Per-thread library resources (hipFFT plans of the SKI calls, rocBLAS
+// handles of the preconditioned calls): released on request.
+hipError_t release_fft_plans();
+hipError_t release_blas_handles();
+
+// General products (prod.hip): the VALU entry sweeps (FP32 and FP64
+// accumulation) and the adjoint sums [G_k per feature, G_s, G_p].
+hipError_t sweep_prod_f32(int D, int tb, const SweepArgs& a, hipStream_t s);
+hipError_t sweep_prod_f64(int D, int tb, const SweepArgs64& a, hipStream_t s);
+hipError_t adjoint_prod(const Operator& op, int tb, const float* A, int lda, int c0, const float* w_host,
+                        const float* B, const SweepPlan& p, double* partial, hipStream_t s);
+// var[i] += s2 k^(x_i, x_i) of a general product (its Linear factors'
+// |x_i|^2; 1 without them), rows Ur [m, D].
+hipError_t prod_prior_add(const Operator& op, const float* Ur, int64_t m, double s2, float* var, hipStream_t s);
 
 }  // namespace mfgp

@@ -33,21 +33,30 @@ bool precision_supported(int p) { return p >= MFGP_FP32 && p <= MFGP_FP32_GRAM; 
 
 // Vh[(jt * NT + ct) * 64 + l] = 8 bf16: V[jt*16 + tile_j(l/32, q, perm)][tv + ct*32 + l%32]
 // (the first piece; Vm and Vl the second and third when split); zero outside
-// [n) x [t).  With tv = 1, Vy[j] = V[j][0] in FP32 (zero for j >= n).
+// [n) x [t).  With tv = 1, Vy[j] = V[j][0] in FP32 (zero for j >= n).  For the
+// Gram form (nrm, gmax non-NULL) every value carries the column factor
+// 2^(-|g_j|^2) while the launch takes the Gram branch (max |g|^2 <=
+// kGramMaxNorm, the sweep's own test) and none otherwise.
 __global__ void pack_vfrag_kernel(const float* __restrict__ V, int64_t n, int t, int tv, int nt_tiles,
-                                  int64_t njt, int split, int perm, bf16x8* __restrict__ Vh,
+                                  int64_t njt, int split, int perm, const float* __restrict__ nrm,
+                                  const unsigned* __restrict__ gmax, bf16x8* __restrict__ Vh,
                                   bf16x8* __restrict__ Vm, bf16x8* __restrict__ Vl,
                                   float* __restrict__ Vy) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t total = njt * nt_tiles * 64;
-    if (tv && idx < njt * kJT) Vy[idx] = idx < n ? V[idx * t] : 0.0f;
+    const float* colnrm = (nrm && __uint_as_float(*gmax) <= kGramMaxNorm) ? nrm : nullptr;
+    if (tv && idx < njt * kJT) {
+        float y = idx < n ? V[idx * t] : 0.0f;
+        if (colnrm) y *= __builtin_amdgcn_exp2f(-colnrm[idx < n ? idx : n - 1]);
+        Vy[idx] = y;
+    }
     if (idx >= total) return;
     const int l = static_cast<int>(idx % 64);
     const int64_t f = idx / 64;
     const int ct = static_cast<int>(f % nt_tiles);
     const int64_t jt = f / nt_tiles;
     bf16x8 h8, m8, l8;
-    vfrag(V, n, t, tv, jt, ct, l, h8, m8, l8, perm != 0);
+    vfrag(V, n, t, tv, jt, ct, l, h8, m8, l8, perm != 0, colnrm);
     Vh[idx] = h8;
     if (split >= 1) Vm[idx] = m8;
     if (split >= 2) Vl[idx] = l8;
@@ -197,7 +206,8 @@ hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const floa
     }
     const int64_t total = std::max<int64_t>(njt * nt * 64, njt * kJT);
     hipLaunchKernelGGL(pack_vfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
-                       0, s, V, n, t, tv, nt, njt, split, gram ? 1 : 0, Vh, Vm, Vl, Vy);
+                       0, s, V, n, t, tv, nt, njt, split, gram ? 1 : 0, gram ? gp.nrm : nullptr,
+                       gram ? gp.gmax : nullptr, Vh, Vm, Vl, Vy);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* tok = timing_begin(s);

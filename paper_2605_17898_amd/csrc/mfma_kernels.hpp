@@ -20,6 +20,37 @@ __host__ __device__ inline int split_of(int precision) {
     return precision == MFGP_BF16X3 ? 2 : (precision == MFGP_BF16X2 ? 1 : 0);
 }
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// The split pieces of eight binary32 entries, two values per conversion
+// (v_cvt_pk_bf16_f32, round to nearest even; the same values as converting
+// them one at a time, half the conversions): h = bf(e), and for SPLIT >= 1
+// m = bf(e - h), for SPLIT >= 2 l = bf(e - h - m); the differences are exact
+// in binary32 (two v_sub_f32, no packed FP32).
+template <int SPLIT>
+__device__ __forceinline__ void split8(const float (&e)[8], bf16x8& h8, bf16x8& m8, bf16x8& l8) {
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+        const f32x2v v = {e[q], e[q + 1]};
+        const bf16x2v h = __builtin_convertvector(v, bf16x2v);
+        h8[q] = h[0];
+        h8[q + 1] = h[1];
+        if (SPLIT >= 1) {
+            const f32x2v r = v - __builtin_convertvector(h, f32x2v);
+            const bf16x2v m = __builtin_convertvector(r, bf16x2v);
+            m8[q] = m[0];
+            m8[q + 1] = m[1];
+            if (SPLIT >= 2) {
+                const f32x2v r2 = r - __builtin_convertvector(m, f32x2v);
+                const bf16x2v l = __builtin_convertvector(r2, bf16x2v);
+                l8[q] = l[0];
+                l8[q + 1] = l[1];
+            }
+        }
+    }
+}
+
 // Exact three-way bf16 split of a binary32 value: v = h + m + l.
 __device__ __forceinline__ void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
     h = static_cast<__bf16>(v);
@@ -38,13 +69,17 @@ __host__ __device__ inline int tile_j(int h, int q, bool perm) {
 
 // One lane's B fragment of j-tile jt, column tile ct of a [n, t] block V:
 // 8 bf16 values V[jt*16 + tile_j(l/32, q)][tv + ct*32 + l%32], zero outside.
+// With colnrm non-NULL the values carry the Gram form's column factor
+// 2^(-colnrm[j]).
 __device__ __forceinline__ void vfrag(const float* __restrict__ V, int64_t n, int t, int tv, int64_t jt,
-                                      int ct, int l, bf16x8& h8, bf16x8& m8, bf16x8& l8, bool perm = false) {
+                                      int ct, int l, bf16x8& h8, bf16x8& m8, bf16x8& l8, bool perm = false,
+                                      const float* __restrict__ colnrm = nullptr) {
     const int c = tv + ct * 32 + (l % 32);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int64_t j = jt * kJT + tile_j(l / 32, q, perm);
-        const float v = (j < n && c < t) ? V[j * t + c] : 0.0f;
+        float v = (j < n && c < t) ? V[j * t + c] : 0.0f;
+        if (colnrm) v *= __builtin_amdgcn_exp2f(-colnrm[j < n ? j : n - 1]);
         __bf16 h, mm, ll;
         split3(v, h, mm, ll);
         h8[q] = h;
@@ -115,19 +150,13 @@ __device__ __forceinline__ void mfma_block(const float* __restrict__ Ur, const f
 #pragma unroll
         for (int r = 0; r < kRT; ++r) {
             bf16x8 ah, am, al;
+            float e8[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const float e = kentry<FAM>(sqdist<D>(ui[r], uj[q]));
-                if (TV) sv[r] = fmaf(e, y8[q], sv[r]);
-                const __bf16 h = static_cast<__bf16>(e);
-                ah[q] = h;
-                if (SPLIT >= 1) {
-                    const float rm = e - static_cast<float>(h);
-                    const __bf16 mm = static_cast<__bf16>(rm);
-                    am[q] = mm;
-                    if (SPLIT >= 2) al[q] = static_cast<__bf16>(rm - static_cast<float>(mm));
-                }
+                e8[q] = kentry<FAM>(sqdist<D>(ui[r], uj[q]));
+                if (TV) sv[r] = fmaf(e8[q], y8[q], sv[r]);
             }
+            split8<SPLIT>(e8, ah, am, al);
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
                 // smallest terms first
@@ -171,10 +200,12 @@ constexpr int kGB = 32;   // j per distance tile of the Gram-form bf16 sweep
 
 // Rows [row_base, row_base + 256) of the n x n RBF product over j in [j0, j1)
 // (j0 a multiple of 32) in the Gram form: per 32 j and row tile of 32 rows,
-// DG / 2 v_mfma_f32_32x32x2_f32 give the squared distances
-//   r2 = |g_i|^2 + |g_j|^2 + sum_k (-2 g_j[k]) g_i[k]
-// (A = -2 g_j: 32 j x 2 dims, B = g_i: 2 dims x 32 rows, the norms as the
-// accumulator input).  Register R of lane l then holds the entry of row
+// DG / 2 v_mfma_f32_32x32x2_f32 give the products
+//   -2 g_i . g_j = sum_k (-2 g_j[k]) g_i[k]
+// (A = -2 g_j: 32 j x 2 dims, B = g_i: 2 dims x 32 rows, zero accumulator);
+// the factored entry 2^(2 g_i . g_j) is split and contracted with fragments
+// that carry 2^(-|g_j|^2), and the row's sums take 2^(-|g_i|^2) at the end
+// (the factoring of gram.hip).  Register R of lane l then holds the entry of row
 // i = l % 32 and j = j0 + 8 (R / 4) + 4 (l / 32) + R % 4: registers 0..7 are
 // exactly the A operand of the first 16-j contraction step and 8..15 of the
 // second when the B fragments list their j in the tile_j(.., true) order.
@@ -212,6 +243,9 @@ __device__ __forceinline__ void gram_mfma_block(const float* __restrict__ G, con
             for (int q = 0; q < 16; ++q) acc[r][c][q] = 0.0f;
     }
 
+    f32x16 zero16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) zero16[q] = 0.0f;
     const int64_t npad = (n + kGB - 1) / kGB * kGB;
     j1 = j1 < npad ? j1 : npad;
     for (int64_t jb = j0; jb < j1; jb += kGB) {
@@ -221,16 +255,13 @@ __device__ __forceinline__ void gram_mfma_block(const float* __restrict__ G, con
         const float* Gb = G + (jb + r32) * DG + half;
 #pragma unroll
         for (int h = 0; h < H; ++h) a[h] = Gb[2 * h];
-        // norms (and y) at this lane's 16 j's: four runs of 4 consecutive j
-        float nj[16], yj[16];
-        const float* nb = nrm + jb + 4 * half;
+        // y (with its column factor) at this lane's 16 j's: four runs of 4
+        // consecutive j
+        float yj[16];
         const float* yb = Vy + jb + 4 * half;
+        if (TV) {
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const f32x4v nv = *reinterpret_cast<const f32x4v*>(nb + 8 * g4);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) nj[4 * g4 + q] = nv[q];
-            if (TV) {
+            for (int g4 = 0; g4 < 4; ++g4) {
                 const f32x4v yv = *reinterpret_cast<const f32x4v*>(yb + 8 * g4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) yj[4 * g4 + q] = yv[q];
@@ -248,27 +279,19 @@ __device__ __forceinline__ void gram_mfma_block(const float* __restrict__ G, con
             }
 #pragma unroll
         for (int r = 0; r < kRT; ++r) {
-            f32x16 d2;
-#pragma unroll
-            for (int R = 0; R < 16; ++R) d2[R] = ni[r] + nj[R];
+            f32x16 d2 = zero16;
 #pragma unroll
             for (int h = 0; h < H; ++h) d2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h], bi[r][h], d2, 0, 0, 0);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 bf16x8 ah, am, al;
+                float e8[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const float e = kentry<MFGP_RBF>(d2[8 * u + q]);
-                    if (TV) sv[r] = fmaf(e, yj[8 * u + q], sv[r]);
-                    const __bf16 hq = static_cast<__bf16>(e);
-                    ah[q] = hq;
-                    if (SPLIT >= 1) {
-                        const float rm = e - static_cast<float>(hq);
-                        const __bf16 mq = static_cast<__bf16>(rm);
-                        am[q] = mq;
-                        if (SPLIT >= 2) al[q] = static_cast<__bf16>(rm - static_cast<float>(mq));
-                    }
+                    e8[q] = kentry<MFGP_RBF>(d2[8 * u + q]);
+                    if (TV) sv[r] = fmaf(e8[q], yj[8 * u + q], sv[r]);
                 }
+                split8<SPLIT>(e8, ah, am, al);
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
                     if (SPLIT >= 2) {
@@ -285,20 +308,22 @@ __device__ __forceinline__ void gram_mfma_block(const float* __restrict__ G, con
             }
         }
     }
+    // row factors 2^(-|g_i|^2) of the rows register q holds (and of the
+    // lane's own row for the VALU column)
 #pragma unroll
     for (int r = 0; r < kRT; ++r) {
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const int col = TV + c * 32 + (lane & 31);
-            if (col >= t) continue;
+        for (int q = 0; q < 16; ++q) {
+            const int64_t i = row0 + r * 32 + 8 * (q / 4) + 4 * half + (q % 4);
+            const float ai = __builtin_amdgcn_exp2f(-nrm[i < n ? i : n - 1]);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int64_t i = row0 + r * 32 + 8 * (q / 4) + 4 * half + (q % 4);
-                if (i < n) out[(i - row_base) * t + col] = acc[r][c][q];
+            for (int c = 0; c < NT; ++c) {
+                const int col = TV + c * 32 + (lane & 31);
+                if (col < t && i < n) out[(i - row_base) * t + col] = acc[r][c][q] * ai;
             }
         }
         if (TV) {
-            const float v = sv[r] + __shfl_xor(sv[r], 32, 64);
+            const float v = (sv[r] + __shfl_xor(sv[r], 32, 64)) * __builtin_amdgcn_exp2f(-ni[r]);
             const int64_t i = row0 + r * 32 + r32;
             if (half == 0 && i < n) out[(i - row_base) * t] = v;
         }

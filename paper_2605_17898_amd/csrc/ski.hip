@@ -527,9 +527,13 @@ SkiGeom make_geom(int d, const int32_t* m) {
     return g;
 }
 
-// hipFFT plans by (device, rank, sizes, batch, direction), kept per host thread.
+// hipFFT plans by (device, rank, sizes, batch, direction), kept per host
+// thread until it releases them (release_fft_plans) or ends.  hipFFT places
+// a plan's tables and work area in device memory when it creates it.
+using PlanKey = std::tuple<int, int, int, int, int, int, int>;
+thread_local std::map<PlanKey, hipfftHandle> plans;
+
 hipfftHandle fft_plan(const SkiGeom& g, int batch, bool forward, hipError_t& err) {
-    thread_local std::map<std::tuple<int, int, int, int, int, int, int>, hipfftHandle> plans;
     int dev = 0;
     err = hipGetDevice(&dev);
     if (err != hipSuccess) return nullptr;
@@ -549,6 +553,18 @@ hipfftHandle fft_plan(const SkiGeom& g, int batch, bool forward, hipError_t& err
 }
 
 }  // namespace
+
+// Destroys the calling thread's cached plans, each with its device current.
+hipError_t release_fft_plans() {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    for (auto& kv : plans) {
+        if (hipSetDevice(std::get<0>(kv.first)) == hipSuccess) (void)hipfftDestroy(kv.second);
+    }
+    plans.clear();
+    return hipSetDevice(cur);
+}
 
 static int64_t cell_count(const SkiGeom& g) {
     int64_t c = 1;

@@ -160,9 +160,43 @@ int grad_from_product(const Operator& op, const double* G, double* grad) {
     return off;
 }
 
+// Gradient entries of a general product term from its adjoint sums
+// G = [G_k per feature (D), G_s, G_p]: per factor in the caller's order its
+// lengthscales (s2 F_k(l) G_k, the two circle features of each input summed
+// for the periodic factor) and the period, none for Linear; then s2.
+int grad_from_general_product(const Operator& op, const double* G, double* grad) {
+    const double s2 = static_cast<double>(op.s2);
+    const double cr = family_scale(MFGP_RBF);
+    const int din = op.din;
+    int off = 0;
+    for (int f = 0; f < op.nfactors; ++f) {
+        const Operator::Factor& fi = op.factor[f];
+        if (fi.family == MFGP_LINEAR) continue;
+        const int nl = fi.ard ? din : 1;
+        for (int k = 0; k < nl; ++k) grad[off + k] = 0.0;
+        for (int k = 0; k < din; ++k) {
+            double gk;
+            if (fi.periodic) {
+                gk = s2 * (G[2 * k] + G[2 * k + 1]) / (cr * cr * op.ls[2 * k]);
+            } else {
+                gk = s2 * lengthscale_factor(fi.family, op.ls[fi.f0 + k]) * G[fi.f0 + k];
+            }
+            grad[off + (fi.ard ? k : 0)] += gk;
+        }
+        off += nl;
+        if (fi.periodic) {
+            const double two_pi = 6.283185307179586477;
+            grad[off++] = s2 * two_pi / (op.period * op.period * cr * cr) * G[op.d + 1];
+        }
+    }
+    grad[off++] = G[op.d];
+    return off;
+}
+
 // Returns the number of entries written.
 int grad_from_sums(const Operator& op, const double* G, double* grad) {
     const int ard = op.ard;
+    if (op.general) return grad_from_general_product(op, G, grad);
     if (op.nfactors > 0) return grad_from_product(op, G, grad);
     if (op.periodic) {
         const int din = op.din;
@@ -301,7 +335,7 @@ hipError_t chain_gradient(const Operator& op, const float* A, const float* B, in
             }
             grad[off++] = g;
         } else {
-            double sums[MFGP_MAX_D + 1];
+            double sums[MFGP_MAX_D + 2];
             hipError_t e = adjoint_sums(*c, A, B, t, colw_host, sums, adj_scratch, s);
             if (e != hipSuccess) return e;
             off += grad_from_sums(*c, sums, grad + off);
@@ -310,21 +344,27 @@ hipError_t chain_gradient(const Operator& op, const float* A, const float* B, in
     return hipSuccess;
 }
 
+// The point-dependent prior k(x*, x*) of Linear terms and general products.
 hipError_t add_linear_prior(const Operator& rows, int64_t m, float* var, hipStream_t s) {
     for (const Operator* r = &rows; r; r = r->next) {
-        if (!r->linear) continue;
-        hipLaunchKernelGGL(linear_prior_kernel, dim3(blocks_for(m)), dim3(256), 0, s, r->U, m, r->d,
-                           static_cast<double>(r->s2), var);
-        hipError_t e = hipGetLastError();
+        hipError_t e = hipSuccess;
+        if (r->general) {
+            e = prod_prior_add(*r, r->U, m, static_cast<double>(r->s2), var, s);
+        } else if (r->linear) {
+            hipLaunchKernelGGL(linear_prior_kernel, dim3(blocks_for(m)), dim3(256), 0, s, r->U, m, r->d,
+                               static_cast<double>(r->s2), var);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// The constant prior s2 of the stationary terms (the others: add_linear_prior).
 double stationary_prior(const Operator& op) {
     double s2 = 0.0;
     for (const Operator* c = &op; c; c = c->next)
-        if (!c->linear) s2 += static_cast<double>(c->s2);
+        if (!c->linear && !c->general) s2 += static_cast<double>(c->s2);
     return s2;
 }
 

@@ -24,6 +24,7 @@ FAMILIES = {"rbf": 0, "matern12": 1, "matern32": 2, "matern52": 3, "periodic": 4
 MAX_TERMS = 4
 PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x2": 2, "fp32_valu": 3, "bf16x3": 4, "fp32_direct": 5,
               "fp32_gram": 6}
+PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 OK, ERR_ARG, ERR_HIP, ERR_WORKSPACE, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = range(7)
 OP_MATVEC, OP_CG, OP_PREDICT, OP_MLL, OP_ADJOINT, OP_RESIDUAL = range(6)
 OP_PCHOL, OP_PAPPLY, OP_PCG, OP_PMLL = range(6, 10)
@@ -52,7 +53,7 @@ class CgInfoT(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lanczos_len", C.c_int32), ("refinements", C.c_int32),
                 ("status", C.c_int32), ("rel_resid_recurrence", C.c_double),
                 ("rel_resid_true", C.c_double), ("replacements", C.c_int32),
-                ("drift_skips", C.c_int32)]
+                ("drift_skips", C.c_int32), ("stalls", C.c_int32), ("precision", C.c_int32)]
 
 
 class BatchT(C.Structure):
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mfgp_status_string": (C.c_char_p, [C.c_int]),
         "mfgp_last_hip_error": (C.c_int, []),
         "mfgp_version": (C.c_int, []),
+        "mfgp_release_thread_resources": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -360,7 +362,8 @@ def _info_list(info, t):
     return [dict(iters=info[c].iters, lanczos_len=info[c].lanczos_len, refinements=info[c].refinements,
                  status=info[c].status, rel_resid_recurrence=info[c].rel_resid_recurrence,
                  rel_resid_true=info[c].rel_resid_true, replacements=info[c].replacements,
-                 drift_skips=info[c].drift_skips) for c in range(t)]
+                 drift_skips=info[c].drift_skips, stalls=info[c].stalls,
+                 precision=PRECISION_NAMES.get(info[c].precision, info[c].precision)) for c in range(t)]
 
 
 def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,
@@ -444,8 +447,11 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
                  Z: Optional[torch.Tensor] = None, tol: float = 1e-6, max_iter: int = 0,
                  precision: str = "fp32", probe_seed: int = 0, want_grad: bool = True,
                  want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None,
-                 replacement: bool = True):
-    """Returns dict(mll, logdet, grad, alpha, info, status)."""
+                 replacement: bool = True, check_every: int = 0):
+    """Returns dict(mll, logdet, grad, alpha, info, status).
+
+    check_every: iterations between the host's convergence checks (0: chosen
+    from the product size); residual replacement runs only at 1 or 2."""
     _dev(X, torch.float32, "X")
     _dev(y, torch.float32, "y")
     n, d = X.shape
@@ -453,7 +459,7 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
         _dev(Z, torch.float32, "Z")
         num_probes = Z.shape[1]
     t = num_probes + 1
-    o = cg_opts(tol, max_iter, 0, -1, precision, False, probe_seed, progress=progress,
+    o = cg_opts(tol, max_iter, check_every, -1, precision, False, probe_seed, progress=progress,
                 replacement=replacement)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     ws = workspace(workspace_bytes(OP_MLL, n, kern.feature_dim(d), t, o.precision, mi), X.device)
@@ -682,6 +688,11 @@ def precond_mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, Z: torc
     _check(st, "precond_mll_and_grad", allow)
     return dict(mll=mll.value, logdet=ld.value, grad=None if grad is None else list(grad),
                 alpha=alpha, info=_info_list(info, t), status=st)
+
+
+def release_thread_resources() -> None:
+    """Free this thread's cached rocBLAS handles and hipFFT plans."""
+    _check(LIB.mfgp_release_thread_resources(), "release_thread_resources")
 
 
 def timing_enable(on: bool = True) -> None:

@@ -118,8 +118,19 @@ def test_product_params_and_checks(m):
     assert matvec(prod.struct(2)) == m.ERR_WORKSPACE
     assert matvec((prod + lin).struct(2)) == m.ERR_WORKSPACE
     assert matvec((per * per).struct(1)) == m.UNSUPPORTED                 # two periodic factors
-    assert matvec((rbf * m.Kernel("matern32", 0.5)).struct(2)) == m.UNSUPPORTED
-    assert matvec((rbf * lin).struct(2)) == m.UNSUPPORTED
+    # products with Matern or Linear factors: valid (the general product);
+    # parameters: each factor's lengthscales (none for Linear), then s2, sigma^2
+    gm = rbf * m.Kernel("matern32", 0.5)
+    gl = rbf * lin
+    assert matvec(gm.struct(2)) == m.ERR_WORKSPACE
+    assert matvec(gl.struct(2)) == m.ERR_WORKSPACE
+    assert gm.n_params(2) == 5 and gm.feature_dim(2) == 4
+    assert gl.n_params(2) == 4 and gl.feature_dim(2) == 4
+    # ... but not in the bf16 forms, nor for the preconditioner
+    assert L.mfgp_kernel_matvec(C.byref(gm.struct(2)), dummy, 10, dummy, 1, C.c_void_p(32), m.PRECISIONS["bf16x2"],
+                                dummy, 16, None) == m.UNSUPPORTED
+    assert L.mfgp_pivoted_cholesky(C.byref(gm.struct(2)), dummy, 10, 2, dummy, dummy, dummy, 16, None) \
+        == m.UNSUPPORTED
     big = m.Kernel("rbf", 0.5, 1.0, 0.1) * m.Kernel("periodic", 0.5, period=1.0)
     assert matvec(big.struct(3)) == m.UNSUPPORTED                          # 9 features > MFGP_MAX_D
     bad = (rbf * m.Kernel("periodic", 0.8, period=-1.0)).struct(2)

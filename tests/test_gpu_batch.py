@@ -142,12 +142,16 @@ def test_batch64_full_with_tuning(mf):
     assert r["status"] == mf.OK
     assert info["tile_j"] > 0 and info["graph_launches"] > 0
     assert all(max(i["rel_resid_true"] for i in inf) <= 1e-6 for inf in r["info"])
-    # stratified check: the smallest problem against the oracle's same-probe values
-    b = int(np.argmin([w.n for w in probs]))
-    w = probs[b]
-    k = okern(w)
-    g = gp.same_probe_grad(k, w.X, w.y, w.Z)
-    assert np.linalg.norm(np.array(r["grad"][b]) - g) / np.linalg.norm(g) <= 1e-3
+    # stratified check: for every input dimension d_b = 1..6 the smallest
+    # problem of that dimension against the oracle's same-probe gradient
+    # (N_b from 3029 to 11085)
+    for d in range(1, 7):
+        b = min((w.n, i) for i, w in enumerate(probs) if w.d == d)[1]
+        w = probs[b]
+        g = gp.same_probe_grad(okern(w), w.X, w.y, w.Z)
+        e = np.linalg.norm(np.array(r["grad"][b]) - g) / np.linalg.norm(g)
+        print(f"batch64 problem {b} (n={w.n}, d={d}): same-probe gradient error {e:.2e}", flush=True)
+        assert e <= 1e-3
 
 
 @pytest.mark.parametrize("form", ["bf16x2", "bf16x3"])

@@ -72,6 +72,28 @@ def test_gram_guard_falls_back(mf, t):
     assert col_rel_err(out, ref).max() <= TOL
 
 
+@pytest.mark.parametrize("t", [1, 33])
+def test_gram_near_its_bound(mf, t):
+    # l = 0.076 on [0, 1]^2: max |g|^2 is about 60, just under the bound of 64,
+    # where the form's cancellation is largest: the Gram branch runs (the
+    # result differs from the direct form's) and still meets the FP32 bar.
+    banner(f"matvec fp32_gram near the guard: rbf d=2 l=0.076 n=4000 t={t}")
+    w = inputs.random_problem(640, 4000, 2, "rbf", lengthscale=0.076)
+    c = np.sqrt(np.log2(np.e) / 2)
+    u = w.X.astype(np.float64) * c / 0.076
+    g2 = ((u - u.mean(axis=0)) ** 2).sum(axis=1).max()
+    assert 50.0 <= g2 <= 64.0, g2
+    V = inputs.gaussian_rhs(641, 4000, t)
+    k = mkern(w)
+    out = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32_gram"))
+    direct = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32_direct"))
+    assert not np.array_equal(out, direct)
+    ref = gp.ky_matrix(okern(w), w.X) @ V.astype(np.float64)
+    err = col_rel_err(out, ref)
+    print(f"max|g|^2 = {g2:.1f}: Gram-form column errors up to {err.max():.2e}")
+    assert err.max() <= TOL
+
+
 def test_gram_symmetric_operator(mf):
     # K~ is symmetric in the Gram form: u^T (K~ v) = v^T (K~ u) up to the
     # FP32 accumulation of the two products.

@@ -124,3 +124,67 @@ def test_seeded_probes_equal_explicit(mf):
     r1 = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(Z), tol=1e-6)
     r2 = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), num_probes=6, probe_seed=1234, tol=1e-6)
     assert r1["mll"] == r2["mll"] and r1["grad"] == r2["grad"]
+
+
+@pytest.fixture(scope="module")
+def replacement_case():
+    w = inputs.exact1k(n=2000, probes=16)
+    k = okern(w)
+    mll, ld, g, alpha = same_probe_reference(w, k)
+    # The sigma^2 component is 1/2 (alpha^T alpha - mean_c u_c^T z_c), here a
+    # difference of two terms of ~2e5 (-21 in all), so it carries two floors:
+    # (1) a solve residual r with |r| <= tol |b| moves b^T K^-1 b by up to
+    #     |K^-1 b| tol |b| (per unit tol below);
+    # (2) the solver converges to the solution of its own FP32-entry operator:
+    #     the same estimator with K's entries evaluated in binary32 differs by
+    #     the entry-rounding floor (its size, not its sign, carries over to the
+    #     GPU's rounding, hence a factor 2 in the test).
+    X, y, Z = w.X.astype(np.float64), w.y.astype(np.float64), w.Z.astype(np.float64)
+    A = gp.ky_matrix(k, X)
+    Ka = np.linalg.solve(A, alpha)
+    U = np.linalg.solve(A, Z)
+    per_tol = 0.5 * (2 * np.linalg.norm(Ka) * np.linalg.norm(y)
+                     + np.mean(np.linalg.norm(U, axis=0) * np.linalg.norm(Z, axis=0)))
+    A32 = gp.kernel_matrix_f32(k, X, X, prescaled=True) + k.noise * np.eye(w.n)
+    a32 = np.linalg.solve(A32, y)
+    U32 = np.linalg.solve(A32, Z)
+    g_s2_32 = 0.5 * (a32 @ a32 - np.mean(np.sum(U32 * Z, axis=0)))
+    entry_floor = abs(g_s2_32 - g[-1])
+    return w, mll, ld, np.asarray(g), per_tol, entry_floor
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_gram", "bf16x3"])
+def test_mll_with_residual_replacement(mf, replacement_case, precision):
+    # The 1e5-point step checks every iteration, which switches on residual
+    # replacement while the first cycle's (alpha, beta) are logged for the
+    # Lanczos log-det.  Force that path at a size the oracle solves exactly:
+    # replacements must fire, and the log-det, MLL and gradient must meet the
+    # same-probe bars.
+    banner(f"mll+grad with residual replacement n=2000 p=16 precision={precision}")
+    w, mll, ld, g, per_tol, entry_floor = replacement_case
+    print(f"sigma^2 component floors: {per_tol:.3e} per unit tol, FP32 entries {entry_floor:.3e}")
+    runs = {}
+    for tol in (1e-6, 1e-8):
+        r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=tol, check_every=1,
+                            precision=precision)
+        assert r["status"] == mf.OK, r["info"]
+        assert sum(c["replacements"] for c in r["info"][1:]) > 0, r["info"]
+        assert min(c["lanczos_len"] for c in r["info"][1:]) > 0, r["info"]
+        assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+        assert r["mll"] == pytest.approx(mll, rel=1e-4)
+        got = np.asarray(r["grad"])
+        print(f"tol {tol:g}: grad {got}, oracle {g}")
+        assert np.linalg.norm(got - g) / np.linalg.norm(g) <= 1e-3
+        # lengthscale and s^2 meet the per-component bar; sigma^2 meets it
+        # up to its floors
+        bar = 1e-3 * np.maximum(np.abs(g), 1e-3 * np.abs(g).max())
+        assert np.all(np.abs(got[:-1] - g[:-1]) <= bar[:-1]), (got, g)
+        assert abs(got[-1] - g[-1]) <= bar[-1] + tol * per_tol + 2 * entry_floor, (got[-1], g[-1])
+        runs[tol] = r
+    # the replacement-free run of the same solve reaches the same log-det and gradient
+    r0 = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-8, check_every=1,
+                         precision=precision, replacement=False)
+    assert sum(c["replacements"] for c in r0["info"]) == 0
+    assert r0["logdet"] == pytest.approx(runs[1e-8]["logdet"], rel=2e-5)
+    ok, rel = grad_ok(r0["grad"], runs[1e-8]["grad"])
+    assert ok, (r0["grad"], runs[1e-8]["grad"], rel)

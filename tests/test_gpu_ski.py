@@ -217,3 +217,20 @@ def test_ski_d3_maximum_columns(mf):
     out = mf.ski_matvec(k, dev(X), dev(V), mf.ski_grid([10, 9, 8]))
     lo, h = ski.grid([X], [10, 9, 8])
     assert col_rel_err(host(out), ski.ski_matvec(o, X, V, lo, h, [10, 9, 8])).max() <= 1e-6
+
+
+def test_ski_release_thread_resources(mf):
+    # Releasing the thread's cached hipFFT plans (and rocBLAS handles) frees
+    # their device memory; the next product creates them again, same result.
+    banner("ski matvec, release thread resources, ski matvec again (d=2)")
+    rng = np.random.default_rng(1390)
+    X = rng.uniform(0.0, 1.0, (2000, 2)).astype(np.float32)
+    V = rng.standard_normal((2000, 3)).astype(np.float32)
+    _, k = kerns(mf, "rbf", 2)
+    g = mf.ski_grid([48, 40])
+    a = host(mf.ski_matvec(k, dev(X), dev(V), g))
+    mf.release_thread_resources()
+    b = host(mf.ski_matvec(k, dev(X), dev(V), g))
+    assert col_rel_err(b, a.astype(np.float64)).max() <= 1e-6
+    mf.release_thread_resources()
+    mf.release_thread_resources()   # nothing cached: still fine
