@@ -73,8 +73,10 @@
  *            kernel's feature dimension mfgp_feature_dim(kern): the input
  *            dimension, twice it for PERIODIC, summed over a sum's terms.
  * Threads    The library is reentrant: no mutable globals besides the
- *            thread-local last HIP error and the thread-local rocBLAS handles
- *            and hipFFT plans (see Memory).
+ *            thread-local last HIP error, the thread-local rocBLAS handles
+ *            and hipFFT plans (see Memory), and the per-device address of the
+ *            fixed workspace of mfgp_kernel_matvec_noalloc (set once, under a
+ *            lock).
  */
 #ifndef MFGP_H
 #define MFGP_H
@@ -238,6 +240,27 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
                        int32_t t, float* KV, int32_t precision, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Capacity of the fixed device workspace of mfgp_kernel_matvec_noalloc (bytes). */
+#define MFGP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* mfgp_kernel_matvec without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * mfgp_kernel_matvec; the scratch is a fixed device array of
+ * MFGP_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends.  The call allocates nothing (no hipMalloc / hipFree, no
+ * allocating library routine).
+ * Limit: returns MFGP_ERR_WORKSPACE, launching nothing, when
+ * mfgp_workspace_bytes(MFGP_OP_MATVEC, n, mfgp_feature_dim(kern), t,
+ * precision, 0) exceeds MFGP_NOALLOC_SCRATCH_BYTES (e.g. n = 1e5, d = 4 fits
+ * for t <= 8).  `stream` must belong to the current device (MFGP_ERR_ARG
+ * otherwise).  The first call on a device looks up that device's array.
+ * Every call on one GPU shares its array: calls that overlap in time on one
+ * GPU (two streams, or two threads) race and give undefined results; calls
+ * on one stream are ordered and safe.  Each call writes every scratch value
+ * it reads, so nothing carries over between calls.  Asynchronous. */
+int mfgp_kernel_matvec_noalloc(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
+                               int32_t t, float* KV, int32_t precision, void* stream);
 
 /* R = B - K_y Xsol with the library's FP32 kernel entries accumulated in FP64
  * (the recomputed residual of the solver).  B [n,t] float32, Xsol [n,t]

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -339,6 +340,43 @@ static int matvec_into(const mfgp_kernel* kern, const float* X, int64_t n, const
     return MFGP_OK;
 }
 
+// Workspace of mfgp_kernel_matvec_noalloc: a fixed device array, one copy per
+// GPU for the life of the process.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address is looked up once per
+// device (hipGetSymbolAddress with that device current) and only that address
+// reaches the kernels.
+constexpr size_t kNoAllocBytes = MFGP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the stream's device, which must be the
+// current device (the lookup is made with it current).
+static int noalloc_scratch(hipStream_t s, void** out) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e);
+    hipDevice_t sdev = cur;
+    if (s) {
+        e = hipStreamGetDevice(s, &sdev);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (sdev != cur) return MFGP_ERR_ARG;
+    if (cur < 0 || cur >= kMaxDevices) return MFGP_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[cur]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!p) return hip_fail(hipErrorInvalidSymbol);
+        g_scratch_addr[cur] = p;
+    }
+    *out = g_scratch_addr[cur];
+    return MFGP_OK;
+}
+
 }  // namespace mfgp
 
 using namespace mfgp;
@@ -411,6 +449,18 @@ int mfgp_kernel_matvec(const mfgp_kernel* kern, const float* X, int64_t n, const
     if (ws_bytes < mfgp_workspace_bytes(MFGP_OP_MATVEC, n, feature_dim(kern), t, precision, 0))
         return MFGP_ERR_WORKSPACE;
     return matvec_into(kern, X, n, V, t, KV, precision, ws, static_cast<hipStream_t>(stream));
+}
+
+int mfgp_kernel_matvec_noalloc(const mfgp_kernel* kern, const float* X, int64_t n, const float* V,
+                               int32_t t, float* KV, int32_t precision, void* stream) {
+    int st = check_matvec_args(kern, X, n, V, t, KV, precision);
+    if (st != MFGP_OK) return st;
+    if (mfgp_workspace_bytes(MFGP_OP_MATVEC, n, feature_dim(kern), t, precision, 0) > kNoAllocBytes)
+        return MFGP_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    if ((st = noalloc_scratch(s, &ws)) != MFGP_OK) return st;
+    return matvec_into(kern, X, n, V, t, KV, precision, ws, s);
 }
 
 int mfgp_residual(const mfgp_kernel* kern, const float* X, int64_t n, const float* B,

@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     sig = {
         "mfgp_workspace_bytes": (SZ, [I32, I64, I32, I32, I32, I32]),
         "mfgp_kernel_matvec": (C.c_int, [KP, P, I64, P, I32, P, I32, P, SZ, P]),
+        "mfgp_kernel_matvec_noalloc": (C.c_int, [KP, P, I64, P, I32, P, I32, P]),
         "mfgp_residual": (C.c_int, [KP, P, I64, P, P, I32, P, P, P, SZ, P]),
         "mfgp_cg_solve": (C.c_int, [KP, P, I64, P, I32, P, OP_, IP, P, P, SZ, P]),
         "mfgp_predict_mean": (C.c_int, [KP, P, I64, P, I64, P, I32, P, P, SZ, P]),
@@ -318,6 +319,25 @@ def kernel_matvec(kern: Kernel, X: torch.Tensor, V: torch.Tensor, precision: str
     ks = kern.struct(d)
     _check(LIB.mfgp_kernel_matvec(C.byref(ks), _ptr(X), n, _ptr(V), t, _ptr(out), pr, _ptr(ws),
                                   ws.numel(), _stream()), "kernel_matvec")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MFGP_NOALLOC_SCRATCH_BYTES
+
+
+def kernel_matvec_noalloc(kern: Kernel, X: torch.Tensor, V: torch.Tensor, out: torch.Tensor,
+                          precision: str = "fp32") -> torch.Tensor:
+    """K_y V into the caller's `out` through the entry point that allocates
+    nothing (the library's fixed per-GPU workspace; see the header for its
+    size limit and the rule that overlapping calls on one GPU race)."""
+    _dev(X, torch.float32, "X")
+    _dev(V, torch.float32, "V")
+    _dev(out, torch.float32, "out")
+    n, d = X.shape
+    t = _cols(V)
+    ks = kern.struct(d)
+    _check(LIB.mfgp_kernel_matvec_noalloc(C.byref(ks), _ptr(X), n, _ptr(V), t, _ptr(out),
+                                          PRECISIONS[precision], _stream()), "kernel_matvec_noalloc")
     return out
 
 
