@@ -58,7 +58,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (
 # reading of the same counters (summaries in profiles/).  Valid only for the
 # kernels named below.
 HYB_TRAFFIC_BYTES = 2.664e8
-GRAM_TRAFFIC_BYTES = 6.574e8
+GRAM_TRAFFIC_BYTES = 6.543e8
 TRAFFIC_SOURCE = {
     "fp32": "profiles/sweep_gram_rbf_d4_t33_rbf100k.md (rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel, "
             "scaled by a 1 GiB copy's counters; taken from that profile, not measured in this run)",
