@@ -357,6 +357,8 @@ def matvec_leg(args) -> int:
     comps = (("rbf(l=0.3) + periodic(l=1, p=0.5)", kern + pk, (1, 33)),
              ("rbf(l=0.3) * rbf(l=0.8) (8 features)",
               mfgp.Kernel("rbf", 0.3, full.outputscale, full.noise) * mfgp.Kernel("rbf", 0.8), (1, 33)),
+             ("matern52(l=0.3) * rbf(l=0.8) (general product, 8 features)",
+              mfgp.Kernel("matern52", 0.3, full.outputscale, full.noise) * mfgp.Kernel("rbf", 0.8), (1, 33)),
              ("linear", mfgp.Kernel("linear", 1.0, 1.0, full.noise), (1, 33)))
     crow = []
     for name, k, ts in comps:
@@ -547,6 +549,9 @@ def main() -> int:
         "adjoint_s": ph["adjoint_ms"] * 1e-3 / args.steps,
         "cg_iters_max": max(i["iters"] for i in info),
         "cg_refinements_max": max(i["refinements"] for i in info),
+        "cg_replacements_max": max(i["replacements"] for i in info),
+        "cg_drift_skips_max": max(i["drift_skips"] for i in info),
+        "precision_final": sorted({i["precision"] for i in info}),
         "rel_resid_true_max": max(i["rel_resid_true"] for i in info),
         "mll": r["mll"],
         "logdet": r["logdet"],

@@ -210,14 +210,17 @@ typedef struct {
     int32_t replacements;         /* residual replacements applied (small drift only)       */
     int32_t drift_skips;          /* replacements refused because the recurrence had
                                      drifted more than 10% from the true residual           */
-    int32_t stalls;               /* cycles ended by stagnation: after falling tenfold, the
-                                     recurrence residual made no new minimum for
-                                     max(100, cycle length / 4) iterations                 */
+    int32_t stalls;               /* cycles ended early: by stagnation (after falling
+                                     tenfold, the recurrence residual made no new minimum
+                                     for max(100, cycle length / 4) iterations), or by a
+                                     replacement that found the recurrence drifted away
+                                     from a true residual still far above tol            */
     int32_t precision;            /* mfgp_precision of the products of the last cycle: the
                                      requested one, or a more accurate form taken after a
-                                     cycle that stagnated or cut the true residual by less
-                                     than 0.7x (x1 -> x2 -> x3 -> MFGP_FP32_DIRECT; the
-                                     batched solver keeps its form)                       */
+                                     cycle that ended early, cut the true residual by less
+                                     than 0.7x, or ended where one more cycle of the same
+                                     reduction would stay above tol (x1 -> x2 -> x3 ->
+                                     MFGP_FP32_DIRECT; the batched solver keeps its form) */
 } mfgp_cg_info;
 
 /* Feature dimension of a kernel (the d of the workspace-size queries): kern->d,

@@ -218,16 +218,33 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
             CG_CHECK(hipMemcpyAsync(h_cross.data(), tmp + t, t * sizeof(double), hipMemcpyDeviceToHost, s));
             CG_CHECK(hipStreamSynchronize(s));
+            const bool has_next = !op.ski && more_accurate_precision(precision) >= 0;
+            bool ended = false;
             for (int c = 0; c < t; ++c) {
                 if (!h_flag[c]) continue;
                 const double drift2 = h_relt[c] + h_rr[c] - 2.0 * h_cross[c];
                 if (!(drift2 <= kMaxDrift2 * h_relt[c])) {
-                    h_flag[c] = 0;          // the recurrence has left the true residual:
-                    h_norepl[c] = 1;        // run this cycle out and refine instead
-                    h_skips[c] += 1;
+                    // the recurrence has left the true residual
+                    h_flag[c] = 0;
+                    const double tr = h_b2[c] > 0.0 ? std::sqrt(h_relt[c] / h_b2[c]) : 0.0;
+                    if (has_next && cycle_wants_fallback(false, h_t0[c], tr, tol)) {
+                        // at this form's floor, far above tol: end the cycle, take the next form
+                        h_active[c] = 0;
+                        h_nstall[c] += 1;
+                        h_stalled[c] = 1;
+                        ended = true;
+                    } else {
+                        h_norepl[c] = 1;    // run this cycle out and refine instead
+                        h_skips[c] += 1;
+                    }
                 } else {
                     h_nrep[c] += 1;
                 }
+            }
+            if (ended) {
+                CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
+                any = false;
+                for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
             }
             CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
             CG_CHECK(cg_replace(st, b.R64, n, t, restart, b.dots, tmp, s));
@@ -279,7 +296,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             }
             bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
                         h_refine[c] < max_refine && h_iters[c] < max_iter && !h_gaveup[c];
-            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c])) fallback = true;
+            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c], tol)) fallback = true;
             if (need && next_form < 0 && cycle_gave_nothing(h_t0[c], h_relt[c])) {
                 h_gaveup[c] = 1;     // the last form cannot improve this column
                 need = false;
@@ -536,7 +553,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
             }
             bool need = h_status[c] == MFGP_OK && !(h_relt[c] <= tol) && std::isfinite(h_relt[c]) &&
                         h_refine[c] < max_refine && h_iters[c] < max_iter && !h_gaveup[c];
-            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c])) fallback = true;
+            if (need && next_form >= 0 && cycle_wants_fallback(h_stalled[c], h_t0[c], h_relt[c], tol)) fallback = true;
             if (need && next_form < 0 && cycle_gave_nothing(h_t0[c], h_relt[c])) {
                 h_gaveup[c] = 1;     // the last form cannot improve this column
                 need = false;

@@ -18,9 +18,15 @@
 //     two conditions would end healthy cycles;
 //   * takes the next more accurate product form (x1 -> x2 -> x3 -> FP32
 //     direct differences, the operator of the recomputed residual itself) for
-//     every column from the next cycle on when a cycle stagnated, or when it
+//     every column from the next cycle on when a cycle stagnated, when it
 //     left the true residual above kNoProgress of its value at the cycle's
-//     start;
+//     start, or when a further cycle with the same reduction would still end
+//     above the tolerance (the form's error floor is far above it, so
+//     refinement on that form would take several more full solves);
+//   * ends a cycle early, with the same fallback, when a residual replacement
+//     finds that the recurrence has left the true residual while that true
+//     residual is still that far above the tolerance (the floor is reached:
+//     the rest of the cycle could only lower the recurrence);
 //   * gives a column up (MFGP_NOT_CONVERGED, its iterate kept) when a cycle
 //     on the last form left its true residual no smaller than before.
 #pragma once
@@ -79,9 +85,11 @@ inline int more_accurate_precision(int precision) {
 }
 
 // True when a finished cycle (true relative residual relt_start -> relt_end,
-// ended by stagnation or not) should move the solve to a more accurate form.
-inline bool cycle_wants_fallback(bool stalled, double relt_start, double relt_end) {
-    return stalled || !(relt_end <= kNoProgress * relt_start);
+// ended by stagnation or not) should move the solve to a more accurate form:
+// it stagnated, it cut the true residual by less than 1 / kNoProgress, or one
+// more cycle with the same reduction would still end above tol.
+inline bool cycle_wants_fallback(bool stalled, double relt_start, double relt_end, double tol) {
+    return stalled || !(relt_end <= kNoProgress * relt_start) || !(relt_end * (relt_end / relt_start) <= tol);
 }
 
 // True when a cycle on the last form left the true residual no smaller.

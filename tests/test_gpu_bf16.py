@@ -139,6 +139,25 @@ def test_x1_cg_reports_status(mf):
     print(f"bf16x1 CG: status {st}, info {info[0]}")
 
 
+def test_x1_with_replacement_falls_back(mf):
+    # With a check every iteration the solver replaces the x1 recurrence's
+    # residual by the true one at every tenfold fall (the path of the large
+    # workloads); the x1 cycle still ends far above 1e-6 (breakdown of the
+    # indefinite x1 operator or its floor), and the solve continues on a more
+    # accurate form to the 1e-6 solution.
+    banner("bf16x1 CG exact1k n=2000 check_every=1: replacement, then fallback")
+    w = inputs.exact1k(n=2000, probes=3)
+    B = np.concatenate([w.y[:, None], w.Z], axis=1)
+    x, info, _, st = mf.cg_solve(mkern(w), dev(w.X), dev(B), tol=1e-6, precision="bf16x1", check_every=1)
+    print(f"bf16x1 fallback with replacement: status {st}, info {info}")
+    assert st == mf.OK, info
+    assert max(i["rel_resid_true"] for i in info) <= 1e-6
+    assert all(i["precision"] != "bf16x1" for i in info), info
+    assert all(i["replacements"] > 0 for i in info), info
+    ref = gp.solve(okern(w), w.X, B)
+    assert col_rel_err(host(x), ref).max() <= 1e-4
+
+
 def test_x1_falls_back_to_a_more_accurate_form(mf):
     # bf16 entries perturb K_y by ~2^-9 |K| against sigma^2 = 0.01 (condition
     # number ~4e4 at this size): CG on the x1 product cannot reach 1e-6, and

@@ -58,11 +58,15 @@ int main() {
                 more_accurate_precision(MFGP_FP32), more_accurate_precision(MFGP_FP32_GRAM),
                 more_accurate_precision(MFGP_FP32_DIRECT), more_accurate_precision(MFGP_FP32_VALU));
     // cycle judgements
-    std::printf("%d %d %d %d %d %d\n", cycle_wants_fallback(false, 1.0, 1e-5),
-                cycle_wants_fallback(false, 3e-6, 2.5e-6), cycle_wants_fallback(false, 2e-6, 1.3e-6),
-                cycle_wants_fallback(true, 1.0, 1e-5), cycle_gave_nothing(2e-6, 2e-6),
+    std::printf("%d %d %d %d %d %d\n", cycle_wants_fallback(false, 1.0, 1e-5, 1e-6),
+                cycle_wants_fallback(false, 3e-6, 2.5e-6, 1e-6), cycle_wants_fallback(false, 2e-6, 1.3e-6, 1e-6),
+                cycle_wants_fallback(true, 1.0, 1e-5, 1e-6), cycle_gave_nothing(2e-6, 2e-6),
                 cycle_gave_nothing(2e-6, 1.9e-6));
-    std::printf("%d\n", cycle_wants_fallback(false, 1.0, NAN));
+    std::printf("%d\n", cycle_wants_fallback(false, 1.0, NAN, 1e-6));
+    // a floor far above tol: one more cycle of the same reduction would not reach it
+    std::printf("%d %d %d %d\n", cycle_wants_fallback(false, 1.0, 1.5e-3, 1e-6),
+                cycle_wants_fallback(false, 1.0, 9e-4, 1e-6), cycle_wants_fallback(false, 1e-2, 1.5e-4, 1e-6),
+                cycle_wants_fallback(false, 1.0, 0.05, 1e-6));
     return 0;
 }
 """
@@ -116,3 +120,11 @@ def test_cycle_judgements(results):
     # at all was gained
     assert results[9].split() == ["0", "1", "0", "1", "1", "0"]
     assert results[10] == "1"   # a non-finite residual never counts as progress
+
+
+def test_cycle_judgement_of_a_high_floor(results):
+    # 1 -> 1.5e-3: a repeat would end at 2.25e-6 > 1e-6, take the next form;
+    # 1 -> 9e-4: a repeat reaches 8.1e-7, refine on the same form;
+    # 1e-2 -> 1.5e-4: a repeat reaches 2.25e-6, take the next form;
+    # 1 -> 0.05 (an inexact form's floor): take the next form
+    assert results[11].split() == ["1", "0", "1", "1"]
