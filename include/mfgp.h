@@ -189,9 +189,10 @@ typedef struct {
                              for products of >= 1e9 entry-columns)                      */
     uint64_t probe_seed;  /* seed of the SplitMix64 probes when Z == NULL (mll_and_grad)      */
     /* Optional progress callback (may be NULL), called from the calling thread
-     * at host convergence checks whenever the largest per-column iteration
-     * count has advanced by progress_every (0 = 100) since the last call:
-     * progress(progress_user, iterations, worst ||r||/||b|| of the recurrence). */
+     * at host convergence checks whenever the solver has run progress_every
+     * (0 = 100) more iterations since the last call: progress(progress_user,
+     * iterations run so far (every cycle; all columns advance together), the
+     * worst ||r||/||b|| of the recurrence over the columns still iterating). */
     void (*progress)(void* user, int32_t iterations, double rel_resid);
     void* progress_user;
     int32_t progress_every;
@@ -202,7 +203,10 @@ typedef struct {
 typedef struct {
     int32_t iters;                /* CG iterations performed (all cycles)                   */
     int32_t lanczos_len;          /* iterations of the first cycle (SLQ length m)           */
-    int32_t refinements;          /* restarts from a recomputed residual                    */
+    int32_t refinements;          /* restarts: from a recomputed residual, or from x = 0
+                                     when the product form switches while the Lanczos
+                                     tridiagonal is recorded (the SLQ then describes the
+                                     form the solution converges on)                     */
     int32_t status;               /* mfgp_status of this column                             */
     double rel_resid_recurrence;  /* ||r_k||/||b|| carried by the recurrence at exit        */
     double rel_resid_true;        /* recomputed ||b - K_y x||/||b||, K_y with FP32 entries,
@@ -218,7 +222,7 @@ typedef struct {
     int32_t precision;            /* mfgp_precision of the products of the last cycle: the
                                      requested one, or a more accurate form taken after a
                                      cycle that ended early, cut the true residual by less
-                                     than 0.7x, or ended where one more cycle of the same
+                                     than 0.7x, or ended where two more cycles of the same
                                      reduction would stay above tol (x1 -> x2 -> x3 ->
                                      MFGP_FP32_DIRECT; the batched solver keeps its form) */
 } mfgp_cg_info;
@@ -451,8 +455,8 @@ int mfgp_batch_plan_info(mfgp_batch_plan plan, int64_t* tile_j, double* tuned_sw
  * info (optional, [nprob][p+1]).  opts->precision: MFGP_FP32 (the FP32-MFMA
  * contraction where t = 16 k + {0,1}), MFGP_FP32_VALU, or the bf16 forms
  * MFGP_BF16X1/X2/X3 (tile lengths are re-tuned when the precision changes);
- * opts->progress, if set, reports the largest iteration count and the worst
- * recurrence residual over the whole batch.  Synchronises.  Returns the
+ * opts->progress, if set, reports the iterations run and the worst recurrence
+ * residual over the columns of the batch still iterating.  Synchronises.  Returns the
  * worst status over all problems. */
 int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y, const float* Z,
                             const mfgp_cg_opts* opts, double* mll, double* logdet, double* grad,

@@ -1249,6 +1249,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     for (int q = 0; q < T; ++q) h_stall[q].begin(0, h_rep[q]);
     const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
     int next_report = report_every;
+    int steps = 0;   // iterations run by the solver (every cycle; all columns advance together)
     for (;;) {
         B_CHECK2(hipMemcpyAsync(h_active.data(), st.active, T * sizeof(int), hipMemcpyDeviceToHost, s));
         B_CHECK2(hipMemcpyAsync(h_iters.data(), st.iters, T * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1315,19 +1316,12 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
             for (int q = 0; q < T; ++q)
                 if (h_restart[q]) h_rep[q] = h_rr[q];
         }
-        if (opts->progress) {
-            int itmax = 0;
-            double worst = 0.0;
-            for (int q = 0; q < T; ++q) {
-                itmax = std::max(itmax, h_iters[q]);
-                if (h_b2[q] > 0.0) worst = std::max(worst, std::sqrt(h_rr[q] / h_b2[q]));
-            }
-            if (itmax >= next_report) {
-                opts->progress(opts->progress_user, itmax, worst);
-                while (next_report <= itmax) next_report += report_every;
-            }
+        if (opts->progress && steps >= next_report) {
+            opts->progress(opts->progress_user, steps, worst_recurrence(h_active, h_rr, h_b2));
+            while (next_report <= steps) next_report += report_every;
         }
         if (any) {
+            steps += check_every;
             if (exec) {
                 B_CHECK2(hipGraphLaunch(exec, s));
                 P.graph_launches += 1;

@@ -39,13 +39,15 @@ namespace mfgp {
 constexpr double kMaxDrift2 = 1e-2;
 constexpr int kMaxReplaceGap = 2;   // largest check interval with replacement
 
-__global__ void cg_init_flags_kernel(CgState st, int t, double tol2) {
+// Flags of a cold start (x = 0, r = p = b); keep_iters keeps the iteration
+// counts of an earlier start on another product form.
+__global__ void cg_init_flags_kernel(CgState st, int t, double tol2, int keep_iters) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
         const bool finite = isfinite(st.bnorm2[c]) && isfinite(st.rr[c]);
         const bool go = finite && st.bnorm2[c] > 0.0 && st.rr[c] > tol2 * st.bnorm2[c];
         st.active[c] = go ? 1 : 0;
         st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
-        st.iters[c] = 0;
+        if (!keep_iters) st.iters[c] = 0;
         st.lanlen[c] = 0;
         st.alpha[c] = 0.0;
         st.beta[c] = 0.0;
@@ -157,7 +159,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         CG_CHECK(copy2_f32(B, st.r, st.p, nt, s));
     }
     CG_CHECK(col_dots_ff(st.r, st.r, n, t, st.rr, b.dots, s));
-    hipLaunchKernelGGL(cg_init_flags_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol);
+    hipLaunchKernelGGL(cg_init_flags_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol, 0);
     CG_CHECK(hipGetLastError());
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
@@ -170,7 +172,8 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     std::vector<double> h_t0(t, 1.0);
     std::vector<int> h_nstall(t, 0), h_gaveup(t, 0), h_stalled(t, 0);
     int precision = o.precision;
-    int log_coeffs = (!o.warm_start && coeff) ? 1 : 0;
+    const bool log_wanted = !o.warm_start && coeff;
+    int log_coeffs = log_wanted ? 1 : 0;
     CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
     CG_CHECK(hipMemcpyAsync(h_b2.data(), st.bnorm2, t * sizeof(double), hipMemcpyDeviceToHost, s));
     CG_CHECK(hipStreamSynchronize(s));
@@ -180,13 +183,18 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     }
     const int report_every = o.progress_every > 0 ? o.progress_every : 100;
     int next_report = report_every;
+    int steps = 0;   // iterations run by the solver (every cycle; all columns advance together)
 
     for (;;) {
         CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
-        // A column whose recurrence has stagnated ends its cycle here.
+        // A column whose recurrence has stagnated ends its cycle here; when
+        // that moves the solve to a more accurate form, every column's cycle
+        // ends with it (they share the product, and the rest would only run
+        // on into the same floor while the stopped column waits).
+        const bool has_next = !op.ski && more_accurate_precision(precision) >= 0;
         bool stop = false;
         for (int c = 0; c < t; ++c) {
             if (!h_active[c] || h_iters[c] >= max_iter) continue;
@@ -197,6 +205,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
                 stop = true;
             }
         }
+        if (stop && has_next) std::fill(h_active.begin(), h_active.end(), 0);
         if (stop)
             CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         // A column whose residual norm fell tenfold since its last true residual
@@ -218,7 +227,6 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             CG_CHECK(hipMemcpyAsync(h_relt.data(), tmp, t * sizeof(double), hipMemcpyDeviceToHost, s));
             CG_CHECK(hipMemcpyAsync(h_cross.data(), tmp + t, t * sizeof(double), hipMemcpyDeviceToHost, s));
             CG_CHECK(hipStreamSynchronize(s));
-            const bool has_next = !op.ski && more_accurate_precision(precision) >= 0;
             bool ended = false;
             for (int c = 0; c < t; ++c) {
                 if (!h_flag[c]) continue;
@@ -241,10 +249,10 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
                     h_nrep[c] += 1;
                 }
             }
-            if (ended) {
+            if (ended) {   // the form changes: every column's cycle ends here
+                std::fill(h_active.begin(), h_active.end(), 0);
                 CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
                 any = false;
-                for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
             }
             CG_CHECK(hipMemcpyAsync(restart, h_flag.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
             CG_CHECK(cg_replace(st, b.R64, n, t, restart, b.dots, tmp, s));
@@ -253,19 +261,12 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             for (int c = 0; c < t; ++c)
                 if (h_flag[c]) h_rep[c] = h_rr[c];
         }
-        if (o.progress) {
-            int itmax = 0;
-            double worst = 0.0;
-            for (int c = 0; c < t; ++c) {
-                itmax = std::max(itmax, h_iters[c]);
-                if (h_b2[c] > 0.0) worst = std::max(worst, std::sqrt(h_rr[c] / h_b2[c]));
-            }
-            if (itmax >= next_report) {
-                o.progress(o.progress_user, itmax, worst);
-                while (next_report <= itmax) next_report += report_every;
-            }
+        if (o.progress && steps >= next_report) {
+            o.progress(o.progress_user, steps, worst_recurrence(h_active, h_rr, h_b2));
+            while (next_report <= steps) next_report += report_every;
         }
         if (any) {
+            steps += check_every;
             for (int k = 0; k < check_every; ++k) {
                 CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
@@ -309,6 +310,29 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         }
         if (!again) break;
         if (fallback) precision = next_form;
+        if (fallback && log_wanted) {
+            // The recorded tridiagonal (the SLQ log-determinant) belongs to
+            // the form just left: solve again from x = 0 on the new form and
+            // record it anew, so that it describes the operator the solution
+            // converges on.  Every column restarts (the iterate is dropped).
+            CG_CHECK(fill_f64(X, nt, 0.0, s));
+            CG_CHECK(copy2_f32(B, st.r, st.p, nt, s));
+            CG_CHECK(col_dots_ff(st.r, st.r, n, t, st.rr, b.dots, s));
+            hipLaunchKernelGGL(cg_init_flags_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol, 1);
+            CG_CHECK(hipGetLastError());
+            CG_CHECK(hipMemcpyAsync(h_rep.data(), st.rr, t * sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_CHECK(hipStreamSynchronize(s));
+            for (int c = 0; c < t; ++c) {
+                h_refine[c] += h_restart[c] ? 0 : 1;   // every column restarts
+                h_norepl[c] = 0;
+                h_stall[c].begin(h_iters[c], h_rep[c]);
+                h_t0[c] = h_b2[c] > 0.0 ? std::sqrt(h_rep[c] / h_b2[c]) : 1.0;
+                h_stalled[c] = 0;
+                h_gaveup[c] = 0;
+            }
+            log_coeffs = 1;
+            continue;
+        }
         if (revive)
             CG_CHECK(hipMemcpyAsync(st.status, h_status.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
@@ -405,13 +429,13 @@ __global__ void pcg_p_kernel(CgState st, const float* __restrict__ Z, int64_t to
 }
 
 __global__ void pcg_init_kernel(CgState st, int t, double tol2, const double* __restrict__ rr0,
-                                double* __restrict__ rz0) {
+                                double* __restrict__ rz0, int keep_iters) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
         const bool finite = isfinite(st.bnorm2[c]) && isfinite(st.rr[c]) && isfinite(rr0[c]);
         const bool go = finite && st.bnorm2[c] > 0.0 && rr0[c] > tol2 * st.bnorm2[c];
         st.active[c] = go ? 1 : 0;
         st.status[c] = finite ? MFGP_OK : MFGP_BREAKDOWN;
-        st.iters[c] = 0;
+        if (!keep_iters) st.iters[c] = 0;
         st.lanlen[c] = 0;
         st.alpha[c] = 0.0;
         st.beta[c] = 0.0;
@@ -457,15 +481,21 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
     int* restart = b.ints + 4 * t;
 
     CG_CHECK(col_dots_ff(B, B, n, t, st.bnorm2, b.dots, s));
-    CG_CHECK(fill_f64(X, nt, 0.0, s));
-    CG_CHECK(copy2_f32(B, st.r, st.r, nt, s));
-    CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
-    CG_CHECK(col_dots_ff(st.r, pb.Zv, n, t, st.rr, b.dots, s));
-    CG_CHECK(col_dots_ff(st.r, st.r, n, t, rrn, b.dots, s));
-    hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol, rrn, pb.rz0);
-    CG_CHECK(hipGetLastError());
-    // the first direction is z itself for every column
-    CG_CHECK(hipMemcpyAsync(st.p, pb.Zv, nt * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // x = 0, r = b, z = P^-1 r, p = z (the first direction is z itself for
+    // every column); keep_iters on a cold restart after a form switch
+    auto cold_start = [&](int keep_iters) -> hipError_t {
+        hipError_t e = fill_f64(X, nt, 0.0, s);
+        if (e == hipSuccess) e = copy2_f32(B, st.r, st.r, nt, s);
+        if (e == hipSuccess) e = pc_apply(pc, st.r, t, pb.Zv, pb.pc, s);
+        if (e == hipSuccess) e = col_dots_ff(st.r, pb.Zv, n, t, st.rr, b.dots, s);
+        if (e == hipSuccess) e = col_dots_ff(st.r, st.r, n, t, rrn, b.dots, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(256), 0, s, st, t, tol * tol, rrn, pb.rz0, keep_iters);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return hipMemcpyAsync(st.p, pb.Zv, nt * sizeof(float), hipMemcpyDeviceToDevice, s);
+    };
+    CG_CHECK(cold_start(0));
 
     std::vector<int> h_active(t), h_iters(t), h_status(t), h_restart(t), h_refine(t, 0), h_lan(t);
     std::vector<double> h_relt(t), h_rr(t), h_b2(t);
@@ -484,12 +514,14 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
     }
     const int report_every = o.progress_every > 0 ? o.progress_every : 100;
     int next_report = report_every;
+    int steps = 0;   // iterations run by the solver (every cycle; all columns advance together)
 
     for (;;) {
         CG_CHECK(hipMemcpyAsync(h_active.data(), st.active, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_iters.data(), st.iters, t * sizeof(int), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipMemcpyAsync(h_rr.data(), st.rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
         CG_CHECK(hipStreamSynchronize(s));
+        const bool has_next = !op.ski && more_accurate_precision(precision) >= 0;
         bool stop = false;
         for (int c = 0; c < t; ++c) {
             if (!h_active[c] || h_iters[c] >= max_iter) continue;
@@ -500,23 +532,17 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
                 stop = true;
             }
         }
+        if (stop && has_next) std::fill(h_active.begin(), h_active.end(), 0);   // as in cg_run
         if (stop)
             CG_CHECK(hipMemcpyAsync(st.active, h_active.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         bool any = false;
         for (int c = 0; c < t; ++c) any = any || (h_active[c] && h_iters[c] < max_iter);
-        if (o.progress) {
-            int itmax = 0;
-            double worst = 0.0;
-            for (int c = 0; c < t; ++c) {
-                itmax = std::max(itmax, h_iters[c]);
-                if (h_b2[c] > 0.0) worst = std::max(worst, std::sqrt(h_rr[c] / h_b2[c]));
-            }
-            if (itmax >= next_report) {
-                o.progress(o.progress_user, itmax, worst);
-                while (next_report <= itmax) next_report += report_every;
-            }
+        if (o.progress && steps >= next_report) {
+            o.progress(o.progress_user, steps, worst_recurrence(h_active, h_rr, h_b2));
+            while (next_report <= steps) next_report += report_every;
         }
         if (any) {
+            steps += check_every;
             for (int k = 0; k < check_every; ++k) {
                 CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
@@ -566,6 +592,21 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         }
         if (!again) break;
         if (fallback) precision = next_form;
+        if (fallback && coeff) {
+            // as in cg_run: the tridiagonal is recorded anew on the new form
+            CG_CHECK(cold_start(1));
+            CG_CHECK(hipMemcpyAsync(h_rr.data(), rrn, t * sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_CHECK(hipStreamSynchronize(s));
+            for (int c = 0; c < t; ++c) {
+                h_refine[c] += h_restart[c] ? 0 : 1;   // every column restarts
+                h_stall[c].begin(h_iters[c], h_rr[c]);
+                h_t0[c] = h_b2[c] > 0.0 ? std::sqrt(h_rr[c] / h_b2[c]) : 1.0;
+                h_stalled[c] = 0;
+                h_gaveup[c] = 0;
+            }
+            log_coeffs = 1;
+            continue;
+        }
         if (revive)
             CG_CHECK(hipMemcpyAsync(st.status, h_status.data(), t * sizeof(int), hipMemcpyHostToDevice, s));
         CG_CHECK(hipMemcpyAsync(restart, h_restart.data(), t * sizeof(int), hipMemcpyHostToDevice, s));

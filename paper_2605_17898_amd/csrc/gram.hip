@@ -22,12 +22,15 @@
 // matvec error against FP64 was 8.8e-7 at max |g|^2 = 30 (N = 1e5, d = 4,
 // l = 0.3) and 3.5e-6 at 144 (N = 5e5, d = 2, l = 0.05).  Every launch
 // therefore checks max |g|^2 (computed on the device before the sweep, no
-// host round trip): up to kGramMaxNorm = 62 it runs the factored form; up to
-// kGramAugMaxNorm = 160 (d <= 6) the augmented form, whose operands carry
-// the norms as two more dimensions so that the MFMA yields r2 itself and no
-// factor can leave binary32's range; above that the direct-difference body
-// of the hybrid sweep.  The last two run on the unscaled fragments (the
-// packing reads the same maximum and scales only below kGramMaxNorm).
+// host round trip) against kGramMaxNorm = 62 and, above it, runs the
+// direct-difference body of the hybrid sweep on the unscaled fragments
+// instead (the packing reads the same maximum and scales only below it).
+// An unfactored form for larger norms (the norms as two more MFMA
+// dimensions, r2 straight out of the MFMA) met the matvec bar at
+// max |g|^2 = 144 (column errors <= 4.7e-6), but its entry errors are
+// coherent over a point's row: at N = 5e5 with sigma^2 = 0.01 they moved
+// K_y's spectrum by more than sigma^2 and CG diverged, for a sweep only 6%
+// faster than direct differences there; it is not built.
 // A slightly negative r2 from the cancellation (i ~ j) gives an entry a few
 // ulp above 1: within the same error, so r2 is not clamped.
 //
@@ -187,18 +190,10 @@ __global__ __launch_bounds__(kBlock) void sweep_gram_kernel(const float* __restr
     const int64_t j0 = static_cast<int64_t>(ch) * jchunk;   // multiple of 16
     const int64_t rbase = static_cast<int64_t>(rb) * kBlock;
     float* out = partial + static_cast<int64_t>(ch) * n * t + rbase * t;
-    const float gm = __uint_as_float(*gmax);
-    if (gm <= kGramMaxNorm) {
+    if (__uint_as_float(*gmax) <= kGramMaxNorm)
         gram_block<D <= 4 ? 4 : 8, NT, TV>(G, nrm, F, n, t, rbase, j0, j0 + jchunk, out);
-        return;
-    }
-    if constexpr (D + 2 <= 8) {
-        if (gm <= kGramAugMaxNorm) {
-            gram_block<D <= 4 ? 4 : 8, NT, TV, D>(G, nrm, F, n, t, rbase, j0, j0 + jchunk, out);
-            return;
-        }
-    }
-    hyb_block<MFGP_RBF, D, NT, TV, NT + TV + 1>(U, U, F, n, n, t, rbase, j0, j0 + jchunk, out);
+    else
+        hyb_block<MFGP_RBF, D, NT, TV, NT + TV + 1>(U, U, F, n, n, t, rbase, j0, j0 + jchunk, out);
 }
 
 bool gram_shape(int t, int& nt, int& tv) {

@@ -25,44 +25,28 @@ constexpr int kGJ = 16;   // j per Gram block (one 16 x 16 distance tile per row
 // j = j0 + 4 s + l / 16 -- exactly the A operand of contraction step s of the
 // hybrid sweep (lane l: row l % 16, j = 4 q + l / 16).  The entries then go
 // through the contraction MFMAs (and the TV VALU columns) unchanged.
-//
-// DA > 0 selects the augmented form for larger norms (DA = d, d + 2 <= 8):
-// the operands carry the norms as two more dimensions,
-//   A_j = [-2 g_j, 1, |g_j|^2],   B_i = [g_i, |g_i|^2, 1],
-// so the MFMA chain yields r2 = |g_i|^2 + |g_j|^2 - 2 g_i . g_j itself and the
-// lane takes 2^(-r2); neither the fragments nor the row sums carry a factor
-// (the packing leaves V unscaled above kGramMaxNorm).  G keeps its d <= DG
-// columns; the 1 and the norm are formed in registers.
-template <int DG, int NT, int TV, int DA = 0>
+template <int DG, int NT, int TV>
 __device__ __forceinline__ void gram_block(const float* __restrict__ G, const float* __restrict__ nrm,
                                            const float* __restrict__ F, int64_t n, int t, int64_t row_base,
                                            int64_t j0, int64_t j1, float* __restrict__ out) {
     constexpr int W = NT + TV;
     constexpr int WS = W + 1;
-    constexpr int H = DA > 0 ? (DA + 2 + 3) / 4 : DG / 4;
-    static_assert(DA == 0 || (DA + 2 <= 8 && DA <= DG), "augmented form: d + 2 <= 8 dimensions");
+    constexpr int H = DG / 4;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane >> 4;
     const int r16 = lane & 15;
     const int64_t row0 = row_base + wave * (kHRT * 16);
 
-    // B operand of the distance MFMA: lane l holds g_i[4 h + l / 16], i = row l % 16
-    // (augmented: |g_i|^2 at dimension DA and 1 at DA + 1).
+    // B operand of the distance MFMA: lane l holds g_i[4 h + l / 16], i = row l % 16.
     float bi[kHRT][H], ni[kHRT];
 #pragma unroll
     for (int r = 0; r < kHRT; ++r) {
         int64_t i = row0 + r * 16 + r16;
         i = i < n ? i : n - 1;
-        ni[r] = nrm[i];
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const int k = 4 * h + grp;
-            if (DA == 0)
-                bi[r][h] = -0.5f * G[i * DG + k];
-            else
-                bi[r][h] = k < DA ? -0.5f * G[i * DG + k] : (k == DA ? ni[r] : (k == DA + 1 ? 1.0f : 0.0f));
-        }
+        for (int h = 0; h < H; ++h) bi[r][h] = -0.5f * G[i * DG + 4 * h + grp];
+        ni[r] = nrm[i];
     }
     f32x4 acc[kHRT][NT > 0 ? NT : 1], tot[kHRT][NT > 0 ? NT : 1];
     float sv[kHRT][TV > 0 ? TV : 1], tv_tot[kHRT][TV > 0 ? TV : 1];
@@ -94,17 +78,8 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     auto load_block = [&](int64_t b, float (&a)[H], float (&f)[4][W]) {
         const int64_t jb = j0 + b * kGJ;
         const float* Gj = G + (jb + ja) * DG + grp;   // rows past n repeat row n - 1
-        if (DA == 0) {
 #pragma unroll
-            for (int h = 0; h < H; ++h) a[h] = Gj[4 * h];
-        } else {
-            const float nj = nrm[jb + ja];
-#pragma unroll
-            for (int h = 0; h < H; ++h) {
-                const int k = 4 * h + grp;
-                a[h] = k < DA ? Gj[4 * h] : (k == DA ? 1.0f : (k == DA + 1 ? nj : 0.0f));
-            }
-        }
+        for (int h = 0; h < H; ++h) a[h] = Gj[4 * h];
         const float* Fb = F + (jb / kHK) * (64 * WS);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -168,14 +143,14 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
     }
     if (b < nblk) compute_block(aa, fa);
 
-    // row factors 2^(-|g_i|^2) (factored form only): of the rows 4 grp + qq of
-    // the contraction tiles, and of the lane's own row for the VALU columns
+    // row factors 2^(-|g_i|^2): of the rows 4 grp + qq of the contraction
+    // tiles, and of the lane's own row for the VALU columns
 #pragma unroll
     for (int r = 0; r < kHRT; ++r) {
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             int64_t i = row0 + r * 16 + 4 * grp + qq;
-            const float ai = DA == 0 ? __builtin_amdgcn_exp2f(-nrm[i < n ? i : n - 1]) : 1.0f;
+            const float ai = __builtin_amdgcn_exp2f(-nrm[i < n ? i : n - 1]);
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
                 const float v = (tot[r][c][qq] + acc[r][c][qq]) * ai;
@@ -188,7 +163,7 @@ __device__ __forceinline__ void gram_block(const float* __restrict__ G, const fl
             v += __shfl_xor(v, 16, 64);
             v += __shfl_xor(v, 32, 64);
             const int64_t i = row0 + r * 16 + r16;
-            if (DA == 0) v *= __builtin_amdgcn_exp2f(-ni[r]);
+            v *= __builtin_amdgcn_exp2f(-ni[r]);
             if (grp == 0 && i < n) out[(i - row_base) * t + c] = v;
         }
     }

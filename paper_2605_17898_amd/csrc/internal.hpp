@@ -169,11 +169,6 @@ bool gram_supported(int t);
 // branch only while that maximum is at most kGramMaxNorm (which also keeps
 // the factored entries 2^(2 g_i . g_j) <= 2^124 inside binary32, see gram.hip).
 constexpr float kGramMaxNorm = 62.0f;
-// Above it (d + 2 <= 8) the FP32 Gram sweep takes the augmented form, whose
-// MFMA yields r2 itself, up to this maximum: its rounding error grows with the
-// norms (a few ulp of 2 max |g|^2 in r2), and beyond it the sweep runs direct
-// differences.
-constexpr float kGramAugMaxNorm = 160.0f;
 // Smallest n for which MFGP_FP32 and the bf16 forms take the Gram form.
 constexpr int64_t kGramMinN = 32768;
 struct GramPrep {

@@ -20,8 +20,8 @@
 //     direct differences, the operator of the recomputed residual itself) for
 //     every column from the next cycle on when a cycle stagnated, when it
 //     left the true residual above kNoProgress of its value at the cycle's
-//     start, or when a further cycle with the same reduction would still end
-//     above the tolerance (the form's error floor is far above it, so
+//     start, or when two further cycles with the same reduction would still
+//     end above the tolerance (the form's error floor is far above it, so
 //     refinement on that form would take several more full solves);
 //   * ends a cycle early, with the same fallback, when a residual replacement
 //     finds that the recurrence has left the true residual while that true
@@ -32,7 +32,9 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <limits>
+#include <vector>
 
 #include "../../include/mfgp.h"
 
@@ -86,10 +88,26 @@ inline int more_accurate_precision(int precision) {
 
 // True when a finished cycle (true relative residual relt_start -> relt_end,
 // ended by stagnation or not) should move the solve to a more accurate form:
-// it stagnated, it cut the true residual by less than 1 / kNoProgress, or one
-// more cycle with the same reduction would still end above tol.
+// it stagnated, it cut the true residual by less than 1 / kNoProgress, or two
+// more cycles with the same reduction would still end above tol.
 inline bool cycle_wants_fallback(bool stalled, double relt_start, double relt_end, double tol) {
-    return stalled || !(relt_end <= kNoProgress * relt_start) || !(relt_end * (relt_end / relt_start) <= tol);
+    const double f = relt_end / relt_start;
+    return stalled || !(relt_end <= kNoProgress * relt_start) || !(relt_end * f * f <= tol);
+}
+
+// Largest ||r|| / ||b|| of the recurrence over the columns still iterating,
+// or over every column when none is (what a progress report shows: a column
+// that has stopped keeps its last norm, which says nothing of the others).
+inline double worst_recurrence(const std::vector<int>& active, const std::vector<double>& rr,
+                               const std::vector<double>& b2) {
+    double live = -1.0, all = 0.0;
+    for (size_t c = 0; c < rr.size(); ++c) {
+        if (!(b2[c] > 0.0)) continue;
+        const double v = std::sqrt(rr[c] / b2[c]);
+        all = std::max(all, v);
+        if (active[c]) live = std::max(live, v);
+    }
+    return live >= 0.0 ? live : all;
 }
 
 // True when a cycle on the last form left the true residual no smaller.

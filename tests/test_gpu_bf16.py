@@ -125,6 +125,28 @@ def test_x2_mll_same_probe(mf):
     assert np.linalg.norm(np.array(r["grad"]) - g) / np.linalg.norm(g) <= 1e-3
 
 
+def test_x1_mll_switches_form_and_records_the_new_tridiagonal(mf):
+    # x1 cannot reach 1e-6 at exact1k (n = 2000); the solve moves to a more
+    # accurate form, and since the Lanczos tridiagonal of the x1 cycle would
+    # describe the x1 operator, it solves again from x = 0 on the new form
+    # and records the tridiagonal there: the log-determinant and gradient
+    # then match the same-probe oracle of the exact K_y.
+    banner("bf16x1 mll+grad exact1k n=2000 p=8: form switch, cold restart, vs same-probe oracle")
+    from oracle import krylov
+    w = inputs.exact1k(n=2000, probes=8)
+    k = okern(w)
+    r = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6, precision="bf16x1")
+    print(f"x1 mll: status {r['status']}, info {r['info']}")
+    assert r["status"] == mf.OK
+    assert all(i["precision"] != "bf16x1" for i in r["info"]), r["info"]
+    assert all(i["refinements"] >= 1 for i in r["info"]), r["info"]
+    A = gp.ky_matrix(k, w.X)
+    ld = float(krylov.quadform_log(A, w.Z).mean())
+    assert r["logdet"] == pytest.approx(ld, rel=1e-4)
+    g = gp.same_probe_grad(k, w.X, w.y, w.Z)
+    assert np.linalg.norm(np.array(r["grad"]) - g) / np.linalg.norm(g) <= 1e-3
+
+
 def test_x1_cg_reports_status(mf):
     # Plain bf16 entries perturb K by more than sigma^2 = 0.01 at exact1k, so
     # the x1 operator may be indefinite: the solver must report what happened.

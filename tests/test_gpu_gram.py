@@ -2,10 +2,9 @@
 the FP64 oracle, at the FP32 matvec bar: per-column relative error <= 1e-5.
 
 The form computes r2 = |g_i|^2 + |g_j|^2 - 2 g_i.g_j from mean-centred
-prescaled points: factored (2^(-|g_i|^2) 2^(2 g_i.g_j) 2^(-|g_j|^2)) while
-max |g|^2 <= 62, augmented (the norms as two more MFMA dimensions, r2 out of
-the MFMA) up to 160 for d <= 6, and direct differences above; the launch
-picks the branch from the maximum it computes.  All three are exercised here.
+prescaled points, factored as 2^(-|g_i|^2) 2^(2 g_i.g_j) 2^(-|g_j|^2), while
+max |g|^2 <= 62, and direct differences above; the launch picks the branch
+from the maximum it computes.  Both branches are exercised here.
 """
 
 import numpy as np
@@ -101,38 +100,19 @@ def _max_norm(X, lengthscale):
     return float(((u - u.mean(axis=0)) ** 2).sum(axis=1).max())
 
 
-@pytest.mark.parametrize("d,ls,t", [(2, 0.05, 1), (2, 0.05, 17), (2, 0.05, 33), (1, 0.035, 33),
-                                    (3, 0.058, 17), (4, 0.07, 33), (5, 0.1, 16), (6, 0.11, 1)])
-def test_gram_augmented_branch(mf, d, ls, t):
-    # 62 < max |g|^2 <= 160: the augmented form runs (its result differs from
-    # the direct form's) and meets the FP32 bar; d = 2, l = 0.05 is the
-    # rbf500k geometry (max |g|^2 about 144).
-    banner(f"matvec fp32_gram augmented: rbf d={d} l={ls} n=4000 t={t}")
-    w = inputs.random_problem(650 + d, 4000, d, "rbf", lengthscale=ls)
+@pytest.mark.parametrize("d,ls,t", [(2, 0.05, 1), (2, 0.05, 17), (1, 0.035, 33), (4, 0.07, 33),
+                                    (6, 0.11, 1), (8, 0.12, 17)])
+def test_gram_above_its_bound_runs_direct_differences(mf, d, ls, t):
+    # 62 < max |g|^2 <= 160 (d = 2, l = 0.05 is the rbf500k geometry, about
+    # 144): the factors would leave binary32, so the launch runs the direct
+    # differences and meets the FP32 bar.
+    banner(f"matvec fp32_gram above the bound: rbf d={d} l={ls} n=4000 t={t}")
+    n = 3000 if d >= 7 else 4000
+    w = inputs.random_problem((650 if d < 7 else 670) + d, n, d, "rbf", lengthscale=ls)
     g2 = _max_norm(w.X, ls)
     assert 62.0 < g2 <= 160.0, g2
-    V = inputs.gaussian_rhs(660 + t, 4000, t)
-    k = mkern(w)
-    out = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32_gram"))
-    direct = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32_direct"))
-    assert not np.array_equal(out, direct)
-    ref = gp.ky_matrix(okern(w), w.X) @ V.astype(np.float64)
-    err = col_rel_err(out, ref)
-    print(f"max|g|^2 = {g2:.1f}: augmented-form column errors up to {err.max():.2e}")
-    assert err.max() <= TOL
-
-
-@pytest.mark.parametrize("d,ls", [(7, 0.12), (8, 0.12)])
-def test_gram_beyond_factored_bound_high_d(mf, d, ls):
-    # d + 2 > 8: no augmented form; above 62 the launch runs direct
-    # differences, bitwise the direct form's result.
-    banner(f"matvec fp32_gram d={d} l={ls} above the factored bound: direct branch")
-    w = inputs.random_problem(670 + d, 3000, d, "rbf", lengthscale=ls)
-    g2 = _max_norm(w.X, ls)
-    assert g2 > 62.0, g2
-    V = inputs.gaussian_rhs(671, 3000, 17)
-    k = mkern(w)
-    out = host(mf.kernel_matvec(k, dev(w.X), dev(V), precision="fp32_gram"))
+    V = inputs.gaussian_rhs(660 + t, n, t)
+    out = host(mf.kernel_matvec(mkern(w), dev(w.X), dev(V), precision="fp32_gram"))
     ref = gp.ky_matrix(okern(w), w.X) @ V.astype(np.float64)
     assert col_rel_err(out, ref).max() <= TOL
 

@@ -63,10 +63,13 @@ int main() {
                 cycle_wants_fallback(true, 1.0, 1e-5, 1e-6), cycle_gave_nothing(2e-6, 2e-6),
                 cycle_gave_nothing(2e-6, 1.9e-6));
     std::printf("%d\n", cycle_wants_fallback(false, 1.0, NAN, 1e-6));
-    // a floor far above tol: one more cycle of the same reduction would not reach it
-    std::printf("%d %d %d %d\n", cycle_wants_fallback(false, 1.0, 1.5e-3, 1e-6),
-                cycle_wants_fallback(false, 1.0, 9e-4, 1e-6), cycle_wants_fallback(false, 1e-2, 1.5e-4, 1e-6),
-                cycle_wants_fallback(false, 1.0, 0.05, 1e-6));
+    // a floor far above tol: two more cycles of the same reduction would not reach it
+    std::printf("%d %d %d %d %d\n", cycle_wants_fallback(false, 1.0, 1.5e-2, 1e-6),
+                cycle_wants_fallback(false, 1.0, 8e-3, 1e-6), cycle_wants_fallback(false, 1e-2, 1.5e-3, 1e-6),
+                cycle_wants_fallback(false, 1.0, 0.05, 1e-6), cycle_wants_fallback(false, 1.0, 1.5e-3, 1e-6));
+    // progress reports: the worst recurrence over the columns still iterating
+    std::printf("%.3f %.3f\n", worst_recurrence({0, 1, 0}, {4.0, 1.0, 9.0}, {1.0, 1.0, 1.0}),
+                worst_recurrence({0, 0, 0}, {4.0, 1.0, 9.0}, {1.0, 1.0, 1.0}));
     return 0;
 }
 """
@@ -123,8 +126,15 @@ def test_cycle_judgements(results):
 
 
 def test_cycle_judgement_of_a_high_floor(results):
-    # 1 -> 1.5e-3: a repeat would end at 2.25e-6 > 1e-6, take the next form;
-    # 1 -> 9e-4: a repeat reaches 8.1e-7, refine on the same form;
-    # 1e-2 -> 1.5e-4: a repeat reaches 2.25e-6, take the next form;
-    # 1 -> 0.05 (an inexact form's floor): take the next form
-    assert results[11].split() == ["1", "0", "1", "1"]
+    # 1 -> 1.5e-2: two repeats would end at 3.4e-6 > 1e-6, take the next form;
+    # 1 -> 8e-3: two repeats reach 5.1e-7, refine on the same form;
+    # 1e-2 -> 1.5e-3: two repeats reach 3.4e-5, take the next form;
+    # 1 -> 0.05 (an inexact form's floor): take the next form;
+    # 1 -> 1.5e-3: refine on the same form
+    assert results[11].split() == ["1", "0", "1", "1", "0"]
+
+
+def test_progress_reports_the_live_columns(results):
+    # a stopped column keeps its last norm (3.0 here); the report shows the
+    # columns still iterating (1.0), or every column when none is
+    assert results[12].split() == ["1.000", "3.000"]
