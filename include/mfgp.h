@@ -436,8 +436,9 @@ typedef struct mfgp_batch_plan_s* mfgp_batch_plan;
  * outputscale or noise, a negative offset, or row_off that is not the prefix
  * sum of n (rows must be packed back to back in problem order);
  * MFGP_UNSUPPORTED for a column count without a compiled kernel, the
- * MFGP_PERIODIC or MFGP_LINEAR family, or a kernel sum or product (next or
- * times != NULL). */
+ * MFGP_PERIODIC or MFGP_LINEAR family, a kernel sum or product (next or
+ * times != NULL), or a problem with n_b > 2^24 rows (the per-problem fragment
+ * indices are 32-bit). */
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter,
                            int32_t tune, int32_t use_graph, mfgp_batch_plan* plan);
 int mfgp_batch_plan_destroy(mfgp_batch_plan plan);

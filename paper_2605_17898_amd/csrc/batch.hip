@@ -206,9 +206,11 @@ __global__ __launch_bounds__(kBlock) void batch_hyb_kernel(
 
 // Fragments of every problem's packed V block (layout as in the single-problem
 // hybrid sweep), problem found by binary search over the fragment offsets.
+// (The fragments of a problem whose columns have all stopped are not read
+// by the sweep, which skips its tiles: they are not packed either.)
 __global__ void batch_pack_hfrag_kernel(const float* __restrict__ V, const BProb* __restrict__ probs,
                                         const int64_t* __restrict__ foffs, int nprob, int t, int nt,
-                                        int tv, float* __restrict__ F) {
+                                        int tv, float* __restrict__ F, const int* __restrict__ live) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= foffs[nprob]) return;
     int lo = 0, hi = nprob - 1;
@@ -216,13 +218,16 @@ __global__ void batch_pack_hfrag_kernel(const float* __restrict__ V, const BProb
         const int mid = (lo + hi + 1) >> 1;
         if (foffs[mid] <= idx) lo = mid; else hi = mid - 1;
     }
+    if (!problem_live(live, lo, t)) return;
     const BProb pb = probs[lo];
-    const int W = nt + tv;
-    const int64_t loc = idx - foffs[lo];
+    const unsigned W = static_cast<unsigned>(nt + tv);
+    // a problem's fragments number at most n_b / 4 steps x 64 lanes x W < 2^32:
+    // 32-bit index arithmetic (64-bit division is a long instruction sequence)
+    const unsigned loc = static_cast<unsigned>(idx - foffs[lo]);
     const int w = static_cast<int>(loc % W);
-    const int64_t lq = loc / W;
-    const int l = static_cast<int>(lq % 64);
-    const int64_t q = lq / 64;
+    const unsigned lq = loc / W;
+    const int l = static_cast<int>(lq & 63u);
+    const int64_t q = lq >> 6;
     const int64_t j = q * kHK + l / 16;
     const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
     F[idx] = (j < pb.n) ? V[(pb.row_off + j) * t + c] : 0.0f;
@@ -280,20 +285,25 @@ __global__ void batch_pack_bfrag_kernel(const float* __restrict__ V, const BProb
                                         const int64_t* __restrict__ goffs, const int64_t* __restrict__ yoffs,
                                         int nprob, int t, int tv, int nt, int split, bf16x8* __restrict__ Gh,
                                         bf16x8* __restrict__ Gm, bf16x8* __restrict__ Gl,
-                                        float* __restrict__ Gy) {
+                                        float* __restrict__ Gy, const int* __restrict__ live) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (tv && idx < yoffs[nprob]) {
-        const BProb pb = probs[find_slot(yoffs, nprob, idx)];
-        const int64_t j = idx - pb.y_off;
-        Gy[idx] = j < pb.n ? V[(pb.row_off + j) * t] : 0.0f;
+        const int b = find_slot(yoffs, nprob, idx);
+        if (problem_live(live, b, t)) {
+            const BProb pb = probs[b];
+            const int64_t j = idx - pb.y_off;
+            Gy[idx] = j < pb.n ? V[(pb.row_off + j) * t] : 0.0f;
+        }
     }
     if (idx >= goffs[nprob]) return;
-    const BProb pb = probs[find_slot(goffs, nprob, idx)];
-    const int64_t loc = idx - pb.g_off;
-    const int l = static_cast<int>(loc % 64);
-    const int64_t f = loc / 64;
-    const int ct = static_cast<int>(f % nt);
-    const int64_t jt = f / nt;
+    const int bg = find_slot(goffs, nprob, idx);
+    if (!problem_live(live, bg, t)) return;
+    const BProb pb = probs[bg];
+    const unsigned loc = static_cast<unsigned>(idx - pb.g_off);   // < 2^32 per problem
+    const int l = static_cast<int>(loc & 63u);
+    const unsigned f = loc >> 6;
+    const int ct = static_cast<int>(f % static_cast<unsigned>(nt));
+    const int64_t jt = f / static_cast<unsigned>(nt);
     bf16x8 h8, m8, l8;
     vfrag(V + pb.row_off * t, pb.n, t, tv, jt, ct, l, h8, m8, l8);
     Gh[idx] = h8;
@@ -480,7 +490,7 @@ __global__ void bcg_beta_kernel(CgState st, int T, const double* __restrict__ rr
     double b = 0.0;
     if (st.active[q]) {
         b = rrn / st.rr[q];
-        if (*log_coeffs && st.lanlen[q] < max_iter) {
+        if (log_coeffs[q] && st.lanlen[q] < max_iter) {
             double* cf = st.coeff + (static_cast<int64_t>(q) * max_iter + st.lanlen[q]) * 2;
             cf[0] = st.alpha[q];
             cf[1] = b;
@@ -498,13 +508,17 @@ __global__ void bcg_beta_kernel(CgState st, int T, const double* __restrict__ rr
     st.beta[q] = b;
 }
 
+// Re-activate restarted columns with their new residual norm; a restarted
+// column no longer records Lanczos coefficients (the tridiagonal of the SLQ
+// belongs to its first cycle).
 __global__ void bcg_activate_kernel(CgState st, int T, const int* __restrict__ restart,
-                                    const double* __restrict__ rr_new) {
+                                    const double* __restrict__ rr_new, int* __restrict__ log_coeffs) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= T) return;
     if (restart[q]) {
         st.active[q] = rr_new[q] > 0.0 ? 1 : 0;
         st.rr[q] = rr_new[q];
+        log_coeffs[q] = 0;
     }
 }
 
@@ -684,7 +698,7 @@ static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     w.seg_first = cv.take<int>(P.nprob + 1);
     w.row_offs = cv.take<int64_t>(P.nprob + 1);
     w.counter = cv.take<int>(64);
-    w.logflag = cv.take<int>(64);
+    w.logflag = cv.take<int>(T + 64);   // per column: records Lanczos coefficients
     w.frag = cv.take<float>(P.frag_off.empty() ? 0 : P.frag_off.back());
     w.foffs = cv.take<int64_t>(P.nprob + 1);
     const size_t g = P.gfrag_off.empty() ? 0 : static_cast<size_t>(P.gfrag_off.back());
@@ -741,7 +755,7 @@ static hipError_t launch_bhyb(const mfgp_batch_plan_s& P, const BatchWs& w, int 
                               float* part, const int* live, hipStream_t s) {
     const int64_t total = P.frag_off.back();
     hipLaunchKernelGGL(batch_pack_hfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
-                       s, V, w.probs, w.foffs, P.nprob, P.t, P.hyb_nt, P.hyb_tv, w.frag);
+                       s, V, w.probs, w.foffs, P.nprob, P.t, P.hyb_nt, P.hyb_tv, w.frag, live);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (P.family) {
@@ -813,7 +827,8 @@ static hipError_t launch_bmfma(const mfgp_batch_plan_s& P, const BatchWs& w, int
     const int tv = vec_cols(P.t), nt = col_tiles(P.t), split = split_of(P.precision);
     const int64_t total = std::max<int64_t>(P.gfrag_off.back(), P.y_off.back());
     hipLaunchKernelGGL(batch_pack_bfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
-                       s, V, w.probs, w.goffs, w.yoffs, P.nprob, P.t, tv, nt, split, w.gh, w.gm, w.gl, w.gy);
+                       s, V, w.probs, w.goffs, w.yoffs, P.nprob, P.t, tv, nt, split, w.gh, w.gm, w.gl, w.gy,
+                       live);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (P.family) {
@@ -1009,6 +1024,10 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
             delete P;
             return MFGP_ERR_ARG;
         }
+        if (n > (int64_t(1) << 24)) {   // per-problem fragment indices are 32-bit
+            delete P;
+            return MFGP_UNSUPPORTED;
+        }
         P->n.push_back(n);
         P->row_off.push_back(batch->row_off[b]);
         P->x_off.push_back(batch->x_off[b]);
@@ -1187,8 +1206,8 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     B_CHECK(copy2_f32(w.Bm, st.r, st.p, rt, s));
     B_CHECK(bdots_ff(P, w, st.r, st.r, st.rr, s));
     hipLaunchKernelGGL(bcg_init_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, tol * tol);
-    const int one = 1, zero = 0;
-    B_CHECK(hipMemcpyAsync(w.logflag, &one, sizeof(int), hipMemcpyHostToDevice, s));
+    const std::vector<int> log_on(T, 1);
+    B_CHECK(hipMemcpyAsync(w.logflag, log_on.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
 
     int check_every = opts->check_every > 0 ? opts->check_every : 8;
     // Residual replacement only with a check at least every other iteration
@@ -1243,6 +1262,11 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     // batched sweep keeps its precision: no fallback to another form)
     std::vector<StallTracker> h_stall(T);
     std::vector<int> h_nstall(T, 0);
+    // per problem: finished (every column assessed and stopped); per column:
+    // stopped and judged final since its last restart, and its last
+    // recomputed true relative residual
+    std::vector<char> done(nprob, 0), assessed(T, 0);
+    std::vector<double> h_final(T, 0.0);
     B_CHECK2(hipMemcpyAsync(h_rep.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipStreamSynchronize(s));
@@ -1266,6 +1290,79 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
         }
         if (stop)
             B_CHECK2(hipMemcpyAsync(st.active, h_active.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
+
+        // A column that has stopped ends its cycle now, not when the slowest
+        // problem of the batch (or the slowest column of its own problem)
+        // does: its problem's true residual is recomputed (FP64 accumulation)
+        // and the column restarts from it if it is above tol, while every
+        // other column keeps iterating.
+        std::vector<int> ending;
+        for (int b = 0; b < nprob; ++b) {
+            if (done[b]) continue;
+            bool fresh = false;
+            for (int c = 0; c < t; ++c) {
+                const int q = b * t + c;
+                fresh = fresh || (!(h_active[q] && h_iters[q] < max_iter) && !assessed[q]);
+            }
+            if (fresh) ending.push_back(b);
+        }
+        if (!ending.empty()) {
+            for (int b : ending) {
+                const int64_t o = P.row_off[b] * t;
+                B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
+            }
+            // columns of every problem are reduced; only those of the ending
+            // problems (whose R64 was just written) are read
+            B_CHECK2(bdots_dd(P, w, w.R64, w.R64, w.tmp, s));
+            B_CHECK2(hipMemcpyAsync(h_relt.data(), w.tmp, T * sizeof(double), hipMemcpyDeviceToHost, s));
+            B_CHECK2(hipMemcpyAsync(h_status.data(), st.status, T * sizeof(int), hipMemcpyDeviceToHost, s));
+            B_CHECK2(hipStreamSynchronize(s));
+            std::fill(h_restart.begin(), h_restart.end(), 0);
+            bool again = false;
+            for (int b : ending) {
+                bool finished = true;
+                for (int c = 0; c < t; ++c) {
+                    const int q = b * t + c;
+                    if (h_active[q] && h_iters[q] < max_iter) {
+                        finished = false;   // still iterating: its R64 is not read
+                        continue;
+                    }
+                    if (assessed[q]) continue;
+                    h_final[q] = h_b2[q] > 0.0 ? std::sqrt(h_relt[q] / h_b2[q]) : 0.0;
+                    const bool need = h_status[q] == MFGP_OK && !(h_final[q] <= tol) && std::isfinite(h_final[q]) &&
+                                      h_refine[q] < max_refine && h_iters[q] < max_iter;
+                    if (need) {
+                        h_restart[q] = 1;
+                        h_refine[q] += 1;
+                        finished = false;
+                        again = true;
+                    } else {
+                        assessed[q] = 1;
+                    }
+                }
+                if (finished) done[b] = 1;
+            }
+            if (again) {
+                B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(bcg_restart_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s,
+                                   st, w.segs, t, w.R64, restart);
+                B_CHECK2(bdots_ff(P, w, st.r, st.r, w.tmp + T, s));
+                hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart,
+                                   w.tmp + T, w.logflag);
+                B_CHECK2(hipGetLastError());
+                B_CHECK2(hipMemcpyAsync(h_rep.data(), w.tmp + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
+                B_CHECK2(hipStreamSynchronize(s));
+                for (int q = 0; q < T; ++q) {
+                    if (!h_restart[q]) continue;
+                    h_norepl[q] = 0;   // a fresh cycle starts without drift
+                    h_stall[q].begin(h_iters[q], h_rep[q]);
+                    h_active[q] = h_rep[q] > 0.0 ? 1 : 0;
+                    h_rr[q] = h_rep[q];
+                    if (!h_active[q]) assessed[q] = 1;   // restarted at an exact zero residual
+                }
+            }
+        }
+
         // Residual replacement (as in the single-problem solver): a tenfold drop
         // since the last true residual triggers it; active columns that fell at
         // least 1.5x join; only problems with a flagged column recompute.
@@ -1280,6 +1377,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
             if (can && h_rr[q] <= 0.01 * h_rep[q]) trig[q / t] = 1;
             h_restart[q] = (can && h_rr[q] <= 0.44 * h_rep[q]) ? 1 : 0;
         }
+        if (!any) break;   // every problem is done
         for (int q = 0; q < T; ++q) h_restart[q] = trig[q / t] ? h_restart[q] : 0;
         for (int b = 0; b < nprob; ++b) replace = replace || trig[b];
         if (replace) {
@@ -1320,52 +1418,16 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
             opts->progress(opts->progress_user, steps, worst_recurrence(h_active, h_rr, h_b2));
             while (next_report <= steps) next_report += report_every;
         }
-        if (any) {
-            steps += check_every;
-            if (exec) {
-                B_CHECK2(hipGraphLaunch(exec, s));
-                P.graph_launches += 1;
-            } else {
-                for (int k = 0; k < check_every; ++k) B_CHECK2(batch_iteration(P, w, st, ntiles, tol, s));
-            }
-            continue;
-        }
-        // all stopped: recompute true residuals problem by problem (FP64 accumulation)
-        for (int b = 0; b < nprob; ++b) {
-            const int64_t o = P.row_off[b] * t;
-            B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
-        }
-        B_CHECK2(bdots_dd(P, w, w.R64, w.R64, w.tmp, s));
-        B_CHECK2(hipMemcpyAsync(h_relt.data(), w.tmp, T * sizeof(double), hipMemcpyDeviceToHost, s));
-        B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
-        B_CHECK2(hipMemcpyAsync(h_status.data(), st.status, T * sizeof(int), hipMemcpyDeviceToHost, s));
-        B_CHECK2(hipStreamSynchronize(s));
-        bool again = false;
-        for (int q = 0; q < T; ++q) {
-            h_relt[q] = h_b2[q] > 0.0 ? std::sqrt(h_relt[q] / h_b2[q]) : 0.0;
-            const bool need = h_status[q] == MFGP_OK && !(h_relt[q] <= tol) && std::isfinite(h_relt[q]) &&
-                              h_refine[q] < max_refine && h_iters[q] < max_iter;
-            h_restart[q] = need ? 1 : 0;
-            if (need) {
-                h_refine[q] += 1;
-                again = true;
-            }
-        }
-        if (!again) break;
-        B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(bcg_restart_kernel, dim3(static_cast<unsigned>(P.segs.size())), dim3(256), 0, s, st,
-                           w.segs, t, w.R64, restart);
-        B_CHECK2(bdots_ff(P, w, st.r, st.r, w.tmp + T, s));
-        hipLaunchKernelGGL(bcg_activate_kernel, dim3(nblocks(T)), dim3(256), 0, s, st, T, restart, w.tmp + T);
-        B_CHECK2(hipMemcpyAsync(w.logflag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
-        B_CHECK2(hipMemcpyAsync(h_rep.data(), w.tmp + T, T * sizeof(double), hipMemcpyDeviceToHost, s));
-        B_CHECK2(hipStreamSynchronize(s));
-        for (int q = 0; q < T; ++q) {
-            if (!h_restart[q]) continue;
-            h_norepl[q] = 0;   // a fresh cycle starts without drift
-            h_stall[q].begin(h_iters[q], h_rep[q]);
+        steps += check_every;
+        if (exec) {
+            B_CHECK2(hipGraphLaunch(exec, s));
+            P.graph_launches += 1;
+        } else {
+            for (int k = 0; k < check_every; ++k) B_CHECK2(batch_iteration(P, w, st, ntiles, tol, s));
         }
     }
+    B_CHECK2(hipMemcpyAsync(h_status.data(), st.status, T * sizeof(int), hipMemcpyDeviceToHost, s));
+    for (int q = 0; q < T; ++q) h_relt[q] = h_final[q];
     cleanup();
     B_CHECK(hipMemcpyAsync(h_rr.data(), st.rr, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK(hipMemcpyAsync(h_lan.data(), st.lanlen, T * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -57,6 +57,10 @@ def test_batch_plan_validation(m):
     assert _create(m, [100, 50], [2, 3], [ks, ks]) == m.UNSUPPORTED
     kx = k * k
     assert _create(m, [100, 50], [2, 3], [kx, kx]) == m.UNSUPPORTED
+    # per-problem fragment indices are 32-bit: at most 2^24 rows per problem
+    # (host validation only; nothing is allocated)
+    assert _create(m, [2 ** 24, 50], [1, 3], [k, k]) == m.OK
+    assert _create(m, [2 ** 24 + 1, 50], [1, 3], [k, k]) == m.UNSUPPORTED
 
 
 def test_bench_refuses_more_than_one_gpu():
