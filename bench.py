@@ -448,7 +448,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32",
                     choices=["fp32", "fp32_direct", "fp32_valu", "bf16x1", "bf16x2", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-rows", type=int, default=10240)
     ap.add_argument("--mode", default="step",
                     choices=["step", "kernel", "batch", "rbf500k", "matvec", "small", "composite", "ski",
                              "variance"])
