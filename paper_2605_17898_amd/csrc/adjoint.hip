@@ -50,6 +50,130 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(
     block_sum_write<D + 1>(v, red, partial + static_cast<int64_t>(blockIdx.x) * (D + 1));
 }
 
+// The same sums with the weights W_ij = sum_c (w_c A_ic) B_jc on the FP32
+// matrix cores (many right-hand sides: tb >= 16).  Rows as in the product
+// sweeps (a wave owns kHRT tiles of 16 rows, a block 256 rows), j in blocks
+// of 16.  Per row tile and block, NC = ceil(tb / 4) v_mfma_f32_16x16x4_f32
+// contract over the columns c: the A operand (16 j x 4 c) is lane l's
+// B[jb + l % 16][4 k + l / 16], the B operand (4 c x 16 i) its
+// w_c A[i][4 k + l / 16], so accumulator register s of lane l holds W_ij for
+// i = row l % 16 and j = jb + 4 (l / 16) + s; columns c >= tb and rows j past
+// the range carry zeros.  The lane then forms that entry's distance, kernel
+// value and derivative factor on the VALU (as adjoint_rows) and accumulates
+// W_ij g du_k^2 and W_ij k^ in two-level FP32 sums.  The VALU work per entry
+// drops from ~(tb + 5d + 4) to ~(5d + 4) operations; the contraction costs
+// NC MFMAs per 256 entries.
+template <int FAM, int D, int NC>
+__global__ __launch_bounds__(kBlock) void adjoint_mfma_kernel(
+    const float* __restrict__ U, const float* __restrict__ A, int lda, int c0, ColW w,
+    const float* __restrict__ B, int tb, int64_t n, int chunks, int64_t jchunk,
+    double* __restrict__ partial) {
+    __shared__ double red[(D + 1) * (kBlock / 64)];
+    int rb, ch;
+    map_block(blockIdx.x, chunks, rb, ch);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane >> 4;
+    const int r16 = lane & 15;
+    const int64_t row0 = static_cast<int64_t>(rb) * kBlock + wave * (kHRT * 16);
+
+    // B operand (w_c A_ic) and u_i of the lane's row in each row tile
+    float ai[kHRT][NC], ui[kHRT][D];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        const int64_t i = row0 + r * 16 + r16;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int k = 0; k < D; ++k) ui[r][k] = U[ic * D + k];
+#pragma unroll
+        for (int kc = 0; kc < NC; ++kc) {
+            const int c = 4 * kc + grp;
+            ai[r][kc] = (i < n && c < tb) ? A[ic * lda + c0 + c] * w.w[c] : 0.0f;
+        }
+    }
+    float g[kHRT][D], gs[kHRT], tg[kHRT][D], ts[kHRT];
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+        gs[r] = 0.0f;
+        ts[r] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            g[r][k] = 0.0f;
+            tg[r][k] = 0.0f;
+        }
+    }
+
+    const int64_t j0 = static_cast<int64_t>(ch) * jchunk;
+    const int64_t j1 = j0 + jchunk < n ? j0 + jchunk : n;
+    const int64_t nblk = j0 < j1 ? (j1 - j0 + 15) / 16 : 0;
+    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t jb = j0 + b * 16;
+        // A operand: B rows of the block (zero past the range and past tb)
+        const int64_t ja = jb + r16;
+        float bj[NC];
+#pragma unroll
+        for (int kc = 0; kc < NC; ++kc) {
+            const int c = 4 * kc + grp;
+            bj[kc] = (ja < j1 && c < tb) ? B[ja * tb + c] : 0.0f;
+        }
+        // u_j of the lane's four entries (clamped rows carry W = 0)
+        float uj[4][D];
+#pragma unroll
+        for (int sq = 0; sq < 4; ++sq) {
+            int64_t js = jb + 4 * grp + sq;
+            js = js < n ? js : n - 1;
+#pragma unroll
+            for (int k = 0; k < D; ++k) uj[sq][k] = U[js * D + k];
+        }
+#pragma unroll
+        for (int r = 0; r < kHRT; ++r) {
+            f32x4 W = zero4;
+#pragma unroll
+            for (int kc = 0; kc < NC; ++kc) W = __builtin_amdgcn_mfma_f32_16x16x4f32(bj[kc], ai[r][kc], W, 0, 0, 0);
+#pragma unroll
+            for (int sq = 0; sq < 4; ++sq) {
+                float df[D];
+                float d2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    df[k] = ui[r][k] - uj[sq][k];
+                    d2 = fmaf(df[k], df[k], d2);
+                }
+                float kv, gf;
+                kentry_and_dfac<FAM>(d2, kv, gf);
+                const float wij = W[sq];
+                gs[r] = fmaf(wij, kv, gs[r]);
+                const float wd = wij * gf;
+#pragma unroll
+                for (int k = 0; k < D; ++k) g[r][k] = fmaf(wd * df[k], df[k], g[r][k]);
+            }
+        }
+        if (((b + 1) & (kSeg / 16 - 1)) == 0) {
+#pragma unroll
+            for (int r = 0; r < kHRT; ++r) {
+                ts[r] += gs[r];
+                gs[r] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    tg[r][k] += g[r][k];
+                    g[r][k] = 0.0f;
+                }
+            }
+        }
+    }
+    double v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kHRT; ++r) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] += static_cast<double>(tg[r][k]) + static_cast<double>(g[r][k]);
+        v[D] += static_cast<double>(ts[r]) + static_cast<double>(gs[r]);
+    }
+    block_sum_write<D + 1>(v, red, partial + static_cast<int64_t>(blockIdx.x) * (D + 1));
+}
+
 __global__ void adjoint_final_kernel(const double* __restrict__ partial, int nblocks, int width,
                                      double* __restrict__ out, int accumulate) {
     const int k = threadIdx.x;
@@ -65,12 +189,20 @@ static hipError_t adjoint_fd(int tb, const float* U, const float* A, int lda, in
                              double* partial, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(p.rowblocks) * p.chunks);
     switch (tb) {
+        // many right-hand sides: the weights on the matrix cores
+#define MFGP_MCASE(TBV, NCV)                                                                          \
+    case TBV:                                                                                         \
+        hipLaunchKernelGGL((adjoint_mfma_kernel<FAM, D, NCV>), grid, dim3(kBlock), 0, s, U, A, lda, c0, w, \
+                           B, TBV, n, p.chunks, p.jchunk, partial);                                   \
+        return hipGetLastError();
+        MFGP_MCASE(16, 4) MFGP_MCASE(17, 5) MFGP_MCASE(32, 8) MFGP_MCASE(33, 9)
+#undef MFGP_MCASE
 #define MFGP_CASE(TBV)                                                                        \
     case TBV:                                                                                 \
         hipLaunchKernelGGL((adjoint_kernel<FAM, D, TBV>), grid, dim3(kBlock), 0, s, U, A, lda, \
                            c0, w, B, n, p.chunks, p.jchunk, partial);                         \
         return hipGetLastError();
-        MFGP_TB_LIST(MFGP_CASE)
+        MFGP_CASE(1) MFGP_CASE(2) MFGP_CASE(3) MFGP_CASE(4) MFGP_CASE(5) MFGP_CASE(6) MFGP_CASE(7) MFGP_CASE(8)
 #undef MFGP_CASE
         default:
             return hipErrorInvalidValue;

@@ -2,7 +2,7 @@
 // gradient kernels (see adjoint.hip for the mathematics).
 #pragma once
 
-#include "sweep_kernels.hpp"
+#include "hybrid_kernels.hpp"
 
 namespace mfgp {
 

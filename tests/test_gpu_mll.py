@@ -116,6 +116,23 @@ def test_adjoint_vs_oracle(mf, family, ard):
     assert np.linalg.norm(np.array(g) - ref) / np.linalg.norm(ref) <= 1e-4
 
 
+@pytest.mark.parametrize("family,d,t", [("rbf", 4, 33), ("rbf", 1, 16), ("rbf", 8, 17), ("matern12", 3, 32),
+                                       ("matern32", 2, 33), ("matern52", 6, 35), ("matern52", 5, 17)])
+def test_adjoint_many_columns_vs_oracle(mf, family, d, t):
+    # t >= 16 takes the weights W_ij = sum_c w_c A_ic B_jc on the matrix cores
+    # (t = 35: a 33-column block on them, then a 2-column block on the VALU);
+    # n = 1201 leaves a ragged row block and a ragged last 16-j block.
+    banner(f"adjoint (MFMA weights) family={family} d={d} n=1201 t={t}, ARD")
+    w = inputs.random_problem(31 + d, 1201, d, family, ard=True, noise=0.03)
+    rng = np.random.default_rng(3 + t)
+    A = rng.standard_normal((w.n, t)).astype(np.float32)
+    B = rng.standard_normal((w.n, t)).astype(np.float32)
+    colw = list(rng.uniform(-1.0, 1.0, size=t))
+    g = mf.kernel_adjoint(mkern(w), dev(w.X), dev(A), dev(B), colw)
+    ref = gp.adjoint_bilinear(okern(w), w.X, A, B, colw)
+    assert np.linalg.norm(np.array(g) - ref) / np.linalg.norm(ref) <= 1e-4
+
+
 def test_seeded_probes_equal_explicit(mf):
     banner("mll with device-seeded probes == explicit SplitMix64 probes")
     from oracle import probes
