@@ -72,6 +72,17 @@ STEP_KERNELS = {
     "fp32_direct": ("sweep_hyb_kernel<RBF, d=4, NT=2, TV=1> (FP32 entries from direct differences on "
                     "the VALU, contraction on v_mfma_f32_16x16x4_f32)", "alu", HYB_TRAFFIC_BYTES),
 }
+# Pipe utilisation of the dominant kernel from rocprofv3 SQ counters (taken
+# from the named profile, not measured in this run): the matrix-core busy
+# fraction and the VALU work beside it.
+STEP_COUNTERS = {
+    "fp32": {"mfma_busy": 0.742, "mfma_insts_per_64_entries": 2.25, "valu_insts_per_64_entries": 2.61,
+             "valu_trans_per_64_entries": 1.00,
+             "source": "profiles/sweep_gram_rbf_d4_t33_rbf100k.md (SQ_VALU_MFMA_BUSY_CYCLES / GRBM_GUI_ACTIVE, "
+                       "SQ_INSTS_VALU*; not measured in this run)"},
+    "fp32_direct": {"mfma_busy": 0.538, "valu_insts_per_64_entries": 11.3,
+                    "source": "profiles/sweep_hyb_rbf_d4_t33_rbf100k.md (same counters; not measured in this run)"},
+}
 METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
 
 
@@ -591,6 +602,7 @@ def main() -> int:
             "kernel": STEP_KERNELS.get(args.precision, ("bf16 mfma sweep", "", None))[0],
             "flop_per_entry": 3 * 4 + 1 + 2 * 33,
             "launch_avg_ms": dom["ms"] / max(dom["launches"], 1),
+            "counters": STEP_COUNTERS.get(args.precision),
         },
     }
     if args.precision == "fp32":
