@@ -72,7 +72,22 @@ CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision) {
                                                  : mfma_scratch_bytes(n, n, t, p));
     b.apply = reinterpret_cast<float*>(cv.take<char>(apply));
     b.sum = cv.take<char>(sum_scratch_bytes(n, t));
+    b.gram = n >= kGramMinN ? static_cast<void*>(cv.take<char>(gram_prep_bytes(n))) : nullptr;
     return b;
+}
+
+// The operator of a solve's products: op itself, with the Gram-form data of
+// its points prepared once into b.gram when the products may take the Gram
+// form (an RBF-class single term at n >= kGramMinN; the points do not change
+// during the solve).
+static hipError_t solve_operator(const Operator& op, const CgBufs& b, Operator& opg, GramPrep& pre,
+                                 hipStream_t s) {
+    opg = op;
+    if (!b.gram || op.ski || op.general || op.family != MFGP_RBF || op.d < 1 || op.d > 8 || op.n < kGramMinN)
+        return hipSuccess;
+    hipError_t e = gram_prepare(op, b.gram, pre, s);
+    if (e == hipSuccess) opg.gram_pre = &pre;
+    return e;
 }
 
 CgBufs carve_cg_vectors(Carver& cv, int64_t n, int t) {
@@ -137,7 +152,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             const double L = static_cast<double>(op.ski->g.Lr);
             work = (static_cast<double>(n) * (1 << (2 * op.ski->g.d)) + L * std::log2(L)) * t;
         }
-        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
+        check_every = work >= 1e9 ? 2 : (work >= 1e8 ? 4 : 8);
     }
     // Residual replacement only when the host sees every iteration or every
     // other one: with longer gaps it destabilised FP32 CG on ill-conditioned
@@ -145,6 +160,9 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     // refinement converged in as many iterations.
     const bool may_replace = !o.no_replacement && check_every <= kMaxReplaceGap;
     CgState st = make_state(b, X, t, coeff);
+    Operator opg;
+    GramPrep gpre;
+    CG_CHECK(solve_operator(op, b, opg, gpre, s));
     double* tmp = b.scal + 5 * t;     // [t] scratch scalars
     double* relt = b.scal + 6 * t;    // [t] true relative residual
     int* restart = b.ints + 4 * t;    // [t]
@@ -268,7 +286,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         if (any) {
             steps += check_every;
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
+                CG_CHECK(apply_op(opg, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, s));
@@ -473,9 +491,12 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
     int check_every = o.check_every;
     if (check_every <= 0) {
         const double work = static_cast<double>(n) * static_cast<double>(n) * t;
-        check_every = work >= 1e9 ? 1 : (work >= 1e8 ? 4 : 8);
+        check_every = work >= 1e9 ? 2 : (work >= 1e8 ? 4 : 8);
     }
     CgState st = make_state(b, X, t, coeff);
+    Operator opg;
+    GramPrep gpre;
+    CG_CHECK(solve_operator(op, b, opg, gpre, s));
     double* rzn = b.scal + 5 * t;     // [t] new r^T z
     double* rrn = b.scal + 6 * t;     // [t] new r^T r (st.rrn holds the current one)
     int* restart = b.ints + 4 * t;
@@ -544,7 +565,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         if (any) {
             steps += check_every;
             for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(op, st.p, t, st.ap, precision, b, s));
+                CG_CHECK(apply_op(opg, st.p, t, st.ap, precision, b, s));
                 CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
                 CG_CHECK(cg_alpha(st, t, s));
                 CG_CHECK(cg_update_rr(st, n, t, b.dots, rrn, s));

@@ -17,6 +17,8 @@ struct CgBufs {
     double* resid = nullptr;
     float* apply = nullptr;
     void* sum = nullptr;      // sum_scratch_bytes(n, t): the terms of a kernel sum
+    void* gram = nullptr;     // gram_prep_bytes(n) for n >= kGramMinN: the Gram data of the points,
+                              // prepared once per solve (null below kGramMinN)
 };
 
 CgBufs carve_cg(Carver& cv, int64_t n, int t, int precision);

@@ -380,7 +380,11 @@ hipError_t apply_gram(const Operator& op, const float* V, int t, float* out, boo
     float* F = reinterpret_cast<float*>(base + L.frag);
     float* partial = reinterpret_cast<float*>(base + L.part);
     GramPrep gp;
-    hipError_t e = gram_prepare(op, base + L.prep, gp, s);
+    hipError_t e = hipSuccess;
+    if (op.gram_pre)
+        gp = *op.gram_pre;   // prepared once by the solver
+    else
+        e = gram_prepare(op, base + L.prep, gp, s);
     if (e != hipSuccess) return e;
     float* G = gp.G;
     float* nrm = gp.nrm;

@@ -59,6 +59,8 @@ hipError_t ski_gradient(const SkiOp& op, const mfgp_kernel& k, const float* X, i
 // on the concatenated features: the periodic factor's 2 din features first
 // (periodic = 1), then dextra features of the RBF factors; factor[] keeps
 // the caller's factor order with each factor's first feature f0.
+struct GramPrep;
+
 struct Operator {
     struct Factor {
         int periodic = 0;
@@ -87,6 +89,10 @@ struct Operator {
     double ls[MFGP_MAX_D] = {};
     const float* X = nullptr;
     float* U = nullptr;
+    // The Gram-form data of these points (centred features, norms, maximum
+    // norm) when a solver prepared them once for all its products; null: each
+    // Gram-form product prepares them itself.
+    const GramPrep* gram_pre = nullptr;
 };
 
 Operator make_operator(const mfgp_kernel& k, const float* X, int64_t n, float* U);

@@ -200,7 +200,9 @@ hipError_t apply_mfma(const Operator& op, const float* Ur, int64_t m, const floa
     // FP32 form), with the fragments in the distance tiles' j order.
     const bool gram = op.family == MFGP_RBF && Ur == op.U && m == n && n >= kGramMinN && op.d >= 1 && op.d <= 8;
     GramPrep gp;
-    if (gram) {
+    if (gram && op.gram_pre) {
+        gp = *op.gram_pre;   // prepared once by the solver
+    } else if (gram) {
         hipError_t ge = gram_prepare(op, prep, gp, s);
         if (ge != hipSuccess) return ge;
     }
