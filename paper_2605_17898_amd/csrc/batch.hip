@@ -206,31 +206,28 @@ __global__ __launch_bounds__(kBlock) void batch_hyb_kernel(
 
 // Fragments of every problem's packed V block (layout as in the single-problem
 // hybrid sweep), problem found by binary search over the fragment offsets.
-// (The fragments of a problem whose columns have all stopped are not read
-// by the sweep, which skips its tiles: they are not packed either.)
+// Fragments of V for the hybrid sweep, per problem (grid laid out per problem
+// as in batch_reduce_kernel).  The fragments of a problem whose columns have
+// all stopped are not read by the sweep, which skips its tiles: they are not
+// packed either.
 __global__ void batch_pack_hfrag_kernel(const float* __restrict__ V, const BProb* __restrict__ probs,
-                                        const int64_t* __restrict__ foffs, int nprob, int t, int nt,
-                                        int tv, float* __restrict__ F, const int* __restrict__ live) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= foffs[nprob]) return;
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (foffs[mid] <= idx) lo = mid; else hi = mid - 1;
-    }
-    if (!problem_live(live, lo, t)) return;
-    const BProb pb = probs[lo];
+                                        const int* __restrict__ blk_prob, const int* __restrict__ blk_first,
+                                        int t, int nt, int tv, float* __restrict__ F, const int* __restrict__ live) {
+    const int b = blk_prob[blockIdx.x];
+    if (!problem_live(live, b, t)) return;   // uniform over the block
+    const BProb pb = probs[b];
     const unsigned W = static_cast<unsigned>(nt + tv);
-    // a problem's fragments number at most n_b / 4 steps x 64 lanes x W < 2^32:
-    // 32-bit index arithmetic (64-bit division is a long instruction sequence)
-    const unsigned loc = static_cast<unsigned>(idx - foffs[lo]);
+    // a problem's fragments: ceil(n_b / 4) steps x 64 lanes x W < 2^32 (n_b <= 2^24)
+    const unsigned cnt = static_cast<unsigned>((pb.n + kHK - 1) / kHK) * 64u * W;
+    const unsigned loc = static_cast<unsigned>(blockIdx.x - blk_first[b]) * 256u + threadIdx.x;
+    if (loc >= cnt) return;
     const int w = static_cast<int>(loc % W);
     const unsigned lq = loc / W;
     const int l = static_cast<int>(lq & 63u);
     const int64_t q = lq >> 6;
     const int64_t j = q * kHK + l / 16;
     const int c = w < nt ? tv + 16 * w + (l % 16) : w - nt;
-    F[idx] = (j < pb.n) ? V[(pb.row_off + j) * t + c] : 0.0f;
+    F[pb.f_off + loc] = (j < pb.n) ? V[(pb.row_off + j) * t + c] : 0.0f;
 }
 
 // Persistent batched sweep with the contraction on the bf16 matrix cores
@@ -313,30 +310,23 @@ __global__ void batch_pack_bfrag_kernel(const float* __restrict__ V, const BProb
 
 // ---------------------------------------------------------------- batched reductions
 
-__device__ __forceinline__ int find_problem(const int64_t* __restrict__ row_offs, int nprob,
-                                            int64_t r) {
-    int lo = 0, hi = nprob - 1;   // row_offs[nprob] = total rows
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (row_offs[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// out[r, c] = s2_b sum_ch partial[tile(b, rb, ch)][li][c] + sig2_b Vself[r, c]
-// Columns that are not active in CG (live non-NULL) are not needed: skipped.
+// out[problem rows, c] = s2 sum over the row's tile partials + sigma2 V
+// (columns not active in CG, live non-NULL, are not needed: skipped).  The
+// grid is laid out per problem (blk_prob: problem of each 256-thread block,
+// blk_first: the problem's first block), so the thread finds its problem and
+// its element (i, c) of that problem with one table load and 32-bit index
+// arithmetic (n_b t < 2^32).
 __global__ void batch_reduce_kernel(const float* __restrict__ partial, const BProb* __restrict__ probs,
-                                    const int64_t* __restrict__ row_offs, int nprob, int64_t rows,
+                                    const int* __restrict__ blk_prob, const int* __restrict__ blk_first,
                                     int t, const float* __restrict__ Vself, float* __restrict__ out,
                                     const int* __restrict__ live) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= rows * t) return;
-    const int64_t r = idx / t;
-    const int c = static_cast<int>(idx % t);
-    const int b = find_problem(row_offs, nprob, r);
-    if (live && !live[b * t + c]) return;
+    const int b = blk_prob[blockIdx.x];
     const BProb pb = probs[b];
-    const int64_t i = r - pb.row_off;
+    const unsigned loc = static_cast<unsigned>(blockIdx.x - blk_first[b]) * 256u + threadIdx.x;
+    if (loc >= static_cast<unsigned>(pb.n) * static_cast<unsigned>(t)) return;
+    const unsigned i = loc / static_cast<unsigned>(t);
+    const int c = static_cast<int>(loc - i * static_cast<unsigned>(t));
+    if (live && !live[b * t + c]) return;
     const int64_t rb = i / kBlock;
     const int64_t li = i % kBlock;
     double acc = 0.0;
@@ -344,6 +334,7 @@ __global__ void batch_reduce_kernel(const float* __restrict__ partial, const BPr
         const int64_t tile = pb.tile_base + rb * pb.chunks + ch;
         acc += static_cast<double>(partial[(tile * kBlock + li) * t + c]);
     }
+    const int64_t idx = pb.row_off * t + loc;
     out[idx] = static_cast<float>(static_cast<double>(pb.s2) * acc +
                                   static_cast<double>(pb.sig2) * static_cast<double>(Vself[idx]));
 }
@@ -584,6 +575,10 @@ struct mfgp_batch_plan_s {
     bool hybrid = false;
     std::vector<int64_t> gfrag_off;  // prefix [nprob + 1] of the BF16 fragments (bf16x8)
     std::vector<int64_t> y_off;      // prefix [nprob + 1] of the FP32 column-0 copies
+    // Per-problem grids of the element-wise kernels: the problem of each
+    // 256-thread block and each problem's first block (fragment packing of
+    // the hybrid sweep; the reduction over n_b t outputs).
+    std::vector<int> pack_blk, pack_first, red_blk, red_first;
     int precision = MFGP_FP32;       // precision of the current call's products
     // Capture stream (default priority, non-blocking): the caller's stream may
     // be the legacy NULL stream, which cannot be captured; the graph recorded
@@ -656,10 +651,10 @@ static int64_t max_tiles(const mfgp_batch_plan_s& P) {
 struct BatchWs {
     float* U; float* Bm; double* X64; float* Zgen; double* coeff; float* R; float* P; float* AP;
     double* R64; double* scal; int* ints; double* dpart; double* tmp; double* resid; char* part;
-    BTile* queue; BProb* probs; BSeg* segs; int* seg_first; int64_t* row_offs; int* counter;
+    BTile* queue; BProb* probs; BSeg* segs; int* seg_first; int* counter;
     int* logflag;
+    int* pack_blk; int* pack_first; int* red_blk; int* red_first;   // per-problem grids (plan)
     float* frag;      // MFMA fragments of the product's right-hand sides
-    int64_t* foffs;   // [nprob + 1] fragment offsets
     bf16x8* gh; bf16x8* gm; bf16x8* gl;   // BF16 fragments (three split pieces)
     float* gy;        // FP32 column 0 of the BF16 products
     int64_t* goffs;   // [nprob + 1] BF16 fragment offsets
@@ -696,11 +691,13 @@ static BatchWs carve_batch(Carver& cv, const mfgp_batch_plan_s& P) {
     w.probs = cv.take<BProb>(P.nprob);
     w.segs = cv.take<BSeg>(P.segs.size());
     w.seg_first = cv.take<int>(P.nprob + 1);
-    w.row_offs = cv.take<int64_t>(P.nprob + 1);
     w.counter = cv.take<int>(64);
     w.logflag = cv.take<int>(T + 64);   // per column: records Lanczos coefficients
+    w.pack_blk = cv.take<int>(P.pack_blk.size());
+    w.pack_first = cv.take<int>(P.pack_first.size());
+    w.red_blk = cv.take<int>(P.red_blk.size());
+    w.red_first = cv.take<int>(P.red_first.size());
     w.frag = cv.take<float>(P.frag_off.empty() ? 0 : P.frag_off.back());
-    w.foffs = cv.take<int64_t>(P.nprob + 1);
     const size_t g = P.gfrag_off.empty() ? 0 : static_cast<size_t>(P.gfrag_off.back());
     w.gh = cv.take<bf16x8>(g);
     w.gm = cv.take<bf16x8>(g);
@@ -753,9 +750,8 @@ static hipError_t launch_bhyb_f(const mfgp_batch_plan_s& P, const BatchWs& w, in
 // Pack the fragments of V for all problems, then run the persistent hybrid sweep.
 static hipError_t launch_bhyb(const mfgp_batch_plan_s& P, const BatchWs& w, int ntiles, const float* V,
                               float* part, const int* live, hipStream_t s) {
-    const int64_t total = P.frag_off.back();
-    hipLaunchKernelGGL(batch_pack_hfrag_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
-                       s, V, w.probs, w.foffs, P.nprob, P.t, P.hyb_nt, P.hyb_tv, w.frag, live);
+    hipLaunchKernelGGL(batch_pack_hfrag_kernel, dim3(static_cast<unsigned>(P.pack_blk.size())), dim3(256), 0,
+                       s, V, w.probs, w.pack_blk, w.pack_first, P.t, P.hyb_nt, P.hyb_tv, w.frag, live);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (P.family) {
@@ -866,9 +862,9 @@ static hipError_t batch_apply(const mfgp_batch_plan_s& P, const BatchWs& w, int 
             fl += e2 * sweep_flops_per_entry(P.family, P.kern[b].d, P.t, false);
         }
     timing_end(tok, s, is_bf16(P.precision) ? kSweepMfma : kSweepF32, ent, fl);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(nblocks(P.rows * P.t)), dim3(256), 0, s,
-                       reinterpret_cast<const float*>(w.part), w.probs, w.row_offs, P.nprob, P.rows, P.t,
-                       V, out, live);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(static_cast<unsigned>(P.red_blk.size())), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(w.part), w.probs, w.red_blk, w.red_first, P.t, V, out,
+                       live);
     return hipGetLastError();
 }
 
@@ -932,6 +928,11 @@ static int upload_tiles(const mfgp_batch_plan_s& P, const BatchWs& w, int64_t J,
     ntiles = static_cast<int>(queue.size());
     B_CHECK(hipMemcpyAsync(w.probs, probs.data(), probs.size() * sizeof(BProb), hipMemcpyHostToDevice, s));
     B_CHECK(hipMemcpyAsync(w.queue, queue.data(), queue.size() * sizeof(BTile), hipMemcpyHostToDevice, s));
+    const std::vector<int>* maps[4] = {&P.pack_blk, &P.pack_first, &P.red_blk, &P.red_first};
+    int* dst[4] = {w.pack_blk, w.pack_first, w.red_blk, w.red_first};
+    for (int k = 0; k < 4; ++k)
+        if (!maps[k]->empty())
+            B_CHECK(hipMemcpyAsync(dst[k], maps[k]->data(), maps[k]->size() * sizeof(int), hipMemcpyHostToDevice, s));
     B_CHECK(hipStreamSynchronize(s));
     return MFGP_OK;
 }
@@ -1072,6 +1073,18 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
         if (P->hybrid) facc += (P->n[b] + kHK - 1) / kHK * 64 * (P->hyb_nt + P->hyb_tv);
     }
     P->frag_off.push_back(facc);
+    // per-problem grids of 256-thread blocks
+    auto block_map = [&](auto count, std::vector<int>& blk, std::vector<int>& first) {
+        for (int b = 0; b < P->nprob; ++b) {
+            first.push_back(static_cast<int>(blk.size()));
+            const int64_t nb = (count(b) + 255) / 256;
+            for (int64_t k = 0; k < nb; ++k) blk.push_back(b);
+        }
+        first.push_back(static_cast<int>(blk.size()));
+    };
+    if (P->hybrid)
+        block_map([&](int b) { return P->frag_off[b + 1] - P->frag_off[b]; }, P->pack_blk, P->pack_first);
+    block_map([&](int b) { return P->n[b] * t; }, P->red_blk, P->red_first);
     int64_t gacc = 0, yacc = 0;
     for (int b = 0; b < P->nprob; ++b) {
         const int64_t njt = (P->n[b] + kJT - 1) / kJT;
@@ -1136,10 +1149,6 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     // Static descriptors and prescaled coordinates.
     B_CHECK(hipMemcpyAsync(w.segs, P.segs.data(), P.segs.size() * sizeof(BSeg), hipMemcpyHostToDevice, s));
     B_CHECK(hipMemcpyAsync(w.seg_first, P.seg_first.data(), P.seg_first.size() * sizeof(int),
-                           hipMemcpyHostToDevice, s));
-    B_CHECK(hipMemcpyAsync(w.row_offs, P.row_offs.data(), P.row_offs.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s));
-    B_CHECK(hipMemcpyAsync(w.foffs, P.frag_off.data(), P.frag_off.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     B_CHECK(hipMemcpyAsync(w.goffs, P.gfrag_off.data(), P.gfrag_off.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
