@@ -403,12 +403,18 @@ __global__ __launch_bounds__(256) void bcg_update_kernel(CgState st, const BSeg*
 }
 
 // p = r + beta p for active (problem, column); restart: r = fl32(R64), p = r.
+// p = r + beta p for the active columns: threads k < S = floor(256 / t) t
+// stride the segment by S, so thread k always holds column k % t (no
+// per-element division) and reads that column's flag and beta once.
 __global__ __launch_bounds__(256) void bcg_p_kernel(CgState st, const BSeg* __restrict__ segs, int t) {
     const BSeg sg = segs[blockIdx.x];
-    for (int64_t e = sg.r0 * t + threadIdx.x; e < sg.r1 * t; e += 256) {
-        const int q = sg.b * t + static_cast<int>(e % t);
-        if (st.active[q]) st.p[e] = fmaf(static_cast<float>(st.beta[q]), st.p[e], st.r[e]);
-    }
+    const int S = (256 / t) * t;
+    const int k = threadIdx.x;
+    if (k >= S) return;
+    const int q = sg.b * t + k % t;
+    if (!st.active[q]) return;
+    const float beta = static_cast<float>(st.beta[q]);
+    for (int64_t e = sg.r0 * t + k; e < sg.r1 * t; e += S) st.p[e] = fmaf(beta, st.p[e], st.r[e]);
 }
 
 __global__ __launch_bounds__(256) void bcg_restart_kernel(CgState st, const BSeg* __restrict__ segs, int t,
