@@ -17,12 +17,14 @@
  *            "host".  The library never allocates: scratch comes from the
  *            caller's workspace `ws` of `ws_bytes` bytes (size it with
  *            mfgp_workspace_bytes; 256-byte alignment is handled inside).  No
- *            pointer is kept after a call returns.  Exceptions, both cached
- *            per host thread and device on first use: the preconditioned
- *            calls' rocBLAS handle (see "preconditioning"), and the hipFFT
- *            plans of the structured-interpolation calls, one per transform
- *            shape, whose tables and work areas hipFFT allocates in device
- *            memory; mfgp_release_thread_resources() frees both.
+ *            pointer is kept after a call returns.  Exceptions, cached per
+ *            host thread and device on first use: the preconditioned calls'
+ *            rocBLAS handle (see "preconditioning"), the hipFFT plans of the
+ *            structured-interpolation calls, one per transform shape, whose
+ *            tables and work areas hipFFT allocates in device memory, and
+ *            the capture stream of the graph-replayed CG iterations (see
+ *            mfgp_cg_opts.no_graph; the graphs themselves live for one call);
+ *            mfgp_release_thread_resources() frees them.
  * Streams    `stream` is a hipStream_t (NULL = the default stream).  Calls
  *            that return only device results are asynchronous on it; calls
  *            that return host values synchronise it before returning.
@@ -196,7 +198,13 @@ typedef struct {
     void (*progress)(void* user, int32_t iterations, double rel_resid);
     void* progress_user;
     int32_t progress_every;
-    int32_t pad2_;
+    int32_t no_graph;     /* nonzero: launch every iteration's kernels directly.  Otherwise,
+                             when the host checks every 4 or more iterations (automatic for
+                             products of < 1e9 entry-columns) and the operator is not SKI,
+                             the iterations between checks are captured once into a HIP
+                             graph (on a capture stream cached per host thread, see
+                             mfgp_release_thread_resources) and replayed on `stream`: the
+                             same kernels with the same arguments, so the same results */
 } mfgp_cg_opts;
 
 /* Per-column CG report (host array, one entry per column). */
@@ -574,8 +582,9 @@ int mfgp_last_hip_error(void);
 int mfgp_version(void);
 
 /* Frees the calling thread's cached library resources on every device: the
- * rocBLAS handles of the preconditioned calls and the hipFFT plans (with
- * their device memory) of the structured-interpolation calls.  Later calls
+ * rocBLAS handles of the preconditioned calls, the hipFFT plans (with their
+ * device memory) of the structured-interpolation calls and the CG capture
+ * streams.  Later calls
  * create them again.  Call it with no library work of this thread in flight.
  * Returns MFGP_ERR_HIP if switching devices fails. */
 int mfgp_release_thread_resources(void);

@@ -390,7 +390,9 @@ int mfgp_last_hip_error(void) { return g_last_hip; }
 int mfgp_release_thread_resources(void) {
     hipError_t e = release_fft_plans();
     const hipError_t e2 = release_blas_handles();
+    const hipError_t e3 = release_cg_streams();
     if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = e3;
     return e == hipSuccess ? MFGP_OK : hip_fail(e);
 }
 

@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <vector>
 
 namespace mfgp {
@@ -128,6 +129,41 @@ static hipError_t apply_op(const Operator& op, const float* V, int t, float* out
     return apply_sum(op, nullptr, op.n, V, t, out, true, V, b.apply, b.sum, precision, s);
 }
 
+// Capture streams for the graph-replayed iterations: one per device and host
+// thread (non-blocking, default priority), created on first use and kept
+// until the thread releases them (release_cg_streams) or ends.  The caller's
+// stream may be the legacy NULL stream, which cannot be captured; the graph
+// recorded on this stream is launched on the caller's.
+static thread_local std::map<int, hipStream_t> cap_streams;
+
+static hipStream_t capture_stream() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = cap_streams.find(dev);
+    if (it == cap_streams.end()) {
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        it = cap_streams.emplace(dev, cs).first;
+    }
+    return it->second;
+}
+
+// The captured iterations of one solve: re-captured when the product form or
+// the Lanczos recording changes (both are kernel arguments), destroyed with
+// the solve.
+struct IterGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int precision = -1, log = -1;
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~IterGraph() { drop(); }
+};
+
 #define CG_CHECK(expr)                         \
     do {                                       \
         hipError_t e_ = (expr);                \
@@ -159,6 +195,11 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
     // 1-d problems (cond ~ 1e6) even at 1% drift, while plain cycles with
     // refinement converged in as many iterations.
     const bool may_replace = !o.no_replacement && check_every <= kMaxReplaceGap;
+    // Launch-bound solves (checks 4 or more iterations apart): the iterations
+    // between checks are captured once and replayed (not with SKI operators,
+    // whose products call hipFFT).
+    const bool use_graph = !o.no_graph && check_every >= 4 && !op.ski;
+    IterGraph ig;
     CgState st = make_state(b, X, t, coeff);
     Operator opg;
     GramPrep gpre;
@@ -285,11 +326,35 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
         }
         if (any) {
             steps += check_every;
-            for (int k = 0; k < check_every; ++k) {
-                CG_CHECK(apply_op(opg, st.p, t, st.ap, precision, b, s));
-                CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
-                CG_CHECK(cg_alpha(st, t, s));
-                CG_CHECK(cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, s));
+            auto iterate = [&](hipStream_t q) -> hipError_t {
+                for (int k = 0; k < check_every; ++k) {
+                    hipError_t e = apply_op(opg, st.p, t, st.ap, precision, b, q);
+                    if (e == hipSuccess) e = col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, q);
+                    if (e == hipSuccess) e = cg_alpha(st, t, q);
+                    if (e == hipSuccess) e = cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, q);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            };
+            if (use_graph) {
+                if (!ig.exec || ig.precision != precision || ig.log != log_coeffs) {
+                    ig.drop();
+                    hipStream_t cs = capture_stream();
+                    if (!cs) CG_CHECK(hipErrorOutOfMemory);
+                    CG_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                    timing_suspend(true);   // no event records inside the graph
+                    const hipError_t ce = iterate(cs);
+                    timing_suspend(false);
+                    const hipError_t ee = hipStreamEndCapture(cs, &ig.graph);
+                    CG_CHECK(ce);
+                    CG_CHECK(ee);
+                    CG_CHECK(hipGraphInstantiate(&ig.exec, ig.graph, nullptr, nullptr, 0));
+                    ig.precision = precision;
+                    ig.log = log_coeffs;
+                }
+                CG_CHECK(hipGraphLaunch(ig.exec, s));
+            } else {
+                CG_CHECK(iterate(s));
             }
             continue;
         }
@@ -675,6 +740,18 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
         }
     }
     return worst;
+}
+
+// Destroys the calling thread's capture streams, each with its device current.
+hipError_t release_cg_streams() {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    for (auto& kv : cap_streams) {
+        if (hipSetDevice(kv.first) == hipSuccess) (void)hipStreamDestroy(kv.second);
+    }
+    cap_streams.clear();
+    return hipSetDevice(cur);
 }
 
 }  // namespace mfgp

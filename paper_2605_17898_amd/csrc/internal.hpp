@@ -253,6 +253,7 @@ void set_last_hip_error(hipError_t e);
 // handles of the preconditioned calls): released on request.
 hipError_t release_fft_plans();
 hipError_t release_blas_handles();
+hipError_t release_cg_streams();
 
 // General products (prod.hip): the VALU entry sweeps (FP32 and FP64
 // accumulation) and the adjoint sums [G_k per feature, G_s, G_p].

@@ -46,7 +46,7 @@ class CgOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("max_refine", C.c_int32), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("no_replacement", C.c_int32), ("probe_seed", C.c_uint64), ("progress", PROGRESS_FN),
-                ("progress_user", C.c_void_p), ("progress_every", C.c_int32), ("pad2_", C.c_int32)]
+                ("progress_user", C.c_void_p), ("progress_every", C.c_int32), ("no_graph", C.c_int32)]
 
 
 class CgInfoT(C.Structure):
@@ -359,10 +359,11 @@ def residual(kern: Kernel, X: torch.Tensor, B: torch.Tensor, Xsol: torch.Tensor)
 
 def cg_opts(tol: float = 1e-6, max_iter: int = 0, check_every: int = 0, max_refine: int = -1,
             precision: str = "fp32", warm_start: bool = False, probe_seed: int = 0,
-            progress=None, progress_every: int = 0, replacement: bool = True) -> CgOptsT:
+            progress=None, progress_every: int = 0, replacement: bool = True, graph: bool = True) -> CgOptsT:
     """CG options; progress(iterations, rel_resid) is called during long solves."""
     o = CgOptsT()
     o.no_replacement = 0 if replacement else 1
+    o.no_graph = 0 if graph else 1
     if progress is not None:
         cb = PROGRESS_FN(lambda _u, it, rr: progress(int(it), float(rr)))
         o.progress = cb
@@ -389,14 +390,14 @@ def _info_list(info, t):
 def cg_solve(kern: Kernel, X: torch.Tensor, B: torch.Tensor, tol: float = 1e-6, max_iter: int = 0,
              precision: str = "fp32", x0: Optional[torch.Tensor] = None, want_lanczos: bool = False,
              check_every: int = 0, max_refine: int = -1, allow=(OK, NOT_CONVERGED, BREAKDOWN),
-             progress=None, replacement: bool = True):
+             progress=None, replacement: bool = True, graph: bool = True):
     """Solve K_y X = B.  Returns (Xsol float64, info list, lanczos or None, status)."""
     _dev(X, torch.float32, "X")
     _dev(B, torch.float32, "B")
     n, d = X.shape
     t = _cols(B)
     o = cg_opts(tol, max_iter, check_every, max_refine, precision, x0 is not None, progress=progress,
-                replacement=replacement)
+                replacement=replacement, graph=graph)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     Xsol = torch.zeros(B.shape, dtype=torch.float64, device=B.device) if x0 is None else \
         _dev(x0, torch.float64, "x0").clone()
@@ -467,11 +468,12 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
                  Z: Optional[torch.Tensor] = None, tol: float = 1e-6, max_iter: int = 0,
                  precision: str = "fp32", probe_seed: int = 0, want_grad: bool = True,
                  want_alpha: bool = False, allow=(OK, NOT_CONVERGED, BREAKDOWN), progress=None,
-                 replacement: bool = True, check_every: int = 0):
+                 replacement: bool = True, check_every: int = 0, graph: bool = True):
     """Returns dict(mll, logdet, grad, alpha, info, status).
 
     check_every: iterations between the host's convergence checks (0: chosen
-    from the product size); residual replacement runs only at 1 or 2."""
+    from the product size); residual replacement runs only at 1 or 2.
+    graph: replay captured iterations when the checks are 4 or more apart."""
     _dev(X, torch.float32, "X")
     _dev(y, torch.float32, "y")
     n, d = X.shape
@@ -480,7 +482,7 @@ def mll_and_grad(kern: Kernel, X: torch.Tensor, y: torch.Tensor, num_probes: int
         num_probes = Z.shape[1]
     t = num_probes + 1
     o = cg_opts(tol, max_iter, check_every, -1, precision, False, probe_seed, progress=progress,
-                replacement=replacement)
+                replacement=replacement, graph=graph)
     mi = max_iter if max_iter > 0 else min(max(2 * n, 64), 20000)
     ws = workspace(workspace_bytes(OP_MLL, n, kern.feature_dim(d), t, o.precision, mi), X.device)
     ks = kern.struct(d)

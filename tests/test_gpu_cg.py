@@ -42,6 +42,47 @@ def test_cg_exact1k_vs_cholesky(mf):
     assert rel[0] == pytest.approx(info[0]["rel_resid_true"], rel=1e-6, abs=1e-12)
 
 
+@pytest.mark.parametrize("case", ["rbf_n1500_t5", "matern32_n3001_t17_x2", "sum_n2000_t3", "prod_n1800_t2"])
+def test_cg_graph_replay_equals_eager(mf, case):
+    # Checks 4-8 iterations apart: the iterations between checks are captured
+    # once per product form and Lanczos-recording state and replayed.  The
+    # replays run the same kernels with the same arguments, with the host's
+    # checks (and refinement restarts) between them, so solutions, logged
+    # coefficients and reports equal those of direct launches bit for bit.
+    banner(f"cg graph replay vs direct launches: {case}")
+    if case.startswith("rbf"):
+        w = inputs.random_problem(81, 1500, 3, "rbf", ard=True, noise=0.02)
+        k, prec, t = mkern(w), "fp32", 5
+    elif case.startswith("matern32"):
+        w = inputs.random_problem(82, 3001, 2, "matern32", noise=0.03)
+        k, prec, t = mkern(w), "bf16x2", 17
+    elif case.startswith("sum"):
+        w = inputs.random_problem(83, 2000, 2, "rbf", noise=0.05)
+        k, prec, t = mkern(w) + mf.Kernel("matern52", 0.7, 0.5), "fp32", 3
+    else:
+        w = inputs.random_problem(84, 1800, 2, "rbf", noise=0.05)
+        k, prec, t = mkern(w) * mf.Kernel("matern12", 1.3), "fp32", 2
+    B = np.concatenate([w.y[:, None], inputs.gaussian_rhs(85, w.n, t - 1)], axis=1)
+    xg, ig, lg, sg = mf.cg_solve(k, dev(w.X), dev(B), tol=1e-6, precision=prec, want_lanczos=True)
+    xe, ie, le, se = mf.cg_solve(k, dev(w.X), dev(B), tol=1e-6, precision=prec, want_lanczos=True,
+                                 graph=False)
+    assert sg == se and ig == ie
+    assert torch.equal(xg, xe)
+    for c in range(t):   # the recorded coefficients (the buffer past them is scratch)
+        m = ig[c]["lanczos_len"]
+        assert torch.equal(lg[c, :m], le[c, :m])
+    assert max(i["rel_resid_true"] for i in ig) <= 1e-6
+
+
+def test_mll_graph_replay_equals_eager(mf):
+    banner("mll+grad exact1k p=16: graph replay vs direct launches")
+    w = inputs.exact1k(probes=16)
+    rg = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6)
+    re_ = mf.mll_and_grad(mkern(w), dev(w.X), dev(w.y), Z=dev(w.Z), tol=1e-6, graph=False)
+    assert rg["mll"] == re_["mll"] and rg["logdet"] == re_["logdet"] and rg["grad"] == re_["grad"]
+    assert rg["info"] == re_["info"]
+
+
 @pytest.mark.parametrize("family", ["rbf", "matern12", "matern32", "matern52"])
 def test_cg_multi_column_families(mf, family):
     banner(f"cg multi-column family={family} n=1500 t=5")
