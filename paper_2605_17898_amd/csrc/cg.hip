@@ -329,8 +329,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
             auto iterate = [&](hipStream_t q) -> hipError_t {
                 for (int k = 0; k < check_every; ++k) {
                     hipError_t e = apply_op(opg, st.p, t, st.ap, precision, b, q);
-                    if (e == hipSuccess) e = col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, q);
-                    if (e == hipSuccess) e = cg_alpha(st, t, q);
+                    if (e == hipSuccess) e = cg_pap_alpha(st, n, t, b.dots, q);
                     if (e == hipSuccess) e = cg_update_and_beta(st, n, t, b.dots, tol, log_coeffs, max_iter, q);
                     if (e != hipSuccess) return e;
                 }
@@ -469,7 +468,7 @@ int cg_run(const Operator& op, const float* B, int t, double* X, const mfgp_cg_o
 static inline unsigned nblk(int64_t total) { return static_cast<unsigned>((total + 255) / 256); }
 
 // rz = r^T z (the PCG inner product) drives alpha and beta; rr = r^T r the
-// stopping rule.  st.rr holds rz so that cg_alpha_kernel computes rz / p^T A p.
+// stopping rule.  st.rr holds rz so that cg_pap_alpha computes rz / p^T A p.
 __global__ void pcg_beta_kernel(CgState st, int t, const double* __restrict__ rzn_all,
                                 const double* __restrict__ rrn_all, double tol2, int log_coeffs, int max_iter) {
     for (int c = threadIdx.x; c < t; c += blockDim.x) {
@@ -631,8 +630,7 @@ int pcg_run(const Operator& op, const Precond& pc, const float* B, int t, double
             steps += check_every;
             for (int k = 0; k < check_every; ++k) {
                 CG_CHECK(apply_op(opg, st.p, t, st.ap, precision, b, s));
-                CG_CHECK(col_dots_ff(st.p, st.ap, n, t, st.pap, b.dots, s));
-                CG_CHECK(cg_alpha(st, t, s));
+                CG_CHECK(cg_pap_alpha(st, n, t, b.dots, s));
                 CG_CHECK(cg_update_rr(st, n, t, b.dots, rrn, s));
                 CG_CHECK(pc_apply(pc, st.r, t, pb.Zv, pb.pc, s));
                 CG_CHECK(col_dots_ff(st.r, pb.Zv, n, t, rzn, b.dots, s));

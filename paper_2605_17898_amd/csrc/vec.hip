@@ -67,6 +67,42 @@ __global__ __launch_bounds__(256) void dot_stage2(const double* __restrict__ par
     if (threadIdx.x == 0) out[c] = lds[0];
 }
 
+// The column sum of dot_stage2 (same order), left in lds[0] of block c.
+__device__ __forceinline__ double stage2_sum(const double* __restrict__ part, int G, int t, int c,
+                                             double* lds) {
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) s += part[static_cast<int64_t>(g) * t + c];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+// p^T A p of column c (block c) and then its step length alpha = r^T r / p^T A p
+// (breakdown when p^T A p is not positive and finite), in one launch: the
+// iteration's chain of dependent small kernels is what bounds small solves.
+__global__ __launch_bounds__(256) void pap_alpha_kernel(const double* __restrict__ part, int G, CgState st,
+                                                        int t) {
+    __shared__ double lds[256];
+    const int c = blockIdx.x;
+    const double pap = stage2_sum(part, G, t, c, lds);
+    if (threadIdx.x != 0) return;
+    st.pap[c] = pap;
+    double a = 0.0;
+    if (st.active[c]) {
+        if (!(pap > 0.0) || !isfinite(pap) || !isfinite(st.rr[c])) {
+            st.status[c] = MFGP_BREAKDOWN;
+            st.active[c] = 0;
+        } else {
+            a = st.rr[c] / pap;
+        }
+    }
+    st.alpha[c] = a;
+}
+
 size_t dots_scratch_doubles(int64_t n, int t) {
     return static_cast<size_t>(stripe_blocks(n, t)) * t + 64;
 }
@@ -95,24 +131,6 @@ hipError_t col_dots_df(const double* a, const float* b, int64_t n, int t, double
 }
 
 // ---------------------------------------------------------------- CG steps
-
-// alpha_c = rr_c / (p_c^T A p_c) for active columns; breakdown when the
-// curvature is not positive and finite.
-__global__ void cg_alpha_kernel(CgState st, int t) {
-    for (int c = threadIdx.x; c < t; c += blockDim.x) {
-        double a = 0.0;
-        if (st.active[c]) {
-            const double pap = st.pap[c];
-            if (!(pap > 0.0) || !isfinite(pap) || !isfinite(st.rr[c])) {
-                st.status[c] = MFGP_BREAKDOWN;
-                st.active[c] = 0;
-            } else {
-                a = st.rr[c] / pap;
-            }
-        }
-        st.alpha[c] = a;
-    }
-}
 
 // x += alpha p (FP64), r -= alpha Ap (FP32), and striped partial sums of r^2.
 __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, int64_t total, int t,
@@ -146,32 +164,35 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, int64_t tota
         part[static_cast<int64_t>(blockIdx.x) * t + c] = block_column_sum(lds, t, c, first);
 }
 
-// beta_c = rr_new / rr; logs (alpha, beta) for the Lanczos tridiagonal while
-// the first cycle runs; freezes converged columns.
-__global__ void cg_beta_kernel(CgState st, int t, const double* __restrict__ rrn_all,
-                               double tol2, int log_coeffs, int max_iter) {
-    for (int c = threadIdx.x; c < t; c += blockDim.x) {
-        const double rrn = rrn_all[c];
-        double b = 0.0;
-        if (st.active[c]) {
-            b = rrn / st.rr[c];
-            if (log_coeffs && st.coeff && st.lanlen[c] < max_iter) {
-                double* cf = st.coeff + (static_cast<int64_t>(c) * max_iter + st.lanlen[c]) * 2;
-                cf[0] = st.alpha[c];
-                cf[1] = b;
-                st.lanlen[c] += 1;
-            }
-            st.iters[c] += 1;
-            st.rr[c] = rrn;
-            if (!isfinite(rrn)) {
-                st.status[c] = MFGP_BREAKDOWN;
-                st.active[c] = 0;
-            } else if (rrn <= tol2 * st.bnorm2[c] || st.iters[c] >= max_iter) {
-                st.active[c] = 0;
-            }
+// r^T r of column c (block c), then beta = r'^T r' / r^T r, the logged
+// (alpha, beta) while the tridiagonal is recorded, the iteration count and
+// the stopping rule for that column, in one launch.
+__global__ __launch_bounds__(256) void rr_beta_kernel(const double* __restrict__ part, int G, CgState st, int t,
+                                                      double tol2, int log_coeffs, int max_iter) {
+    __shared__ double lds[256];
+    const int c = blockIdx.x;
+    const double rrn = stage2_sum(part, G, t, c, lds);
+    if (threadIdx.x != 0) return;
+    st.rrn[c] = rrn;
+    double b = 0.0;
+    if (st.active[c]) {
+        b = rrn / st.rr[c];
+        if (log_coeffs && st.coeff && st.lanlen[c] < max_iter) {
+            double* cf = st.coeff + (static_cast<int64_t>(c) * max_iter + st.lanlen[c]) * 2;
+            cf[0] = st.alpha[c];
+            cf[1] = b;
+            st.lanlen[c] += 1;
         }
-        st.beta[c] = b;
+        st.iters[c] += 1;
+        st.rr[c] = rrn;
+        if (!isfinite(rrn)) {
+            st.status[c] = MFGP_BREAKDOWN;
+            st.active[c] = 0;
+        } else if (rrn <= tol2 * st.bnorm2[c] || st.iters[c] >= max_iter) {
+            st.active[c] = 0;
+        }
     }
+    st.beta[c] = b;
 }
 
 // p = r + beta p
@@ -266,20 +287,22 @@ __global__ void diag_variance_kernel(const float* __restrict__ Z, const float* _
     var[q] = static_cast<float>(den > 0.0 ? s2 - num / den : s2);
 }
 
-hipError_t cg_alpha(const CgState& st, int t, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(256), 0, s, st, t);
-    return hipGetLastError();
-}
-
 hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scratch, double tol,
                               int log_coeffs, int max_iter, hipStream_t s) {
     const int G = stripe_blocks(n, t);
     const int64_t S = (static_cast<int64_t>(G) * 256 / t) * t;
     hipLaunchKernelGGL(cg_update_kernel, dim3(G), dim3(256), 0, s, st, n * t, t, S, scratch);
-    hipLaunchKernelGGL(dot_stage2, dim3(t), dim3(256), 0, s, scratch, G, t, st.rrn);
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(256), 0, s, st, t, st.rrn, tol * tol,
-                       log_coeffs, max_iter);
+    hipLaunchKernelGGL(rr_beta_kernel, dim3(t), dim3(256), 0, s, scratch, G, st, t, tol * tol, log_coeffs,
+                       max_iter);
     hipLaunchKernelGGL(cg_p_kernel, dim3(nblk(n * t)), dim3(256), 0, s, st, n * t, t);
+    return hipGetLastError();
+}
+
+hipError_t cg_pap_alpha(const CgState& st, int64_t n, int t, double* scratch, hipStream_t s) {
+    const int G = stripe_blocks(n, t);
+    const int64_t S = (static_cast<int64_t>(G) * 256 / t) * t;
+    hipLaunchKernelGGL((dot_stage1<float, float>), dim3(G), dim3(256), 0, s, st.p, st.ap, n * t, t, S, scratch);
+    hipLaunchKernelGGL(pap_alpha_kernel, dim3(t), dim3(256), 0, s, scratch, G, st, t);
     return hipGetLastError();
 }
 

@@ -25,7 +25,10 @@ struct CgState {
 };
 
 int stripe_blocks(int64_t n, int t);
-hipError_t cg_alpha(const CgState& st, int t, hipStream_t s);
+// st.pap = p^T (A p) per column and the step length alpha = st.rr / st.pap
+// in two launches: the striped partial dots, then one block per column
+// (breakdown when p^T A p is not positive and finite).
+hipError_t cg_pap_alpha(const CgState& st, int64_t n, int t, double* scratch, hipStream_t s);
 hipError_t cg_update_and_beta(const CgState& st, int64_t n, int t, double* scratch, double tol,
                               int log_coeffs, int max_iter, hipStream_t s);
 // x += alpha p, r -= alpha A p for active columns; rr_out[c] = r_c^T r_c (FP64).
