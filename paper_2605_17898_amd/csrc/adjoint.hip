@@ -174,13 +174,21 @@ __global__ __launch_bounds__(kBlock) void adjoint_mfma_kernel(
     block_sum_write<D + 1>(v, red, partial + static_cast<int64_t>(blockIdx.x) * (D + 1));
 }
 
-__global__ void adjoint_final_kernel(const double* __restrict__ partial, int nblocks, int width,
-                                     double* __restrict__ out, int accumulate) {
-    const int k = threadIdx.x;
-    if (k >= width) return;
+// Grid sum of component k (block k) over the sweep's block partials: 256
+// threads stride the blocks, then a fixed tree (the same order every call).
+__global__ __launch_bounds__(256) void adjoint_final_kernel(const double* __restrict__ partial, int nblocks,
+                                                            int width, double* __restrict__ out, int accumulate) {
+    __shared__ double lds[256];
+    const int k = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[static_cast<int64_t>(b) * width + k];
-    out[k] = accumulate ? out[k] + s : s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[static_cast<int64_t>(b) * width + k];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = accumulate ? out[k] + lds[0] : lds[0];
 }
 
 template <int FAM, int D>
@@ -399,7 +407,7 @@ hipError_t adjoint_sums(const Operator& op, const float* A, const float* B, int 
             timing_end(tok, s, kSweepAdjoint, ent, ent * sweep_flops_per_entry(op.family, d, tb, true));
         }
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(adjoint_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, width,
+        hipLaunchKernelGGL(adjoint_final_kernel, dim3(width), dim3(256), 0, s, partial, nblocks, width,
                            total, first ? 0 : 1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
