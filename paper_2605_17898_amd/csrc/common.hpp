@@ -21,7 +21,7 @@
 namespace mfgp {
 
 constexpr float kLn2 = 0.693147180559945309f;
-constexpr float kLn2Sq3 = 0.160148454934364935f;  // ln(2)^2 / 3
+constexpr float kLn2Sq3 = 0.160151004639400475f;  // ln(2)^2 / 3
 
 // ---------------------------------------------------------------- entries
 
