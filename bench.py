@@ -84,6 +84,28 @@ STEP_COUNTERS = {
                     "source": "profiles/sweep_hyb_rbf_d4_t33_rbf100k.md (same counters; not measured in this run)"},
 }
 METRIC = "kernel entries/s and CG solve time at N=100k; MLL+grad time, BF16 vs FP32"
+# SIMD cycles per wave64 instruction on gfx950 (paper_2605_17898_amd/issue_rates,
+# profiles/issue_rates_gfx950.md): v_exp_f32 issues at half the FMA rate, and
+# FP32 MFMA does not overlap the VALU, so a sweep's instruction counts priced at
+# these rates and summed bound its cycles from below.
+ISSUE_CYCLES = {"exp": 8.34, "valu": 4.21, "mfma_f32_16x16x4": 32.43}
+# Instruction counts per 64 entries of the FP32 Gram sweep at t = 1 (rocprofv3
+# SQ_INSTS_VALU*, profiles/sweep_gram_rbf_d4_t1_rbf100k.md; not measured in this run)
+T1_COUNTERS = {"mfma_insts_per_64_entries": 0.25, "valu_insts_per_64_entries": 2.31,
+               "valu_trans_per_64_entries": 1.00}
+
+
+def issue_bound(counters: dict, launch_ms: float, entries: float) -> dict:
+    """The sweep's cycles per 64 entries at the measured issue rates (exp2,
+    other VALU, FP32 MFMA, summed) against the cycles one launch took at
+    2.4 GHz over the 64-entry slots each of the 1024 SIMDs executes."""
+    trans = counters["valu_trans_per_64_entries"]
+    model = (trans * ISSUE_CYCLES["exp"] + (counters["valu_insts_per_64_entries"] - trans) * ISSUE_CYCLES["valu"]
+             + counters["mfma_insts_per_64_entries"] * ISSUE_CYCLES["mfma_f32_16x16x4"])
+    measured = launch_ms * 1e-3 * 2.4e9 / (entries / 64.0 / 1024.0)
+    return {"model_cycles_per_64_entries": model, "measured_cycles_per_64_entries": measured,
+            "frac": model / measured,
+            "source": "profiles/issue_rates_gfx950.md (rates) and the counters' profile (counts)"}
 
 
 def cpu_baseline(w, rows: int) -> dict:
@@ -606,6 +628,9 @@ def main() -> int:
         },
     }
     if args.precision == "fp32":
+        line["roofline"]["issue_bound"] = issue_bound(STEP_COUNTERS["fp32"], line["roofline"]["launch_avg_ms"],
+                                                      float(w.n) * float(w.n))
+    if args.precision == "fp32":
         # The paper's Table 3 product on this geometry: K_y v with one
         # right-hand side (RBF, d = 4, N = 1e5), median of 9 calls after about
         # 100 ms of warm-up calls (sustained clocks, as inside a solve); the
@@ -627,7 +652,8 @@ def main() -> int:
             "roofline": {"bound": "alu", "kernel": "sweep_gram_kernel<d=4, NT=0, TV=1> (squared distances on "
                                                    "v_mfma_f32_16x16x4_f32; exp2 and the FMA on the VALU)",
                          "flop_per_entry": fl1, "achieved": ach1, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach1 / FP32_VECTOR_PEAK_TFLOPS, "launch_avg_ms": sw1},
+                         "unit": "TFLOP/s", "frac": ach1 / FP32_VECTOR_PEAK_TFLOPS, "launch_avg_ms": sw1,
+                         "issue_bound": issue_bound(T1_COUNTERS, sw1, float(w.n) * float(w.n))},
         }
         print(f"[bench] t=1 product: {ms1:.3f} ms per call, sweep {sw1:.3f} ms", file=sys.stderr, flush=True)
     if args.precision == "fp32" and not args.no_compare:

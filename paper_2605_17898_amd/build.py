@@ -52,6 +52,9 @@ UNITS = [
     ("prod.hip", "prod.o", []),
 ]
 HOST_UNITS = [("slq.cpp", "slq.o")]
+# Standalone measurement programs (not linked into the library): the issue-rate
+# probe whose cycle costs turn a sweep's instruction counts into its bound.
+PROGRAMS = [("issue_rates.hip", "issue_rates")]
 
 
 def hipcc() -> str:
@@ -77,6 +80,8 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     for src, obj in HOST_UNITS:
         cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o",
                      os.path.join(BUILD, obj)])
+    for src, exe in PROGRAMS:
+        cmds.append([cc, *HIP_FLAGS, os.path.join(CSRC, src), "-o", os.path.join(PKG, exe)])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for r in ex.map(_run, cmds):
             if verbose and (r.stdout or r.stderr):
