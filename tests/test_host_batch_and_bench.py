@@ -69,3 +69,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_issue_bound_prices_the_counted_instructions():
+    # one exp2, two other VALU and two FP32 MFMA per 64 entries, for a launch
+    # that took exactly the cycles they cost: the bound equals the measurement
+    sys.path.insert(0, ROOT)
+    import bench
+    rates = bench.ISSUE_CYCLES
+    c = {"valu_trans_per_64_entries": 1.0, "valu_insts_per_64_entries": 3.0, "mfma_insts_per_64_entries": 2.0}
+    model = rates["exp"] + 2.0 * rates["valu"] + 2.0 * rates["mfma_f32_16x16x4"]
+    entries = 64.0 * 1024.0 * 1000.0           # 1000 slots of 64 entries per SIMD
+    launch_ms = model * 1000.0 / 2.4e9 * 1e3    # those slots at the model's cycles and 2.4 GHz
+    ib = bench.issue_bound(c, launch_ms, entries)
+    assert abs(ib["model_cycles_per_64_entries"] - model) < 1e-9
+    assert abs(ib["measured_cycles_per_64_entries"] - model) < 1e-6
+    assert abs(ib["frac"] - 1.0) < 1e-9
+    # twice as long a launch halves the fraction
+    assert abs(bench.issue_bound(c, 2 * launch_ms, entries)["frac"] - 0.5) < 1e-9
