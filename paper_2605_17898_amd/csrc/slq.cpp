@@ -10,6 +10,10 @@
 // implicit symmetric tridiagonal QR iteration with the Wilkinson shift (Golub
 // & Van Loan, Matrix Computations, Sec. 8.3), carrying only the first row of
 // the eigenvector matrix, which keeps the cost O(m^2) and the memory O(m).
+// T is first scaled by a power of two so that no entry exceeds 1 in
+// magnitude (exact, and log theta = log theta' - log scale): the rotations
+// then take sqrt(x^2 + z^2) without overflow, about twice as fast as
+// std::hypot on this serial chain of rotations.
 #include <cmath>
 #include <vector>
 
@@ -40,12 +44,12 @@ bool tridiag_eig_first_row(std::vector<double>& d, std::vector<double>& e, std::
         const double delta = 0.5 * (d[hi - 1] - d[hi]);
         const double b2 = e[hi - 1] * e[hi - 1];
         const double sgn = delta >= 0.0 ? 1.0 : -1.0;
-        const double mu = d[hi] - b2 / (delta + sgn * std::hypot(delta, e[hi - 1]));
+        const double mu = d[hi] - b2 / (delta + sgn * std::sqrt(delta * delta + b2));
         // Implicit QR step: a chain of rotations R_k on (k, k+1) chasing the bulge.
         double x = d[lo] - mu;
         double z = e[lo];
         for (int k = lo; k < hi; ++k) {
-            const double r = std::hypot(x, z);
+            const double r = std::sqrt(x * x + z * z);
             const double c = r > 0.0 ? x / r : 1.0;
             const double s = r > 0.0 ? z / r : 0.0;
             if (k > lo) e[k - 1] = r;
@@ -85,13 +89,23 @@ int slq_quadrature(const double* coeffs, int m, double znorm2, double* q) {
         *q = znorm2 * std::log(d[0]);
         return MFGP_OK;
     }
+    double amax = 0.0;
+    for (int j = 0; j < m; ++j) amax = std::fmax(amax, std::fabs(d[j]));
+    for (int j = 0; j + 1 < m; ++j) amax = std::fmax(amax, std::fabs(e[j]));
+    if (!std::isfinite(amax) || !(amax > 0.0)) return MFGP_BREAKDOWN;
+    int ex = 0;
+    (void)std::frexp(amax, &ex);   // amax = f 2^ex, f in [0.5, 1)
+    for (int j = 0; j < m; ++j) d[j] = std::ldexp(d[j], -ex);
+    for (int j = 0; j + 1 < m; ++j) e[j] = std::ldexp(e[j], -ex);
     if (!tridiag_eig_first_row(d, e, w)) return MFGP_NOT_CONVERGED;
-    double acc = 0.0;
+    double acc = 0.0, wsum = 0.0;
     for (int k = 0; k < m; ++k) {
         if (!(d[k] > 0.0)) return MFGP_BREAKDOWN;
         acc += w[k] * std::log(d[k]);
+        wsum += w[k];
     }
-    *q = znorm2 * acc;
+    // log theta = log theta' + ex ln 2, weighted by the (unit-sum) weights
+    *q = znorm2 * (acc + wsum * ex * 0.69314718055994530942);
     return MFGP_OK;
 }
 

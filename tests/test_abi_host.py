@@ -270,6 +270,19 @@ def test_host_slq_special_cases(m):
         assert m.slq_quadrature(list(zip(al, be)), 3.0) == pytest.approx(ref, rel=1e-10, abs=1e-12)
 
 
+def test_host_slq_scale_covariance(m):
+    # CG coefficients alpha / c, beta belong to c T, and e_1^T log(c T) e_1 =
+    # log c + e_1^T log(T) e_1: the quadrature must follow at magnitudes where
+    # squaring the tridiagonal's entries would overflow or underflow
+    rng = np.random.default_rng(5)
+    al = rng.uniform(0.1, 2.0, size=80)
+    be = rng.uniform(0.0, 0.9, size=80)
+    base = m.slq_quadrature(list(zip(al, be)), 3.0)
+    for c in (2.0 ** 600, 1e150, 2.0 ** -600, 1e-170):
+        q = m.slq_quadrature(list(zip(al / c, be)), 3.0)
+        assert q == pytest.approx(base + 3.0 * math.log(c), rel=1e-12, abs=1e-9)
+
+
 def test_struct_layouts_match_the_header(m, tmp_path):
     # Compile a C probe against include/mfgp.h and compare sizes and offsets
     # with the ctypes mirrors the binding passes across the ABI.
