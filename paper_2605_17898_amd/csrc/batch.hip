@@ -17,7 +17,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -991,6 +994,67 @@ static double lengthscale_factor_b(int family, double l) {
 
 }  // namespace mfgp
 
+// Stochastic Lanczos quadratures (Sec. 3 "Inference") of the batch's probe
+// columns on host threads.  A problem's Lanczos coefficients are recorded in
+// its columns' first cycles only and never change once every column of the
+// problem has stopped for good, so its quadratures are queued then and run
+// while the other problems keep iterating; the last problems' are queued when
+// the solve ends.  Each column is computed by one thread into its own slots
+// (qv[q], qs[q]); the owner joins the threads before reading them, also on an
+// error return (the destructor drops what is still queued).
+namespace {
+struct SlqQueue {
+    std::vector<std::vector<double>> cf;   // [T] coefficients (alpha, beta) of column q
+    std::vector<int> len;                  // [T] their count
+    std::vector<double> zn;                // [T] ||z_q||^2
+    std::vector<double> qv;                // [T] quadrature of column q
+    std::vector<int> qs;                   // [T] its status
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int> todo;
+    bool closing = false, dropping = false;
+    std::vector<std::thread> pool;
+
+    explicit SlqQueue(int T) : cf(T), len(T, 0), zn(T, 0.0), qv(T, 0.0), qs(T, MFGP_OK) {}
+    void start(int nth) {
+        for (int k = 0; k < nth; ++k)
+            pool.emplace_back([this]() {
+                for (;;) {
+                    int q;
+                    {
+                        std::unique_lock<std::mutex> lk(mu);
+                        cv.wait(lk, [this]() { return closing || !todo.empty(); });
+                        if (todo.empty() || dropping) return;
+                        q = todo.front();
+                        todo.pop_front();
+                    }
+                    qs[q] = len[q] < 1 ? MFGP_BREAKDOWN : mfgp_slq_quadrature(cf[q].data(), len[q], zn[q], &qv[q]);
+                }
+            });
+    }
+    void push(int q) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            todo.push_back(q);
+        }
+        cv.notify_one();
+    }
+    // wait for every queued column (drop == false) or for the running ones only
+    void finish(bool drop) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            closing = true;
+            dropping = drop;
+        }
+        cv.notify_all();
+        for (auto& th : pool)
+            if (th.joinable()) th.join();
+        pool.clear();
+    }
+    ~SlqQueue() { finish(true); }
+};
+}  // namespace
+
 extern "C" {
 
 int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t max_iter, int32_t tune,
@@ -1286,6 +1350,42 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     B_CHECK2(hipMemcpyAsync(h_b2.data(), st.bnorm2, T * sizeof(double), hipMemcpyDeviceToHost, s));
     B_CHECK2(hipStreamSynchronize(s));
     for (int q = 0; q < T; ++q) h_stall[q].begin(0, h_rep[q]);
+    // quadratures of finished problems, overlapped with the rest of the solve
+    SlqQueue slq(T);
+    std::vector<char> queued(T, 0);
+    slq.zn = h_b2;   // ||z_q||^2 (the column norms of B, computed once)
+    {
+        // at most 16 threads: they run beside the thread that drives the GPU,
+        // and a larger host count need not be this process's CPU share
+        const unsigned hw = std::thread::hardware_concurrency();
+        slq.start(static_cast<int>(std::max(1u, std::min(hw ? hw : 1u, 16u))));
+    }
+    // copy the Lanczos coefficients of the probe columns of the listed
+    // problems (their columns no longer iterate) and queue their quadratures
+    auto queue_slq = [&](const std::vector<int>& probs_done) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(h_lan.data(), st.lanlen, T * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        std::vector<int> qs_new;
+        for (int b : probs_done)
+            for (int c = 1; c < t && e == hipSuccess; ++c) {
+                const int q = b * t + c;
+                if (queued[q]) continue;
+                slq.len[q] = h_lan[q];
+                if (h_lan[q] >= 1) {
+                    slq.cf[q].resize(2 * static_cast<size_t>(h_lan[q]));
+                    e = hipMemcpyAsync(slq.cf[q].data(), w.coeff + static_cast<size_t>(q) * max_iter * 2,
+                                       2 * h_lan[q] * sizeof(double), hipMemcpyDeviceToHost, s);
+                }
+                qs_new.push_back(q);
+            }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (int q : qs_new) {
+            queued[q] = 1;
+            slq.push(q);
+        }
+        return hipSuccess;
+    };
     const int report_every = opts->progress_every > 0 ? opts->progress_every : 100;
     int next_report = report_every;
     int steps = 0;   // iterations run by the solver (every cycle; all columns advance together)
@@ -1322,6 +1422,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
             if (fresh) ending.push_back(b);
         }
         if (!ending.empty()) {
+            std::vector<int> newly_done;
             for (int b : ending) {
                 const int64_t o = P.row_off[b] * t;
                 B_CHECK2(residual_f64(ops[b], w.Bm + o, st.x + o, t, w.R64 + o, w.resid, s));
@@ -1355,7 +1456,10 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                         assessed[q] = 1;
                     }
                 }
-                if (finished) done[b] = 1;
+                if (finished) {
+                    done[b] = 1;
+                    newly_done.push_back(b);
+                }
             }
             if (again) {
                 B_CHECK2(hipMemcpyAsync(restart, h_restart.data(), T * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1376,6 +1480,7 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
                     if (!h_active[q]) assessed[q] = 1;   // restarted at an exact zero residual
                 }
             }
+            if (!newly_done.empty()) B_CHECK2(queue_slq(newly_done));
         }
 
         // Residual replacement (as in the single-problem solver): a tenfold drop
@@ -1470,42 +1575,29 @@ int mfgp_batch_mll_and_grad(mfgp_batch_plan plan, const float* X, const float* y
     timing_phase(0, std::chrono::duration<double, std::milli>(clock::now() - t0).count());
     t0 = clock::now();
 
-    // Column dot products and Lanczos coefficients.
-    double* bb = w.tmp;
+    // Column dot products (x^T b for the data fit) and the quadratures.
     double* xb = w.tmp + T;
     double* xx = w.tmp + 2 * T;
-    B_CHECK(bdots_ff(P, w, w.Bm, w.Bm, bb, s));
     B_CHECK(bdots_df(P, w, w.X64, w.Bm, xb, s));
     B_CHECK(bdots_dd(P, w, w.X64, w.X64, xx, s));
     std::vector<double> h(3 * T);
-    B_CHECK(hipMemcpyAsync(h.data(), w.tmp, 3 * T * sizeof(double), hipMemcpyDeviceToHost, s));
-    std::vector<std::vector<double>> cf(T);
-    for (int q = 0; q < T; ++q) {
-        if (q % t == 0 || h_lan[q] < 1) continue;
-        cf[q].resize(2 * static_cast<size_t>(h_lan[q]));
-        B_CHECK(hipMemcpyAsync(cf[q].data(), w.coeff + static_cast<size_t>(q) * max_iter * 2,
-                               2 * h_lan[q] * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    B_CHECK(hipStreamSynchronize(s));
-    std::vector<double> qv(T, 0.0);
-    std::vector<int> qs(T, MFGP_OK);
+    B_CHECK(hipMemcpyAsync(h.data() + T, xb, 2 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the problems whose quadratures are not queued yet (those that ended
+    // with the solve; queue_slq synchronises the stream, also for h), then
+    // every quadrature
     {
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nth = static_cast<int>(std::max(1u, std::min(hw ? hw : 1u, 64u)));
-        std::vector<std::thread> pool;
-        for (int th = 0; th < nth; ++th)
-            pool.emplace_back([&, th]() {
-                for (int q = th; q < T; q += nth) {
-                    if (q % t == 0) continue;
-                    if (h_lan[q] < 1) {
-                        qs[q] = MFGP_BREAKDOWN;
-                        continue;
-                    }
-                    qs[q] = mfgp_slq_quadrature(cf[q].data(), h_lan[q], h[q], &qv[q]);
+        std::vector<int> rest;
+        for (int b = 0; b < nprob; ++b)
+            for (int c = 1; c < t; ++c)
+                if (!queued[b * t + c]) {
+                    rest.push_back(b);
+                    break;
                 }
-            });
-        for (auto& th : pool) th.join();
+        B_CHECK(queue_slq(rest));
     }
+    slq.finish(false);
+    const std::vector<double>& qv = slq.qv;
+    const std::vector<int>& qs = slq.qs;
     int slq_status = MFGP_OK;
     const double two_pi = 6.283185307179586477;
     for (int b = 0; b < nprob; ++b) {
