@@ -78,7 +78,10 @@
  *            thread-local last HIP error, the thread-local rocBLAS handles
  *            and hipFFT plans (see Memory), and the per-device address of the
  *            fixed workspace of mfgp_kernel_matvec_noalloc (set once, under a
- *            lock).
+ *            lock).  The MLL calls compute the stochastic Lanczos quadratures
+ *            on short-lived host threads of their own (at most 16 for a
+ *            batch, started and joined within the call; the batched call runs
+ *            a problem's quadratures while the other problems iterate).
  */
 #ifndef MFGP_H
 #define MFGP_H
