@@ -83,7 +83,9 @@ struct SweepPlan {
     int chunks = 1;
     int64_t jchunk = 0;
 };
-SweepPlan plan_sweep(int64_t m, int64_t n);
+// Split-j plan of an m x n sweep: 256-row blocks times j-range chunks, about
+// `target` blocks per launch.
+SweepPlan plan_sweep(int64_t m, int64_t n, int64_t target = 4096);
 
 // Column-block sizes with a compiled register-resident kernel.
 int column_block(int t_remaining);

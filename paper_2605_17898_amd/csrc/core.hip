@@ -29,14 +29,14 @@ double family_scale(int family) {
     }
 }
 
-SweepPlan plan_sweep(int64_t m, int64_t n) {
+SweepPlan plan_sweep(int64_t m, int64_t n, int64_t target) {
     SweepPlan p;
     p.m = m;
     p.n = n;
     p.rowblocks = static_cast<int>((m + kBlock - 1) / kBlock);
-    // Aim for ~4096 blocks (2 dispatch rounds at 8 resident 256-thread
-    // blocks per CU on 256 CUs), each j-range at least 256 long.
-    const int64_t target = 4096;
+    // Aim for ~target blocks (4096 by default: 2 dispatch rounds at 8
+    // resident 256-thread blocks per CU on 256 CUs), each j-range at least
+    // 256 long.
     int64_t chunks = (target + p.rowblocks - 1) / p.rowblocks;
     const int64_t max_chunks = n / 256 > 1 ? n / 256 : 1;
     if (chunks > max_chunks) chunks = max_chunks;
