@@ -665,18 +665,25 @@ static hipError_t probe_logdet(const std::vector<mfgp_cg_info>& inf, const doubl
     {
         unsigned hw = std::thread::hardware_concurrency();
         const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
-        std::vector<std::thread> pool;
-        for (int th = 0; th < nth; ++th) {
-            pool.emplace_back([&, th]() {
-                for (int c = 1 + th; c < t; c += nth) {
-                    if (inf[c].lanczos_len < 1) {
-                        qs[c] = MFGP_BREAKDOWN;
-                        continue;
-                    }
-                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, bnorm2[c], &q[c]);
+        auto work = [&](int th) {
+            for (int c = 1 + th; c < t; c += nth) {
+                if (inf[c].lanczos_len < 1) {
+                    qs[c] = MFGP_BREAKDOWN;
+                    continue;
                 }
-            });
+                qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, bnorm2[c], &q[c]);
+            }
+        };
+        std::vector<std::thread> pool;
+        int started = 0;
+        for (; started < nth; ++started) {
+            try {
+                pool.emplace_back(work, started);
+            } catch (...) {
+                break;   // no more threads: the caller takes the rest
+            }
         }
+        for (int th = started; th < nth; ++th) work(th);
         for (auto& th : pool) th.join();
     }
     double sum = 0.0;

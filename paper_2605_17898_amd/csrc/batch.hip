@@ -1016,21 +1016,29 @@ struct SlqQueue {
     std::vector<std::thread> pool;
 
     explicit SlqQueue(int T) : cf(T), len(T, 0), zn(T, 0.0), qv(T, 0.0), qs(T, MFGP_OK) {}
+    void run(int q) { qs[q] = len[q] < 1 ? MFGP_BREAKDOWN : mfgp_slq_quadrature(cf[q].data(), len[q], zn[q], &qv[q]); }
+    // as many threads as the system gives, up to nth (none: finish() runs
+    // the queue on the calling thread)
     void start(int nth) {
-        for (int k = 0; k < nth; ++k)
-            pool.emplace_back([this]() {
-                for (;;) {
-                    int q;
-                    {
-                        std::unique_lock<std::mutex> lk(mu);
-                        cv.wait(lk, [this]() { return closing || !todo.empty(); });
-                        if (todo.empty() || dropping) return;
-                        q = todo.front();
-                        todo.pop_front();
+        for (int k = 0; k < nth; ++k) {
+            try {
+                pool.emplace_back([this]() {
+                    for (;;) {
+                        int q;
+                        {
+                            std::unique_lock<std::mutex> lk(mu);
+                            cv.wait(lk, [this]() { return closing || !todo.empty(); });
+                            if (todo.empty() || dropping) return;
+                            q = todo.front();
+                            todo.pop_front();
+                        }
+                        run(q);
                     }
-                    qs[q] = len[q] < 1 ? MFGP_BREAKDOWN : mfgp_slq_quadrature(cf[q].data(), len[q], zn[q], &qv[q]);
-                }
-            });
+                });
+            } catch (...) {
+                break;
+            }
+        }
     }
     void push(int q) {
         {
@@ -1050,6 +1058,9 @@ struct SlqQueue {
         for (auto& th : pool)
             if (th.joinable()) th.join();
         pool.clear();
+        if (!drop)   // what no thread took (none could be started)
+            for (; !todo.empty(); todo.pop_front()) run(todo.front());
+        todo.clear();
     }
     ~SlqQueue() { finish(true); }
 };
