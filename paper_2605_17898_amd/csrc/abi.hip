@@ -641,6 +641,35 @@ int mfgp_kernel_adjoint(const mfgp_kernel* kern, const float* X, int64_t n, cons
 
 }  // extern "C"
 
+// The quadratures e_1^T log(T_c) e_1 ||z_c||^2 of columns 1..t-1 (column 0 is
+// the data column) from their CG coefficients cf[c] (len[c] pairs), on up to
+// min(cores, t - 1) host threads; a thread the system refuses to start
+// leaves its share to the calling thread, so no exception leaves the library.
+static void run_quadratures(int t, const std::vector<int>& len, const std::vector<std::vector<double>>& cf,
+                            const double* znorm2, std::vector<double>& q, std::vector<int>& qs) {
+    const int p = t - 1;
+    q.assign(t, 0.0);
+    qs.assign(t, MFGP_OK);
+    if (p < 1) return;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
+    auto work = [&](int th) {
+        for (int c = 1 + th; c < t; c += nth)
+            qs[c] = len[c] < 1 ? MFGP_BREAKDOWN : slq_quadrature(cf[c].data(), len[c], znorm2[c], &q[c]);
+    };
+    std::vector<std::thread> pool;
+    int started = 0;
+    for (; started < nth; ++started) {
+        try {
+            pool.emplace_back(work, started);
+        } catch (...) {
+            break;
+        }
+    }
+    for (int th = started; th < nth; ++th) work(th);
+    for (auto& th : pool) th.join();
+}
+
 // log|K_y| ~ (1/p) sum over the probe columns c = 1 .. t-1 of ||z_c||^2
 // e_1^T log(T_c) e_1 (stochastic Lanczos quadrature, Sec. 3 "Inference"),
 // T_c from the CG coefficients in coeff [t][max_iter][2] (device); bnorm2
@@ -660,32 +689,11 @@ static hipError_t probe_logdet(const std::vector<mfgp_cg_info>& inf, const doubl
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    std::vector<double> q(t, 0.0);
-    std::vector<int> qs(t, MFGP_OK);
-    {
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
-        auto work = [&](int th) {
-            for (int c = 1 + th; c < t; c += nth) {
-                if (inf[c].lanczos_len < 1) {
-                    qs[c] = MFGP_BREAKDOWN;
-                    continue;
-                }
-                qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, bnorm2[c], &q[c]);
-            }
-        };
-        std::vector<std::thread> pool;
-        int started = 0;
-        for (; started < nth; ++started) {
-            try {
-                pool.emplace_back(work, started);
-            } catch (...) {
-                break;   // no more threads: the caller takes the rest
-            }
-        }
-        for (int th = started; th < nth; ++th) work(th);
-        for (auto& th : pool) th.join();
-    }
+    std::vector<int> len(t, 0);
+    for (int c = 1; c < t; ++c) len[c] = inf[c].lanczos_len;
+    std::vector<double> q;
+    std::vector<int> qs;
+    run_quadratures(t, len, cf, bnorm2, q, qs);
     double sum = 0.0;
     *slq_status = MFGP_OK;
     for (int c = 1; c < t; ++c) {
@@ -1151,25 +1159,11 @@ int mfgp_precond_mll_and_grad(const mfgp_kernel* kern, const float* X, int64_t n
     ABI_CHECK(hipStreamSynchronize(s));
 
     // log|K_y| = log|P| + (1/p) sum_c (z_c^T P^{-1} z_c) e_1^T log(T_c) e_1.
-    std::vector<double> q(t, 0.0);
-    std::vector<int> qs(t, MFGP_OK);
-    {
-        unsigned hw = std::thread::hardware_concurrency();
-        const int nth = static_cast<int>(std::min<unsigned>(hw ? hw : 1, static_cast<unsigned>(p)));
-        std::vector<std::thread> pool;
-        for (int th = 0; th < nth; ++th) {
-            pool.emplace_back([&, th]() {
-                for (int c = 1 + th; c < t; c += nth) {
-                    if (inf[c].lanczos_len < 1) {
-                        qs[c] = MFGP_BREAKDOWN;
-                        continue;
-                    }
-                    qs[c] = slq_quadrature(cf[c].data(), inf[c].lanczos_len, rz0[c], &q[c]);
-                }
-            });
-        }
-        for (auto& th : pool) th.join();
-    }
+    std::vector<int> len(t, 0);
+    for (int c = 1; c < t; ++c) len[c] = inf[c].lanczos_len;
+    std::vector<double> q;
+    std::vector<int> qs;
+    run_quadratures(t, len, cf, rz0.data(), q, qs);
     double ld = 0.0;
     int slq_status = MFGP_OK;
     for (int c = 1; c < t; ++c) {

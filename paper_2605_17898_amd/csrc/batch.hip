@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -1082,7 +1083,11 @@ int mfgp_batch_plan_create(const mfgp_batch* batch, int32_t num_probes, int32_t 
     const int fam = batch->kern[0].family;
     if (fam == MFGP_PERIODIC || fam == MFGP_LINEAR) return MFGP_UNSUPPORTED;
     if (fam < MFGP_RBF || fam > MFGP_MATERN52) return MFGP_ERR_ARG;
-    auto* P = new mfgp_batch_plan_s();
+    auto* P = new (std::nothrow) mfgp_batch_plan_s();
+    if (!P) {
+        set_last_hip_error(hipErrorOutOfMemory);
+        return MFGP_ERR_HIP;
+    }
     P->nprob = batch->nprob;
     P->p = num_probes;
     P->t = t;
